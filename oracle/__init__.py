@@ -1,0 +1,279 @@
+"""FP64 CPU oracle of the LKS forward scheme and its ALKS adjoint.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark use this package to check and time the GPU library. The
+product path never imports it. It shares no code with the GPU library; the
+arithmetic lives in ``lks_oracle.c`` (plain C, OpenMP over rows), and this
+module only marshals arrays and runs the time loops the paper describes
+(Sec. 2.7, Steps 2-5):
+
+  * steady problems: N_f forward steps from rest, the objective on the final
+    state, then N_a adjoint steps with the state frozen at the final level
+    and the seed applied every step, then the sensitivity once;
+  * unsteady problems: N forward steps storing (u, T) of every level (the
+    paper stores the whole trajectory, Sec. 3.2 and 3.4), the objective as
+    the average over levels 1..N, then the adjoint from the terminal
+    condition f~ = g~ = 0 (eq:afinitial, eq:aginitial) down to level 0,
+    summing the sensitivity over levels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lks_oracle.c")
+_LIB = os.path.join(_HERE, "liblks_oracle.so")
+
+FLOW_CORNER = 3
+TAG_J_INLET = 16
+TAG_J_OUTLET = 32
+OBJ_PRESSURE_DROP = 0
+OBJ_HEAT = 1
+MODE_STEADY = 0
+MODE_UNSTEADY = 1
+N_ADJ_FIELDS = 9
+ADJ_NAMES = ("rho", "ux", "uy", "sxx", "sxy", "syy", "T", "qx", "qy")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C99 + OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("periodic", ctypes.c_int), ("thermal", ctypes.c_int),
+                ("nu", ctypes.c_double), ("Kf", ctypes.c_double),
+                ("Ks", ctypes.c_double), ("q_K", ctypes.c_double),
+                ("alpha_max", ctypes.c_double), ("q_alpha", ctypes.c_double),
+                ("rho_out", ctypes.c_double),
+                ("mask", ctypes.POINTER(ctypes.c_uint8)),
+                ("ubar", ctypes.POINTER(ctypes.c_double)),
+                ("Tbar", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        d = ctypes.POINTER(ctypes.c_double)
+        P = ctypes.POINTER(_Problem)
+        dd = ctypes.POINTER(d)
+        _lib.orc_coefficients.argtypes = [P, d, d, d, d, d]
+        _lib.orc_init_state.argtypes = [P, ctypes.c_double, d, d, d, d]
+        _lib.orc_lks_step.argtypes = [P, d, d, ctypes.c_double, d, d, d, d, d, d, d, d]
+        _lib.orc_pressure_drop.argtypes = [P, d]
+        _lib.orc_pressure_drop.restype = ctypes.c_double
+        _lib.orc_probe_heat.argtypes = [P, d, d]
+        _lib.orc_probe_heat.restype = ctypes.c_double
+        _lib.orc_adjoint_equilibrium.argtypes = [P, d, d, d, dd, d, d, d]
+        _lib.orc_alks_step.argtypes = [P, d, d, d, d, d, d, d, d, dd, dd,
+                                       ctypes.c_double, ctypes.c_double, d]
+        _lib.orc_sens_add.argtypes = [P, d, d, d, d, d, dd, ctypes.c_double, d]
+        _lib.orc_boundary_fill.argtypes = [P, ctypes.c_uint8, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, d, d, d]
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _pp(arrs):
+    arr = (ctypes.POINTER(ctypes.c_double) * len(arrs))(*[_p(a) for a in arrs])
+    return ctypes.cast(arr, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))), arr
+
+
+class Problem:
+    """Binds a workload's arrays to the C problem descriptor."""
+
+    def __init__(self, wl):
+        self.wl = wl
+        self.nx, self.ny = wl.nx, wl.ny
+        self.N = wl.nx * wl.ny
+        self.mask = np.ascontiguousarray(wl.mask, dtype=np.uint8).reshape(-1)
+        self.ubar = np.ascontiguousarray(wl.ubar, dtype=np.float64).reshape(-1)
+        self.Tbar = np.ascontiguousarray(wl.Tbar, dtype=np.float64).reshape(-1)
+        Kf = wl.nu / wl.Pr
+        self.c = _Problem(wl.nx, wl.ny, int(wl.periodic), int(wl.thermal), wl.nu, Kf,
+                          Kf * wl.Ks_over_Kf, wl.q_K, wl.alpha_max, wl.q_alpha,
+                          wl.rho_out,
+                          self.mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                          _p(self.ubar), _p(self.Tbar))
+        self.ref = ctypes.byref(self.c)
+
+    def zeros(self, k=None):
+        return np.zeros(self.N) if k is None else [np.zeros(self.N) for _ in range(k)]
+
+
+@dataclass
+class State:
+    drho: np.ndarray
+    ux: np.ndarray
+    uy: np.ndarray
+    T: np.ndarray
+
+    def copy(self):
+        return State(self.drho.copy(), self.ux.copy(), self.uy.copy(), self.T.copy())
+
+
+def coefficients(pb: Problem, gamma):
+    g = np.ascontiguousarray(gamma, dtype=np.float64).reshape(-1)
+    a, da, B, dB = pb.zeros(4)
+    lib().orc_coefficients(pb.ref, _p(g), _p(a), _p(da), _p(B), _p(dB))
+    return a, da, B, dB
+
+
+def init_state(pb: Problem, ufac0=1.0) -> State:
+    s = State(*pb.zeros(4))
+    lib().orc_init_state(pb.ref, ufac0, _p(s.drho), _p(s.ux), _p(s.uy), _p(s.T))
+    return s
+
+
+def lks_step(pb: Problem, alpha, B, ufac, s: State) -> State:
+    o = State(*pb.zeros(4))
+    lib().orc_lks_step(pb.ref, _p(alpha), _p(B), ufac, _p(s.drho), _p(s.ux), _p(s.uy),
+                       _p(s.T), _p(o.drho), _p(o.ux), _p(o.uy), _p(o.T))
+    return o
+
+
+def pressure_drop(pb: Problem, s: State) -> float:
+    return lib().orc_pressure_drop(pb.ref, _p(s.drho))
+
+
+def probe_heat(pb: Problem, s: State) -> float:
+    return lib().orc_probe_heat(pb.ref, _p(s.ux), _p(s.T))
+
+
+def level_objective(pb: Problem, s: State) -> float:
+    if pb.wl.objective == OBJ_PRESSURE_DROP:
+        return pressure_drop(pb, s)
+    return probe_heat(pb, s)
+
+
+def adjoint_equilibrium(pb: Problem, B, ux, uy, adj):
+    """(V_x, V_y, Theta): the coefficients of eq:afeq / eq:ageq."""
+    Vx, Vy, Th = pb.zeros(3)
+    pp, keep = _pp(adj)
+    lib().orc_adjoint_equilibrium(pb.ref, _p(B), _p(ux), _p(uy), pp, _p(Vx), _p(Vy),
+                                  _p(Th))
+    return Vx, Vy, Th
+
+
+def alks_step(pb: Problem, alpha, B, src: State, dst: State, adj_in, seed_dp, seed_heat):
+    out = pb.zeros(N_ADJ_FIELDS)
+    work = np.zeros(3 * pb.N)
+    pin, k1 = _pp(adj_in)
+    pout, k2 = _pp(out)
+    lib().orc_alks_step(pb.ref, _p(alpha), _p(B), _p(src.ux), _p(src.uy), _p(src.T),
+                        _p(dst.ux), _p(dst.uy), _p(dst.T), pin, pout, seed_dp, seed_heat,
+                        _p(work))
+    return out
+
+
+def sens_add(pb: Problem, dalpha, dB, s: State, adj, weight, sens):
+    pp, keep = _pp(adj)
+    lib().orc_sens_add(pb.ref, _p(dalpha), _p(dB), _p(s.ux), _p(s.uy), _p(s.T), pp,
+                       weight, _p(sens))
+
+
+def boundary_fill(pb: Problem, m, normal, Bn, Tn, u, seed_dp, fk, gk):
+    """Completed (f~, g~) at one ring node and the multipliers
+    (flow pair, thermal)."""
+    fk = np.ascontiguousarray(fk, dtype=np.float64).copy()
+    gk = np.ascontiguousarray(gk, dtype=np.float64).copy()
+    mult = np.zeros(3)
+    lib().orc_boundary_fill(pb.ref, int(m), int(normal[0]), int(normal[1]), Bn, Tn,
+                            float(u[0]), float(u[1]), seed_dp, _p(fk), _p(gk), _p(mult))
+    return fk, gk, mult
+
+
+# --------------------------------------------------------------------------
+# drivers
+# --------------------------------------------------------------------------
+def forward(pb: Problem, gamma, n_steps, store=False, state0: State | None = None):
+    """n_steps LKS steps from the level-0 state. Returns (final state, J,
+    trajectory or None). Steady: J on the final state. Unsteady: J averaged
+    over levels 1..n_steps."""
+    wl = pb.wl
+    alpha, _, B, _ = coefficients(pb, gamma)
+    s = init_state(pb, wl.ufac[0]) if state0 is None else state0.copy()
+    traj = [s] if store else None
+    acc = 0.0
+    for n in range(n_steps):
+        s = lks_step(pb, alpha, B, float(wl.ufac[min(n + 1, len(wl.ufac) - 1)]), s)
+        if wl.mode == MODE_UNSTEADY:
+            acc += level_objective(pb, s)
+        if store:
+            traj.append(s)
+    if wl.mode == MODE_UNSTEADY:
+        J = acc / max(n_steps, 1)
+    else:
+        J = level_objective(pb, s)
+    return s, J, traj
+
+
+def adjoint_steady(pb: Problem, gamma, state: State, n_adj, seed=1.0):
+    """n_adj ALKS steps with (u, T) frozen at `state` and the seed applied
+    every step; returns (adjoint fields, dJ/dgamma)."""
+    wl = pb.wl
+    alpha, dalpha, B, dB = coefficients(pb, gamma)
+    adj = pb.zeros(N_ADJ_FIELDS)
+    sdp = seed if wl.objective == OBJ_PRESSURE_DROP else 0.0
+    sh = seed if wl.objective == OBJ_HEAT else 0.0
+    for _ in range(n_adj):
+        adj = alks_step(pb, alpha, B, state, state, adj, sdp, sh)
+    sens = np.zeros(pb.N)
+    sens_add(pb, dalpha, dB, state, adj, 1.0, sens)
+    return adj, sens
+
+
+def adjoint_unsteady(pb: Problem, gamma, traj, seed=1.0):
+    """Reverse sweep over a stored trajectory of N+1 levels; the objective is
+    the average over levels 1..N, so the seed at level n >= 1 is seed/N."""
+    wl = pb.wl
+    N = len(traj) - 1
+    alpha, dalpha, B, dB = coefficients(pb, gamma)
+    adj = pb.zeros(N_ADJ_FIELDS)
+    sens = np.zeros(pb.N)
+    for n in range(N, -1, -1):
+        w = seed / N if n >= 1 else 0.0
+        sdp = w if wl.objective == OBJ_PRESSURE_DROP else 0.0
+        sh = w if wl.objective == OBJ_HEAT else 0.0
+        src = traj[min(n + 1, N)]
+        adj = alks_step(pb, alpha, B, src, traj[n], adj, sdp, sh)
+        sens_add(pb, dalpha, dB, traj[n], adj, 1.0, sens)
+    return adj, sens
+
+
+def gradient(wl, gamma=None, seed=1.0):
+    """Objective and ALKS sensitivity for a workload (steady or unsteady)."""
+    pb = Problem(wl)
+    g = wl.gamma if gamma is None else gamma
+    if wl.mode == MODE_STEADY:
+        s, J, _ = forward(pb, g, wl.n_fwd)
+        adj, sens = adjoint_steady(pb, g, s, wl.n_adj, seed)
+        return J, sens.reshape(wl.ny, wl.nx), s, adj
+    s, J, traj = forward(pb, g, wl.n_fwd, store=True)
+    adj, sens = adjoint_unsteady(pb, g, traj, seed)
+    return J, sens.reshape(wl.ny, wl.nx), s, adj
+
+
+def objective(wl, gamma):
+    pb = Problem(wl)
+    return forward(pb, gamma, wl.n_fwd)[1]

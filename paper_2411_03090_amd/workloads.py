@@ -1,0 +1,247 @@
+"""Seeded synthetic workloads for the LKS/ALKS path.
+
+This module builds the *inputs* of a run -- node-class masks, design fields
+gamma, prescribed boundary values and inflow time factors -- from a seed. It
+holds none of the scheme's arithmetic (no equilibria, gradients, adjoints or
+sensitivities), so that the FP64 oracle and the HIP library can both be fed
+from it without sharing any code of the method.
+
+Node-class byte (one per lattice node, x fastest) -- the input format of both
+implementations:
+
+    bits 0-1  flow class   0 interior (design) node, 1 prescribed velocity
+                           (inlet or wall), 2 prescribed pressure (outlet),
+                           3 corner
+    bits 2-3  thermal      0 none/interior, 1 prescribed temperature,
+                           2 prescribed heat flux (adiabatic, zero flux)
+    bit  4    member of the inlet set of the pressure-drop objective
+    bit  5    member of the outlet set of the pressure-drop objective
+    bit  6    member of the probe set of the heat-transfer objective
+
+The geometry is the rectangle of nodes [0,nx) x [0,ny); the outer ring of
+nodes is the boundary (Sec. 2.4 prescribes velocity at inlets and walls,
+pressure and zero tangential velocity at outlets, temperature or heat flux
+on thermal boundaries).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+FLOW_INTERIOR = 0
+FLOW_VELOCITY = 1
+FLOW_PRESSURE = 2
+FLOW_CORNER = 3
+THERM_NONE = 0 << 2
+THERM_DIRICHLET = 1 << 2
+THERM_FLUX = 2 << 2
+TAG_J_INLET = 1 << 4
+TAG_J_OUTLET = 1 << 5
+TAG_PROBE = 1 << 6
+
+OBJ_PRESSURE_DROP = 0
+OBJ_HEAT = 1
+MODE_STEADY = 0
+MODE_UNSTEADY = 1
+
+
+@dataclass
+class Workload:
+    """Everything a forward+adjoint run needs, as plain arrays and scalars."""
+    name: str
+    nx: int
+    ny: int
+    nu: float
+    u_max: float
+    alpha_max: float
+    q_alpha: float
+    thermal: bool
+    Pr: float = 6.0
+    Ks_over_Kf: float = 1.0
+    q_K: float = 0.1
+    rho_out: float = 1.0
+    objective: int = OBJ_PRESSURE_DROP
+    mode: int = MODE_STEADY
+    n_fwd: int = 0
+    n_adj: int = 0
+    periodic: bool = False
+    mask: np.ndarray = field(default=None, repr=False)      # (ny, nx) uint8
+    gamma: np.ndarray = field(default=None, repr=False)     # (ny, nx) f64
+    ubar: np.ndarray = field(default=None, repr=False)      # (2, ny, nx) f64
+    Tbar: np.ndarray = field(default=None, repr=False)      # (ny, nx) f64
+    ufac: np.ndarray = field(default=None, repr=False)      # (n_fwd+1,) f64
+
+    @property
+    def n_nodes(self) -> int:
+        return self.nx * self.ny
+
+
+# --------------------------------------------------------------------------
+# geometry
+# --------------------------------------------------------------------------
+def channel_mask(nx: int, ny: int, thermal: bool, probe_col: int | None = None):
+    """Channel: inlet on the left column, outlet on the right column, walls
+    top and bottom, corners separate. Thermal tags: inlet and bottom wall
+    prescribed temperature, top wall and outlet adiabatic."""
+    if nx < 4 or ny < 4:
+        raise ValueError("channel needs nx, ny >= 4")
+    m = np.zeros((ny, nx), np.uint8)
+    m[1:-1, 0] = FLOW_VELOCITY | TAG_J_INLET
+    m[1:-1, -1] = FLOW_PRESSURE | TAG_J_OUTLET
+    m[0, 1:-1] = FLOW_VELOCITY
+    m[-1, 1:-1] = FLOW_VELOCITY
+    for j, i in ((0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1)):
+        m[j, i] = FLOW_CORNER
+    if thermal:
+        m[1:-1, 0] |= THERM_DIRICHLET
+        m[0, 1:-1] |= THERM_DIRICHLET
+        m[-1, 1:-1] |= THERM_FLUX
+        m[1:-1, -1] |= THERM_FLUX
+    if probe_col is not None:
+        m[1:-1, probe_col] |= TAG_PROBE
+    return m
+
+
+def parabolic_inflow(ny: int, u_max: float):
+    """u_x(j) = u_max * 4 j (H-j) / H^2 with H = ny-1 (zero at both walls)."""
+    H = ny - 1
+    j = np.arange(ny, dtype=np.float64)
+    return u_max * 4.0 * j * (H - j) / (H * H)
+
+
+def channel_boundary_values(nx: int, ny: int, u_max: float, thermal: bool,
+                            T_in: float = 0.0, T_wall: float = 1.0):
+    ubar = np.zeros((2, ny, nx))
+    ubar[0, 1:-1, 0] = parabolic_inflow(ny, u_max)[1:-1]
+    Tbar = np.zeros((ny, nx))
+    if thermal:
+        Tbar[1:-1, 0] = T_in
+        Tbar[0, 1:-1] = T_wall
+    return ubar, Tbar
+
+
+# --------------------------------------------------------------------------
+# design fields
+# --------------------------------------------------------------------------
+def gamma_uniform(nx: int, ny: int, seed: int):
+    """i.i.d. uniform[0,1] design; the boundary ring is fluid (gamma = 1)."""
+    g = np.random.default_rng(seed).random((ny, nx))
+    _ring_to_fluid(g)
+    return g
+
+
+def gaussian_random_field(shape, sigma: float, seed: int):
+    """White N(0,1) noise from default_rng(seed), blurred by a periodic FFT
+    Gaussian of standard deviation sigma cells, normalised to unit std."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal(shape)
+    k = [np.fft.fftfreq(n) for n in shape]
+    grids = np.meshgrid(*k, indexing="ij")
+    k2 = sum(g * g for g in grids)
+    kern = np.exp(-2.0 * (math.pi ** 2) * (sigma ** 2) * k2)
+    z = np.real(np.fft.ifftn(np.fft.fftn(z) * kern))
+    return z / z.std()
+
+
+def gamma_grf(nx: int, ny: int, sigma: float, seed: int):
+    """gamma = clip(0.5 + 0.5 z, 0, 1) of a smoothed Gaussian field; ring = 1."""
+    z = gaussian_random_field((ny, nx), sigma, seed)
+    g = np.clip(0.5 + 0.5 * z, 0.0, 1.0)
+    _ring_to_fluid(g)
+    return g
+
+
+def _ring_to_fluid(g):
+    g[0, :] = 1.0
+    g[-1, :] = 1.0
+    g[:, 0] = 1.0
+    g[:, -1] = 1.0
+
+
+# --------------------------------------------------------------------------
+# time factors
+# --------------------------------------------------------------------------
+def oscillating_factors(n_levels: int, amp: float, period: float):
+    """Inflow factor per time level n: 1 + amp * sin(2 pi n / period)."""
+    n = np.arange(n_levels, dtype=np.float64)
+    return 1.0 + amp * np.sin(2.0 * math.pi * n / period)
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+def _steady_channel(name, nx, ny, Re, gamma, n_fwd, n_adj, nu=0.1):
+    H = ny - 1
+    u_max = Re * nu / H
+    if u_max > 0.1:                       # keep the inflow low-Mach
+        u_max = 0.1
+        nu = u_max * H / Re
+    mask = channel_mask(nx, ny, thermal=False)
+    ubar, Tbar = channel_boundary_values(nx, ny, u_max, thermal=False)
+    return Workload(name=name, nx=nx, ny=ny, nu=nu, u_max=u_max,
+                    alpha_max=1e3 / Re, q_alpha=0.1, thermal=False,
+                    objective=OBJ_PRESSURE_DROP, mode=MODE_STEADY,
+                    n_fwd=n_fwd, n_adj=n_adj, mask=mask, gamma=gamma,
+                    ubar=ubar, Tbar=Tbar, ufac=np.ones(n_fwd + 1))
+
+
+def steady_channel_uniform(nx=64, ny=64, Re=10.0, seed=0, n_fwd=3000, n_adj=3000):
+    """Steady non-thermal channel, gamma i.i.d. uniform (the 64x64, Re=10,
+    3000+3000-step pressure-drop case at its defaults)."""
+    return _steady_channel(f"steady_uniform_{nx}x{ny}_Re{Re:g}", nx, ny, Re,
+                           gamma_uniform(nx, ny, seed), n_fwd, n_adj)
+
+
+def steady_channel_grf(nx=512, ny=512, Re=100.0, sigma=8.0, seed=0,
+                       n_fwd=40000, n_adj=40000):
+    """Steady non-thermal channel, gamma from a smoothed Gaussian field (the
+    512x512, Re=100, 40000+40000-step case at its defaults)."""
+    return _steady_channel(f"steady_grf_{nx}x{ny}_Re{Re:g}", nx, ny, Re,
+                           gamma_grf(nx, ny, sigma, seed), n_fwd, n_adj)
+
+
+def unsteady_thermal_channel(nx=1024, ny=512, Re=200.0, Pr=6.0, sigma=8.0,
+                             seed=0, n_steps=20000, period=5000.0, amp=0.2,
+                             nu=0.1, Ks_over_Kf=10.0, q_K=0.1):
+    """Unsteady forced convection: oscillating parabolic inflow at T=0,
+    heated bottom wall T=1, adiabatic top wall and outlet; objective is the
+    time-averaged enthalpy flux through the last interior column."""
+    H = ny - 1
+    u_max = Re * nu / H
+    mask = channel_mask(nx, ny, thermal=True, probe_col=nx - 2)
+    ubar, Tbar = channel_boundary_values(nx, ny, u_max, thermal=True)
+    return Workload(name=f"unsteady_thermal_{nx}x{ny}_Re{Re:g}", nx=nx, ny=ny,
+                    nu=nu, u_max=u_max, alpha_max=1e3 / Re, q_alpha=0.1,
+                    thermal=True, Pr=Pr, Ks_over_Kf=Ks_over_Kf, q_K=q_K,
+                    objective=OBJ_HEAT, mode=MODE_UNSTEADY, n_fwd=n_steps,
+                    n_adj=n_steps, mask=mask, gamma=gamma_grf(nx, ny, sigma, seed),
+                    ubar=ubar, Tbar=Tbar,
+                    ufac=oscillating_factors(n_steps + 1, amp, period))
+
+
+def batch_designs(n_designs=64, sizes=(128, 192, 256, 384, 512),
+                  Re_range=(10.0, 200.0), sigma=8.0, n_steps=2000):
+    """Independent steady designs of uneven size: for design d, default_rng(d)
+    draws the edge length and Re; gamma is a smoothed random field."""
+    out = []
+    for d in range(n_designs):
+        rng = np.random.default_rng(d)
+        L = int(rng.choice(sizes))
+        Re = float(rng.uniform(*Re_range))
+        w = _steady_channel(f"batch{d}_{L}_Re{Re:.1f}", L, L, Re,
+                            gamma_grf(L, L, sigma, 1000 + d), n_steps, n_steps)
+        out.append(w)
+    return out
+
+
+def periodic_box(nx, ny, nu=0.1, thermal=False, Pr=6.0):
+    """Fully periodic box (no boundary nodes): used for the scheme's exact
+    discrete invariants."""
+    mask = np.zeros((ny, nx), np.uint8)
+    return Workload(name=f"periodic_{nx}x{ny}", nx=nx, ny=ny, nu=nu, u_max=0.0,
+                    alpha_max=0.0, q_alpha=0.1, thermal=thermal, Pr=Pr,
+                    periodic=True, mask=mask, gamma=np.ones((ny, nx)),
+                    ubar=np.zeros((2, ny, nx)), Tbar=np.zeros((ny, nx)),
+                    ufac=np.ones(1))
