@@ -1,0 +1,200 @@
+/*
+ * lks.h -- C ABI of the MI355X (gfx950) library for the Lattice Kinetic
+ * Scheme (LKS) forward step and its adjoint (ALKS) sweep, which produce the
+ * flow and thermal fields and the design sensitivity dJ/dgamma for
+ * Brinkman-penalised topology optimisation (Tanabe, Yaji and Ushijima,
+ * "Adjoint lattice kinetic scheme for topology optimization in fluid
+ * problems", arXiv 2411.03090).
+ *
+ * The calls follow the optimisation procedure of Sec. 2.7: Step 2 (state by
+ * LKS) is lks_forward, Step 3 (objective) is lks_objective, Steps 4-5
+ * (adjoint fields by ALKS and the sensitivity) are alks_backward.
+ *
+ * Conventions shared by every call
+ *   - Lattice units dx = dt = 1, relaxation times tau_f = tau_g = 1 (Sec. 2.4).
+ *   - D2Q9 lattice; fields are node arrays of nx*ny values, x fastest:
+ *     node (i, j) is element j*nx + i.
+ *   - The outer ring of nodes is the boundary; its class comes from the
+ *     node-class byte below, its outward normal from its position.
+ *   - Device pointers are plain HIP device addresses (for example the
+ *     data_ptr() of a torch tensor on the same device); host pointers are
+ *     ordinary memory. The library never frees caller memory.
+ *   - Every call returns an lks_status and never throws. On an error the
+ *     context keeps its previous state and lks_last_error() holds a message.
+ *   - Calls are asynchronous on the HIP stream given to lks_create, except
+ *     lks_objective and the sizing/report calls. A context is not thread
+ *     safe; distinct contexts are independent.
+ */
+#ifndef LKS_H_
+#define LKS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lks_ctx lks_ctx;
+
+typedef enum {
+  LKS_OK = 0,
+  LKS_E_INVALID = 1,     /* bad argument or parameter outside the scheme's range */
+  LKS_E_NOMEM = 2,       /* workspace or memory budget too small */
+  LKS_E_HIP = 3,         /* a HIP runtime call failed */
+  LKS_E_STATE = 4,       /* call out of order (e.g. backward before forward) */
+  LKS_E_DIVERGED = 5,    /* non-finite state detected */
+  LKS_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+} lks_status;
+
+/* lattice and precision */
+enum { LKS_D2Q9 = 0, LKS_D3Q19 = 1 };
+/* FP64: state and arithmetic in double.
+ * FP32DEV: state in float with the density stored as rho - 1; objective and
+ * sensitivity accumulated in double. */
+enum { LKS_FP64 = 0, LKS_FP32DEV = 1 };
+enum { LKS_OBJ_PRESSURE_DROP = 0, LKS_OBJ_HEAT = 1 };
+enum { LKS_STEADY = 0, LKS_UNSTEADY = 1 };
+
+/* Node-class byte (one per node):
+ *   bits 0-1 flow class: interior (design) node, prescribed velocity
+ *            (inlet or wall), prescribed pressure (outlet), corner;
+ *   bits 2-3 thermal class: none, prescribed temperature, prescribed zero
+ *            heat flux (adiabatic);
+ *   bit 4/5  member of the inlet/outlet set of the pressure drop
+ *            (eq:objective_pipebend);
+ *   bit 6    member of the probe set of the heat-transfer objective.
+ * Sec. 2.4 names the boundary conditions (velocity at inlets and walls,
+ * pressure and tangential velocity at outlets, temperature or heat flux). */
+#define LKS_FLOW_INTERIOR 0
+#define LKS_FLOW_VELOCITY 1
+#define LKS_FLOW_PRESSURE 2
+#define LKS_FLOW_CORNER 3
+#define LKS_THERM_DIRICHLET (1 << 2)
+#define LKS_THERM_FLUX (2 << 2)
+#define LKS_TAG_J_INLET (1 << 4)
+#define LKS_TAG_J_OUTLET (1 << 5)
+#define LKS_TAG_PROBE (1 << 6)
+
+/* Fields for lks_read_field / lks_write_field. Forward state: density
+ * deviation rho - 1, velocity, temperature, at the current level. Adjoint
+ * state: the coefficients of the adjoint equilibria at the current adjoint
+ * level, f~_i^eq = rho~ + c_i . V (eq:afeq) and g~_i^eq = Theta (eq:ageq). */
+enum {
+  LKS_FIELD_DRHO = 0,
+  LKS_FIELD_UX = 1,
+  LKS_FIELD_UY = 2,
+  LKS_FIELD_T = 3,
+  LKS_FIELD_ADJ_RHO = 4,
+  LKS_FIELD_ADJ_VX = 5,
+  LKS_FIELD_ADJ_VY = 6,
+  LKS_FIELD_ADJ_THETA = 7
+};
+
+typedef struct {
+  int nx, ny, nz;  /* nodes per axis; nz = 1 for D2Q9 */
+  int lattice;     /* LKS_D2Q9 (LKS_D3Q19 returns LKS_E_UNSUPPORTED) */
+  int precision;   /* LKS_FP64 or LKS_FP32DEV */
+  int periodic;    /* 1: periodic box, every node interior */
+} lks_grid;
+
+typedef struct {
+  double nu;          /* kinematic viscosity; A = (9/2)(1/6 - nu), eq:A */
+  double Pr;          /* Prandtl number; fluid diffusivity K_f = nu / Pr */
+  double alpha_max;   /* alpha-bar of eq:brinkman */
+  double q_alpha;     /* q_alpha of eq:brinkman */
+  double Ks_over_Kf;  /* K_s / K_f of eq:conductivity */
+  double q_K;         /* q_K of eq:conductivity */
+  int thermal;        /* 1: solve the temperature field too */
+} lks_phys;
+
+typedef struct {
+  const uint8_t *node_class; /* host, nx*ny node classes (copied) */
+  const double *u_bar;       /* host, 2*nx*ny: x block then y block; the
+                                velocity prescribed at velocity nodes (copied) */
+  const double *T_bar;       /* host, nx*ny: temperature at prescribed-T nodes
+                                (copied); may be NULL if not thermal */
+  const double *u_factor;    /* host, n_factor: u_bar is scaled by
+                                u_factor[min(n, n_factor-1)] at level n;
+                                NULL means 1 (copied) */
+  int n_factor;
+  double rho_out;            /* prescribed outlet density (p = rho/3) */
+  int objective;             /* LKS_OBJ_* */
+  int mode;                  /* LKS_STEADY or LKS_UNSTEADY */
+  int n_steps;               /* unsteady: steps N of the horizon (levels
+                                0..N); steady: ignored */
+} lks_bc;
+
+/* Create a context. Validates the problem (Sec. 2.4 ranges: 0 < nu < 1/6,
+ * 0 <= K_s, K_f <= 1/6, alpha_max >= 0, q > 0, |u_bar| <= 0.3, node classes
+ * consistent with the ring) and plans the memory: for unsteady problems the
+ * trajectory (u, T) is kept either whole or as checkpoints every K levels
+ * with K chosen as the largest interval whose storage fits
+ * mem_budget_bytes (0 = no limit). Makes no HIP call. hip_stream is a
+ * hipStream_t (NULL = the null stream). On success *out owns host memory
+ * only; bind a device workspace before computing. */
+lks_status lks_create(const lks_grid *grid, const lks_phys *phys, const lks_bc *bc,
+                      size_t mem_budget_bytes, void *hip_stream, lks_ctx **out);
+
+/* Bytes of device workspace the context needs (state, adjoint, design
+ * coefficients, boundary data, checkpoints and replay segment). */
+lks_status lks_workspace_size(const lks_ctx *ctx, size_t *bytes);
+
+/* Bind caller-owned device memory of at least lks_workspace_size bytes,
+ * 256-byte aligned. Uploads the boundary data. The memory must outlive the
+ * context's use. */
+lks_status lks_bind_workspace(lks_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Step 2: reset to the level-0 state (rho = 1, u = 0, T = 0 inside, the
+ * prescribed values on the boundary) and run `steps` LKS steps
+ * (eq:rho, eq:u, eq:T with eq:feq2, eq:geq2 and the implicit Brinkman term
+ * of eq:lbef_ex) for the design gamma_dev (device, nx*ny doubles in [0,1]).
+ * Unsteady contexts require steps == n_steps and store the trajectory. */
+lks_status lks_forward(lks_ctx *ctx, const double *gamma_dev, int steps);
+
+/* Continue the current forward state by `steps` steps without reset and
+ * without trajectory storage (steady contexts; parity and convergence runs). */
+lks_status lks_advance(lks_ctx *ctx, const double *gamma_dev, int steps);
+
+/* Step 3: the objective of the last forward run, in double. Steady: on the
+ * final state. Unsteady: averaged over levels 1..N. Synchronises the stream. */
+lks_status lks_objective(lks_ctx *ctx, double *J_host);
+
+/* Steps 4-5: ALKS adjoint sweep (eq:ap..eq:aq with eq:afeq, eq:ageq and the
+ * least-squares adjoint boundary treatment of Sec. 2.5 / Appendix A) and
+ * the sensitivity (Sec. 2.5) written to dJdgamma_dev (device, nx*ny doubles,
+ * overwritten; zero on boundary nodes). Linear in J_seed.
+ * Steady: adj_steps ALKS steps with the state frozen at the last forward
+ * level and the seed applied every step, then the sensitivity once.
+ * Unsteady: adj_steps is ignored; the sweep runs from the terminal condition
+ * f~ = g~ = 0 down to level 0, replaying checkpoint segments, and sums the
+ * sensitivity over levels. Returns LKS_E_STATE before a forward run. */
+lks_status alks_backward(lks_ctx *ctx, double J_seed, int adj_steps, double *dJdgamma_dev);
+
+/* Continue the steady adjoint by `steps` ALKS steps from its current state
+ * (no reset), with the state frozen at the current forward level; writes the
+ * sensitivity of the final level when dJdgamma_dev is not NULL. */
+lks_status alks_advance(lks_ctx *ctx, double J_seed, int steps, double *dJdgamma_dev);
+
+/* Copy field `which` (LKS_FIELD_*) of the current level to dev_out
+ * (device, nx*ny doubles). Asynchronous. */
+lks_status lks_read_field(lks_ctx *ctx, int which, double *dev_out);
+
+/* Overwrite field `which` of the current level from dev_in (device, nx*ny
+ * doubles), e.g. to start a step from a prescribed state. Asynchronous. */
+lks_status lks_write_field(lks_ctx *ctx, int which, const double *dev_in);
+
+/* Memory plan: bytes of checkpoint + replay storage, bytes of the rest of
+ * the workspace, and the checkpoint interval K (N when the whole trajectory
+ * is stored; 0 for steady problems). */
+lks_status lks_memory_report(const lks_ctx *ctx, size_t *ckpt_bytes, size_t *state_bytes,
+                             int *K);
+
+const char *lks_strerror(lks_status s);
+const char *lks_last_error(const lks_ctx *ctx);
+void lks_destroy(lks_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LKS_H_ */

@@ -1,0 +1,123 @@
+// Device-side definitions shared by the LKS/ALKS kernels and their host
+// runtime (gfx950). Lattice: D2Q9 with c0=(0,0) c1=(1,0) c2=(0,1) c3=(-1,0)
+// c4=(0,-1) c5=(1,1) c6=(-1,1) c7=(-1,-1) c8=(1,-1) and weights 4/9, 1/9,
+// 1/36 (Sec. 2.3); the numbering is the one of the boundary matrices of
+// Sec. 2.5.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lks {
+
+// Tile of the 2D kernels: 64 nodes along x (one wavefront) by 4 rows. A
+// remainder of a single column/row is merged into the last tile so that
+// every tile is at least 2 nodes wide and tall; the one-sided boundary
+// stencils then always find their nodes inside the tile plus a 1-node halo.
+constexpr int TX = 64;
+constexpr int TY = 4;
+constexpr int NTHREADS = 256;
+constexpr int LW = TX + 3;          // LDS row pitch: max tile width + halo
+constexpr int LH = TY + 3;
+constexpr int LPOS = LW * LH;
+
+// node-class byte
+constexpr int FLOW_INTERIOR = 0, FLOW_VELOCITY = 1, FLOW_PRESSURE = 2, FLOW_CORNER = 3;
+constexpr int THERM_DIRICHLET = 1, THERM_FLUX = 2;
+constexpr int TAG_J_INLET = 16, TAG_J_OUTLET = 32, TAG_PROBE = 64;
+
+struct Geo {
+  int nx, ny, N;
+  int periodic, thermal;
+  int ntx, nty;     // tiles along x and y
+  double A;         // eq:A
+  double Bf;        // B of the fluid, used on boundary nodes
+  double drho_out;  // prescribed outlet density minus 1
+};
+
+__host__ __device__ inline int tiles_along(int n, int t) {
+  int k = (n + t - 1) / t;
+  if (k > 1 && n % t == 1) --k;
+  return k;
+}
+
+__device__ inline void tile_extent(int b, int nb, int n, int t, int* lo, int* hi) {
+  *lo = b * t;
+  *hi = (b == nb - 1) ? n : (b + 1) * t;
+}
+
+template <typename R>
+struct FwdArgs {
+  const uint8_t* mask;
+  const R* inv1pa;  // 1 / (1 + alpha_gamma)
+  const R* B;       // B_gamma (thermal)
+  const R* ubx;
+  const R* uby;
+  const R* Tb;
+  const double* ufac;  // inflow factor per level
+  int level_out;       // level written by this step
+  const R* d0;
+  const R* ux0;
+  const R* uy0;
+  const R* T0;
+  R* d1;
+  R* ux1;
+  R* uy1;
+  R* T1;
+  double* acc;  // per-tile objective accumulator, or nullptr
+  int objective;
+};
+
+template <typename R>
+struct AdjArgs {
+  const uint8_t* mask;
+  const R* inv1pa;
+  const R* B;
+  const R* dA3;  // 3 alpha'(gamma)
+  const R* dB;   // B'(gamma)
+  const R* ux;   // state at the destination level n
+  const R* uy;
+  const R* T;
+  const R* r0;   // adjoint equilibrium coefficients at level n+1
+  const R* vx0;
+  const R* vy0;
+  const R* th0;
+  R* r1;         // ... at level n
+  R* vx1;
+  R* vy1;
+  R* th1;
+  double* sens;  // dJ/dgamma (double)
+  int sens_mode; // 0 none, 1 accumulate, 2 overwrite
+  double seed_dp;
+  double seed_heat;
+};
+
+// kernel launchers (lks_kernels.hip)
+template <typename R>
+void launch_coef(const Geo& g, const double* gamma, double alpha_max, double q_alpha,
+                 double Kf, double Ks, double q_K, R* inv1pa, R* B, R* dA3, R* dB,
+                 hipStream_t s);
+template <typename R>
+void launch_init(const Geo& g, const uint8_t* mask, const R* ubx, const R* uby, const R* Tb,
+                 double fac0, R* d, R* ux, R* uy, R* T, hipStream_t s);
+template <typename R>
+void launch_lks_step(const Geo& g, const FwdArgs<R>& a, hipStream_t s);
+template <typename R>
+void launch_alks_step(const Geo& g, const AdjArgs<R>& a, R* ring, hipStream_t s);
+template <typename R>
+void launch_pressure_drop(const Geo& g, const uint8_t* mask, const R* d, double* out,
+                          hipStream_t s);
+template <typename R>
+void launch_probe_heat(const Geo& g, const uint8_t* mask, const R* ux, const R* T, double* out,
+                       hipStream_t s);
+void launch_sum(const double* v, int n, double* out, hipStream_t s);
+void launch_fill(double* p, size_t n, double v, hipStream_t s);
+template <typename R>
+void launch_fill_r(R* p, size_t n, hipStream_t s);
+template <typename R>
+void launch_to_double(const R* src, double* dst, size_t n, hipStream_t s);
+template <typename R>
+void launch_from_double(const double* src, R* dst, size_t n, hipStream_t s);
+template <typename R>
+void launch_finite_check(const R* a, size_t n, int* flag, hipStream_t s);
+
+}  // namespace lks

@@ -1,0 +1,764 @@
+// Host runtime and C ABI of the LKS/ALKS library (see include/lks.h).
+//
+// Owns the problem description, validates it, plans the device workspace
+// (state, adjoint, design coefficients, boundary data and -- for unsteady
+// problems -- checkpoints every K levels plus one replay segment), and drives
+// the forward sweep, the adjoint sweep and the checkpoint replay on one HIP
+// stream.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lks.h"
+#include "lks_device.h"
+
+using lks::Geo;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Plan {
+  int K = 0;          // checkpoint interval (N+1: whole trajectory kept)
+  int n_ckpt = 0;     // checkpoints at levels 0, K, 2K, ..., ls
+  int n_slots = 0;    // replay segment slots (K-1)
+  int ls = 0;         // level of the last checkpoint
+  size_t ckpt_bytes = 0;
+  size_t total = 0;
+};
+
+}  // namespace
+
+struct lks_ctx {
+  lks_grid grid{};
+  lks_phys phys{};
+  int objective = 0, mode = 0, n_steps = 0;
+  double rho_out = 1.0;
+  std::vector<uint8_t> mask;
+  std::vector<double> ubar, Tbar, ufac;
+  int n_in = 0, n_out = 0;
+  Geo geo{};
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  int rsz = 8;
+  Plan plan;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool bound = false;
+  // carved device pointers (element type depends on precision)
+  uint8_t* d_mask = nullptr;
+  void *ubx = nullptr, *uby = nullptr, *Tb = nullptr;
+  double* d_ufac = nullptr;
+  void *inv1pa = nullptr, *B = nullptr, *dA3 = nullptr, *dB = nullptr;
+  void* S[2][4] = {};    // forward ping-pong: drho, ux, uy, T
+  void* P[2][4] = {};    // adjoint ping-pong: rho~, Vx, Vy, Theta
+  void* C = nullptr;     // checkpoints
+  void* Seg = nullptr;   // replay segment
+  void* ring = nullptr;  // completed moments of the ring nodes (adjoint)
+  double* acc = nullptr; // per-tile objective accumulators
+  double* scal = nullptr;
+  int* flag = nullptr;
+  // run state
+  bool have_forward = false;
+  bool have_adjoint = false;
+  int cur = 0;      // steady forward: ping-pong index of the current level
+  int acur = 0;     // adjoint: ping-pong index of the current level
+  int last_level = 0;
+  std::string err;
+};
+
+namespace {
+
+lks_status fail(lks_ctx* c, lks_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+bool hip_ok(lks_ctx* c, hipError_t e, const char* what, lks_status* st) {
+  if (e == hipSuccess) return true;
+  *st = fail(c, LKS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return false;
+}
+
+int n_tiles(const Geo& g) { return g.ntx * g.nty; }
+
+// fields stored per checkpoint / per replay slot
+int ckpt_fields(const lks_ctx* c) { return c->phys.thermal ? 4 : 3; }
+int slot_fields(const lks_ctx* c) { return c->phys.thermal ? 3 : 2; }
+
+size_t traj_bytes(const lks_ctx* c, int K) {
+  const size_t N = size_t(c->geo.N), r = size_t(c->rsz);
+  const int n = c->n_steps;
+  size_t n_ckpt = size_t(n / K) + 1;
+  return n_ckpt * ckpt_fields(c) * N * r + size_t(K - 1) * slot_fields(c) * N * r;
+}
+
+size_t base_bytes(const lks_ctx* c) {
+  const size_t N = size_t(c->geo.N), r = size_t(c->rsz);
+  size_t b = 0;
+  b += align256(N);                        // mask
+  b += 3 * align256(N * r);                // ubx, uby, Tb
+  b += align256(sizeof(double) * c->ufac.size());
+  b += 4 * align256(N * r);                // coefficients
+  b += 8 * align256(N * r);                // forward ping-pong
+  b += 8 * align256(N * r);                // adjoint ping-pong
+  b += align256(sizeof(double) * n_tiles(c->geo));
+  b += align256(9 * r * size_t(2 * (c->geo.nx + c->geo.ny)));  // ring moments
+  b += align256(sizeof(double) * 8);
+  b += align256(sizeof(int) * 4);
+  return b;
+}
+
+// Largest checkpoint interval whose storage fits the budget: the fewest
+// replayed steps for the memory given. K = N+1 keeps every level.
+lks_status plan_memory(lks_ctx* c) {
+  Plan p;
+  size_t base = base_bytes(c);
+  if (c->mode != LKS_UNSTEADY) {
+    p.total = base;
+    c->plan = p;
+    return LKS_OK;
+  }
+  const int n = c->n_steps;
+  int best = 0;
+  for (int K = n + 1; K >= 1; --K) {
+    size_t t = traj_bytes(c, K) + 2 * 256;
+    if (c->budget == 0 || base + t <= c->budget) {
+      best = K;
+      break;
+    }
+  }
+  if (best == 0) {
+    // report the smallest footprint for the message
+    size_t mn = ~size_t(0);
+    for (int K = 1; K <= n + 1; ++K) mn = std::min(mn, traj_bytes(c, K));
+    char buf[160];
+    snprintf(buf, sizeof buf, "memory budget %zu B below the smallest checkpoint plan (%zu B)",
+             c->budget, base + mn);
+    return fail(nullptr, LKS_E_NOMEM, buf);
+  }
+  p.K = best;
+  p.n_ckpt = n / best + 1;
+  p.n_slots = best - 1;
+  p.ls = (n / best) * best;
+  p.ckpt_bytes = traj_bytes(c, best);
+  p.total = base + align256(size_t(p.n_ckpt) * ckpt_fields(c) * c->geo.N * c->rsz) +
+            align256(size_t(p.n_slots) * slot_fields(c) * c->geo.N * c->rsz);
+  c->plan = p;
+  return LKS_OK;
+}
+
+lks_status validate(const lks_grid* gr, const lks_phys* ph, const lks_bc* bc) {
+  if (!gr || !ph || !bc) return fail(nullptr, LKS_E_INVALID, "null descriptor");
+  if (gr->lattice == LKS_D3Q19) return fail(nullptr, LKS_E_UNSUPPORTED, "D3Q19 is not built");
+  if (gr->lattice != LKS_D2Q9) return fail(nullptr, LKS_E_INVALID, "unknown lattice");
+  if (gr->precision != LKS_FP64 && gr->precision != LKS_FP32DEV)
+    return fail(nullptr, LKS_E_INVALID, "unknown precision");
+  if (gr->nz > 1) return fail(nullptr, LKS_E_INVALID, "nz must be 1 for D2Q9");
+  const int minn = gr->periodic ? 3 : 4;
+  if (gr->nx < minn || gr->ny < minn) return fail(nullptr, LKS_E_INVALID, "grid too small");
+  if ((long long)gr->nx * gr->ny > (1LL << 31) / 16)
+    return fail(nullptr, LKS_E_INVALID, "grid too large");
+  if (!(ph->nu > 0.0 && ph->nu < 1.0 / 6.0))
+    return fail(nullptr, LKS_E_INVALID, "nu must lie in (0, 1/6) (A > 0, eq:A)");
+  if (!(ph->alpha_max >= 0.0) || !(ph->q_alpha > 0.0))
+    return fail(nullptr, LKS_E_INVALID, "alpha_max must be >= 0 and q_alpha > 0");
+  if (ph->thermal) {
+    if (!(ph->Pr > 0.0) || !(ph->Ks_over_Kf >= 0.0) || !(ph->q_K > 0.0))
+      return fail(nullptr, LKS_E_INVALID, "Pr, q_K must be > 0 and Ks/Kf >= 0");
+    double Kf = ph->nu / ph->Pr, Ks = Kf * ph->Ks_over_Kf;
+    if (Kf > 1.0 / 6.0 || Ks > 1.0 / 6.0)
+      return fail(nullptr, LKS_E_INVALID, "diffusivity above 1/6 gives B < 0 (eq:B)");
+  }
+  if (!bc->node_class || !bc->u_bar) return fail(nullptr, LKS_E_INVALID, "null boundary data");
+  if (ph->thermal && !bc->T_bar) return fail(nullptr, LKS_E_INVALID, "thermal needs T_bar");
+  if (bc->objective != LKS_OBJ_PRESSURE_DROP && bc->objective != LKS_OBJ_HEAT)
+    return fail(nullptr, LKS_E_INVALID, "unknown objective");
+  if (bc->objective == LKS_OBJ_HEAT && !ph->thermal)
+    return fail(nullptr, LKS_E_INVALID, "heat objective needs a thermal problem");
+  if (bc->mode != LKS_STEADY && bc->mode != LKS_UNSTEADY)
+    return fail(nullptr, LKS_E_INVALID, "unknown mode");
+  if (bc->mode == LKS_UNSTEADY && bc->n_steps < 1)
+    return fail(nullptr, LKS_E_INVALID, "unsteady needs n_steps >= 1");
+  if (bc->u_factor && bc->n_factor < 1) return fail(nullptr, LKS_E_INVALID, "n_factor < 1");
+  if (!(bc->rho_out > 0.0)) return fail(nullptr, LKS_E_INVALID, "rho_out must be > 0");
+  const int nx = gr->nx, ny = gr->ny, N = nx * ny;
+  double fmax = 1.0;
+  if (bc->u_factor)
+    for (int n = 0; n < bc->n_factor; ++n) {
+      if (!std::isfinite(bc->u_factor[n])) return fail(nullptr, LKS_E_INVALID, "u_factor not finite");
+      fmax = std::max(fmax, std::fabs(bc->u_factor[n]));
+    }
+  for (int k = 0; k < N; ++k) {
+    const int i = k % nx, j = k / nx;
+    const int m = bc->node_class[k];
+    if (m & 0x80) return fail(nullptr, LKS_E_INVALID, "reserved node-class bit set");
+    const double u = std::hypot(bc->u_bar[k], bc->u_bar[N + k]) * fmax;
+    if (!(u <= 0.3)) return fail(nullptr, LKS_E_INVALID, "prescribed |u| above 0.3");
+    if (gr->periodic) continue;
+    const bool ring = i == 0 || j == 0 || i == nx - 1 || j == ny - 1;
+    const bool corner = (i == 0 || i == nx - 1) && (j == 0 || j == ny - 1);
+    const int fc = m & 3, tc = (m >> 2) & 3;
+    if (corner) {
+      if (fc != LKS_FLOW_CORNER) return fail(nullptr, LKS_E_INVALID, "corner node not classed corner");
+      if (m & (LKS_TAG_J_INLET | LKS_TAG_J_OUTLET | LKS_TAG_PROBE))
+        return fail(nullptr, LKS_E_INVALID, "corner nodes carry no objective tag");
+    } else if (ring) {
+      if (fc != LKS_FLOW_VELOCITY && fc != LKS_FLOW_PRESSURE)
+        return fail(nullptr, LKS_E_INVALID, "ring node needs a velocity or pressure class");
+      if (ph->thermal && tc != 1 && tc != 2)
+        return fail(nullptr, LKS_E_INVALID, "ring node needs a thermal class");
+    } else {
+      if (fc != LKS_FLOW_INTERIOR || tc != 0)
+        return fail(nullptr, LKS_E_INVALID, "interior node with a boundary class");
+      if (m & (LKS_TAG_J_INLET | LKS_TAG_J_OUTLET))
+        return fail(nullptr, LKS_E_INVALID, "pressure-drop tags belong on ring nodes");
+    }
+    if (tc == 3) return fail(nullptr, LKS_E_INVALID, "unknown thermal class");
+  }
+  return LKS_OK;
+}
+
+template <typename R>
+R* rp(void* p) { return static_cast<R*>(p); }
+
+// ---------------------------------------------------------------------------
+// drivers
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Run {
+  lks_ctx* c;
+  const Geo& g;
+  size_t N;
+  explicit Run(lks_ctx* cc) : c(cc), g(cc->geo), N(size_t(cc->geo.N)) {}
+
+  R* ckpt(int m, int f) { return rp<R>(c->C) + (size_t(m) * ckpt_fields(c) + f) * N; }
+  R* slot(int s, int f) { return rp<R>(c->Seg) + (size_t(s) * slot_fields(c) + f) * N; }
+
+  // pointers (drho, ux, uy, T) of level n of an unsteady run; seg_base is
+  // the first level of the segment held in the replay slots
+  void level(int n, int seg_base, R* out[4]) {
+    const int K = c->plan.K;
+    if (n % K == 0) {
+      const int m = n / K;
+      out[0] = ckpt(m, 0);
+      out[1] = ckpt(m, 1);
+      out[2] = ckpt(m, 2);
+      out[3] = c->phys.thermal ? ckpt(m, 3) : nullptr;
+      return;
+    }
+    if (n > seg_base) {
+      const int s = n - seg_base - 1;
+      out[0] = rp<R>(c->S[n & 1][0]);
+      out[1] = slot(s, 0);
+      out[2] = slot(s, 1);
+      out[3] = c->phys.thermal ? slot(s, 2) : nullptr;
+      return;
+    }
+    for (int f = 0; f < 4; ++f) out[f] = rp<R>(c->S[n & 1][f]);
+  }
+
+  void step(R* const in[4], R* const out[4], int level_out, double* acc) {
+    lks::FwdArgs<R> a;
+    a.mask = c->d_mask;
+    a.inv1pa = rp<R>(c->inv1pa);
+    a.B = rp<R>(c->B);
+    a.ubx = rp<R>(c->ubx);
+    a.uby = rp<R>(c->uby);
+    a.Tb = rp<R>(c->Tb);
+    a.ufac = c->d_ufac;
+    a.level_out = std::min(level_out, int(c->ufac.size()) - 1);
+    a.d0 = in[0];
+    a.ux0 = in[1];
+    a.uy0 = in[2];
+    a.T0 = in[3];
+    a.d1 = out[0];
+    a.ux1 = out[1];
+    a.uy1 = out[2];
+    a.T1 = out[3];
+    a.acc = acc;
+    a.objective = c->objective;
+    lks::launch_lks_step<R>(g, a, c->stream);
+  }
+
+  void coefficients(const double* gamma) {
+    const double Kf = c->phys.thermal ? c->phys.nu / c->phys.Pr : 0.0;
+    const double Ks = Kf * (c->phys.thermal ? c->phys.Ks_over_Kf : 1.0);
+    lks::launch_coef<R>(g, gamma, c->phys.alpha_max, c->phys.q_alpha, Kf, Ks,
+                        c->phys.thermal ? c->phys.q_K : 1.0, rp<R>(c->inv1pa), rp<R>(c->B),
+                        rp<R>(c->dA3), rp<R>(c->dB), c->stream);
+  }
+
+  void init(R* const s[4]) {
+    lks::launch_init<R>(g, c->d_mask, rp<R>(c->ubx), rp<R>(c->uby), rp<R>(c->Tb), c->ufac[0],
+                        s[0], s[1], s[2], s[3], c->stream);
+  }
+
+  void forward(const double* gamma, int steps) {
+    coefficients(gamma);
+    if (c->mode == LKS_STEADY) {
+      R* s0[4];
+      for (int f = 0; f < 4; ++f) s0[f] = rp<R>(c->S[0][f]);
+      init(s0);
+      c->cur = 0;
+      advance(steps);
+      return;
+    }
+    lks::launch_fill(c->acc, size_t(n_tiles(g)), 0.0, c->stream);
+    R* lv[4];
+    level(0, c->plan.ls, lv);
+    init(lv);
+    for (int n = 0; n < steps; ++n) {
+      R* in[4];
+      R* out[4];
+      level(n, c->plan.ls, in);
+      level(n + 1, c->plan.ls, out);
+      step(in, out, n + 1, c->acc);
+    }
+    R* last[4];
+    level(steps, c->plan.ls, last);
+    lks::launch_finite_check<R>(last[1], N, c->flag, c->stream);
+    c->last_level = steps;
+  }
+
+  void advance(int steps) {
+    for (int n = 0; n < steps; ++n) {
+      R* in[4];
+      R* out[4];
+      for (int f = 0; f < 4; ++f) {
+        in[f] = rp<R>(c->S[c->cur][f]);
+        out[f] = rp<R>(c->S[c->cur ^ 1][f]);
+      }
+      step(in, out, c->last_level + n + 1, nullptr);
+      c->cur ^= 1;
+    }
+    c->last_level += steps;
+    lks::launch_finite_check<R>(rp<R>(c->S[c->cur][1]), N, c->flag, c->stream);
+    if (c->objective == LKS_OBJ_PRESSURE_DROP)
+      lks::launch_pressure_drop<R>(g, c->d_mask, rp<R>(c->S[c->cur][0]), c->scal, c->stream);
+    else
+      probe_heat_steady();
+  }
+
+  void probe_heat_steady() {
+    lks::launch_probe_heat<R>(g, c->d_mask, rp<R>(c->S[c->cur][1]), rp<R>(c->S[c->cur][3]),
+                              c->scal, c->stream);
+  }
+
+  void zero_adjoint(int which) {
+    for (int f = 0; f < 4; ++f) lks::launch_fill_r<R>(rp<R>(c->P[which][f]), N, c->stream);
+  }
+
+  void adj_step(const R* ux, const R* uy, const R* T, double sdp, double sh, double* sens,
+                int mode) {
+    lks::AdjArgs<R> a;
+    a.mask = c->d_mask;
+    a.inv1pa = rp<R>(c->inv1pa);
+    a.B = rp<R>(c->B);
+    a.dA3 = rp<R>(c->dA3);
+    a.dB = rp<R>(c->dB);
+    a.ux = ux;
+    a.uy = uy;
+    a.T = T ? T : ux;
+    const int i0 = c->acur, i1 = c->acur ^ 1;
+    a.r0 = rp<R>(c->P[i0][0]);
+    a.vx0 = rp<R>(c->P[i0][1]);
+    a.vy0 = rp<R>(c->P[i0][2]);
+    a.th0 = rp<R>(c->P[i0][3]);
+    a.r1 = rp<R>(c->P[i1][0]);
+    a.vx1 = rp<R>(c->P[i1][1]);
+    a.vy1 = rp<R>(c->P[i1][2]);
+    a.th1 = rp<R>(c->P[i1][3]);
+    a.sens = sens;
+    a.sens_mode = sens ? mode : 0;
+    a.seed_dp = sdp;
+    a.seed_heat = sh;
+    lks::launch_alks_step<R>(g, a, rp<R>(c->ring), c->stream);
+    c->acur = i1;
+  }
+
+  void adjoint_steady(double seed, int steps, double* dJ, bool reset) {
+    if (reset) {
+      c->acur = 0;
+      zero_adjoint(0);
+    }
+    const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? seed : 0.0;
+    const double sh = c->objective == LKS_OBJ_HEAT ? seed : 0.0;
+    const R* ux = rp<R>(c->S[c->cur][1]);
+    const R* uy = rp<R>(c->S[c->cur][2]);
+    const R* T = c->phys.thermal ? rp<R>(c->S[c->cur][3]) : nullptr;
+    for (int n = 0; n < steps; ++n) {
+      const bool last = n == steps - 1;
+      adj_step(ux, uy, T, sdp, sh, last ? dJ : nullptr, 2);
+    }
+  }
+
+  void adjoint_unsteady(double seed, double* dJ) {
+    const int Nst = c->n_steps, K = c->plan.K;
+    lks::launch_fill(dJ, N, 0.0, c->stream);
+    c->acur = 0;
+    zero_adjoint(0);
+    for (int b = c->plan.ls; b >= 0; b -= K) {
+      const int top = (b == c->plan.ls) ? Nst : b + K - 1;
+      if (b != c->plan.ls) {
+        // replay levels b+1 .. top into the segment slots
+        for (int n = b; n < top; ++n) {
+          R* in[4];
+          R* out[4];
+          level(n, b, in);
+          level(n + 1, b, out);
+          step(in, out, n + 1, nullptr);
+        }
+      }
+      for (int n = top; n >= b; --n) {
+        R* lv[4];
+        level(n, b, lv);
+        const double w = n >= 1 ? seed / Nst : 0.0;
+        const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? w : 0.0;
+        const double sh = c->objective == LKS_OBJ_HEAT ? w : 0.0;
+        adj_step(lv[1], lv[2], lv[3], sdp, sh, dJ, 1);
+      }
+    }
+  }
+
+  lks_status read(int which, double* out) {
+    const void* src = nullptr;
+    if (which <= LKS_FIELD_T) {
+      if (which == LKS_FIELD_T && !c->phys.thermal) return LKS_E_INVALID;
+      if (c->mode == LKS_STEADY) {
+        src = c->S[c->cur][which];
+      } else {
+        R* lv[4];
+        level(c->last_level, c->plan.ls, lv);
+        src = lv[which];
+      }
+    } else if (which <= LKS_FIELD_ADJ_THETA) {
+      if (which == LKS_FIELD_ADJ_THETA && !c->phys.thermal) return LKS_E_INVALID;
+      src = c->P[c->acur][which - LKS_FIELD_ADJ_RHO];
+    } else {
+      return LKS_E_INVALID;
+    }
+    lks::launch_to_double<R>(static_cast<const R*>(src), out, N, c->stream);
+    return LKS_OK;
+  }
+
+  lks_status write(int which, const double* in) {
+    void* dst = nullptr;
+    if (which <= LKS_FIELD_T) {
+      if (which == LKS_FIELD_T && !c->phys.thermal) return LKS_E_INVALID;
+      if (c->mode != LKS_STEADY) return LKS_E_UNSUPPORTED;
+      dst = c->S[c->cur][which];
+    } else if (which <= LKS_FIELD_ADJ_THETA) {
+      if (which == LKS_FIELD_ADJ_THETA && !c->phys.thermal) return LKS_E_INVALID;
+      dst = c->P[c->acur][which - LKS_FIELD_ADJ_RHO];
+    } else {
+      return LKS_E_INVALID;
+    }
+    lks::launch_from_double<R>(in, static_cast<R*>(dst), N, c->stream);
+    return LKS_OK;
+  }
+};
+
+lks_status check_launch(lks_ctx* c) {
+  hipError_t e = hipGetLastError();
+  lks_status st = LKS_OK;
+  hip_ok(c, e, "kernel launch", &st);
+  return st;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* bc,
+                      size_t mem_budget_bytes, void* hip_stream, lks_ctx** out) {
+  if (!out) return fail(nullptr, LKS_E_INVALID, "null output pointer");
+  *out = nullptr;
+  lks_status st = validate(grid, phys, bc);
+  if (st != LKS_OK) return st;
+  lks_ctx* c = new lks_ctx();
+  c->grid = *grid;
+  c->grid.nz = 1;
+  c->phys = *phys;
+  c->objective = bc->objective;
+  c->mode = bc->mode;
+  c->n_steps = bc->mode == LKS_UNSTEADY ? bc->n_steps : 0;
+  c->rho_out = bc->rho_out;
+  const int N = grid->nx * grid->ny;
+  c->mask.assign(bc->node_class, bc->node_class + N);
+  if (grid->periodic)
+    for (auto& m : c->mask) m &= uint8_t(~15);
+  c->ubar.assign(bc->u_bar, bc->u_bar + 2 * N);
+  if (bc->T_bar) c->Tbar.assign(bc->T_bar, bc->T_bar + N);
+  else c->Tbar.assign(N, 0.0);
+  if (bc->u_factor) c->ufac.assign(bc->u_factor, bc->u_factor + bc->n_factor);
+  else c->ufac.assign(1, 1.0);
+  for (int k = 0; k < N; ++k) {
+    if (c->mask[k] & LKS_TAG_J_INLET) ++c->n_in;
+    if (c->mask[k] & LKS_TAG_J_OUTLET) ++c->n_out;
+  }
+  Geo& g = c->geo;
+  g.nx = grid->nx;
+  g.ny = grid->ny;
+  g.N = N;
+  g.periodic = grid->periodic ? 1 : 0;
+  g.thermal = phys->thermal ? 1 : 0;
+  g.ntx = lks::tiles_along(g.nx, lks::TX);
+  g.nty = lks::tiles_along(g.ny, lks::TY);
+  g.A = 4.5 * (1.0 / 6.0 - phys->nu);
+  const double Kf = phys->thermal ? phys->nu / phys->Pr : 0.0;
+  g.Bf = 3.0 * (1.0 / 6.0 - Kf);
+  g.drho_out = bc->rho_out - 1.0;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->budget = mem_budget_bytes;
+  c->rsz = grid->precision == LKS_FP64 ? 8 : 4;
+  st = plan_memory(c);
+  if (st != LKS_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return LKS_OK;
+}
+
+lks_status lks_workspace_size(const lks_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return LKS_E_INVALID;
+  *bytes = c->plan.total;
+  return LKS_OK;
+}
+
+lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c) return LKS_E_INVALID;
+  if (!dev_ptr) return fail(c, LKS_E_INVALID, "null workspace");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) & 255)
+    return fail(c, LKS_E_INVALID, "workspace must be 256-byte aligned");
+  if (bytes < c->plan.total) return fail(c, LKS_E_NOMEM, "workspace smaller than lks_workspace_size");
+  const size_t N = size_t(c->geo.N), r = size_t(c->rsz);
+  char* p = static_cast<char*>(dev_ptr);
+  auto take = [&](size_t b) {
+    char* q = p;
+    p += align256(b);
+    return q;
+  };
+  c->ws = static_cast<char*>(dev_ptr);
+  c->ws_bytes = bytes;
+  c->d_mask = reinterpret_cast<uint8_t*>(take(N));
+  c->ubx = take(N * r);
+  c->uby = take(N * r);
+  c->Tb = take(N * r);
+  c->d_ufac = reinterpret_cast<double*>(take(sizeof(double) * c->ufac.size()));
+  c->inv1pa = take(N * r);
+  c->B = take(N * r);
+  c->dA3 = take(N * r);
+  c->dB = take(N * r);
+  for (int s = 0; s < 2; ++s)
+    for (int f = 0; f < 4; ++f) c->S[s][f] = take(N * r);
+  for (int s = 0; s < 2; ++s)
+    for (int f = 0; f < 4; ++f) c->P[s][f] = take(N * r);
+  c->acc = reinterpret_cast<double*>(take(sizeof(double) * n_tiles(c->geo)));
+  c->ring = take(9 * r * size_t(2 * (c->geo.nx + c->geo.ny)));
+  c->scal = reinterpret_cast<double*>(take(sizeof(double) * 8));
+  c->flag = reinterpret_cast<int*>(take(sizeof(int) * 4));
+  if (c->mode == LKS_UNSTEADY) {
+    c->C = take(size_t(c->plan.n_ckpt) * ckpt_fields(c) * N * r);
+    c->Seg = take(size_t(c->plan.n_slots) * slot_fields(c) * N * r);
+  }
+  // upload boundary data in the working precision
+  lks_status st = LKS_OK;
+  std::vector<char> tmp(3 * N * r);
+  for (size_t k = 0; k < N; ++k) {
+    if (r == 8) {
+      reinterpret_cast<double*>(tmp.data())[k] = c->ubar[k];
+      reinterpret_cast<double*>(tmp.data())[N + k] = c->ubar[N + k];
+      reinterpret_cast<double*>(tmp.data())[2 * N + k] = c->Tbar[k];
+    } else {
+      reinterpret_cast<float*>(tmp.data())[k] = float(c->ubar[k]);
+      reinterpret_cast<float*>(tmp.data())[N + k] = float(c->ubar[N + k]);
+      reinterpret_cast<float*>(tmp.data())[2 * N + k] = float(c->Tbar[k]);
+    }
+  }
+  if (!hip_ok(c, hipMemcpyAsync(c->d_mask, c->mask.data(), N, hipMemcpyHostToDevice, c->stream),
+              "upload mask", &st) ||
+      !hip_ok(c, hipMemcpyAsync(c->ubx, tmp.data(), N * r, hipMemcpyHostToDevice, c->stream),
+              "upload u_bar", &st) ||
+      !hip_ok(c, hipMemcpyAsync(c->uby, tmp.data() + N * r, N * r, hipMemcpyHostToDevice, c->stream),
+              "upload u_bar", &st) ||
+      !hip_ok(c, hipMemcpyAsync(c->Tb, tmp.data() + 2 * N * r, N * r, hipMemcpyHostToDevice,
+                                c->stream),
+              "upload T_bar", &st) ||
+      !hip_ok(c, hipMemcpyAsync(c->d_ufac, c->ufac.data(), sizeof(double) * c->ufac.size(),
+                                hipMemcpyHostToDevice, c->stream),
+              "upload u_factor", &st) ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "bind sync", &st))
+    return st;
+  // clear the state so that an unused thermal field reads as zero
+  for (int s = 0; s < 2; ++s)
+    for (int f = 0; f < 4; ++f) {
+      if (r == 8) lks::launch_fill_r<double>(static_cast<double*>(c->S[s][f]), N, c->stream);
+      else lks::launch_fill_r<float>(static_cast<float*>(c->S[s][f]), N, c->stream);
+    }
+  int zero[4] = {0, 0, 0, 0};
+  if (!hip_ok(c, hipMemcpyAsync(c->flag, zero, sizeof zero, hipMemcpyHostToDevice, c->stream),
+              "clear flag", &st) ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "bind sync", &st))
+    return st;
+  c->bound = true;
+  c->have_forward = false;
+  c->have_adjoint = false;
+  return check_launch(c);
+}
+
+static lks_status forward_impl(lks_ctx* c, const double* gamma, int steps, bool reset) {
+  if (!c) return LKS_E_INVALID;
+  if (!c->bound) return fail(c, LKS_E_STATE, "no workspace bound");
+  if (!gamma) return fail(c, LKS_E_INVALID, "null gamma");
+  if (steps < 0) return fail(c, LKS_E_INVALID, "negative step count");
+  if (c->mode == LKS_UNSTEADY) {
+    if (!reset) return fail(c, LKS_E_UNSUPPORTED, "advance applies to steady problems");
+    if (steps != c->n_steps) return fail(c, LKS_E_INVALID, "unsteady forward needs steps == n_steps");
+  } else if (!reset && !c->have_forward) {
+    return fail(c, LKS_E_STATE, "advance before forward");
+  }
+  if (reset) c->last_level = 0;
+  if (c->rsz == 8) {
+    Run<double> r(c);
+    if (reset) r.forward(gamma, steps);
+    else { r.coefficients(gamma); r.advance(steps); }
+  } else {
+    Run<float> r(c);
+    if (reset) r.forward(gamma, steps);
+    else { r.coefficients(gamma); r.advance(steps); }
+  }
+  lks_status st = check_launch(c);
+  if (st == LKS_OK) {
+    c->have_forward = true;
+    c->have_adjoint = false;
+  }
+  return st;
+}
+
+lks_status lks_forward(lks_ctx* c, const double* gamma_dev, int steps) {
+  return forward_impl(c, gamma_dev, steps, true);
+}
+
+lks_status lks_advance(lks_ctx* c, const double* gamma_dev, int steps) {
+  return forward_impl(c, gamma_dev, steps, false);
+}
+
+lks_status lks_objective(lks_ctx* c, double* J) {
+  if (!c || !J) return LKS_E_INVALID;
+  if (!c->have_forward) return fail(c, LKS_E_STATE, "objective before forward");
+  lks_status st = LKS_OK;
+  double sc[8];
+  int flag[4];
+  if (c->mode == LKS_UNSTEADY) lks::launch_sum(c->acc, n_tiles(c->geo), c->scal, c->stream);
+  if (!hip_ok(c, hipMemcpyAsync(sc, c->scal, sizeof sc, hipMemcpyDeviceToHost, c->stream),
+              "read objective", &st) ||
+      !hip_ok(c, hipMemcpyAsync(flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream),
+              "read flag", &st) ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "objective sync", &st))
+    return st;
+  if (flag[0]) return fail(c, LKS_E_DIVERGED, "non-finite velocity in the forward state");
+  const double s = sc[0];
+  if (c->objective == LKS_OBJ_PRESSURE_DROP) {
+    if (c->mode == LKS_UNSTEADY)
+      *J = (s / c->n_steps + double(c->n_in - c->n_out)) / 3.0;
+    else
+      *J = (s + double(c->n_in - c->n_out)) / 3.0;
+  } else {
+    *J = c->mode == LKS_UNSTEADY ? s / c->n_steps : s;
+  }
+  return LKS_OK;
+}
+
+static lks_status backward_impl(lks_ctx* c, double seed, int steps, double* dJ, bool reset) {
+  if (!c) return LKS_E_INVALID;
+  if (!c->have_forward) return fail(c, LKS_E_STATE, "alks_backward before lks_forward");
+  if (!std::isfinite(seed)) return fail(c, LKS_E_INVALID, "seed not finite");
+  if (c->mode == LKS_UNSTEADY) {
+    if (!reset) return fail(c, LKS_E_UNSUPPORTED, "alks_advance applies to steady problems");
+    if (!dJ) return fail(c, LKS_E_INVALID, "null dJ/dgamma");
+  } else {
+    if (steps < 1) return fail(c, LKS_E_INVALID, "steady adjoint needs adj_steps >= 1");
+    if (reset && !dJ) return fail(c, LKS_E_INVALID, "null dJ/dgamma");
+    if (!reset && !c->have_adjoint) return fail(c, LKS_E_STATE, "alks_advance before alks_backward");
+  }
+  if (c->rsz == 8) {
+    Run<double> r(c);
+    if (c->mode == LKS_UNSTEADY) r.adjoint_unsteady(seed, dJ);
+    else r.adjoint_steady(seed, steps, dJ, reset);
+  } else {
+    Run<float> r(c);
+    if (c->mode == LKS_UNSTEADY) r.adjoint_unsteady(seed, dJ);
+    else r.adjoint_steady(seed, steps, dJ, reset);
+  }
+  lks_status st = check_launch(c);
+  if (st == LKS_OK) c->have_adjoint = true;
+  return st;
+}
+
+lks_status alks_backward(lks_ctx* c, double J_seed, int adj_steps, double* dJdgamma_dev) {
+  return backward_impl(c, J_seed, adj_steps, dJdgamma_dev, true);
+}
+
+lks_status alks_advance(lks_ctx* c, double J_seed, int steps, double* dJdgamma_dev) {
+  return backward_impl(c, J_seed, steps, dJdgamma_dev, false);
+}
+
+lks_status lks_read_field(lks_ctx* c, int which, double* dev_out) {
+  if (!c || !dev_out) return LKS_E_INVALID;
+  if (!c->bound) return fail(c, LKS_E_STATE, "no workspace bound");
+  lks_status st = c->rsz == 8 ? Run<double>(c).read(which, dev_out)
+                              : Run<float>(c).read(which, dev_out);
+  if (st != LKS_OK) return fail(c, st, "field not available");
+  return check_launch(c);
+}
+
+lks_status lks_write_field(lks_ctx* c, int which, const double* dev_in) {
+  if (!c || !dev_in) return LKS_E_INVALID;
+  if (!c->bound) return fail(c, LKS_E_STATE, "no workspace bound");
+  lks_status st = c->rsz == 8 ? Run<double>(c).write(which, dev_in)
+                              : Run<float>(c).write(which, dev_in);
+  if (st != LKS_OK) return fail(c, st, "field not writable");
+  if (which <= LKS_FIELD_T) c->have_forward = true;
+  else c->have_adjoint = true;
+  return check_launch(c);
+}
+
+lks_status lks_memory_report(const lks_ctx* c, size_t* ckpt_bytes, size_t* state_bytes, int* K) {
+  if (!c) return LKS_E_INVALID;
+  if (ckpt_bytes) *ckpt_bytes = c->plan.ckpt_bytes;
+  if (state_bytes) *state_bytes = c->plan.total - c->plan.ckpt_bytes;
+  if (K) *K = c->mode == LKS_UNSTEADY ? std::min(c->plan.K, c->n_steps) : 0;
+  return LKS_OK;
+}
+
+const char* lks_strerror(lks_status s) {
+  switch (s) {
+    case LKS_OK: return "ok";
+    case LKS_E_INVALID: return "invalid argument";
+    case LKS_E_NOMEM: return "not enough memory";
+    case LKS_E_HIP: return "HIP runtime error";
+    case LKS_E_STATE: return "call out of order";
+    case LKS_E_DIVERGED: return "state diverged";
+    case LKS_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* lks_last_error(const lks_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+void lks_destroy(lks_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+"""ctypes binding of the C ABI in include/lks.h.
+
+Argument marshalling only: every step of the LKS/ALKS path runs in the HIP
+library ``liblks.so`` built from ``csrc/``. There is no fallback: if the
+library is missing this module raises at import time. PyTorch provides the
+device memory (the workspace and the gamma / dJ/dgamma tensors) and the
+stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblks.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# status codes
+LKS_OK = 0
+LKS_E_INVALID = 1
+LKS_E_NOMEM = 2
+LKS_E_HIP = 3
+LKS_E_STATE = 4
+LKS_E_DIVERGED = 5
+LKS_E_UNSUPPORTED = 6
+LKS_D2Q9, LKS_D3Q19 = 0, 1
+LKS_FP64, LKS_FP32DEV = 0, 1
+LKS_OBJ_PRESSURE_DROP, LKS_OBJ_HEAT = 0, 1
+LKS_STEADY, LKS_UNSTEADY = 0, 1
+FIELDS = {"drho": 0, "ux": 1, "uy": 2, "T": 3,
+          "adj_rho": 4, "adj_vx": 5, "adj_vy": 6, "adj_theta": 7}
+
+EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forward",
+            "lks_advance", "lks_objective", "alks_backward", "alks_advance",
+            "lks_read_field", "lks_write_field", "lks_memory_report", "lks_strerror",
+            "lks_last_error", "lks_destroy")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("lattice", ctypes.c_int), ("precision", ctypes.c_int),
+                ("periodic", ctypes.c_int)]
+
+
+class Phys(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("Pr", ctypes.c_double),
+                ("alpha_max", ctypes.c_double), ("q_alpha", ctypes.c_double),
+                ("Ks_over_Kf", ctypes.c_double), ("q_K", ctypes.c_double),
+                ("thermal", ctypes.c_int)]
+
+
+class BC(ctypes.Structure):
+    _fields_ = [("node_class", ctypes.POINTER(ctypes.c_uint8)),
+                ("u_bar", ctypes.POINTER(ctypes.c_double)),
+                ("T_bar", ctypes.POINTER(ctypes.c_double)),
+                ("u_factor", ctypes.POINTER(ctypes.c_double)),
+                ("n_factor", ctypes.c_int), ("rho_out", ctypes.c_double),
+                ("objective", ctypes.c_int), ("mode", ctypes.c_int),
+                ("n_steps", ctypes.c_int)]
+
+
+_vp = ctypes.c_void_p
+_st = ctypes.c_int
+_lib.lks_create.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Phys), ctypes.POINTER(BC),
+                            ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
+_lib.lks_create.restype = _st
+_lib.lks_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+_lib.lks_workspace_size.restype = _st
+_lib.lks_bind_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
+_lib.lks_bind_workspace.restype = _st
+_lib.lks_forward.argtypes = [_vp, _vp, ctypes.c_int]
+_lib.lks_forward.restype = _st
+_lib.lks_advance.argtypes = [_vp, _vp, ctypes.c_int]
+_lib.lks_advance.restype = _st
+_lib.lks_objective.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
+_lib.lks_objective.restype = _st
+_lib.alks_backward.argtypes = [_vp, ctypes.c_double, ctypes.c_int, _vp]
+_lib.alks_backward.restype = _st
+_lib.alks_advance.argtypes = [_vp, ctypes.c_double, ctypes.c_int, _vp]
+_lib.alks_advance.restype = _st
+_lib.lks_read_field.argtypes = [_vp, ctypes.c_int, _vp]
+_lib.lks_read_field.restype = _st
+_lib.lks_write_field.argtypes = [_vp, ctypes.c_int, _vp]
+_lib.lks_write_field.restype = _st
+_lib.lks_memory_report.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int)]
+_lib.lks_memory_report.restype = _st
+_lib.lks_strerror.argtypes = [ctypes.c_int]
+_lib.lks_strerror.restype = ctypes.c_char_p
+_lib.lks_last_error.argtypes = [_vp]
+_lib.lks_last_error.restype = ctypes.c_char_p
+_lib.lks_destroy.argtypes = [_vp]
+_lib.lks_destroy.restype = None
+
+
+class LKSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_lib.lks_strerror(status).decode()}: {msg}")
+        self.status = status
+
+
+def lib():
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != LKS_OK:
+        raise LKSError(status, _lib.lks_last_error(ctx).decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class LKS:
+    """One forward/adjoint problem bound to a device workspace.
+
+    ``wl`` is a workloads.Workload. ``precision`` is "fp64" or "fp32".
+    ``mem_budget`` bounds the unsteady trajectory storage (bytes, 0 = none).
+    """
+
+    def __init__(self, wl, precision="fp64", mem_budget=0, device=None, stream=None,
+                 bind=True):
+        self.wl = wl
+        self.N = wl.nx * wl.ny
+        self._mask = np.ascontiguousarray(wl.mask, dtype=np.uint8).reshape(-1)
+        self._ubar = np.ascontiguousarray(wl.ubar, dtype=np.float64).reshape(-1)
+        self._Tbar = np.ascontiguousarray(wl.Tbar, dtype=np.float64).reshape(-1)
+        self._ufac = np.ascontiguousarray(wl.ufac, dtype=np.float64).reshape(-1)
+        prec = LKS_FP64 if precision == "fp64" else LKS_FP32DEV
+        self.grid = Grid(wl.nx, wl.ny, 1, LKS_D2Q9, prec, int(wl.periodic))
+        self.phys = Phys(wl.nu, wl.Pr, wl.alpha_max, wl.q_alpha, wl.Ks_over_Kf, wl.q_K,
+                         int(wl.thermal))
+        self.bc = BC(self._mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                     _dptr(self._ubar), _dptr(self._Tbar), _dptr(self._ufac),
+                     len(self._ufac), wl.rho_out, wl.objective, wl.mode,
+                     wl.n_fwd if wl.mode == LKS_UNSTEADY else 0)
+        self.device = device
+        if bind and stream is None:
+            import torch
+            stream = torch.cuda.current_stream(torch.device(device or "cuda")).cuda_stream
+        self.stream = stream
+        self.workspace = None
+        self.ctx = _vp()
+        _check(_lib.lks_create(ctypes.byref(self.grid), ctypes.byref(self.phys),
+                               ctypes.byref(self.bc), ctypes.c_size_t(int(mem_budget)),
+                               _vp(stream or 0), ctypes.byref(self.ctx)))
+        if bind:
+            self.bind()
+
+    # -- workspace -------------------------------------------------------
+    def workspace_size(self):
+        n = ctypes.c_size_t()
+        _check(_lib.lks_workspace_size(self.ctx, ctypes.byref(n)), self.ctx)
+        return n.value
+
+    def bind(self):
+        """Allocate the workspace as a torch tensor and hand it to the library."""
+        import torch
+        n = self.workspace_size()
+        self.workspace = torch.empty(n + 256, dtype=torch.uint8,
+                                     device=torch.device(self.device or "cuda"))
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        _check(_lib.lks_bind_workspace(self.ctx, _vp(aligned), ctypes.c_size_t(n)), self.ctx)
+
+    # -- calls -----------------------------------------------------------
+    def forward(self, gamma, steps=None):
+        steps = self.wl.n_fwd if steps is None else steps
+        _check(_lib.lks_forward(self.ctx, _vp(gamma.data_ptr()), int(steps)), self.ctx)
+
+    def advance(self, gamma, steps):
+        _check(_lib.lks_advance(self.ctx, _vp(gamma.data_ptr()), int(steps)), self.ctx)
+
+    def objective(self):
+        J = ctypes.c_double()
+        _check(_lib.lks_objective(self.ctx, ctypes.byref(J)), self.ctx)
+        return J.value
+
+    def backward(self, seed, out, adj_steps=None):
+        adj_steps = self.wl.n_adj if adj_steps is None else adj_steps
+        _check(_lib.alks_backward(self.ctx, float(seed), int(adj_steps), _vp(out.data_ptr())),
+               self.ctx)
+
+    def adjoint_advance(self, seed, steps, out=None):
+        _check(_lib.alks_advance(self.ctx, float(seed), int(steps),
+                                 _vp(out.data_ptr() if out is not None else 0)), self.ctx)
+
+    def read(self, name, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float64, device=self.workspace.device)
+        _check(_lib.lks_read_field(self.ctx, FIELDS[name], _vp(out.data_ptr())), self.ctx)
+        return out
+
+    def write(self, name, t):
+        _check(_lib.lks_write_field(self.ctx, FIELDS[name], _vp(t.data_ptr())), self.ctx)
+
+    def memory_report(self):
+        a, b, k = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int()
+        _check(_lib.lks_memory_report(self.ctx, ctypes.byref(a), ctypes.byref(b),
+                                      ctypes.byref(k)), self.ctx)
+        return {"ckpt_bytes": a.value, "state_bytes": b.value, "K": k.value}
+
+    def close(self):
+        if self.ctx:
+            _lib.lks_destroy(self.ctx)
+            self.ctx = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+

@@ -210,6 +210,9 @@ def unsteady_thermal_channel(nx=1024, ny=512, Re=200.0, Pr=6.0, sigma=8.0,
     time-averaged enthalpy flux through the last interior column."""
     H = ny - 1
     u_max = Re * nu / H
+    if u_max > 0.1:                       # keep the inflow low-Mach
+        u_max = 0.1
+        nu = u_max * H / Re
     mask = channel_mask(nx, ny, thermal=True, probe_col=nx - 2)
     ubar, Tbar = channel_boundary_values(nx, ny, u_max, thermal=True)
     return Workload(name=f"unsteady_thermal_{nx}x{ny}_Re{Re:g}", nx=nx, ny=ny,

@@ -1,0 +1,278 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances (relative L2 over nodes, density measured as rho - 1):
+FP64 path: 1e-12 for fields, objective and gradient; FP32-deviation path:
+1e-5 for fields of a single step and 1e-3 for the gradient.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+from paper_2411_03090_amd import lks, workloads as W  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1), device=DEV)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _steady_thermal(nx, ny, seed=0):
+    wl = W.unsteady_thermal_channel(nx, ny, Re=50.0, sigma=3.0, seed=seed, n_steps=1)
+    wl.mode = W.MODE_STEADY
+    wl.ufac = np.ones(2)
+    return wl
+
+
+def _periodic(nx, ny, thermal):
+    wl = W.periodic_box(nx, ny, nu=0.08, thermal=thermal)
+    wl.alpha_max, wl.Ks_over_Kf = 0.7, 3.0
+    wl.gamma = np.clip(W.gamma_grf(nx, ny, 2.0, 5), 0.05, 1.0)
+    wl.mask = wl.mask.copy()
+    wl.mask[2:5, 3] |= W.TAG_PROBE
+    if thermal:
+        wl.objective = W.OBJ_HEAT
+    return wl
+
+
+CASES = {
+    "channel_70x37": lambda: W.steady_channel_uniform(70, 37, Re=10.0, seed=1),
+    "channel_65x9": lambda: W.steady_channel_uniform(65, 9, Re=20.0, seed=2),
+    "thermal_129x14": lambda: _steady_thermal(129, 14, seed=3),
+    "periodic_67x13": lambda: _periodic(67, 13, False),
+    "periodic_thermal_40x21": lambda: _periodic(40, 21, True),
+}
+
+
+def _random_state(wl, rng):
+    N = wl.nx * wl.ny
+    return O.State(1e-3 * rng.standard_normal(N), 0.02 * rng.standard_normal(N),
+                   0.02 * rng.standard_normal(N), rng.random(N))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_single_forward_step(case, prec):
+    say(f"[gpu] single forward step {case} {prec}")
+    wl = CASES[case]()
+    rng = np.random.default_rng(42)
+    s = _random_state(wl, rng)
+    pb = O.Problem(wl)
+    a, _, B, _ = O.coefficients(pb, wl.gamma)
+    want = O.lks_step(pb, a, B, 1.0, s)
+    ctx = lks.LKS(wl, precision=prec, device=DEV)
+    g = T(wl.gamma)
+    ctx.forward(g, 0)
+    names = ["drho", "ux", "uy"] + (["T"] if wl.thermal else [])
+    for n in names:
+        ctx.write(n, T(getattr(s, n)))
+    ctx.advance(g, 1)
+    tol = 1e-13 if prec == "fp64" else 1e-5
+    for n in names:
+        got = ctx.read(n).cpu().numpy()
+        ref = getattr(want, n)
+        assert rel(got, ref) < tol, (n, rel(got, ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_single_adjoint_step(case, prec):
+    say(f"[gpu] single adjoint step {case} {prec}")
+    wl = CASES[case]()
+    rng = np.random.default_rng(7)
+    s = _random_state(wl, rng)
+    pb = O.Problem(wl)
+    a, da, B, dB = O.coefficients(pb, wl.gamma)
+    adj1 = [rng.standard_normal(wl.nx * wl.ny) for _ in range(9)]
+    Vx1, Vy1, Th1 = O.adjoint_equilibrium(pb, B, s.ux, s.uy, adj1)
+    seed = 0.75
+    sdp = seed if wl.objective == W.OBJ_PRESSURE_DROP else 0.0
+    sh = seed if wl.objective == W.OBJ_HEAT else 0.0
+    adj0 = O.alks_step(pb, a, B, s, s, adj1, sdp, sh)
+    Vx0, Vy0, Th0 = O.adjoint_equilibrium(pb, B, s.ux, s.uy, adj0)
+    sens = np.zeros(wl.nx * wl.ny)
+    O.sens_add(pb, da, dB, s, adj0, 1.0, sens)
+
+    ctx = lks.LKS(wl, precision=prec, device=DEV)
+    g = T(wl.gamma)
+    ctx.forward(g, 0)
+    for n in ["drho", "ux", "uy"] + (["T"] if wl.thermal else []):
+        ctx.write(n, T(getattr(s, n)))
+    ctx.write("adj_rho", T(adj1[0]))
+    ctx.write("adj_vx", T(Vx1))
+    ctx.write("adj_vy", T(Vy1))
+    if wl.thermal:
+        ctx.write("adj_theta", T(Th1))
+    dJ = torch.zeros(wl.nx * wl.ny, dtype=torch.float64, device=DEV)
+    ctx.adjoint_advance(seed, 1, dJ)
+    tol = 1e-13 if prec == "fp64" else 2e-5
+    pairs = [("adj_rho", adj0[0]), ("adj_vx", Vx0), ("adj_vy", Vy0)]
+    if wl.thermal:
+        pairs.append(("adj_theta", Th0))
+    for n, ref in pairs:
+        got = ctx.read(n).cpu().numpy()
+        assert rel(got, ref) < tol, (n, rel(got, ref))
+    assert rel(dJ.cpu().numpy(), sens) < tol
+
+
+def _gpu_gradient(wl, prec, budget=0):
+    ctx = lks.LKS(wl, precision=prec, mem_budget=budget, device=DEV)
+    g = T(wl.gamma)
+    dJ = torch.empty_like(g)
+    ctx.forward(g, wl.n_fwd)
+    J = ctx.objective()
+    fields = {n: ctx.read(n).cpu().numpy() for n in ["drho", "ux", "uy"]}
+    ctx.backward(1.0, dJ, wl.n_adj)
+    torch.cuda.synchronize()
+    return J, dJ.cpu().numpy().reshape(wl.ny, wl.nx), fields, ctx
+
+
+@pytest.fixture(scope="module")
+def channel64():
+    wl = W.steady_channel_uniform(64, 64, Re=10.0, seed=0, n_fwd=3000, n_adj=3000)
+    J, sens, s, adj = O.gradient(wl)
+    return wl, J, sens, s
+
+
+def test_steady_channel64_fp64_matches_oracle(channel64):
+    say("[gpu] steady 64x64 Re=10 3000+3000 fp64")
+    wl, Jo, so, st = channel64
+    J, dJ, f, _ = _gpu_gradient(wl, "fp64")
+    assert abs(J - Jo) / abs(Jo) < 1e-12
+    assert rel(f["drho"], st.drho) < 1e-12
+    assert rel(f["ux"], st.ux) < 1e-12
+    assert rel(f["uy"], st.uy) < 1e-12
+    assert rel(dJ, so) < 1e-12
+
+
+def test_steady_channel64_fp32_within_tolerance(channel64):
+    say("[gpu] steady 64x64 Re=10 3000+3000 fp32")
+    wl, Jo, so, st = channel64
+    J, dJ, f, _ = _gpu_gradient(wl, "fp32")
+    assert abs(J - Jo) / abs(Jo) < 1e-3
+    assert rel(f["ux"], st.ux) < 1e-4
+    assert rel(dJ, so) < 1e-3
+
+
+def test_seed_linearity_bitwise():
+    say("[gpu] seed linearity")
+    wl = W.steady_channel_uniform(70, 37, Re=10.0, seed=1, n_fwd=200, n_adj=100)
+    ctx = lks.LKS(wl, precision="fp32", device=DEV)
+    g = T(wl.gamma)
+    ctx.forward(g, wl.n_fwd)
+    a = torch.empty_like(g)
+    b = torch.empty_like(g)
+    ctx.backward(1.0, a, wl.n_adj)
+    ctx.backward(4.0, b, wl.n_adj)
+    torch.cuda.synchronize()
+    assert torch.equal(4.0 * a, b)
+
+
+def _budget_for(wl, prec, K):
+    """Workspace bytes of a plan with checkpoint interval K (thermal)."""
+    c = lks.LKS(wl, precision=prec, bind=False)
+    base = c.workspace_size() - c.memory_report()["ckpt_bytes"]
+    r = 8 if prec == "fp64" else 4
+    N = wl.nx * wl.ny
+    return base + ((wl.n_fwd // K) + 1) * 4 * N * r + (K - 1) * 3 * N * r + 1024
+
+
+def _unsteady(nx, ny, n):
+    return W.unsteady_thermal_channel(nx, ny, Re=60.0, sigma=3.0, seed=4, n_steps=n,
+                                      period=n / 2)
+
+
+def test_unsteady_thermal_fp64_matches_oracle_and_checkpointing_is_exact():
+    say("[gpu] unsteady thermal 70x26 240 steps fp64, store-all and checkpointed")
+    wl = _unsteady(70, 26, 240)
+    Jo, so, _, _ = O.gradient(wl)
+    J, dJ, _, ctx = _gpu_gradient(wl, "fp64")
+    assert ctx.memory_report()["K"] == 240
+    assert abs(J - Jo) / abs(Jo) < 1e-12
+    assert rel(dJ, so) < 1e-12
+    J2, dJ2, _, ctx2 = _gpu_gradient(wl, "fp64", _budget_for(wl, "fp64", 20))
+    K = ctx2.memory_report()["K"]
+    assert 20 <= K < 240
+    say(f"[gpu]   checkpoint interval K={K}")
+    assert J2 == J
+    assert np.array_equal(dJ2, dJ)
+
+
+def test_unsteady_thermal_fp32_within_tolerance():
+    say("[gpu] unsteady thermal 70x26 240 steps fp32 checkpointed")
+    wl = _unsteady(70, 26, 240)
+    Jo, so, _, _ = O.gradient(wl)
+    J, dJ, _, ctx = _gpu_gradient(wl, "fp32", _budget_for(wl, "fp32", 17))
+    assert ctx.memory_report()["K"] < 240
+    assert abs(J - Jo) / abs(Jo) < 1e-4
+    assert rel(dJ, so) < 1e-3
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-3)])
+def test_full_size_512_steady_short_run(prec, tol):
+    """The 512x512 Re=100 workload at full size, in the launch configuration
+    the benchmark times, over a step count the oracle finishes quickly."""
+    say(f"[gpu] 512x512 Re=100 150+150 steps {prec}")
+    wl = W.steady_channel_grf(512, 512, Re=100.0, sigma=8.0, seed=0, n_fwd=150, n_adj=150)
+    Jo, so, st, _ = O.gradient(wl)
+    J, dJ, f, _ = _gpu_gradient(wl, prec)
+    assert abs(J - Jo) / abs(Jo) < tol
+    assert rel(f["ux"], st.ux) < (1e-12 if prec == "fp64" else 1e-5)
+    assert rel(dJ, so) < tol
+
+
+def test_full_size_1024x512_unsteady_thermal_short_run():
+    say("[gpu] 1024x512 Re=200 Pr=6 unsteady 30 steps fp64 checkpointed")
+    wl = W.unsteady_thermal_channel(1024, 512, n_steps=30, period=12.0)
+    # in 30 steps from rest the flow reaches only the first columns: probe there
+    wl.mask = W.channel_mask(1024, 512, thermal=True, probe_col=6)
+    Jo, so, _, _ = O.gradient(wl)
+    J, dJ, _, ctx = _gpu_gradient(wl, "fp64", _budget_for(wl, "fp64", 6))
+    assert ctx.memory_report()["K"] < 30
+    assert abs(J - Jo) / abs(Jo) < 1e-12
+    assert rel(dJ, so) < 1e-12
+
+
+def test_poiseuille_fixed_point_on_gpu():
+    """Exact solution of the scheme at any size: the pressure-driven
+    Poiseuille state is kept to round-off by the GPU step."""
+    say("[gpu] poiseuille fixed point 300x130")
+    nx, ny = 300, 130
+    wl = W.steady_channel_uniform(nx, ny, Re=20.0, seed=0)
+    wl.gamma[:] = 1.0
+    H, U, nu = ny - 1, wl.u_max, wl.nu
+    j = np.arange(ny)[:, None] * np.ones((1, nx))
+    i = np.arange(nx)[None, :] * np.ones((ny, 1))
+    ux = 4 * U * j * (H - j) / H ** 2
+    drho = 24 * nu * U * (nx - 1 - i) / H ** 2
+    ctx = lks.LKS(wl, precision="fp64", device=DEV)
+    g = T(wl.gamma)
+    ctx.forward(g, 0)
+    ctx.write("drho", T(drho))
+    ctx.write("ux", T(ux))
+    ctx.write("uy", T(np.zeros_like(ux)))
+    ctx.advance(g, 25)
+    assert np.abs(ctx.read("ux").cpu().numpy() - ux.ravel()).max() < 1e-15
+    assert np.abs(ctx.read("drho").cpu().numpy() - drho.ravel()).max() < 1e-15
+    Jp = (ny - 2) * 8 * nu * U * (nx - 1) / H ** 2
+    assert abs(ctx.objective() - Jp) / Jp < 1e-12
