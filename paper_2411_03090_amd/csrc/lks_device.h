@@ -9,16 +9,14 @@
 
 namespace lks {
 
-// Tile of the 2D kernels: 64 nodes along x (one wavefront) by 4 rows. A
-// remainder of a single column/row is merged into the last tile so that
-// every tile is at least 2 nodes wide and tall; the one-sided boundary
-// stencils then always find their nodes inside the tile plus a 1-node halo.
+// Tile of the 2D kernels: 64 nodes along x (one wavefront) by TY rows, 256
+// threads (64 x 4). A remainder of a single column/row is merged into the
+// last tile so that every tile is at least 2 nodes wide and tall; the
+// one-sided boundary stencils then always find their nodes inside the tile
+// plus its halo.
 constexpr int TX = 64;
-constexpr int TY = 4;
 constexpr int NTHREADS = 256;
-constexpr int LW = TX + 3;          // LDS row pitch: max tile width + halo
-constexpr int LH = TY + 3;
-constexpr int LPOS = LW * LH;
+constexpr int NXCD = 8;  // accelerator complex dies of an MI355X
 
 // node-class byte
 constexpr int FLOW_INTERIOR = 0, FLOW_VELOCITY = 1, FLOW_PRESSURE = 2, FLOW_CORNER = 3;
@@ -29,6 +27,7 @@ struct Geo {
   int nx, ny, N;
   int periodic, thermal;
   int ntx, nty;     // tiles along x and y
+  int ty;           // tile height
   double A;         // eq:A
   double Bf;        // B of the fluid, used on boundary nodes
   double drho_out;  // prescribed outlet density minus 1
@@ -40,10 +39,35 @@ __host__ __device__ inline int tiles_along(int n, int t) {
   return k;
 }
 
-__device__ inline void tile_extent(int b, int nb, int n, int t, int* lo, int* hi) {
-  *lo = b * t;
-  *hi = (b == nb - 1) ? n : (b + 1) * t;
+// Blocks are handed to the XCDs round-robin; block b runs tile
+// (b mod 8) * ceil(T/8) + b / 8 so that each XCD owns a contiguous band of
+// tile rows and finds the previous step's data of that band in its own L2.
+__host__ __device__ inline int xcd_blocks(int tiles) {
+  return NXCD * ((tiles + NXCD - 1) / NXCD);
 }
+
+// Least-squares completion operators of a ring orientation (host-built in
+// double, Sec. 2.5 / Appendix A). Unknown directions unk[] are those with
+// c_i.n > 0 in ascending order; known values are those with c_i.n <= 0.
+//   flow (velocity node v=0, pressure node v=1):
+//     f_unk[a] = sum_q Lf[v][a][q] f_q + Ls[v][a] s + Lk[v][a] kappa T
+//   temperature node: g_unk[a] = sum_q Ld[a][q] g_q
+//   zero-flux node with normal velocity u_n:
+//     kappa = -(sum_q (ga_q - u_n ge_q) g_q) / (A0 - 2 u_n A1 + u_n^2 A2)
+//     g_unk[a] = sum_q Lg0[a][q] g_q - kappa (hc[a] - u_n h1[a])
+struct RingOp {
+  double Lf[2][3][9];
+  double Ls[2][3];
+  double Lk[2][3];
+  double Ld[3][9];
+  double Lg0[3][9];
+  double ga[9], ge[9];
+  double A0, A1, A2;
+  double hc[3], h1[3];
+  double uw[3], ucx[3], ucy[3];  // weight and velocity of the unknown directions
+  int unk[3];
+  int pad;
+};
 
 template <typename R>
 struct FwdArgs {
@@ -85,11 +109,15 @@ struct AdjArgs {
   R* vx1;
   R* vy1;
   R* th1;
+  const RingOp* ops;  // 4 ring orientations: -x, +x, -y, +y
   double* sens;  // dJ/dgamma (double)
   int sens_mode; // 0 none, 1 accumulate, 2 overwrite
   double seed_dp;
   double seed_heat;
 };
+
+// host: the four ring operators for a given A and fluid B
+void build_ring_ops(double A, double Bf, RingOp ops[4]);
 
 // kernel launchers (lks_kernels.hip)
 template <typename R>
@@ -102,7 +130,7 @@ void launch_init(const Geo& g, const uint8_t* mask, const R* ubx, const R* uby, 
 template <typename R>
 void launch_lks_step(const Geo& g, const FwdArgs<R>& a, hipStream_t s);
 template <typename R>
-void launch_alks_step(const Geo& g, const AdjArgs<R>& a, R* ring, hipStream_t s);
+void launch_alks_step(const Geo& g, const AdjArgs<R>& a, hipStream_t s);
 template <typename R>
 void launch_pressure_drop(const Geo& g, const uint8_t* mask, const R* d, double* out,
                           hipStream_t s);

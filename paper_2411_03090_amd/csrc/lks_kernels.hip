@@ -123,6 +123,113 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
+// tiles
+// ---------------------------------------------------------------------------
+// A block owns a tile of TX x TY nodes (the last tile along an axis may be
+// up to one node larger or smaller). LDS holds the tile with a 2-node halo
+// (raw state, pitch W2) or a 1-node halo (post-collision values, pitch W1).
+// Full tiles -- TX x TY, the common case -- walk their rectangles with
+// compile-time extents; the others use the runtime extents.
+template <int TY>
+struct Tile {
+  static constexpr int W2 = TX + 1 + 4, H2 = TY + 1 + 4;
+  static constexpr int W1 = TX + 1 + 2, H1 = TY + 1 + 2;
+};
+
+__device__ inline bool block_tile(const Geo& g, int* x0, int* x1, int* y0, int* y1, int* t) {
+  const int T = g.ntx * g.nty;
+  const int nper = (T + NXCD - 1) / NXCD;
+  const int b = blockIdx.x;
+  const int tile = (b % NXCD) * nper + b / NXCD;
+  if (tile >= T) return false;
+  const int bx = tile % g.ntx, by = tile / g.ntx;
+  *x0 = bx * TX;
+  *x1 = (bx == g.ntx - 1) ? g.nx : *x0 + TX;
+  *y0 = by * g.ty;
+  *y1 = (by == g.nty - 1) ? g.ny : *y0 + g.ty;
+  *t = tile;
+  return true;
+}
+
+// Visit the positions (lx, ly) of a w x h rectangle, 256 threads, flat order.
+template <bool FULL, int WC, int HC, typename F>
+__device__ inline void rect_loop(int w, int h, F&& f) {
+  if constexpr (FULL) {
+    constexpr int n = WC * HC;
+#pragma unroll
+    for (int p0 = 0; p0 < n; p0 += NTHREADS) {
+      const int p = p0 + int(threadIdx.x);
+      if (p < n) f(p % WC, p / WC);
+    }
+  } else {
+    const int n = w * h;
+    for (int p = threadIdx.x; p < n; p += NTHREADS) f(p % w, p / w);
+  }
+}
+
+// Load NF fields of the tile plus a 2-node halo into LDS (zeros outside a
+// non-periodic domain). For full tiles every load is issued before any is
+// used so that their latencies overlap.
+template <typename R, bool FULL, int TY, int NF>
+__device__ inline void load_halo2(const Geo& g, int x0, int y0, int tw, int th,
+                                  const R* const (&src)[NF], R* const (&dst)[NF]) {
+  using TL = Tile<TY>;
+  auto node = [&](int lx, int ly, int* k) {
+    int i = x0 + lx - 2, j = y0 + ly - 2;
+    bool in = true;
+    if (g.periodic) {
+      i = wrapi(i, g.nx);
+      j = wrapi(j, g.ny);
+    } else {
+      in = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+    }
+    *k = in ? j * g.nx + i : 0;
+    return in;
+  };
+  if constexpr (FULL) {
+    constexpr int WC = TX + 4, HC = TY + 4, n = WC * HC, NP = (n + NTHREADS - 1) / NTHREADS;
+    int kk[NP], pp[NP];
+    bool ok[NP];
+#pragma unroll
+    for (int e = 0; e < NP; ++e) {
+      const int p = e * NTHREADS + int(threadIdx.x);
+      const int lx = p % WC, ly = p / WC;
+      ok[e] = node(lx, ly, &kk[e]) && p < n;
+      if (p >= n) kk[e] = 0;
+      pp[e] = p < n ? ly * TL::W2 + lx : -1;
+    }
+    R v[NF][NP];
+#pragma unroll
+    for (int e = 0; e < NP; ++e)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) v[f][e] = src[f][kk[e]];
+#pragma unroll
+    for (int e = 0; e < NP; ++e)
+      if (pp[e] >= 0)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) dst[f][pp[e]] = ok[e] ? v[f][e] : R(0);
+  } else {
+    rect_loop<false, 1, 1>(tw + 4, th + 4, [&](int lx, int ly) {
+      int k;
+      const bool in = node(lx, ly, &k);
+      const int p = ly * TL::W2 + lx;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) dst[f][p] = in ? src[f][k] : R(0);
+    });
+  }
+}
+
+// LDS finite difference along x or y at position p of a field with the
+// given row step, for node coordinate c along that axis (second-order
+// central, one-sided at the two ends of a non-periodic axis).
+template <typename R>
+__device__ inline R lds_d(const R* s, int p, int step, int c, int n, int periodic) {
+  if (periodic || (c > 0 && c < n - 1)) return R(0.5) * (s[p + step] - s[p - step]);
+  if (c == 0) return R(0.5) * (R(-3) * s[p] + R(4) * s[p + step] - s[p + 2 * step]);
+  return R(0.5) * (R(3) * s[p] - R(4) * s[p - step] + s[p - 2 * step]);
+}
+
+// ---------------------------------------------------------------------------
 // LKS step
 // ---------------------------------------------------------------------------
 // One LKS step, level n -> n+1 (eq:rho, eq:u, eq:T with eq:feq2 and eq:geq2
@@ -130,37 +237,74 @@ __device__ inline double block_sum(double v, double* red) {
 // Brinkman term of eq:lbef_ex giving u = U* / (1 + alpha)).
 // Density is carried as drho = rho - 1: the constant part of f_i^eq adds 1
 // to the density and 0 to the momentum, so LDS holds f'_i = f_i^eq - w_i.
-// Boundary nodes complete the density (velocity node), normal velocity
-// (pressure node) or temperature (adiabatic node) from the moment balance of
-// the pulled populations; corners copy density and temperature from their
-// y-neighbour, whose thread writes them.
-template <typename R, bool TH>
-__global__ __launch_bounds__(NTHREADS) void lks_step_kernel(Geo g, FwdArgs<R> a) {
-  __shared__ R sf[9][LPOS];
-  __shared__ R sg[TH ? 9 : 1][TH ? LPOS : 1];
-  __shared__ double red[NTHREADS / 64];
+//   stage A0  the raw state of the tile and a 2-node halo into LDS;
+//   stage A1  the nine post-collision values f'_i (and g_i) of every node of
+//             the tile and a 1-node halo, gradients from LDS;
+//   stage B   every tile node pulls f'_i(x - c_i) from LDS. Boundary nodes
+//             complete the density (velocity node), normal velocity
+//             (pressure node) or temperature (adiabatic node) from the moment
+//             balance of the pulled populations; corners copy density and
+//             temperature from their y-neighbour, whose thread writes them.
+template <typename R, bool TH, int TY>
+struct FwdLds {
+  using TL = Tile<TY>;
+  R d[TL::W2 * TL::H2], u[TL::W2 * TL::H2], v[TL::W2 * TL::H2];
+  R T[TH ? TL::W2 * TL::H2 : 1], B[TH ? TL::W2 * TL::H2 : 1];
+  R f[9][TL::W1 * TL::H1];
+  R gq[TH ? 9 : 1][TH ? TL::W1 * TL::H1 : 1];
+  double red[NTHREADS / 64];
+};
 
-  int x0, x1, y0, y1;
-  tile_extent(blockIdx.x, g.ntx, g.nx, TX, &x0, &x1);
-  tile_extent(blockIdx.y, g.nty, g.ny, TY, &y0, &y1);
-  const int tw = x1 - x0, th = y1 - y0, hw = tw + 2, hh = th + 2;
+template <typename R, bool TH, int TY, bool FULL>
+__device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L, int x0, int y0,
+                         int tw, int th, int tile) {
+  using TL = Tile<TY>;
+  constexpr int W2 = TL::W2, W1 = TL::W1;
   const R A = R(g.A);
+  if constexpr (FULL) {
+    tw = TX;
+    th = TY;
+  }
+  // node-local inputs of stage B, loaded before the first barrier (full tiles)
+  constexpr int NB = FULL ? (TX * TY + NTHREADS - 1) / NTHREADS : 1;
+  int mpre[NB];
+  R spre[NB];
+  if constexpr (FULL) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int p = e * NTHREADS + int(threadIdx.x);
+      const int k = (y0 + p / TX) * g.nx + x0 + p % TX;
+      mpre[e] = a.mask[k];
+      spre[e] = a.inv1pa[k];
+    }
+  }
 
-  // stage A: post-collision populations of the tile and its halo
-  for (int p = threadIdx.x; p < hw * hh; p += NTHREADS) {
-    int lx = p % hw, ly = p / hw;
+  if constexpr (TH) {
+    const R* src[5] = {a.d0, a.ux0, a.uy0, a.T0, a.B};
+    R* dst[5] = {L.d, L.u, L.v, L.T, L.B};
+    load_halo2<R, FULL, TY, 5>(g, x0, y0, tw, th, src, dst);
+  } else {
+    const R* src[3] = {a.d0, a.ux0, a.uy0};
+    R* dst[3] = {L.d, L.u, L.v};
+    load_halo2<R, FULL, TY, 3>(g, x0, y0, tw, th, src, dst);
+  }
+  __syncthreads();
+
+  rect_loop<FULL, TX + 2, TY + 2>(tw + 2, th + 2, [&](int lx, int ly) {
     int i = x0 + lx - 1, j = y0 + ly - 1;
     if (g.periodic) {
       i = wrapi(i, g.nx);
       j = wrapi(j, g.ny);
     } else if (i < 0 || j < 0 || i >= g.nx || j >= g.ny) {
-      continue;
+      return;
     }
-    const int k = j * g.nx + i;
-    const int pos = ly * LW + lx;
-    const R d = a.d0[k], ux = a.ux0[k], uy = a.uy0[k];
-    const R uxx = gdx(a.ux0, i, j, g), uxy = gdy(a.ux0, i, j, g);
-    const R uyx = gdx(a.uy0, i, j, g), uyy = gdy(a.uy0, i, j, g);
+    const int p2 = (ly + 1) * W2 + lx + 1;
+    const int p1 = ly * W1 + lx;
+    const R d = L.d[p2], ux = L.u[p2], uy = L.v[p2];
+    const R uxx = lds_d(L.u, p2, 1, i, g.nx, g.periodic);
+    const R uxy = lds_d(L.u, p2, W2, j, g.ny, g.periodic);
+    const R uyx = lds_d(L.v, p2, 1, i, g.nx, g.periodic);
+    const R uyy = lds_d(L.v, p2, W2, j, g.ny, g.periodic);
     // f'_i = w_i [P + 3 c.u + cx^2 Xx + cy^2 Yy + cx cy Xy]
     const R P = d - R(1.5) * (ux * ux + uy * uy);
     const R Xx = R(4.5) * ux * ux + R(2) * A * uxx;
@@ -169,59 +313,67 @@ __global__ __launch_bounds__(NTHREADS) void lks_step_kernel(Geo g, FwdArgs<R> a)
     const R u3x = R(3) * ux, u3y = R(3) * uy;
     const R w0 = R(4.0 / 9), w1 = R(1.0 / 9), w5 = R(1.0 / 36);
     const R diag = P + Xx + Yy;
-    sf[0][pos] = w0 * P;
-    sf[1][pos] = w1 * (P + u3x + Xx);
-    sf[2][pos] = w1 * (P + u3y + Yy);
-    sf[3][pos] = w1 * (P - u3x + Xx);
-    sf[4][pos] = w1 * (P - u3y + Yy);
-    sf[5][pos] = w5 * (diag + u3x + u3y + Xy);
-    sf[6][pos] = w5 * (diag - u3x + u3y - Xy);
-    sf[7][pos] = w5 * (diag - u3x - u3y + Xy);
-    sf[8][pos] = w5 * (diag + u3x - u3y - Xy);
+    L.f[0][p1] = w0 * P;
+    L.f[1][p1] = w1 * (P + u3x + Xx);
+    L.f[2][p1] = w1 * (P + u3y + Yy);
+    L.f[3][p1] = w1 * (P - u3x + Xx);
+    L.f[4][p1] = w1 * (P - u3y + Yy);
+    L.f[5][p1] = w5 * (diag + u3x + u3y + Xy);
+    L.f[6][p1] = w5 * (diag - u3x + u3y - Xy);
+    L.f[7][p1] = w5 * (diag - u3x - u3y + Xy);
+    L.f[8][p1] = w5 * (diag + u3x - u3y - Xy);
     if constexpr (TH) {
-      const R T = a.T0[k];
-      const R Bk = a.B[k];
-      const R Wx = R(3) * T * ux + Bk * gdx(a.T0, i, j, g);
-      const R Wy = R(3) * T * uy + Bk * gdy(a.T0, i, j, g);
-      sg[0][pos] = w0 * T;
-      sg[1][pos] = w1 * (T + Wx);
-      sg[2][pos] = w1 * (T + Wy);
-      sg[3][pos] = w1 * (T - Wx);
-      sg[4][pos] = w1 * (T - Wy);
-      sg[5][pos] = w5 * (T + Wx + Wy);
-      sg[6][pos] = w5 * (T - Wx + Wy);
-      sg[7][pos] = w5 * (T - Wx - Wy);
-      sg[8][pos] = w5 * (T + Wx - Wy);
+      const R T = L.T[p2];
+      const R Bk = L.B[p2];
+      const R Wx = R(3) * T * ux + Bk * lds_d(L.T, p2, 1, i, g.nx, g.periodic);
+      const R Wy = R(3) * T * uy + Bk * lds_d(L.T, p2, W2, j, g.ny, g.periodic);
+      L.gq[0][p1] = w0 * T;
+      L.gq[1][p1] = w1 * (T + Wx);
+      L.gq[2][p1] = w1 * (T + Wy);
+      L.gq[3][p1] = w1 * (T - Wx);
+      L.gq[4][p1] = w1 * (T - Wy);
+      L.gq[5][p1] = w5 * (T + Wx + Wy);
+      L.gq[6][p1] = w5 * (T - Wx + Wy);
+      L.gq[7][p1] = w5 * (T - Wx - Wy);
+      L.gq[8][p1] = w5 * (T + Wx - Wy);
     }
-  }
+  });
   __syncthreads();
 
-  // stage B: pull and close
   double part = 0.0;
-  for (int p = threadIdx.x; p < tw * th; p += NTHREADS) {
-    const int lx = p % tw, ly = p / tw;
+  int e = 0;
+  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
     const int i = x0 + lx, j = y0 + ly;
     const int k = j * g.nx + i;
-    const int pos = (ly + 1) * LW + (lx + 1);
-    const int m = a.mask[k];
+    const int p1 = (ly + 1) * W1 + lx + 1;
+    int m;
+    R s;
+    if constexpr (FULL) {
+      m = mpre[e];
+      s = spre[e];
+      ++e;
+    } else {
+      m = a.mask[k];
+      s = a.inv1pa[k];
+    }
     const int fc = g.periodic ? FLOW_INTERIOR : (m & 3);
-    if (fc == FLOW_CORNER) continue;
+    if (fc == FLOW_CORNER) return;
     R f[9], gg[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) f[q] = sf[q][pos - CX[q] - CY[q] * LW];
+    for (int q = 0; q < 9; ++q) f[q] = L.f[q][p1 - CX[q] - CY[q] * W1];
     if constexpr (TH) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) gg[q] = sg[q][pos - CX[q] - CY[q] * LW];
+      for (int q = 0; q < 9; ++q) gg[q] = L.gq[q][p1 - CX[q] - CY[q] * W1];
     }
     R dn, uxn, uyn, Tn = R(0);
     if (fc == FLOW_INTERIOR) {
       dn = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
       const R Ux = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
       const R Uy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-      const R s = a.inv1pa[k];
       uxn = Ux * s;
       uyn = Uy * s;
-      if constexpr (TH) Tn = gg[0] + gg[1] + gg[2] + gg[3] + gg[4] + gg[5] + gg[6] + gg[7] + gg[8];
+      if constexpr (TH)
+        Tn = gg[0] + gg[1] + gg[2] + gg[3] + gg[4] + gg[5] + gg[6] + gg[7] + gg[8];
     } else {
       const int nx_ = (i == 0) ? -1 : (i == g.nx - 1 ? 1 : 0);
       const int ny_ = nx_ != 0 ? 0 : (j == 0 ? -1 : 1);
@@ -255,14 +407,12 @@ __global__ __launch_bounds__(NTHREADS) void lks_step_kernel(Geo g, FwdArgs<R> a)
         if (((m >> 2) & 3) == THERM_DIRICHLET) Tn = a.Tb[k];
         else Tn = (S0g + R(2) * Spg) / (R(1) + un);
       }
-      // the y-neighbour of a corner writes the corner
       if (i == 0 || i == g.nx - 1) {
         if (j == 1) {
-          const int kc = i;
-          a.d1[kc] = dn;
-          a.ux1[kc] = R(0);
-          a.uy1[kc] = R(0);
-          if constexpr (TH) a.T1[kc] = Tn;
+          a.d1[i] = dn;
+          a.ux1[i] = R(0);
+          a.uy1[i] = R(0);
+          if constexpr (TH) a.T1[i] = Tn;
         }
         if (j == g.ny - 2) {
           const int kc = (g.ny - 1) * g.nx + i;
@@ -285,182 +435,118 @@ __global__ __launch_bounds__(NTHREADS) void lks_step_kernel(Geo g, FwdArgs<R> a)
         if (m & TAG_J_OUTLET) part -= double(dn);
       }
     }
-  }
+  });
   if (a.acc) {
-    double s = block_sum(part, red);
-    if (threadIdx.x == 0) a.acc[blockIdx.y * g.ntx + blockIdx.x] += s;
+    double s = block_sum(part, L.red);
+    if (threadIdx.x == 0) a.acc[tile] += s;
   }
 }
 
-// ---------------------------------------------------------------------------
-// adjoint boundary fill (double precision, per ring node)
-// ---------------------------------------------------------------------------
-// Solve min ||K x + b|| through the normal equations K^T K x = -K^T b with a
-// Cholesky factorisation; C <= 5 unknowns.
-template <int C>
-struct Normal {
-  double G[C][C];
-  double h[C];
-  __device__ void zero() {
-#pragma unroll
-    for (int r = 0; r < C; ++r) {
-      h[r] = 0.0;
-#pragma unroll
-      for (int c = 0; c < C; ++c) G[r][c] = 0.0;
-    }
-  }
-  __device__ void row(const double (&k)[C], double b) {
-#pragma unroll
-    for (int r = 0; r < C; ++r) {
-      h[r] += k[r] * b;
-#pragma unroll
-      for (int c = 0; c <= r; ++c) G[r][c] += k[r] * k[c];
-    }
-  }
-  __device__ void solve(double (&x)[C]) {
-    double L[C][C];
-#pragma unroll
-    for (int r = 0; r < C; ++r) {
-#pragma unroll
-      for (int c = 0; c <= r; ++c) {
-        double s = G[r][c];
-#pragma unroll
-        for (int t = 0; t < c; ++t) s -= L[r][t] * L[c][t];
-        L[r][c] = (r == c) ? sqrt(s) : s / L[c][c];
-      }
-    }
-    double y[C];
-#pragma unroll
-    for (int r = 0; r < C; ++r) {
-      double s = -h[r];
-#pragma unroll
-      for (int t = 0; t < r; ++t) s -= L[r][t] * y[t];
-      y[r] = s / L[r][r];
-    }
-#pragma unroll
-    for (int r = C - 1; r >= 0; --r) {
-      double s = y[r];
-#pragma unroll
-      for (int t = r + 1; t < C; ++t) s -= L[t][r] * x[t];
-      x[r] = s / L[r][r];
-    }
-  }
-};
+template <typename R, bool TH, int TY>
+__global__ __launch_bounds__(NTHREADS) void lks_step_kernel(Geo g, FwdArgs<R> a) {
+  __shared__ FwdLds<R, TH, TY> L;
+  int x0, x1, y0, y1, tile;
+  if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
+  const int tw = x1 - x0, th = y1 - y0;
+  if (tw == TX && th == TY) lks_tile<R, TH, TY, true>(g, a, L, x0, y0, tw, th, tile);
+  else lks_tile<R, TH, TY, false>(g, a, L, x0, y0, tw, th, tile);
+}
 
-// Least-squares completion of the adjoint populations at a ring node
-// (Sec. 2.5, Appendix A). With outward normal n, the pulled values are known
-// for c_i.n <= 0; the three with c_i.n > 0 and the multipliers minimise,
-// over all nine rows i,
-//   flow:    (n.c_i) f~_i - 2A sum_j w_j (n.c_j)(c_j.c_i) f~_j
-//            + [mu~.c_i | lambda~ + mu~_s (c_i.t)] - kappa~ T (c_i.n) + s_i
-//   thermal: (n.c_i) g~_i - B (n.q~) + [eta~ | kappa~ (c_i - u).n]
-// (eq:afboundaryu, eq:afboundaryp, eq:agboundaryT, eq:afboundaryuq,
-// eq:afboundarypq, eq:agboundaryq with s~ and q~ expanded through eq:afs and
-// eq:agq). The thermal system is solved first; its kappa~ enters the flow
-// rows of a flux node as a known term. s_i = dJ_dO/df_i: +seed/3 on inlet
-// nodes and -seed/3 on outlet nodes of the pressure drop (p = sum f_i / 3).
-// Returns the raw moments rho~, U~, s~ (xx, xy, yy), T~, q~ of the
-// completed set.
-template <typename R, bool TH>
-__device__ void ring_fill(const Geo& g, const AdjArgs<R>& a, int i, int j, int k, int m,
-                          double mom[9]) {
-  const int nx_ = (i == 0) ? -1 : (i == g.nx - 1 ? 1 : 0);
-  const int ny_ = nx_ != 0 ? 0 : (j == 0 ? -1 : 1);
-  double f[9], gq[9];
-  int cn[9];
-  int uq[3], nu = 0;
+// ---------------------------------------------------------------------------
+// ALKS step
+// ---------------------------------------------------------------------------
+// Least-squares completion of the adjoint populations at a ring node (see
+// RingOp): the known populations f~_i = rho~ + c_i.V and g~_i = Theta at
+// x + c_i come from LDS (the unknown directions point outside the domain,
+// where LDS holds zeros); returns the raw moments rho~, U~, s~ (xx, xy, yy),
+// T~, q~ of the completed set.
+template <typename R, bool TH, int W2>
+__device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, const R* svx,
+                             const R* svy, const R* sth, const R* sTn, int p2, int i, int j,
+                             int k, int m, R mom[9]) {
+  const int o = (i == 0) ? 0 : (i == g.nx - 1 ? 1 : (j == 0 ? 2 : 3));
+  const RingOp& op = a.ops[o];
+  R f[9], gq[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    cn[q] = CX[q] * nx_ + CY[q] * ny_;
-    f[q] = 0.0;
-    gq[q] = 0.0;
-    if (cn[q] <= 0) {
-      const int kz = (j + CY[q]) * g.nx + (i + CX[q]);
-      f[q] = double(a.r0[kz]) + CX[q] * double(a.vx0[kz]) + CY[q] * double(a.vy0[kz]);
-      if constexpr (TH) gq[q] = double(a.th0[kz]);
-    } else {
-      uq[nu++] = q;
-    }
+    const int p = p2 + CX[q] + CY[q] * W2;
+    f[q] = sr[p] + R(CX[q]) * svx[p] + R(CY[q]) * svy[p];
+    if constexpr (TH) gq[q] = sth[p];
   }
-  double kappa = 0.0;
-  const int tclass = (m >> 2) & 3;
-  const bool flux = TH && tclass == THERM_FLUX;
+  R kappa = R(0), gu[3] = {R(0), R(0), R(0)};
   if constexpr (TH) {
-    const double Bn = double(a.B[k]);
-    const double un = double(a.ux[k]) * nx_ + double(a.uy[k]) * ny_;
-    double Qk = 0.0;
-#pragma unroll
-    for (int q = 0; q < 9; ++q)
-      if (cn[q] <= 0) Qk += WD[q] * cn[q] * gq[q];
-    Normal<4> ne;
-    ne.zero();
-#pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      double kr[4];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) kr[c] = (uq[c] == r ? double(cn[r]) : 0.0) - Bn * WD[uq[c]];
-      kr[3] = flux ? double(cn[r]) - un : 1.0;
-      const double b = (cn[r] <= 0 ? cn[r] * gq[r] : 0.0) - Bn * Qk;
-      ne.row(kr, b);
-    }
-    double x[4];
-    ne.solve(x);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) gq[uq[c]] = x[c];
-    if (flux) kappa = x[3];
-  }
-  {
-    const double A = g.A;
-    double Mx = 0.0, My = 0.0;
-#pragma unroll
-    for (int q = 0; q < 9; ++q)
-      if (cn[q] <= 0) {
-        Mx += WD[q] * cn[q] * CX[q] * f[q];
-        My += WD[q] * cn[q] * CY[q] * f[q];
-      }
-    double s = 0.0;
-    if (m & TAG_J_INLET) s += a.seed_dp / 3.0;
-    if (m & TAG_J_OUTLET) s -= a.seed_dp / 3.0;
-    const double Tn = TH ? double(a.T[k]) : 0.0;
-    const bool vel = (m & 3) == FLOW_VELOCITY;
-    const int tx_ = -ny_, ty_ = nx_;
-    Normal<5> ne;
-    ne.zero();
-#pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      double kr[5];
+    if (((m >> 2) & 3) == THERM_DIRICHLET) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const int q = uq[c];
-        kr[c] = (q == r ? double(cn[r]) : 0.0) -
-                2.0 * A * WD[q] * double(CX[q] * CX[r] + CY[q] * CY[r]);
-      }
-      kr[3] = vel ? double(CX[r]) : 1.0;
-      kr[4] = vel ? double(CY[r]) : double(CX[r] * tx_ + CY[r] * ty_);
-      const double b = (cn[r] <= 0 ? cn[r] * f[r] : 0.0) - 2.0 * A * (CX[r] * Mx + CY[r] * My) +
-                       s - kappa * Tn * cn[r];
-      ne.row(kr, b);
-    }
-    double x[5];
-    ne.solve(x);
+        R t = R(0);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) f[uq[c]] = x[c];
+        for (int q = 0; q < 9; ++q) t += R(op.Ld[c][q]) * gq[q];
+        gu[c] = t;
+      }
+    } else {
+      const int nx_ = o == 0 ? -1 : (o == 1 ? 1 : 0);
+      const int ny_ = o == 2 ? -1 : (o == 3 ? 1 : 0);
+      const R un = a.ux[k] * R(nx_) + a.uy[k] * R(ny_);
+      R num = R(0);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) num += (R(op.ga[q]) - un * R(op.ge[q])) * gq[q];
+      const R den = R(op.A0) - R(2) * un * R(op.A1) + un * un * R(op.A2);
+      kappa = -num / den;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R t = R(0);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) t += R(op.Lg0[c][q]) * gq[q];
+        gu[c] = t - kappa * (R(op.hc[c]) - un * R(op.h1[c]));
+      }
+    }
   }
-  double r = 0, Ux = 0, Uy = 0, sxx = 0, sxy = 0, syy = 0, Tt = 0, qx = 0, qy = 0;
+  R s = R(0);
+  if (m & TAG_J_INLET) s += R(a.seed_dp / 3.0);
+  if (m & TAG_J_OUTLET) s -= R(a.seed_dp / 3.0);
+  const int v = (m & 3) == FLOW_VELOCITY ? 0 : 1;
+  const R kT = TH ? kappa * sTn[p2] : R(0);
+  R fu[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    R t = R(op.Ls[v][c]) * s + R(op.Lk[v][c]) * kT;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) t += R(op.Lf[v][c][q]) * f[q];
+    fu[c] = t;
+  }
+  R r = R(0), Ux = R(0), Uy = R(0), sxx = R(0), sxy = R(0), syy = R(0);
+  R Tt = R(0), qx = R(0), qy = R(0);
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    const double wf = WD[q] * f[q];
+    const R wf = R(WD[q]) * f[q];
     r += wf;
-    Ux += CX[q] * wf;
-    Uy += CY[q] * wf;
-    sxx += CX[q] * CX[q] * wf;
-    sxy += CX[q] * CY[q] * wf;
-    syy += CY[q] * CY[q] * wf;
+    if (CX[q]) Ux += R(CX[q]) * wf;
+    if (CY[q]) Uy += R(CY[q]) * wf;
+    if (CX[q]) sxx += wf;
+    if (CX[q] * CY[q]) sxy += R(CX[q] * CY[q]) * wf;
+    if (CY[q]) syy += wf;
     if constexpr (TH) {
-      const double wg = WD[q] * gq[q];
+      const R wg = R(WD[q]) * gq[q];
       Tt += wg;
-      qx += CX[q] * wg;
-      qy += CY[q] * wg;
+      if (CX[q]) qx += R(CX[q]) * wg;
+      if (CY[q]) qy += R(CY[q]) * wg;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const R cx = R(op.ucx[c]), cy = R(op.ucy[c]);
+    const R wf = R(op.uw[c]) * fu[c];
+    r += wf;
+    Ux += cx * wf;
+    Uy += cy * wf;
+    sxx += cx * cx * wf;
+    sxy += cx * cy * wf;
+    syy += cy * cy * wf;
+    if constexpr (TH) {
+      const R wg = R(op.uw[c]) * gu[c];
+      Tt += wg;
+      qx += cx * wg;
+      qy += cy * wg;
     }
   }
   mom[0] = r;
@@ -474,95 +560,85 @@ __device__ void ring_fill(const Geo& g, const AdjArgs<R>& a, int i, int j, int k
   mom[8] = qy;
 }
 
-// Ring nodes without corners, enumerated bottom row, top row, left column,
-// right column.
-__device__ inline int ring_count(const Geo& g) { return 2 * (g.nx - 2) + 2 * (g.ny - 2); }
-__device__ inline void ring_node(const Geo& g, int t, int* i, int* j) {
-  const int a = g.nx - 2, b = g.ny - 2;
-  if (t < a) { *i = t + 1; *j = 0; }
-  else if (t < 2 * a) { *i = t - a + 1; *j = g.ny - 1; }
-  else if (t < 2 * a + b) { *i = 0; *j = t - 2 * a + 1; }
-  else { *i = g.nx - 1; *j = t - 2 * a - b + 1; }
-}
-__device__ inline int ring_index(const Geo& g, int i, int j) {
-  const int a = g.nx - 2, b = g.ny - 2;
-  if (j == 0) return i - 1;
-  if (j == g.ny - 1) return a + i - 1;
-  if (i == 0) return 2 * a + j - 1;
-  return 2 * a + b + j - 1;
-}
-
-// Boundary pre-pass of an ALKS step: the least-squares completion of every
-// ring node (one thread each), written as raw moments to a perimeter buffer
-// that the step kernel reads. Kept apart so that the step kernel does not
-// carry the registers of the small dense solves.
-template <typename R, bool TH>
-__global__ __launch_bounds__(NTHREADS) void alks_ring_kernel(Geo g, AdjArgs<R> a, R* ring) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nr = ring_count(g);
-  if (t >= nr) return;
-  int i, j;
-  ring_node(g, t, &i, &j);
-  const int k = j * g.nx + i;
-  double mom[9];
-  ring_fill<R, TH>(g, a, i, j, k, a.mask[k], mom);
-  constexpr int NM = TH ? 9 : 6;
-#pragma unroll
-  for (int f = 0; f < NM; ++f) ring[size_t(f) * nr + t] = R(mom[f]);
-}
-
-// ---------------------------------------------------------------------------
-// ALKS step
-// ---------------------------------------------------------------------------
 // One ALKS step, adjoint level n+1 -> n. The adjoint state is kept as the
 // coefficients of the adjoint equilibria, f~_i^eq = rho~ + c_i.V (eq:afeq)
 // and g~_i^eq = Theta (eq:ageq), so a step needs the forward state of one
 // level only:
-//   stage A  weighted pull of the level-n+1 equilibria from the 8
-//            neighbours (eq:ap..eq:aq), or the least-squares completion at
-//            ring nodes, for the tile and its halo;
-//   stage B  the local terms of eq:albef_ex / eq:albeg_ex at level n
-//            (seeds, 3 T q~ coupling, implicit Brinkman
-//            u~ = (U~ + T q~ - seed) / (1 + alpha)), then
-//            V = 3 u~ + 9 s~ u - 3 rho~ u - 2A div s~ and
-//            Theta = T~ + 3 q~.u - B div q~ - grad B . q~ with the
-//            level-n state, and the sensitivity
-//            3 alpha' u.u~ - B' grad T . q~ (Sec. 2.5).
-template <typename R, bool TH>
-__global__ __launch_bounds__(NTHREADS) void alks_step_kernel(Geo g, AdjArgs<R> a,
-                                                            const R* __restrict__ ring) {
-  constexpr int NM = TH ? 9 : 6;
-  __shared__ R sm[NM][LPOS];
+//   stage A0  the level-n+1 coefficients of the tile and a 2-node halo (and
+//             T^n, B for the thermal terms) into LDS;
+//   stage A1  weighted pull of the equilibria from the 8 neighbours
+//             (eq:ap..eq:aq), or the least-squares completion on ring
+//             nodes, for the tile and a 1-node halo; corners copy their
+//             y-neighbour;
+//   stage B   the local terms of eq:albef_ex / eq:albeg_ex at level n
+//             (seeds, 3 T q~ coupling, implicit Brinkman
+//             u~ = (U~ + T q~ - seed) / (1 + alpha)), then
+//             V = 3 u~ + 9 s~ u - 3 rho~ u - 2A div s~ and
+//             Theta = T~ + 3 q~.u - B div q~ - grad B . q~ with the
+//             level-n state, and the sensitivity
+//             3 alpha' u.u~ - B' grad T . q~ (Sec. 2.5).
+template <typename R, bool TH, int TY>
+struct AdjLds {
+  using TL = Tile<TY>;
+  static constexpr int NM = TH ? 9 : 6;
+  R r[TL::W2 * TL::H2], vx[TL::W2 * TL::H2], vy[TL::W2 * TL::H2];
+  R th[TH ? TL::W2 * TL::H2 : 1], Tn[TH ? TL::W2 * TL::H2 : 1], B[TH ? TL::W2 * TL::H2 : 1];
+  R m[NM][TL::W1 * TL::H1];
+};
 
-  int x0, x1, y0, y1;
-  tile_extent(blockIdx.x, g.ntx, g.nx, TX, &x0, &x1);
-  tile_extent(blockIdx.y, g.nty, g.ny, TY, &y0, &y1);
-  const int tw = x1 - x0, th = y1 - y0, hw = tw + 2, hh = th + 2;
+template <typename R, bool TH, int TY, bool FULL>
+__device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& L, int x0,
+                          int y0, int tw, int th) {
+  using TL = Tile<TY>;
+  constexpr int W2 = TL::W2, W1 = TL::W1, NM = AdjLds<R, TH, TY>::NM;
+  const int x1 = x0 + tw, y1 = y0 + th;
+  if constexpr (FULL) {
+    tw = TX;
+    th = TY;
+  }
+  // node-local inputs of stage B, loaded before the first barrier (full tiles)
+  constexpr int NB = FULL ? (TX * TY + NTHREADS - 1) / NTHREADS : 1;
+  R spre[NB], uxpre[NB], uypre[NB];
+  if constexpr (FULL) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int p = e * NTHREADS + int(threadIdx.x);
+      const int k = (y0 + p / TX) * g.nx + x0 + p % TX;
+      spre[e] = a.inv1pa[k];
+      uxpre[e] = a.ux[k];
+      uypre[e] = a.uy[k];
+    }
+  }
 
-  // stage A: raw moments of the pulled (or completed) adjoint populations
-  for (int p = threadIdx.x; p < hw * hh; p += NTHREADS) {
-    int lx = p % hw, ly = p / hw;
+  if constexpr (TH) {
+    const R* src[6] = {a.r0, a.vx0, a.vy0, a.th0, a.T, a.B};
+    R* dst[6] = {L.r, L.vx, L.vy, L.th, L.Tn, L.B};
+    load_halo2<R, FULL, TY, 6>(g, x0, y0, tw, th, src, dst);
+  } else {
+    const R* src[3] = {a.r0, a.vx0, a.vy0};
+    R* dst[3] = {L.r, L.vx, L.vy};
+    load_halo2<R, FULL, TY, 3>(g, x0, y0, tw, th, src, dst);
+  }
+  __syncthreads();
+
+  rect_loop<FULL, TX + 2, TY + 2>(tw + 2, th + 2, [&](int lx, int ly) {
     int i = x0 + lx - 1, j = y0 + ly - 1;
     if (g.periodic) {
       i = wrapi(i, g.nx);
       j = wrapi(j, g.ny);
     } else if (i < 0 || j < 0 || i >= g.nx || j >= g.ny) {
-      continue;
+      return;
     }
-    const int k = j * g.nx + i;
-    const int pos = ly * LW + lx;
-    const int m = a.mask[k];
-    const int fc = g.periodic ? FLOW_INTERIOR : (m & 3);
-    if (fc == FLOW_CORNER) continue;
-    if (fc == FLOW_INTERIOR) {
+    const int p2 = (ly + 1) * W2 + lx + 1;
+    const int p1 = ly * W1 + lx;
+    const bool ring = !g.periodic && (i == 0 || j == 0 || i == g.nx - 1 || j == g.ny - 1);
+    if (!ring) {
       R r = R(0), Ux = R(0), Uy = R(0), sxx = R(0), sxy = R(0), syy = R(0);
       R Tt = R(0), qx = R(0), qy = R(0);
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
-        const int iz = g.periodic ? wrapi(i + CX[q], g.nx) : i + CX[q];
-        const int jz = g.periodic ? wrapi(j + CY[q], g.ny) : j + CY[q];
-        const int kz = jz * g.nx + iz;
-        const R E = a.r0[kz] + R(CX[q]) * a.vx0[kz] + R(CY[q]) * a.vy0[kz];
+        const int p = p2 + CX[q] + CY[q] * W2;
+        const R E = L.r[p] + R(CX[q]) * L.vx[p] + R(CY[q]) * L.vy[p];
         const R wE = R(WD[q]) * E;
         r += wE;
         if (CX[q]) Ux += R(CX[q]) * wE;
@@ -571,82 +647,92 @@ __global__ __launch_bounds__(NTHREADS) void alks_step_kernel(Geo g, AdjArgs<R> a
         if (CX[q] * CY[q]) sxy += R(CX[q] * CY[q]) * wE;
         if (CY[q]) syy += wE;
         if constexpr (TH) {
-          const R wT = R(WD[q]) * a.th0[kz];
+          const R wT = R(WD[q]) * L.th[p];
           Tt += wT;
           if (CX[q]) qx += R(CX[q]) * wT;
           if (CY[q]) qy += R(CY[q]) * wT;
         }
       }
-      sm[0][pos] = r;
-      sm[1][pos] = Ux;
-      sm[2][pos] = Uy;
-      sm[3][pos] = sxx;
-      sm[4][pos] = sxy;
-      sm[5][pos] = syy;
+      L.m[0][p1] = r;
+      L.m[1][p1] = Ux;
+      L.m[2][p1] = Uy;
+      L.m[3][p1] = sxx;
+      L.m[4][p1] = sxy;
+      L.m[5][p1] = syy;
       if constexpr (TH) {
-        sm[6][pos] = Tt;
-        sm[7][pos] = qx;
-        sm[8][pos] = qy;
+        L.m[6][p1] = Tt;
+        L.m[7][p1] = qx;
+        L.m[8][p1] = qy;
       }
     } else {
-      const int nr = ring_count(g), t = ring_index(g, i, j);
+      const bool corner = (i == 0 || i == g.nx - 1) && (j == 0 || j == g.ny - 1);
+      if (corner) return;
+      const int k = j * g.nx + i;
+      R mom[9];
+      ring_moments<R, TH, W2>(g, a, L.r, L.vx, L.vy, L.th, L.Tn, p2, i, j, k, a.mask[k], mom);
 #pragma unroll
-      for (int f = 0; f < NM; ++f) sm[f][pos] = ring[size_t(f) * nr + t];
+      for (int f = 0; f < NM; ++f) L.m[f][p1] = mom[f];
     }
-  }
+  });
   __syncthreads();
-  // corners copy the moments of their y-neighbour (always inside tile+halo)
-  if (!g.periodic) {
-    for (int p = threadIdx.x; p < hw * hh; p += NTHREADS) {
-      int lx = p % hw, ly = p / hw;
-      int i = x0 + lx - 1, j = y0 + ly - 1;
-      if ((i != 0 && i != g.nx - 1) || (j != 0 && j != g.ny - 1)) continue;
-      const int pos = ly * LW + lx;
-      const int pn = pos + (j == 0 ? LW : -LW);
+  // corners copy the moments of their y-neighbour (both inside the tile)
+  const bool has_corner = !g.periodic && (x0 == 0 || x1 == g.nx) && (y0 == 0 || y1 == g.ny);
+  if (has_corner) {
+    if (threadIdx.x < 4) {
+      const int ci = (threadIdx.x & 1) ? g.nx - 1 : 0;
+      const int cj = (threadIdx.x & 2) ? g.ny - 1 : 0;
+      if (ci >= x0 && ci < x1 && cj >= y0 && cj < y1) {
+        const int p1 = (cj - y0 + 1) * W1 + (ci - x0 + 1);
+        const int pn = p1 + (cj == 0 ? W1 : -W1);
 #pragma unroll
-      for (int f = 0; f < NM; ++f) sm[f][pos] = sm[f][pn];
+        for (int f = 0; f < NM; ++f) L.m[f][p1] = L.m[f][pn];
+      }
     }
     __syncthreads();
   }
 
-  // stage B
   const R A2 = R(2.0 * g.A);
-  for (int p = threadIdx.x; p < tw * th; p += NTHREADS) {
-    const int lx = p % tw, ly = p / tw;
+  int e = 0;
+  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
     const int i = x0 + lx, j = y0 + ly;
     const int k = j * g.nx + i;
-    const int pos = (ly + 1) * LW + (lx + 1);
+    const int p1 = (ly + 1) * W1 + lx + 1;
+    const int p2 = (ly + 2) * W2 + lx + 2;
+    R s, ux, uy;
+    if constexpr (FULL) {
+      s = spre[e];
+      ux = uxpre[e];
+      uy = uypre[e];
+      ++e;
+    } else {
+      s = a.inv1pa[k];
+      ux = a.ux[k];
+      uy = a.uy[k];
+    }
     const bool ring = !g.periodic && (i == 0 || j == 0 || i == g.nx - 1 || j == g.ny - 1);
     const bool corner = ring && (i == 0 || i == g.nx - 1) && (j == 0 || j == g.ny - 1);
     // local terms are those of the node whose moments were taken
     const int kl = corner ? (j == 0 ? g.nx + i : (g.ny - 2) * g.nx + i) : k;
-    const int ml = a.mask[kl];
-    const R r = sm[0][pos];
-    R Ux = sm[1][pos], Uy = sm[2][pos];
-    const R sxx = sm[3][pos], sxy = sm[4][pos], syy = sm[5][pos];
+    const int pl2 = corner ? p2 + (j == 0 ? W2 : -W2) : p2;
+    const R r = L.m[0][p1];
+    R Ux = L.m[1][p1], Uy = L.m[2][p1];
+    const R sxx = L.m[3][p1], sxy = L.m[4][p1], syy = L.m[5][p1];
     R Tt = R(0), qx = R(0), qy = R(0);
     if constexpr (TH) {
-      Tt = sm[6][pos];
-      qx = sm[7][pos];
-      qy = sm[8][pos];
-      const R Tl = a.T[kl];
+      Tt = L.m[6][p1];
+      qx = L.m[7][p1];
+      qy = L.m[8][p1];
+      const R Tl = L.Tn[pl2];
       Ux += Tl * qx;
       Uy += Tl * qy;
-      if (ml & TAG_PROBE) {
+      if (a.seed_heat != 0.0 && (a.mask[kl] & TAG_PROBE)) {
         Ux -= R(a.seed_heat / 3.0) * Tl;
         Tt -= R(a.seed_heat) * a.ux[kl];
       }
     }
-    const R s = a.inv1pa[k];
     const R utx = Ux * s, uty = Uy * s;
-    const R ux = a.ux[k], uy = a.uy[k];
-    // div s~: (d_x s~xx + d_y s~xy, d_x s~xy + d_y s~yy) from LDS
-    auto ldx = [&](int f) {
-      return fd_axis<R>(i, g.nx, g.periodic, [&](int o) { return sm[f][pos + o]; });
-    };
-    auto ldy = [&](int f) {
-      return fd_axis<R>(j, g.ny, g.periodic, [&](int o) { return sm[f][pos + o * LW]; });
-    };
+    auto ldx = [&](int f) { return lds_d(L.m[f], p1, 1, i, g.nx, g.periodic); };
+    auto ldy = [&](int f) { return lds_d(L.m[f], p1, W1, j, g.ny, g.periodic); };
     const R dsx = ldx(3) + ldy(4);
     const R dsy = ldx(4) + ldy(5);
     const R Vx = R(3) * utx + R(9) * (sxx * ux + sxy * uy) - R(3) * r * ux - A2 * dsx;
@@ -654,27 +740,37 @@ __global__ __launch_bounds__(NTHREADS) void alks_step_kernel(Geo g, AdjArgs<R> a
     a.r1[k] = r;
     a.vx1[k] = Vx;
     a.vy1[k] = Vy;
-    R Th = R(0);
     if constexpr (TH) {
       const R divq = ldx(7) + ldy(8);
-      const R Bk = a.B[k];
-      const R dBx = gdx(a.B, i, j, g), dBy = gdy(a.B, i, j, g);
-      Th = Tt + R(3) * (qx * ux + qy * uy) - Bk * divq - (dBx * qx + dBy * qy);
-      a.th1[k] = Th;
+      const R Bk = L.B[p2];
+      const R dBx = lds_d(L.B, p2, 1, i, g.nx, g.periodic);
+      const R dBy = lds_d(L.B, p2, W2, j, g.ny, g.periodic);
+      a.th1[k] = Tt + R(3) * (qx * ux + qy * uy) - Bk * divq - (dBx * qx + dBy * qy);
     }
     if (a.sens_mode) {
       double v = 0.0;
       if (!ring) {
         v = double(a.dA3[k]) * (double(ux) * double(utx) + double(uy) * double(uty));
         if constexpr (TH) {
-          const double dTx = double(gdx(a.T, i, j, g)), dTy = double(gdy(a.T, i, j, g));
+          const double dTx = double(lds_d(L.Tn, p2, 1, i, g.nx, g.periodic));
+          const double dTy = double(lds_d(L.Tn, p2, W2, j, g.ny, g.periodic));
           v -= double(a.dB[k]) * (dTx * double(qx) + dTy * double(qy));
         }
       }
       if (a.sens_mode == 1) a.sens[k] += v;
       else a.sens[k] = v;
     }
-  }
+  });
+}
+
+template <typename R, bool TH, int TY>
+__global__ __launch_bounds__(NTHREADS) void alks_step_kernel(Geo g, AdjArgs<R> a) {
+  __shared__ AdjLds<R, TH, TY> L;
+  int x0, x1, y0, y1, tile;
+  if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
+  const int tw = x1 - x0, th = y1 - y0;
+  if (tw == TX && th == TY) alks_tile<R, TH, TY, true>(g, a, L, x0, y0, tw, th);
+  else alks_tile<R, TH, TY, false>(g, a, L, x0, y0, tw, th);
 }
 
 // ---------------------------------------------------------------------------
@@ -768,21 +864,25 @@ void launch_init(const Geo& g, const uint8_t* mask, const R* ubx, const R* uby, 
 }
 template <typename R>
 void launch_lks_step(const Geo& g, const FwdArgs<R>& a, hipStream_t s) {
-  dim3 grid(g.ntx, g.nty);
-  if (g.thermal) lks_step_kernel<R, true><<<grid, NTHREADS, 0, s>>>(g, a);
-  else lks_step_kernel<R, false><<<grid, NTHREADS, 0, s>>>(g, a);
+  const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
+  if (g.ty == 8) {
+    if (g.thermal) lks_step_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+    else lks_step_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+  } else {
+    if (g.thermal) lks_step_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+    else lks_step_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+  }
 }
 template <typename R>
-void launch_alks_step(const Geo& g, const AdjArgs<R>& a, R* ring, hipStream_t s) {
-  dim3 grid(g.ntx, g.nty);
-  if (!g.periodic) {
-    const int nr = 2 * (g.nx - 2) + 2 * (g.ny - 2);
-    const unsigned nb = unsigned((nr + NTHREADS - 1) / NTHREADS);
-    if (g.thermal) alks_ring_kernel<R, true><<<nb, NTHREADS, 0, s>>>(g, a, ring);
-    else alks_ring_kernel<R, false><<<nb, NTHREADS, 0, s>>>(g, a, ring);
+void launch_alks_step(const Geo& g, const AdjArgs<R>& a, hipStream_t s) {
+  const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
+  if (g.ty == 8) {
+    if (g.thermal) alks_step_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+    else alks_step_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+  } else {
+    if (g.thermal) alks_step_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+    else alks_step_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
   }
-  if (g.thermal) alks_step_kernel<R, true><<<grid, NTHREADS, 0, s>>>(g, a, ring);
-  else alks_step_kernel<R, false><<<grid, NTHREADS, 0, s>>>(g, a, ring);
 }
 template <typename R>
 void launch_pressure_drop(const Geo& g, const uint8_t* mask, const R* d, double* out,
@@ -823,7 +923,7 @@ void launch_finite_check(const R* a, size_t n, int* flag, hipStream_t s) {
   template void launch_init<R>(const Geo&, const uint8_t*, const R*, const R*, const R*,      \
                                double, R*, R*, R*, R*, hipStream_t);                          \
   template void launch_lks_step<R>(const Geo&, const FwdArgs<R>&, hipStream_t);               \
-  template void launch_alks_step<R>(const Geo&, const AdjArgs<R>&, R*, hipStream_t);          \
+  template void launch_alks_step<R>(const Geo&, const AdjArgs<R>&, hipStream_t);              \
   template void launch_pressure_drop<R>(const Geo&, const uint8_t*, const R*, double*,        \
                                         hipStream_t);                                         \
   template void launch_probe_heat<R>(const Geo&, const uint8_t*, const R*, const R*, double*,  \

@@ -59,7 +59,8 @@ struct lks_ctx {
   void* P[2][4] = {};    // adjoint ping-pong: rho~, Vx, Vy, Theta
   void* C = nullptr;     // checkpoints
   void* Seg = nullptr;   // replay segment
-  void* ring = nullptr;  // completed moments of the ring nodes (adjoint)
+  lks::RingOp* d_ops = nullptr;  // adjoint boundary operators (4 orientations)
+  lks::RingOp ops[4];
   double* acc = nullptr; // per-tile objective accumulators
   double* scal = nullptr;
   int* flag = nullptr;
@@ -109,7 +110,7 @@ size_t base_bytes(const lks_ctx* c) {
   b += 8 * align256(N * r);                // forward ping-pong
   b += 8 * align256(N * r);                // adjoint ping-pong
   b += align256(sizeof(double) * n_tiles(c->geo));
-  b += align256(9 * r * size_t(2 * (c->geo.nx + c->geo.ny)));  // ring moments
+  b += align256(4 * sizeof(lks::RingOp));  // ring operators
   b += align256(sizeof(double) * 8);
   b += align256(sizeof(int) * 4);
   return b;
@@ -379,7 +380,8 @@ struct Run {
     a.sens_mode = sens ? mode : 0;
     a.seed_dp = sdp;
     a.seed_heat = sh;
-    lks::launch_alks_step<R>(g, a, rp<R>(c->ring), c->stream);
+    a.ops = c->d_ops;
+    lks::launch_alks_step<R>(g, a, c->stream);
     c->acur = i1;
   }
 
@@ -512,12 +514,14 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
   g.N = N;
   g.periodic = grid->periodic ? 1 : 0;
   g.thermal = phys->thermal ? 1 : 0;
+  g.ty = 8;
   g.ntx = lks::tiles_along(g.nx, lks::TX);
-  g.nty = lks::tiles_along(g.ny, lks::TY);
+  g.nty = lks::tiles_along(g.ny, g.ty);
   g.A = 4.5 * (1.0 / 6.0 - phys->nu);
   const double Kf = phys->thermal ? phys->nu / phys->Pr : 0.0;
   g.Bf = 3.0 * (1.0 / 6.0 - Kf);
   g.drho_out = bc->rho_out - 1.0;
+  lks::build_ring_ops(g.A, g.Bf, c->ops);
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->budget = mem_budget_bytes;
   c->rsz = grid->precision == LKS_FP64 ? 8 : 4;
@@ -565,7 +569,7 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
   for (int s = 0; s < 2; ++s)
     for (int f = 0; f < 4; ++f) c->P[s][f] = take(N * r);
   c->acc = reinterpret_cast<double*>(take(sizeof(double) * n_tiles(c->geo)));
-  c->ring = take(9 * r * size_t(2 * (c->geo.nx + c->geo.ny)));
+  c->d_ops = reinterpret_cast<lks::RingOp*>(take(4 * sizeof(lks::RingOp)));
   c->scal = reinterpret_cast<double*>(take(sizeof(double) * 8));
   c->flag = reinterpret_cast<int*>(take(sizeof(int) * 4));
   if (c->mode == LKS_UNSTEADY) {
@@ -598,6 +602,8 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
       !hip_ok(c, hipMemcpyAsync(c->d_ufac, c->ufac.data(), sizeof(double) * c->ufac.size(),
                                 hipMemcpyHostToDevice, c->stream),
               "upload u_factor", &st) ||
+      !hip_ok(c, hipMemcpyAsync(c->d_ops, c->ops, sizeof c->ops, hipMemcpyHostToDevice, c->stream),
+              "upload ring operators", &st) ||
       !hip_ok(c, hipStreamSynchronize(c->stream), "bind sync", &st))
     return st;
   // clear the state so that an unused thermal field reads as zero
