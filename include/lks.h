@@ -190,6 +190,33 @@ lks_status lks_write_field(lks_ctx *ctx, int which, const double *dev_in);
 lks_status lks_memory_report(const lks_ctx *ctx, size_t *ckpt_bytes, size_t *state_bytes,
                              int *K);
 
+/* ---- batches (Sec. 2.7 Steps 2-5 for many independent designs) ----------
+ * A batch holds n steady pressure-drop problems of possibly different sizes
+ * and parameters (same precision, all thermal or all non-thermal). One call runs
+ * n_fwd LKS steps, the pressure-drop objective, n_adj ALKS steps and the
+ * sensitivity of every design; each step of all designs is one kernel
+ * launch, and the whole sequence is captured once as a HIP graph and
+ * replayed (use_graph = 1) or launched eagerly (use_graph = 0). */
+typedef struct lks_batch lks_batch;
+
+/* Validates every design as lks_create does (steady mode only). Makes no HIP
+ * call. grids/phys/bcs are arrays of n descriptors. */
+lks_status lks_batch_create(int n, const lks_grid *grids, const lks_phys *phys,
+                            const lks_bc *bcs, void *hip_stream, lks_batch **out);
+lks_status lks_batch_workspace_size(const lks_batch *b, size_t *bytes);
+/* Bind caller-owned device memory (256-byte aligned); creates the batch's
+ * internal capture stream and events. */
+lks_status lks_batch_bind_workspace(lks_batch *b, void *dev_ptr, size_t bytes);
+/* gamma_dev[d], dJdgamma_dev[d]: device pointers of design d (nx*ny doubles);
+ * J_host: n doubles. Synchronises the stream. Linear in J_seed. */
+lks_status lks_batch_run(lks_batch *b, const double *const *gamma_dev, int n_fwd, int n_adj,
+                         double J_seed, double *const *dJdgamma_dev, double *J_host,
+                         int use_graph);
+/* Field `which` of design d at its final forward / adjoint level. */
+lks_status lks_batch_read_field(lks_batch *b, int design, int which, double *dev_out);
+const char *lks_batch_last_error(const lks_batch *b);
+void lks_batch_destroy(lks_batch *b);
+
 const char *lks_strerror(lks_status s);
 const char *lks_last_error(const lks_ctx *ctx);
 void lks_destroy(lks_ctx *ctx);

@@ -116,6 +116,18 @@ struct AdjArgs {
   double seed_heat;
 };
 
+// one design of a batch: geometry and the arguments of both ping-pong parities
+template <typename R>
+struct BatchFwd {
+  Geo g;
+  FwdArgs<R> a[2];
+};
+template <typename R>
+struct BatchAdj {
+  Geo g;
+  AdjArgs<R> a[2];
+};
+
 // host: the four ring operators for a given A and fluid B
 void build_ring_ops(double A, double Bf, RingOp ops[4]);
 
@@ -137,6 +149,15 @@ void launch_pressure_drop(const Geo& g, const uint8_t* mask, const R* d, double*
 template <typename R>
 void launch_probe_heat(const Geo& g, const uint8_t* mask, const R* ux, const R* T, double* out,
                        hipStream_t s);
+template <typename R>
+void launch_lks_step_batch(const BatchFwd<R>* d, const int* tile0, int nd, int total, int ty,
+                           bool thermal, int parity, hipStream_t s);
+template <typename R>
+void launch_alks_step_batch(const BatchAdj<R>* d, const int* tile0, int nd, int total, int ty,
+                            bool thermal, int parity, int last, hipStream_t s);
+template <typename R>
+void launch_pressure_drop_batch(const BatchFwd<R>* d, int nd, int parity, double* out,
+                                hipStream_t s);
 void launch_sum(const double* v, int n, double* out, hipStream_t s);
 void launch_fill(double* p, size_t n, double v, hipStream_t s);
 template <typename R>

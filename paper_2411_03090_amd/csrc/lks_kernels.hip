@@ -136,17 +136,26 @@ struct Tile {
   static constexpr int W1 = TX + 1 + 2, H1 = TY + 1 + 2;
 };
 
-__device__ inline bool block_tile(const Geo& g, int* x0, int* x1, int* y0, int* y1, int* t) {
-  const int T = g.ntx * g.nty;
+// Global tile of this block under the XCD-aware mapping, or -1.
+__device__ inline int xcd_tile(int T) {
   const int nper = (T + NXCD - 1) / NXCD;
   const int b = blockIdx.x;
   const int tile = (b % NXCD) * nper + b / NXCD;
-  if (tile >= T) return false;
+  return tile < T ? tile : -1;
+}
+
+__device__ inline void tile_box(const Geo& g, int tile, int* x0, int* x1, int* y0, int* y1) {
   const int bx = tile % g.ntx, by = tile / g.ntx;
   *x0 = bx * TX;
   *x1 = (bx == g.ntx - 1) ? g.nx : *x0 + TX;
   *y0 = by * g.ty;
   *y1 = (by == g.nty - 1) ? g.ny : *y0 + g.ty;
+}
+
+__device__ inline bool block_tile(const Geo& g, int* x0, int* x1, int* y0, int* y1, int* t) {
+  const int tile = xcd_tile(g.ntx * g.nty);
+  if (tile < 0) return false;
+  tile_box(g, tile, x0, x1, y0, y1);
   *t = tile;
   return true;
 }
@@ -774,6 +783,85 @@ __global__ __launch_bounds__(NTHREADS) void alks_step_kernel(Geo g, AdjArgs<R> a
 }
 
 // ---------------------------------------------------------------------------
+// batched steps: many independent designs in one launch
+// ---------------------------------------------------------------------------
+// Block b runs global tile xcd_tile(total); the design owning it is found by
+// binary search over the designs' first global tiles. All designs advance
+// in lockstep, so one parity selects the ping-pong buffers of every design.
+__device__ inline int design_of(const int* tile0, int nd, int t) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile0[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename R, bool TH, int TY>
+__global__ __launch_bounds__(NTHREADS) void lks_step_batch_kernel(const BatchFwd<R>* __restrict__ d,
+                                                                  const int* __restrict__ tile0,
+                                                                  int nd, int total, int parity) {
+  __shared__ FwdLds<R, TH, TY> L;
+  const int t = xcd_tile(total);
+  if (t < 0) return;
+  const int di = design_of(tile0, nd, t);
+  const Geo g = d[di].g;
+  const FwdArgs<R> a = d[di].a[parity];
+  const int lt = t - tile0[di];
+  int x0, x1, y0, y1;
+  tile_box(g, lt, &x0, &x1, &y0, &y1);
+  const int tw = x1 - x0, th = y1 - y0;
+  if (tw == TX && th == TY) lks_tile<R, TH, TY, true>(g, a, L, x0, y0, tw, th, lt);
+  else lks_tile<R, TH, TY, false>(g, a, L, x0, y0, tw, th, lt);
+}
+
+template <typename R, bool TH, int TY>
+__global__ __launch_bounds__(NTHREADS) void alks_step_batch_kernel(const BatchAdj<R>* __restrict__ d,
+                                                                   const int* __restrict__ tile0,
+                                                                   int nd, int total, int parity,
+                                                                   int last) {
+  __shared__ AdjLds<R, TH, TY> L;
+  const int t = xcd_tile(total);
+  if (t < 0) return;
+  const int di = design_of(tile0, nd, t);
+  const Geo g = d[di].g;
+  AdjArgs<R> a = d[di].a[parity];
+  a.sens_mode = last ? 2 : 0;
+  const int lt = t - tile0[di];
+  int x0, x1, y0, y1;
+  tile_box(g, lt, &x0, &x1, &y0, &y1);
+  const int tw = x1 - x0, th = y1 - y0;
+  if (tw == TX && th == TY) alks_tile<R, TH, TY, true>(g, a, L, x0, y0, tw, th);
+  else alks_tile<R, TH, TY, false>(g, a, L, x0, y0, tw, th);
+}
+
+// pressure drop of every design on its current level: one block per design
+template <typename R>
+__global__ __launch_bounds__(NTHREADS) void pressure_drop_batch_kernel(const BatchFwd<R>* d,
+                                                                      int parity, double* out) {
+  __shared__ double red[NTHREADS / 64];
+  const Geo g = d[blockIdx.x].g;
+  const FwdArgs<R>& a = d[blockIdx.x].a[parity];
+  const int per = 2 * g.nx + 2 * g.ny;
+  double part = 0.0;
+  for (int t = threadIdx.x; t < per; t += NTHREADS) {
+    int i, j;
+    if (t < g.nx) { i = t; j = 0; }
+    else if (t < 2 * g.nx) { i = t - g.nx; j = g.ny - 1; }
+    else if (t < 2 * g.nx + g.ny) { i = 0; j = t - 2 * g.nx; }
+    else { i = g.nx - 1; j = t - 2 * g.nx - g.ny; }
+    const int k = j * g.nx + i;
+    const int m = a.mask[k];
+    if ((m & 3) == FLOW_CORNER) continue;
+    if (m & TAG_J_INLET) part += double(a.d0[k]);
+    if (m & TAG_J_OUTLET) part -= double(a.d0[k]);
+  }
+  double s = block_sum(part, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
 // sum over inlet nodes minus sum over outlet nodes of drho (ring only)
@@ -894,6 +982,35 @@ void launch_probe_heat(const Geo& g, const uint8_t* mask, const R* ux, const R* 
                        hipStream_t s) {
   probe_heat_kernel<R><<<1, NTHREADS, 0, s>>>(g, mask, ux, T, out);
 }
+template <typename R>
+void launch_lks_step_batch(const BatchFwd<R>* d, const int* tile0, int nd, int total, int ty,
+                           bool thermal, int parity, hipStream_t s) {
+  const unsigned nb = unsigned(xcd_blocks(total));
+  if (ty == 8) {
+    if (thermal) lks_step_batch_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
+    else lks_step_batch_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
+  } else {
+    if (thermal) lks_step_batch_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
+    else lks_step_batch_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
+  }
+}
+template <typename R>
+void launch_alks_step_batch(const BatchAdj<R>* d, const int* tile0, int nd, int total, int ty,
+                            bool thermal, int parity, int last, hipStream_t s) {
+  const unsigned nb = unsigned(xcd_blocks(total));
+  if (ty == 8) {
+    if (thermal) alks_step_batch_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity, last);
+    else alks_step_batch_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity, last);
+  } else {
+    if (thermal) alks_step_batch_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity, last);
+    else alks_step_batch_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity, last);
+  }
+}
+template <typename R>
+void launch_pressure_drop_batch(const BatchFwd<R>* d, int nd, int parity, double* out,
+                                hipStream_t s) {
+  pressure_drop_batch_kernel<R><<<nd, NTHREADS, 0, s>>>(d, parity, out);
+}
 void launch_sum(const double* v, int n, double* out, hipStream_t s) {
   sum_kernel<<<1, NTHREADS, 0, s>>>(v, n, out);
 }
@@ -929,6 +1046,11 @@ void launch_finite_check(const R* a, size_t n, int* flag, hipStream_t s) {
   template void launch_probe_heat<R>(const Geo&, const uint8_t*, const R*, const R*, double*,  \
                                      hipStream_t);                                            \
   template void launch_fill_r<R>(R*, size_t, hipStream_t);                                    \
+  template void launch_lks_step_batch<R>(const BatchFwd<R>*, const int*, int, int, int, bool, int, \
+                                         hipStream_t);                                        \
+  template void launch_alks_step_batch<R>(const BatchAdj<R>*, const int*, int, int, int, bool, int, \
+                                          int, hipStream_t);                                  \
+  template void launch_pressure_drop_batch<R>(const BatchFwd<R>*, int, int, double*, hipStream_t); \
   template void launch_to_double<R>(const R*, double*, size_t, hipStream_t);                  \
   template void launch_from_double<R>(const double*, R*, size_t, hipStream_t);                \
   template void launch_finite_check<R>(const R*, size_t, int*, hipStream_t);

@@ -768,3 +768,351 @@ const char* lks_last_error(const lks_ctx* c) {
 void lks_destroy(lks_ctx* c) { delete c; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches: many independent steady designs, one launch per step
+// ---------------------------------------------------------------------------
+struct lks_batch {
+  int n = 0;
+  std::vector<lks_ctx*> ctx;
+  std::vector<size_t> off;  // workspace offset of each design's slice
+  int rsz = 4;
+  int thermal = 0;
+  int ty = 8;
+  hipStream_t user = nullptr;
+  hipStream_t own = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  size_t total = 0;
+  bool bound = false;
+  char* ws = nullptr;
+  std::vector<int> tile0;
+  int total_tiles = 0;
+  // device
+  int* d_tile0 = nullptr;
+  void* d_fwd = nullptr;     // BatchFwd<R>[n]
+  void* d_adj = nullptr;     // BatchAdj<R>[3 n]: parities 0, 1 and the zero-input first step
+  double* d_J = nullptr;
+  double* d_sens = nullptr;  // n * maxN doubles
+  void* d_zero = nullptr;    // maxN values, all zero
+  size_t maxN = 0;
+  // graph of the last (n_fwd, n_adj)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int g_nf = -1, g_na = -1;
+  int last_nf = 0, last_na = 0;
+  bool have_run = false;
+  std::string err;
+};
+
+namespace {
+
+lks_status bfail(lks_batch* b, lks_status s, const std::string& msg) {
+  if (b) b->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+template <typename R>
+void build_batch_desc(lks_batch* b, double seed, int nf, std::vector<char>& fwd,
+                      std::vector<char>& adj) {
+  fwd.assign(sizeof(lks::BatchFwd<R>) * b->n, 0);
+  adj.assign(sizeof(lks::BatchAdj<R>) * 3 * b->n, 0);
+  auto* F = reinterpret_cast<lks::BatchFwd<R>*>(fwd.data());
+  auto* Aj = reinterpret_cast<lks::BatchAdj<R>*>(adj.data());
+  for (int d = 0; d < b->n; ++d) {
+    lks_ctx* c = b->ctx[d];
+    F[d].g = c->geo;
+    for (int p = 0; p < 2; ++p) {
+      lks::FwdArgs<R>& a = F[d].a[p];
+      a.mask = c->d_mask;
+      a.inv1pa = rp<R>(c->inv1pa);
+      a.B = rp<R>(c->B);
+      a.ubx = rp<R>(c->ubx);
+      a.uby = rp<R>(c->uby);
+      a.Tb = rp<R>(c->Tb);
+      a.ufac = c->d_ufac;
+      a.level_out = 0;
+      a.d0 = rp<R>(c->S[p][0]);
+      a.ux0 = rp<R>(c->S[p][1]);
+      a.uy0 = rp<R>(c->S[p][2]);
+      a.T0 = rp<R>(c->S[p][3]);
+      a.d1 = rp<R>(c->S[p ^ 1][0]);
+      a.ux1 = rp<R>(c->S[p ^ 1][1]);
+      a.uy1 = rp<R>(c->S[p ^ 1][2]);
+      a.T1 = rp<R>(c->S[p ^ 1][3]);
+      a.acc = nullptr;
+      a.objective = c->objective;
+    }
+    const int fin = nf & 1;  // ping-pong index of the final forward level
+    for (int v = 0; v < 3; ++v) {
+      lks::BatchAdj<R>& D = Aj[v * b->n + d];
+      D.g = c->geo;
+      for (int p = 0; p < 2; ++p) {
+        lks::AdjArgs<R>& a = D.a[p];
+        a.mask = c->d_mask;
+        a.inv1pa = rp<R>(c->inv1pa);
+        a.B = rp<R>(c->B);
+        a.dA3 = rp<R>(c->dA3);
+        a.dB = rp<R>(c->dB);
+        a.ux = rp<R>(c->S[fin][1]);
+        a.uy = rp<R>(c->S[fin][2]);
+        a.T = rp<R>(c->S[fin][3]);
+        const bool zero = v == 2;
+        const R* z = rp<R>(b->d_zero);
+        a.r0 = zero ? z : rp<R>(c->P[p][0]);
+        a.vx0 = zero ? z : rp<R>(c->P[p][1]);
+        a.vy0 = zero ? z : rp<R>(c->P[p][2]);
+        a.th0 = zero ? z : rp<R>(c->P[p][3]);
+        a.r1 = rp<R>(c->P[p ^ 1][0]);
+        a.vx1 = rp<R>(c->P[p ^ 1][1]);
+        a.vy1 = rp<R>(c->P[p ^ 1][2]);
+        a.th1 = rp<R>(c->P[p ^ 1][3]);
+        a.ops = c->d_ops;
+        a.sens = b->d_sens + size_t(d) * b->maxN;
+        a.sens_mode = 0;
+        a.seed_dp = c->objective == LKS_OBJ_PRESSURE_DROP ? seed : 0.0;
+        a.seed_heat = c->objective == LKS_OBJ_HEAT ? seed : 0.0;
+      }
+    }
+  }
+}
+
+// the step sequence of one batch run: n_fwd LKS steps of every design, the
+// pressure drop of every design, n_adj ALKS steps with the last writing the
+// sensitivity
+template <typename R>
+void enqueue_batch_steps(lks_batch* b, int nf, int na, hipStream_t s) {
+  auto* F = static_cast<const lks::BatchFwd<R>*>(b->d_fwd);
+  auto* Aj = static_cast<const lks::BatchAdj<R>*>(b->d_adj);
+  for (int k = 0; k < nf; ++k)
+    lks::launch_lks_step_batch<R>(F, b->d_tile0, b->n, b->total_tiles, b->ty, b->thermal, k & 1, s);
+  lks::launch_pressure_drop_batch<R>(F, b->n, nf & 1, b->d_J, s);
+  for (int k = 0; k < na; ++k) {
+    const lks::BatchAdj<R>* D = k == 0 ? Aj + 2 * b->n : Aj;
+    lks::launch_alks_step_batch<R>(D, b->d_tile0, b->n, b->total_tiles, b->ty, b->thermal, k & 1,
+                                   k == na - 1, s);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lks_status lks_batch_create(int n, const lks_grid* grids, const lks_phys* phys, const lks_bc* bcs,
+                            void* hip_stream, lks_batch** out) {
+  if (!out) return bfail(nullptr, LKS_E_INVALID, "null output pointer");
+  *out = nullptr;
+  if (n < 1 || !grids || !phys || !bcs) return bfail(nullptr, LKS_E_INVALID, "empty batch");
+  lks_batch* b = new lks_batch();
+  b->n = n;
+  b->user = static_cast<hipStream_t>(hip_stream);
+  size_t off = 0;
+  for (int d = 0; d < n; ++d) {
+    if (bcs[d].mode != LKS_STEADY || bcs[d].objective != LKS_OBJ_PRESSURE_DROP) {
+      for (auto* p : b->ctx) lks_destroy(p);
+      delete b;
+      return bfail(nullptr, LKS_E_UNSUPPORTED,
+                   "batches hold steady problems with the pressure-drop objective");
+    }
+    if (grids[d].precision != grids[0].precision || phys[d].thermal != phys[0].thermal) {
+      for (auto* p : b->ctx) lks_destroy(p);
+      delete b;
+      return bfail(nullptr, LKS_E_INVALID, "designs of a batch share precision and physics kind");
+    }
+    lks_ctx* c = nullptr;
+    lks_status st = lks_create(&grids[d], &phys[d], &bcs[d], 0, hip_stream, &c);
+    if (st != LKS_OK) {
+      for (auto* p : b->ctx) lks_destroy(p);
+      delete b;
+      return bfail(nullptr, st, "design " + std::to_string(d) + ": " + g_create_error);
+    }
+    b->ctx.push_back(c);
+    b->off.push_back(off);
+    off += align256(c->plan.total);
+    b->tile0.push_back(b->total_tiles);
+    b->total_tiles += n_tiles(c->geo);
+    b->maxN = std::max(b->maxN, size_t(c->geo.N));
+    b->ty = c->geo.ty;
+  }
+  b->rsz = b->ctx[0]->rsz;
+  b->thermal = phys[0].thermal ? 1 : 0;
+  const size_t fwd = sizeof(lks::BatchFwd<double>) * n;   // the double variant is the larger
+  const size_t adj = sizeof(lks::BatchAdj<double>) * 3 * n;
+  off += align256(sizeof(int) * n) + align256(fwd) + align256(adj) + align256(sizeof(double) * n);
+  off += align256(sizeof(double) * b->maxN * n) + align256(size_t(b->rsz) * b->maxN);
+  b->total = off;
+  *out = b;
+  return LKS_OK;
+}
+
+lks_status lks_batch_workspace_size(const lks_batch* b, size_t* bytes) {
+  if (!b || !bytes) return LKS_E_INVALID;
+  *bytes = b->total;
+  return LKS_OK;
+}
+
+lks_status lks_batch_bind_workspace(lks_batch* b, void* dev_ptr, size_t bytes) {
+  if (!b) return LKS_E_INVALID;
+  if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255))
+    return bfail(b, LKS_E_INVALID, "workspace must be non-null and 256-byte aligned");
+  if (bytes < b->total) return bfail(b, LKS_E_NOMEM, "workspace smaller than lks_batch_workspace_size");
+  char* base = static_cast<char*>(dev_ptr);
+  for (int d = 0; d < b->n; ++d) {
+    lks_status st = lks_bind_workspace(b->ctx[d], base + b->off[d], b->ctx[d]->plan.total);
+    if (st != LKS_OK) return bfail(b, st, "design " + std::to_string(d) + ": " + b->ctx[d]->err);
+  }
+  char* p = base + (b->off.back() + align256(b->ctx.back()->plan.total));
+  auto take = [&](size_t s) {
+    char* q = p;
+    p += align256(s);
+    return q;
+  };
+  b->d_tile0 = reinterpret_cast<int*>(take(sizeof(int) * b->n));
+  b->d_fwd = take(sizeof(lks::BatchFwd<double>) * b->n);
+  b->d_adj = take(sizeof(lks::BatchAdj<double>) * 3 * b->n);
+  b->d_J = reinterpret_cast<double*>(take(sizeof(double) * b->n));
+  b->d_sens = reinterpret_cast<double*>(take(sizeof(double) * b->maxN * b->n));
+  b->d_zero = take(size_t(b->rsz) * b->maxN);
+  lks_status st = LKS_OK;
+  hipStream_t s = b->user;
+  if (b->rsz == 8) lks::launch_fill_r<double>(static_cast<double*>(b->d_zero), b->maxN, s);
+  else lks::launch_fill_r<float>(static_cast<float*>(b->d_zero), b->maxN, s);
+  if (!hip_ok(nullptr, hipMemcpyAsync(b->d_tile0, b->tile0.data(), sizeof(int) * b->n,
+                                      hipMemcpyHostToDevice, s), "upload tiles", &st) ||
+      !hip_ok(nullptr, hipStreamSynchronize(s), "bind sync", &st))
+    return bfail(b, st, g_create_error);
+  if (!b->own) {
+    if (!hip_ok(nullptr, hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking), "stream", &st) ||
+        !hip_ok(nullptr, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming), "event", &st) ||
+        !hip_ok(nullptr, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming), "event", &st))
+      return bfail(b, st, g_create_error);
+  }
+  b->ws = base;
+  b->bound = true;
+  b->have_run = false;
+  return LKS_OK;
+}
+
+lks_status lks_batch_run(lks_batch* b, const double* const* gamma_dev, int n_fwd, int n_adj,
+                         double J_seed, double* const* dJdgamma_dev, double* J_host,
+                         int use_graph) {
+  if (!b) return LKS_E_INVALID;
+  if (!b->bound) return bfail(b, LKS_E_STATE, "no workspace bound");
+  if (!gamma_dev || !dJdgamma_dev || !J_host) return bfail(b, LKS_E_INVALID, "null argument");
+  if (n_fwd < 0 || n_adj < 1) return bfail(b, LKS_E_INVALID, "need n_fwd >= 0 and n_adj >= 1");
+  if (!std::isfinite(J_seed)) return bfail(b, LKS_E_INVALID, "seed not finite");
+  for (int d = 0; d < b->n; ++d)
+    if (!gamma_dev[d] || !dJdgamma_dev[d]) return bfail(b, LKS_E_INVALID, "null design pointer");
+  lks_status st = LKS_OK;
+  // descriptor tables (host -> device, ordered before the steps)
+  std::vector<char> fwd, adj;
+  if (b->rsz == 8) build_batch_desc<double>(b, J_seed, n_fwd, fwd, adj);
+  else build_batch_desc<float>(b, J_seed, n_fwd, fwd, adj);
+  hipStream_t s = b->user;
+  if (!hip_ok(nullptr, hipMemcpyAsync(b->d_fwd, fwd.data(), fwd.size(), hipMemcpyHostToDevice, s),
+              "upload descriptors", &st) ||
+      !hip_ok(nullptr, hipMemcpyAsync(b->d_adj, adj.data(), adj.size(), hipMemcpyHostToDevice, s),
+              "upload descriptors", &st))
+    return bfail(b, st, g_create_error);
+  // design coefficients and level-0 states
+  for (int d = 0; d < b->n; ++d) {
+    lks_ctx* c = b->ctx[d];
+    c->last_level = 0;
+    c->cur = 0;
+    if (b->rsz == 8) {
+      Run<double> r(c);
+      r.coefficients(gamma_dev[d]);
+      double* s0[4];
+      for (int f = 0; f < 4; ++f) s0[f] = rp<double>(c->S[0][f]);
+      r.init(s0);
+    } else {
+      Run<float> r(c);
+      r.coefficients(gamma_dev[d]);
+      float* s0[4];
+      for (int f = 0; f < 4; ++f) s0[f] = rp<float>(c->S[0][f]);
+      r.init(s0);
+    }
+  }
+  if (use_graph) {
+    if (b->exec && (b->g_nf != n_fwd || b->g_na != n_adj)) {
+      hipGraphExecDestroy(b->exec);
+      hipGraphDestroy(b->graph);
+      b->exec = nullptr;
+      b->graph = nullptr;
+    }
+    if (!b->exec) {
+      if (!hip_ok(nullptr, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal),
+                  "begin capture", &st))
+        return bfail(b, st, g_create_error);
+      if (b->rsz == 8) enqueue_batch_steps<double>(b, n_fwd, n_adj, b->own);
+      else enqueue_batch_steps<float>(b, n_fwd, n_adj, b->own);
+      if (!hip_ok(nullptr, hipStreamEndCapture(b->own, &b->graph), "end capture", &st) ||
+          !hip_ok(nullptr, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0),
+                  "instantiate graph", &st))
+        return bfail(b, st, g_create_error);
+      b->g_nf = n_fwd;
+      b->g_na = n_adj;
+    }
+    if (!hip_ok(nullptr, hipEventRecord(b->ev_in, s), "event", &st) ||
+        !hip_ok(nullptr, hipStreamWaitEvent(b->own, b->ev_in, 0), "wait", &st) ||
+        !hip_ok(nullptr, hipGraphLaunch(b->exec, b->own), "graph launch", &st) ||
+        !hip_ok(nullptr, hipEventRecord(b->ev_out, b->own), "event", &st) ||
+        !hip_ok(nullptr, hipStreamWaitEvent(s, b->ev_out, 0), "wait", &st))
+      return bfail(b, st, g_create_error);
+  } else {
+    if (b->rsz == 8) enqueue_batch_steps<double>(b, n_fwd, n_adj, s);
+    else enqueue_batch_steps<float>(b, n_fwd, n_adj, s);
+  }
+  // sensitivities to the caller, objectives to the host
+  std::vector<double> Js(b->n);
+  for (int d = 0; d < b->n; ++d) {
+    const size_t N = size_t(b->ctx[d]->geo.N);
+    if (!hip_ok(nullptr, hipMemcpyAsync(dJdgamma_dev[d], b->d_sens + size_t(d) * b->maxN,
+                                        N * sizeof(double), hipMemcpyDeviceToDevice, s),
+                "copy sensitivity", &st))
+      return bfail(b, st, g_create_error);
+  }
+  if (!hip_ok(nullptr, hipMemcpyAsync(Js.data(), b->d_J, sizeof(double) * b->n,
+                                      hipMemcpyDeviceToHost, s), "read objectives", &st) ||
+      !hip_ok(nullptr, hipStreamSynchronize(s), "batch sync", &st) ||
+      !hip_ok(nullptr, hipGetLastError(), "batch launch", &st))
+    return bfail(b, st, g_create_error);
+  for (int d = 0; d < b->n; ++d) {
+    lks_ctx* c = b->ctx[d];
+    J_host[d] = (Js[d] + double(c->n_in - c->n_out)) / 3.0;
+    c->cur = n_fwd & 1;
+    c->acur = n_adj & 1;
+    c->last_level = n_fwd;
+    c->have_forward = true;
+    c->have_adjoint = true;
+  }
+  b->last_nf = n_fwd;
+  b->last_na = n_adj;
+  b->have_run = true;
+  return LKS_OK;
+}
+
+lks_status lks_batch_read_field(lks_batch* b, int design, int which, double* dev_out) {
+  if (!b || design < 0 || design >= b->n) return LKS_E_INVALID;
+  if (!b->have_run) return bfail(b, LKS_E_STATE, "read before lks_batch_run");
+  lks_status st = lks_read_field(b->ctx[design], which, dev_out);
+  if (st != LKS_OK) return bfail(b, st, b->ctx[design]->err);
+  return LKS_OK;
+}
+
+const char* lks_batch_last_error(const lks_batch* b) {
+  return b ? b->err.c_str() : g_create_error.c_str();
+}
+
+void lks_batch_destroy(lks_batch* b) {
+  if (!b) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->ev_in) hipEventDestroy(b->ev_in);
+  if (b->ev_out) hipEventDestroy(b->ev_out);
+  if (b->own) hipStreamDestroy(b->own);
+  for (auto* c : b->ctx) lks_destroy(c);
+  delete b;
+}
+
+}  // extern "C"

@@ -40,7 +40,9 @@ FIELDS = {"drho": 0, "ux": 1, "uy": 2, "T": 3,
 EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forward",
             "lks_advance", "lks_objective", "alks_backward", "alks_advance",
             "lks_read_field", "lks_write_field", "lks_memory_report", "lks_strerror",
-            "lks_last_error", "lks_destroy")
+            "lks_last_error", "lks_destroy", "lks_batch_create", "lks_batch_workspace_size",
+            "lks_batch_bind_workspace", "lks_batch_run", "lks_batch_read_field",
+            "lks_batch_last_error", "lks_batch_destroy")
 
 
 class Grid(ctypes.Structure):
@@ -98,6 +100,23 @@ _lib.lks_last_error.argtypes = [_vp]
 _lib.lks_last_error.restype = ctypes.c_char_p
 _lib.lks_destroy.argtypes = [_vp]
 _lib.lks_destroy.restype = None
+_lib.lks_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(Grid), ctypes.POINTER(Phys),
+                                  ctypes.POINTER(BC), _vp, ctypes.POINTER(_vp)]
+_lib.lks_batch_create.restype = _st
+_lib.lks_batch_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+_lib.lks_batch_workspace_size.restype = _st
+_lib.lks_batch_bind_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
+_lib.lks_batch_bind_workspace.restype = _st
+_lib.lks_batch_run.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int,
+                               ctypes.c_double, ctypes.POINTER(_vp),
+                               ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+_lib.lks_batch_run.restype = _st
+_lib.lks_batch_read_field.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp]
+_lib.lks_batch_read_field.restype = _st
+_lib.lks_batch_last_error.argtypes = [_vp]
+_lib.lks_batch_last_error.restype = ctypes.c_char_p
+_lib.lks_batch_destroy.argtypes = [_vp]
+_lib.lks_batch_destroy.restype = None
 
 
 class LKSError(RuntimeError):
@@ -220,3 +239,74 @@ class LKS:
             pass
 
 
+
+
+def _bcheck(status, b=None):
+    if status != LKS_OK:
+        raise LKSError(status, _lib.lks_batch_last_error(b).decode())
+
+
+class Batch:
+    """Many independent steady pressure-drop designs advanced together: one
+    kernel launch per step for all designs, the step sequence replayed as a
+    HIP graph."""
+
+    def __init__(self, workloads, precision="fp32", device=None, stream=None, bind=True):
+        self.wls = list(workloads)
+        self.n = len(self.wls)
+        self._keep = [LKS(w, precision=precision, bind=False, stream=0) for w in self.wls]
+        self.grids = (Grid * self.n)(*[k.grid for k in self._keep])
+        self.phys = (Phys * self.n)(*[k.phys for k in self._keep])
+        self.bcs = (BC * self.n)(*[k.bc for k in self._keep])
+        self.device = device
+        if bind and stream is None:
+            import torch
+            stream = torch.cuda.current_stream(torch.device(device or "cuda")).cuda_stream
+        self.stream = stream
+        self.b = _vp()
+        _bcheck(_lib.lks_batch_create(self.n, self.grids, self.phys, self.bcs, _vp(stream or 0),
+                                      ctypes.byref(self.b)))
+        self.workspace = None
+        if bind:
+            self.bind()
+
+    def workspace_size(self):
+        n = ctypes.c_size_t()
+        _bcheck(_lib.lks_batch_workspace_size(self.b, ctypes.byref(n)), self.b)
+        return n.value
+
+    def bind(self):
+        import torch
+        n = self.workspace_size()
+        self.workspace = torch.empty(n + 256, dtype=torch.uint8,
+                                     device=torch.device(self.device or "cuda"))
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        _bcheck(_lib.lks_batch_bind_workspace(self.b, _vp(aligned), ctypes.c_size_t(n)), self.b)
+
+    def run(self, gammas, outs, n_fwd, n_adj, seed=1.0, graph=True):
+        g = (_vp * self.n)(*[t.data_ptr() for t in gammas])
+        o = (_vp * self.n)(*[t.data_ptr() for t in outs])
+        J = (ctypes.c_double * self.n)()
+        _bcheck(_lib.lks_batch_run(self.b, g, int(n_fwd), int(n_adj), float(seed), o, J,
+                                   int(bool(graph))), self.b)
+        return list(J)
+
+    def read(self, design, name, out=None):
+        import torch
+        wl = self.wls[design]
+        if out is None:
+            out = torch.empty(wl.nx * wl.ny, dtype=torch.float64, device=self.workspace.device)
+        _bcheck(_lib.lks_batch_read_field(self.b, int(design), FIELDS[name], _vp(out.data_ptr())),
+                self.b)
+        return out
+
+    def close(self):
+        if self.b:
+            _lib.lks_batch_destroy(self.b)
+            self.b = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,110 @@
+"""Batched designs: one launch per step for many designs of uneven size, the
+step sequence replayed as a HIP graph."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+from paper_2411_03090_amd import lks, workloads as W  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1), device=DEV)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def _small_designs(nf, na):
+    shapes = [(40, 24, 10.0), (70, 37, 30.0), (64, 64, 120.0), (130, 9, 15.0), (33, 65, 60.0)]
+    out = []
+    for s, (nx, ny, Re) in enumerate(shapes):
+        w = W.steady_channel_grf(nx, ny, Re=Re, sigma=3.0, seed=s, n_fwd=nf, n_adj=na)
+        out.append(w)
+    return out
+
+
+def _single(wl, prec):
+    c = lks.LKS(wl, precision=prec, device=DEV)
+    g = T(wl.gamma)
+    d = torch.empty_like(g)
+    c.forward(g, wl.n_fwd)
+    J = c.objective()
+    c.backward(1.0, d, wl.n_adj)
+    torch.cuda.synchronize()
+    return J, d.cpu().numpy()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_fp64_equals_single_runs_and_oracle(graph):
+    print(f"[gpu] batch of 5 uneven designs fp64 graph={graph}", flush=True)
+    wls = _small_designs(400, 300)
+    b = lks.Batch(wls, precision="fp64", device=DEV)
+    gs = [T(w.gamma) for w in wls]
+    outs = [torch.empty_like(g) for g in gs]
+    Js = b.run(gs, outs, 400, 300, graph=graph)
+    for d, w in enumerate(wls):
+        Js1, d1 = _single(w, "fp64")
+        assert Js[d] == Js1
+        assert np.array_equal(outs[d].cpu().numpy(), d1)
+        Jo, so, _, _ = O.gradient(w)
+        assert abs(Js[d] - Jo) / abs(Jo) < 1e-12
+        assert rel(outs[d].cpu().numpy(), so) < 1e-12
+
+
+def test_graph_replays_match_eager():
+    print("[gpu] batch graph replays", flush=True)
+    wls = _small_designs(300, 200)
+    b = lks.Batch(wls, precision="fp32", device=DEV)
+    gs = [T(w.gamma) for w in wls]
+    ref = [torch.empty_like(g) for g in gs]
+    Jref = b.run(gs, ref, 300, 200, graph=False)
+    ref = [r.clone() for r in ref]
+    for rep in range(3):
+        outs = [torch.full_like(g, float("nan")) for g in gs]
+        Js = b.run(gs, outs, 300, 200, graph=True)
+        torch.cuda.synchronize()
+        assert Js == Jref, rep
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), rep
+        # eager work of the program between replays
+        x = torch.randn(1 << 20, device=DEV)
+        (x * x).sum().item()
+
+
+def test_batch_fp32_within_tolerance():
+    print("[gpu] batch fp32 vs oracle", flush=True)
+    wls = _small_designs(400, 300)
+    b = lks.Batch(wls, precision="fp32", device=DEV)
+    gs = [T(w.gamma) for w in wls]
+    outs = [torch.empty_like(g) for g in gs]
+    Js = b.run(gs, outs, 400, 300)
+    for d, w in enumerate(wls):
+        Jo, so, _, _ = O.gradient(w)
+        assert abs(Js[d] - Jo) / abs(Jo) < 1e-3
+        assert rel(outs[d].cpu().numpy(), so) < 1e-3
+
+
+def test_batch_of_64_uneven_designs_matches_single_runs():
+    """The 64-design workload (edge lengths from {128,...,512}, Re in
+    [10, 200]) at full size, over a step count short enough to repeat a few
+    designs singly; the batch must reproduce them bit for bit."""
+    print("[gpu] batch of 64 designs, 200+200 steps fp32", flush=True)
+    wls = W.batch_designs(64, n_steps=200)
+    b = lks.Batch(wls, precision="fp32", device=DEV)
+    gs = [T(w.gamma) for w in wls]
+    outs = [torch.empty_like(g) for g in gs]
+    Js = b.run(gs, outs, 200, 200)
+    assert all(np.isfinite(Js))
+    for d in (0, 17, 63):
+        J1, d1 = _single(wls[d], "fp32")
+        assert Js[d] == J1
+        assert np.array_equal(outs[d].cpu().numpy(), d1)
