@@ -31,6 +31,8 @@ def parse():
     p.add_argument("--n-adj", type=int, default=40000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-steps", type=int, default=400)
+    p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--batch-steps", type=int, default=2000)
     return p.parse_args()
 
 
@@ -74,8 +76,10 @@ def main():
         return e0.elapsed_time(e1) / k, J, out
 
     c32 = lks.LKS(wl, precision="fp32", device=dev)
+    ty32 = c32.autotune(g, 200)
     ms32, J32, d32 = timed(c32, args.steps, args.warmup)
     c64 = lks.LKS(wl, precision="fp64", device=dev)
+    ty64 = c64.autotune(g, 200)
     ms64, J64, d64 = timed(c64, args.fp64_steps, 0)
 
     upd = nodes * (wl.n_fwd + wl.n_adj)
@@ -109,6 +113,8 @@ def main():
                 "traffic": None, "avg_launch_us": alks_us,
                 "bytes_per_node": bytes_per_node, "nodes_per_launch": nodes}
 
+    batched = None if args.no_batch else batched_bench(args, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, args.cpu_sample_steps)
@@ -129,7 +135,8 @@ def main():
         "config": {"workload": "steady channel 512x512 D2Q9, Re=100, gamma smoothed Gaussian "
                                "field (sigma=8), pressure-drop objective",
                    "nx": wl.nx, "ny": wl.ny, "n_fwd": wl.n_fwd, "n_adj": wl.n_adj,
-                   "precision": "fp32 state (rho-1), fp64 objective and sensitivity"},
+                   "precision": "fp32 state (rho-1), fp64 objective and sensitivity",
+                   "tile_rows": {"fp32": ty32, "fp64": ty64}},
         "gradients_per_s": 1e3 / ms32,
         "fp64_gpu": {"value": mlups64, "unit": "MLUPS", "ms_per_step": ms64,
                      "gradients_per_s": 1e3 / ms64},
@@ -137,8 +144,50 @@ def main():
         "fp32_vs_fp64_rel_error": {"J": err_J, "dJdgamma_l2": err_grad},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_64_designs": batched,
     }
     print(json.dumps(line), flush=True)
+
+
+def batched_bench(args, dev):
+    """64 independent steady designs, edge lengths from {128,...,512} and
+    Re in [10, 200], forward + adjoint of all designs with one launch per
+    step, replayed as a HIP graph (FP32 state, FP64 J and dJ/dgamma)."""
+    import torch
+    from paper_2411_03090_amd import lks, workloads as W
+    n = args.batch_steps
+    wls = W.batch_designs(64, n_steps=n)
+    nodes = sum(w.nx * w.ny for w in wls)
+    b = lks.Batch(wls, precision="fp32", device=dev)
+    gs = [torch.tensor(w.gamma.reshape(-1), dtype=torch.float64, device=dev) for w in wls]
+    outs = [torch.empty_like(x) for x in gs]
+    ty = b.autotune(gs, outs, 50)
+    b.run(gs, outs, n, n)                                   # warm-up, builds the graph
+    torch.cuda.synchronize()
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.run(gs, outs, n, n)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    # batched ALKS step alone: a run with no forward steps and n adjoint steps
+    b.run(gs, outs, 0, n)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.run(gs, outs, 0, n)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_us = e0.elapsed_time(e1) * 1e3 / n
+    achieved = 37 * nodes / (adj_us * 1e-6) / 1e9
+    return {"designs": 64, "nodes": nodes, "n_fwd": n, "n_adj": n, "ms_per_batch": ms,
+            "mlups": nodes * 2 * n / (ms * 1e-3) / 1e6,
+            "gradients_per_s": 64 * 1e3 / ms, "tile_rows": ty,
+            "roofline": {"bound": "hbm", "kernel": "alks_step_batch_kernel<float>",
+                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "avg_launch_us": adj_us,
+                         "bytes_per_node": 37, "nodes_per_launch": nodes}}
 
 
 def cpu_baseline(wl, n):

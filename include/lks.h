@@ -184,6 +184,17 @@ lks_status lks_read_field(lks_ctx *ctx, int which, double *dev_out);
  * doubles), e.g. to start a step from a prescribed state. Asynchronous. */
 lks_status lks_write_field(lks_ctx *ctx, int which, const double *dev_in);
 
+/* Tile autotuner: times `steps` forward and `steps` adjoint steps of the
+ * design gamma_dev for each tile height the kernels provide (64 x 4 and
+ * 64 x 8 nodes) on this context's stream, keeps the fastest and reports it in
+ * *tile_rows. Synchronises; the forward and adjoint states are discarded
+ * (run lks_forward afterwards). */
+lks_status lks_autotune(lks_ctx *ctx, const double *gamma_dev, int steps, int *tile_rows);
+
+/* Set the tile height (4 or 8 rows of 64 nodes) explicitly; results do not
+ * depend on it. Discards the forward and adjoint states. */
+lks_status lks_set_tile_rows(lks_ctx *ctx, int tile_rows);
+
 /* Memory plan: bytes of checkpoint + replay storage, bytes of the rest of
  * the workspace, and the checkpoint interval K (N when the whole trajectory
  * is stored; 0 for steady problems). */
@@ -212,6 +223,11 @@ lks_status lks_batch_bind_workspace(lks_batch *b, void *dev_ptr, size_t bytes);
 lks_status lks_batch_run(lks_batch *b, const double *const *gamma_dev, int n_fwd, int n_adj,
                          double J_seed, double *const *dJdgamma_dev, double *J_host,
                          int use_graph);
+/* Tile autotuner of a batch: runs the batch eagerly for `steps` forward and
+ * adjoint steps per tile height and keeps the fastest. scratch_dev[d]
+ * receives a throw-away sensitivity. Synchronises. */
+lks_status lks_batch_autotune(lks_batch *b, const double *const *gamma_dev, int steps,
+                              double *const *scratch_dev, int *tile_rows);
 /* Field `which` of design d at its final forward / adjoint level. */
 lks_status lks_batch_read_field(lks_batch *b, int design, int which, double *dev_out);
 const char *lks_batch_last_error(const lks_batch *b);

@@ -88,6 +88,16 @@ bool hip_ok(lks_ctx* c, hipError_t e, const char* what, lks_status* st) {
 }
 
 int n_tiles(const Geo& g) { return g.ntx * g.nty; }
+// tiles of the smallest tile height the kernels support (sizes accumulators)
+int max_tiles(const Geo& g) {
+  return lks::tiles_along(g.nx, lks::TX) * lks::tiles_along(g.ny, 4);
+}
+constexpr int TILE_ROWS[2] = {4, 8};
+void set_tile_rows(Geo& g, int ty) {
+  g.ty = ty;
+  g.ntx = lks::tiles_along(g.nx, lks::TX);
+  g.nty = lks::tiles_along(g.ny, ty);
+}
 
 // fields stored per checkpoint / per replay slot
 int ckpt_fields(const lks_ctx* c) { return c->phys.thermal ? 4 : 3; }
@@ -109,7 +119,7 @@ size_t base_bytes(const lks_ctx* c) {
   b += 4 * align256(N * r);                // coefficients
   b += 8 * align256(N * r);                // forward ping-pong
   b += 8 * align256(N * r);                // adjoint ping-pong
-  b += align256(sizeof(double) * n_tiles(c->geo));
+  b += align256(sizeof(double) * max_tiles(c->geo));
   b += align256(4 * sizeof(lks::RingOp));  // ring operators
   b += align256(sizeof(double) * 8);
   b += align256(sizeof(int) * 4);
@@ -514,9 +524,7 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
   g.N = N;
   g.periodic = grid->periodic ? 1 : 0;
   g.thermal = phys->thermal ? 1 : 0;
-  g.ty = 8;
-  g.ntx = lks::tiles_along(g.nx, lks::TX);
-  g.nty = lks::tiles_along(g.ny, g.ty);
+  set_tile_rows(g, 8);
   g.A = 4.5 * (1.0 / 6.0 - phys->nu);
   const double Kf = phys->thermal ? phys->nu / phys->Pr : 0.0;
   g.Bf = 3.0 * (1.0 / 6.0 - Kf);
@@ -568,7 +576,7 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
     for (int f = 0; f < 4; ++f) c->S[s][f] = take(N * r);
   for (int s = 0; s < 2; ++s)
     for (int f = 0; f < 4; ++f) c->P[s][f] = take(N * r);
-  c->acc = reinterpret_cast<double*>(take(sizeof(double) * n_tiles(c->geo)));
+  c->acc = reinterpret_cast<double*>(take(sizeof(double) * max_tiles(c->geo)));
   c->d_ops = reinterpret_cast<lks::RingOp*>(take(4 * sizeof(lks::RingOp)));
   c->scal = reinterpret_cast<double*>(take(sizeof(double) * 8));
   c->flag = reinterpret_cast<int*>(take(sizeof(int) * 4));
@@ -737,6 +745,69 @@ lks_status lks_write_field(lks_ctx* c, int which, const double* dev_in) {
   if (st != LKS_OK) return fail(c, st, "field not writable");
   if (which <= LKS_FIELD_T) c->have_forward = true;
   else c->have_adjoint = true;
+  return check_launch(c);
+}
+
+lks_status lks_set_tile_rows(lks_ctx* c, int tile_rows) {
+  if (!c) return LKS_E_INVALID;
+  for (int ty : TILE_ROWS)
+    if (ty == tile_rows) {
+      set_tile_rows(c->geo, ty);
+      c->have_forward = false;
+      c->have_adjoint = false;
+      return LKS_OK;
+    }
+  return fail(c, LKS_E_INVALID, "tile height must be 4 or 8");
+}
+
+lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* tile_rows) {
+  if (!c || !gamma_dev || steps < 1) return LKS_E_INVALID;
+  if (!c->bound) return fail(c, LKS_E_STATE, "no workspace bound");
+  lks_status st = LKS_OK;
+  hipEvent_t e[3];
+  for (auto& ev : e)
+    if (!hip_ok(c, hipEventCreate(&ev), "event", &st)) return st;
+  float best = 0.0f;
+  int best_ty = c->geo.ty;
+  const int mode = c->mode;
+  c->mode = LKS_STEADY;  // time plain steps on the ping-pong buffers
+  for (int ty : TILE_ROWS) {
+    set_tile_rows(c->geo, ty);
+    float t = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {  // the first repetition warms up
+      hipEventRecord(e[0], c->stream);
+      if (c->rsz == 8) {
+        Run<double> r(c);
+        r.forward(gamma_dev, steps);
+        hipEventRecord(e[1], c->stream);
+        r.adjoint_steady(1.0, steps, nullptr, true);
+      } else {
+        Run<float> r(c);
+        r.forward(gamma_dev, steps);
+        hipEventRecord(e[1], c->stream);
+        r.adjoint_steady(1.0, steps, nullptr, true);
+      }
+      hipEventRecord(e[2], c->stream);
+      if (!hip_ok(c, hipEventSynchronize(e[2]), "autotune sync", &st)) break;
+      float a = 0.0f, b = 0.0f;
+      hipEventElapsedTime(&a, e[0], e[1]);
+      hipEventElapsedTime(&b, e[1], e[2]);
+      t = a + b;
+    }
+    if (st != LKS_OK) break;
+    if (best == 0.0f || t < best) {
+      best = t;
+      best_ty = ty;
+    }
+  }
+  c->mode = mode;
+  for (auto& ev : e) hipEventDestroy(ev);
+  set_tile_rows(c->geo, best_ty);
+  c->have_forward = false;
+  c->have_adjoint = false;
+  c->last_level = 0;
+  if (tile_rows) *tile_rows = best_ty;
+  if (st != LKS_OK) return st;
   return check_launch(c);
 }
 
@@ -1089,6 +1160,66 @@ lks_status lks_batch_run(lks_batch* b, const double* const* gamma_dev, int n_fwd
   b->last_nf = n_fwd;
   b->last_na = n_adj;
   b->have_run = true;
+  return LKS_OK;
+}
+
+static lks_status batch_set_tile_rows(lks_batch* b, int ty) {
+  b->total_tiles = 0;
+  for (int d = 0; d < b->n; ++d) {
+    set_tile_rows(b->ctx[d]->geo, ty);
+    b->tile0[d] = b->total_tiles;
+    b->total_tiles += n_tiles(b->ctx[d]->geo);
+  }
+  b->ty = ty;
+  if (b->exec) {
+    hipGraphExecDestroy(b->exec);
+    hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+  }
+  lks_status st = LKS_OK;
+  if (b->bound &&
+      !hip_ok(nullptr, hipMemcpyAsync(b->d_tile0, b->tile0.data(), sizeof(int) * b->n,
+                                      hipMemcpyHostToDevice, b->user), "upload tiles", &st))
+    return bfail(b, st, g_create_error);
+  return LKS_OK;
+}
+
+lks_status lks_batch_autotune(lks_batch* b, const double* const* gamma_dev, int steps,
+                              double* const* scratch_dev, int* tile_rows) {
+  if (!b || !gamma_dev || !scratch_dev || steps < 1) return LKS_E_INVALID;
+  if (!b->bound) return bfail(b, LKS_E_STATE, "no workspace bound");
+  std::vector<double> J(b->n);
+  float best = 0.0f;
+  int best_ty = b->ty;
+  lks_status st = LKS_OK;
+  hipEvent_t e0, e1;
+  if (!hip_ok(nullptr, hipEventCreate(&e0), "event", &st) ||
+      !hip_ok(nullptr, hipEventCreate(&e1), "event", &st))
+    return bfail(b, st, g_create_error);
+  for (int ty : TILE_ROWS) {
+    if ((st = batch_set_tile_rows(b, ty)) != LKS_OK) break;
+    float t = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      hipEventRecord(e0, b->user);
+      st = lks_batch_run(b, gamma_dev, steps, steps, 1.0, scratch_dev, J.data(), 0);
+      hipEventRecord(e1, b->user);
+      if (st != LKS_OK) break;
+      hipEventSynchronize(e1);
+      hipEventElapsedTime(&t, e0, e1);
+    }
+    if (st != LKS_OK) break;
+    if (best == 0.0f || t < best) {
+      best = t;
+      best_ty = ty;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != LKS_OK) return st;
+  if ((st = batch_set_tile_rows(b, best_ty)) != LKS_OK) return st;
+  if (tile_rows) *tile_rows = best_ty;
+  b->have_run = false;
   return LKS_OK;
 }
 

@@ -20,6 +20,15 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
 
+# PyTorch ships its own HIP runtime under the same soname as the system one
+# (libamdhip64.so.7). Loading torch first makes the library bind to the
+# runtime torch already uses, so device memory and streams are shared by one
+# runtime in the process whatever the import order of the caller.
+try:
+    import torch  # noqa: F401
+except ImportError:  # CPU-only use: validation and planning need no runtime
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # status codes
@@ -42,7 +51,8 @@ EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forwa
             "lks_read_field", "lks_write_field", "lks_memory_report", "lks_strerror",
             "lks_last_error", "lks_destroy", "lks_batch_create", "lks_batch_workspace_size",
             "lks_batch_bind_workspace", "lks_batch_run", "lks_batch_read_field",
-            "lks_batch_last_error", "lks_batch_destroy")
+            "lks_batch_last_error", "lks_batch_destroy", "lks_autotune",
+            "lks_batch_autotune", "lks_set_tile_rows")
 
 
 class Grid(ctypes.Structure):
@@ -115,6 +125,13 @@ _lib.lks_batch_read_field.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp]
 _lib.lks_batch_read_field.restype = _st
 _lib.lks_batch_last_error.argtypes = [_vp]
 _lib.lks_batch_last_error.restype = ctypes.c_char_p
+_lib.lks_autotune.argtypes = [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+_lib.lks_autotune.restype = _st
+_lib.lks_batch_autotune.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
+                                    ctypes.POINTER(ctypes.c_int)]
+_lib.lks_batch_autotune.restype = _st
+_lib.lks_set_tile_rows.argtypes = [_vp, ctypes.c_int]
+_lib.lks_set_tile_rows.restype = _st
 _lib.lks_batch_destroy.argtypes = [_vp]
 _lib.lks_batch_destroy.restype = None
 
@@ -221,6 +238,16 @@ class LKS:
     def write(self, name, t):
         _check(_lib.lks_write_field(self.ctx, FIELDS[name], _vp(t.data_ptr())), self.ctx)
 
+    def autotune(self, gamma, steps=200):
+        """Pick the fastest tile height; returns it."""
+        ty = ctypes.c_int()
+        _check(_lib.lks_autotune(self.ctx, _vp(gamma.data_ptr()), int(steps), ctypes.byref(ty)),
+               self.ctx)
+        return ty.value
+
+    def set_tile_rows(self, ty):
+        _check(_lib.lks_set_tile_rows(self.ctx, int(ty)), self.ctx)
+
     def memory_report(self):
         a, b, k = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int()
         _check(_lib.lks_memory_report(self.ctx, ctypes.byref(a), ctypes.byref(b),
@@ -290,6 +317,13 @@ class Batch:
         _bcheck(_lib.lks_batch_run(self.b, g, int(n_fwd), int(n_adj), float(seed), o, J,
                                    int(bool(graph))), self.b)
         return list(J)
+
+    def autotune(self, gammas, scratch, steps=100):
+        g = (_vp * self.n)(*[t.data_ptr() for t in gammas])
+        o = (_vp * self.n)(*[t.data_ptr() for t in scratch])
+        ty = ctypes.c_int()
+        _bcheck(_lib.lks_batch_autotune(self.b, g, int(steps), o, ctypes.byref(ty)), self.b)
+        return ty.value
 
     def read(self, design, name, out=None):
         import torch

@@ -276,3 +276,42 @@ def test_poiseuille_fixed_point_on_gpu():
     assert np.abs(ctx.read("drho").cpu().numpy() - drho.ravel()).max() < 1e-15
     Jp = (ny - 2) * 8 * nu * U * (nx - 1) / H ** 2
     assert abs(ctx.objective() - Jp) / Jp < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_results_do_not_depend_on_tile_height(prec):
+    say(f"[gpu] tile height invariance {prec}")
+    wl = W.unsteady_thermal_channel(131, 37, Re=60.0, sigma=3.0, seed=2, n_steps=60, period=30.0)
+    out = []
+    for ty in (4, 8):
+        ctx = lks.LKS(wl, precision=prec, device=DEV)
+        ctx.set_tile_rows(ty)
+        g = T(wl.gamma)
+        d = torch.empty_like(g)
+        ctx.forward(g, wl.n_fwd)
+        J = ctx.objective()
+        ctx.backward(1.0, d)
+        torch.cuda.synchronize()
+        out.append((J, d.cpu().numpy()))
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_autotune_picks_a_supported_height_and_keeps_results():
+    say("[gpu] autotune 512x512")
+    wl = W.steady_channel_grf(512, 512, Re=100.0, sigma=8.0, seed=0, n_fwd=100, n_adj=100)
+    ctx = lks.LKS(wl, precision="fp32", device=DEV)
+    g = T(wl.gamma)
+    ty = ctx.autotune(g, 50)
+    assert ty in (4, 8)
+    d = torch.empty_like(g)
+    ctx.forward(g, wl.n_fwd)
+    J = ctx.objective()
+    ctx.backward(1.0, d, wl.n_adj)
+    ref = lks.LKS(wl, precision="fp32", device=DEV)
+    d2 = torch.empty_like(g)
+    ref.forward(g, wl.n_fwd)
+    J2 = ref.objective()
+    ref.backward(1.0, d2, wl.n_adj)
+    torch.cuda.synchronize()
+    assert J == J2 and torch.equal(d, d2)
