@@ -485,7 +485,7 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
   R kappa = R(0), gu[3] = {R(0), R(0), R(0)};
   if constexpr (TH) {
     if (((m >> 2) & 3) == THERM_DIRICHLET) {
-#pragma unroll
+#pragma nounroll
       for (int c = 0; c < 3; ++c) {
         R t = R(0);
 #pragma unroll
@@ -501,7 +501,7 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
       for (int q = 0; q < 9; ++q) num += (R(op.ga[q]) - un * R(op.ge[q])) * gq[q];
       const R den = R(op.A0) - R(2) * un * R(op.A1) + un * un * R(op.A2);
       kappa = -num / den;
-#pragma unroll
+#pragma nounroll
       for (int c = 0; c < 3; ++c) {
         R t = R(0);
 #pragma unroll
@@ -516,7 +516,7 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
   const int v = (m & 3) == FLOW_VELOCITY ? 0 : 1;
   const R kT = TH ? kappa * sTn[p2] : R(0);
   R fu[3];
-#pragma unroll
+#pragma nounroll
   for (int c = 0; c < 3; ++c) {
     R t = R(op.Ls[v][c]) * s + R(op.Lk[v][c]) * kT;
 #pragma unroll

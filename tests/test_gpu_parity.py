@@ -297,6 +297,39 @@ def test_results_do_not_depend_on_tile_height(prec):
     assert np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["channel_70x37", "thermal_129x14", "periodic_thermal_40x21"])
+def test_steps_do_not_depend_on_the_tile_height(case, prec):
+    """Forward and adjoint steps from a random state are the same bit for bit
+    with 64 x 4 and 64 x 8 tiles (different tile seams, halo loads and
+    partial tiles)."""
+    say(f"[gpu] tile-height invariance of steps {case} {prec}")
+    wl = CASES[case]()
+    rng = np.random.default_rng(11)
+    s = _random_state(wl, rng)
+    adj = [rng.standard_normal(wl.nx * wl.ny) for _ in range(4)]
+    fwd = ["drho", "ux", "uy"] + (["T"] if wl.thermal else [])
+    adn = ["adj_rho", "adj_vx", "adj_vy"] + (["adj_theta"] if wl.thermal else [])
+    out = []
+    for ty in (4, 8):
+        ctx = lks.LKS(wl, precision=prec, device=DEV)
+        ctx.set_tile_rows(ty)
+        g = T(wl.gamma)
+        ctx.forward(g, 0)
+        for n in fwd:
+            ctx.write(n, T(getattr(s, n)))
+        ctx.advance(g, 5)
+        for n, v in zip(adn, adj):
+            ctx.write(n, T(v))
+        dJ = torch.zeros(wl.nx * wl.ny, dtype=torch.float64, device=DEV)
+        ctx.adjoint_advance(0.5, 4, dJ)
+        torch.cuda.synchronize()
+        out.append([ctx.read(n).cpu().numpy() for n in fwd + adn] + [dJ.cpu().numpy()])
+    for o in out[1:]:
+        for a, b in zip(out[0], o):
+            assert np.array_equal(a, b)
+
+
 def test_autotune_picks_a_supported_height_and_keeps_results():
     say("[gpu] autotune 512x512")
     wl = W.steady_channel_grf(512, 512, Re=100.0, sigma=8.0, seed=0, n_fwd=100, n_adj=100)
