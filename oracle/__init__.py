@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark use this package to check and time the GPU library. The
 product path never imports it. It shares no code with the GPU library; the
-arithmetic lives in ``lks_oracle.c`` (plain C, OpenMP over rows), and this
+arithmetic lives in ``lks_oracle.c`` (D2Q9) and ``lks_oracle3d.c`` (D3Q19, driven
+from ``oracle.d3``), plain C with OpenMP over nodes, and this
 module only marshals arrays and runs the time loops the paper describes
 (Sec. 2.7, Steps 2-5):
 
@@ -27,6 +28,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lks_oracle.c")
+_SRC3 = os.path.join(_HERE, "lks_oracle3d.c")
 _LIB = os.path.join(_HERE, "liblks_oracle.so")
 
 FLOW_CORNER = 3
@@ -42,10 +44,11 @@ ADJ_NAMES = ("rho", "ux", "uy", "sxx", "sxy", "syy", "T", "qx", "qy")
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C99 + OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC3))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, _SRC, _SRC3, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

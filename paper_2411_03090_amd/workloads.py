@@ -248,3 +248,138 @@ def periodic_box(nx, ny, nu=0.1, thermal=False, Pr=6.0):
                     periodic=True, mask=mask, gamma=np.ones((ny, nx)),
                     ubar=np.zeros((2, ny, nx)), Tbar=np.zeros((ny, nx)),
                     ufac=np.ones(1))
+
+
+# --------------------------------------------------------------------------
+# three-dimensional (D3Q19) workloads
+# --------------------------------------------------------------------------
+# Arrays are (nz, ny, nx), x fastest; ubar is (3, nz, ny, nx). A node is a
+# boundary node when it sits at an end of a non-periodic axis; face nodes
+# (one coordinate at an end) carry flow class 1 or 2, edge and corner nodes
+# (two or three) flow class 3, "copy": they take density, temperature and
+# adjoint moments from the node reached by stepping inwards along y and z.
+FLOW_COPY = FLOW_CORNER
+TAG_SOLID = 1 << 7          # interior node that is not a design node
+
+
+@dataclass
+class Workload3(Workload):
+    nz: int = 1
+    periodic_axes: int = 0   # bit 0: x, bit 1: y, bit 2: z
+
+    @property
+    def n_nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def _ends3(nx, ny, nz, periodic_axes):
+    """Per node, the number of coordinates at an end of a non-periodic axis."""
+    c = np.zeros((nz, ny, nx), np.int32)
+    for ax, n in ((2, nx), (1, ny), (0, nz)):
+        a = {2: 0, 1: 1, 0: 2}[ax]
+        if (periodic_axes >> a) & 1:
+            continue
+        sl = [slice(None)] * 3
+        for e in (0, n - 1):
+            sl[ax] = e
+            c[tuple(sl)] += 1
+    return c
+
+
+def duct_mask3(nx, ny, nz, probe_col=None):
+    """Duct along x: inlet face x=0 (prescribed velocity and temperature),
+    outlet face x=nx-1 (pressure, adiabatic), walls y=0, y=ny-1, z=0, z=nz-1
+    (no slip, adiabatic); edges and corners copy."""
+    if min(nx, ny, nz) < 4:
+        raise ValueError("duct needs nx, ny, nz >= 4")
+    m = np.zeros((nz, ny, nx), np.uint8)
+    m[1:-1, 1:-1, 0] = FLOW_VELOCITY | TAG_J_INLET | THERM_DIRICHLET
+    m[1:-1, 1:-1, -1] = FLOW_PRESSURE | TAG_J_OUTLET | THERM_FLUX
+    for sl in ((slice(1, -1), 0, slice(1, -1)), (slice(1, -1), -1, slice(1, -1)),
+               (0, slice(1, -1), slice(1, -1)), (-1, slice(1, -1), slice(1, -1))):
+        m[sl] = FLOW_VELOCITY | THERM_FLUX
+    m[_ends3(nx, ny, nz, 0) >= 2] = FLOW_COPY
+    if probe_col is not None:
+        m[1:-1, 1:-1, probe_col] |= TAG_PROBE
+    return m
+
+
+def duct_inflow3(ny, nz, u_max):
+    """u_x(j, l) = 16 u_max j (Hy-j) l (Hz-l) / (Hy^2 Hz^2)."""
+    Hy, Hz = ny - 1, nz - 1
+    j = np.arange(ny, dtype=np.float64)[None, :]
+    l = np.arange(nz, dtype=np.float64)[:, None]
+    return 16.0 * u_max * j * (Hy - j) * l * (Hz - l) / (Hy * Hy * Hz * Hz)
+
+
+def gamma_grf3(nx, ny, nz, sigma, seed):
+    """gamma = clip(0.5 + 0.5 z, 0, 1) of a smoothed 3D Gaussian field; the
+    boundary nodes are fluid (gamma = 1)."""
+    z = gaussian_random_field((nz, ny, nx), sigma, seed)
+    g = np.clip(0.5 + 0.5 * z, 0.0, 1.0)
+    g[_ends3(nx, ny, nz, 0) > 0] = 1.0
+    return g
+
+
+def heated_block_duct(nx=256, ny=128, nz=128, Re=100.0, Pr=0.71, sigma=6.0, seed=0,
+                      n_steps=5000, nu=0.1, block=((0.25, 0.375), (0.0, 0.25),
+                                                    (0.375, 0.625))):
+    """Unsteady forced convection in a duct past a heated solid block (the
+    256x128x128, Re=100, Pr=0.71, 5000-step case at its defaults): inflow at
+    T=0 with the duct profile, started from rest; the block, given as
+    fractions of the domain along x, y, z (x in [64,96), y in [0,32),
+    z in [48,80) at full size, resting on the y=0 wall), is a non-design solid
+    (gamma = 0) held at T = 1; objective is the time-averaged enthalpy flux
+    through the plane x = nx-2."""
+    H = ny - 1
+    u_max = Re * nu / H
+    if u_max > 0.1:
+        u_max = 0.1
+        nu = u_max * H / Re
+    m = duct_mask3(nx, ny, nz, probe_col=nx - 2)
+    ubar = np.zeros((3, nz, ny, nx))
+    ubar[0, 1:-1, 1:-1, 0] = duct_inflow3(ny, nz, u_max)[1:-1, 1:-1]
+    Tbar = np.zeros((nz, ny, nx))
+    g = gamma_grf3(nx, ny, nz, sigma, seed)
+    (x0, x1), (y0, y1), (z0, z1) = [(int(round(a * n)), int(round(b * n)))
+                                    for (a, b), n in zip(block, (nx, ny, nz))]
+    blk = np.zeros((nz, ny, nx), bool)
+    blk[z0:z1, y0:y1, x0:x1] = True
+    blk &= _ends3(nx, ny, nz, 0) < 2            # edges keep their copy rule
+    m[blk] = (m[blk] & ~np.uint8(12)) | THERM_DIRICHLET
+    inner = blk & (_ends3(nx, ny, nz, 0) == 0)
+    m[inner] |= TAG_SOLID
+    g[inner] = 0.0
+    Tbar[blk] = 1.0
+    return Workload3(name=f"heated_block_duct_{nx}x{ny}x{nz}_Re{Re:g}", nx=nx, ny=ny, nz=nz,
+                     nu=nu, u_max=u_max, alpha_max=1e3 / Re, q_alpha=0.1, thermal=True,
+                     Pr=Pr, Ks_over_Kf=1.0, q_K=0.1, objective=OBJ_HEAT,
+                     mode=MODE_UNSTEADY, n_fwd=n_steps, n_adj=n_steps, mask=m, gamma=g,
+                     ubar=ubar, Tbar=Tbar, ufac=np.ones(n_steps + 1), periodic_axes=0)
+
+
+def extrude_z(wl: Workload, nz: int) -> Workload3:
+    """The two-dimensional workload repeated along a periodic z axis (z
+    velocity 0); a z-invariant D3Q19 run of it reproduces the D2Q9 run."""
+    rep = lambda a: np.repeat(np.asarray(a)[None], nz, axis=0)
+    ubar = np.zeros((3, nz, wl.ny, wl.nx))
+    ubar[0] = rep(wl.ubar[0])
+    ubar[1] = rep(wl.ubar[1])
+    axes = 7 if wl.periodic else 4
+    return Workload3(name=f"{wl.name}_z{nz}", nx=wl.nx, ny=wl.ny, nz=nz, nu=wl.nu,
+                     u_max=wl.u_max, alpha_max=wl.alpha_max, q_alpha=wl.q_alpha,
+                     thermal=wl.thermal, Pr=wl.Pr, Ks_over_Kf=wl.Ks_over_Kf, q_K=wl.q_K,
+                     rho_out=wl.rho_out, objective=wl.objective, mode=wl.mode,
+                     n_fwd=wl.n_fwd, n_adj=wl.n_adj, periodic=wl.periodic,
+                     mask=rep(wl.mask).astype(np.uint8), gamma=rep(wl.gamma), ubar=ubar,
+                     Tbar=rep(wl.Tbar), ufac=np.array(wl.ufac, dtype=np.float64),
+                     periodic_axes=axes)
+
+
+def periodic_box3(nx, ny, nz, nu=0.1, thermal=False, Pr=6.0):
+    """Fully periodic 3D box (no boundary nodes)."""
+    return Workload3(name=f"periodic_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, nu=nu, u_max=0.0,
+                     alpha_max=0.0, q_alpha=0.1, thermal=thermal, Pr=Pr, periodic=True,
+                     mask=np.zeros((nz, ny, nx), np.uint8), gamma=np.ones((nz, ny, nx)),
+                     ubar=np.zeros((3, nz, ny, nx)), Tbar=np.zeros((nz, ny, nx)),
+                     ufac=np.ones(1), periodic_axes=7)
