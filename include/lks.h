@@ -13,9 +13,14 @@
  * Conventions shared by every call
  *   - Lattice units dx = dt = 1, relaxation times tau_f = tau_g = 1 (Sec. 2.4).
  *   - D2Q9 lattice; fields are node arrays of nx*ny values, x fastest:
- *     node (i, j) is element j*nx + i.
- *   - The outer ring of nodes is the boundary; its class comes from the
- *     node-class byte below, its outward normal from its position.
+ *     node (i, j) is element j*nx + i. The outer ring of nodes is the
+ *     boundary; its class comes from the node-class byte below, its outward
+ *     normal from its position.
+ *   - D3Q19 extension (the same equations with the indices running over
+ *     x, y, z, Sec. 2.1): fields of nx*ny*nz values, node (i, j, l) is
+ *     element (l*ny + j)*nx + i. A node at an end of a non-periodic axis is
+ *     a boundary node: a face node when one coordinate is at an end (outward
+ *     normal along that axis), an edge or corner node when two or three are.
  *   - Device pointers are plain HIP device addresses (for example the
  *     data_ptr() of a torch tensor on the same device); host pointers are
  *     ordinary memory. The library never frees caller memory.
@@ -58,12 +63,19 @@ enum { LKS_STEADY = 0, LKS_UNSTEADY = 1 };
 
 /* Node-class byte (one per node):
  *   bits 0-1 flow class: interior (design) node, prescribed velocity
- *            (inlet or wall), prescribed pressure (outlet), corner;
+ *            (inlet or wall), prescribed pressure (outlet), corner (D2Q9) /
+ *            edge or corner (D3Q19): u = 0, density, temperature and adjoint
+ *            moments copied from the neighbour one step inwards along y
+ *            (and z);
  *   bits 2-3 thermal class: none, prescribed temperature, prescribed zero
  *            heat flux (adiabatic);
  *   bit 4/5  member of the inlet/outlet set of the pressure drop
  *            (eq:objective_pipebend);
- *   bit 6    member of the probe set of the heat-transfer objective.
+ *   bit 6    member of the probe set of the heat-transfer objective;
+ *   bit 7    D3Q19 only: interior node that is not a design node (its
+ *            sensitivity is zero), e.g. a solid held at a prescribed
+ *            temperature (interior node with thermal class "prescribed
+ *            temperature": T = T_bar, adjoint T~ = q~ = 0).
  * Sec. 2.4 names the boundary conditions (velocity at inlets and walls,
  * pressure and tangential velocity at outlets, temperature or heat flux). */
 #define LKS_FLOW_INTERIOR 0
@@ -75,6 +87,7 @@ enum { LKS_STEADY = 0, LKS_UNSTEADY = 1 };
 #define LKS_TAG_J_INLET (1 << 4)
 #define LKS_TAG_J_OUTLET (1 << 5)
 #define LKS_TAG_PROBE (1 << 6)
+#define LKS_TAG_SOLID (1 << 7)
 
 /* Fields for lks_read_field / lks_write_field. Forward state: density
  * deviation rho - 1, velocity, temperature, at the current level. Adjoint
@@ -88,14 +101,17 @@ enum {
   LKS_FIELD_ADJ_RHO = 4,
   LKS_FIELD_ADJ_VX = 5,
   LKS_FIELD_ADJ_VY = 6,
-  LKS_FIELD_ADJ_THETA = 7
+  LKS_FIELD_ADJ_THETA = 7,
+  LKS_FIELD_UZ = 8,     /* D3Q19 */
+  LKS_FIELD_ADJ_VZ = 9  /* D3Q19 */
 };
 
 typedef struct {
   int nx, ny, nz;  /* nodes per axis; nz = 1 for D2Q9 */
-  int lattice;     /* LKS_D2Q9 (LKS_D3Q19 returns LKS_E_UNSUPPORTED) */
+  int lattice;     /* LKS_D2Q9 or LKS_D3Q19 */
   int precision;   /* LKS_FP64 or LKS_FP32DEV */
-  int periodic;    /* 1: periodic box, every node interior */
+  int periodic;    /* D2Q9: 1 = periodic box, every node interior.
+                      D3Q19: mask of periodic axes (bit 0 x, 1 y, 2 z) */
 } lks_grid;
 
 typedef struct {
@@ -109,10 +125,12 @@ typedef struct {
 } lks_phys;
 
 typedef struct {
-  const uint8_t *node_class; /* host, nx*ny node classes (copied) */
-  const double *u_bar;       /* host, 2*nx*ny: x block then y block; the
+  const uint8_t *node_class; /* host, one class per node (copied) */
+  const double *u_bar;       /* host, 2 (D3Q19: 3) blocks of one value per
+                                node: x block, y block (, z block); the
                                 velocity prescribed at velocity nodes (copied) */
-  const double *T_bar;       /* host, nx*ny: temperature at prescribed-T nodes
+  const double *T_bar;       /* host, one value per node: temperature at
+                                prescribed-T nodes
                                 (copied); may be NULL if not thermal */
   const double *u_factor;    /* host, n_factor: u_bar is scaled by
                                 u_factor[min(n, n_factor-1)] at level n;
@@ -188,11 +206,12 @@ lks_status lks_write_field(lks_ctx *ctx, int which, const double *dev_in);
  * design gamma_dev for each tile height the kernels provide (64 x 4 and
  * 64 x 8 nodes) on this context's stream, keeps the fastest and reports it in
  * *tile_rows. Synchronises; the forward and adjoint states are discarded
- * (run lks_forward afterwards). */
+ * (run lks_forward afterwards). D2Q9 only (LKS_E_UNSUPPORTED for D3Q19,
+ * whose node-parallel kernels have no tile shape). */
 lks_status lks_autotune(lks_ctx *ctx, const double *gamma_dev, int steps, int *tile_rows);
 
 /* Set the tile height (4 or 8 rows of 64 nodes) explicitly; results do not
- * depend on it. Discards the forward and adjoint states. */
+ * depend on it. Discards the forward and adjoint states. D2Q9 only. */
 lks_status lks_set_tile_rows(lks_ctx *ctx, int tile_rows);
 
 /* Memory plan: bytes of checkpoint + replay storage, bytes of the rest of
@@ -210,7 +229,7 @@ lks_status lks_memory_report(const lks_ctx *ctx, size_t *ckpt_bytes, size_t *sta
  * replayed (use_graph = 1) or launched eagerly (use_graph = 0). */
 typedef struct lks_batch lks_batch;
 
-/* Validates every design as lks_create does (steady mode only). Makes no HIP
+/* Validates every design as lks_create does (steady D2Q9 only). Makes no HIP
  * call. grids/phys/bcs are arrays of n descriptors. */
 lks_status lks_batch_create(int n, const lks_grid *grids, const lks_phys *phys,
                             const lks_bc *bcs, void *hip_stream, lks_batch **out);

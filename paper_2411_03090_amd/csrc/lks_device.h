@@ -131,6 +131,93 @@ struct BatchAdj {
 // host: the four ring operators for a given A and fluid B
 void build_ring_ops(double A, double Bf, RingOp ops[4]);
 
+// ---------------------------------------------------------------------------
+// D3Q19 (three-dimensional extension)
+// ---------------------------------------------------------------------------
+// Nodes (i, j, l), k = (l ny + j) nx + i. An axis is periodic when its bit
+// of `periodic` is set; a node at an end of a non-periodic axis is a
+// boundary node: a face node (one coordinate at an end) or an edge/corner
+// node (two or three), which copies density, temperature and adjoint
+// moments from (i, j', l'), the node one step inwards along y and z.
+struct Geo3 {
+  int nx, ny, nz, N;
+  int periodic;     // bit 0: x, bit 1: y, bit 2: z
+  int thermal;
+  double A;         // eq:A
+  double Bf;        // B of the fluid, used on boundary nodes
+  double drho_out;  // prescribed outlet density minus 1
+};
+
+// Least-squares completion operators of a face orientation o = 2 axis +
+// (n = +e_axis), the D3Q19 counterpart of RingOp with five unknowns.
+struct FaceOp3 {
+  double Lf[2][5][19];
+  double Ls[2][5];
+  double Lk[2][5];
+  double Ld[5][19];
+  double Lg0[5][19];
+  double ga[19], ge[19];
+  double A0, A1, A2;
+  double hc[5], h1[5];
+  double uw[5], uc[5][3];
+  int unk[5];
+  int pad[3];
+};
+void build_face_ops3(double A, double Bf, FaceOp3 ops[6]);
+
+// fields of the forward state: drho, ux, uy, uz, T
+template <typename R>
+struct Fwd3Args {
+  const uint8_t* mask;
+  const R* inv1pa;
+  const R* B;
+  const R* ub[3];      // prescribed velocity
+  const R* Tb;         // prescribed temperature
+  const double* ufac;  // inflow factor per level
+  int level_out;
+  const R* s0[5];      // level n
+  R* s1[5];            // level n+1
+  R* e;                // equilibrium coefficients: a0, P (6), G (3); 10 N
+  double* acc;         // per-block objective accumulator, or nullptr
+  int objective;
+};
+
+// fields of the adjoint coefficients: rho~, Vx, Vy, Vz, Theta
+template <typename R>
+struct Adj3Args {
+  const uint8_t* mask;
+  const R* inv1pa;
+  const R* B;
+  const R* dA3;
+  const R* dB;
+  const R* u[3];       // state at the destination level n
+  const R* T;
+  const R* p0[5];      // level n+1
+  R* p1[5];            // level n
+  R* m;                // moments: rho~, u~ (3), s~ (6), T~, q~ (3); 14 N
+  const FaceOp3* ops;  // -x, +x, -y, +y, -z, +z
+  double* sens;
+  int sens_mode;       // 0 none, 1 accumulate, 2 overwrite
+  double seed_dp;
+  double seed_heat;
+};
+
+int blocks3(int N);  // blocks of a node-parallel 3D launch (multiple of 8)
+template <typename R>
+void launch_coef3(const Geo3& g, const uint8_t* mask, const double* gamma, double alpha_max,
+                  double q_alpha, double Kf, double Ks, double qK, R* inv1pa, R* B, R* dA3,
+                  R* dB, hipStream_t s);
+template <typename R>
+void launch_init3(const Geo3& g, const uint8_t* mask, const R* const ub[3], const R* Tb,
+                  double ufac0, R* const st[5], hipStream_t s);
+template <typename R>
+void launch_lks3_step(const Geo3& g, const Fwd3Args<R>& a, hipStream_t s);
+template <typename R>
+void launch_alks3_step(const Geo3& g, const Adj3Args<R>& a, hipStream_t s);
+template <typename R>
+void launch_tag_sum3(const Geo3& g, const uint8_t* mask, const R* d, const R* ux, const R* T,
+                     int objective, double* out, hipStream_t s);
+
 // kernel launchers (lks_kernels.hip)
 template <typename R>
 void launch_coef(const Geo& g, const double* gamma, double alpha_max, double q_alpha,

@@ -41,7 +41,10 @@ struct lks_ctx {
   std::vector<uint8_t> mask;
   std::vector<double> ubar, Tbar, ufac;
   int n_in = 0, n_out = 0;
-  Geo geo{};
+  int dim = 2;         // 2: D2Q9, 3: D3Q19
+  int N = 0;           // nodes
+  Geo geo{};           // D2Q9 geometry
+  lks::Geo3 geo3{};    // D3Q19 geometry
   hipStream_t stream = nullptr;
   size_t budget = 0;
   int rsz = 8;
@@ -52,15 +55,20 @@ struct lks_ctx {
   bool bound = false;
   // carved device pointers (element type depends on precision)
   uint8_t* d_mask = nullptr;
-  void *ubx = nullptr, *uby = nullptr, *Tb = nullptr;
+  void *ubx = nullptr, *uby = nullptr, *ubz = nullptr, *Tb = nullptr;
   double* d_ufac = nullptr;
   void *inv1pa = nullptr, *B = nullptr, *dA3 = nullptr, *dB = nullptr;
-  void* S[2][4] = {};    // forward ping-pong: drho, ux, uy, T
-  void* P[2][4] = {};    // adjoint ping-pong: rho~, Vx, Vy, Theta
+  // forward ping-pong: drho, ux, uy, T (D2Q9) or drho, ux, uy, uz, T (D3Q19)
+  void* S[2][5] = {};
+  // adjoint ping-pong: rho~, Vx, Vy, Theta or rho~, Vx, Vy, Vz, Theta
+  void* P[2][5] = {};
   void* C = nullptr;     // checkpoints
   void* Seg = nullptr;   // replay segment
   lks::RingOp* d_ops = nullptr;  // adjoint boundary operators (4 orientations)
   lks::RingOp ops[4];
+  lks::FaceOp3* d_ops3 = nullptr;  // D3Q19 face operators (6 orientations)
+  lks::FaceOp3 ops3[6];
+  void* E3 = nullptr;    // D3Q19 per-step scratch: equilibrium coefficients / moments
   double* acc = nullptr; // per-tile objective accumulators
   double* scal = nullptr;
   int* flag = nullptr;
@@ -99,28 +107,47 @@ void set_tile_rows(Geo& g, int ty) {
   g.nty = lks::tiles_along(g.ny, ty);
 }
 
-// fields stored per checkpoint / per replay slot
-int ckpt_fields(const lks_ctx* c) { return c->phys.thermal ? 4 : 3; }
-int slot_fields(const lks_ctx* c) { return c->phys.thermal ? 3 : 2; }
+// state fields per level (the last one is T) and the stored ones
+int nfields(const lks_ctx* c) { return c->dim == 3 ? 5 : 4; }
+int tfield(const lks_ctx* c) { return nfields(c) - 1; }
+// fields stored per checkpoint / per replay slot (the replay keeps drho in
+// the ping-pong buffers)
+int ckpt_fields(const lks_ctx* c) { return c->phys.thermal ? nfields(c) : nfields(c) - 1; }
+int slot_fields(const lks_ctx* c) { return ckpt_fields(c) - 1; }
+// per-block objective accumulators of an unsteady forward sweep
+int acc_count(const lks_ctx* c) {
+  return c->dim == 3 ? lks::blocks3(c->N) : n_tiles(c->geo);
+}
+int acc_capacity(const lks_ctx* c) {
+  return c->dim == 3 ? lks::blocks3(c->N) : max_tiles(c->geo);
+}
+// D3Q19 scratch fields: 10 coefficients / moments, 14 with temperature
+int scratch3_fields(const lks_ctx* c) { return c->phys.thermal ? 14 : 10; }
 
 size_t traj_bytes(const lks_ctx* c, int K) {
-  const size_t N = size_t(c->geo.N), r = size_t(c->rsz);
+  const size_t N = size_t(c->N), r = size_t(c->rsz);
   const int n = c->n_steps;
   size_t n_ckpt = size_t(n / K) + 1;
   return n_ckpt * ckpt_fields(c) * N * r + size_t(K - 1) * slot_fields(c) * N * r;
 }
 
 size_t base_bytes(const lks_ctx* c) {
-  const size_t N = size_t(c->geo.N), r = size_t(c->rsz);
+  const size_t N = size_t(c->N), r = size_t(c->rsz);
+  const int nf = nfields(c);
   size_t b = 0;
-  b += align256(N);                        // mask
-  b += 3 * align256(N * r);                // ubx, uby, Tb
+  b += align256(N);                          // mask
+  b += size_t(c->dim + 1) * align256(N * r);  // prescribed velocity, T
   b += align256(sizeof(double) * c->ufac.size());
-  b += 4 * align256(N * r);                // coefficients
-  b += 8 * align256(N * r);                // forward ping-pong
-  b += 8 * align256(N * r);                // adjoint ping-pong
-  b += align256(sizeof(double) * max_tiles(c->geo));
-  b += align256(4 * sizeof(lks::RingOp));  // ring operators
+  b += 4 * align256(N * r);                  // coefficients
+  b += 2 * nf * align256(N * r);             // forward ping-pong
+  b += 2 * nf * align256(N * r);             // adjoint ping-pong
+  b += align256(sizeof(double) * acc_capacity(c));
+  if (c->dim == 3) {
+    b += align256(6 * sizeof(lks::FaceOp3));  // face operators
+    b += align256(size_t(scratch3_fields(c)) * N * r);
+  } else {
+    b += align256(4 * sizeof(lks::RingOp));   // ring operators
+  }
   b += align256(sizeof(double) * 8);
   b += align256(sizeof(int) * 4);
   return b;
@@ -159,23 +186,16 @@ lks_status plan_memory(lks_ctx* c) {
   p.n_slots = best - 1;
   p.ls = (n / best) * best;
   p.ckpt_bytes = traj_bytes(c, best);
-  p.total = base + align256(size_t(p.n_ckpt) * ckpt_fields(c) * c->geo.N * c->rsz) +
-            align256(size_t(p.n_slots) * slot_fields(c) * c->geo.N * c->rsz);
+  p.total = base + align256(size_t(p.n_ckpt) * ckpt_fields(c) * c->N * c->rsz) +
+            align256(size_t(p.n_slots) * slot_fields(c) * c->N * c->rsz);
   c->plan = p;
   return LKS_OK;
 }
 
-lks_status validate(const lks_grid* gr, const lks_phys* ph, const lks_bc* bc) {
-  if (!gr || !ph || !bc) return fail(nullptr, LKS_E_INVALID, "null descriptor");
-  if (gr->lattice == LKS_D3Q19) return fail(nullptr, LKS_E_UNSUPPORTED, "D3Q19 is not built");
-  if (gr->lattice != LKS_D2Q9) return fail(nullptr, LKS_E_INVALID, "unknown lattice");
+// checks shared by both lattices
+lks_status validate_common(const lks_grid* gr, const lks_phys* ph, const lks_bc* bc) {
   if (gr->precision != LKS_FP64 && gr->precision != LKS_FP32DEV)
     return fail(nullptr, LKS_E_INVALID, "unknown precision");
-  if (gr->nz > 1) return fail(nullptr, LKS_E_INVALID, "nz must be 1 for D2Q9");
-  const int minn = gr->periodic ? 3 : 4;
-  if (gr->nx < minn || gr->ny < minn) return fail(nullptr, LKS_E_INVALID, "grid too small");
-  if ((long long)gr->nx * gr->ny > (1LL << 31) / 16)
-    return fail(nullptr, LKS_E_INVALID, "grid too large");
   if (!(ph->nu > 0.0 && ph->nu < 1.0 / 6.0))
     return fail(nullptr, LKS_E_INVALID, "nu must lie in (0, 1/6) (A > 0, eq:A)");
   if (!(ph->alpha_max >= 0.0) || !(ph->q_alpha > 0.0))
@@ -199,6 +219,29 @@ lks_status validate(const lks_grid* gr, const lks_phys* ph, const lks_bc* bc) {
     return fail(nullptr, LKS_E_INVALID, "unsteady needs n_steps >= 1");
   if (bc->u_factor && bc->n_factor < 1) return fail(nullptr, LKS_E_INVALID, "n_factor < 1");
   if (!(bc->rho_out > 0.0)) return fail(nullptr, LKS_E_INVALID, "rho_out must be > 0");
+  if (bc->u_factor)
+    for (int n = 0; n < bc->n_factor; ++n)
+      if (!std::isfinite(bc->u_factor[n])) return fail(nullptr, LKS_E_INVALID, "u_factor not finite");
+  return LKS_OK;
+}
+
+double factor_max(const lks_bc* bc) {
+  double fmax = 1.0;
+  if (bc->u_factor)
+    for (int n = 0; n < bc->n_factor; ++n) fmax = std::max(fmax, std::fabs(bc->u_factor[n]));
+  return fmax;
+}
+
+lks_status validate(const lks_grid* gr, const lks_phys* ph, const lks_bc* bc) {
+  if (!gr || !ph || !bc) return fail(nullptr, LKS_E_INVALID, "null descriptor");
+  if (gr->lattice != LKS_D2Q9) return fail(nullptr, LKS_E_INVALID, "unknown lattice");
+  if (gr->nz > 1) return fail(nullptr, LKS_E_INVALID, "nz must be 1 for D2Q9");
+  const int minn = gr->periodic ? 3 : 4;
+  if (gr->nx < minn || gr->ny < minn) return fail(nullptr, LKS_E_INVALID, "grid too small");
+  if ((long long)gr->nx * gr->ny > (1LL << 31) / 16)
+    return fail(nullptr, LKS_E_INVALID, "grid too large");
+  lks_status st = validate_common(gr, ph, bc);
+  if (st != LKS_OK) return st;
   const int nx = gr->nx, ny = gr->ny, N = nx * ny;
   double fmax = 1.0;
   if (bc->u_factor)
@@ -236,6 +279,58 @@ lks_status validate(const lks_grid* gr, const lks_phys* ph, const lks_bc* bc) {
   return LKS_OK;
 }
 
+// D3Q19: grid->periodic is a bit mask of periodic axes (bit 0 x, bit 1 y,
+// bit 2 z). Face nodes (one coordinate at an end of a non-periodic axis)
+// need a velocity or pressure class (and a thermal class); edge and corner
+// nodes the copy class and no tag; interior nodes the interior class, with
+// an optional prescribed temperature (a solid held at T_bar) and the SOLID
+// tag for non-design nodes.
+lks_status validate3(const lks_grid* gr, const lks_phys* ph, const lks_bc* bc) {
+  if (gr->periodic < 0 || gr->periodic > 7)
+    return fail(nullptr, LKS_E_INVALID, "periodic must be an axis mask 0..7 for D3Q19");
+  const int n3[3] = {gr->nx, gr->ny, gr->nz};
+  for (int a = 0; a < 3; ++a)
+    if (n3[a] < (((gr->periodic >> a) & 1) ? 3 : 4))
+      return fail(nullptr, LKS_E_INVALID, "grid too small");
+  if ((long long)gr->nx * gr->ny * gr->nz > (1LL << 31) / 16)
+    return fail(nullptr, LKS_E_INVALID, "grid too large");
+  lks_status st = validate_common(gr, ph, bc);
+  if (st != LKS_OK) return st;
+  const long long N = (long long)gr->nx * gr->ny * gr->nz;
+  const double fmax = factor_max(bc);
+  for (long long k = 0; k < N; ++k) {
+    const int x[3] = {int(k % gr->nx), int((k / gr->nx) % gr->ny), int(k / ((long long)gr->nx * gr->ny))};
+    int ne = 0;
+    for (int a = 0; a < 3; ++a)
+      if (!((gr->periodic >> a) & 1) && (x[a] == 0 || x[a] == n3[a] - 1)) ++ne;
+    const int m = bc->node_class[k];
+    const double u = std::sqrt(bc->u_bar[k] * bc->u_bar[k] + bc->u_bar[N + k] * bc->u_bar[N + k] +
+                               bc->u_bar[2 * N + k] * bc->u_bar[2 * N + k]) * fmax;
+    if (!(u <= 0.3)) return fail(nullptr, LKS_E_INVALID, "prescribed |u| above 0.3");
+    const int fc = m & 3, tc = (m >> 2) & 3;
+    if (tc == 3) return fail(nullptr, LKS_E_INVALID, "unknown thermal class");
+    if (ne >= 2) {
+      if (fc != LKS_FLOW_CORNER) return fail(nullptr, LKS_E_INVALID, "edge node not classed copy");
+      if (m & (LKS_TAG_J_INLET | LKS_TAG_J_OUTLET | LKS_TAG_PROBE | LKS_TAG_SOLID))
+        return fail(nullptr, LKS_E_INVALID, "edge nodes carry no tag");
+    } else if (ne == 1) {
+      if (fc != LKS_FLOW_VELOCITY && fc != LKS_FLOW_PRESSURE)
+        return fail(nullptr, LKS_E_INVALID, "face node needs a velocity or pressure class");
+      if (ph->thermal && tc != 1 && tc != 2)
+        return fail(nullptr, LKS_E_INVALID, "face node needs a thermal class");
+      if (m & LKS_TAG_SOLID) return fail(nullptr, LKS_E_INVALID, "SOLID tags interior nodes");
+    } else {
+      if (fc != LKS_FLOW_INTERIOR || tc == 2)
+        return fail(nullptr, LKS_E_INVALID, "interior node with a boundary class");
+      if (tc == 1 && !ph->thermal)
+        return fail(nullptr, LKS_E_INVALID, "prescribed temperature needs a thermal problem");
+      if (m & (LKS_TAG_J_INLET | LKS_TAG_J_OUTLET))
+        return fail(nullptr, LKS_E_INVALID, "pressure-drop tags belong on face nodes");
+    }
+  }
+  return LKS_OK;
+}
+
 template <typename R>
 R* rp(void* p) { return static_cast<R*>(p); }
 
@@ -247,35 +342,56 @@ struct Run {
   lks_ctx* c;
   const Geo& g;
   size_t N;
-  explicit Run(lks_ctx* cc) : c(cc), g(cc->geo), N(size_t(cc->geo.N)) {}
+  int nf;  // state fields per level; the last is T
+  explicit Run(lks_ctx* cc) : c(cc), g(cc->geo), N(size_t(cc->N)), nf(nfields(cc)) {}
 
   R* ckpt(int m, int f) { return rp<R>(c->C) + (size_t(m) * ckpt_fields(c) + f) * N; }
   R* slot(int s, int f) { return rp<R>(c->Seg) + (size_t(s) * slot_fields(c) + f) * N; }
+  R* cur_field(int f) { return rp<R>(c->S[c->cur][f]); }
 
-  // pointers (drho, ux, uy, T) of level n of an unsteady run; seg_base is
-  // the first level of the segment held in the replay slots
-  void level(int n, int seg_base, R* out[4]) {
-    const int K = c->plan.K;
+  // pointers (drho, u..., T) of level n of an unsteady run; seg_base is the
+  // first level of the segment held in the replay slots; T is null when the
+  // problem is not thermal
+  void level(int n, int seg_base, R* out[5]) {
+    const int K = c->plan.K, nst = ckpt_fields(c);
+    for (int f = 0; f < 5; ++f) out[f] = nullptr;
     if (n % K == 0) {
       const int m = n / K;
-      out[0] = ckpt(m, 0);
-      out[1] = ckpt(m, 1);
-      out[2] = ckpt(m, 2);
-      out[3] = c->phys.thermal ? ckpt(m, 3) : nullptr;
+      for (int f = 0; f < nst; ++f) out[f] = ckpt(m, f);
       return;
     }
     if (n > seg_base) {
       const int s = n - seg_base - 1;
       out[0] = rp<R>(c->S[n & 1][0]);
-      out[1] = slot(s, 0);
-      out[2] = slot(s, 1);
-      out[3] = c->phys.thermal ? slot(s, 2) : nullptr;
+      for (int f = 1; f < nst; ++f) out[f] = slot(s, f - 1);
       return;
     }
-    for (int f = 0; f < 4; ++f) out[f] = rp<R>(c->S[n & 1][f]);
+    for (int f = 0; f < nf; ++f) out[f] = rp<R>(c->S[n & 1][f]);
+    if (!c->phys.thermal) out[nf - 1] = nullptr;
   }
 
-  void step(R* const in[4], R* const out[4], int level_out, double* acc) {
+  void step(R* const in[5], R* const out[5], int level_out, double* acc) {
+    if (c->dim == 3) {
+      lks::Fwd3Args<R> a;
+      a.mask = c->d_mask;
+      a.inv1pa = rp<R>(c->inv1pa);
+      a.B = rp<R>(c->B);
+      a.ub[0] = rp<R>(c->ubx);
+      a.ub[1] = rp<R>(c->uby);
+      a.ub[2] = rp<R>(c->ubz);
+      a.Tb = rp<R>(c->Tb);
+      a.ufac = c->d_ufac;
+      a.level_out = std::min(level_out, int(c->ufac.size()) - 1);
+      for (int f = 0; f < 5; ++f) {
+        a.s0[f] = in[f];
+        a.s1[f] = out[f];
+      }
+      a.e = rp<R>(c->E3);
+      a.acc = acc;
+      a.objective = c->objective;
+      lks::launch_lks3_step<R>(c->geo3, a, c->stream);
+      return;
+    }
     lks::FwdArgs<R> a;
     a.mask = c->d_mask;
     a.inv1pa = rp<R>(c->inv1pa);
@@ -301,12 +417,22 @@ struct Run {
   void coefficients(const double* gamma) {
     const double Kf = c->phys.thermal ? c->phys.nu / c->phys.Pr : 0.0;
     const double Ks = Kf * (c->phys.thermal ? c->phys.Ks_over_Kf : 1.0);
-    lks::launch_coef<R>(g, gamma, c->phys.alpha_max, c->phys.q_alpha, Kf, Ks,
-                        c->phys.thermal ? c->phys.q_K : 1.0, rp<R>(c->inv1pa), rp<R>(c->B),
-                        rp<R>(c->dA3), rp<R>(c->dB), c->stream);
+    const double qK = c->phys.thermal ? c->phys.q_K : 1.0;
+    if (c->dim == 3)
+      lks::launch_coef3<R>(c->geo3, c->d_mask, gamma, c->phys.alpha_max, c->phys.q_alpha, Kf, Ks,
+                           qK, rp<R>(c->inv1pa), rp<R>(c->B), rp<R>(c->dA3), rp<R>(c->dB),
+                           c->stream);
+    else
+      lks::launch_coef<R>(g, gamma, c->phys.alpha_max, c->phys.q_alpha, Kf, Ks, qK,
+                          rp<R>(c->inv1pa), rp<R>(c->B), rp<R>(c->dA3), rp<R>(c->dB), c->stream);
   }
 
-  void init(R* const s[4]) {
+  void init(R* const s[5]) {
+    if (c->dim == 3) {
+      const R* ub[3] = {rp<R>(c->ubx), rp<R>(c->uby), rp<R>(c->ubz)};
+      lks::launch_init3<R>(c->geo3, c->d_mask, ub, rp<R>(c->Tb), c->ufac[0], s, c->stream);
+      return;
+    }
     lks::launch_init<R>(g, c->d_mask, rp<R>(c->ubx), rp<R>(c->uby), rp<R>(c->Tb), c->ufac[0],
                         s[0], s[1], s[2], s[3], c->stream);
   }
@@ -314,25 +440,25 @@ struct Run {
   void forward(const double* gamma, int steps) {
     coefficients(gamma);
     if (c->mode == LKS_STEADY) {
-      R* s0[4];
-      for (int f = 0; f < 4; ++f) s0[f] = rp<R>(c->S[0][f]);
+      R* s0[5] = {};
+      for (int f = 0; f < nf; ++f) s0[f] = rp<R>(c->S[0][f]);
       init(s0);
       c->cur = 0;
       advance(steps);
       return;
     }
-    lks::launch_fill(c->acc, size_t(n_tiles(g)), 0.0, c->stream);
-    R* lv[4];
+    lks::launch_fill(c->acc, size_t(acc_count(c)), 0.0, c->stream);
+    R* lv[5];
     level(0, c->plan.ls, lv);
     init(lv);
     for (int n = 0; n < steps; ++n) {
-      R* in[4];
-      R* out[4];
+      R* in[5];
+      R* out[5];
       level(n, c->plan.ls, in);
       level(n + 1, c->plan.ls, out);
       step(in, out, n + 1, c->acc);
     }
-    R* last[4];
+    R* last[5];
     level(steps, c->plan.ls, last);
     lks::launch_finite_check<R>(last[1], N, c->flag, c->stream);
     c->last_level = steps;
@@ -340,9 +466,9 @@ struct Run {
 
   void advance(int steps) {
     for (int n = 0; n < steps; ++n) {
-      R* in[4];
-      R* out[4];
-      for (int f = 0; f < 4; ++f) {
+      R* in[5] = {};
+      R* out[5] = {};
+      for (int f = 0; f < nf; ++f) {
         in[f] = rp<R>(c->S[c->cur][f]);
         out[f] = rp<R>(c->S[c->cur ^ 1][f]);
       }
@@ -350,34 +476,67 @@ struct Run {
       c->cur ^= 1;
     }
     c->last_level += steps;
-    lks::launch_finite_check<R>(rp<R>(c->S[c->cur][1]), N, c->flag, c->stream);
-    if (c->objective == LKS_OBJ_PRESSURE_DROP)
-      lks::launch_pressure_drop<R>(g, c->d_mask, rp<R>(c->S[c->cur][0]), c->scal, c->stream);
-    else
+    lks::launch_finite_check<R>(cur_field(1), N, c->flag, c->stream);
+    if (c->objective == LKS_OBJ_PRESSURE_DROP) {
+      if (c->dim == 3)
+        lks::launch_tag_sum3<R>(c->geo3, c->d_mask, cur_field(0), cur_field(1), cur_field(4),
+                                LKS_OBJ_PRESSURE_DROP, c->scal, c->stream);
+      else
+        lks::launch_pressure_drop<R>(g, c->d_mask, cur_field(0), c->scal, c->stream);
+    } else {
       probe_heat_steady();
+    }
   }
 
   void probe_heat_steady() {
-    lks::launch_probe_heat<R>(g, c->d_mask, rp<R>(c->S[c->cur][1]), rp<R>(c->S[c->cur][3]),
-                              c->scal, c->stream);
+    if (c->dim == 3)
+      lks::launch_tag_sum3<R>(c->geo3, c->d_mask, cur_field(0), cur_field(1), cur_field(4),
+                              LKS_OBJ_HEAT, c->scal, c->stream);
+    else
+      lks::launch_probe_heat<R>(g, c->d_mask, cur_field(1), cur_field(3), c->scal, c->stream);
   }
 
   void zero_adjoint(int which) {
-    for (int f = 0; f < 4; ++f) lks::launch_fill_r<R>(rp<R>(c->P[which][f]), N, c->stream);
+    for (int f = 0; f < nf; ++f) lks::launch_fill_r<R>(rp<R>(c->P[which][f]), N, c->stream);
   }
 
-  void adj_step(const R* ux, const R* uy, const R* T, double sdp, double sh, double* sens,
-                int mode) {
+  // one ALKS step with the state st (drho, u..., T) of the destination level
+  void adj_step(R* const st[5], double sdp, double sh, double* sens, int mode) {
+    const int i0 = c->acur, i1 = c->acur ^ 1;
+    if (c->dim == 3) {
+      lks::Adj3Args<R> a;
+      a.mask = c->d_mask;
+      a.inv1pa = rp<R>(c->inv1pa);
+      a.B = rp<R>(c->B);
+      a.dA3 = rp<R>(c->dA3);
+      a.dB = rp<R>(c->dB);
+      a.u[0] = st[1];
+      a.u[1] = st[2];
+      a.u[2] = st[3];
+      a.T = st[4] ? st[4] : st[1];
+      for (int f = 0; f < 5; ++f) {
+        a.p0[f] = rp<R>(c->P[i0][f]);
+        a.p1[f] = rp<R>(c->P[i1][f]);
+      }
+      a.m = rp<R>(c->E3);
+      a.ops = c->d_ops3;
+      a.sens = sens;
+      a.sens_mode = sens ? mode : 0;
+      a.seed_dp = sdp;
+      a.seed_heat = sh;
+      lks::launch_alks3_step<R>(c->geo3, a, c->stream);
+      c->acur = i1;
+      return;
+    }
     lks::AdjArgs<R> a;
     a.mask = c->d_mask;
     a.inv1pa = rp<R>(c->inv1pa);
     a.B = rp<R>(c->B);
     a.dA3 = rp<R>(c->dA3);
     a.dB = rp<R>(c->dB);
-    a.ux = ux;
-    a.uy = uy;
-    a.T = T ? T : ux;
-    const int i0 = c->acur, i1 = c->acur ^ 1;
+    a.ux = st[1];
+    a.uy = st[2];
+    a.T = st[3] ? st[3] : st[1];
     a.r0 = rp<R>(c->P[i0][0]);
     a.vx0 = rp<R>(c->P[i0][1]);
     a.vy0 = rp<R>(c->P[i0][2]);
@@ -402,12 +561,12 @@ struct Run {
     }
     const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? seed : 0.0;
     const double sh = c->objective == LKS_OBJ_HEAT ? seed : 0.0;
-    const R* ux = rp<R>(c->S[c->cur][1]);
-    const R* uy = rp<R>(c->S[c->cur][2]);
-    const R* T = c->phys.thermal ? rp<R>(c->S[c->cur][3]) : nullptr;
+    R* st[5] = {};
+    for (int f = 0; f < nf; ++f) st[f] = cur_field(f);
+    if (!c->phys.thermal) st[nf - 1] = nullptr;
     for (int n = 0; n < steps; ++n) {
       const bool last = n == steps - 1;
-      adj_step(ux, uy, T, sdp, sh, last ? dJ : nullptr, 2);
+      adj_step(st, sdp, sh, last ? dJ : nullptr, 2);
     }
   }
 
@@ -421,38 +580,52 @@ struct Run {
       if (b != c->plan.ls) {
         // replay levels b+1 .. top into the segment slots
         for (int n = b; n < top; ++n) {
-          R* in[4];
-          R* out[4];
+          R* in[5];
+          R* out[5];
           level(n, b, in);
           level(n + 1, b, out);
           step(in, out, n + 1, nullptr);
         }
       }
       for (int n = top; n >= b; --n) {
-        R* lv[4];
+        R* lv[5];
         level(n, b, lv);
         const double w = n >= 1 ? seed / Nst : 0.0;
         const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? w : 0.0;
         const double sh = c->objective == LKS_OBJ_HEAT ? w : 0.0;
-        adj_step(lv[1], lv[2], lv[3], sdp, sh, dJ, 1);
+        adj_step(lv, sdp, sh, dJ, 1);
       }
     }
   }
 
+  // internal index of a forward field id, or -1
+  int fwd_index(int which) {
+    if (which == LKS_FIELD_DRHO || which == LKS_FIELD_UX || which == LKS_FIELD_UY) return which;
+    if (which == LKS_FIELD_T) return c->phys.thermal ? nf - 1 : -1;
+    if (which == LKS_FIELD_UZ) return c->dim == 3 ? 3 : -1;
+    return -1;
+  }
+  int adj_index(int which) {
+    if (which == LKS_FIELD_ADJ_RHO || which == LKS_FIELD_ADJ_VX || which == LKS_FIELD_ADJ_VY)
+      return which - LKS_FIELD_ADJ_RHO;
+    if (which == LKS_FIELD_ADJ_THETA) return c->phys.thermal ? nf - 1 : -1;
+    if (which == LKS_FIELD_ADJ_VZ) return c->dim == 3 ? 3 : -1;
+    return -1;
+  }
+
   lks_status read(int which, double* out) {
     const void* src = nullptr;
-    if (which <= LKS_FIELD_T) {
-      if (which == LKS_FIELD_T && !c->phys.thermal) return LKS_E_INVALID;
+    int f;
+    if ((f = fwd_index(which)) >= 0) {
       if (c->mode == LKS_STEADY) {
-        src = c->S[c->cur][which];
+        src = c->S[c->cur][f];
       } else {
-        R* lv[4];
+        R* lv[5];
         level(c->last_level, c->plan.ls, lv);
-        src = lv[which];
+        src = lv[f];
       }
-    } else if (which <= LKS_FIELD_ADJ_THETA) {
-      if (which == LKS_FIELD_ADJ_THETA && !c->phys.thermal) return LKS_E_INVALID;
-      src = c->P[c->acur][which - LKS_FIELD_ADJ_RHO];
+    } else if ((f = adj_index(which)) >= 0) {
+      src = c->P[c->acur][f];
     } else {
       return LKS_E_INVALID;
     }
@@ -462,13 +635,12 @@ struct Run {
 
   lks_status write(int which, const double* in) {
     void* dst = nullptr;
-    if (which <= LKS_FIELD_T) {
-      if (which == LKS_FIELD_T && !c->phys.thermal) return LKS_E_INVALID;
+    int f;
+    if ((f = fwd_index(which)) >= 0) {
       if (c->mode != LKS_STEADY) return LKS_E_UNSUPPORTED;
-      dst = c->S[c->cur][which];
-    } else if (which <= LKS_FIELD_ADJ_THETA) {
-      if (which == LKS_FIELD_ADJ_THETA && !c->phys.thermal) return LKS_E_INVALID;
-      dst = c->P[c->acur][which - LKS_FIELD_ADJ_RHO];
+      dst = c->S[c->cur][f];
+    } else if ((f = adj_index(which)) >= 0) {
+      dst = c->P[c->acur][f];
     } else {
       return LKS_E_INVALID;
     }
@@ -495,21 +667,25 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
                       size_t mem_budget_bytes, void* hip_stream, lks_ctx** out) {
   if (!out) return fail(nullptr, LKS_E_INVALID, "null output pointer");
   *out = nullptr;
-  lks_status st = validate(grid, phys, bc);
+  if (!grid || !phys || !bc) return fail(nullptr, LKS_E_INVALID, "null descriptor");
+  const bool d3 = grid->lattice == LKS_D3Q19;
+  lks_status st = d3 ? validate3(grid, phys, bc) : validate(grid, phys, bc);
   if (st != LKS_OK) return st;
   lks_ctx* c = new lks_ctx();
   c->grid = *grid;
-  c->grid.nz = 1;
+  if (!d3) c->grid.nz = 1;
+  c->dim = d3 ? 3 : 2;
   c->phys = *phys;
   c->objective = bc->objective;
   c->mode = bc->mode;
   c->n_steps = bc->mode == LKS_UNSTEADY ? bc->n_steps : 0;
   c->rho_out = bc->rho_out;
-  const int N = grid->nx * grid->ny;
+  const int N = grid->nx * grid->ny * c->grid.nz;
+  c->N = N;
   c->mask.assign(bc->node_class, bc->node_class + N);
-  if (grid->periodic)
+  if (d3 ? grid->periodic == 7 : grid->periodic != 0)
     for (auto& m : c->mask) m &= uint8_t(~15);
-  c->ubar.assign(bc->u_bar, bc->u_bar + 2 * N);
+  c->ubar.assign(bc->u_bar, bc->u_bar + size_t(c->dim) * N);
   if (bc->T_bar) c->Tbar.assign(bc->T_bar, bc->T_bar + N);
   else c->Tbar.assign(N, 0.0);
   if (bc->u_factor) c->ufac.assign(bc->u_factor, bc->u_factor + bc->n_factor);
@@ -530,6 +706,19 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
   g.Bf = 3.0 * (1.0 / 6.0 - Kf);
   g.drho_out = bc->rho_out - 1.0;
   lks::build_ring_ops(g.A, g.Bf, c->ops);
+  if (d3) {
+    lks::Geo3& g3 = c->geo3;
+    g3.nx = grid->nx;
+    g3.ny = grid->ny;
+    g3.nz = grid->nz;
+    g3.N = N;
+    g3.periodic = grid->periodic;
+    g3.thermal = g.thermal;
+    g3.A = g.A;
+    g3.Bf = g.Bf;
+    g3.drho_out = g.drho_out;
+    lks::build_face_ops3(g3.A, g3.Bf, c->ops3);
+  }
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->budget = mem_budget_bytes;
   c->rsz = grid->precision == LKS_FP64 ? 8 : 4;
@@ -554,7 +743,8 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
   if (reinterpret_cast<uintptr_t>(dev_ptr) & 255)
     return fail(c, LKS_E_INVALID, "workspace must be 256-byte aligned");
   if (bytes < c->plan.total) return fail(c, LKS_E_NOMEM, "workspace smaller than lks_workspace_size");
-  const size_t N = size_t(c->geo.N), r = size_t(c->rsz);
+  const size_t N = size_t(c->N), r = size_t(c->rsz);
+  const int nf = nfields(c), nu = c->dim;
   char* p = static_cast<char*>(dev_ptr);
   auto take = [&](size_t b) {
     char* q = p;
@@ -566,6 +756,7 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
   c->d_mask = reinterpret_cast<uint8_t*>(take(N));
   c->ubx = take(N * r);
   c->uby = take(N * r);
+  c->ubz = nu == 3 ? take(N * r) : nullptr;
   c->Tb = take(N * r);
   c->d_ufac = reinterpret_cast<double*>(take(sizeof(double) * c->ufac.size()));
   c->inv1pa = take(N * r);
@@ -573,50 +764,55 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
   c->dA3 = take(N * r);
   c->dB = take(N * r);
   for (int s = 0; s < 2; ++s)
-    for (int f = 0; f < 4; ++f) c->S[s][f] = take(N * r);
+    for (int f = 0; f < 5; ++f) c->S[s][f] = f < nf ? take(N * r) : nullptr;
   for (int s = 0; s < 2; ++s)
-    for (int f = 0; f < 4; ++f) c->P[s][f] = take(N * r);
-  c->acc = reinterpret_cast<double*>(take(sizeof(double) * max_tiles(c->geo)));
-  c->d_ops = reinterpret_cast<lks::RingOp*>(take(4 * sizeof(lks::RingOp)));
+    for (int f = 0; f < 5; ++f) c->P[s][f] = f < nf ? take(N * r) : nullptr;
+  c->acc = reinterpret_cast<double*>(take(sizeof(double) * acc_capacity(c)));
+  if (nu == 3) {
+    c->d_ops3 = reinterpret_cast<lks::FaceOp3*>(take(6 * sizeof(lks::FaceOp3)));
+    c->E3 = take(size_t(scratch3_fields(c)) * N * r);
+  } else {
+    c->d_ops = reinterpret_cast<lks::RingOp*>(take(4 * sizeof(lks::RingOp)));
+  }
   c->scal = reinterpret_cast<double*>(take(sizeof(double) * 8));
   c->flag = reinterpret_cast<int*>(take(sizeof(int) * 4));
   if (c->mode == LKS_UNSTEADY) {
     c->C = take(size_t(c->plan.n_ckpt) * ckpt_fields(c) * N * r);
     c->Seg = take(size_t(c->plan.n_slots) * slot_fields(c) * N * r);
   }
-  // upload boundary data in the working precision
+  // upload boundary data in the working precision: u_bar blocks, then T_bar
   lks_status st = LKS_OK;
-  std::vector<char> tmp(3 * N * r);
-  for (size_t k = 0; k < N; ++k) {
-    if (r == 8) {
-      reinterpret_cast<double*>(tmp.data())[k] = c->ubar[k];
-      reinterpret_cast<double*>(tmp.data())[N + k] = c->ubar[N + k];
-      reinterpret_cast<double*>(tmp.data())[2 * N + k] = c->Tbar[k];
-    } else {
-      reinterpret_cast<float*>(tmp.data())[k] = float(c->ubar[k]);
-      reinterpret_cast<float*>(tmp.data())[N + k] = float(c->ubar[N + k]);
-      reinterpret_cast<float*>(tmp.data())[2 * N + k] = float(c->Tbar[k]);
+  std::vector<char> tmp(size_t(nu + 1) * N * r);
+  for (int b = 0; b <= nu; ++b) {
+    const double* src = b < nu ? c->ubar.data() + size_t(b) * N : c->Tbar.data();
+    for (size_t k = 0; k < N; ++k) {
+      if (r == 8) reinterpret_cast<double*>(tmp.data())[size_t(b) * N + k] = src[k];
+      else reinterpret_cast<float*>(tmp.data())[size_t(b) * N + k] = float(src[k]);
     }
   }
+  void* dst[4] = {c->ubx, c->uby, nu == 3 ? c->ubz : c->Tb, c->Tb};
   if (!hip_ok(c, hipMemcpyAsync(c->d_mask, c->mask.data(), N, hipMemcpyHostToDevice, c->stream),
-              "upload mask", &st) ||
-      !hip_ok(c, hipMemcpyAsync(c->ubx, tmp.data(), N * r, hipMemcpyHostToDevice, c->stream),
-              "upload u_bar", &st) ||
-      !hip_ok(c, hipMemcpyAsync(c->uby, tmp.data() + N * r, N * r, hipMemcpyHostToDevice, c->stream),
-              "upload u_bar", &st) ||
-      !hip_ok(c, hipMemcpyAsync(c->Tb, tmp.data() + 2 * N * r, N * r, hipMemcpyHostToDevice,
-                                c->stream),
-              "upload T_bar", &st) ||
+              "upload mask", &st))
+    return st;
+  for (int b = 0; b <= nu; ++b)
+    if (!hip_ok(c, hipMemcpyAsync(dst[b], tmp.data() + size_t(b) * N * r, N * r,
+                                  hipMemcpyHostToDevice, c->stream),
+                "upload boundary values", &st))
+      return st;
+  const bool ops_ok = nu == 3
+      ? hip_ok(c, hipMemcpyAsync(c->d_ops3, c->ops3, sizeof c->ops3, hipMemcpyHostToDevice,
+                                 c->stream), "upload face operators", &st)
+      : hip_ok(c, hipMemcpyAsync(c->d_ops, c->ops, sizeof c->ops, hipMemcpyHostToDevice,
+                                 c->stream), "upload ring operators", &st);
+  if (!ops_ok ||
       !hip_ok(c, hipMemcpyAsync(c->d_ufac, c->ufac.data(), sizeof(double) * c->ufac.size(),
                                 hipMemcpyHostToDevice, c->stream),
               "upload u_factor", &st) ||
-      !hip_ok(c, hipMemcpyAsync(c->d_ops, c->ops, sizeof c->ops, hipMemcpyHostToDevice, c->stream),
-              "upload ring operators", &st) ||
       !hip_ok(c, hipStreamSynchronize(c->stream), "bind sync", &st))
     return st;
   // clear the state so that an unused thermal field reads as zero
   for (int s = 0; s < 2; ++s)
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < nf; ++f) {
       if (r == 8) lks::launch_fill_r<double>(static_cast<double*>(c->S[s][f]), N, c->stream);
       else lks::launch_fill_r<float>(static_cast<float*>(c->S[s][f]), N, c->stream);
     }
@@ -674,7 +870,7 @@ lks_status lks_objective(lks_ctx* c, double* J) {
   lks_status st = LKS_OK;
   double sc[8];
   int flag[4];
-  if (c->mode == LKS_UNSTEADY) lks::launch_sum(c->acc, n_tiles(c->geo), c->scal, c->stream);
+  if (c->mode == LKS_UNSTEADY) lks::launch_sum(c->acc, acc_count(c), c->scal, c->stream);
   if (!hip_ok(c, hipMemcpyAsync(sc, c->scal, sizeof sc, hipMemcpyDeviceToHost, c->stream),
               "read objective", &st) ||
       !hip_ok(c, hipMemcpyAsync(flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream),
@@ -743,13 +939,14 @@ lks_status lks_write_field(lks_ctx* c, int which, const double* dev_in) {
   lks_status st = c->rsz == 8 ? Run<double>(c).write(which, dev_in)
                               : Run<float>(c).write(which, dev_in);
   if (st != LKS_OK) return fail(c, st, "field not writable");
-  if (which <= LKS_FIELD_T) c->have_forward = true;
+  if (which <= LKS_FIELD_T || which == LKS_FIELD_UZ) c->have_forward = true;
   else c->have_adjoint = true;
   return check_launch(c);
 }
 
 lks_status lks_set_tile_rows(lks_ctx* c, int tile_rows) {
   if (!c) return LKS_E_INVALID;
+  if (c->dim == 3) return fail(c, LKS_E_UNSUPPORTED, "D3Q19 kernels are not tiled");
   for (int ty : TILE_ROWS)
     if (ty == tile_rows) {
       set_tile_rows(c->geo, ty);
@@ -762,6 +959,7 @@ lks_status lks_set_tile_rows(lks_ctx* c, int tile_rows) {
 
 lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* tile_rows) {
   if (!c || !gamma_dev || steps < 1) return LKS_E_INVALID;
+  if (c->dim == 3) return fail(c, LKS_E_UNSUPPORTED, "D3Q19 kernels are not tiled");
   if (!c->bound) return fail(c, LKS_E_STATE, "no workspace bound");
   lks_status st = LKS_OK;
   hipEvent_t e[3];
@@ -979,11 +1177,12 @@ lks_status lks_batch_create(int n, const lks_grid* grids, const lks_phys* phys, 
   b->user = static_cast<hipStream_t>(hip_stream);
   size_t off = 0;
   for (int d = 0; d < n; ++d) {
-    if (bcs[d].mode != LKS_STEADY || bcs[d].objective != LKS_OBJ_PRESSURE_DROP) {
+    if (bcs[d].mode != LKS_STEADY || bcs[d].objective != LKS_OBJ_PRESSURE_DROP ||
+        grids[d].lattice != LKS_D2Q9) {
       for (auto* p : b->ctx) lks_destroy(p);
       delete b;
       return bfail(nullptr, LKS_E_UNSUPPORTED,
-                   "batches hold steady problems with the pressure-drop objective");
+                   "batches hold steady D2Q9 problems with the pressure-drop objective");
     }
     if (grids[d].precision != grids[0].precision || phys[d].thermal != phys[0].thermal) {
       for (auto* p : b->ctx) lks_destroy(p);

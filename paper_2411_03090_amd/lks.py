@@ -44,7 +44,8 @@ LKS_FP64, LKS_FP32DEV = 0, 1
 LKS_OBJ_PRESSURE_DROP, LKS_OBJ_HEAT = 0, 1
 LKS_STEADY, LKS_UNSTEADY = 0, 1
 FIELDS = {"drho": 0, "ux": 1, "uy": 2, "T": 3,
-          "adj_rho": 4, "adj_vx": 5, "adj_vy": 6, "adj_theta": 7}
+          "adj_rho": 4, "adj_vx": 5, "adj_vy": 6, "adj_theta": 7,
+          "uz": 8, "adj_vz": 9}
 
 EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forward",
             "lks_advance", "lks_objective", "alks_backward", "alks_advance",
@@ -158,20 +159,26 @@ def _dptr(a):
 class LKS:
     """One forward/adjoint problem bound to a device workspace.
 
-    ``wl`` is a workloads.Workload. ``precision`` is "fp64" or "fp32".
-    ``mem_budget`` bounds the unsteady trajectory storage (bytes, 0 = none).
+    ``wl`` is a workloads.Workload (D2Q9) or workloads.Workload3 (D3Q19).
+    ``precision`` is "fp64" or "fp32". ``mem_budget`` bounds the unsteady
+    trajectory storage (bytes, 0 = none).
     """
 
     def __init__(self, wl, precision="fp64", mem_budget=0, device=None, stream=None,
                  bind=True):
         self.wl = wl
-        self.N = wl.nx * wl.ny
+        nz = getattr(wl, "nz", 1)
+        self.d3 = nz > 1 or hasattr(wl, "periodic_axes")
+        self.N = wl.nx * wl.ny * nz
         self._mask = np.ascontiguousarray(wl.mask, dtype=np.uint8).reshape(-1)
         self._ubar = np.ascontiguousarray(wl.ubar, dtype=np.float64).reshape(-1)
         self._Tbar = np.ascontiguousarray(wl.Tbar, dtype=np.float64).reshape(-1)
         self._ufac = np.ascontiguousarray(wl.ufac, dtype=np.float64).reshape(-1)
         prec = LKS_FP64 if precision == "fp64" else LKS_FP32DEV
-        self.grid = Grid(wl.nx, wl.ny, 1, LKS_D2Q9, prec, int(wl.periodic))
+        if self.d3:
+            self.grid = Grid(wl.nx, wl.ny, nz, LKS_D3Q19, prec, int(wl.periodic_axes))
+        else:
+            self.grid = Grid(wl.nx, wl.ny, 1, LKS_D2Q9, prec, int(wl.periodic))
         self.phys = Phys(wl.nu, wl.Pr, wl.alpha_max, wl.q_alpha, wl.Ks_over_Kf, wl.q_K,
                          int(wl.thermal))
         self.bc = BC(self._mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),

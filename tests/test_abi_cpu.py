@@ -79,18 +79,59 @@ def test_invalid_masks_and_inflow_are_rejected():
     assert "B < 0" in str(e.value)
 
 
-def test_heat_objective_needs_thermal_and_3d_is_unsupported():
+def test_heat_objective_needs_thermal():
     wl = W.steady_channel_uniform(16, 12, Re=10, seed=0)
     wl.objective = W.OBJ_HEAT
     with pytest.raises(lks.LKSError):
         _create(wl)
-    wl = W.steady_channel_uniform(16, 12, Re=10, seed=0)
-    c = _create(wl)
-    g = lks.Grid(16, 12, 4, lks.LKS_D3Q19, lks.LKS_FP32DEV, 0)
-    ctx = ctypes.c_void_p()
-    st = lks.lib().lks_create(ctypes.byref(g), ctypes.byref(c.phys), ctypes.byref(c.bc), 0,
-                              None, ctypes.byref(ctx))
-    assert st == lks.LKS_E_UNSUPPORTED
+
+
+def test_d3q19_duct_validates_and_plans_without_gpu():
+    wl = W.heated_block_duct(32, 16, 12, Re=50.0, n_steps=100)
+    c = _create(wl, "fp32")
+    N = 32 * 16 * 12
+    rep = c.memory_report()
+    assert rep["K"] == 100                       # whole trajectory kept
+    # level-0 checkpoint (drho, u, T) plus 100 levels of (u, T)
+    assert rep["ckpt_bytes"] == (5 + 100 * 4) * N * 4
+    # the full-size heated-block duct: 5000 levels do not fit 288 GB whole
+    big = W.heated_block_duct(256, 128, 128, n_steps=5000)
+    Nb = 256 * 128 * 128
+    full = _create(big, "fp32")
+    assert full.memory_report()["ckpt_bytes"] == (5 + 5000 * 4) * Nb * 4
+    assert full.memory_report()["ckpt_bytes"] > 288 * 2 ** 30
+    cb = _create(big, "fp32", 16 * 2 ** 30)
+    r = cb.memory_report()
+    assert 1 < r["K"] < 5000 and cb.workspace_size() <= 16 * 2 ** 30
+
+
+def _expect_invalid(wl):
+    with pytest.raises(lks.LKSError) as e:
+        _create(wl)
+    assert e.value.status == lks.LKS_E_INVALID
+
+
+def test_invalid_d3q19_masks_are_rejected():
+    base = lambda: W.heated_block_duct(20, 10, 8, Re=20.0, n_steps=10)
+    wl = base()
+    wl.mask = wl.mask.copy()
+    wl.mask[0, 0, 5] = W.FLOW_VELOCITY            # edge node not classed copy
+    _expect_invalid(wl)
+    wl = base()
+    wl.mask = wl.mask.copy()
+    wl.mask[3, 4, 0] = W.THERM_DIRICHLET          # face node without a flow class
+    _expect_invalid(wl)
+    wl = base()
+    wl.mask = wl.mask.copy()
+    wl.mask[3, 0, 6] |= W.TAG_SOLID               # SOLID on a face node
+    _expect_invalid(wl)
+    wl = base()
+    wl.periodic_axes = 9
+    _expect_invalid(wl)
+    wl = base()
+    wl.mask = wl.mask.copy()
+    wl.mask[3, 4, 5] |= W.TAG_J_INLET             # pressure-drop tag inside
+    _expect_invalid(wl)
 
 
 def test_calls_out_of_order_report_state_errors():

@@ -1,0 +1,284 @@
+"""D3Q19 path on the GPU against the FP64 oracle: single forward and adjoint
+steps from random states (duct with a heated block, z-periodic channel,
+periodic box), whole unsteady gradients, checkpoint replay, the full-size
+256x128x128 duct, and the autograd wrapper."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import d3 as O3  # noqa: E402
+from paper_2411_03090_amd import autograd, lks, workloads as W  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1), device=DEV)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def _duct(nx=18, ny=10, nz=12, n=40, Re=20.0, seed=0):
+    return W.heated_block_duct(nx, ny, nz, Re=Re, Pr=0.71, sigma=2.0, seed=seed, n_steps=n)
+
+
+def _zchannel():
+    wl = W.steady_channel_uniform(21, 9, Re=10.0, seed=1)
+    return W.extrude_z(wl, 5)
+
+
+def _box():
+    wl = W.periodic_box3(9, 7, 6, nu=0.08, thermal=True, Pr=6.0)
+    wl.alpha_max, wl.Ks_over_Kf = 0.7, 3.0
+    wl.gamma = np.clip(0.6 + 0.4 * W.gaussian_random_field((6, 7, 9), 1.5, 2), 0.05, 1.0)
+    wl.mask = wl.mask.copy()
+    wl.mask[1:3, 2:5, 3] |= W.TAG_PROBE
+    wl.objective = W.OBJ_HEAT
+    return wl
+
+
+CASES = {"duct_18x10x12": _duct, "zchannel_21x9x5": _zchannel, "box_9x7x6": _box}
+FWD = ["drho", "ux", "uy", "uz", "T"]
+ADJ = ["adj_rho", "adj_vx", "adj_vy", "adj_vz", "adj_theta"]
+
+
+def _random_state(wl, rng, smooth=False):
+    N = wl.nx * wl.ny * wl.nz
+    if smooth:
+        f = lambda s: W.gaussian_random_field((wl.nz, wl.ny, wl.nx), 4.0, s).ravel()
+        return O3.State3(1e-3 * f(11), np.concatenate([0.03 * f(12), 0.02 * f(13), 0.02 * f(14)]),
+                         0.5 + 0.3 * f(15))
+    return O3.State3(1e-3 * rng.standard_normal(N), 0.02 * rng.standard_normal(3 * N), rng.random(N))
+
+
+def _write_state(ctx, wl, s):
+    N = wl.nx * wl.ny * wl.nz
+    ctx.write("drho", T(s.drho))
+    for c, n in enumerate(("ux", "uy", "uz")):
+        ctx.write(n, T(s.u[c * N:(c + 1) * N]))
+    if wl.thermal:
+        ctx.write("T", T(s.T))
+
+
+def _state_fields(wl, s):
+    N = wl.nx * wl.ny * wl.nz
+    out = {"drho": s.drho, "ux": s.u[:N], "uy": s.u[N:2 * N], "uz": s.u[2 * N:]}
+    if wl.thermal:
+        out["T"] = s.T
+    return out
+
+
+def _steady(wl):
+    wl.mode = W.MODE_STEADY
+    wl.ufac = np.ones(2)
+    return wl
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_single_forward_step_3d(case, prec):
+    say(f"[gpu] 3D forward step {case} {prec}")
+    wl = _steady(CASES[case]())
+    rng = np.random.default_rng(3)
+    s = _random_state(wl, rng)
+    pb = O3.Problem3(wl)
+    a, _, B, _ = O3.coefficients(pb, wl.gamma)
+    want = _state_fields(wl, O3.lks_step(pb, a, B, 1.0, s))
+    ctx = lks.LKS(wl, precision=prec, device=DEV)
+    g = T(wl.gamma)
+    ctx.forward(g, 0)
+    _write_state(ctx, wl, s)
+    ctx.advance(g, 1)
+    tol = 1e-13 if prec == "fp64" else 2e-5
+    for n, ref in want.items():
+        got = ctx.read(n).cpu().numpy()
+        if np.abs(ref).max() == 0:
+            assert np.abs(got).max() < 1e-12, n
+        else:
+            assert rel(got, ref) < tol, (n, rel(got, ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_single_adjoint_step_3d(case, prec):
+    say(f"[gpu] 3D adjoint step {case} {prec}")
+    wl = _steady(CASES[case]())
+    rng = np.random.default_rng(8)
+    s = _random_state(wl, rng)
+    pb = O3.Problem3(wl)
+    N = pb.N
+    a, da, B, dB = O3.coefficients(pb, wl.gamma)
+    adj1 = [rng.standard_normal(N) for _ in range(14)]
+    V1, Th1 = O3.adjoint_equilibrium(pb, B, s.u, adj1)
+    seed = 0.6
+    sdp = seed if wl.objective == W.OBJ_PRESSURE_DROP else 0.0
+    sh = seed if wl.objective == W.OBJ_HEAT else 0.0
+    adj0 = O3.alks_step(pb, a, B, s, s, adj1, sdp, sh)
+    V0, Th0 = O3.adjoint_equilibrium(pb, B, s.u, adj0)
+    sens = np.zeros(N)
+    O3.sens_add(pb, da, dB, s, adj0, 1.0, sens)
+
+    ctx = lks.LKS(wl, precision=prec, device=DEV)
+    g = T(wl.gamma)
+    ctx.forward(g, 0)
+    _write_state(ctx, wl, s)
+    ctx.write("adj_rho", T(adj1[0]))
+    for c, n in enumerate(("adj_vx", "adj_vy", "adj_vz")):
+        ctx.write(n, T(V1[c * N:(c + 1) * N]))
+    if wl.thermal:
+        ctx.write("adj_theta", T(Th1))
+    dJ = torch.zeros(N, dtype=torch.float64, device=DEV)
+    ctx.adjoint_advance(seed, 1, dJ)
+    tol = 1e-13 if prec == "fp64" else 3e-5
+    pairs = [("adj_rho", adj0[0]), ("adj_vx", V0[:N]), ("adj_vy", V0[N:2 * N]),
+             ("adj_vz", V0[2 * N:])]
+    if wl.thermal:
+        pairs.append(("adj_theta", Th0))
+    for n, ref in pairs:
+        got = ctx.read(n).cpu().numpy()
+        assert rel(got, ref) < tol, (n, rel(got, ref))
+    if np.abs(sens).max() > 0:
+        assert rel(dJ.cpu().numpy(), sens) < tol
+
+
+def _gpu_gradient(wl, prec, budget=0):
+    ctx = lks.LKS(wl, precision=prec, mem_budget=budget, device=DEV)
+    g = T(wl.gamma)
+    dJ = torch.empty_like(g)
+    ctx.forward(g, wl.n_fwd)
+    J = ctx.objective()
+    fields = {n: ctx.read(n).cpu().numpy() for n in FWD}
+    ctx.backward(1.0, dJ)
+    torch.cuda.synchronize()
+    return J, dJ.cpu().numpy(), fields, ctx
+
+
+@pytest.fixture(scope="module")
+def duct_gradient():
+    wl = _duct(n=60)
+    J, sens, s, _ = O3.gradient(wl)
+    return wl, J, sens.ravel(), s
+
+
+def test_unsteady_duct_gradient_fp64_matches_oracle(duct_gradient):
+    say("[gpu] 3D unsteady duct 18x10x12, 60 steps, fp64")
+    wl, Jo, so, st = duct_gradient
+    J, dJ, f, _ = _gpu_gradient(wl, "fp64")
+    assert abs(J - Jo) / abs(Jo) < 1e-12
+    for n, ref in _state_fields(wl, st).items():
+        assert rel(f[n], ref) < 1e-12, n
+    assert rel(dJ, so) < 1e-12
+
+
+def test_unsteady_duct_gradient_fp32_within_tolerance(duct_gradient):
+    say("[gpu] 3D unsteady duct 18x10x12, 60 steps, fp32")
+    wl, Jo, so, st = duct_gradient
+    J, dJ, f, _ = _gpu_gradient(wl, "fp32")
+    assert abs(J - Jo) / abs(Jo) < 1e-4
+    assert rel(f["ux"], _state_fields(wl, st)["ux"]) < 1e-5
+    assert rel(dJ, so) < 1e-3
+
+
+def _budget_for(wl, prec, K):
+    """A budget that forces checkpointing with an interval near K."""
+    r = 8 if prec == "fp64" else 4
+    N = wl.nx * wl.ny * wl.nz
+    full = lks.LKS(wl, precision=prec, bind=False)
+    base = full.workspace_size() - full.memory_report()["ckpt_bytes"]
+    n = wl.n_fwd
+    traj = (n // K + 1) * 5 * N * r + (K - 1) * 4 * N * r
+    return base + traj + 4096
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_checkpointed_sweep_equals_store_all_3d(prec):
+    say(f"[gpu] 3D checkpoint replay vs store-all {prec}")
+    wl = _duct(n=45, seed=2)
+    J0, d0, _, c0 = _gpu_gradient(wl, prec)
+    assert c0.memory_report()["K"] == 45
+    J1, d1, _, c1 = _gpu_gradient(wl, prec, _budget_for(wl, prec, 7))
+    assert 1 < c1.memory_report()["K"] < 45
+    assert J0 == J1
+    assert np.array_equal(d0, d1)
+
+
+def test_full_size_duct_single_steps_match_oracle():
+    """256x128x128 heated-block duct: one forward and one adjoint step from a
+    smooth random state, compared with the oracle node for node."""
+    say("[gpu] 3D full size 256x128x128 single steps fp32")
+    wl = _steady(W.heated_block_duct())
+    rng = np.random.default_rng(0)
+    s = _random_state(wl, rng, smooth=True)
+    pb = O3.Problem3(wl)
+    N = pb.N
+    a, da, B, dB = O3.coefficients(pb, wl.gamma)
+    want = _state_fields(wl, O3.lks_step(pb, a, B, 1.0, s))
+    ctx = lks.LKS(wl, precision="fp32", device=DEV)
+    g = T(wl.gamma)
+    ctx.forward(g, 0)
+    _write_state(ctx, wl, s)
+    ctx.advance(g, 1)
+    for n, ref in want.items():
+        assert rel(ctx.read(n).cpu().numpy(), ref) < 2e-5, n
+    adj1 = [1e-2 * W.gaussian_random_field((wl.nz, wl.ny, wl.nx), 3.0, 20 + f).ravel()
+            for f in range(14)]
+    V1, Th1 = O3.adjoint_equilibrium(pb, B, s.u, adj1)
+    adj0 = O3.alks_step(pb, a, B, s, s, adj1, 0.0, 0.5)
+    V0, Th0 = O3.adjoint_equilibrium(pb, B, s.u, adj0)
+    ctx2 = lks.LKS(wl, precision="fp32", device=DEV)
+    ctx2.forward(g, 0)
+    _write_state(ctx2, wl, s)
+    ctx2.write("adj_rho", T(adj1[0]))
+    for c, n in enumerate(("adj_vx", "adj_vy", "adj_vz")):
+        ctx2.write(n, T(V1[c * N:(c + 1) * N]))
+    ctx2.write("adj_theta", T(Th1))
+    ctx2.adjoint_advance(0.5, 1, None)
+    for n, ref in (("adj_rho", adj0[0]), ("adj_vx", V0[:N]), ("adj_vz", V0[2 * N:]),
+                   ("adj_theta", Th0)):
+        assert rel(ctx2.read(n).cpu().numpy(), ref) < 3e-5, n
+
+
+def test_full_size_duct_checkpointed_gradient():
+    """The full-size duct over 120 steps with a checkpoint budget: the
+    replayed sweep equals the stored one bit for bit, the state stays finite
+    and the objective is positive."""
+    say("[gpu] 3D full size 256x128x128, 120 steps, checkpointed fp32")
+    wl = W.heated_block_duct(n_steps=120)
+    # information moves at most one node per step: in 120 steps neither the
+    # inflow nor the heat of the block reaches the outlet plane, so probe the
+    # plane x = 50, between the inlet and the block, instead
+    wl.mask = wl.mask.copy()
+    wl.mask[:, :, wl.nx - 2] &= ~np.uint8(W.TAG_PROBE)
+    wl.mask[1:-1, 1:-1, 50] |= W.TAG_PROBE
+    J0, d0, f0, c0 = _gpu_gradient(wl, "fp32")
+    J1, d1, f1, c1 = _gpu_gradient(wl, "fp32", _budget_for(wl, "fp32", 11))
+    assert 1 < c1.memory_report()["K"] < 120
+    assert J0 == J1 and J0 > 0
+    assert np.array_equal(d0, d1)
+    assert np.all(np.isfinite(f0["ux"])) and np.all(np.isfinite(d0))
+    assert np.abs(d0).max() > 0
+    del c0, c1
+    torch.cuda.empty_cache()
+
+
+def test_autograd_through_3d_solver():
+    say("[gpu] 3D autograd 18x10x12")
+    wl = _duct(n=30, seed=4)
+    solver = lks.LKS(wl, precision="fp64", device=DEV)
+    gm = torch.tensor(wl.gamma.reshape(-1), dtype=torch.float64, device=DEV, requires_grad=True)
+    J = autograd.objective(gm, solver)
+    (2.0 * J).backward()
+    Jo, so, _, _ = O3.gradient(wl)
+    assert abs(J.item() - Jo) / abs(Jo) < 1e-12
+    assert rel(gm.grad.cpu().numpy(), 2.0 * so.ravel()) < 1e-12
