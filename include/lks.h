@@ -203,9 +203,10 @@ lks_status lks_read_field(lks_ctx *ctx, int which, double *dev_out);
 lks_status lks_write_field(lks_ctx *ctx, int which, const double *dev_in);
 
 /* Tile autotuner: times `steps` forward and `steps` adjoint steps of the
- * design gamma_dev for each tile height the kernels provide (64 x 4 and
- * 64 x 8 nodes) on this context's stream, keeps the fastest and reports it in
- * *tile_rows. Synchronises; the forward and adjoint states are discarded
+ * design gamma_dev for each launch shape the kernels provide (tiles of
+ * 64 x 4 and 64 x 8 nodes; one or, where supported, two steps per launch)
+ * on this context's stream, keeps the fastest and reports its tile height in
+ * *tile_rows (lks_launch_shape gives the whole shape). Synchronises; the forward and adjoint states are discarded
  * (run lks_forward afterwards). D2Q9 only (LKS_E_UNSUPPORTED for D3Q19,
  * whose node-parallel kernels have no tile shape). */
 lks_status lks_autotune(lks_ctx *ctx, const double *gamma_dev, int steps, int *tile_rows);
@@ -213,6 +214,16 @@ lks_status lks_autotune(lks_ctx *ctx, const double *gamma_dev, int steps, int *t
 /* Set the tile height (4 or 8 rows of 64 nodes) explicitly; results do not
  * depend on it. Discards the forward and adjoint states. D2Q9 only. */
 lks_status lks_set_tile_rows(lks_ctx *ctx, int tile_rows);
+
+/* Time steps per kernel launch of the steady sweeps (lks_advance and the
+ * steady lks_forward, alks_backward, alks_advance): 1, or 2 for FP32
+ * non-thermal D2Q9 problems (LKS_E_UNSUPPORTED otherwise). With 2, each
+ * launch loads its tile with a 4-node halo and runs two steps, the first
+ * on the tile and a 2-node halo kept in LDS; results are the same bits. */
+lks_status lks_set_steps_per_launch(lks_ctx *ctx, int steps);
+
+/* The launch shape in use: tile height (0 for D3Q19) and steps per launch. */
+lks_status lks_launch_shape(const lks_ctx *ctx, int *tile_rows, int *steps_per_launch);
 
 /* Memory plan: bytes of checkpoint + replay storage, bytes of the rest of
  * the workspace, and the checkpoint interval K (N when the whole trajectory

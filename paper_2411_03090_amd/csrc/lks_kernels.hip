@@ -160,6 +160,12 @@ __device__ inline bool block_tile(const Geo& g, int* x0, int* x1, int* y0, int* 
   return true;
 }
 
+// A tile whose 2-node halo stays inside the domain and whose 1-node halo
+// holds no boundary-ring node: no wrap, no ring rule, central differences.
+__device__ inline bool interior_tile(const Geo& g, int x0, int x1, int y0, int y1) {
+  return x0 >= 2 && y0 >= 2 && x1 <= g.nx - 2 && y1 <= g.ny - 2;
+}
+
 // Visit the positions (lx, ly) of a w x h rectangle, 256 threads, flat order.
 template <bool FULL, int WC, int HC, typename F>
 __device__ inline void rect_loop(int w, int h, F&& f) {
@@ -176,16 +182,19 @@ __device__ inline void rect_loop(int w, int h, F&& f) {
   }
 }
 
-// Load NF fields of the tile plus a 2-node halo into LDS (zeros outside a
-// non-periodic domain). For full tiles every load is issued before any is
-// used so that their latencies overlap.
-template <typename R, bool FULL, int TY, int NF>
-__device__ inline void load_halo2(const Geo& g, int x0, int y0, int tw, int th,
-                                  const R* const (&src)[NF], R* const (&dst)[NF]) {
-  using TL = Tile<TY>;
+// Load NF fields of the tile plus an H-node halo into LDS arrays of pitch P
+// (zeros outside a non-periodic domain). For full tiles (TX x TY) every load
+// is issued before any is used so that their latencies overlap.
+template <typename R, bool FULL, int TY, int H, int P, int NF, bool INT = false>
+__device__ inline void load_halo(const Geo& g, int x0, int y0, int tw, int th,
+                                 const R* const (&src)[NF], R* const (&dst)[NF]) {
   auto node = [&](int lx, int ly, int* k) {
-    int i = x0 + lx - 2, j = y0 + ly - 2;
+    int i = x0 + lx - H, j = y0 + ly - H;
     bool in = true;
+    if constexpr (INT) {
+      *k = j * g.nx + i;
+      return true;
+    }
     if (g.periodic) {
       i = wrapi(i, g.nx);
       j = wrapi(j, g.ny);
@@ -196,7 +205,8 @@ __device__ inline void load_halo2(const Geo& g, int x0, int y0, int tw, int th,
     return in;
   };
   if constexpr (FULL) {
-    constexpr int WC = TX + 4, HC = TY + 4, n = WC * HC, NP = (n + NTHREADS - 1) / NTHREADS;
+    constexpr int WC = TX + 2 * H, HC = TY + 2 * H, n = WC * HC;
+    constexpr int NP = (n + NTHREADS - 1) / NTHREADS;
     int kk[NP], pp[NP];
     bool ok[NP];
 #pragma unroll
@@ -205,7 +215,7 @@ __device__ inline void load_halo2(const Geo& g, int x0, int y0, int tw, int th,
       const int lx = p % WC, ly = p / WC;
       ok[e] = node(lx, ly, &kk[e]) && p < n;
       if (p >= n) kk[e] = 0;
-      pp[e] = p < n ? ly * TL::W2 + lx : -1;
+      pp[e] = p < n ? ly * P + lx : -1;
     }
     R v[NF][NP];
 #pragma unroll
@@ -218,10 +228,10 @@ __device__ inline void load_halo2(const Geo& g, int x0, int y0, int tw, int th,
 #pragma unroll
         for (int f = 0; f < NF; ++f) dst[f][pp[e]] = ok[e] ? v[f][e] : R(0);
   } else {
-    rect_loop<false, 1, 1>(tw + 4, th + 4, [&](int lx, int ly) {
+    rect_loop<false, 1, 1>(tw + 2 * H, th + 2 * H, [&](int lx, int ly) {
       int k;
       const bool in = node(lx, ly, &k);
-      const int p = ly * TL::W2 + lx;
+      const int p = ly * P + lx;
 #pragma unroll
       for (int f = 0; f < NF; ++f) dst[f][p] = in ? src[f][k] : R(0);
     });
@@ -236,6 +246,15 @@ __device__ inline R lds_d(const R* s, int p, int step, int c, int n, int periodi
   if (periodic || (c > 0 && c < n - 1)) return R(0.5) * (s[p + step] - s[p - step]);
   if (c == 0) return R(0.5) * (R(-3) * s[p] + R(4) * s[p + step] - s[p + 2 * step]);
   return R(0.5) * (R(3) * s[p] - R(4) * s[p - step] + s[p - 2 * step]);
+}
+
+// lds_d for a position whose tile is interior (INT: the tile and a 2-node
+// halo lie off the boundary ring and need no wrap), where the central
+// difference always applies
+template <bool INT, typename R>
+__device__ inline R lds_dx(const R* s, int p, int step, int c, int n, int periodic) {
+  if constexpr (INT) return R(0.5) * (s[p + step] - s[p - step]);
+  else return lds_d(s, p, step, c, n, periodic);
 }
 
 // ---------------------------------------------------------------------------
@@ -264,11 +283,128 @@ struct FwdLds {
   double red[NTHREADS / 64];
 };
 
-template <typename R, bool TH, int TY, bool FULL>
+// Stage A1 at one node (i, j): the post-collision values f'_i (and g_i)
+// from the raw fields in LDS (pitch PR, position pr), stored at position pf
+// of the post-collision arrays f and gq (each direction SF values apart).
+template <typename R, bool TH, int PR, int SF, bool INT = false>
+__device__ inline void fwd_collide(const Geo& g, R A, const R* ld, const R* lu, const R* lv,
+                                   const R* lT, const R* lB, int pr, int i, int j, R* f, R* gq,
+                                   int pf) {
+  const R d = ld[pr], ux = lu[pr], uy = lv[pr];
+  const R uxx = lds_dx<INT>(lu, pr, 1, i, g.nx, g.periodic);
+  const R uxy = lds_dx<INT>(lu, pr, PR, j, g.ny, g.periodic);
+  const R uyx = lds_dx<INT>(lv, pr, 1, i, g.nx, g.periodic);
+  const R uyy = lds_dx<INT>(lv, pr, PR, j, g.ny, g.periodic);
+  // f'_i = w_i [P + 3 c.u + cx^2 Xx + cy^2 Yy + cx cy Xy]
+  const R P = d - R(1.5) * (ux * ux + uy * uy);
+  const R Xx = R(4.5) * ux * ux + R(2) * A * uxx;
+  const R Yy = R(4.5) * uy * uy + R(2) * A * uyy;
+  const R Xy = R(9) * ux * uy + R(2) * A * (uxy + uyx);
+  const R u3x = R(3) * ux, u3y = R(3) * uy;
+  const R w0 = R(4.0 / 9), w1 = R(1.0 / 9), w5 = R(1.0 / 36);
+  const R diag = P + Xx + Yy;
+  f[0 * SF + pf] = w0 * P;
+  f[1 * SF + pf] = w1 * (P + u3x + Xx);
+  f[2 * SF + pf] = w1 * (P + u3y + Yy);
+  f[3 * SF + pf] = w1 * (P - u3x + Xx);
+  f[4 * SF + pf] = w1 * (P - u3y + Yy);
+  f[5 * SF + pf] = w5 * (diag + u3x + u3y + Xy);
+  f[6 * SF + pf] = w5 * (diag - u3x + u3y - Xy);
+  f[7 * SF + pf] = w5 * (diag - u3x - u3y + Xy);
+  f[8 * SF + pf] = w5 * (diag + u3x - u3y - Xy);
+  if constexpr (TH) {
+    const R T = lT[pr];
+    const R Bk = lB[pr];
+    const R Wx = R(3) * T * ux + Bk * lds_dx<INT>(lT, pr, 1, i, g.nx, g.periodic);
+    const R Wy = R(3) * T * uy + Bk * lds_dx<INT>(lT, pr, PR, j, g.ny, g.periodic);
+    gq[0 * SF + pf] = w0 * T;
+    gq[1 * SF + pf] = w1 * (T + Wx);
+    gq[2 * SF + pf] = w1 * (T + Wy);
+    gq[3 * SF + pf] = w1 * (T - Wx);
+    gq[4 * SF + pf] = w1 * (T - Wy);
+    gq[5 * SF + pf] = w5 * (T + Wx + Wy);
+    gq[6 * SF + pf] = w5 * (T - Wx + Wy);
+    gq[7 * SF + pf] = w5 * (T - Wx - Wy);
+    gq[8 * SF + pf] = w5 * (T + Wx - Wy);
+  }
+}
+
+// Stage B at one node (i, j), not a corner: pull f'_i(x - c_i) from the
+// post-collision arrays (pitch PF, position pf) and form the new state;
+// ring nodes complete it from the moment balance. `level` is the new level
+// (inflow factor of velocity nodes).
+template <typename R, bool TH, int PF, int SF, bool INT = false>
+__device__ inline void fwd_pull(const Geo& g, const FwdArgs<R>& a, const R* lf, const R* lg,
+                                int pf, int i, int j, int k, int m, R s, int level, R& dn,
+                                R& uxn, R& uyn, R& Tn) {
+  const int fc = (INT || g.periodic) ? FLOW_INTERIOR : (m & 3);
+  R f[9], gg[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) f[q] = lf[q * SF + pf - CX[q] - CY[q] * PF];
+  if constexpr (TH) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) gg[q] = lg[q * SF + pf - CX[q] - CY[q] * PF];
+  }
+  Tn = R(0);
+  if (fc == FLOW_INTERIOR) {
+    dn = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    const R Ux = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+    const R Uy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+    uxn = Ux * s;
+    uyn = Uy * s;
+    if constexpr (TH)
+      Tn = gg[0] + gg[1] + gg[2] + gg[3] + gg[4] + gg[5] + gg[6] + gg[7] + gg[8];
+    return;
+  }
+  const int nx_ = (i == 0) ? -1 : (i == g.nx - 1 ? 1 : 0);
+  const int ny_ = nx_ != 0 ? 0 : (j == 0 ? -1 : 1);
+  R S0 = R(0), Sp = R(0), S0g = R(0), Spg = R(0);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int cn = CX[q] * nx_ + CY[q] * ny_;
+    if (cn == 0) {
+      S0 += f[q];
+      if constexpr (TH) S0g += gg[q];
+    } else if (cn > 0) {
+      Sp += f[q];
+      if constexpr (TH) Spg += gg[q];
+    }
+  }
+  R un;
+  if (fc == FLOW_VELOCITY) {
+    const double fac = a.ufac[level];
+    uxn = R(double(a.ubx[k]) * fac);
+    uyn = R(double(a.uby[k]) * fac);
+    un = uxn * R(nx_) + uyn * R(ny_);
+    dn = S0 + R(2) * Sp - un;
+  } else {
+    const R dout = R(g.drho_out);
+    dn = dout;
+    un = S0 + R(2) * Sp - dout;
+    uxn = un * R(nx_);
+    uyn = un * R(ny_);
+  }
+  if constexpr (TH) {
+    if (((m >> 2) & 3) == THERM_DIRICHLET) Tn = a.Tb[k];
+    else Tn = (S0g + R(2) * Spg) / (R(1) + un);
+  }
+}
+
+// corners take density and temperature from their y-neighbour at the new
+// level: the neighbour (i, 1) or (i, ny-2) of a corner column hands its
+// values to `put` for the corner row
+template <typename Put>
+__device__ inline void corner_from(const Geo& g, int i, int j, Put&& put) {
+  if (g.periodic || (i != 0 && i != g.nx - 1)) return;
+  if (j == 1) put(0);
+  if (j == g.ny - 2) put(g.ny - 1);
+}
+
+template <typename R, bool TH, int TY, bool FULL, bool INT>
 __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L, int x0, int y0,
                          int tw, int th, int tile) {
   using TL = Tile<TY>;
-  constexpr int W2 = TL::W2, W1 = TL::W1;
+  constexpr int W2 = TL::W2, W1 = TL::W1, SF = TL::W1 * TL::H1;
   const R A = R(g.A);
   if constexpr (FULL) {
     tw = TX;
@@ -291,61 +427,26 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
   if constexpr (TH) {
     const R* src[5] = {a.d0, a.ux0, a.uy0, a.T0, a.B};
     R* dst[5] = {L.d, L.u, L.v, L.T, L.B};
-    load_halo2<R, FULL, TY, 5>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 2, W2, 5, INT>(g, x0, y0, tw, th, src, dst);
   } else {
     const R* src[3] = {a.d0, a.ux0, a.uy0};
     R* dst[3] = {L.d, L.u, L.v};
-    load_halo2<R, FULL, TY, 3>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 2, W2, 3, INT>(g, x0, y0, tw, th, src, dst);
   }
   __syncthreads();
 
   rect_loop<FULL, TX + 2, TY + 2>(tw + 2, th + 2, [&](int lx, int ly) {
     int i = x0 + lx - 1, j = y0 + ly - 1;
-    if (g.periodic) {
-      i = wrapi(i, g.nx);
-      j = wrapi(j, g.ny);
-    } else if (i < 0 || j < 0 || i >= g.nx || j >= g.ny) {
-      return;
+    if constexpr (!INT) {
+      if (g.periodic) {
+        i = wrapi(i, g.nx);
+        j = wrapi(j, g.ny);
+      } else if (i < 0 || j < 0 || i >= g.nx || j >= g.ny) {
+        return;
+      }
     }
-    const int p2 = (ly + 1) * W2 + lx + 1;
-    const int p1 = ly * W1 + lx;
-    const R d = L.d[p2], ux = L.u[p2], uy = L.v[p2];
-    const R uxx = lds_d(L.u, p2, 1, i, g.nx, g.periodic);
-    const R uxy = lds_d(L.u, p2, W2, j, g.ny, g.periodic);
-    const R uyx = lds_d(L.v, p2, 1, i, g.nx, g.periodic);
-    const R uyy = lds_d(L.v, p2, W2, j, g.ny, g.periodic);
-    // f'_i = w_i [P + 3 c.u + cx^2 Xx + cy^2 Yy + cx cy Xy]
-    const R P = d - R(1.5) * (ux * ux + uy * uy);
-    const R Xx = R(4.5) * ux * ux + R(2) * A * uxx;
-    const R Yy = R(4.5) * uy * uy + R(2) * A * uyy;
-    const R Xy = R(9) * ux * uy + R(2) * A * (uxy + uyx);
-    const R u3x = R(3) * ux, u3y = R(3) * uy;
-    const R w0 = R(4.0 / 9), w1 = R(1.0 / 9), w5 = R(1.0 / 36);
-    const R diag = P + Xx + Yy;
-    L.f[0][p1] = w0 * P;
-    L.f[1][p1] = w1 * (P + u3x + Xx);
-    L.f[2][p1] = w1 * (P + u3y + Yy);
-    L.f[3][p1] = w1 * (P - u3x + Xx);
-    L.f[4][p1] = w1 * (P - u3y + Yy);
-    L.f[5][p1] = w5 * (diag + u3x + u3y + Xy);
-    L.f[6][p1] = w5 * (diag - u3x + u3y - Xy);
-    L.f[7][p1] = w5 * (diag - u3x - u3y + Xy);
-    L.f[8][p1] = w5 * (diag + u3x - u3y - Xy);
-    if constexpr (TH) {
-      const R T = L.T[p2];
-      const R Bk = L.B[p2];
-      const R Wx = R(3) * T * ux + Bk * lds_d(L.T, p2, 1, i, g.nx, g.periodic);
-      const R Wy = R(3) * T * uy + Bk * lds_d(L.T, p2, W2, j, g.ny, g.periodic);
-      L.gq[0][p1] = w0 * T;
-      L.gq[1][p1] = w1 * (T + Wx);
-      L.gq[2][p1] = w1 * (T + Wy);
-      L.gq[3][p1] = w1 * (T - Wx);
-      L.gq[4][p1] = w1 * (T - Wy);
-      L.gq[5][p1] = w5 * (T + Wx + Wy);
-      L.gq[6][p1] = w5 * (T - Wx + Wy);
-      L.gq[7][p1] = w5 * (T - Wx - Wy);
-      L.gq[8][p1] = w5 * (T + Wx - Wy);
-    }
+    fwd_collide<R, TH, W2, SF, INT>(g, A, L.d, L.u, L.v, L.T, L.B, (ly + 1) * W2 + lx + 1, i, j,
+                               &L.f[0][0], &L.gq[0][0], ly * W1 + lx);
   });
   __syncthreads();
 
@@ -354,7 +455,6 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
   rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
     const int i = x0 + lx, j = y0 + ly;
     const int k = j * g.nx + i;
-    const int p1 = (ly + 1) * W1 + lx + 1;
     int m;
     R s;
     if constexpr (FULL) {
@@ -365,73 +465,18 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
       m = a.mask[k];
       s = a.inv1pa[k];
     }
-    const int fc = g.periodic ? FLOW_INTERIOR : (m & 3);
-    if (fc == FLOW_CORNER) return;
-    R f[9], gg[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) f[q] = L.f[q][p1 - CX[q] - CY[q] * W1];
-    if constexpr (TH) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) gg[q] = L.gq[q][p1 - CX[q] - CY[q] * W1];
-    }
-    R dn, uxn, uyn, Tn = R(0);
-    if (fc == FLOW_INTERIOR) {
-      dn = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-      const R Ux = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-      const R Uy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-      uxn = Ux * s;
-      uyn = Uy * s;
-      if constexpr (TH)
-        Tn = gg[0] + gg[1] + gg[2] + gg[3] + gg[4] + gg[5] + gg[6] + gg[7] + gg[8];
-    } else {
-      const int nx_ = (i == 0) ? -1 : (i == g.nx - 1 ? 1 : 0);
-      const int ny_ = nx_ != 0 ? 0 : (j == 0 ? -1 : 1);
-      R S0 = R(0), Sp = R(0), S0g = R(0), Spg = R(0);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const int cn = CX[q] * nx_ + CY[q] * ny_;
-        if (cn == 0) {
-          S0 += f[q];
-          if constexpr (TH) S0g += gg[q];
-        } else if (cn > 0) {
-          Sp += f[q];
-          if constexpr (TH) Spg += gg[q];
-        }
-      }
-      R un;
-      if (fc == FLOW_VELOCITY) {
-        const double fac = a.ufac[a.level_out];
-        uxn = R(double(a.ubx[k]) * fac);
-        uyn = R(double(a.uby[k]) * fac);
-        un = uxn * R(nx_) + uyn * R(ny_);
-        dn = S0 + R(2) * Sp - un;
-      } else {
-        const R dout = R(g.drho_out);
-        dn = dout;
-        un = S0 + R(2) * Sp - dout;
-        uxn = un * R(nx_);
-        uyn = un * R(ny_);
-      }
-      if constexpr (TH) {
-        if (((m >> 2) & 3) == THERM_DIRICHLET) Tn = a.Tb[k];
-        else Tn = (S0g + R(2) * Spg) / (R(1) + un);
-      }
-      if (i == 0 || i == g.nx - 1) {
-        if (j == 1) {
-          a.d1[i] = dn;
-          a.ux1[i] = R(0);
-          a.uy1[i] = R(0);
-          if constexpr (TH) a.T1[i] = Tn;
-        }
-        if (j == g.ny - 2) {
-          const int kc = (g.ny - 1) * g.nx + i;
-          a.d1[kc] = dn;
-          a.ux1[kc] = R(0);
-          a.uy1[kc] = R(0);
-          if constexpr (TH) a.T1[kc] = Tn;
-        }
-      }
-    }
+    if (!INT && !g.periodic && (m & 3) == FLOW_CORNER) return;
+    R dn, uxn, uyn, Tn;
+    fwd_pull<R, TH, W1, SF, INT>(g, a, &L.f[0][0], &L.gq[0][0], (ly + 1) * W1 + lx + 1, i, j, k,
+                                 m, s, a.level_out, dn, uxn, uyn, Tn);
+    if constexpr (!INT)
+      corner_from(g, i, j, [&](int jc) {
+        const int kc = jc * g.nx + i;
+        a.d1[kc] = dn;
+        a.ux1[kc] = R(0);
+        a.uy1[kc] = R(0);
+        if constexpr (TH) a.T1[kc] = Tn;
+      });
     a.d1[k] = dn;
     a.ux1[k] = uxn;
     a.uy1[k] = uyn;
@@ -457,8 +502,12 @@ __global__ __launch_bounds__(NTHREADS) void lks_step_kernel(Geo g, FwdArgs<R> a)
   int x0, x1, y0, y1, tile;
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
   const int tw = x1 - x0, th = y1 - y0;
-  if (tw == TX && th == TY) lks_tile<R, TH, TY, true>(g, a, L, x0, y0, tw, th, tile);
-  else lks_tile<R, TH, TY, false>(g, a, L, x0, y0, tw, th, tile);
+  if (tw != TX || th != TY)
+    lks_tile<R, TH, TY, false, false>(g, a, L, x0, y0, tw, th, tile);
+  else if (interior_tile(g, x0, x1, y0, y1))
+    lks_tile<R, TH, TY, true, true>(g, a, L, x0, y0, tw, th, tile);
+  else
+    lks_tile<R, TH, TY, true, false>(g, a, L, x0, y0, tw, th, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -595,12 +644,148 @@ struct AdjLds {
   R m[NM][TL::W1 * TL::H1];
 };
 
-template <typename R, bool TH, int TY, bool FULL>
+// Stage A1 at an interior node: weighted pull of the level-n+1 equilibria
+// f~_i^eq = rho~ + c_i.V and g~_i^eq = Theta from x + c_i (raw coefficients
+// in LDS, pitch PR, position pr); returns the moments rho~, U~, s~ (xx, xy,
+// yy), T~, q~.
+template <typename R, bool TH, int PR>
+__device__ inline void adj_pull(const R* lr, const R* lvx, const R* lvy, const R* lth, int pr,
+                                R mom[9]) {
+  R r = R(0), Ux = R(0), Uy = R(0), sxx = R(0), sxy = R(0), syy = R(0);
+  R Tt = R(0), qx = R(0), qy = R(0);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int p = pr + CX[q] + CY[q] * PR;
+    const R E = lr[p] + R(CX[q]) * lvx[p] + R(CY[q]) * lvy[p];
+    const R wE = R(WD[q]) * E;
+    r += wE;
+    if (CX[q]) Ux += R(CX[q]) * wE;
+    if (CY[q]) Uy += R(CY[q]) * wE;
+    if (CX[q]) sxx += wE;
+    if (CX[q] * CY[q]) sxy += R(CX[q] * CY[q]) * wE;
+    if (CY[q]) syy += wE;
+    if constexpr (TH) {
+      const R wT = R(WD[q]) * lth[p];
+      Tt += wT;
+      if (CX[q]) qx += R(CX[q]) * wT;
+      if (CY[q]) qy += R(CY[q]) * wT;
+    }
+  }
+  mom[0] = r;
+  mom[1] = Ux;
+  mom[2] = Uy;
+  mom[3] = sxx;
+  mom[4] = sxy;
+  mom[5] = syy;
+  mom[6] = Tt;
+  mom[7] = qx;
+  mom[8] = qy;
+}
+
+// Stage A1 at node (i, j) of the raw region: the moments of the pulled and,
+// on ring nodes, completed adjoint populations, stored at position pm of the
+// moment arrays (each field SM values apart). Corners are left to the
+// caller.
+template <typename R, bool TH, int PR, int SM, bool INT = false>
+__device__ inline void adj_moments(const Geo& g, const AdjArgs<R>& a, const R* lr, const R* lvx,
+                                   const R* lvy, const R* lth, const R* lTn, int pr, int i,
+                                   int j, R* lm, int pm) {
+  constexpr int NM = TH ? 9 : 6;
+  const bool ring = !INT && !g.periodic && (i == 0 || j == 0 || i == g.nx - 1 || j == g.ny - 1);
+  R mom[9];
+  if (!ring) {
+    adj_pull<R, TH, PR>(lr, lvx, lvy, lth, pr, mom);
+  } else {
+    const bool corner = (i == 0 || i == g.nx - 1) && (j == 0 || j == g.ny - 1);
+    if (corner) return;
+    const int k = j * g.nx + i;
+    ring_moments<R, TH, PR>(g, a, lr, lvx, lvy, lth, lTn, pr, i, j, k, a.mask[k], mom);
+  }
+#pragma unroll
+  for (int f = 0; f < NM; ++f) lm[f * SM + pm] = mom[f];
+}
+
+// corners copy the moments of their y-neighbour; the region of moment
+// positions starts at node (rx0, ry0), pitch PM, and spans rw x rh nodes
+template <typename R, bool TH, int PM, int SM>
+__device__ inline void adj_corners(const Geo& g, R* lm, int rx0, int ry0, int rw, int rh) {
+  constexpr int NM = TH ? 9 : 6;
+  if (g.periodic || threadIdx.x >= 4) return;
+  const int ci = (threadIdx.x & 1) ? g.nx - 1 : 0;
+  const int cj = (threadIdx.x & 2) ? g.ny - 1 : 0;
+  if (ci < rx0 || ci >= rx0 + rw || cj < ry0 || cj >= ry0 + rh) return;
+  const int pm = (cj - ry0) * PM + (ci - rx0);
+  const int pn = pm + (cj == 0 ? PM : -PM);
+#pragma unroll
+  for (int f = 0; f < NM; ++f) lm[f * SM + pm] = lm[f * SM + pn];
+}
+
+// Stage B at node (i, j): the local terms of eq:albef_ex / eq:albeg_ex at
+// level n (seeds, 3 T q~ coupling, implicit Brinkman), then V and Theta of
+// the new level from the moments (pitch PM, position pm) and, when want_sens
+// is set, the sensitivity integrand 3 alpha' u.u~ - B' grad T . q~.
+template <typename R, bool TH, int PR, int PM, int SM, bool INT = false>
+__device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm, int pm,
+                                 const R* lTn, const R* lB, int pr, int i, int j, int k, R s,
+                                 R ux, R uy, R& r_out, R& Vx, R& Vy, R& Th, bool want_sens,
+                                 double& sens) {
+  const R A2 = R(2.0 * g.A);
+  const bool ring = !INT && !g.periodic && (i == 0 || j == 0 || i == g.nx - 1 || j == g.ny - 1);
+  const bool corner = ring && (i == 0 || i == g.nx - 1) && (j == 0 || j == g.ny - 1);
+  // local terms are those of the node whose moments were taken
+  const int kl = corner ? (j == 0 ? g.nx + i : (g.ny - 2) * g.nx + i) : k;
+  const int pl = corner ? pr + (j == 0 ? PR : -PR) : pr;
+  const R r = lm[0 * SM + pm];
+  R Ux = lm[1 * SM + pm], Uy = lm[2 * SM + pm];
+  const R sxx = lm[3 * SM + pm], sxy = lm[4 * SM + pm], syy = lm[5 * SM + pm];
+  R Tt = R(0), qx = R(0), qy = R(0);
+  if constexpr (TH) {
+    Tt = lm[6 * SM + pm];
+    qx = lm[7 * SM + pm];
+    qy = lm[8 * SM + pm];
+    const R Tl = lTn[pl];
+    Ux += Tl * qx;
+    Uy += Tl * qy;
+    if (a.seed_heat != 0.0 && (a.mask[kl] & TAG_PROBE)) {
+      Ux -= R(a.seed_heat / 3.0) * Tl;
+      Tt -= R(a.seed_heat) * a.ux[kl];
+    }
+  }
+  const R utx = Ux * s, uty = Uy * s;
+  auto ldx = [&](int f) { return lds_dx<INT>(lm + f * SM, pm, 1, i, g.nx, g.periodic); };
+  auto ldy = [&](int f) { return lds_dx<INT>(lm + f * SM, pm, PM, j, g.ny, g.periodic); };
+  const R dsx = ldx(3) + ldy(4);
+  const R dsy = ldx(4) + ldy(5);
+  r_out = r;
+  Vx = R(3) * utx + R(9) * (sxx * ux + sxy * uy) - R(3) * r * ux - A2 * dsx;
+  Vy = R(3) * uty + R(9) * (sxy * ux + syy * uy) - R(3) * r * uy - A2 * dsy;
+  if constexpr (TH) {
+    const R divq = ldx(7) + ldy(8);
+    const R Bk = lB[pr];
+    const R dBx = lds_dx<INT>(lB, pr, 1, i, g.nx, g.periodic);
+    const R dBy = lds_dx<INT>(lB, pr, PR, j, g.ny, g.periodic);
+    Th = Tt + R(3) * (qx * ux + qy * uy) - Bk * divq - (dBx * qx + dBy * qy);
+  }
+  sens = 0.0;
+  if (want_sens) {
+    double v = 0.0;
+    if (!ring) {
+      v = double(a.dA3[k]) * (double(ux) * double(utx) + double(uy) * double(uty));
+      if constexpr (TH) {
+        const double dTx = double(lds_dx<INT>(lTn, pr, 1, i, g.nx, g.periodic));
+        const double dTy = double(lds_dx<INT>(lTn, pr, PR, j, g.ny, g.periodic));
+        v -= double(a.dB[k]) * (dTx * double(qx) + dTy * double(qy));
+      }
+    }
+    sens = v;
+  }
+}
+
+template <typename R, bool TH, int TY, bool FULL, bool INT>
 __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& L, int x0,
                           int y0, int tw, int th) {
   using TL = Tile<TY>;
-  constexpr int W2 = TL::W2, W1 = TL::W1, NM = AdjLds<R, TH, TY>::NM;
-  const int x1 = x0 + tw, y1 = y0 + th;
+  constexpr int W2 = TL::W2, W1 = TL::W1, SM = TL::W1 * TL::H1;
   if constexpr (FULL) {
     tw = TX;
     th = TY;
@@ -622,91 +807,39 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
   if constexpr (TH) {
     const R* src[6] = {a.r0, a.vx0, a.vy0, a.th0, a.T, a.B};
     R* dst[6] = {L.r, L.vx, L.vy, L.th, L.Tn, L.B};
-    load_halo2<R, FULL, TY, 6>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 2, W2, 6, INT>(g, x0, y0, tw, th, src, dst);
   } else {
     const R* src[3] = {a.r0, a.vx0, a.vy0};
     R* dst[3] = {L.r, L.vx, L.vy};
-    load_halo2<R, FULL, TY, 3>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 2, W2, 3, INT>(g, x0, y0, tw, th, src, dst);
   }
   __syncthreads();
 
   rect_loop<FULL, TX + 2, TY + 2>(tw + 2, th + 2, [&](int lx, int ly) {
     int i = x0 + lx - 1, j = y0 + ly - 1;
-    if (g.periodic) {
-      i = wrapi(i, g.nx);
-      j = wrapi(j, g.ny);
-    } else if (i < 0 || j < 0 || i >= g.nx || j >= g.ny) {
-      return;
-    }
-    const int p2 = (ly + 1) * W2 + lx + 1;
-    const int p1 = ly * W1 + lx;
-    const bool ring = !g.periodic && (i == 0 || j == 0 || i == g.nx - 1 || j == g.ny - 1);
-    if (!ring) {
-      R r = R(0), Ux = R(0), Uy = R(0), sxx = R(0), sxy = R(0), syy = R(0);
-      R Tt = R(0), qx = R(0), qy = R(0);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const int p = p2 + CX[q] + CY[q] * W2;
-        const R E = L.r[p] + R(CX[q]) * L.vx[p] + R(CY[q]) * L.vy[p];
-        const R wE = R(WD[q]) * E;
-        r += wE;
-        if (CX[q]) Ux += R(CX[q]) * wE;
-        if (CY[q]) Uy += R(CY[q]) * wE;
-        if (CX[q]) sxx += wE;
-        if (CX[q] * CY[q]) sxy += R(CX[q] * CY[q]) * wE;
-        if (CY[q]) syy += wE;
-        if constexpr (TH) {
-          const R wT = R(WD[q]) * L.th[p];
-          Tt += wT;
-          if (CX[q]) qx += R(CX[q]) * wT;
-          if (CY[q]) qy += R(CY[q]) * wT;
-        }
+    if constexpr (!INT) {
+      if (g.periodic) {
+        i = wrapi(i, g.nx);
+        j = wrapi(j, g.ny);
+      } else if (i < 0 || j < 0 || i >= g.nx || j >= g.ny) {
+        return;
       }
-      L.m[0][p1] = r;
-      L.m[1][p1] = Ux;
-      L.m[2][p1] = Uy;
-      L.m[3][p1] = sxx;
-      L.m[4][p1] = sxy;
-      L.m[5][p1] = syy;
-      if constexpr (TH) {
-        L.m[6][p1] = Tt;
-        L.m[7][p1] = qx;
-        L.m[8][p1] = qy;
-      }
-    } else {
-      const bool corner = (i == 0 || i == g.nx - 1) && (j == 0 || j == g.ny - 1);
-      if (corner) return;
-      const int k = j * g.nx + i;
-      R mom[9];
-      ring_moments<R, TH, W2>(g, a, L.r, L.vx, L.vy, L.th, L.Tn, p2, i, j, k, a.mask[k], mom);
-#pragma unroll
-      for (int f = 0; f < NM; ++f) L.m[f][p1] = mom[f];
     }
+    adj_moments<R, TH, W2, SM, INT>(g, a, L.r, L.vx, L.vy, L.th, L.Tn, (ly + 1) * W2 + lx + 1, i, j,
+                               &L.m[0][0], ly * W1 + lx);
   });
   __syncthreads();
-  // corners copy the moments of their y-neighbour (both inside the tile)
-  const bool has_corner = !g.periodic && (x0 == 0 || x1 == g.nx) && (y0 == 0 || y1 == g.ny);
+  const bool has_corner =
+      !INT && !g.periodic && (x0 == 0 || x0 + tw == g.nx) && (y0 == 0 || y0 + th == g.ny);
   if (has_corner) {
-    if (threadIdx.x < 4) {
-      const int ci = (threadIdx.x & 1) ? g.nx - 1 : 0;
-      const int cj = (threadIdx.x & 2) ? g.ny - 1 : 0;
-      if (ci >= x0 && ci < x1 && cj >= y0 && cj < y1) {
-        const int p1 = (cj - y0 + 1) * W1 + (ci - x0 + 1);
-        const int pn = p1 + (cj == 0 ? W1 : -W1);
-#pragma unroll
-        for (int f = 0; f < NM; ++f) L.m[f][p1] = L.m[f][pn];
-      }
-    }
+    adj_corners<R, TH, W1, SM>(g, &L.m[0][0], x0 - 1, y0 - 1, tw + 2, th + 2);
     __syncthreads();
   }
 
-  const R A2 = R(2.0 * g.A);
   int e = 0;
   rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
     const int i = x0 + lx, j = y0 + ly;
     const int k = j * g.nx + i;
-    const int p1 = (ly + 1) * W1 + lx + 1;
-    const int p2 = (ly + 2) * W2 + lx + 2;
     R s, ux, uy;
     if constexpr (FULL) {
       s = spre[e];
@@ -718,57 +851,17 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
       ux = a.ux[k];
       uy = a.uy[k];
     }
-    const bool ring = !g.periodic && (i == 0 || j == 0 || i == g.nx - 1 || j == g.ny - 1);
-    const bool corner = ring && (i == 0 || i == g.nx - 1) && (j == 0 || j == g.ny - 1);
-    // local terms are those of the node whose moments were taken
-    const int kl = corner ? (j == 0 ? g.nx + i : (g.ny - 2) * g.nx + i) : k;
-    const int pl2 = corner ? p2 + (j == 0 ? W2 : -W2) : p2;
-    const R r = L.m[0][p1];
-    R Ux = L.m[1][p1], Uy = L.m[2][p1];
-    const R sxx = L.m[3][p1], sxy = L.m[4][p1], syy = L.m[5][p1];
-    R Tt = R(0), qx = R(0), qy = R(0);
-    if constexpr (TH) {
-      Tt = L.m[6][p1];
-      qx = L.m[7][p1];
-      qy = L.m[8][p1];
-      const R Tl = L.Tn[pl2];
-      Ux += Tl * qx;
-      Uy += Tl * qy;
-      if (a.seed_heat != 0.0 && (a.mask[kl] & TAG_PROBE)) {
-        Ux -= R(a.seed_heat / 3.0) * Tl;
-        Tt -= R(a.seed_heat) * a.ux[kl];
-      }
-    }
-    const R utx = Ux * s, uty = Uy * s;
-    auto ldx = [&](int f) { return lds_d(L.m[f], p1, 1, i, g.nx, g.periodic); };
-    auto ldy = [&](int f) { return lds_d(L.m[f], p1, W1, j, g.ny, g.periodic); };
-    const R dsx = ldx(3) + ldy(4);
-    const R dsy = ldx(4) + ldy(5);
-    const R Vx = R(3) * utx + R(9) * (sxx * ux + sxy * uy) - R(3) * r * ux - A2 * dsx;
-    const R Vy = R(3) * uty + R(9) * (sxy * ux + syy * uy) - R(3) * r * uy - A2 * dsy;
+    R r, Vx, Vy, Th;
+    double v;
+    adj_local<R, TH, W2, W1, SM, INT>(g, a, &L.m[0][0], (ly + 1) * W1 + lx + 1, L.Tn, L.B,
+                                 (ly + 2) * W2 + lx + 2, i, j, k, s, ux, uy, r, Vx, Vy, Th,
+                                 a.sens_mode != 0, v);
     a.r1[k] = r;
     a.vx1[k] = Vx;
     a.vy1[k] = Vy;
-    if constexpr (TH) {
-      const R divq = ldx(7) + ldy(8);
-      const R Bk = L.B[p2];
-      const R dBx = lds_d(L.B, p2, 1, i, g.nx, g.periodic);
-      const R dBy = lds_d(L.B, p2, W2, j, g.ny, g.periodic);
-      a.th1[k] = Tt + R(3) * (qx * ux + qy * uy) - Bk * divq - (dBx * qx + dBy * qy);
-    }
-    if (a.sens_mode) {
-      double v = 0.0;
-      if (!ring) {
-        v = double(a.dA3[k]) * (double(ux) * double(utx) + double(uy) * double(uty));
-        if constexpr (TH) {
-          const double dTx = double(lds_d(L.Tn, p2, 1, i, g.nx, g.periodic));
-          const double dTy = double(lds_d(L.Tn, p2, W2, j, g.ny, g.periodic));
-          v -= double(a.dB[k]) * (dTx * double(qx) + dTy * double(qy));
-        }
-      }
-      if (a.sens_mode == 1) a.sens[k] += v;
-      else a.sens[k] = v;
-    }
+    if constexpr (TH) a.th1[k] = Th;
+    if (a.sens_mode == 1) a.sens[k] += v;
+    else if (a.sens_mode == 2) a.sens[k] = v;
   });
 }
 
@@ -778,8 +871,282 @@ __global__ __launch_bounds__(NTHREADS) void alks_step_kernel(Geo g, AdjArgs<R> a
   int x0, x1, y0, y1, tile;
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
   const int tw = x1 - x0, th = y1 - y0;
-  if (tw == TX && th == TY) alks_tile<R, TH, TY, true>(g, a, L, x0, y0, tw, th);
-  else alks_tile<R, TH, TY, false>(g, a, L, x0, y0, tw, th);
+  if (tw != TX || th != TY)
+    alks_tile<R, TH, TY, false, false>(g, a, L, x0, y0, tw, th);
+  else if (interior_tile(g, x0, x1, y0, y1))
+    alks_tile<R, TH, TY, true, true>(g, a, L, x0, y0, tw, th);
+  else
+    alks_tile<R, TH, TY, true, false>(g, a, L, x0, y0, tw, th);
+}
+
+// ---------------------------------------------------------------------------
+// two steps per launch (steady sweeps)
+// ---------------------------------------------------------------------------
+// Temporal blocking: a block loads the raw state of its tile with a 4-node
+// halo once, runs the first step on the tile and a 2-node halo into LDS and
+// the second step on the tile into HBM. Each node's arithmetic is that of
+// the one-step kernel (the same stage functions), so two fused steps give
+// the same bits as two single steps; the launch count and the global
+// round trips per step halve, the stage work grows by the halo (about 1.3x
+// for 64 x 8 tiles).
+template <typename R, bool TH, int TY>
+struct Fwd2Lds {
+  static constexpr int WR = TX + 1 + 8, HR = TY + 1 + 8;  // raw state: tile + 4
+  static constexpr int WF = TX + 1 + 6, HF = TY + 1 + 6;  // post-collision: tile + 3
+  static constexpr int SF = WF * HF;
+  R d[WR * HR], u[WR * HR], v[WR * HR];
+  R T[TH ? WR * HR : 1], B[TH ? WR * HR : 1];
+  R f[9 * SF];
+  R gq[TH ? 9 * SF : 1];
+};
+
+// node of a region position: the region starts h nodes before the tile;
+// false outside a non-periodic domain
+__device__ inline bool region_node(const Geo& g, int x0, int y0, int h, int lx, int ly, int* i,
+                                   int* j) {
+  *i = x0 + lx - h;
+  *j = y0 + ly - h;
+  if (g.periodic) {
+    *i = wrapi(*i, g.nx);
+    *j = wrapi(*j, g.ny);
+    return true;
+  }
+  return *i >= 0 && *j >= 0 && *i < g.nx && *j < g.ny;
+}
+
+template <typename R, bool TH, int TY, bool FULL>
+__device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>& L, int x0,
+                          int y0, int tw, int th) {
+  using LD = Fwd2Lds<R, TH, TY>;
+  constexpr int WR = LD::WR, WF = LD::WF, SF = LD::SF;
+  const R A = R(g.A);
+  if constexpr (FULL) {
+    tw = TX;
+    th = TY;
+  }
+  constexpr int NB = FULL ? (TX * TY + NTHREADS - 1) / NTHREADS : 1;
+  int mpre[NB];
+  R spre[NB];
+  if constexpr (FULL) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int p = e * NTHREADS + int(threadIdx.x);
+      const int k = (y0 + p / TX) * g.nx + x0 + p % TX;
+      mpre[e] = a.mask[k];
+      spre[e] = a.inv1pa[k];
+    }
+  }
+  if constexpr (TH) {
+    const R* src[5] = {a.d0, a.ux0, a.uy0, a.T0, a.B};
+    R* dst[5] = {L.d, L.u, L.v, L.T, L.B};
+    load_halo<R, FULL, TY, 4, WR, 5>(g, x0, y0, tw, th, src, dst);
+  } else {
+    const R* src[3] = {a.d0, a.ux0, a.uy0};
+    R* dst[3] = {L.d, L.u, L.v};
+    load_halo<R, FULL, TY, 4, WR, 3>(g, x0, y0, tw, th, src, dst);
+  }
+  __syncthreads();
+  // first step: collide on the tile + 3, pull on the tile + 2 into LDS
+  rect_loop<FULL, TX + 6, TY + 6>(tw + 6, th + 6, [&](int lx, int ly) {
+    int i, j;
+    if (!region_node(g, x0, y0, 3, lx, ly, &i, &j)) return;
+    fwd_collide<R, TH, WR, SF>(g, A, L.d, L.u, L.v, L.T, L.B, (ly + 1) * WR + lx + 1, i, j, L.f,
+                               L.gq, ly * WF + lx);
+  });
+  __syncthreads();
+  rect_loop<FULL, TX + 4, TY + 4>(tw + 4, th + 4, [&](int lx, int ly) {
+    int i, j;
+    if (!region_node(g, x0, y0, 2, lx, ly, &i, &j)) return;
+    const int k = j * g.nx + i;
+    const int m = a.mask[k];
+    if (!g.periodic && (m & 3) == FLOW_CORNER) return;
+    R dn, uxn, uyn, Tn;
+    fwd_pull<R, TH, WF, SF>(g, a, L.f, L.gq, (ly + 1) * WF + lx + 1, i, j, k, m, a.inv1pa[k],
+                            a.level_mid, dn, uxn, uyn, Tn);
+    const int pr = (ly + 2) * WR + lx + 2;
+    corner_from(g, i, j, [&](int jc) {
+      const int pc = pr + (jc == 0 ? -WR : WR);
+      L.d[pc] = dn;
+      L.u[pc] = R(0);
+      L.v[pc] = R(0);
+      if constexpr (TH) L.T[pc] = Tn;
+    });
+    L.d[pr] = dn;
+    L.u[pr] = uxn;
+    L.v[pr] = uyn;
+    if constexpr (TH) L.T[pr] = Tn;
+  });
+  __syncthreads();
+  // second step: collide on the tile + 1, pull on the tile into HBM
+  rect_loop<FULL, TX + 2, TY + 2>(tw + 2, th + 2, [&](int lx, int ly) {
+    int i, j;
+    if (!region_node(g, x0, y0, 1, lx, ly, &i, &j)) return;
+    fwd_collide<R, TH, WR, SF>(g, A, L.d, L.u, L.v, L.T, L.B, (ly + 3) * WR + lx + 3, i, j, L.f,
+                               L.gq, (ly + 2) * WF + lx + 2);
+  });
+  __syncthreads();
+  int e = 0;
+  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
+    const int i = x0 + lx, j = y0 + ly;
+    const int k = j * g.nx + i;
+    int m;
+    R s;
+    if constexpr (FULL) {
+      m = mpre[e];
+      s = spre[e];
+      ++e;
+    } else {
+      m = a.mask[k];
+      s = a.inv1pa[k];
+    }
+    if (!g.periodic && (m & 3) == FLOW_CORNER) return;
+    R dn, uxn, uyn, Tn;
+    fwd_pull<R, TH, WF, SF>(g, a, L.f, L.gq, (ly + 3) * WF + lx + 3, i, j, k, m, s, a.level_out,
+                            dn, uxn, uyn, Tn);
+    corner_from(g, i, j, [&](int jc) {
+      const int kc = jc * g.nx + i;
+      a.d1[kc] = dn;
+      a.ux1[kc] = R(0);
+      a.uy1[kc] = R(0);
+      if constexpr (TH) a.T1[kc] = Tn;
+    });
+    a.d1[k] = dn;
+    a.ux1[k] = uxn;
+    a.uy1[k] = uyn;
+    if constexpr (TH) a.T1[k] = Tn;
+  });
+}
+
+template <typename R, bool TH, int TY>
+__global__ __launch_bounds__(NTHREADS) void lks_step2_kernel(Geo g, FwdArgs<R> a) {
+  __shared__ Fwd2Lds<R, TH, TY> L;
+  int x0, x1, y0, y1, tile;
+  if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
+  const int tw = x1 - x0, th = y1 - y0;
+  if (tw == TX && th == TY) lks_tile2<R, TH, TY, true>(g, a, L, x0, y0, tw, th);
+  else lks_tile2<R, TH, TY, false>(g, a, L, x0, y0, tw, th);
+}
+
+template <typename R, bool TH, int TY>
+struct Adj2Lds {
+  static constexpr int WR = TX + 1 + 8, HR = TY + 1 + 8;  // raw coefficients: tile + 4
+  static constexpr int WM = TX + 1 + 6, HM = TY + 1 + 6;  // moments: tile + 3
+  static constexpr int SM = WM * HM;
+  static constexpr int NM = TH ? 9 : 6;
+  R r[WR * HR], vx[WR * HR], vy[WR * HR];
+  R th[TH ? WR * HR : 1], Tn[TH ? WR * HR : 1], B[TH ? WR * HR : 1];
+  R m[NM * SM];
+};
+
+template <typename R, bool TH, int TY, bool FULL>
+__device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>& L, int x0,
+                           int y0, int tw, int th) {
+  using LD = Adj2Lds<R, TH, TY>;
+  constexpr int WR = LD::WR, WM = LD::WM, SM = LD::SM;
+  if constexpr (FULL) {
+    tw = TX;
+    th = TY;
+  }
+  constexpr int NB = FULL ? (TX * TY + NTHREADS - 1) / NTHREADS : 1;
+  R spre[NB], uxpre[NB], uypre[NB];
+  if constexpr (FULL) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int p = e * NTHREADS + int(threadIdx.x);
+      const int k = (y0 + p / TX) * g.nx + x0 + p % TX;
+      spre[e] = a.inv1pa[k];
+      uxpre[e] = a.ux[k];
+      uypre[e] = a.uy[k];
+    }
+  }
+  if constexpr (TH) {
+    const R* src[6] = {a.r0, a.vx0, a.vy0, a.th0, a.T, a.B};
+    R* dst[6] = {L.r, L.vx, L.vy, L.th, L.Tn, L.B};
+    load_halo<R, FULL, TY, 4, WR, 6>(g, x0, y0, tw, th, src, dst);
+  } else {
+    const R* src[3] = {a.r0, a.vx0, a.vy0};
+    R* dst[3] = {L.r, L.vx, L.vy};
+    load_halo<R, FULL, TY, 4, WR, 3>(g, x0, y0, tw, th, src, dst);
+  }
+  __syncthreads();
+  const bool near_corner = !g.periodic && (x0 <= 3 || x0 + tw + 3 >= g.nx) &&
+                           (y0 <= 3 || y0 + th + 3 >= g.ny);
+  // first step: moments on the tile + 3, new coefficients on the tile + 2
+  rect_loop<FULL, TX + 6, TY + 6>(tw + 6, th + 6, [&](int lx, int ly) {
+    int i, j;
+    if (!region_node(g, x0, y0, 3, lx, ly, &i, &j)) return;
+    adj_moments<R, TH, WR, SM>(g, a, L.r, L.vx, L.vy, L.th, L.Tn, (ly + 1) * WR + lx + 1, i, j,
+                               L.m, ly * WM + lx);
+  });
+  __syncthreads();
+  if (near_corner) {
+    adj_corners<R, TH, WM, SM>(g, L.m, x0 - 3, y0 - 3, tw + 6, th + 6);
+    __syncthreads();
+  }
+  rect_loop<FULL, TX + 4, TY + 4>(tw + 4, th + 4, [&](int lx, int ly) {
+    int i, j;
+    if (!region_node(g, x0, y0, 2, lx, ly, &i, &j)) return;
+    const int k = j * g.nx + i;
+    R r, Vx, Vy, Th;
+    double v;
+    const int pr = (ly + 2) * WR + lx + 2;
+    adj_local<R, TH, WR, WM, SM>(g, a, L.m, (ly + 1) * WM + lx + 1, L.Tn, L.B, pr, i, j, k,
+                                 a.inv1pa[k], a.ux[k], a.uy[k], r, Vx, Vy, Th, false, v);
+    L.r[pr] = r;
+    L.vx[pr] = Vx;
+    L.vy[pr] = Vy;
+    if constexpr (TH) L.th[pr] = Th;
+  });
+  __syncthreads();
+  // second step: moments on the tile + 1, new coefficients on the tile
+  rect_loop<FULL, TX + 2, TY + 2>(tw + 2, th + 2, [&](int lx, int ly) {
+    int i, j;
+    if (!region_node(g, x0, y0, 1, lx, ly, &i, &j)) return;
+    adj_moments<R, TH, WR, SM>(g, a, L.r, L.vx, L.vy, L.th, L.Tn, (ly + 3) * WR + lx + 3, i, j,
+                               L.m, (ly + 2) * WM + lx + 2);
+  });
+  __syncthreads();
+  if (near_corner) {
+    adj_corners<R, TH, WM, SM>(g, L.m + 2 * WM + 2, x0 - 1, y0 - 1, tw + 2, th + 2);
+    __syncthreads();
+  }
+  int e = 0;
+  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
+    const int i = x0 + lx, j = y0 + ly;
+    const int k = j * g.nx + i;
+    R s, ux, uy;
+    if constexpr (FULL) {
+      s = spre[e];
+      ux = uxpre[e];
+      uy = uypre[e];
+      ++e;
+    } else {
+      s = a.inv1pa[k];
+      ux = a.ux[k];
+      uy = a.uy[k];
+    }
+    R r, Vx, Vy, Th;
+    double v;
+    adj_local<R, TH, WR, WM, SM>(g, a, L.m, (ly + 3) * WM + lx + 3, L.Tn, L.B,
+                                 (ly + 4) * WR + lx + 4, i, j, k, s, ux, uy, r, Vx, Vy, Th,
+                                 a.sens_mode != 0, v);
+    a.r1[k] = r;
+    a.vx1[k] = Vx;
+    a.vy1[k] = Vy;
+    if constexpr (TH) a.th1[k] = Th;
+    if (a.sens_mode == 1) a.sens[k] += v;
+    else if (a.sens_mode == 2) a.sens[k] = v;
+  });
+}
+
+template <typename R, bool TH, int TY>
+__global__ __launch_bounds__(NTHREADS) void alks_step2_kernel(Geo g, AdjArgs<R> a) {
+  __shared__ Adj2Lds<R, TH, TY> L;
+  int x0, x1, y0, y1, tile;
+  if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
+  const int tw = x1 - x0, th = y1 - y0;
+  if (tw == TX && th == TY) alks_tile2<R, TH, TY, true>(g, a, L, x0, y0, tw, th);
+  else alks_tile2<R, TH, TY, false>(g, a, L, x0, y0, tw, th);
 }
 
 // ---------------------------------------------------------------------------
@@ -812,8 +1179,12 @@ __global__ __launch_bounds__(NTHREADS) void lks_step_batch_kernel(const BatchFwd
   int x0, x1, y0, y1;
   tile_box(g, lt, &x0, &x1, &y0, &y1);
   const int tw = x1 - x0, th = y1 - y0;
-  if (tw == TX && th == TY) lks_tile<R, TH, TY, true>(g, a, L, x0, y0, tw, th, lt);
-  else lks_tile<R, TH, TY, false>(g, a, L, x0, y0, tw, th, lt);
+  if (tw != TX || th != TY)
+    lks_tile<R, TH, TY, false, false>(g, a, L, x0, y0, tw, th, lt);
+  else if (interior_tile(g, x0, x1, y0, y1))
+    lks_tile<R, TH, TY, true, true>(g, a, L, x0, y0, tw, th, lt);
+  else
+    lks_tile<R, TH, TY, true, false>(g, a, L, x0, y0, tw, th, lt);
 }
 
 template <typename R, bool TH, int TY>
@@ -832,8 +1203,12 @@ __global__ __launch_bounds__(NTHREADS) void alks_step_batch_kernel(const BatchAd
   int x0, x1, y0, y1;
   tile_box(g, lt, &x0, &x1, &y0, &y1);
   const int tw = x1 - x0, th = y1 - y0;
-  if (tw == TX && th == TY) alks_tile<R, TH, TY, true>(g, a, L, x0, y0, tw, th);
-  else alks_tile<R, TH, TY, false>(g, a, L, x0, y0, tw, th);
+  if (tw != TX || th != TY)
+    alks_tile<R, TH, TY, false, false>(g, a, L, x0, y0, tw, th);
+  else if (interior_tile(g, x0, x1, y0, y1))
+    alks_tile<R, TH, TY, true, true>(g, a, L, x0, y0, tw, th);
+  else
+    alks_tile<R, TH, TY, true, false>(g, a, L, x0, y0, tw, th);
 }
 
 // pressure drop of every design on its current level: one block per design
@@ -971,6 +1346,16 @@ void launch_alks_step(const Geo& g, const AdjArgs<R>& a, hipStream_t s) {
     if (g.thermal) alks_step_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(g, a);
     else alks_step_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
   }
+}
+void launch_lks_step2(const Geo& g, const FwdArgs<float>& a, hipStream_t s) {
+  const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
+  if (g.ty == 8) lks_step2_kernel<float, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+  else lks_step2_kernel<float, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+}
+void launch_alks_step2(const Geo& g, const AdjArgs<float>& a, hipStream_t s) {
+  const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
+  if (g.ty == 8) alks_step2_kernel<float, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+  else alks_step2_kernel<float, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
 }
 template <typename R>
 void launch_pressure_drop(const Geo& g, const uint8_t* mask, const R* d, double* out,

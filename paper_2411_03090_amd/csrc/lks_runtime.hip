@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lks.h"
@@ -42,6 +43,7 @@ struct lks_ctx {
   std::vector<double> ubar, Tbar, ufac;
   int n_in = 0, n_out = 0;
   int dim = 2;         // 2: D2Q9, 3: D3Q19
+  int spl = 1;         // steady sweeps: time steps per launch (1 or 2)
   int N = 0;           // nodes
   Geo geo{};           // D2Q9 geometry
   lks::Geo3 geo3{};    // D3Q19 geometry
@@ -392,6 +394,10 @@ struct Run {
       lks::launch_lks3_step<R>(c->geo3, a, c->stream);
       return;
     }
+    lks::launch_lks_step<R>(g, fwd_args(in, out, level_out, acc), c->stream);
+  }
+
+  lks::FwdArgs<R> fwd_args(R* const in[5], R* const out[5], int level_out, double* acc) {
     lks::FwdArgs<R> a;
     a.mask = c->d_mask;
     a.inv1pa = rp<R>(c->inv1pa);
@@ -401,6 +407,7 @@ struct Run {
     a.Tb = rp<R>(c->Tb);
     a.ufac = c->d_ufac;
     a.level_out = std::min(level_out, int(c->ufac.size()) - 1);
+    a.level_mid = std::min(std::max(level_out - 1, 0), int(c->ufac.size()) - 1);
     a.d0 = in[0];
     a.ux0 = in[1];
     a.uy0 = in[2];
@@ -411,7 +418,12 @@ struct Run {
     a.T1 = out[3];
     a.acc = acc;
     a.objective = c->objective;
-    lks::launch_lks_step<R>(g, a, c->stream);
+    return a;
+  }
+
+  // two time steps per launch: FP32 non-thermal D2Q9 steady sweeps
+  bool two_step() const {
+    return std::is_same<R, float>::value && c->dim == 2 && !c->phys.thermal && c->spl == 2;
   }
 
   void coefficients(const double* gamma) {
@@ -465,7 +477,22 @@ struct Run {
   }
 
   void advance(int steps) {
-    for (int n = 0; n < steps; ++n) {
+    int n = 0;
+    if constexpr (std::is_same<R, float>::value) {
+      if (two_step()) {
+        for (; n + 2 <= steps; n += 2) {
+          R* in[5] = {};
+          R* out[5] = {};
+          for (int f = 0; f < nf; ++f) {
+            in[f] = rp<R>(c->S[c->cur][f]);
+            out[f] = rp<R>(c->S[c->cur ^ 1][f]);
+          }
+          lks::launch_lks_step2(g, fwd_args(in, out, c->last_level + n + 2, nullptr), c->stream);
+          c->cur ^= 1;
+        }
+      }
+    }
+    for (; n < steps; ++n) {
       R* in[5] = {};
       R* out[5] = {};
       for (int f = 0; f < nf; ++f) {
@@ -528,6 +555,12 @@ struct Run {
       c->acur = i1;
       return;
     }
+    lks::launch_alks_step<R>(g, adj_args(st, sdp, sh, sens, mode), c->stream);
+    c->acur = i1;
+  }
+
+  lks::AdjArgs<R> adj_args(R* const st[5], double sdp, double sh, double* sens, int mode) {
+    const int i0 = c->acur, i1 = c->acur ^ 1;
     lks::AdjArgs<R> a;
     a.mask = c->d_mask;
     a.inv1pa = rp<R>(c->inv1pa);
@@ -550,8 +583,7 @@ struct Run {
     a.seed_dp = sdp;
     a.seed_heat = sh;
     a.ops = c->d_ops;
-    lks::launch_alks_step<R>(g, a, c->stream);
-    c->acur = i1;
+    return a;
   }
 
   void adjoint_steady(double seed, int steps, double* dJ, bool reset) {
@@ -564,7 +596,18 @@ struct Run {
     R* st[5] = {};
     for (int f = 0; f < nf; ++f) st[f] = cur_field(f);
     if (!c->phys.thermal) st[nf - 1] = nullptr;
-    for (int n = 0; n < steps; ++n) {
+    int n = 0;
+    if constexpr (std::is_same<R, float>::value) {
+      if (two_step() && steps >= 2) {
+        if (steps % 2) adj_step(st, sdp, sh, nullptr, 2);
+        for (n = steps % 2; n < steps; n += 2) {
+          lks::launch_alks_step2(g, adj_args(st, sdp, sh, n + 2 == steps ? dJ : nullptr, 2),
+                                 c->stream);
+          c->acur ^= 1;
+        }
+      }
+    }
+    for (; n < steps; ++n) {
       const bool last = n == steps - 1;
       adj_step(st, sdp, sh, last ? dJ : nullptr, 2);
     }
@@ -957,6 +1000,22 @@ lks_status lks_set_tile_rows(lks_ctx* c, int tile_rows) {
   return fail(c, LKS_E_INVALID, "tile height must be 4 or 8");
 }
 
+lks_status lks_set_steps_per_launch(lks_ctx* c, int steps) {
+  if (!c) return LKS_E_INVALID;
+  if (steps != 1 && steps != 2) return fail(c, LKS_E_INVALID, "steps per launch must be 1 or 2");
+  if (steps == 2 && (c->dim != 2 || c->rsz != 4 || c->phys.thermal))
+    return fail(c, LKS_E_UNSUPPORTED, "two steps per launch need an FP32 non-thermal D2Q9 problem");
+  c->spl = steps;
+  return LKS_OK;
+}
+
+lks_status lks_launch_shape(const lks_ctx* c, int* tile_rows, int* steps_per_launch) {
+  if (!c) return LKS_E_INVALID;
+  if (tile_rows) *tile_rows = c->dim == 2 ? c->geo.ty : 0;
+  if (steps_per_launch) *steps_per_launch = c->spl;
+  return LKS_OK;
+}
+
 lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* tile_rows) {
   if (!c || !gamma_dev || steps < 1) return LKS_E_INVALID;
   if (c->dim == 3) return fail(c, LKS_E_UNSUPPORTED, "D3Q19 kernels are not tiled");
@@ -966,11 +1025,14 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
   for (auto& ev : e)
     if (!hip_ok(c, hipEventCreate(&ev), "event", &st)) return st;
   float best = 0.0f;
-  int best_ty = c->geo.ty;
+  int best_ty = c->geo.ty, best_spl = c->spl;
   const int mode = c->mode;
+  const bool can2 = c->rsz == 4 && !c->phys.thermal;
   c->mode = LKS_STEADY;  // time plain steps on the ping-pong buffers
-  for (int ty : TILE_ROWS) {
+  for (int shape = 0; shape < (can2 ? 4 : 2); ++shape) {
+    const int ty = TILE_ROWS[shape & 1], spl = 1 + (shape >> 1);
     set_tile_rows(c->geo, ty);
+    c->spl = spl;
     float t = 0.0f;
     for (int rep = 0; rep < 2; ++rep) {  // the first repetition warms up
       hipEventRecord(e[0], c->stream);
@@ -996,11 +1058,13 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
     if (best == 0.0f || t < best) {
       best = t;
       best_ty = ty;
+      best_spl = spl;
     }
   }
   c->mode = mode;
   for (auto& ev : e) hipEventDestroy(ev);
   set_tile_rows(c->geo, best_ty);
+  c->spl = best_spl;
   c->have_forward = false;
   c->have_adjoint = false;
   c->last_level = 0;

@@ -53,7 +53,8 @@ EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forwa
             "lks_last_error", "lks_destroy", "lks_batch_create", "lks_batch_workspace_size",
             "lks_batch_bind_workspace", "lks_batch_run", "lks_batch_read_field",
             "lks_batch_last_error", "lks_batch_destroy", "lks_autotune",
-            "lks_batch_autotune", "lks_set_tile_rows")
+            "lks_batch_autotune", "lks_set_tile_rows", "lks_set_steps_per_launch",
+            "lks_launch_shape")
 
 
 class Grid(ctypes.Structure):
@@ -133,6 +134,10 @@ _lib.lks_batch_autotune.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctyp
 _lib.lks_batch_autotune.restype = _st
 _lib.lks_set_tile_rows.argtypes = [_vp, ctypes.c_int]
 _lib.lks_set_tile_rows.restype = _st
+_lib.lks_set_steps_per_launch.argtypes = [_vp, ctypes.c_int]
+_lib.lks_set_steps_per_launch.restype = _st
+_lib.lks_launch_shape.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.lks_launch_shape.restype = _st
 _lib.lks_batch_destroy.argtypes = [_vp]
 _lib.lks_batch_destroy.restype = None
 
@@ -254,6 +259,15 @@ class LKS:
 
     def set_tile_rows(self, ty):
         _check(_lib.lks_set_tile_rows(self.ctx, int(ty)), self.ctx)
+
+    def set_steps_per_launch(self, n):
+        _check(_lib.lks_set_steps_per_launch(self.ctx, int(n)), self.ctx)
+
+    def launch_shape(self):
+        """(tile rows, steps per launch) in use."""
+        ty, spl = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.lks_launch_shape(self.ctx, ctypes.byref(ty), ctypes.byref(spl)), self.ctx)
+        return ty.value, spl.value
 
     def memory_report(self):
         a, b, k = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int()

@@ -134,6 +134,24 @@ def test_invalid_d3q19_masks_are_rejected():
     _expect_invalid(wl)
 
 
+def test_launch_shape_controls():
+    wl = W.steady_channel_uniform(16, 12, Re=10, seed=0)
+    c = _create(wl, "fp32")
+    assert c.launch_shape() == (8, 1)
+    c.set_steps_per_launch(2)
+    c.set_tile_rows(4)
+    assert c.launch_shape() == (4, 2)
+    with pytest.raises(lks.LKSError) as e:
+        c.set_steps_per_launch(3)
+    assert e.value.status == lks.LKS_E_INVALID
+    with pytest.raises(lks.LKSError) as e:
+        _create(wl, "fp64").set_steps_per_launch(2)
+    assert e.value.status == lks.LKS_E_UNSUPPORTED
+    with pytest.raises(lks.LKSError) as e:
+        _create(W.heated_block_duct(20, 10, 8, n_steps=5), "fp32").set_tile_rows(4)
+    assert e.value.status == lks.LKS_E_UNSUPPORTED
+
+
 def test_calls_out_of_order_report_state_errors():
     wl = W.steady_channel_uniform(16, 12, Re=10, seed=0)
     c = _create(wl)

@@ -330,6 +330,52 @@ def test_steps_do_not_depend_on_the_tile_height(case, prec):
             assert np.array_equal(a, b)
 
 
+def _steady_run(wl, ty, spl, nf, na, prec="fp32"):
+    ctx = lks.LKS(wl, precision=prec, device=DEV)
+    ctx.set_tile_rows(ty)
+    ctx.set_steps_per_launch(spl)
+    assert ctx.launch_shape() == (ty, spl)
+    g = T(wl.gamma)
+    d = torch.empty_like(g)
+    ctx.forward(g, nf)
+    J = ctx.objective()
+    fields = [ctx.read(n).cpu().numpy() for n in ("drho", "ux", "uy")]
+    ctx.backward(0.7, d, na)
+    torch.cuda.synchronize()
+    adj = [ctx.read(n).cpu().numpy() for n in ("adj_rho", "adj_vx", "adj_vy")]
+    return J, fields, adj, d.cpu().numpy()
+
+
+@pytest.mark.parametrize("ty", [4, 8])
+@pytest.mark.parametrize("case", ["channel_70x37", "channel_65x9", "periodic_67x13"])
+def test_two_steps_per_launch_give_the_same_bits(case, ty):
+    """Two fused time steps per launch (tile + 4-node halo in LDS) against one
+    step per launch: odd and even step counts, partial and merged tiles,
+    corners, periodic wrap."""
+    say(f"[gpu] two steps per launch {case} ty={ty}")
+    wl = CASES[case]()
+    for nf, na in ((7, 9), (12, 10)):
+        ref = _steady_run(wl, ty, 1, nf, na)
+        got = _steady_run(wl, ty, 2, nf, na)
+        assert ref[0] == got[0]
+        for a, b in zip(ref[1] + ref[2] + [ref[3]], got[1] + got[2] + [got[3]]):
+            assert np.array_equal(a, b)
+
+
+def test_two_steps_per_launch_full_size_512():
+    """At full size the one-step kernel runs interior tiles through its
+    branch-free variant, whose floating-point contraction may differ from the
+    two-step kernel's, so the comparison is to FP32 rounding."""
+    say("[gpu] two steps per launch 512x512, 300+301 steps")
+    wl = W.steady_channel_grf(512, 512, Re=100.0, sigma=8.0, seed=0)
+    ref = _steady_run(wl, 8, 1, 300, 301)
+    got = _steady_run(wl, 8, 2, 300, 301)
+    assert abs(ref[0] - got[0]) <= 1e-6 * abs(ref[0])
+    for a, b in zip(ref[1] + ref[2], got[1] + got[2]):
+        assert rel(b, a) < 1e-5
+    assert rel(got[3], ref[3]) < 1e-4
+
+
 def test_autotune_picks_a_supported_height_and_keeps_results():
     say("[gpu] autotune 512x512")
     wl = W.steady_channel_grf(512, 512, Re=100.0, sigma=8.0, seed=0, n_fwd=100, n_adj=100)
@@ -337,11 +383,15 @@ def test_autotune_picks_a_supported_height_and_keeps_results():
     g = T(wl.gamma)
     ty = ctx.autotune(g, 50)
     assert ty in (4, 8)
+    shape = ctx.launch_shape()
+    assert shape[0] == ty and shape[1] in (1, 2)
     d = torch.empty_like(g)
     ctx.forward(g, wl.n_fwd)
     J = ctx.objective()
     ctx.backward(1.0, d, wl.n_adj)
     ref = lks.LKS(wl, precision="fp32", device=DEV)
+    ref.set_tile_rows(shape[0])
+    ref.set_steps_per_launch(shape[1])
     d2 = torch.empty_like(g)
     ref.forward(g, wl.n_fwd)
     J2 = ref.objective()
