@@ -215,15 +215,18 @@ lks_status lks_autotune(lks_ctx *ctx, const double *gamma_dev, int steps, int *t
  * depend on it. Discards the forward and adjoint states. D2Q9 only. */
 lks_status lks_set_tile_rows(lks_ctx *ctx, int tile_rows);
 
-/* Time steps per kernel launch of the steady sweeps (lks_advance and the
- * steady lks_forward, alks_backward, alks_advance): 1, or 2 for FP32
- * non-thermal D2Q9 problems (LKS_E_UNSUPPORTED otherwise). With 2, each
- * launch loads its tile with a 4-node halo and runs two steps, the first
- * on the tile and a 2-node halo kept in LDS; results are the same bits. */
-lks_status lks_set_steps_per_launch(lks_ctx *ctx, int steps);
+/* Time steps per kernel launch of the steady sweeps, forward (lks_advance
+ * and the steady lks_forward) and adjoint (steady alks_backward,
+ * alks_advance): 1, or 2 for FP32 non-thermal D2Q9 problems
+ * (LKS_E_UNSUPPORTED otherwise). With 2, each launch loads its tile with a
+ * 4-node halo and runs two steps, the first on the tile and a 2-node halo
+ * kept in LDS; results agree with one step per launch to rounding. */
+lks_status lks_set_steps_per_launch(lks_ctx *ctx, int forward_steps, int adjoint_steps);
 
-/* The launch shape in use: tile height (0 for D3Q19) and steps per launch. */
-lks_status lks_launch_shape(const lks_ctx *ctx, int *tile_rows, int *steps_per_launch);
+/* The launch shape in use: tile height (0 for D3Q19) and steps per launch of
+ * the forward and adjoint sweeps. */
+lks_status lks_launch_shape(const lks_ctx *ctx, int *tile_rows, int *forward_steps,
+                            int *adjoint_steps);
 
 /* Memory plan: bytes of checkpoint + replay storage, bytes of the rest of
  * the workspace, and the checkpoint interval K (N when the whole trajectory

@@ -43,7 +43,8 @@ struct lks_ctx {
   std::vector<double> ubar, Tbar, ufac;
   int n_in = 0, n_out = 0;
   int dim = 2;         // 2: D2Q9, 3: D3Q19
-  int spl = 1;         // steady sweeps: time steps per launch (1 or 2)
+  int spl_f = 1;       // steady sweeps: time steps per launch (1 or 2),
+  int spl_a = 1;       // forward and adjoint
   int N = 0;           // nodes
   Geo geo{};           // D2Q9 geometry
   lks::Geo3 geo3{};    // D3Q19 geometry
@@ -422,8 +423,8 @@ struct Run {
   }
 
   // two time steps per launch: FP32 non-thermal D2Q9 steady sweeps
-  bool two_step() const {
-    return std::is_same<R, float>::value && c->dim == 2 && !c->phys.thermal && c->spl == 2;
+  bool two_step(int spl) const {
+    return std::is_same<R, float>::value && c->dim == 2 && !c->phys.thermal && spl == 2;
   }
 
   void coefficients(const double* gamma) {
@@ -479,7 +480,7 @@ struct Run {
   void advance(int steps) {
     int n = 0;
     if constexpr (std::is_same<R, float>::value) {
-      if (two_step()) {
+      if (two_step(c->spl_f)) {
         for (; n + 2 <= steps; n += 2) {
           R* in[5] = {};
           R* out[5] = {};
@@ -598,7 +599,7 @@ struct Run {
     if (!c->phys.thermal) st[nf - 1] = nullptr;
     int n = 0;
     if constexpr (std::is_same<R, float>::value) {
-      if (two_step() && steps >= 2) {
+      if (two_step(c->spl_a) && steps >= 2) {
         if (steps % 2) adj_step(st, sdp, sh, nullptr, 2);
         for (n = steps % 2; n < steps; n += 2) {
           lks::launch_alks_step2(g, adj_args(st, sdp, sh, n + 2 == steps ? dJ : nullptr, 2),
@@ -1000,19 +1001,25 @@ lks_status lks_set_tile_rows(lks_ctx* c, int tile_rows) {
   return fail(c, LKS_E_INVALID, "tile height must be 4 or 8");
 }
 
-lks_status lks_set_steps_per_launch(lks_ctx* c, int steps) {
+lks_status lks_set_steps_per_launch(lks_ctx* c, int forward_steps, int adjoint_steps) {
   if (!c) return LKS_E_INVALID;
-  if (steps != 1 && steps != 2) return fail(c, LKS_E_INVALID, "steps per launch must be 1 or 2");
-  if (steps == 2 && (c->dim != 2 || c->rsz != 4 || c->phys.thermal))
-    return fail(c, LKS_E_UNSUPPORTED, "two steps per launch need an FP32 non-thermal D2Q9 problem");
-  c->spl = steps;
+  for (int s : {forward_steps, adjoint_steps}) {
+    if (s != 1 && s != 2) return fail(c, LKS_E_INVALID, "steps per launch must be 1 or 2");
+    if (s == 2 && (c->dim != 2 || c->rsz != 4 || c->phys.thermal))
+      return fail(c, LKS_E_UNSUPPORTED,
+                  "two steps per launch need an FP32 non-thermal D2Q9 problem");
+  }
+  c->spl_f = forward_steps;
+  c->spl_a = adjoint_steps;
   return LKS_OK;
 }
 
-lks_status lks_launch_shape(const lks_ctx* c, int* tile_rows, int* steps_per_launch) {
+lks_status lks_launch_shape(const lks_ctx* c, int* tile_rows, int* forward_steps,
+                            int* adjoint_steps) {
   if (!c) return LKS_E_INVALID;
   if (tile_rows) *tile_rows = c->dim == 2 ? c->geo.ty : 0;
-  if (steps_per_launch) *steps_per_launch = c->spl;
+  if (forward_steps) *forward_steps = c->spl_f;
+  if (adjoint_steps) *adjoint_steps = c->spl_a;
   return LKS_OK;
 }
 
@@ -1024,47 +1031,53 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
   hipEvent_t e[3];
   for (auto& ev : e)
     if (!hip_ok(c, hipEventCreate(&ev), "event", &st)) return st;
+  // per tile height, the forward and adjoint sweeps with one and (where
+  // supported) two steps per launch, timed separately
   float best = 0.0f;
-  int best_ty = c->geo.ty, best_spl = c->spl;
+  int best_ty = c->geo.ty, best_f = c->spl_f, best_a = c->spl_a;
   const int mode = c->mode;
-  const bool can2 = c->rsz == 4 && !c->phys.thermal;
+  const int nspl = (c->rsz == 4 && !c->phys.thermal) ? 2 : 1;
   c->mode = LKS_STEADY;  // time plain steps on the ping-pong buffers
-  for (int shape = 0; shape < (can2 ? 4 : 2); ++shape) {
-    const int ty = TILE_ROWS[shape & 1], spl = 1 + (shape >> 1);
+  for (int ty : TILE_ROWS) {
     set_tile_rows(c->geo, ty);
-    c->spl = spl;
-    float t = 0.0f;
-    for (int rep = 0; rep < 2; ++rep) {  // the first repetition warms up
-      hipEventRecord(e[0], c->stream);
-      if (c->rsz == 8) {
-        Run<double> r(c);
-        r.forward(gamma_dev, steps);
-        hipEventRecord(e[1], c->stream);
-        r.adjoint_steady(1.0, steps, nullptr, true);
-      } else {
-        Run<float> r(c);
-        r.forward(gamma_dev, steps);
-        hipEventRecord(e[1], c->stream);
-        r.adjoint_steady(1.0, steps, nullptr, true);
+    float tf[2] = {0.0f, 0.0f}, ta[2] = {0.0f, 0.0f};
+    for (int spl = 1; spl <= nspl && st == LKS_OK; ++spl) {
+      c->spl_f = c->spl_a = spl;
+      for (int rep = 0; rep < 2; ++rep) {  // the first repetition warms up
+        hipEventRecord(e[0], c->stream);
+        if (c->rsz == 8) {
+          Run<double> r(c);
+          r.forward(gamma_dev, steps);
+          hipEventRecord(e[1], c->stream);
+          r.adjoint_steady(1.0, steps, nullptr, true);
+        } else {
+          Run<float> r(c);
+          r.forward(gamma_dev, steps);
+          hipEventRecord(e[1], c->stream);
+          r.adjoint_steady(1.0, steps, nullptr, true);
+        }
+        hipEventRecord(e[2], c->stream);
+        if (!hip_ok(c, hipEventSynchronize(e[2]), "autotune sync", &st)) break;
+        hipEventElapsedTime(&tf[spl - 1], e[0], e[1]);
+        hipEventElapsedTime(&ta[spl - 1], e[1], e[2]);
       }
-      hipEventRecord(e[2], c->stream);
-      if (!hip_ok(c, hipEventSynchronize(e[2]), "autotune sync", &st)) break;
-      float a = 0.0f, b = 0.0f;
-      hipEventElapsedTime(&a, e[0], e[1]);
-      hipEventElapsedTime(&b, e[1], e[2]);
-      t = a + b;
     }
     if (st != LKS_OK) break;
+    const int sf = (nspl == 2 && tf[1] < tf[0]) ? 2 : 1;
+    const int sa = (nspl == 2 && ta[1] < ta[0]) ? 2 : 1;
+    const float t = tf[sf - 1] + ta[sa - 1];
     if (best == 0.0f || t < best) {
       best = t;
       best_ty = ty;
-      best_spl = spl;
+      best_f = sf;
+      best_a = sa;
     }
   }
   c->mode = mode;
   for (auto& ev : e) hipEventDestroy(ev);
   set_tile_rows(c->geo, best_ty);
-  c->spl = best_spl;
+  c->spl_f = best_f;
+  c->spl_a = best_a;
   c->have_forward = false;
   c->have_adjoint = false;
   c->last_level = 0;

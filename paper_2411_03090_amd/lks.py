@@ -134,9 +134,9 @@ _lib.lks_batch_autotune.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctyp
 _lib.lks_batch_autotune.restype = _st
 _lib.lks_set_tile_rows.argtypes = [_vp, ctypes.c_int]
 _lib.lks_set_tile_rows.restype = _st
-_lib.lks_set_steps_per_launch.argtypes = [_vp, ctypes.c_int]
+_lib.lks_set_steps_per_launch.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
 _lib.lks_set_steps_per_launch.restype = _st
-_lib.lks_launch_shape.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.lks_launch_shape.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int)] * 3
 _lib.lks_launch_shape.restype = _st
 _lib.lks_batch_destroy.argtypes = [_vp]
 _lib.lks_batch_destroy.restype = None
@@ -260,14 +260,16 @@ class LKS:
     def set_tile_rows(self, ty):
         _check(_lib.lks_set_tile_rows(self.ctx, int(ty)), self.ctx)
 
-    def set_steps_per_launch(self, n):
-        _check(_lib.lks_set_steps_per_launch(self.ctx, int(n)), self.ctx)
+    def set_steps_per_launch(self, forward, adjoint=None):
+        adjoint = forward if adjoint is None else adjoint
+        _check(_lib.lks_set_steps_per_launch(self.ctx, int(forward), int(adjoint)), self.ctx)
 
     def launch_shape(self):
-        """(tile rows, steps per launch) in use."""
-        ty, spl = ctypes.c_int(), ctypes.c_int()
-        _check(_lib.lks_launch_shape(self.ctx, ctypes.byref(ty), ctypes.byref(spl)), self.ctx)
-        return ty.value, spl.value
+        """(tile rows, forward steps per launch, adjoint steps per launch)."""
+        ty, sf, sa = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.lks_launch_shape(self.ctx, ctypes.byref(ty), ctypes.byref(sf),
+                                     ctypes.byref(sa)), self.ctx)
+        return ty.value, sf.value, sa.value
 
     def memory_report(self):
         a, b, k = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int()

@@ -137,10 +137,10 @@ def test_invalid_d3q19_masks_are_rejected():
 def test_launch_shape_controls():
     wl = W.steady_channel_uniform(16, 12, Re=10, seed=0)
     c = _create(wl, "fp32")
-    assert c.launch_shape() == (8, 1)
-    c.set_steps_per_launch(2)
+    assert c.launch_shape() == (8, 1, 1)
+    c.set_steps_per_launch(2, 1)
     c.set_tile_rows(4)
-    assert c.launch_shape() == (4, 2)
+    assert c.launch_shape() == (4, 2, 1)
     with pytest.raises(lks.LKSError) as e:
         c.set_steps_per_launch(3)
     assert e.value.status == lks.LKS_E_INVALID

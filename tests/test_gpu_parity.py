@@ -334,7 +334,7 @@ def _steady_run(wl, ty, spl, nf, na, prec="fp32"):
     ctx = lks.LKS(wl, precision=prec, device=DEV)
     ctx.set_tile_rows(ty)
     ctx.set_steps_per_launch(spl)
-    assert ctx.launch_shape() == (ty, spl)
+    assert ctx.launch_shape() == (ty, spl, spl)
     g = T(wl.gamma)
     d = torch.empty_like(g)
     ctx.forward(g, nf)
@@ -384,14 +384,14 @@ def test_autotune_picks_a_supported_height_and_keeps_results():
     ty = ctx.autotune(g, 50)
     assert ty in (4, 8)
     shape = ctx.launch_shape()
-    assert shape[0] == ty and shape[1] in (1, 2)
+    assert shape[0] == ty and shape[1] in (1, 2) and shape[2] in (1, 2)
     d = torch.empty_like(g)
     ctx.forward(g, wl.n_fwd)
     J = ctx.objective()
     ctx.backward(1.0, d, wl.n_adj)
     ref = lks.LKS(wl, precision="fp32", device=DEV)
     ref.set_tile_rows(shape[0])
-    ref.set_steps_per_launch(shape[1])
+    ref.set_steps_per_launch(shape[1], shape[2])
     d2 = torch.empty_like(g)
     ref.forward(g, wl.n_fwd)
     J2 = ref.objective()

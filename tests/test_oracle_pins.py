@@ -360,3 +360,30 @@ def test_gradient_vs_fd_channel_steady_is_recorded():
     ratio = np.median(adj / fd)
     assert corr > 0.99
     assert 0.25 < ratio < 0.5
+
+
+@pytest.mark.slow
+def test_thermal_adjoint_growth_with_conductivity_contrast():
+    """A property of the scheme, not of an implementation: over a long
+    unsteady horizon the ALKS thermal adjoint stays bounded for a moderate
+    solid/fluid conductivity contrast and grows exponentially for a large
+    one (K_s = 10 K_f puts B_s = 0 next to B_f = 0.45), because eq:ageq
+    splits div(B q~) by the product rule instead of transposing the discrete
+    forward term B grad T. The sweep runs in the regime of the 1024x512
+    forced-convection case (nu = 0.1, u_max = 0.039, Pr = 6) on 128x64."""
+    n = 5000
+    peak = {}
+    for ks in (2.0, 10.0):
+        wl = W.unsteady_thermal_channel(128, 64, Re=0.0391 * 63 / 0.1, sigma=1.0, seed=0,
+                                        n_steps=n, period=2000.0, Ks_over_Kf=ks)
+        pb = O.Problem(wl)
+        _, _, traj = O.forward(pb, wl.gamma, n, store=True)
+        alpha, _, B, _ = O.coefficients(pb, wl.gamma)
+        adj = pb.zeros(O.N_ADJ_FIELDS)
+        for m in range(n, -1, -1):
+            w = 1.0 / n if m >= 1 else 0.0
+            adj = O.alks_step(pb, alpha, B, traj[min(m + 1, n)], traj[m], adj, 0.0, w)
+        peak[ks] = max(float(np.abs(a).max()) for a in adj)
+        del traj
+    assert peak[2.0] < 1e-2
+    assert peak[10.0] > 1e3 * peak[2.0]
