@@ -204,15 +204,18 @@ lks_status lks_write_field(lks_ctx *ctx, int which, const double *dev_in);
 
 /* Tile autotuner: times `steps` forward and `steps` adjoint steps of the
  * design gamma_dev for each launch shape the kernels provide (tiles of
- * 64 x 4 and 64 x 8 nodes; one or, where supported, two steps per launch)
+ * 64 x 4, 64 x 8 and, where supported, 64 x 16 nodes; one or, where
+ * supported, two steps per launch)
  * on this context's stream, keeps the fastest and reports its tile height in
  * *tile_rows (lks_launch_shape gives the whole shape). Synchronises; the forward and adjoint states are discarded
  * (run lks_forward afterwards). D2Q9 only (LKS_E_UNSUPPORTED for D3Q19,
  * whose node-parallel kernels have no tile shape). */
 lks_status lks_autotune(lks_ctx *ctx, const double *gamma_dev, int steps, int *tile_rows);
 
-/* Set the tile height (4 or 8 rows of 64 nodes) explicitly; results do not
- * depend on it. Discards the forward and adjoint states. D2Q9 only. */
+/* Set the tile height (4 or 8 rows of 64 nodes, or 16 for FP32 non-thermal
+ * problems) explicitly; results do not depend on it. Discards the forward and
+ * adjoint states. D2Q9 only. Two steps per launch apply to heights 4 and 8;
+ * with 16 every launch runs one step. */
 lks_status lks_set_tile_rows(lks_ctx *ctx, int tile_rows);
 
 /* Time steps per kernel launch of the steady sweeps, forward (lks_advance
@@ -261,6 +264,8 @@ lks_status lks_batch_run(lks_batch *b, const double *const *gamma_dev, int n_fwd
  * receives a throw-away sensitivity. Synchronises. */
 lks_status lks_batch_autotune(lks_batch *b, const double *const *gamma_dev, int steps,
                               double *const *scratch_dev, int *tile_rows);
+/* Tile height of a batch's step launches (as lks_set_tile_rows). */
+lks_status lks_batch_set_tile_rows(lks_batch *b, int tile_rows);
 /* Field `which` of design d at its final forward / adjoint level. */
 lks_status lks_batch_read_field(lks_batch *b, int design, int which, double *dev_out);
 const char *lks_batch_last_error(const lks_batch *b);

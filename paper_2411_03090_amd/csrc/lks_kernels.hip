@@ -10,6 +10,8 @@
 // Nothing is a dense contraction, so there is no MFMA; reductions use
 // wavefront shuffles and a fixed per-tile order, so every result is
 // deterministic run to run (the checkpoint replay relies on it).
+#include <type_traits>
+
 #include "lks_device.h"
 
 namespace lks {
@@ -1328,6 +1330,12 @@ void launch_init(const Geo& g, const uint8_t* mask, const R* ubx, const R* uby, 
 template <typename R>
 void launch_lks_step(const Geo& g, const FwdArgs<R>& a, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
+  if constexpr (std::is_same<R, float>::value) {
+    if (g.ty == 16 && !g.thermal) {
+      lks_step_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(g, a);
+      return;
+    }
+  }
   if (g.ty == 8) {
     if (g.thermal) lks_step_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(g, a);
     else lks_step_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
@@ -1339,6 +1347,12 @@ void launch_lks_step(const Geo& g, const FwdArgs<R>& a, hipStream_t s) {
 template <typename R>
 void launch_alks_step(const Geo& g, const AdjArgs<R>& a, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
+  if constexpr (std::is_same<R, float>::value) {
+    if (g.ty == 16 && !g.thermal) {
+      alks_step_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(g, a);
+      return;
+    }
+  }
   if (g.ty == 8) {
     if (g.thermal) alks_step_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(g, a);
     else alks_step_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
@@ -1347,6 +1361,7 @@ void launch_alks_step(const Geo& g, const AdjArgs<R>& a, hipStream_t s) {
     else alks_step_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
   }
 }
+// two-step kernels exist for tile heights 4 and 8 (the runtime never asks for others)
 void launch_lks_step2(const Geo& g, const FwdArgs<float>& a, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
   if (g.ty == 8) lks_step2_kernel<float, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
@@ -1371,6 +1386,12 @@ template <typename R>
 void launch_lks_step_batch(const BatchFwd<R>* d, const int* tile0, int nd, int total, int ty,
                            bool thermal, int parity, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(total));
+  if constexpr (std::is_same<R, float>::value) {
+    if (ty == 16 && !thermal) {
+      lks_step_batch_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
+      return;
+    }
+  }
   if (ty == 8) {
     if (thermal) lks_step_batch_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
     else lks_step_batch_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
@@ -1383,6 +1404,13 @@ template <typename R>
 void launch_alks_step_batch(const BatchAdj<R>* d, const int* tile0, int nd, int total, int ty,
                             bool thermal, int parity, int last, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(total));
+  if constexpr (std::is_same<R, float>::value) {
+    if (ty == 16 && !thermal) {
+      alks_step_batch_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity,
+                                                                       last);
+      return;
+    }
+  }
   if (ty == 8) {
     if (thermal) alks_step_batch_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity, last);
     else alks_step_batch_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity, last);

@@ -103,7 +103,11 @@ int n_tiles(const Geo& g) { return g.ntx * g.nty; }
 int max_tiles(const Geo& g) {
   return lks::tiles_along(g.nx, lks::TX) * lks::tiles_along(g.ny, 4);
 }
-constexpr int TILE_ROWS[2] = {4, 8};
+constexpr int TILE_ROWS[3] = {4, 8, 16};
+// 64 x 16 tiles exist for FP32 non-thermal D2Q9 problems only (LDS size)
+bool tile_rows_ok(int ty, int rsz, int thermal) {
+  return ty == 4 || ty == 8 || (ty == 16 && rsz == 4 && !thermal);
+}
 void set_tile_rows(Geo& g, int ty) {
   g.ty = ty;
   g.ntx = lks::tiles_along(g.nx, lks::TX);
@@ -423,8 +427,10 @@ struct Run {
   }
 
   // two time steps per launch: FP32 non-thermal D2Q9 steady sweeps
+  // (two-step kernels exist for 64 x 4 and 64 x 8 tiles)
   bool two_step(int spl) const {
-    return std::is_same<R, float>::value && c->dim == 2 && !c->phys.thermal && spl == 2;
+    return std::is_same<R, float>::value && c->dim == 2 && !c->phys.thermal && spl == 2 &&
+           (c->geo.ty == 4 || c->geo.ty == 8);
   }
 
   void coefficients(const double* gamma) {
@@ -992,13 +998,13 @@ lks_status lks_set_tile_rows(lks_ctx* c, int tile_rows) {
   if (!c) return LKS_E_INVALID;
   if (c->dim == 3) return fail(c, LKS_E_UNSUPPORTED, "D3Q19 kernels are not tiled");
   for (int ty : TILE_ROWS)
-    if (ty == tile_rows) {
+    if (ty == tile_rows && tile_rows_ok(ty, c->rsz, c->phys.thermal)) {
       set_tile_rows(c->geo, ty);
       c->have_forward = false;
       c->have_adjoint = false;
       return LKS_OK;
     }
-  return fail(c, LKS_E_INVALID, "tile height must be 4 or 8");
+  return fail(c, LKS_E_INVALID, "tile height must be 4 or 8 (or 16 for FP32 non-thermal)");
 }
 
 lks_status lks_set_steps_per_launch(lks_ctx* c, int forward_steps, int adjoint_steps) {
@@ -1039,9 +1045,11 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
   const int nspl = (c->rsz == 4 && !c->phys.thermal) ? 2 : 1;
   c->mode = LKS_STEADY;  // time plain steps on the ping-pong buffers
   for (int ty : TILE_ROWS) {
+    if (!tile_rows_ok(ty, c->rsz, c->phys.thermal)) continue;
     set_tile_rows(c->geo, ty);
     float tf[2] = {0.0f, 0.0f}, ta[2] = {0.0f, 0.0f};
-    for (int spl = 1; spl <= nspl && st == LKS_OK; ++spl) {
+    const int nspl_ty = ty == 16 ? 1 : nspl;
+    for (int spl = 1; spl <= nspl_ty && st == LKS_OK; ++spl) {
       c->spl_f = c->spl_a = spl;
       for (int rep = 0; rep < 2; ++rep) {  // the first repetition warms up
         hipEventRecord(e[0], c->stream);
@@ -1063,8 +1071,8 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
       }
     }
     if (st != LKS_OK) break;
-    const int sf = (nspl == 2 && tf[1] < tf[0]) ? 2 : 1;
-    const int sa = (nspl == 2 && ta[1] < ta[0]) ? 2 : 1;
+    const int sf = (nspl_ty == 2 && tf[1] < tf[0]) ? 2 : 1;
+    const int sa = (nspl_ty == 2 && ta[1] < ta[0]) ? 2 : 1;
     const float t = tf[sf - 1] + ta[sa - 1];
     if (best == 0.0f || t < best) {
       best = t;
@@ -1474,6 +1482,7 @@ lks_status lks_batch_autotune(lks_batch* b, const double* const* gamma_dev, int 
       !hip_ok(nullptr, hipEventCreate(&e1), "event", &st))
     return bfail(b, st, g_create_error);
   for (int ty : TILE_ROWS) {
+    if (!tile_rows_ok(ty, b->rsz, b->thermal)) continue;
     if ((st = batch_set_tile_rows(b, ty)) != LKS_OK) break;
     float t = 0.0f;
     for (int rep = 0; rep < 2; ++rep) {
@@ -1497,6 +1506,17 @@ lks_status lks_batch_autotune(lks_batch* b, const double* const* gamma_dev, int 
   if (tile_rows) *tile_rows = best_ty;
   b->have_run = false;
   return LKS_OK;
+}
+
+lks_status lks_batch_set_tile_rows(lks_batch* b, int tile_rows) {
+  if (!b) return LKS_E_INVALID;
+  bool known = false;
+  for (int ty : TILE_ROWS) known = known || ty == tile_rows;
+  if (!known || !tile_rows_ok(tile_rows, b->rsz, b->thermal))
+    return bfail(b, LKS_E_INVALID, "tile height must be 4 or 8 (or 16 for FP32 non-thermal)");
+  lks_status st = batch_set_tile_rows(b, tile_rows);
+  if (st == LKS_OK) b->have_run = false;
+  return st;
 }
 
 lks_status lks_batch_read_field(lks_batch* b, int design, int which, double* dev_out) {

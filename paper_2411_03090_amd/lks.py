@@ -54,7 +54,7 @@ EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forwa
             "lks_batch_bind_workspace", "lks_batch_run", "lks_batch_read_field",
             "lks_batch_last_error", "lks_batch_destroy", "lks_autotune",
             "lks_batch_autotune", "lks_set_tile_rows", "lks_set_steps_per_launch",
-            "lks_launch_shape")
+            "lks_launch_shape", "lks_batch_set_tile_rows")
 
 
 class Grid(ctypes.Structure):
@@ -138,6 +138,8 @@ _lib.lks_set_steps_per_launch.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
 _lib.lks_set_steps_per_launch.restype = _st
 _lib.lks_launch_shape.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int)] * 3
 _lib.lks_launch_shape.restype = _st
+_lib.lks_batch_set_tile_rows.argtypes = [_vp, ctypes.c_int]
+_lib.lks_batch_set_tile_rows.restype = _st
 _lib.lks_batch_destroy.argtypes = [_vp]
 _lib.lks_batch_destroy.restype = None
 
@@ -347,6 +349,9 @@ class Batch:
         ty = ctypes.c_int()
         _bcheck(_lib.lks_batch_autotune(self.b, g, int(steps), o, ctypes.byref(ty)), self.b)
         return ty.value
+
+    def set_tile_rows(self, ty):
+        _bcheck(_lib.lks_batch_set_tile_rows(self.b, int(ty)), self.b)
 
     def read(self, design, name, out=None):
         import torch

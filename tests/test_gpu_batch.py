@@ -80,6 +80,23 @@ def test_graph_replays_match_eager():
         (x * x).sum().item()
 
 
+def test_batch_tile_heights_agree():
+    print("[gpu] batch fp32 tile heights 4, 8, 16", flush=True)
+    wls = _small_designs(120, 90)
+    res = []
+    for ty in (4, 8, 16):
+        b = lks.Batch(wls, precision="fp32", device=DEV)
+        b.set_tile_rows(ty)
+        gs = [T(w.gamma) for w in wls]
+        outs = [torch.empty_like(g) for g in gs]
+        Js = b.run(gs, outs, 120, 90)
+        res.append((Js, [o.cpu().numpy() for o in outs]))
+    for Js, outs in res[1:]:
+        for d in range(len(wls)):
+            assert abs(Js[d] - res[0][0][d]) <= 1e-6 * abs(res[0][0][d])
+            assert rel(outs[d], res[0][1][d]) < 1e-5
+
+
 def test_batch_fp32_within_tolerance():
     print("[gpu] batch fp32 vs oracle", flush=True)
     wls = _small_designs(400, 300)
