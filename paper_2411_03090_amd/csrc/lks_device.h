@@ -144,6 +144,7 @@ struct Geo3 {
   int nx, ny, nz, N;
   int periodic;     // bit 0: x, bit 1: y, bit 2: z
   int thermal;
+  int zc;           // z-planes per block of the marching kernels (>= 2)
   double A;         // eq:A
   double Bf;        // B of the fluid, used on boundary nodes
   double drho_out;  // prescribed outlet density minus 1
@@ -178,7 +179,8 @@ struct Fwd3Args {
   int level_out;
   const R* s0[5];      // level n
   R* s1[5];            // level n+1
-  R* e;                // equilibrium coefficients: a0, P (6), G (3); 10 N
+  const int* copy;     // edge and corner nodes, copied after the step
+  int ncopy;
   double* acc;         // per-block objective accumulator, or nullptr
   int objective;
 };
@@ -195,7 +197,7 @@ struct Adj3Args {
   const R* T;
   const R* p0[5];      // level n+1
   R* p1[5];            // level n
-  R* m;                // moments: rho~, u~ (3), s~ (6), T~, q~ (3); 14 N
+  R* m;                // moments: rho~, u~ (3), s~ (6), T~, q~ (3); 14 N (10 N without T)
   const FaceOp3* ops;  // -x, +x, -y, +y, -z, +z
   double* sens;
   int sens_mode;       // 0 none, 1 accumulate, 2 overwrite
@@ -204,6 +206,10 @@ struct Adj3Args {
 };
 
 int blocks3(int N);  // blocks of a node-parallel 3D launch (multiple of 8)
+// blocks of the z-marching step kernels, each with one objective accumulator
+int zblocks3(const Geo3& g);
+// edge and corner nodes in increasing order (out may be null); returns the count
+int copy_nodes3(const Geo3& g, int* out);
 template <typename R>
 void launch_coef3(const Geo3& g, const uint8_t* mask, const double* gamma, double alpha_max,
                   double q_alpha, double Kf, double Ks, double qK, R* inv1pa, R* B, R* dA3,
@@ -215,9 +221,11 @@ template <typename R>
 void launch_lks3_step(const Geo3& g, const Fwd3Args<R>& a, hipStream_t s);
 template <typename R>
 void launch_alks3_step(const Geo3& g, const Adj3Args<R>& a, hipStream_t s);
+// objective over tagged nodes: part holds tag_sum3_parts() partial sums
 template <typename R>
 void launch_tag_sum3(const Geo3& g, const uint8_t* mask, const R* d, const R* ux, const R* T,
-                     int objective, double* out, hipStream_t s);
+                     int objective, double* part, double* out, hipStream_t s);
+int tag_sum3_parts();
 
 // kernel launchers (lks_kernels.hip)
 template <typename R>

@@ -2,20 +2,21 @@
 // extension (the equations of Sec. 2.3-2.5 with indices running over x, y,
 // z, Sec. 2.1), on gfx950.
 //
-// Each step is two node-parallel passes with the neighbour gathers served by
+// LKS step: one z-marching kernel. A block owns 64 x 4 columns and walks
+// through a range of z-planes with the state of two planes in LDS; per plane
+// it forms a0 = drho - 3/2 u.u, P = 9/2 u u + A (grad u + grad u^T),
+// G = 3 T u + B grad T and the equilibria f'_i^eq = w_i [a0 + 3 c.u + c.P.c],
+// g_i^eq = w_i [T + c.G] (eq:feq2, eq:geq2) of the tile and its ring, streams
+// them to the columns that pull them, and closes the plane behind with the
+// implicit Brinkman division and the face closures. Edge and corner nodes
+// are copied by a small second kernel.
+// ALKS step: two node-parallel passes with the neighbour gathers served by
 // the L1/L2 caches:
-//   forward  pass 1  per node the coefficients of f_i^eq and g_i^eq,
-//                    f'_i^eq = w_i [a0 + 3 c.u + c.P.c], g_i^eq = w_i [T + c.G]
-//                    with a0 = drho - 3/2 u.u, P = 9/2 u u + A (grad u +
-//                    grad u^T), G = 3 T u + B grad T (eq:feq2, eq:geq2);
-//            pass 2  per node the pull of the 19 equilibria from x - c_i,
-//                    the implicit Brinkman division and the face closures;
-//   adjoint  pass 1  per node the pull of f~_i^eq = rho~ + c_i.V and
-//                    g~_i^eq = Theta from x + c_i (eq:afeq, eq:ageq), the face
-//                    least-squares completion, the local terms and the moments
-//                    rho~, u~, s~, T~, q~;
-//            pass 2  per node V and Theta of the new level from the moments
-//                    and the sensitivity 3 alpha' u.u~ - B' grad T.q~.
+//   pass 1  per node the pull of f~_i^eq = rho~ + c_i.V and g~_i^eq = Theta
+//           from x + c_i (eq:afeq, eq:ageq), the face least-squares
+//           completion, the local terms and the moments rho~, u~, s~, T~, q~;
+//   pass 2  per node V and Theta of the new level from the moments and the
+//           sensitivity 3 alpha' u.u~ - B' grad T.q~.
 // Blocks are mapped so that each XCD works on a contiguous slab of nodes,
 // keeping the neighbour planes of a block in that XCD's L2.
 #include <hip/hip_runtime.h>
@@ -183,161 +184,646 @@ __global__ __launch_bounds__(NT3) void init3_kernel(Geo3 g, const uint8_t* __res
 }
 
 // ---------------------------------------------------------------------------
+// z-marching tiles
+// ---------------------------------------------------------------------------
+// A block owns a tile of ZX x ZY columns and marches through a range of
+// z-planes. Each iteration loads one plane of the inputs (the tile plus a
+// 2-node halo, rows coalesced) into LDS, so a field plane leaves HBM once per
+// block and every neighbour gather reads LDS. The last tile along x or y is
+// shifted to end at the domain end (its overlap with the previous tile is
+// computed but not written), so one-sided differences at the ends stay
+// inside the tile.
+constexpr int ZX = 64, ZY = 4, ZT = ZX * ZY;
+constexpr int SX = ZX + 4, NSR = SX * (ZY + 4);    // tile + 2-node halo
+constexpr int CXN = ZX + 2, NCR = CXN * (ZY + 2);  // tile + 1-node halo
+constexpr int SRL = (NSR + ZT - 1) / ZT;           // halo-region loads per thread
+static_assert(ZT == NT3, "one block size for the 3D kernels");
+// the directions with an x or y component: their values cross columns
+__device__ constexpr int LQ[16] = {1, 2, 3, 4, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18};
+
+__host__ __device__ inline int zchunks(const Geo3& g) {
+  const int zc = g.zc < 2 ? 2 : g.zc;
+  return g.nz / zc > 1 ? g.nz / zc : 1;
+}
+__host__ __device__ inline int ztiles(int n, int t) { return (n + t - 1) / t; }
+
+struct ZTile {
+  int x0, y0, w, h;  // origin and extent of the tile
+  int xo, yo;        // first column and row the block writes
+  int z0, z1;        // output planes
+  int lb;            // logical block
+};
+
+// tile of this block; logical blocks run x fastest, then y, then z-chunk, and
+// the blocks of XCD x (blockIdx % 8) take the x-th eighth of them
+__device__ inline bool ztile(const Geo3& g, ZTile& t) {
+  const int ntx = ztiles(g.nx, ZX), nty = ztiles(g.ny, ZY), nch = zchunks(g);
+  const int per = int(gridDim.x) / NXCD;
+  t.lb = (int(blockIdx.x) % NXCD) * per + int(blockIdx.x) / NXCD;
+  if (t.lb >= ntx * nty * nch) return false;
+  const int ix = t.lb % ntx, iy = (t.lb / ntx) % nty, ic = t.lb / (ntx * nty);
+  t.w = g.nx < ZX ? g.nx : ZX;
+  t.h = g.ny < ZY ? g.ny : ZY;
+  t.xo = ix * ZX;
+  t.yo = iy * ZY;
+  t.x0 = t.xo < g.nx - t.w ? t.xo : g.nx - t.w;
+  t.y0 = t.yo < g.ny - t.h ? t.yo : g.ny - t.h;
+  t.z0 = int((long long)ic * g.nz / nch);
+  t.z1 = int((long long)(ic + 1) * g.nz / nch);
+  return true;
+}
+
+// coordinate c of an axis of n nodes, wrapped on a periodic axis, -1 beyond a
+// non-periodic one (c is at most 2 nodes outside, and n >= 3)
+__device__ inline int axc(int c, int n, int per) {
+  if (c < 0) return per ? c + n : -1;
+  if (c >= n) return per ? c - n : -1;
+  return c;
+}
+// -1 / +1 at the low / high end of a non-periodic axis, else 0
+__device__ inline int endof(int c, int n, int per) {
+  return per ? 0 : (c == 0 ? -1 : (c == n - 1 ? 1 : 0));
+}
+__device__ inline int zwrap(int s, int n) { return s < 0 ? s + n : (s >= n ? s - n : s); }
+
+// a column of the tile or of its 1-node ring
+struct ZNode {
+  int on;      // the thread has this column
+  int dx, dy;  // tile-local position, -1 .. w and -1 .. h
+  int lds;     // index in the 2-node halo region
+  int ci;      // index in the 1-node halo region
+  int off;     // in-plane offset j nx + i, -1 off the domain
+  int ex, ey;  // end flags of the column
+};
+
+__device__ inline ZNode znode(const Geo3& g, const ZTile& t, int dx, int dy, bool on) {
+  ZNode n;
+  n.on = on;
+  n.dx = dx;
+  n.dy = dy;
+  n.lds = (dy + 2) * SX + dx + 2;
+  n.ci = (dy + 1) * CXN + dx + 1;
+  const int x = axc(t.x0 + dx, g.nx, g.periodic & 1), y = axc(t.y0 + dy, g.ny, g.periodic & 2);
+  n.off = (x < 0 || y < 0) ? -1 : y * g.nx + x;
+  n.ex = x < 0 ? 0 : endof(x, g.nx, g.periodic & 1);
+  n.ey = y < 0 ? 0 : endof(y, g.ny, g.periodic & 2);
+  return n;
+}
+
+// the thread's column of the ring around the tile; ring positions are dealt
+// round-robin over the four waves
+__device__ inline ZNode zring(const Geo3& g, const ZTile& t) {
+  const int tid = int(threadIdx.x);
+  const int r = (tid % 64) * (ZT / 64) + tid / 64;
+  const int a = t.w + 2;
+  int dx, dy;
+  if (r < a) {
+    dx = r - 1;
+    dy = -1;
+  } else if (r < 2 * a) {
+    dx = r - a - 1;
+    dy = t.h;
+  } else if (r < 2 * a + t.h) {
+    dx = -1;
+    dy = r - 2 * a;
+  } else {
+    dx = t.w;
+    dy = r - 2 * a - t.h;
+  }
+  const bool on = r < 2 * a + 2 * t.h;
+  return znode(g, t, on ? dx : 0, on ? dy : 0, on);
+}
+
+// in-plane offsets of the thread's elements of the 2-node halo region; -1
+// off the domain or beyond the tile's region
+__device__ inline void zregion(const Geo3& g, const ZTile& t, int off[SRL]) {
+#pragma unroll
+  for (int r = 0; r < SRL; ++r) {
+    const int e = int(threadIdx.x) + r * ZT;
+    const int dx = e % SX - 2, dy = e / SX - 2;
+    off[r] = -1;
+    if (e < NSR && dx < t.w + 2 && dy < t.h + 2) {
+      const int x = axc(t.x0 + dx, g.nx, g.periodic & 1);
+      const int y = axc(t.y0 + dy, g.ny, g.periodic & 2);
+      if (x >= 0 && y >= 0) off[r] = y * g.nx + x;
+    }
+  }
+}
+
+// one plane of NF fields over the thread's region elements (zero where the
+// plane or the node does not exist)
+template <typename R, int NF>
+__device__ inline void zload(const R* const F[NF], bool exists, size_t base, const int off[SRL],
+                             R v[SRL][NF]) {
+#pragma unroll
+  for (int r = 0; r < SRL; ++r)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[r][f] = (exists && off[r] >= 0) ? F[f][base + off[r]] : R(0);
+}
+template <typename R, int NF>
+__device__ inline void zstore(R (*dst)[NSR], const R v[SRL][NF]) {
+#pragma unroll
+  for (int r = 0; r < SRL; ++r) {
+    const int e = int(threadIdx.x) + r * ZT;
+    if (e < NSR)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) dst[f][e] = v[r][f];
+  }
+}
+
+// difference at index i of an LDS field along a stride st: central, or
+// second-order one-sided at the low (e < 0) or high (e > 0) end of an axis
+template <typename R>
+__device__ inline R d1(const R* f, int i, int st, int e) {
+  if (e == 0) return R(0.5) * (f[i + st] - f[i - st]);
+  if (e < 0) return R(0.5) * (R(-3) * f[i] + R(4) * f[i + st] - f[i + 2 * st]);
+  return R(0.5) * (R(3) * f[i] - R(4) * f[i - st] + f[i - 2 * st]);
+}
+
+// ---------------------------------------------------------------------------
 // LKS step
 // ---------------------------------------------------------------------------
+// Per plane s of the march, every column of the tile and its ring forms the
+// coefficients a0 = drho - 3/2 u.u, P = 9/2 u u + A (grad u + grad u^T),
+// G = 3 T u + B grad T and the 19 equilibria f'_q = w_q [a0 + 3 c.u + c.P.c],
+// g_q = w_q [T + c.G] of its node (eq:feq2, eq:geq2). The values with an x or
+// y component go through LDS to the column they stream to; every column adds
+// what it receives from plane s to the moments of planes s - 1, s, s + 1 that
+// it keeps in registers (the pull of f_i^eq(x - c_i)). Plane s - 1 is then
+// complete. A source off the domain sends zeros, so a face node's sums over
+// the directions it receives are rho + sg (c_n . f) with n its normal.
 template <typename R, bool TH>
-__global__ __launch_bounds__(NT3) void eq3_kernel(Geo3 g, Fwd3Args<R> a) {
-  const int k = node3(g.N);
-  if (k < 0) return;
-  const P3 p = decode(g, k);
-  const size_t N = size_t(g.N);
-  const R* uf[3] = {a.s0[1], a.s0[2], a.s0[3]};
-  R u[3], G[3][3];
+struct FwdZLds {
+  R st[2][TH ? 5 : 4][NSR];  // drho, u (3), T of planes s and s + 1
+  R fq[16][ZT];              // f'_q arriving at each column
+  R gq[TH ? 16 : 1][ZT];     // g_q arriving at each column
+  double red[ZT / 64];
+};
+
+// moments of three planes (s - 1, s, s + 1) of a column
+template <typename R, bool TH>
+struct FwdAcc {
+  R r[3], U[3][3], T[3], Q[3][3];
+};
+
+template <typename R, bool TH>
+__device__ inline void facc_add(FwdAcc<R, TH>& A, int q, R f, R gv) {
+  const int sl = QZ[q] + 1;
+  A.r[sl] += f;
+  if (QX[q]) A.U[sl][0] += R(QX[q]) * f;
+  if (QY[q]) A.U[sl][1] += R(QY[q]) * f;
+  if (QZ[q]) A.U[sl][2] += R(QZ[q]) * f;
+  if constexpr (TH) {
+    A.T[sl] += gv;
+    if (QX[q]) A.Q[sl][0] += R(QX[q]) * gv;
+    if (QY[q]) A.Q[sl][1] += R(QY[q]) * gv;
+    if (QZ[q]) A.Q[sl][2] += R(QZ[q]) * gv;
+  }
+}
+
+template <typename R, bool TH>
+__device__ inline void facc_shift(FwdAcc<R, TH>& A) {
+  A.r[0] = A.r[1];
+  A.r[1] = A.r[2];
+  A.r[2] = R(0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    u[c] = uf[c][k];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) G[c][b] = dd(g, uf[c], p, k, b);
+    A.U[0][c] = A.U[1][c];
+    A.U[1][c] = A.U[2][c];
+    A.U[2][c] = R(0);
   }
-  const R A = R(g.A);
-  const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  R* e = a.e;
-  e[k] = a.s0[0][k] - R(1.5) * uu;
-#pragma unroll
-  for (int x = 0; x < 3; ++x)
-#pragma unroll
-    for (int y = x; y < 3; ++y)
-      e[(1 + SI[x][y]) * N + k] = R(4.5) * u[x] * u[y] + A * (G[x][y] + G[y][x]);
   if constexpr (TH) {
-    const R T = a.s0[4][k], Bk = a.B[k];
+    A.T[0] = A.T[1];
+    A.T[1] = A.T[2];
+    A.T[2] = R(0);
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      e[(7 + c) * N + k] = R(3) * T * u[c] + Bk * dd(g, a.s0[4], p, k, c);
+    for (int c = 0; c < 3; ++c) {
+      A.Q[0][c] = A.Q[1][c];
+      A.Q[1][c] = A.Q[2][c];
+      A.Q[2][c] = R(0);
+    }
   }
 }
 
-// new-level values of a node that is not an edge or corner node
-template <typename R, bool TH>
-__device__ void lks3_node(const Geo3& g, const Fwd3Args<R>& a, P3 p, int k, int ne, int o,
-                          R& d_out, R u_out[3], R& T_out) {
-  const size_t N = size_t(g.N);
-  const R* e = a.e;
-  const int ax = o >> 1, sg = (o & 1) ? 1 : -1;
-  R rho = R(0), U[3] = {R(0), R(0), R(0)}, Ts = R(0);
-  R S0 = R(0), Sp = R(0), S0g = R(0), Spg = R(0);
+// z difference of a field at plane s from its values at s - 1 (zp), s (fc)
+// and s + 1 (zn); z2 is plane 2 (low end) or nz - 3 (high end)
+template <typename R>
+__device__ inline R dz3(int ez, R fc, R zp, R zn, R z2) {
+  if (ez < 0) return R(0.5) * (R(-3) * fc + R(4) * zn - z2);
+  if (ez > 0) return R(0.5) * (R(3) * fc - R(4) * zp + z2);
+  return R(0.5) * (zn - zp);
+}
+
+// equilibria of the node of column n at plane sw, sent to the columns they
+// stream to; the own column keeps its c = 0 and c = +-e_z values. zp holds
+// u and T of plane sw - 1 and is advanced to plane sw.
+template <typename R, bool TH, bool OWN>
+__device__ inline void fwd_src(const Geo3& g, const Fwd3Args<R>& a, FwdZLds<R, TH>& L,
+                               const ZTile& t, const ZNode& n, int cur, int nxt, bool hn, int sw,
+                               size_t nxy, R Bk, R zp[4], FwdAcc<R, TH>& A) {
+  if (!n.on) return;
+  R fv[19], gv[19];
+  if (n.off < 0) {
 #pragma unroll
-  for (int q = 0; q < 19; ++q) {
-    const int cq[3] = {QX[q], QY[q], QZ[q]};
-    int cn = 0;
-    if (ne) cn = sg * (ax == 0 ? cq[0] : (ax == 1 ? cq[1] : cq[2]));
-    if (cn < 0) continue;
-    const int z = nbr(g, p, -cq[0], -cq[1], -cq[2]);
-    R cu = R(0), cpc = R(0);
+    for (int q = 0; q < 19; ++q) fv[q] = gv[q] = R(0);
+  } else {
+    const int i = n.lds;
+    const int ez = endof(sw, g.nz, g.periodic & 4);
+    R u[3], zn[4] = {R(0), R(0), R(0), R(0)}, z2[4] = {R(0), R(0), R(0), R(0)};
+    constexpr int NZ = TH ? 4 : 3;
 #pragma unroll
-    for (int x = 0; x < 3; ++x) {
-      if (!cq[x]) continue;
-      cu += R(cq[x]) * a.s0[1 + x][z];
-      cpc += e[(1 + SI[x][x]) * N + z];
+    for (int c = 0; c < 3; ++c) u[c] = L.st[cur][1 + c][i];
+    const R T = TH ? L.st[cur][4][i] : R(0);
+    if (hn)
 #pragma unroll
-      for (int y = x + 1; y < 3; ++y)
-        if (cq[y]) cpc += R(2 * cq[x] * cq[y]) * e[(1 + SI[x][y]) * N + z];
+      for (int c = 0; c < NZ; ++c) zn[c] = L.st[nxt][1 + c][i];
+    if (ez) {
+      const size_t b2 = size_t(ez < 0 ? 2 : g.nz - 3) * nxy + size_t(n.off);
+#pragma unroll
+      for (int c = 0; c < NZ; ++c) z2[c] = a.s0[1 + c][b2];
     }
-    const R f = R(QW[q]) * (e[z] + R(3) * cu + cpc);
-    rho += f;
+    R G[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      G[c][0] = d1(L.st[cur][1 + c], i, 1, n.ex);
+      G[c][1] = d1(L.st[cur][1 + c], i, SX, n.ey);
+      G[c][2] = dz3(ez, u[c], zp[c], zn[c], z2[c]);
+    }
+    const R A_ = R(g.A);
+    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const R a0 = L.st[cur][0][i] - R(1.5) * uu;
+    R P[6];
 #pragma unroll
     for (int x = 0; x < 3; ++x)
-      if (cq[x]) U[x] += R(cq[x]) * f;
-    R gq = R(0);
+#pragma unroll
+      for (int y = x; y < 3; ++y) P[SI[x][y]] = R(4.5) * u[x] * u[y] + A_ * (G[x][y] + G[y][x]);
+    R Gt[3] = {R(0), R(0), R(0)};
     if constexpr (TH) {
-      R cg = R(0);
+      const R dT[3] = {d1(L.st[cur][4], i, 1, n.ex), d1(L.st[cur][4], i, SX, n.ey),
+                       dz3(ez, T, zp[3], zn[3], z2[3])};
 #pragma unroll
-      for (int x = 0; x < 3; ++x)
-        if (cq[x]) cg += R(cq[x]) * e[(7 + x) * N + z];
-      gq = R(QW[q]) * (a.s0[4][z] + cg);
-      Ts += gq;
+      for (int c = 0; c < 3; ++c) Gt[c] = R(3) * T * u[c] + Bk * dT[c];
+      zp[3] = T;
     }
-    if (ne) {
-      if (cn == 0) { S0 += f; S0g += gq; }
-      else { Sp += f; Spg += gq; }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) zp[c] = u[c];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+      const int cq[3] = {QX[q], QY[q], QZ[q]};
+      R cu = R(0), cpc = R(0), cg = R(0);
+#pragma unroll
+      for (int x = 0; x < 3; ++x) {
+        if (!cq[x]) continue;
+        cu += R(cq[x]) * u[x];
+        cpc += P[SI[x][x]];
+#pragma unroll
+        for (int y = x + 1; y < 3; ++y)
+          if (cq[y]) cpc += R(2 * cq[x] * cq[y]) * P[SI[x][y]];
+        if constexpr (TH) cg += R(cq[x]) * Gt[x];
+      }
+      fv[q] = R(QW[q]) * (a0 + R(3) * cu + cpc);
+      gv[q] = TH ? R(QW[q]) * (T + cg) : R(0);
     }
   }
-  const int m = a.mask[k];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int q = LQ[j];
+    const int px = n.dx + QX[q], py = n.dy + QY[q];
+    if (px >= 0 && px < t.w && py >= 0 && py < t.h) {
+      L.fq[j][py * ZX + px] = fv[q];
+      if constexpr (TH) L.gq[j][py * ZX + px] = gv[q];
+    }
+  }
+  if constexpr (OWN) {
+    facc_add(A, 0, fv[0], gv[0]);
+    facc_add(A, 5, fv[5], gv[5]);
+    facc_add(A, 6, fv[6], gv[6]);
+  }
+}
+
+// component ax of (v0, v1, v2)
+template <typename R>
+__device__ inline R pick3(int ax, R v0, R v1, R v2) {
+  return (ax == 0 ? v0 : R(0)) + (ax == 1 ? v1 : R(0)) + (ax == 2 ? v2 : R(0));
+}
+
+// new-level values of a node from its moments: the implicit Brinkman
+// division inside, the velocity / pressure closures and the temperature
+// closure on faces; edge and corner nodes are copied afterwards
+template <typename R, bool TH>
+__device__ inline void fwd3_out(const Geo3& g, const Fwd3Args<R>& a, size_t k, int ex, int ey,
+                                int ez, int m, R s, R Tb, R rho, const R U[3], R Ts,
+                                const R Q[3], double& part) {
+  const int ne = (ex != 0) + (ey != 0) + (ez != 0);
+  if (ne >= 2) return;
+  R d, u[3], T = R(0);
   if (!ne) {
-    const R s = a.inv1pa[k];
-    d_out = rho;
+    d = rho;
 #pragma unroll
-    for (int x = 0; x < 3; ++x) u_out[x] = U[x] * s;
-    if constexpr (TH) T_out = ((m >> 2) & 3) == THERM_DIRICHLET3 ? a.Tb[k] : Ts;
-    return;
-  }
-  R un;
-  if ((m & 3) == FLOW_VELOCITY3) {
-    const double fac = a.ufac[a.level_out];
-#pragma unroll
-    for (int x = 0; x < 3; ++x) u_out[x] = R(double(a.ub[x][k]) * fac);
-    un = R(sg) * (ax == 0 ? u_out[0] : (ax == 1 ? u_out[1] : u_out[2]));
-    d_out = S0 + R(2) * Sp - un;
+    for (int x = 0; x < 3; ++x) u[x] = U[x] * s;
+    if constexpr (TH) T = ((m >> 2) & 3) == THERM_DIRICHLET3 ? Tb : Ts;
   } else {
-    const R dro = R(g.drho_out);
-    d_out = dro;
-    un = S0 + R(2) * Sp - dro;
+    const int ax = ex ? 0 : (ey ? 1 : 2);
+    const int sg = ex ? ex : (ey ? ey : ez);
+    // components along the normal as masked sums (no indexing by ax, which
+    // would move the register arrays to memory)
+    const R Un = pick3(ax, U[0], U[1], U[2]);
+    const R sn = rho + R(sg) * Un;  // S0 + 2 S+ over the received directions
+    R un;
+    if ((m & 3) == FLOW_VELOCITY3) {
+      const double fac = a.ufac[a.level_out];
 #pragma unroll
-    for (int x = 0; x < 3; ++x) u_out[x] = x == ax ? R(sg) * un : R(0);
+      for (int x = 0; x < 3; ++x) u[x] = R(double(a.ub[x][k]) * fac);
+      un = R(sg) * pick3(ax, u[0], u[1], u[2]);
+      d = sn - un;
+    } else {
+      const R dro = R(g.drho_out);
+      d = dro;
+      un = sn - dro;
+#pragma unroll
+      for (int x = 0; x < 3; ++x) u[x] = x == ax ? R(sg) * un : R(0);
+    }
+    if constexpr (TH) {
+      const R Qn = pick3(ax, Q[0], Q[1], Q[2]);
+      if (((m >> 2) & 3) == THERM_DIRICHLET3) T = Tb;
+      else T = (Ts + R(sg) * Qn) / (R(1) + un);
+    }
   }
-  if constexpr (TH) {
-    if (((m >> 2) & 3) == THERM_DIRICHLET3) T_out = a.Tb[k];
-    else T_out = (S0g + R(2) * Spg) / (R(1) + un);
+  a.s1[0][k] = d;
+  a.s1[1][k] = u[0];
+  a.s1[2][k] = u[1];
+  a.s1[3][k] = u[2];
+  if constexpr (TH) a.s1[4][k] = T;
+  if (a.acc) {
+    if (a.objective == 1) {
+      if (m & TAG_PROBE3) part += double(u[0]) * double(T);
+    } else {
+      if (m & TAG_J_INLET3) part += double(d);
+      if (m & TAG_J_OUTLET3) part -= double(d);
+    }
   }
 }
 
 template <typename R, bool TH>
-__global__ __launch_bounds__(NT3) void lks3_kernel(Geo3 g, Fwd3Args<R> a) {
-  __shared__ double red[NT3 / 64];
-  const int k = node3(g.N);
+__global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
+  constexpr int NF = TH ? 5 : 4;
+  __shared__ FwdZLds<R, TH> L;
+  ZTile t;
+  if (!ztile(g, t)) return;
+  const int tid = int(threadIdx.x), lx = tid % ZX, ly = tid / ZX;
+  const int pz = g.periodic & 4;
+  const size_t nxy = size_t(g.nx) * size_t(g.ny);
+  int roff[SRL];
+  zregion(g, t, roff);
+  const ZNode n0 = znode(g, t, lx, ly, lx < t.w && ly < t.h);
+  const ZNode n1 = zring(g, t);
+  const bool own = n0.on && t.x0 + lx >= t.xo && t.y0 + ly >= t.yo;
+  // source planes: one beyond the output range on each side where it exists
+  const int sb = (t.z0 == 0 && !pz) ? 0 : t.z0 - 1;
+  const int se = (t.z1 == g.nz && !pz) ? g.nz - 1 : t.z1;
+  const R* F[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) F[f] = a.s0[f];
+  R v[SRL][NF];
+  zload<R, NF>(F, true, size_t(zwrap(sb, g.nz)) * nxy, roff, v);
+  zstore<R, NF>(L.st[0], v);
+  auto has = [&](int s) { return pz || (s >= 0 && s < g.nz); };
+  if (has(sb + 1)) zload<R, NF>(F, true, size_t(zwrap(sb + 1, g.nz)) * nxy, roff, v);
+  R zp0[4] = {R(0), R(0), R(0), R(0)}, zp1[4] = {R(0), R(0), R(0), R(0)};
+  if (has(sb - 1)) {
+    const size_t b = size_t(zwrap(sb - 1, g.nz)) * nxy;
+#pragma unroll
+    for (int c = 0; c < NF - 1; ++c) {
+      if (n0.on && n0.off >= 0) zp0[c] = F[1 + c][b + size_t(n0.off)];
+      if (n1.on && n1.off >= 0) zp1[c] = F[1 + c][b + size_t(n1.off)];
+    }
+  }
+  // per-node inputs one iteration ahead: B of the source nodes, class,
+  // Brinkman factor and prescribed temperature of the output node
+  auto node_in = [&](int s, R& b0, R& b1, int& mk, R& ip, R& tb) {
+    b0 = b1 = ip = tb = R(0);
+    mk = 0;
+    if (!has(s)) return;
+    const size_t base = size_t(zwrap(s, g.nz)) * nxy;
+    if constexpr (TH) {
+      if (n0.on && n0.off >= 0) b0 = a.B[base + size_t(n0.off)];
+      if (n1.on && n1.off >= 0) b1 = a.B[base + size_t(n1.off)];
+    }
+    const int p = s - 1;
+    if (own && p >= t.z0 && p < t.z1) {
+      const size_t k = size_t(p) * nxy + size_t(n0.off);
+      mk = a.mask[k];
+      ip = a.inv1pa[k];
+      if constexpr (TH) tb = a.Tb[k];
+    }
+  };
+  R b0, b1, ip, tb;
+  int mk;
+  node_in(sb, b0, b1, mk, ip, tb);
+  FwdAcc<R, TH> A = {};
   double part = 0.0;
-  if (k >= 0) {
-    const P3 p = decode(g, k);
-    int o;
-    const int ne = ends(g, p, &o);
-    R d, u[3], T = R(0);
-    if (ne >= 2) {
-      const P3 s = copy_src(g, p);
-      int os;
-      const int nes = ends(g, s, &os);
-      lks3_node<R, TH>(g, a, s, (s.l * g.ny + s.j) * g.nx + s.i, nes, os, d, u, T);
-      u[0] = u[1] = u[2] = R(0);
-    } else {
-      lks3_node<R, TH>(g, a, p, k, ne, o, d, u, T);
+  for (int s = sb; s <= se; ++s) {
+    const int it = s - sb, cur = it & 1, nxt = cur ^ 1;
+    const bool hn = has(s + 1);
+    if (hn) zstore<R, NF>(L.st[nxt], v);
+    __syncthreads();
+    if (has(s + 2)) zload<R, NF>(F, true, size_t(zwrap(s + 2, g.nz)) * nxy, roff, v);
+    const R cb0 = b0, cb1 = b1, cip = ip, ctb = tb;
+    const int cmk = mk;
+    if (s + 1 <= se) node_in(s + 1, b0, b1, mk, ip, tb);
+    const int sw = zwrap(s, g.nz);
+    fwd_src<R, TH, true>(g, a, L, t, n0, cur, nxt, hn, sw, nxy, cb0, zp0, A);
+    fwd_src<R, TH, false>(g, a, L, t, n1, cur, nxt, hn, sw, nxy, cb1, zp1, A);
+    __syncthreads();
+    if (n0.on) {
+      const int me = ly * ZX + lx;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) facc_add(A, LQ[j], L.fq[j][me], TH ? L.gq[j][me] : R(0));
     }
-    a.s1[0][k] = d;
-    a.s1[1][k] = u[0];
-    a.s1[2][k] = u[1];
-    a.s1[3][k] = u[2];
-    if constexpr (TH) a.s1[4][k] = T;
-    if (a.acc) {
-      const int m = a.mask[k];
-      if (a.objective == 1) {
-        if (m & TAG_PROBE3) part = double(u[0]) * double(T);
-      } else {
-        if (m & TAG_J_INLET3) part += double(d);
-        if (m & TAG_J_OUTLET3) part -= double(d);
-      }
-    }
+    const int p = s - 1;
+    if (own && p >= t.z0 && p < t.z1)
+      fwd3_out<R, TH>(g, a, size_t(p) * nxy + size_t(n0.off), n0.ex, n0.ey,
+                      endof(p, g.nz, pz), cmk, cip, ctb, A.r[0], A.U[0], A.T[0], A.Q[0], part);
+    facc_shift(A);
+  }
+  if (!pz && se == g.nz - 1 && own) {
+    const size_t k = size_t(g.nz - 1) * nxy + size_t(n0.off);
+    fwd3_out<R, TH>(g, a, k, n0.ex, n0.ey, 1, a.mask[k], a.inv1pa[k], TH ? a.Tb[k] : R(0),
+                    A.r[0], A.U[0], A.T[0], A.Q[0], part);
   }
   if (a.acc) {
-    const double s = block_sum3(part, red);
-    if (threadIdx.x == 0) a.acc[logical_block()] += s;
+    const double s = block_sum3(part, L.red);
+    if (tid == 0) a.acc[t.lb] += s;
   }
+}
+
+// edge and corner nodes: density and temperature of the node one step
+// inwards along y and z, zero velocity
+template <typename R, bool TH>
+__global__ __launch_bounds__(NT3) void copy3_kernel(Geo3 g, const int* __restrict__ list, int n,
+                                                    R* d, R* ux, R* uy, R* uz, R* T) {
+  const int i = int(blockIdx.x) * NT3 + int(threadIdx.x);
+  if (i >= n) return;
+  const int k = list[i];
+  const P3 s = copy_src(g, decode(g, k));
+  const int ks = (s.l * g.ny + s.j) * g.nx + s.i;
+  d[k] = d[ks];
+  ux[k] = R(0);
+  uy[k] = R(0);
+  uz[k] = R(0);
+  if constexpr (TH) T[k] = T[ks];
 }
 
 // ---------------------------------------------------------------------------
 // ALKS step
 // ---------------------------------------------------------------------------
+// raw moments of the 19 pulled values f~_q, g~_q, summed by weight class
+// (rest, the six axis directions, and the three diagonal planes):
+// rho~, u~ (3), s~ xx xy xz yy yz zz, T~, q~ (3)
+template <typename R, bool TH>
+__device__ inline void mom19(const R f[19], const R g[19], R M[14]) {
+  const R w0 = R(1.0 / 3), w1 = R(1.0 / 18), w2 = R(1.0 / 36);
+  // axis pairs (1,2) x, (3,4) y, (5,6) z
+  const R sa[3] = {f[1] + f[2], f[3] + f[4], f[5] + f[6]};
+  const R da[3] = {f[1] - f[2], f[3] - f[4], f[5] - f[6]};
+  // diagonal planes xy (7-10), xz (11-14), yz (15-18): directions
+  // (+,+), (-,-), (+,-), (-,+) in the plane's two axes
+  R ps[3], sab[3], d1[3], d2[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const int q = 7 + 4 * p;
+    const R s1 = f[q] + f[q + 1], s2 = f[q + 2] + f[q + 3];
+    d1[p] = f[q] - f[q + 1];
+    d2[p] = f[q + 2] - f[q + 3];
+    ps[p] = s1 + s2;
+    sab[p] = s1 - s2;
+  }
+  M[0] = w0 * f[0] + w1 * (sa[0] + sa[1] + sa[2]) + w2 * (ps[0] + ps[1] + ps[2]);
+  M[1] = w1 * da[0] + w2 * ((d1[0] + d2[0]) + (d1[1] + d2[1]));
+  M[2] = w1 * da[1] + w2 * ((d1[0] - d2[0]) + (d1[2] + d2[2]));
+  M[3] = w1 * da[2] + w2 * ((d1[1] - d2[1]) + (d1[2] - d2[2]));
+  M[4] = w1 * sa[0] + w2 * (ps[0] + ps[1]);
+  M[5] = w2 * sab[0];
+  M[6] = w2 * sab[1];
+  M[7] = w1 * sa[1] + w2 * (ps[0] + ps[2]);
+  M[8] = w2 * sab[2];
+  M[9] = w1 * sa[2] + w2 * (ps[1] + ps[2]);
+  if constexpr (TH) {
+    const R ga[3] = {g[1] + g[2], g[3] + g[4], g[5] + g[6]};
+    const R ha[3] = {g[1] - g[2], g[3] - g[4], g[5] - g[6]};
+    R gs[3], e1[3], e2[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int q = 7 + 4 * p;
+      gs[p] = (g[q] + g[q + 1]) + (g[q + 2] + g[q + 3]);
+      e1[p] = g[q] - g[q + 1];
+      e2[p] = g[q + 2] - g[q + 3];
+    }
+    M[10] = w0 * g[0] + w1 * (ga[0] + ga[1] + ga[2]) + w2 * (gs[0] + gs[1] + gs[2]);
+    M[11] = w1 * ha[0] + w2 * ((e1[0] + e2[0]) + (e1[1] + e2[1]));
+    M[12] = w1 * ha[1] + w2 * ((e1[0] - e2[0]) + (e1[2] + e2[2]));
+    M[13] = w1 * ha[2] + w2 * ((e1[1] - e2[1]) + (e1[2] - e2[2]));
+  } else {
+    M[10] = M[11] = M[12] = M[13] = R(0);
+  }
+}
+
+// least-squares fill of a face node with orientation o: the moments of its
+// five missing directions from the 14 received ones (zero in f, g at the
+// missing directions), the J seed and the thermal closure
+template <typename R, bool TH>
+__device__ void face_fill(const Adj3Args<R>& a, int k, int m, int o, R Tn, const R f[19],
+                          const R gq[19], R M[14]) {
+  const int ax = o >> 1, sg = (o & 1) ? 1 : -1;
+  const FaceOp3& op = a.ops[o];
+  R kappa = R(0), gu[5] = {R(0), R(0), R(0), R(0), R(0)};
+  if constexpr (TH) {
+    if (((m >> 2) & 3) == THERM_DIRICHLET3) {
+#pragma nounroll
+      for (int c = 0; c < 5; ++c) {
+        R t = R(0);
+#pragma unroll
+        for (int q = 0; q < 19; ++q) t += R(op.Ld[c][q]) * gq[q];
+        gu[c] = t;
+      }
+    } else {
+      const R* un_src = ax == 0 ? a.u[0] : (ax == 1 ? a.u[1] : a.u[2]);
+      const R un = R(sg) * un_src[k];
+      R num = R(0);
+#pragma unroll
+      for (int q = 0; q < 19; ++q) num += (R(op.ga[q]) - un * R(op.ge[q])) * gq[q];
+      const R den = R(op.A0) - R(2) * un * R(op.A1) + un * un * R(op.A2);
+      kappa = -num / den;
+#pragma nounroll
+      for (int c = 0; c < 5; ++c) {
+        R t = R(0);
+#pragma unroll
+        for (int q = 0; q < 19; ++q) t += R(op.Lg0[c][q]) * gq[q];
+        gu[c] = t - kappa * (R(op.hc[c]) - un * R(op.h1[c]));
+      }
+    }
+  }
+  R s = R(0);
+  if (m & TAG_J_INLET3) s += R(a.seed_dp / 3.0);
+  if (m & TAG_J_OUTLET3) s -= R(a.seed_dp / 3.0);
+  const int v = (m & 3) == FLOW_VELOCITY3 ? 0 : 1;
+  const R kT = kappa * Tn;
+#pragma nounroll
+  for (int c = 0; c < 5; ++c) {
+    R t = R(op.Ls[v][c]) * s + R(op.Lk[v][c]) * kT;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) t += R(op.Lf[v][c][q]) * f[q];
+    const R wf = R(op.uw[c]) * t;
+    const R cx[3] = {R(op.uc[c][0]), R(op.uc[c][1]), R(op.uc[c][2])};
+    M[0] += wf;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      M[1 + x] += cx[x] * wf;
+#pragma unroll
+      for (int y = x; y < 3; ++y) M[4 + SI[x][y]] += cx[x] * cx[y] * wf;
+    }
+    if constexpr (TH) {
+      const R wg = R(op.uw[c]) * gu[c];
+      M[10] += wg;
+#pragma unroll
+      for (int x = 0; x < 3; ++x) M[11 + x] += cx[x] * wg;
+    }
+  }
+}
+
+// local terms of the adjoint moments: the probe seed, the prescribed
+// temperature inside, the T q~ coupling and the Brinkman factor of u~
+template <typename R, bool TH>
+__device__ inline void adj_local(const Adj3Args<R>& a, int k, int m, int ne, R Tn, R s,
+                                 R M[14]) {
+  if constexpr (TH) {
+    const bool probe = (m & TAG_PROBE3) && a.seed_heat != 0.0;
+    if (probe) M[10] -= R(a.seed_heat) * a.u[0][k];
+    if (!ne && ((m >> 2) & 3) == THERM_DIRICHLET3) {
+      M[10] = R(0);
+      M[11] = M[12] = M[13] = R(0);
+    }
+#pragma unroll
+    for (int x = 0; x < 3; ++x) M[1 + x] += Tn * M[11 + x];
+    if (probe) M[1] -= R(a.seed_heat / 3.0) * Tn;
+  }
+#pragma unroll
+  for (int x = 0; x < 3; ++x) M[1 + x] *= s;
+}
+
+// Two node-parallel passes per ALKS step, the neighbour gathers served by
+// the L1/L2 caches:
+//   pass 1  per node the pull of f~_i^eq = rho~ + c_i.V and g~_i^eq = Theta
+//           from x + c_i (eq:afeq, eq:ageq), the face least-squares
+//           completion, the local terms and the moments rho~, u~, s~, T~, q~;
+//   pass 2  per node V and Theta of the new level from the moments and the
+//           sensitivity 3 alpha' u.u~ - B' grad T.q~.
+// moments of the node p (not an edge or corner node) with orientation o if
+// it is a face node
 template <typename R, bool TH>
 __device__ void alks3_node(const Geo3& g, const Adj3Args<R>& a, P3 p, int k, int ne, int o,
-                           R mom[14]) {
+                           R M[14]) {
   const int ax = o >> 1, sg = (o & 1) ? 1 : -1;
-  const int m = a.mask[k];
   R f[19], gq[19];
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
@@ -355,106 +841,11 @@ __device__ void alks3_node(const Geo3& g, const Adj3Args<R>& a, P3 p, int k, int
     f[q] = v;
     if constexpr (TH) gq[q] = a.p0[4][z];
   }
-  R r = R(0), U[3] = {R(0), R(0), R(0)}, S[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-  R Tt = R(0), qv[3] = {R(0), R(0), R(0)};
-#pragma unroll
-  for (int q = 0; q < 19; ++q) {
-    const int cq[3] = {QX[q], QY[q], QZ[q]};
-    const R wf = R(QW[q]) * f[q];
-    r += wf;
-#pragma unroll
-    for (int x = 0; x < 3; ++x) {
-      if (!cq[x]) continue;
-      U[x] += R(cq[x]) * wf;
-#pragma unroll
-      for (int y = x; y < 3; ++y)
-        if (cq[y]) S[SI[x][y]] += R(cq[x] * cq[y]) * wf;
-    }
-    if constexpr (TH) {
-      const R wg = R(QW[q]) * gq[q];
-      Tt += wg;
-#pragma unroll
-      for (int x = 0; x < 3; ++x)
-        if (cq[x]) qv[x] += R(cq[x]) * wg;
-    }
-  }
+  mom19<R, TH>(f, gq, M);
+  const int m = a.mask[k];
   const R Tn = TH ? a.T[k] : R(0);
-  if (ne) {
-    const FaceOp3& op = a.ops[o];
-    R kappa = R(0), gu[5] = {R(0), R(0), R(0), R(0), R(0)};
-    if constexpr (TH) {
-      if (((m >> 2) & 3) == THERM_DIRICHLET3) {
-#pragma nounroll
-        for (int c = 0; c < 5; ++c) {
-          R t = R(0);
-#pragma unroll
-          for (int q = 0; q < 19; ++q) t += R(op.Ld[c][q]) * gq[q];
-          gu[c] = t;
-        }
-      } else {
-        const R* un_src = ax == 0 ? a.u[0] : (ax == 1 ? a.u[1] : a.u[2]);
-        const R un = R(sg) * un_src[k];
-        R num = R(0);
-#pragma unroll
-        for (int q = 0; q < 19; ++q) num += (R(op.ga[q]) - un * R(op.ge[q])) * gq[q];
-        const R den = R(op.A0) - R(2) * un * R(op.A1) + un * un * R(op.A2);
-        kappa = -num / den;
-#pragma nounroll
-        for (int c = 0; c < 5; ++c) {
-          R t = R(0);
-#pragma unroll
-          for (int q = 0; q < 19; ++q) t += R(op.Lg0[c][q]) * gq[q];
-          gu[c] = t - kappa * (R(op.hc[c]) - un * R(op.h1[c]));
-        }
-      }
-    }
-    R s = R(0);
-    if (m & TAG_J_INLET3) s += R(a.seed_dp / 3.0);
-    if (m & TAG_J_OUTLET3) s -= R(a.seed_dp / 3.0);
-    const int v = (m & 3) == FLOW_VELOCITY3 ? 0 : 1;
-    const R kT = kappa * Tn;
-#pragma nounroll
-    for (int c = 0; c < 5; ++c) {
-      R t = R(op.Ls[v][c]) * s + R(op.Lk[v][c]) * kT;
-#pragma unroll
-      for (int q = 0; q < 19; ++q) t += R(op.Lf[v][c][q]) * f[q];
-      const R wf = R(op.uw[c]) * t;
-      const R cx[3] = {R(op.uc[c][0]), R(op.uc[c][1]), R(op.uc[c][2])};
-      r += wf;
-#pragma unroll
-      for (int x = 0; x < 3; ++x) {
-        U[x] += cx[x] * wf;
-#pragma unroll
-        for (int y = x; y < 3; ++y) S[SI[x][y]] += cx[x] * cx[y] * wf;
-      }
-      if constexpr (TH) {
-        const R wg = R(op.uw[c]) * gu[c];
-        Tt += wg;
-#pragma unroll
-        for (int x = 0; x < 3; ++x) qv[x] += cx[x] * wg;
-      }
-    }
-  }
-  if constexpr (TH) {
-    const bool probe = (m & TAG_PROBE3) && a.seed_heat != 0.0;
-    if (probe) Tt -= R(a.seed_heat) * a.u[0][k];
-    if (!ne && ((m >> 2) & 3) == THERM_DIRICHLET3) {
-      Tt = R(0);
-      qv[0] = qv[1] = qv[2] = R(0);
-    }
-#pragma unroll
-    for (int x = 0; x < 3; ++x) U[x] += Tn * qv[x];
-    if (probe) U[0] -= R(a.seed_heat / 3.0) * Tn;
-  }
-  const R s = a.inv1pa[k];
-  mom[0] = r;
-#pragma unroll
-  for (int x = 0; x < 3; ++x) mom[1 + x] = U[x] * s;
-#pragma unroll
-  for (int c = 0; c < 6; ++c) mom[4 + c] = S[c];
-  mom[10] = Tt;
-#pragma unroll
-  for (int x = 0; x < 3; ++x) mom[11 + x] = qv[x];
+  if (ne) face_fill<R, TH>(a, k, m, o, Tn, f, gq, M);
+  adj_local<R, TH>(a, k, m, ne, Tn, a.inv1pa[k], M);
 }
 
 template <typename R, bool TH>
@@ -534,14 +925,16 @@ __global__ __launch_bounds__(NT3) void alks3_eq_kernel(Geo3 g, Adj3Args<R> a) {
 }
 
 // objective sum over tagged nodes (steady runs): pressure-drop tags of
-// drho, or the probe enthalpy flux u_x T; one block, fixed order
+// drho, or the probe enthalpy flux u_x T. TS blocks stride over the nodes in
+// a fixed order and leave one partial sum each.
+constexpr int TS = 256;
 template <typename R>
 __global__ __launch_bounds__(NT3) void tag_sum3_kernel(Geo3 g, const uint8_t* __restrict__ mask,
                                                        const R* d, const R* ux, const R* T,
-                                                       int objective, double* out) {
+                                                       int objective, double* part) {
   __shared__ double red[NT3 / 64];
   double s = 0.0;
-  for (int k = int(threadIdx.x); k < g.N; k += NT3) {
+  for (int k = int(blockIdx.x) * NT3 + int(threadIdx.x); k < g.N; k += TS * NT3) {
     const int m = mask[k];
     if (objective == 1) {
       if (m & TAG_PROBE3) s += double(ux[k]) * double(T[k]);
@@ -551,7 +944,7 @@ __global__ __launch_bounds__(NT3) void tag_sum3_kernel(Geo3 g, const uint8_t* __
     }
   }
   s = block_sum3(s, red);
-  if (threadIdx.x == 0) out[0] = s;
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 }  // namespace
@@ -559,6 +952,25 @@ __global__ __launch_bounds__(NT3) void tag_sum3_kernel(Geo3 g, const uint8_t* __
 int blocks3(int N) {
   const int b = (N + NT3 - 1) / NT3;
   return NXCD * ((b + NXCD - 1) / NXCD);
+}
+
+int zblocks3(const Geo3& g) { return ztiles(g.nx, ZX) * ztiles(g.ny, ZY) * zchunks(g); }
+
+int copy_nodes3(const Geo3& g, int* out) {
+  const int n3[3] = {g.nx, g.ny, g.nz};
+  int n = 0;
+  for (int l = 0; l < g.nz; ++l)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        const int c[3] = {i, j, l};
+        int ne = 0;
+        for (int ax = 0; ax < 3; ++ax)
+          if (!((g.periodic >> ax) & 1) && (c[ax] == 0 || c[ax] == n3[ax] - 1)) ++ne;
+        if (ne < 2) continue;
+        if (out) out[n] = (l * g.ny + j) * g.nx + i;
+        ++n;
+      }
+  return n;
 }
 
 template <typename R>
@@ -578,13 +990,18 @@ void launch_init3(const Geo3& g, const uint8_t* mask, const R* const ub[3], cons
 
 template <typename R>
 void launch_lks3_step(const Geo3& g, const Fwd3Args<R>& a, hipStream_t s) {
-  const unsigned nb = unsigned(blocks3(g.N));
+  const unsigned nb = unsigned(NXCD * ((zblocks3(g) + NXCD - 1) / NXCD));
+  const unsigned nc = unsigned((a.ncopy + NT3 - 1) / NT3);
   if (g.thermal) {
-    eq3_kernel<R, true><<<nb, NT3, 0, s>>>(g, a);
-    lks3_kernel<R, true><<<nb, NT3, 0, s>>>(g, a);
+    lks3z_kernel<R, true><<<nb, ZT, 0, s>>>(g, a);
+    if (a.ncopy)
+      copy3_kernel<R, true><<<nc, NT3, 0, s>>>(g, a.copy, a.ncopy, a.s1[0], a.s1[1], a.s1[2],
+                                               a.s1[3], a.s1[4]);
   } else {
-    eq3_kernel<R, false><<<nb, NT3, 0, s>>>(g, a);
-    lks3_kernel<R, false><<<nb, NT3, 0, s>>>(g, a);
+    lks3z_kernel<R, false><<<nb, ZT, 0, s>>>(g, a);
+    if (a.ncopy)
+      copy3_kernel<R, false><<<nc, NT3, 0, s>>>(g, a.copy, a.ncopy, a.s1[0], a.s1[1], a.s1[2],
+                                                a.s1[3], a.s1[4]);
   }
 }
 
@@ -602,9 +1019,12 @@ void launch_alks3_step(const Geo3& g, const Adj3Args<R>& a, hipStream_t s) {
 
 template <typename R>
 void launch_tag_sum3(const Geo3& g, const uint8_t* mask, const R* d, const R* ux, const R* T,
-                     int objective, double* out, hipStream_t s) {
-  tag_sum3_kernel<R><<<1, NT3, 0, s>>>(g, mask, d, ux, T, objective, out);
+                     int objective, double* part, double* out, hipStream_t s) {
+  tag_sum3_kernel<R><<<TS, NT3, 0, s>>>(g, mask, d, ux, T, objective, part);
+  launch_sum(part, TS, out, s);
 }
+
+int tag_sum3_parts() { return TS; }
 
 #define LKS3_INSTANTIATE(R)                                                                   \
   template void launch_coef3<R>(const Geo3&, const uint8_t*, const double*, double, double,  \
@@ -614,7 +1034,7 @@ void launch_tag_sum3(const Geo3& g, const uint8_t* mask, const R* d, const R* ux
   template void launch_lks3_step<R>(const Geo3&, const Fwd3Args<R>&, hipStream_t);           \
   template void launch_alks3_step<R>(const Geo3&, const Adj3Args<R>&, hipStream_t);          \
   template void launch_tag_sum3<R>(const Geo3&, const uint8_t*, const R*, const R*, const R*, \
-                                   int, double*, hipStream_t);
+                                   int, double*, double*, hipStream_t);
 LKS3_INSTANTIATE(float)
 LKS3_INSTANTIATE(double)
 

@@ -71,7 +71,9 @@ struct lks_ctx {
   lks::RingOp ops[4];
   lks::FaceOp3* d_ops3 = nullptr;  // D3Q19 face operators (6 orientations)
   lks::FaceOp3 ops3[6];
-  void* E3 = nullptr;    // D3Q19 per-step scratch: equilibrium coefficients / moments
+  int* copy3 = nullptr;  // D3Q19 edge and corner nodes (device)
+  void* M3 = nullptr;    // D3Q19 adjoint moments of one step
+  std::vector<int> copy3h;
   double* acc = nullptr; // per-tile objective accumulators
   double* scal = nullptr;
   int* flag = nullptr;
@@ -123,13 +125,14 @@ int ckpt_fields(const lks_ctx* c) { return c->phys.thermal ? nfields(c) : nfield
 int slot_fields(const lks_ctx* c) { return ckpt_fields(c) - 1; }
 // per-block objective accumulators of an unsteady forward sweep
 int acc_count(const lks_ctx* c) {
-  return c->dim == 3 ? lks::blocks3(c->N) : n_tiles(c->geo);
+  return c->dim == 3 ? lks::zblocks3(c->geo3) : n_tiles(c->geo);
 }
+// D3Q19 adjoint moments between the two passes of a step: 14, 10 without T
+int moments3_fields(const lks_ctx* c) { return c->phys.thermal ? 14 : 10; }
+// (D3Q19 steady runs also take the partial sums of the objective there)
 int acc_capacity(const lks_ctx* c) {
-  return c->dim == 3 ? lks::blocks3(c->N) : max_tiles(c->geo);
+  return c->dim == 3 ? std::max(lks::zblocks3(c->geo3), lks::tag_sum3_parts()) : max_tiles(c->geo);
 }
-// D3Q19 scratch fields: 10 coefficients / moments, 14 with temperature
-int scratch3_fields(const lks_ctx* c) { return c->phys.thermal ? 14 : 10; }
 
 size_t traj_bytes(const lks_ctx* c, int K) {
   const size_t N = size_t(c->N), r = size_t(c->rsz);
@@ -151,7 +154,8 @@ size_t base_bytes(const lks_ctx* c) {
   b += align256(sizeof(double) * acc_capacity(c));
   if (c->dim == 3) {
     b += align256(6 * sizeof(lks::FaceOp3));  // face operators
-    b += align256(size_t(scratch3_fields(c)) * N * r);
+    b += align256(sizeof(int) * c->copy3h.size());  // edge and corner nodes
+    b += align256(size_t(moments3_fields(c)) * N * r);
   } else {
     b += align256(4 * sizeof(lks::RingOp));   // ring operators
   }
@@ -393,7 +397,8 @@ struct Run {
         a.s0[f] = in[f];
         a.s1[f] = out[f];
       }
-      a.e = rp<R>(c->E3);
+      a.copy = c->copy3;
+      a.ncopy = int(c->copy3h.size());
       a.acc = acc;
       a.objective = c->objective;
       lks::launch_lks3_step<R>(c->geo3, a, c->stream);
@@ -514,7 +519,7 @@ struct Run {
     if (c->objective == LKS_OBJ_PRESSURE_DROP) {
       if (c->dim == 3)
         lks::launch_tag_sum3<R>(c->geo3, c->d_mask, cur_field(0), cur_field(1), cur_field(4),
-                                LKS_OBJ_PRESSURE_DROP, c->scal, c->stream);
+                                LKS_OBJ_PRESSURE_DROP, c->acc, c->scal, c->stream);
       else
         lks::launch_pressure_drop<R>(g, c->d_mask, cur_field(0), c->scal, c->stream);
     } else {
@@ -525,7 +530,7 @@ struct Run {
   void probe_heat_steady() {
     if (c->dim == 3)
       lks::launch_tag_sum3<R>(c->geo3, c->d_mask, cur_field(0), cur_field(1), cur_field(4),
-                              LKS_OBJ_HEAT, c->scal, c->stream);
+                              LKS_OBJ_HEAT, c->acc, c->scal, c->stream);
     else
       lks::launch_probe_heat<R>(g, c->d_mask, cur_field(1), cur_field(3), c->scal, c->stream);
   }
@@ -552,7 +557,7 @@ struct Run {
         a.p0[f] = rp<R>(c->P[i0][f]);
         a.p1[f] = rp<R>(c->P[i1][f]);
       }
-      a.m = rp<R>(c->E3);
+      a.m = rp<R>(c->M3);
       a.ops = c->d_ops3;
       a.sens = sens;
       a.sens_mode = sens ? mode : 0;
@@ -767,7 +772,10 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
     g3.A = g.A;
     g3.Bf = g.Bf;
     g3.drho_out = g.drho_out;
+    g3.zc = 16;
     lks::build_face_ops3(g3.A, g3.Bf, c->ops3);
+    c->copy3h.resize(size_t(lks::copy_nodes3(g3, nullptr)));
+    lks::copy_nodes3(g3, c->copy3h.data());
   }
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->budget = mem_budget_bytes;
@@ -820,7 +828,8 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
   c->acc = reinterpret_cast<double*>(take(sizeof(double) * acc_capacity(c)));
   if (nu == 3) {
     c->d_ops3 = reinterpret_cast<lks::FaceOp3*>(take(6 * sizeof(lks::FaceOp3)));
-    c->E3 = take(size_t(scratch3_fields(c)) * N * r);
+    c->copy3 = reinterpret_cast<int*>(take(sizeof(int) * c->copy3h.size()));
+    c->M3 = take(size_t(moments3_fields(c)) * N * r);
   } else {
     c->d_ops = reinterpret_cast<lks::RingOp*>(take(4 * sizeof(lks::RingOp)));
   }
@@ -851,7 +860,10 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
       return st;
   const bool ops_ok = nu == 3
       ? hip_ok(c, hipMemcpyAsync(c->d_ops3, c->ops3, sizeof c->ops3, hipMemcpyHostToDevice,
-                                 c->stream), "upload face operators", &st)
+                                 c->stream), "upload face operators", &st) &&
+            hip_ok(c, hipMemcpyAsync(c->copy3, c->copy3h.data(), sizeof(int) * c->copy3h.size(),
+                                     hipMemcpyHostToDevice, c->stream),
+                   "upload edge nodes", &st)
       : hip_ok(c, hipMemcpyAsync(c->d_ops, c->ops, sizeof c->ops, hipMemcpyHostToDevice,
                                  c->stream), "upload ring operators", &st);
   if (!ops_ok ||
