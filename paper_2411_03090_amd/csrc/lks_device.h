@@ -18,6 +18,16 @@ constexpr int TX = 64;
 constexpr int NTHREADS = 256;
 constexpr int NXCD = 8;  // accelerator complex dies of an MI355X
 
+// Workgroup barrier that orders LDS only. __syncthreads() also waits for every
+// outstanding global load and store of the wave, which would drain prefetches
+// issued one iteration ahead; data exchanged between the waves of a block goes
+// through LDS only, so the fences are limited to the local address space.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // node-class byte
 constexpr int FLOW_INTERIOR = 0, FLOW_VELOCITY = 1, FLOW_PRESSURE = 2, FLOW_CORNER = 3;
 constexpr int THERM_DIRICHLET = 1, THERM_FLUX = 2;
@@ -144,7 +154,7 @@ struct Geo3 {
   int nx, ny, nz, N;
   int periodic;     // bit 0: x, bit 1: y, bit 2: z
   int thermal;
-  int zc;           // z-planes per block of the marching kernels (>= 2)
+  int zc, zca;      // z-planes per block: LKS step, ALKS update pass (>= 2)
   double A;         // eq:A
   double Bf;        // B of the fluid, used on boundary nodes
   double drho_out;  // prescribed outlet density minus 1
@@ -208,6 +218,9 @@ struct Adj3Args {
 int blocks3(int N);  // blocks of a node-parallel 3D launch (multiple of 8)
 // blocks of the z-marching step kernels, each with one objective accumulator
 int zblocks3(const Geo3& g);
+// z-planes per block for the device: each kernel's launch fills whole rounds of
+// its resident blocks
+void zplan3(Geo3& g, int rsz);
 // edge and corner nodes in increasing order (out may be null); returns the count
 int copy_nodes3(const Geo3& g, int* out);
 template <typename R>

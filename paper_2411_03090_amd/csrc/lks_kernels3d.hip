@@ -10,13 +10,13 @@
 // them to the columns that pull them, and closes the plane behind with the
 // implicit Brinkman division and the face closures. Edge and corner nodes
 // are copied by a small second kernel.
-// ALKS step: two node-parallel passes with the neighbour gathers served by
-// the L1/L2 caches:
-//   pass 1  per node the pull of f~_i^eq = rho~ + c_i.V and g~_i^eq = Theta
-//           from x + c_i (eq:afeq, eq:ageq), the face least-squares
-//           completion, the local terms and the moments rho~, u~, s~, T~, q~;
-//   pass 2  per node V and Theta of the new level from the moments and the
-//           sensitivity 3 alpha' u.u~ - B' grad T.q~.
+// ALKS step: two passes.
+//   pass 1  node-parallel: the pull of f~_i^eq = rho~ + c_i.V and
+//           g~_i^eq = Theta from x + c_i (eq:afeq, eq:ageq) through L1/L2,
+//           the face least-squares completion, the local terms and the
+//           moments rho~, u~, s~, T~, q~, stored to a scratch;
+//   pass 2  z-marching: V and Theta of the new level from the moments and
+//           the sensitivity 3 alpha' u.u~ - B' grad T.q~.
 // Blocks are mapped so that each XCD works on a contiguous slab of nodes,
 // keeping the neighbour planes of a block in that XCD's L2.
 #include <hip/hip_runtime.h>
@@ -313,12 +313,12 @@ __device__ inline void zregion(const Geo3& g, const ZTile& t, int off[SRL]) {
 // one plane of NF fields over the thread's region elements (zero where the
 // plane or the node does not exist)
 template <typename R, int NF>
-__device__ inline void zload(const R* const F[NF], bool exists, size_t base, const int off[SRL],
+__device__ inline void zload(const R* const F[NF], bool exists, unsigned base, const int off[SRL],
                              R v[SRL][NF]) {
 #pragma unroll
   for (int r = 0; r < SRL; ++r)
 #pragma unroll
-    for (int f = 0; f < NF; ++f) v[r][f] = (exists && off[r] >= 0) ? F[f][base + off[r]] : R(0);
+    for (int f = 0; f < NF; ++f) v[r][f] = (exists && off[r] >= 0) ? F[f][base + unsigned(off[r])] : R(0);
 }
 template <typename R, int NF>
 __device__ inline void zstore(R (*dst)[NSR], const R v[SRL][NF]) {
@@ -354,7 +354,7 @@ __device__ inline R d1(const R* f, int i, int st, int e) {
 // the directions it receives are rho + sg (c_n . f) with n its normal.
 template <typename R, bool TH>
 struct FwdZLds {
-  R st[2][TH ? 5 : 4][NSR];  // drho, u (3), T of planes s and s + 1
+  R st[2][TH ? 4 : 3][NSR];  // u (3), T of planes s and s + 1
   R fq[16][ZT];              // f'_q arriving at each column
   R gq[TH ? 16 : 1][ZT];     // g_q arriving at each column
   double red[ZT / 64];
@@ -420,7 +420,7 @@ __device__ inline R dz3(int ez, R fc, R zp, R zn, R z2) {
 template <typename R, bool TH, bool OWN>
 __device__ inline void fwd_src(const Geo3& g, const Fwd3Args<R>& a, FwdZLds<R, TH>& L,
                                const ZTile& t, const ZNode& n, int cur, int nxt, bool hn, int sw,
-                               size_t nxy, R Bk, R zp[4], FwdAcc<R, TH>& A) {
+                               unsigned nxy, R dk, R Bk, R zp[4], FwdAcc<R, TH>& A) {
   if (!n.on) return;
   R fv[19], gv[19];
   if (n.off < 0) {
@@ -432,26 +432,26 @@ __device__ inline void fwd_src(const Geo3& g, const Fwd3Args<R>& a, FwdZLds<R, T
     R u[3], zn[4] = {R(0), R(0), R(0), R(0)}, z2[4] = {R(0), R(0), R(0), R(0)};
     constexpr int NZ = TH ? 4 : 3;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = L.st[cur][1 + c][i];
-    const R T = TH ? L.st[cur][4][i] : R(0);
+    for (int c = 0; c < 3; ++c) u[c] = L.st[cur][c][i];
+    const R T = TH ? L.st[cur][TH ? 3 : 0][i] : R(0);
     if (hn)
 #pragma unroll
-      for (int c = 0; c < NZ; ++c) zn[c] = L.st[nxt][1 + c][i];
+      for (int c = 0; c < NZ; ++c) zn[c] = L.st[nxt][c][i];
     if (ez) {
-      const size_t b2 = size_t(ez < 0 ? 2 : g.nz - 3) * nxy + size_t(n.off);
+      const unsigned b2 = unsigned(ez < 0 ? 2 : g.nz - 3) * nxy + unsigned(n.off);
 #pragma unroll
       for (int c = 0; c < NZ; ++c) z2[c] = a.s0[1 + c][b2];
     }
     R G[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      G[c][0] = d1(L.st[cur][1 + c], i, 1, n.ex);
-      G[c][1] = d1(L.st[cur][1 + c], i, SX, n.ey);
+      G[c][0] = d1(L.st[cur][c], i, 1, n.ex);
+      G[c][1] = d1(L.st[cur][c], i, SX, n.ey);
       G[c][2] = dz3(ez, u[c], zp[c], zn[c], z2[c]);
     }
     const R A_ = R(g.A);
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const R a0 = L.st[cur][0][i] - R(1.5) * uu;
+    const R a0 = dk - R(1.5) * uu;
     R P[6];
 #pragma unroll
     for (int x = 0; x < 3; ++x)
@@ -459,7 +459,7 @@ __device__ inline void fwd_src(const Geo3& g, const Fwd3Args<R>& a, FwdZLds<R, T
       for (int y = x; y < 3; ++y) P[SI[x][y]] = R(4.5) * u[x] * u[y] + A_ * (G[x][y] + G[y][x]);
     R Gt[3] = {R(0), R(0), R(0)};
     if constexpr (TH) {
-      const R dT[3] = {d1(L.st[cur][4], i, 1, n.ex), d1(L.st[cur][4], i, SX, n.ey),
+      const R dT[3] = {d1(L.st[cur][TH ? 3 : 0], i, 1, n.ex), d1(L.st[cur][TH ? 3 : 0], i, SX, n.ey),
                        dz3(ez, T, zp[3], zn[3], z2[3])};
 #pragma unroll
       for (int c = 0; c < 3; ++c) Gt[c] = R(3) * T * u[c] + Bk * dT[c];
@@ -511,7 +511,7 @@ __device__ inline R pick3(int ax, R v0, R v1, R v2) {
 // division inside, the velocity / pressure closures and the temperature
 // closure on faces; edge and corner nodes are copied afterwards
 template <typename R, bool TH>
-__device__ inline void fwd3_out(const Geo3& g, const Fwd3Args<R>& a, size_t k, int ex, int ey,
+__device__ inline void fwd3_out(const Geo3& g, const Fwd3Args<R>& a, unsigned k, int ex, int ey,
                                 int ez, int m, R s, R Tb, R rho, const R U[3], R Ts,
                                 const R Q[3], double& part) {
   const int ne = (ex != 0) + (ey != 0) + (ez != 0);
@@ -566,13 +566,13 @@ __device__ inline void fwd3_out(const Geo3& g, const Fwd3Args<R>& a, size_t k, i
 
 template <typename R, bool TH>
 __global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
-  constexpr int NF = TH ? 5 : 4;
+  constexpr int NF = TH ? 4 : 3;  // u (3), T in the LDS ring
   __shared__ FwdZLds<R, TH> L;
   ZTile t;
   if (!ztile(g, t)) return;
   const int tid = int(threadIdx.x), lx = tid % ZX, ly = tid / ZX;
   const int pz = g.periodic & 4;
-  const size_t nxy = size_t(g.nx) * size_t(g.ny);
+  const unsigned nxy = unsigned(g.nx) * unsigned(g.ny);
   int roff[SRL];
   zregion(g, t, roff);
   const ZNode n0 = znode(g, t, lx, ly, lx < t.w && ly < t.h);
@@ -583,58 +583,62 @@ __global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
   const int se = (t.z1 == g.nz && !pz) ? g.nz - 1 : t.z1;
   const R* F[NF];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) F[f] = a.s0[f];
+  for (int f = 0; f < NF; ++f) F[f] = a.s0[1 + f];
   R v[SRL][NF];
-  zload<R, NF>(F, true, size_t(zwrap(sb, g.nz)) * nxy, roff, v);
+  zload<R, NF>(F, true, unsigned(zwrap(sb, g.nz)) * nxy, roff, v);
   zstore<R, NF>(L.st[0], v);
   auto has = [&](int s) { return pz || (s >= 0 && s < g.nz); };
-  if (has(sb + 1)) zload<R, NF>(F, true, size_t(zwrap(sb + 1, g.nz)) * nxy, roff, v);
+  if (has(sb + 1)) zload<R, NF>(F, true, unsigned(zwrap(sb + 1, g.nz)) * nxy, roff, v);
   R zp0[4] = {R(0), R(0), R(0), R(0)}, zp1[4] = {R(0), R(0), R(0), R(0)};
   if (has(sb - 1)) {
-    const size_t b = size_t(zwrap(sb - 1, g.nz)) * nxy;
+    const unsigned b = unsigned(zwrap(sb - 1, g.nz)) * nxy;
 #pragma unroll
-    for (int c = 0; c < NF - 1; ++c) {
-      if (n0.on && n0.off >= 0) zp0[c] = F[1 + c][b + size_t(n0.off)];
-      if (n1.on && n1.off >= 0) zp1[c] = F[1 + c][b + size_t(n1.off)];
+    for (int c = 0; c < NF; ++c) {
+      if (n0.on && n0.off >= 0) zp0[c] = F[c][b + unsigned(n0.off)];
+      if (n1.on && n1.off >= 0) zp1[c] = F[c][b + unsigned(n1.off)];
     }
   }
-  // per-node inputs one iteration ahead: B of the source nodes, class,
-  // Brinkman factor and prescribed temperature of the output node
-  auto node_in = [&](int s, R& b0, R& b1, int& mk, R& ip, R& tb) {
-    b0 = b1 = ip = tb = R(0);
+  // per-node inputs one iteration ahead: drho and B of the source nodes,
+  // class, Brinkman factor and prescribed temperature of the output node
+  auto node_in = [&](int s, R& d0, R& d1_, R& b0, R& b1, int& mk, R& ip, R& tb) {
+    d0 = d1_ = b0 = b1 = ip = tb = R(0);
     mk = 0;
     if (!has(s)) return;
-    const size_t base = size_t(zwrap(s, g.nz)) * nxy;
-    if constexpr (TH) {
-      if (n0.on && n0.off >= 0) b0 = a.B[base + size_t(n0.off)];
-      if (n1.on && n1.off >= 0) b1 = a.B[base + size_t(n1.off)];
+    const unsigned base = unsigned(zwrap(s, g.nz)) * nxy;
+    if (n0.on && n0.off >= 0) {
+      d0 = a.s0[0][base + unsigned(n0.off)];
+      if constexpr (TH) b0 = a.B[base + unsigned(n0.off)];
+    }
+    if (n1.on && n1.off >= 0) {
+      d1_ = a.s0[0][base + unsigned(n1.off)];
+      if constexpr (TH) b1 = a.B[base + unsigned(n1.off)];
     }
     const int p = s - 1;
     if (own && p >= t.z0 && p < t.z1) {
-      const size_t k = size_t(p) * nxy + size_t(n0.off);
+      const unsigned k = unsigned(p) * nxy + unsigned(n0.off);
       mk = a.mask[k];
       ip = a.inv1pa[k];
       if constexpr (TH) tb = a.Tb[k];
     }
   };
-  R b0, b1, ip, tb;
+  R dd0, dd1, b0, b1, ip, tb;
   int mk;
-  node_in(sb, b0, b1, mk, ip, tb);
+  node_in(sb, dd0, dd1, b0, b1, mk, ip, tb);
   FwdAcc<R, TH> A = {};
   double part = 0.0;
   for (int s = sb; s <= se; ++s) {
     const int it = s - sb, cur = it & 1, nxt = cur ^ 1;
     const bool hn = has(s + 1);
     if (hn) zstore<R, NF>(L.st[nxt], v);
-    __syncthreads();
-    if (has(s + 2)) zload<R, NF>(F, true, size_t(zwrap(s + 2, g.nz)) * nxy, roff, v);
-    const R cb0 = b0, cb1 = b1, cip = ip, ctb = tb;
+    lds_barrier();
+    if (has(s + 2)) zload<R, NF>(F, true, unsigned(zwrap(s + 2, g.nz)) * nxy, roff, v);
+    const R cd0 = dd0, cd1 = dd1, cb0 = b0, cb1 = b1, cip = ip, ctb = tb;
     const int cmk = mk;
-    if (s + 1 <= se) node_in(s + 1, b0, b1, mk, ip, tb);
+    if (s + 1 <= se) node_in(s + 1, dd0, dd1, b0, b1, mk, ip, tb);
     const int sw = zwrap(s, g.nz);
-    fwd_src<R, TH, true>(g, a, L, t, n0, cur, nxt, hn, sw, nxy, cb0, zp0, A);
-    fwd_src<R, TH, false>(g, a, L, t, n1, cur, nxt, hn, sw, nxy, cb1, zp1, A);
-    __syncthreads();
+    fwd_src<R, TH, true>(g, a, L, t, n0, cur, nxt, hn, sw, nxy, cd0, cb0, zp0, A);
+    fwd_src<R, TH, false>(g, a, L, t, n1, cur, nxt, hn, sw, nxy, cd1, cb1, zp1, A);
+    lds_barrier();
     if (n0.on) {
       const int me = ly * ZX + lx;
 #pragma unroll
@@ -642,12 +646,12 @@ __global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
     }
     const int p = s - 1;
     if (own && p >= t.z0 && p < t.z1)
-      fwd3_out<R, TH>(g, a, size_t(p) * nxy + size_t(n0.off), n0.ex, n0.ey,
+      fwd3_out<R, TH>(g, a, unsigned(p) * nxy + unsigned(n0.off), n0.ex, n0.ey,
                       endof(p, g.nz, pz), cmk, cip, ctb, A.r[0], A.U[0], A.T[0], A.Q[0], part);
     facc_shift(A);
   }
   if (!pz && se == g.nz - 1 && own) {
-    const size_t k = size_t(g.nz - 1) * nxy + size_t(n0.off);
+    const unsigned k = unsigned(g.nz - 1) * nxy + unsigned(n0.off);
     fwd3_out<R, TH>(g, a, k, n0.ex, n0.ey, 1, a.mask[k], a.inv1pa[k], TH ? a.Tb[k] : R(0),
                     A.r[0], A.U[0], A.T[0], A.Q[0], part);
   }
@@ -811,13 +815,6 @@ __device__ inline void adj_local(const Adj3Args<R>& a, int k, int m, int ne, R T
   for (int x = 0; x < 3; ++x) M[1 + x] *= s;
 }
 
-// Two node-parallel passes per ALKS step, the neighbour gathers served by
-// the L1/L2 caches:
-//   pass 1  per node the pull of f~_i^eq = rho~ + c_i.V and g~_i^eq = Theta
-//           from x + c_i (eq:afeq, eq:ageq), the face least-squares
-//           completion, the local terms and the moments rho~, u~, s~, T~, q~;
-//   pass 2  per node V and Theta of the new level from the moments and the
-//           sensitivity 3 alpha' u.u~ - B' grad T.q~.
 // moments of the node p (not an edge or corner node) with orientation o if
 // it is a face node
 template <typename R, bool TH>
@@ -870,57 +867,198 @@ __global__ __launch_bounds__(NT3) void alks3_pull_kernel(Geo3 g, Adj3Args<R> a) 
   for (int c = 0; c < NM; ++c) a.m[c * N + k] = mom[c];
 }
 
+// in-plane offsets of the thread's elements of the 1-node halo region; -1
+// off the domain or beyond the tile's region
+__device__ inline void zregion1(const Geo3& g, const ZTile& t, int off[2]) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int e = int(threadIdx.x) + r * ZT;
+    const int dx = e % CXN - 1, dy = e / CXN - 1;
+    off[r] = -1;
+    if (e < NCR && dx < t.w + 1 && dy < t.h + 1) {
+      const int x = axc(t.x0 + dx, g.nx, g.periodic & 1);
+      const int y = axc(t.y0 + dy, g.ny, g.periodic & 2);
+      if (x >= 0 && y >= 0) off[r] = y * g.nx + x;
+    }
+  }
+}
+
+// ALKS pass 2, z-marching: V, Theta (eq:afp - eq:agq) and the sensitivity
+// from the moments; x and y differences from an LDS plane, z differences
+// from a window of three planes in registers.
+// The update pass. LDS plane fields: s~xx s~xy s~xz s~yy s~yz (q~x q~y T B),
+// 1-node halo, two planes.
 template <typename R, bool TH>
-__global__ __launch_bounds__(NT3) void alks3_eq_kernel(Geo3 g, Adj3Args<R> a) {
-  const int k = node3(g.N);
-  if (k < 0) return;
-  const P3 p = decode(g, k);
-  const size_t N = size_t(g.N);
-  const R* M = a.m;
-  const R u[3] = {a.u[0][k], a.u[1][k], a.u[2][k]};
-  const R r = M[k];
-  const R A2 = R(2.0 * g.A);
+struct AdjELds {
+  static constexpr int NE = TH ? 9 : 5;
+  R e[2][NE][NCR];
+};
+
+template <typename R, bool TH>
+__global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
+  constexpr int NE = AdjELds<R, TH>::NE;
+  constexpr int NZ = TH ? 6 : 3;  // z window: s~xz s~yz s~zz (q~z T B)
+  __shared__ AdjELds<R, TH> L;
+  ZTile t;
+  if (!ztile(g, t)) return;
+  const int tid = int(threadIdx.x), lx = tid % ZX, ly = tid / ZX;
+  const int pz = g.periodic & 4;
+  const unsigned nxy = unsigned(g.nx) * unsigned(g.ny);
+  const unsigned N = unsigned(g.N);
+  int coff[2];
+  zregion1(g, t, coff);
+  const ZNode n0 = znode(g, t, lx, ly, lx < t.w && ly < t.h);
+  const bool own = n0.on && t.x0 + lx >= t.xo && t.y0 + ly >= t.yo;
+  // plane fields: moments 4, 5, 6, 7, 8 (11, 12) and T, B
+  const R* FE[9];
+  FE[0] = a.m + 4 * N;
+  FE[1] = a.m + 5 * N;
+  FE[2] = a.m + 6 * N;
+  FE[3] = a.m + 7 * N;
+  FE[4] = a.m + 8 * N;
+  FE[5] = a.m + 11 * N;
+  FE[6] = a.m + 12 * N;
+  FE[7] = a.T;
+  FE[8] = a.B;
+  // z window fields: moments 6, 8, 9 (13) and T, B
+  const R* FZ[6] = {a.m + 6 * N, a.m + 8 * N, a.m + 9 * N, a.m + 13 * N, a.T, a.B};
+  auto has = [&](int s) { return pz || (s >= 0 && s < g.nz); };
+  R v[2][NE];
+  auto load = [&](int s) {
+    const bool e = has(s);
+    const unsigned b = unsigned(zwrap(s, g.nz)) * nxy;
 #pragma unroll
-  for (int x = 0; x < 3; ++x) {
-    R su = R(0), ds = R(0);
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int y = 0; y < 3; ++y) {
-      const R* sf = M + (4 + SI[x][y]) * N;
-      su += sf[k] * u[y];
-      ds += dd(g, sf, p, k, y);
+      for (int f = 0; f < NE; ++f) v[r][f] = (e && coff[r] >= 0) ? FE[f][b + coff[r]] : R(0);
+  };
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = tid + r * ZT;
+      if (e < NCR)
+#pragma unroll
+        for (int f = 0; f < NE; ++f) L.e[slot][f][e] = v[r][f];
     }
-    a.p1[1 + x][k] = R(3) * M[(1 + x) * N + k] + R(9) * su - R(3) * r * u[x] - A2 * ds;
-  }
-  a.p1[0][k] = r;
-  R qv[3] = {R(0), R(0), R(0)};
-  if constexpr (TH) {
-    R qu = R(0), divq = R(0), gbq = R(0);
+  };
+  auto zload = [&](int s, R z[6]) {
 #pragma unroll
-    for (int x = 0; x < 3; ++x) {
-      qv[x] = M[(11 + x) * N + k];
-      qu += qv[x] * u[x];
-      divq += dd(g, M + (11 + x) * N, p, k, x);
-      gbq += dd(g, a.B, p, k, x) * qv[x];
+    for (int f = 0; f < 6; ++f) z[f] = R(0);
+    if (!own || !has(s)) return;
+    const unsigned k = unsigned(zwrap(s, g.nz)) * nxy + unsigned(n0.off);
+#pragma unroll
+    for (int f = 0; f < NZ; ++f) z[f] = FZ[f][k];
+  };
+  // per-node inputs one plane ahead
+  struct In {
+    R r, U[3], Tt, u[3], dA, dB;
+    int mk;
+  };
+  auto node_in = [&](int p, In& q) {
+    q.r = q.Tt = q.dA = q.dB = R(0);
+    q.mk = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q.U[c] = q.u[c] = R(0);
+    if (!own || p >= t.z1) return;
+    const unsigned k = unsigned(p) * nxy + unsigned(n0.off);
+    q.r = a.m[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      q.U[c] = a.m[(1 + c) * N + k];
+      q.u[c] = a.u[c][k];
     }
-    a.p1[4][k] = M[10 * N + k] + R(3) * qu - a.B[k] * divq - gbq;
-  }
-  if (a.sens_mode) {
-    int o;
-    double v = 0.0;
-    if (!ends(g, p, &o) && !(a.mask[k] & TAG_SOLID3)) {
-      double uu = 0.0;
+    if constexpr (TH) q.Tt = a.m[10 * N + k];
+    q.mk = a.mask[k];
+    if (a.sens_mode) {
+      q.dA = a.dA3[k];
+      if constexpr (TH) q.dB = a.dB[k];
+    }
+  };
+  load(t.z0);
+  store(0);
+  load(t.z0 + 1);
+  R zm1[6], zc[6], zn[6];
+  zload(t.z0 - 1, zm1);
+  zload(t.z0, zc);
+  zload(t.z0 + 1, zn);
+  In nx;
+  node_in(t.z0, nx);
+  const int ci = n0.ci;
+  for (int p = t.z0; p < t.z1; ++p) {
+    const int it = p - t.z0, sc = it & 1;
+    lds_barrier();
+    if (p + 1 < t.z1) {
+      store(sc ^ 1);
+      load(p + 2);
+    }
+    const In cu = nx;
+    node_in(p + 1, nx);
+    R znn[6];
+    zload(p + 2, znn);  // the window's next plane, in flight during this one
+    R z2[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    const int ez = endof(zwrap(p, g.nz), g.nz, pz);
+    if (ez < 0) zload(2, z2);
+    if (ez > 0) zload(g.nz - 3, z2);
+    R zd[6];
 #pragma unroll
-      for (int x = 0; x < 3; ++x) uu += double(u[x]) * double(M[(1 + x) * N + k]);
-      v = double(a.dA3[k]) * uu;
+    for (int f = 0; f < 6; ++f) zd[f] = dz3(ez, zc[f], zm1[f], zn[f], z2[f]);
+    if (own) {
+      const unsigned k = unsigned(p) * nxy + unsigned(n0.off);
+      const R(*E)[NCR] = L.e[sc];
+      const R S[6] = {E[0][ci], E[1][ci], E[2][ci], E[3][ci], E[4][ci], zc[2]};
+      const R A2 = R(2.0 * g.A);
+      const R ds[3] = {d1(E[0], ci, 1, n0.ex) + d1(E[1], ci, CXN, n0.ey) + zd[0],
+                       d1(E[1], ci, 1, n0.ex) + d1(E[3], ci, CXN, n0.ey) + zd[1],
+                       d1(E[2], ci, 1, n0.ex) + d1(E[4], ci, CXN, n0.ey) + zd[2]};
+      R V[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R su = R(0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) su += S[SI[c][b]] * cu.u[b];
+        V[c] = R(3) * cu.U[c] + R(9) * su - R(3) * cu.r * cu.u[c] - A2 * ds[c];
+      }
+      a.p1[0][k] = cu.r;
+      a.p1[1][k] = V[0];
+      a.p1[2][k] = V[1];
+      a.p1[3][k] = V[2];
+      R qv[3] = {R(0), R(0), R(0)};
       if constexpr (TH) {
-        double gq = 0.0;
+        qv[0] = E[TH ? 5 : 0][ci];
+        qv[1] = E[TH ? 6 : 0][ci];
+        qv[2] = zc[3];
+        const R qu = qv[0] * cu.u[0] + qv[1] * cu.u[1] + qv[2] * cu.u[2];
+        const R divq = d1(E[TH ? 5 : 0], ci, 1, n0.ex) + d1(E[TH ? 6 : 0], ci, CXN, n0.ey) + zd[3];
+        const R* Bp = E[TH ? 8 : 0];
+        const R gbq = d1(Bp, ci, 1, n0.ex) * qv[0] + d1(Bp, ci, CXN, n0.ey) * qv[1] + zd[5] * qv[2];
+        a.p1[4][k] = cu.Tt + R(3) * qu - Bp[ci] * divq - gbq;
+      }
+      if (a.sens_mode) {
+        double sv = 0.0;
+        if (!n0.ex && !n0.ey && !ez && !(cu.mk & TAG_SOLID3)) {
+          double uu = 0.0;
 #pragma unroll
-        for (int x = 0; x < 3; ++x) gq += double(dd(g, a.T, p, k, x)) * double(qv[x]);
-        v -= double(a.dB[k]) * gq;
+          for (int c = 0; c < 3; ++c) uu += double(cu.u[c]) * double(cu.U[c]);
+          sv = double(cu.dA) * uu;
+          if constexpr (TH) {
+            const R* Tp = E[TH ? 7 : 0];
+            const R gt[3] = {d1(Tp, ci, 1, n0.ex), d1(Tp, ci, CXN, n0.ey), zd[4]};
+            double gq = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gq += double(gt[c]) * double(qv[c]);
+            sv -= double(cu.dB) * gq;
+          }
+        }
+        if (a.sens_mode == 1) a.sens[k] += sv;
+        else a.sens[k] = sv;
       }
     }
-    if (a.sens_mode == 1) a.sens[k] += v;
-    else a.sens[k] = v;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      zm1[f] = zc[f];
+      zc[f] = zn[f];
+      zn[f] = znn[f];
+    }
   }
 }
 
@@ -955,6 +1093,38 @@ int blocks3(int N) {
 }
 
 int zblocks3(const Geo3& g) { return ztiles(g.nx, ZX) * ztiles(g.ny, ZY) * zchunks(g); }
+
+namespace {
+// planes per chunk so that tiles x chunks fills whole rounds of the kernel's
+// resident blocks (one round when the grid allows)
+template <typename K>
+int zplanes(const Geo3& g, K kernel) {
+  int dev = 0, ncu = 0, bpc = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, kernel, ZT, 0) != hipSuccess ||
+      ncu <= 0 || bpc <= 0)
+    return 16;
+  const int tiles = ztiles(g.nx, ZX) * ztiles(g.ny, ZY);
+  int nch = (bpc * ncu) / tiles;
+  if (nch < 1) nch = 1;
+  if (nch > g.nz / 2) nch = g.nz / 2 > 1 ? g.nz / 2 : 1;
+  const int zc = g.nz / nch;
+  return zc < 2 ? 2 : zc;
+}
+}  // namespace
+
+void zplan3(Geo3& g, int rsz) {
+  if (rsz == 8) {
+    g.zc = g.thermal ? zplanes(g, lks3z_kernel<double, true>) : zplanes(g, lks3z_kernel<double, false>);
+    g.zca = g.thermal ? zplanes(g, alks3e_kernel<double, true>)
+                      : zplanes(g, alks3e_kernel<double, false>);
+  } else {
+    g.zc = g.thermal ? zplanes(g, lks3z_kernel<float, true>) : zplanes(g, lks3z_kernel<float, false>);
+    g.zca = g.thermal ? zplanes(g, alks3e_kernel<float, true>)
+                      : zplanes(g, alks3e_kernel<float, false>);
+  }
+}
 
 int copy_nodes3(const Geo3& g, int* out) {
   const int n3[3] = {g.nx, g.ny, g.nz};
@@ -1006,14 +1176,17 @@ void launch_lks3_step(const Geo3& g, const Fwd3Args<R>& a, hipStream_t s) {
 }
 
 template <typename R>
-void launch_alks3_step(const Geo3& g, const Adj3Args<R>& a, hipStream_t s) {
+void launch_alks3_step(const Geo3& g0, const Adj3Args<R>& a, hipStream_t s) {
+  Geo3 g = g0;
+  g.zc = g0.zca;
   const unsigned nb = unsigned(blocks3(g.N));
+  const unsigned nz = unsigned(NXCD * ((zblocks3(g) + NXCD - 1) / NXCD));
   if (g.thermal) {
     alks3_pull_kernel<R, true><<<nb, NT3, 0, s>>>(g, a);
-    alks3_eq_kernel<R, true><<<nb, NT3, 0, s>>>(g, a);
+    alks3e_kernel<R, true><<<nz, ZT, 0, s>>>(g, a);
   } else {
     alks3_pull_kernel<R, false><<<nb, NT3, 0, s>>>(g, a);
-    alks3_eq_kernel<R, false><<<nb, NT3, 0, s>>>(g, a);
+    alks3e_kernel<R, false><<<nz, ZT, 0, s>>>(g, a);
   }
 }
 

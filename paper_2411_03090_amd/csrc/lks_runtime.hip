@@ -127,11 +127,15 @@ int slot_fields(const lks_ctx* c) { return ckpt_fields(c) - 1; }
 int acc_count(const lks_ctx* c) {
   return c->dim == 3 ? lks::zblocks3(c->geo3) : n_tiles(c->geo);
 }
+int acc_bound3(const lks_ctx* c) {
+  const lks::Geo3& g = c->geo3;
+  return ((g.nx + 63) / 64) * ((g.ny + 3) / 4) * std::max(1, g.nz / 2);
+}
 // D3Q19 adjoint moments between the two passes of a step: 14, 10 without T
 int moments3_fields(const lks_ctx* c) { return c->phys.thermal ? 14 : 10; }
 // (D3Q19 steady runs also take the partial sums of the objective there)
 int acc_capacity(const lks_ctx* c) {
-  return c->dim == 3 ? std::max(lks::zblocks3(c->geo3), lks::tag_sum3_parts()) : max_tiles(c->geo);
+  return c->dim == 3 ? std::max(acc_bound3(c), lks::tag_sum3_parts()) : max_tiles(c->geo);
 }
 
 size_t traj_bytes(const lks_ctx* c, int K) {
@@ -772,7 +776,7 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
     g3.A = g.A;
     g3.Bf = g.Bf;
     g3.drho_out = g.drho_out;
-    g3.zc = 16;
+    g3.zc = g3.zca = 16;  // re-planned for the device at bind
     lks::build_face_ops3(g3.A, g3.Bf, c->ops3);
     c->copy3h.resize(size_t(lks::copy_nodes3(g3, nullptr)));
     lks::copy_nodes3(g3, c->copy3h.data());
@@ -811,6 +815,7 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
   };
   c->ws = static_cast<char*>(dev_ptr);
   c->ws_bytes = bytes;
+  if (c->dim == 3) lks::zplan3(c->geo3, int(c->rsz));
   c->d_mask = reinterpret_cast<uint8_t*>(take(N));
   c->ubx = take(N * r);
   c->uby = take(N * r);
