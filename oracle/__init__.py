@@ -62,7 +62,8 @@ class _Problem(ctypes.Structure):
                 ("rho_out", ctypes.c_double),
                 ("mask", ctypes.POINTER(ctypes.c_uint8)),
                 ("ubar", ctypes.POINTER(ctypes.c_double)),
-                ("Tbar", ctypes.POINTER(ctypes.c_double))]
+                ("Tbar", ctypes.POINTER(ctypes.c_double)),
+                ("adj_exact", ctypes.c_int)]
 
 
 _lib = None
@@ -82,10 +83,10 @@ def lib():
         _lib.orc_pressure_drop.restype = ctypes.c_double
         _lib.orc_probe_heat.argtypes = [P, d, d]
         _lib.orc_probe_heat.restype = ctypes.c_double
-        _lib.orc_adjoint_equilibrium.argtypes = [P, d, d, d, dd, d, d, d]
+        _lib.orc_adjoint_equilibrium.argtypes = [P, d, d, d, dd, d, d, d, d]
         _lib.orc_alks_step.argtypes = [P, d, d, d, d, d, d, d, d, dd, dd,
                                        ctypes.c_double, ctypes.c_double, d]
-        _lib.orc_sens_add.argtypes = [P, d, d, d, d, d, dd, ctypes.c_double, d]
+        _lib.orc_sens_add.argtypes = [P, d, d, d, d, d, d, dd, ctypes.c_double, d]
         _lib.orc_boundary_fill.argtypes = [P, ctypes.c_uint8, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double,
@@ -117,7 +118,8 @@ class Problem:
                           Kf * wl.Ks_over_Kf, wl.q_K, wl.alpha_max, wl.q_alpha,
                           wl.rho_out,
                           self.mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
-                          _p(self.ubar), _p(self.Tbar))
+                          _p(self.ubar), _p(self.Tbar),
+                          int(getattr(wl, "adjoint_mode", "paper") == "exact"))
         self.ref = ctypes.byref(self.c)
 
     def zeros(self, k=None):
@@ -169,12 +171,14 @@ def level_objective(pb: Problem, s: State) -> float:
     return probe_heat(pb, s)
 
 
-def adjoint_equilibrium(pb: Problem, B, ux, uy, adj):
-    """(V_x, V_y, Theta): the coefficients of eq:afeq / eq:ageq."""
+def adjoint_equilibrium(pb: Problem, B, ux, uy, adj, alpha=None):
+    """(V_x, V_y, Theta): the coefficients of eq:afeq / eq:ageq; with alpha,
+    V divided by 1 + alpha (the propagated coefficient of the exact mode)."""
     Vx, Vy, Th = pb.zeros(3)
     pp, keep = _pp(adj)
+    a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
     lib().orc_adjoint_equilibrium(pb.ref, _p(B), _p(ux), _p(uy), pp, _p(Vx), _p(Vy),
-                                  _p(Th))
+                                  _p(Th), None if a is None else _p(a))
     return Vx, Vy, Th
 
 
@@ -189,10 +193,10 @@ def alks_step(pb: Problem, alpha, B, src: State, dst: State, adj_in, seed_dp, se
     return out
 
 
-def sens_add(pb: Problem, dalpha, dB, s: State, adj, weight, sens):
+def sens_add(pb: Problem, alpha, dalpha, dB, s: State, adj, weight, sens):
     pp, keep = _pp(adj)
-    lib().orc_sens_add(pb.ref, _p(dalpha), _p(dB), _p(s.ux), _p(s.uy), _p(s.T), pp,
-                       weight, _p(sens))
+    lib().orc_sens_add(pb.ref, _p(alpha), _p(dalpha), _p(dB), _p(s.ux), _p(s.uy), _p(s.T),
+                       pp, weight, _p(sens))
 
 
 def boundary_fill(pb: Problem, m, normal, Bn, Tn, u, seed_dp, fk, gk):
@@ -242,13 +246,15 @@ def adjoint_steady(pb: Problem, gamma, state: State, n_adj, seed=1.0):
     for _ in range(n_adj):
         adj = alks_step(pb, alpha, B, state, state, adj, sdp, sh)
     sens = np.zeros(pb.N)
-    sens_add(pb, dalpha, dB, state, adj, 1.0, sens)
+    sens_add(pb, alpha, dalpha, dB, state, adj, 1.0, sens)
     return adj, sens
 
 
 def adjoint_unsteady(pb: Problem, gamma, traj, seed=1.0):
     """Reverse sweep over a stored trajectory of N+1 levels; the objective is
-    the average over levels 1..N, so the seed at level n >= 1 is seed/N."""
+    the average over levels 1..N, so the seed at level n >= 1 is seed/N.
+    The paper's sensitivity sums levels 0..N; the exact mode sums 1..N, the
+    levels the steps produce (the initial state does not depend on gamma)."""
     wl = pb.wl
     N = len(traj) - 1
     alpha, dalpha, B, dB = coefficients(pb, gamma)
@@ -260,7 +266,8 @@ def adjoint_unsteady(pb: Problem, gamma, traj, seed=1.0):
         sh = w if wl.objective == OBJ_HEAT else 0.0
         src = traj[min(n + 1, N)]
         adj = alks_step(pb, alpha, B, src, traj[n], adj, sdp, sh)
-        sens_add(pb, dalpha, dB, traj[n], adj, 1.0, sens)
+        if n >= 1 or getattr(wl, "adjoint_mode", "paper") != "exact":
+            sens_add(pb, alpha, dalpha, dB, traj[n], adj, 1.0, sens)
     return adj, sens
 
 

@@ -63,6 +63,7 @@ typedef struct {
   const uint8_t *mask;   /* nx*ny node classes */
   const double *ubar;    /* 2*nx*ny prescribed velocity (x block, y block) */
   const double *Tbar;    /* nx*ny prescribed temperature */
+  int adj_exact;         /* 1: exact discrete adjoint of the Brinkman step */
 } orc_problem;
 
 /* ------------------------------------------------------------------ */
@@ -356,31 +357,40 @@ enum { A_R = 0, A_UX, A_UY, A_SXX, A_SXY, A_SYY, A_T, A_QX, A_QY, A_NF };
  * eq:ageq: g~_i^eq = Theta (independent of i) with
  *   Theta = T~ + 3 q~.u - B div q~ - grad B . q~
  * evaluated with the state (u, T) of the same time level. */
+static void adj_V(const orc_problem *P, int i, int j, const double *ux,
+                  const double *uy, const double *const *adj, double V[2]) {
+  const double A = coef_A(P);
+  int k = idx(P, i, j);
+  double r = adj[A_R][k];
+  double u[2] = {ux[k], uy[k]};
+  double s[2][2] = {{adj[A_SXX][k], adj[A_SXY][k]}, {adj[A_SXY][k], adj[A_SYY][k]}};
+  /* d/dx_b (s~_ab + s~_ba) = 2 d/dx_b s~_ab */
+  double divs[2];
+  divs[0] = 2.0 * (ddx(P, adj[A_SXX], i, j, 0) + ddx(P, adj[A_SXY], i, j, 1));
+  divs[1] = 2.0 * (ddx(P, adj[A_SXY], i, j, 0) + ddx(P, adj[A_SYY], i, j, 1));
+  double ut[2] = {adj[A_UX][k], adj[A_UY][k]};
+  for (int a = 0; a < 2; ++a)
+    V[a] = 3.0 * ut[a] + 9.0 * (s[a][0] * u[0] + s[a][1] * u[1]) - 3.0 * r * u[a] -
+           A * divs[a];
+}
+
+/* With alpha given (exact mode), V is divided by 1 + alpha at its node: the
+ * transpose of u = U* / (1 + alpha) applied where the velocity was formed. */
 void orc_adjoint_equilibrium(const orc_problem *P, const double *B,
                              const double *ux, const double *uy,
                              const double *const *adj, double *Vx, double *Vy,
-                             double *Theta) {
+                             double *Theta, const double *alpha) {
   const int nx = P->nx, ny = P->ny;
-  const double A = coef_A(P);
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j) {
     for (int i = 0; i < nx; ++i) {
       int k = idx(P, i, j);
-      double r = adj[A_R][k];
       double u[2] = {ux[k], uy[k]};
-      double s[2][2] = {{adj[A_SXX][k], adj[A_SXY][k]},
-                        {adj[A_SXY][k], adj[A_SYY][k]}};
-      /* d/dx_b (s~_ab + s~_ba) = 2 d/dx_b s~_ab */
-      double divs[2];
-      divs[0] = 2.0 * (ddx(P, adj[A_SXX], i, j, 0) + ddx(P, adj[A_SXY], i, j, 1));
-      divs[1] = 2.0 * (ddx(P, adj[A_SXY], i, j, 0) + ddx(P, adj[A_SYY], i, j, 1));
-      double ut[2] = {adj[A_UX][k], adj[A_UY][k]};
       double V[2];
-      for (int a = 0; a < 2; ++a)
-        V[a] = 3.0 * ut[a] + 9.0 * (s[a][0] * u[0] + s[a][1] * u[1]) -
-               3.0 * r * u[a] - A * divs[a];
-      Vx[k] = V[0];
-      Vy[k] = V[1];
+      adj_V(P, i, j, ux, uy, adj, V);
+      const double sc = alpha ? 1.0 / (1.0 + alpha[k]) : 1.0;
+      Vx[k] = V[0] * sc;
+      Vy[k] = V[1] * sc;
       if (Theta) {
         double qx = adj[A_QX][k], qy = adj[A_QY][k];
         double divq = ddx(P, adj[A_QX], i, j, 0) + ddx(P, adj[A_QY], i, j, 1);
@@ -563,7 +573,8 @@ void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
   const double A = coef_A(P);
   const int th = P->thermal;
   double *Vx = work, *Vy = work + N, *Th = work + 2 * N;
-  orc_adjoint_equilibrium(P, B, ux_src, uy_src, adj_in, Vx, Vy, th ? Th : NULL);
+  orc_adjoint_equilibrium(P, B, ux_src, uy_src, adj_in, Vx, Vy, th ? Th : NULL,
+                          P->adj_exact ? alpha : NULL);
 
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j) {
@@ -618,7 +629,9 @@ void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
         sxy += W[q] * CX[q] * CY[q] * f;
         syy += W[q] * CY[q] * CY[q] * f;
       }
-      double inv = 1.0 / (1.0 + alpha[k]);
+      /* paper: u~ = U~ / (1 + alpha) here; exact: the division is applied to
+       * V at this node before the next pull */
+      double inv = P->adj_exact ? 1.0 : 1.0 / (1.0 + alpha[k]);
       adj_out[A_R][k] = r;
       adj_out[A_UX][k] = Ux * inv;
       adj_out[A_UY][k] = Uy * inv;
@@ -644,9 +657,12 @@ void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
 /* ------------------------------------------------------------------ */
 /* Adds weight * (3 alpha'(gamma) u.u~ - B'(gamma) grad T . q~) at every
  * design (interior) node: the integrand of <J', dgamma> in Sec. 2.5 with
- * G = Q = 0 and dJ_O/dgamma = 0, in lattice units. */
-void orc_sens_add(const orc_problem *P, const double *dalpha, const double *dB,
-                  const double *ux, const double *uy, const double *T,
+ * G = Q = 0 and dJ_O/dgamma = 0, in lattice units. In exact mode the
+ * Brinkman part is alpha' u.V / (1 + alpha), with V the undivided
+ * coefficient of eq:afeq: the derivative of u = U* / (1 + alpha) in alpha
+ * paired with the adjoint of u. */
+void orc_sens_add(const orc_problem *P, const double *alpha, const double *dalpha,
+                  const double *dB, const double *ux, const double *uy, const double *T,
                   const double *const *adj, double weight, double *sens) {
   const int nx = P->nx, ny = P->ny;
 #pragma omp parallel for schedule(static)
@@ -654,7 +670,14 @@ void orc_sens_add(const orc_problem *P, const double *dalpha, const double *dB,
     for (int i = 0; i < nx; ++i) {
       int k = idx(P, i, j);
       if (on_ring(P, i, j)) continue;
-      double v = 3.0 * dalpha[k] * (ux[k] * adj[A_UX][k] + uy[k] * adj[A_UY][k]);
+      double v;
+      if (P->adj_exact) {
+        double V[2];
+        adj_V(P, i, j, ux, uy, adj, V);
+        v = dalpha[k] * (ux[k] * V[0] + uy[k] * V[1]) / (1.0 + alpha[k]);
+      } else {
+        v = 3.0 * dalpha[k] * (ux[k] * adj[A_UX][k] + uy[k] * adj[A_UY][k]);
+      }
       if (P->thermal && T) {
         double dTx = ddx(P, T, i, j, 0), dTy = ddx(P, T, i, j, 1);
         v -= dB[k] * (dTx * adj[A_QX][k] + dTy * adj[A_QY][k]);

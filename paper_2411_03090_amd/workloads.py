@@ -67,6 +67,10 @@ class Workload:
     n_fwd: int = 0
     n_adj: int = 0
     periodic: bool = False
+    # "paper": the ALKS of Sec. 2.5 (u~ divided by 1 + alpha where it is
+    # formed); "exact": the transpose of the discrete Brinkman step (V divided
+    # by 1 + alpha at its node, sensitivity alpha' u.V / (1 + alpha))
+    adjoint_mode: str = "paper"
     mask: np.ndarray = field(default=None, repr=False)      # (ny, nx) uint8
     gamma: np.ndarray = field(default=None, repr=False)     # (ny, nx) f64
     ubar: np.ndarray = field(default=None, repr=False)      # (2, ny, nx) f64
@@ -377,6 +381,7 @@ def extrude_z(wl: Workload, nz: int) -> Workload3:
                      thermal=wl.thermal, Pr=wl.Pr, Ks_over_Kf=wl.Ks_over_Kf, q_K=wl.q_K,
                      rho_out=wl.rho_out, objective=wl.objective, mode=wl.mode,
                      n_fwd=wl.n_fwd, n_adj=wl.n_adj, periodic=wl.periodic,
+                     adjoint_mode=wl.adjoint_mode,
                      mask=rep(wl.mask).astype(np.uint8), gamma=rep(wl.gamma), ubar=ubar,
                      Tbar=rep(wl.Tbar), ufac=np.array(wl.ufac, dtype=np.float64),
                      periodic_axes=axes)

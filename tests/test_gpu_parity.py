@@ -111,7 +111,7 @@ def test_single_adjoint_step(case, prec):
     adj0 = O.alks_step(pb, a, B, s, s, adj1, sdp, sh)
     Vx0, Vy0, Th0 = O.adjoint_equilibrium(pb, B, s.ux, s.uy, adj0)
     sens = np.zeros(wl.nx * wl.ny)
-    O.sens_add(pb, da, dB, s, adj0, 1.0, sens)
+    O.sens_add(pb, a, da, dB, s, adj0, 1.0, sens)
 
     ctx = lks.LKS(wl, precision=prec, device=DEV)
     g = T(wl.gamma)

@@ -1,0 +1,106 @@
+"""The exact-discrete-adjoint mode of the oracle (a variant beside the ALKS
+of Sec. 2.5). The forward velocity is u = U* / (1 + alpha) (eq:lbef_ex with
+the Brinkman term implicit); its transpose divides the propagated
+coefficient V of eq:afeq by 1 + alpha at the node where the velocity was
+formed, and the Brinkman part of the sensitivity becomes
+alpha' u.V / (1 + alpha).
+
+Pins: on periodic grids with uniform B the ALKS step is then the exact
+transpose of the LKS tangent for any alpha (the paper's placement is not),
+and the unsteady gradient equals central differences of J to their
+truncation error (the paper's gradient does not)."""
+import numpy as np
+import pytest
+
+from oracle import Problem, State, adjoint_equilibrium, adjoint_unsteady, alks_step
+from oracle import forward, lks_step
+from paper_2411_03090_amd import workloads as W
+
+
+def _dot_mismatch(mode, thermal):
+    nx, ny = 12, 10
+    wl = W.periodic_box(nx, ny, nu=0.1, thermal=thermal)
+    wl.adjoint_mode = mode
+    pb = Problem(wl)
+    N = nx * ny
+    rng = np.random.default_rng(3)
+    a = 2.0 * rng.random(N)  # alpha in [0, 2)
+    B = np.full(N, 0.45)
+    S = State(1e-2 * rng.standard_normal(N), 0.05 * rng.standard_normal(N),
+              0.05 * rng.standard_normal(N), rng.standard_normal(N))
+    d = State(*(rng.standard_normal(N) for _ in range(4)))
+
+    def shifted(sg):
+        return State(S.drho + sg * d.drho, S.ux + sg * d.ux, S.uy + sg * d.uy, S.T + sg * d.T)
+
+    # the step is quadratic in the state: L d = (F(S + d) - F(S - d)) / 2
+    Fp = lks_step(pb, a, B, 1.0, shifted(1.0))
+    Fm = lks_step(pb, a, B, 1.0, shifted(-1.0))
+    Ld = [(x - y) / 2 for x, y in ((Fp.drho, Fm.drho), (Fp.ux, Fm.ux), (Fp.uy, Fm.uy),
+                                   (Fp.T, Fm.T))]
+    S1 = lks_step(pb, a, B, 1.0, S)
+    adj1 = [rng.standard_normal(N) for _ in range(9)]
+    # the undivided V pairs with u in both modes' identity
+    Vx, Vy, Th = adjoint_equilibrium(pb, B, S1.ux, S1.uy, adj1)
+    lhs = adj1[0] @ Ld[0] + Vx @ Ld[1] + Vy @ Ld[2] + (Th @ Ld[3] if thermal else 0.0)
+    adj0 = alks_step(pb, a, B, S1, S, adj1, 0.0, 0.0)
+    Vx0, Vy0, Th0 = adjoint_equilibrium(pb, B, S.ux, S.uy, adj0)
+    rhs = adj0[0] @ d.drho + Vx0 @ d.ux + Vy0 @ d.uy + (Th0 @ d.T if thermal else 0.0)
+    return abs(lhs - rhs) / abs(lhs)
+
+
+@pytest.mark.parametrize("thermal", [False, True])
+def test_exact_mode_is_the_transpose_for_any_alpha(thermal):
+    assert _dot_mismatch("exact", thermal) < 1e-12
+
+
+@pytest.mark.parametrize("thermal", [False, True])
+def test_paper_mode_is_not_the_transpose_with_brinkman(thermal):
+    assert _dot_mismatch("paper", thermal) > 1e-4
+
+
+def _periodic_unsteady(mode):
+    nx, ny = 14, 12
+    wl = W.periodic_box(nx, ny, nu=0.1, thermal=True, Pr=6)
+    wl.mode, wl.objective = W.MODE_UNSTEADY, W.OBJ_HEAT
+    wl.Ks_over_Kf, wl.alpha_max = 1.0, 0.5  # uniform B; alpha varies with gamma
+    wl.adjoint_mode = mode
+    wl.mask = wl.mask.copy()
+    wl.mask[3:8, 5] |= W.TAG_PROBE
+    wl.gamma = np.clip(W.gamma_grf(nx, ny, 3.0, 4), 0.2, 1.0)
+    n = 40
+    wl.n_fwd, wl.ufac = n, np.ones(n + 1)
+    j = np.arange(ny)[:, None] * np.ones((1, nx))
+    i = np.arange(nx)[None, :] * np.ones((ny, 1))
+    s0 = State(np.zeros(nx * ny), (0.05 * np.sin(2 * np.pi * j / ny)).ravel(),
+               (0.03 * np.cos(2 * np.pi * i / nx)).ravel(), np.sin(2 * np.pi * i / nx).ravel())
+    return wl, s0
+
+
+def _grad_vs_fd(mode):
+    wl, s0 = _periodic_unsteady(mode)
+    pb = Problem(wl)
+    n = wl.n_fwd
+    _, _, traj = forward(pb, wl.gamma, n, store=True, state0=s0)
+    _, sens = adjoint_unsteady(pb, wl.gamma, traj, 1.0)
+    sens = sens.reshape(wl.ny, wl.nx)
+    pts = [(5, 8), (3, 5), (8, 4), (6, 1), (1, 7), (10, 12)]
+    err = []
+    for (jj, ii) in pts:
+        vals = []
+        for e in (1e-4, -1e-4):
+            g = wl.gamma.copy()
+            g[jj, ii] += e
+            vals.append(forward(pb, g, n, state0=s0)[1])
+        fd = (vals[0] - vals[1]) / 2e-4
+        err.append(abs(sens[jj, ii] / fd - 1.0))
+    return max(err)
+
+
+def test_exact_mode_gradient_equals_central_differences():
+    # central differences with eps = 1e-4 carry an O(eps^2) truncation error
+    assert _grad_vs_fd("exact") < 1e-6
+
+
+def test_paper_mode_gradient_is_approximate():
+    assert _grad_vs_fd("paper") > 1e-4
