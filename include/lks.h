@@ -60,6 +60,7 @@ enum { LKS_D2Q9 = 0, LKS_D3Q19 = 1 };
 enum { LKS_FP64 = 0, LKS_FP32DEV = 1 };
 enum { LKS_OBJ_PRESSURE_DROP = 0, LKS_OBJ_HEAT = 1 };
 enum { LKS_STEADY = 0, LKS_UNSTEADY = 1 };
+enum { LKS_ADJ_PAPER = 0, LKS_ADJ_EXACT = 1 };
 
 /* Node-class byte (one per node):
  *   bits 0-1 flow class: interior (design) node, prescribed velocity
@@ -225,6 +226,21 @@ lks_status lks_set_tile_rows(lks_ctx *ctx, int tile_rows);
  * 4-node halo and runs two steps, the first on the tile and a 2-node halo
  * kept in LDS; results agree with one step per launch to rounding. */
 lks_status lks_set_steps_per_launch(lks_ctx *ctx, int forward_steps, int adjoint_steps);
+
+/* Adjoint formulation used by alks_backward and alks_advance.
+ * LKS_ADJ_PAPER (default): the ALKS of Sec. 2.5, where the implicit Brinkman
+ * division acts on u~ at the node where the adjoint moments are formed
+ * (eq:albef_ex) and the sensitivity pairs 3 alpha'(gamma) u.u~.
+ * LKS_ADJ_EXACT: the transpose of the discrete LKS step u = U* / (1 + alpha).
+ * u~ stays undivided, the coefficient V of eq:afeq is divided by 1 + alpha at
+ * its own node before it propagates, the Brinkman part of the sensitivity is
+ * alpha' u.V / (1 + alpha) with the undivided V, and an unsteady sweep sums
+ * the sensitivity over levels 1..N only (level 0 is the initial state). On
+ * periodic grids with uniform B this gives the exact discrete gradient; ring
+ * and face nodes keep the paper's least-squares completion. Changing the
+ * mode discards the adjoint state. Batches always use LKS_ADJ_PAPER.
+ * Errors: LKS_E_INVALID for another value. */
+lks_status lks_set_adjoint_mode(lks_ctx *ctx, int mode);
 
 /* The launch shape in use: tile height (0 for D3Q19) and steps per launch of
  * the forward and adjoint sweeps. */

@@ -32,7 +32,8 @@ class _Problem3(ctypes.Structure):
                 ("rho_out", ctypes.c_double),
                 ("mask", ctypes.POINTER(ctypes.c_uint8)),
                 ("ubar", ctypes.POINTER(ctypes.c_double)),
-                ("Tbar", ctypes.POINTER(ctypes.c_double))]
+                ("Tbar", ctypes.POINTER(ctypes.c_double)),
+                ("adj_exact", ctypes.c_int)]
 
 
 _lib = None
@@ -53,9 +54,9 @@ def lib():
         _lib.orc3_pressure_drop.restype = c
         _lib.orc3_probe_heat.argtypes = [P, d, d]
         _lib.orc3_probe_heat.restype = c
-        _lib.orc3_adjoint_equilibrium.argtypes = [P, d, d, dd, d, d]
+        _lib.orc3_adjoint_equilibrium.argtypes = [P, d, d, dd, d, d, d]
         _lib.orc3_alks_step.argtypes = [P, d, d, d, d, d, d, dd, dd, c, c, d]
-        _lib.orc3_sens_add.argtypes = [P, d, d, d, d, dd, c, d]
+        _lib.orc3_sens_add.argtypes = [P, d, d, d, d, d, dd, c, d]
         _lib.orc3_boundary_fill.argtypes = [P, ctypes.c_uint8, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_int, c, c, c, c, c, c, d, d, d]
     return _lib
@@ -82,7 +83,8 @@ class Problem3:
                            wl.nu, Kf, Kf * wl.Ks_over_Kf, wl.q_K, wl.alpha_max, wl.q_alpha,
                            wl.rho_out,
                            self.mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
-                           _p(self.ubar), _p(self.Tbar))
+                           _p(self.ubar), _p(self.Tbar),
+                           int(getattr(wl, "adjoint_mode", "paper") == "exact"))
         self.ref = ctypes.byref(self.c)
 
     def zeros(self, k=None, width=1):
@@ -127,11 +129,14 @@ def level_objective(pb: Problem3, s: State3) -> float:
     return lib().orc3_probe_heat(pb.ref, _p(s.u), _p(s.T))
 
 
-def adjoint_equilibrium(pb: Problem3, B, u, adj):
-    """(V (3 N), Theta): the coefficients of eq:afeq / eq:ageq."""
+def adjoint_equilibrium(pb: Problem3, B, u, adj, alpha=None):
+    """(V (3 N), Theta): the coefficients of eq:afeq / eq:ageq; with alpha,
+    V divided by 1 + alpha (the propagated coefficient of the exact mode)."""
     V, Th = pb.zeros(width=3), pb.zeros()
     pp, keep = _pp(adj)
-    lib().orc3_adjoint_equilibrium(pb.ref, _p(B), _p(u), pp, _p(V), _p(Th))
+    a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
+    lib().orc3_adjoint_equilibrium(pb.ref, _p(B), _p(u), pp, _p(V), _p(Th),
+                                   None if a is None else _p(a))
     return V, Th
 
 
@@ -145,9 +150,9 @@ def alks_step(pb: Problem3, alpha, B, src: State3, dst: State3, adj_in, seed_dp,
     return out
 
 
-def sens_add(pb: Problem3, dalpha, dB, s: State3, adj, weight, sens):
+def sens_add(pb: Problem3, alpha, dalpha, dB, s: State3, adj, weight, sens):
     pp, keep = _pp(adj)
-    lib().orc3_sens_add(pb.ref, _p(dalpha), _p(dB), _p(s.u), _p(s.T), pp, weight,
+    lib().orc3_sens_add(pb.ref, _p(alpha), _p(dalpha), _p(dB), _p(s.u), _p(s.T), pp, weight,
                         _p(sens))
 
 
@@ -187,7 +192,7 @@ def adjoint_steady(pb: Problem3, gamma, state: State3, n_adj, seed=1.0):
     for _ in range(n_adj):
         adj = alks_step(pb, alpha, B, state, state, adj, sdp, sh)
     sens = np.zeros(pb.N)
-    sens_add(pb, dalpha, dB, state, adj, 1.0, sens)
+    sens_add(pb, alpha, dalpha, dB, state, adj, 1.0, sens)
     return adj, sens
 
 
@@ -204,7 +209,9 @@ def adjoint_unsteady(pb: Problem3, gamma, traj, seed=1.0):
         sdp = w if wl.objective == OBJ_PRESSURE_DROP else 0.0
         sh = w if wl.objective == OBJ_HEAT else 0.0
         adj = alks_step(pb, alpha, B, traj[min(n + 1, N)], traj[n], adj, sdp, sh)
-        sens_add(pb, dalpha, dB, traj[n], adj, 1.0, sens)
+        # the exact mode sums the levels the steps produce (1..N)
+        if n >= 1 or getattr(wl, "adjoint_mode", "paper") != "exact":
+            sens_add(pb, alpha, dalpha, dB, traj[n], adj, 1.0, sens)
     return adj, sens
 
 

@@ -75,6 +75,7 @@ typedef struct {
   const uint8_t *mask;       /* nx*ny*nz node classes */
   const double *ubar;        /* 3 N prescribed velocity (x, y, z blocks) */
   const double *Tbar;        /* N prescribed temperature */
+  int adj_exact;             /* 1: exact discrete adjoint of the Brinkman step */
 } orc3_problem;
 
 static inline int n_of(const orc3_problem *P, int a) {
@@ -330,24 +331,37 @@ static const int SIDX[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
 /* eq:afeq, eq:ageq with three components:
  *   V_a = 3 u~_a + 9 s~_ab u_b - 3 rho~ u_a - 2A d_b s~_ab
  *   Theta = T~ + 3 q~.u - B div q~ - grad B . q~ */
-void orc3_adjoint_equilibrium(const orc3_problem *P, const double *B, const double *u,
-                              const double *const *adj, double *V, double *Theta) {
+/* V_a at node k (x its coordinates) from the adjoint moments and the state u */
+static void adj_V3(const orc3_problem *P, long k, const int x[3], const double *u,
+                   const double *const *adj, double V[3]) {
   const long N = (long)P->nx * P->ny * P->nz;
   const double A = coef_A3(P);
+  double uk[3] = {u[k], u[N + k], u[2 * N + k]};
+  for (int a = 0; a < 3; ++a) {
+    double su = 0, ds = 0;
+    for (int b = 0; b < 3; ++b) {
+      const double *s = adj[S3 + SIDX[a][b]];
+      su += s[k] * uk[b];
+      ds += dd3(P, s, x, b);
+    }
+    V[a] = 3.0 * adj[U3 + a][k] + 9.0 * su - 3.0 * adj[R3][k] * uk[a] - 2.0 * A * ds;
+  }
+}
+
+/* With alpha given (exact mode), V is divided by 1 + alpha at its node. */
+void orc3_adjoint_equilibrium(const orc3_problem *P, const double *B, const double *u,
+                              const double *const *adj, double *V, double *Theta,
+                              const double *alpha) {
+  const long N = (long)P->nx * P->ny * P->nz;
 #pragma omp parallel for schedule(static)
   for (long k = 0; k < N; ++k) {
     int x[3];
     coords(P, k, x);
     double uk[3] = {u[k], u[N + k], u[2 * N + k]};
-    for (int a = 0; a < 3; ++a) {
-      double su = 0, ds = 0;
-      for (int b = 0; b < 3; ++b) {
-        const double *s = adj[S3 + SIDX[a][b]];
-        su += s[k] * uk[b];
-        ds += dd3(P, s, x, b);
-      }
-      V[a * N + k] = 3.0 * adj[U3 + a][k] + 9.0 * su - 3.0 * adj[R3][k] * uk[a] - 2.0 * A * ds;
-    }
+    double Vk[3];
+    adj_V3(P, k, x, u, adj, Vk);
+    const double sc = alpha ? 1.0 / (1.0 + alpha[k]) : 1.0;
+    for (int a = 0; a < 3; ++a) V[a * N + k] = Vk[a] * sc;
     if (Theta) {
       double qu = 0, divq = 0, gbq = 0;
       for (int a = 0; a < 3; ++a) {
@@ -488,7 +502,7 @@ void orc3_alks_step(const orc3_problem *P, const double *alpha, const double *B,
   const double A = coef_A3(P);
   const int th = P->thermal;
   double *V = work, *Th = work + 3 * N;
-  orc3_adjoint_equilibrium(P, B, u_src, adj_in, V, th ? Th : NULL);
+  orc3_adjoint_equilibrium(P, B, u_src, adj_in, V, th ? Th : NULL, P->adj_exact ? alpha : NULL);
 #pragma omp parallel for schedule(static)
   for (long k = 0; k < N; ++k) {
     int x[3], nrm[3];
@@ -537,7 +551,7 @@ void orc3_alks_step(const orc3_problem *P, const double *alpha, const double *B,
         for (int b = a; b < 3; ++b) s[SIDX[a][b]] += C3[q][a] * C3[q][b] * wf;
       }
     }
-    double inv = 1.0 / (1.0 + alpha[k]);
+    double inv = P->adj_exact ? 1.0 : 1.0 / (1.0 + alpha[k]);
     adj_out[R3][k] = r;
     for (int a = 0; a < 3; ++a) adj_out[U3 + a][k] = U[a] * inv;
     for (int c = 0; c < 6; ++c) adj_out[S3 + c][k] = s[c];
@@ -554,9 +568,9 @@ void orc3_alks_step(const orc3_problem *P, const double *alpha, const double *B,
 }
 
 /* weight * (3 alpha' u.u~ - B' grad T . q~) at every design node */
-void orc3_sens_add(const orc3_problem *P, const double *dalpha, const double *dB,
-                   const double *u, const double *T, const double *const *adj,
-                   double weight, double *sens) {
+void orc3_sens_add(const orc3_problem *P, const double *alpha, const double *dalpha,
+                   const double *dB, const double *u, const double *T,
+                   const double *const *adj, double weight, double *sens) {
   const long N = (long)P->nx * P->ny * P->nz;
 #pragma omp parallel for schedule(static)
   for (long k = 0; k < N; ++k) {
@@ -564,8 +578,16 @@ void orc3_sens_add(const orc3_problem *P, const double *dalpha, const double *dB
     coords(P, k, x);
     if (ends(P, x, nrm) > 0 || (P->mask[k] & TAG_SOLID)) continue;
     double v = 0.0;
-    for (int a = 0; a < 3; ++a) v += u[a * N + k] * adj[U3 + a][k];
-    v *= 3.0 * dalpha[k];
+    if (P->adj_exact) {
+      /* alpha' u.V / (1 + alpha) with the undivided V */
+      double Vk[3];
+      adj_V3(P, k, x, u, adj, Vk);
+      for (int a = 0; a < 3; ++a) v += u[a * N + k] * Vk[a];
+      v *= dalpha[k] / (1.0 + alpha[k]);
+    } else {
+      for (int a = 0; a < 3; ++a) v += u[a * N + k] * adj[U3 + a][k];
+      v *= 3.0 * dalpha[k];
+    }
     if (P->thermal && T)
       for (int a = 0; a < 3; ++a) v -= dB[k] * dd3(P, T, x, a) * adj[Q3 + a][k];
     sens[k] += weight * v;

@@ -123,6 +123,7 @@ struct AdjArgs {
   const RingOp* ops;  // 4 ring orientations: -x, +x, -y, +y
   double* sens;  // dJ/dgamma (double)
   int sens_mode; // 0 none, 1 accumulate, 2 overwrite
+  int exact;     // 1: exact discrete adjoint of the Brinkman step
   double seed_dp;
   double seed_heat;
 };
@@ -211,6 +212,7 @@ struct Adj3Args {
   const FaceOp3* ops;  // -x, +x, -y, +y, -z, +z
   double* sens;
   int sens_mode;       // 0 none, 1 accumulate, 2 overwrite
+  int exact;           // 1: exact discrete adjoint of the Brinkman step
   double seed_dp;
   double seed_heat;
 };

@@ -753,7 +753,10 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
       Tt -= R(a.seed_heat) * a.ux[kl];
     }
   }
-  const R utx = Ux * s, uty = Uy * s;
+  // paper: u~ = U~ / (1 + alpha) here; exact: V is divided by 1 + alpha
+  // instead, after it is formed from the undivided u~
+  const R su = a.exact ? R(1) : s;
+  const R utx = Ux * su, uty = Uy * su;
   auto ldx = [&](int f) { return lds_dx<INT>(lm + f * SM, pm, 1, i, g.nx, g.periodic); };
   auto ldy = [&](int f) { return lds_dx<INT>(lm + f * SM, pm, PM, j, g.ny, g.periodic); };
   const R dsx = ldx(3) + ldy(4);
@@ -761,6 +764,14 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
   r_out = r;
   Vx = R(3) * utx + R(9) * (sxx * ux + sxy * uy) - R(3) * r * ux - A2 * dsx;
   Vy = R(3) * uty + R(9) * (sxy * ux + syy * uy) - R(3) * r * uy - A2 * dsy;
+  // the Brinkman pairing of the sensitivity: 3 alpha' u.u~ (paper) or
+  // alpha' u.V / (1 + alpha) with the undivided V (exact)
+  const double pair = a.exact ? double(s) / 3.0 * (double(ux) * double(Vx) + double(uy) * double(Vy))
+                              : double(ux) * double(utx) + double(uy) * double(uty);
+  if (a.exact) {
+    Vx *= s;
+    Vy *= s;
+  }
   if constexpr (TH) {
     const R divq = ldx(7) + ldy(8);
     const R Bk = lB[pr];
@@ -772,7 +783,7 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
   if (want_sens) {
     double v = 0.0;
     if (!ring) {
-      v = double(a.dA3[k]) * (double(ux) * double(utx) + double(uy) * double(uty));
+      v = double(a.dA3[k]) * pair;
       if constexpr (TH) {
         const double dTx = double(lds_dx<INT>(lTn, pr, 1, i, g.nx, g.periodic));
         const double dTy = double(lds_dx<INT>(lTn, pr, PR, j, g.ny, g.periodic));

@@ -842,7 +842,8 @@ __device__ void alks3_node(const Geo3& g, const Adj3Args<R>& a, P3 p, int k, int
   const int m = a.mask[k];
   const R Tn = TH ? a.T[k] : R(0);
   if (ne) face_fill<R, TH>(a, k, m, o, Tn, f, gq, M);
-  adj_local<R, TH>(a, k, m, ne, Tn, a.inv1pa[k], M);
+  // exact mode: u~ stays undivided; the update pass divides V instead
+  adj_local<R, TH>(a, k, m, ne, Tn, a.exact ? R(1) : a.inv1pa[k], M);
 }
 
 template <typename R, bool TH>
@@ -951,11 +952,12 @@ __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
   };
   // per-node inputs one plane ahead
   struct In {
-    R r, U[3], Tt, u[3], dA, dB;
+    R r, U[3], Tt, u[3], dA, dB, ip;
     int mk;
   };
   auto node_in = [&](int p, In& q) {
     q.r = q.Tt = q.dA = q.dB = R(0);
+    q.ip = R(1);
     q.mk = 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) q.U[c] = q.u[c] = R(0);
@@ -969,6 +971,7 @@ __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
     }
     if constexpr (TH) q.Tt = a.m[10 * N + k];
     q.mk = a.mask[k];
+    if (a.exact) q.ip = a.inv1pa[k];
     if (a.sens_mode) {
       q.dA = a.dA3[k];
       if constexpr (TH) q.dB = a.dB[k];
@@ -1018,6 +1021,18 @@ __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
         for (int b = 0; b < 3; ++b) su += S[SI[c][b]] * cu.u[b];
         V[c] = R(3) * cu.U[c] + R(9) * su - R(3) * cu.r * cu.u[c] - A2 * ds[c];
       }
+      // the Brinkman pairing of the sensitivity: 3 alpha' u.u~ (paper) or
+      // alpha' u.V / (1 + alpha) with the undivided V, which then propagates
+      // divided by 1 + alpha (exact)
+      double pair = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        pair += double(cu.u[c]) * double(a.exact ? V[c] : cu.U[c]);
+      if (a.exact) {
+        pair *= double(cu.ip) / 3.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[c] *= cu.ip;
+      }
       a.p1[0][k] = cu.r;
       a.p1[1][k] = V[0];
       a.p1[2][k] = V[1];
@@ -1036,10 +1051,7 @@ __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
       if (a.sens_mode) {
         double sv = 0.0;
         if (!n0.ex && !n0.ey && !ez && !(cu.mk & TAG_SOLID3)) {
-          double uu = 0.0;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) uu += double(cu.u[c]) * double(cu.U[c]);
-          sv = double(cu.dA) * uu;
+          sv = double(cu.dA) * pair;
           if constexpr (TH) {
             const R* Tp = E[TH ? 7 : 0];
             const R gt[3] = {d1(Tp, ci, 1, n0.ex), d1(Tp, ci, CXN, n0.ey), zd[4]};

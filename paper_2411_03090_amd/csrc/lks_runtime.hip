@@ -80,6 +80,7 @@ struct lks_ctx {
   // run state
   bool have_forward = false;
   bool have_adjoint = false;
+  int adj_exact = 0;     // LKS_ADJ_EXACT: transpose of the discrete Brinkman step
   int cur = 0;      // steady forward: ping-pong index of the current level
   int acur = 0;     // adjoint: ping-pong index of the current level
   int last_level = 0;
@@ -565,6 +566,7 @@ struct Run {
       a.ops = c->d_ops3;
       a.sens = sens;
       a.sens_mode = sens ? mode : 0;
+      a.exact = c->adj_exact;
       a.seed_dp = sdp;
       a.seed_heat = sh;
       lks::launch_alks3_step<R>(c->geo3, a, c->stream);
@@ -596,6 +598,7 @@ struct Run {
     a.th1 = rp<R>(c->P[i1][3]);
     a.sens = sens;
     a.sens_mode = sens ? mode : 0;
+    a.exact = c->adj_exact;
     a.seed_dp = sdp;
     a.seed_heat = sh;
     a.ops = c->d_ops;
@@ -652,7 +655,9 @@ struct Run {
         const double w = n >= 1 ? seed / Nst : 0.0;
         const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? w : 0.0;
         const double sh = c->objective == LKS_OBJ_HEAT ? w : 0.0;
-        adj_step(lv, sdp, sh, dJ, 1);
+        // the exact mode sums the levels the steps produce; level 0 is the
+        // initial state, which does not depend on gamma
+        adj_step(lv, sdp, sh, (n == 0 && c->adj_exact) ? nullptr : dJ, 1);
       }
     }
   }
@@ -1037,6 +1042,15 @@ lks_status lks_set_steps_per_launch(lks_ctx* c, int forward_steps, int adjoint_s
   return LKS_OK;
 }
 
+lks_status lks_set_adjoint_mode(lks_ctx* c, int mode) {
+  if (!c) return LKS_E_INVALID;
+  if (mode != LKS_ADJ_PAPER && mode != LKS_ADJ_EXACT)
+    return fail(c, LKS_E_INVALID, "adjoint mode must be LKS_ADJ_PAPER or LKS_ADJ_EXACT");
+  if (mode != c->adj_exact) c->have_adjoint = false;
+  c->adj_exact = mode;
+  return LKS_OK;
+}
+
 lks_status lks_launch_shape(const lks_ctx* c, int* tile_rows, int* forward_steps,
                             int* adjoint_steps) {
   if (!c) return LKS_E_INVALID;
@@ -1241,6 +1255,7 @@ void build_batch_desc(lks_batch* b, double seed, int nf, std::vector<char>& fwd,
         a.ops = c->d_ops;
         a.sens = b->d_sens + size_t(d) * b->maxN;
         a.sens_mode = 0;
+        a.exact = 0;
         a.seed_dp = c->objective == LKS_OBJ_PRESSURE_DROP ? seed : 0.0;
         a.seed_heat = c->objective == LKS_OBJ_HEAT ? seed : 0.0;
       }

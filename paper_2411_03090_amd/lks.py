@@ -43,6 +43,7 @@ LKS_D2Q9, LKS_D3Q19 = 0, 1
 LKS_FP64, LKS_FP32DEV = 0, 1
 LKS_OBJ_PRESSURE_DROP, LKS_OBJ_HEAT = 0, 1
 LKS_STEADY, LKS_UNSTEADY = 0, 1
+LKS_ADJ_PAPER, LKS_ADJ_EXACT = 0, 1
 FIELDS = {"drho": 0, "ux": 1, "uy": 2, "T": 3,
           "adj_rho": 4, "adj_vx": 5, "adj_vy": 6, "adj_theta": 7,
           "uz": 8, "adj_vz": 9}
@@ -54,7 +55,7 @@ EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forwa
             "lks_batch_bind_workspace", "lks_batch_run", "lks_batch_read_field",
             "lks_batch_last_error", "lks_batch_destroy", "lks_autotune",
             "lks_batch_autotune", "lks_set_tile_rows", "lks_set_steps_per_launch",
-            "lks_launch_shape", "lks_batch_set_tile_rows")
+            "lks_launch_shape", "lks_batch_set_tile_rows", "lks_set_adjoint_mode")
 
 
 class Grid(ctypes.Structure):
@@ -138,6 +139,8 @@ _lib.lks_set_steps_per_launch.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
 _lib.lks_set_steps_per_launch.restype = _st
 _lib.lks_launch_shape.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int)] * 3
 _lib.lks_launch_shape.restype = _st
+_lib.lks_set_adjoint_mode.argtypes = [_vp, ctypes.c_int]
+_lib.lks_set_adjoint_mode.restype = _st
 _lib.lks_batch_set_tile_rows.argtypes = [_vp, ctypes.c_int]
 _lib.lks_batch_set_tile_rows.restype = _st
 _lib.lks_batch_destroy.argtypes = [_vp]
@@ -202,6 +205,9 @@ class LKS:
         _check(_lib.lks_create(ctypes.byref(self.grid), ctypes.byref(self.phys),
                                ctypes.byref(self.bc), ctypes.c_size_t(int(mem_budget)),
                                _vp(stream or 0), ctypes.byref(self.ctx)))
+        mode = getattr(wl, "adjoint_mode", "paper")
+        if mode != "paper":
+            self.set_adjoint_mode(mode)
         if bind:
             self.bind()
 
@@ -265,6 +271,12 @@ class LKS:
     def set_steps_per_launch(self, forward, adjoint=None):
         adjoint = forward if adjoint is None else adjoint
         _check(_lib.lks_set_steps_per_launch(self.ctx, int(forward), int(adjoint)), self.ctx)
+
+    def set_adjoint_mode(self, mode):
+        """"paper" (the ALKS of Sec. 2.5) or "exact" (the transpose of the
+        discrete Brinkman step); see lks_set_adjoint_mode."""
+        code = {"paper": LKS_ADJ_PAPER, "exact": LKS_ADJ_EXACT}[mode]
+        _check(_lib.lks_set_adjoint_mode(self.ctx, code), self.ctx)
 
     def launch_shape(self):
         """(tile rows, forward steps per launch, adjoint steps per launch)."""

@@ -127,7 +127,7 @@ def test_single_adjoint_step_3d(case, prec):
     adj0 = O3.alks_step(pb, a, B, s, s, adj1, sdp, sh)
     V0, Th0 = O3.adjoint_equilibrium(pb, B, s.u, adj0)
     sens = np.zeros(N)
-    O3.sens_add(pb, da, dB, s, adj0, 1.0, sens)
+    O3.sens_add(pb, a, da, dB, s, adj0, 1.0, sens)
 
     ctx = lks.LKS(wl, precision=prec, device=DEV)
     g = T(wl.gamma)

@@ -104,3 +104,72 @@ def test_exact_mode_gradient_equals_central_differences():
 
 def test_paper_mode_gradient_is_approximate():
     assert _grad_vs_fd("paper") > 1e-4
+
+
+# ---------------------------------------------------------------------------
+# D3Q19
+# ---------------------------------------------------------------------------
+def _dot_mismatch_3d(mode, thermal):
+    from oracle import d3 as O3
+    nx, ny, nz = 6, 5, 4
+    wl = W.periodic_box3(nx, ny, nz, nu=0.1, thermal=thermal)
+    wl.adjoint_mode = mode
+    pb = O3.Problem3(wl)
+    N = nx * ny * nz
+    rng = np.random.default_rng(5)
+    a = 2.0 * rng.random(N)
+    B = np.full(N, 0.45)
+    S = O3.State3(1e-2 * rng.standard_normal(N), 0.05 * rng.standard_normal(3 * N),
+                  rng.standard_normal(N))
+    d = O3.State3(rng.standard_normal(N), rng.standard_normal(3 * N), rng.standard_normal(N))
+    sh = lambda sg: O3.State3(S.drho + sg * d.drho, S.u + sg * d.u, S.T + sg * d.T)
+    Fp = O3.lks_step(pb, a, B, 1.0, sh(1.0))
+    Fm = O3.lks_step(pb, a, B, 1.0, sh(-1.0))
+    Ld = O3.State3((Fp.drho - Fm.drho) / 2, (Fp.u - Fm.u) / 2, (Fp.T - Fm.T) / 2)
+    S1 = O3.lks_step(pb, a, B, 1.0, S)
+    adj1 = [rng.standard_normal(N) for _ in range(14)]
+    V1, Th1 = O3.adjoint_equilibrium(pb, B, S1.u, adj1)
+    lhs = adj1[0] @ Ld.drho + V1 @ Ld.u + (Th1 @ Ld.T if thermal else 0.0)
+    adj0 = O3.alks_step(pb, a, B, S1, S, adj1, 0.0, 0.0)
+    V0, Th0 = O3.adjoint_equilibrium(pb, B, S.u, adj0)
+    rhs = adj0[0] @ d.drho + V0 @ d.u + (Th0 @ d.T if thermal else 0.0)
+    return abs(lhs - rhs) / abs(lhs)
+
+
+@pytest.mark.parametrize("thermal", [False, True])
+def test_exact_mode_is_the_transpose_for_any_alpha_3d(thermal):
+    assert _dot_mismatch_3d("exact", thermal) < 1e-12
+
+
+def test_paper_mode_is_not_the_transpose_with_brinkman_3d():
+    assert _dot_mismatch_3d("paper", True) > 1e-4
+
+
+def test_exact_mode_gradient_equals_central_differences_3d():
+    from oracle import d3 as O3
+    nx, ny, nz = 6, 5, 4
+    wl = W.periodic_box3(nx, ny, nz, nu=0.1, thermal=True, Pr=6.0)
+    wl.mode, wl.objective = W.MODE_UNSTEADY, W.OBJ_HEAT
+    wl.alpha_max, wl.Ks_over_Kf = 0.5, 1.0
+    wl.adjoint_mode = "exact"
+    wl.gamma = np.clip(0.6 + 0.4 * W.gaussian_random_field((nz, ny, nx), 1.5, 2), 0.1, 1.0)
+    wl.mask = wl.mask.copy()
+    wl.mask[1:3, 2:4, 3] |= W.TAG_PROBE
+    n = 20
+    wl.n_fwd, wl.ufac = n, np.ones(n + 1)
+    pb = O3.Problem3(wl)
+    rng = np.random.default_rng(2)
+    N = pb.N
+    s0 = O3.State3(np.zeros(N), 0.03 * rng.standard_normal(3 * N), rng.random(N))
+    _, _, traj = O3.forward(pb, wl.gamma, n, store=True, state0=s0)
+    _, sens = O3.adjoint_unsteady(pb, wl.gamma, traj, 1.0)
+    sens = sens.reshape(nz, ny, nx)
+    err = []
+    for p in [(1, 2, 3), (2, 3, 1), (3, 1, 4), (0, 4, 2)]:
+        vals = []
+        for e in (1e-4, -1e-4):
+            g = wl.gamma.copy()
+            g[p] += e
+            vals.append(O3.forward(pb, g, n, state0=s0)[1])
+        err.append(abs(sens[p] / ((vals[0] - vals[1]) / 2e-4) - 1.0))
+    assert max(err) < 1e-6
