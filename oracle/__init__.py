@@ -63,7 +63,8 @@ class _Problem(ctypes.Structure):
                 ("mask", ctypes.POINTER(ctypes.c_uint8)),
                 ("ubar", ctypes.POINTER(ctypes.c_double)),
                 ("Tbar", ctypes.POINTER(ctypes.c_double)),
-                ("adj_exact", ctypes.c_int)]
+                ("adj_exact", ctypes.c_int),
+                ("gbeta", ctypes.c_double * 2), ("T_ref", ctypes.c_double)]
 
 
 _lib = None
@@ -119,7 +120,9 @@ class Problem:
                           wl.rho_out,
                           self.mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                           _p(self.ubar), _p(self.Tbar),
-                          int(getattr(wl, "adjoint_mode", "paper") == "exact"))
+                          int(getattr(wl, "adjoint_mode", "paper") == "exact"),
+                          (ctypes.c_double * 2)(*[float(v) for v in getattr(wl, "gbeta", (0, 0))[:2]]),
+                          float(getattr(wl, "T_ref", 0.0)))
         self.ref = ctypes.byref(self.c)
 
     def zeros(self, k=None):

@@ -64,6 +64,8 @@ typedef struct {
   const double *ubar;    /* 2*nx*ny prescribed velocity (x block, y block) */
   const double *Tbar;    /* nx*ny prescribed temperature */
   int adj_exact;         /* 1: exact discrete adjoint of the Brinkman step */
+  double gbeta[2];       /* g beta of the Boussinesq force eq:boussinesqforce */
+  double T_ref;          /* its reference temperature */
 } orc_problem;
 
 /* ------------------------------------------------------------------ */
@@ -281,9 +283,17 @@ void orc_lks_step(const orc_problem *P, const double *alpha, const double *B,
       }
 
       if (!bnd) {
+        /* eq:lbef_ex with the Brinkman and the Boussinesq force
+         * G = g beta (T - T_ref) (eq:boussinesqforce) at the new level:
+         * u (1 + alpha) = U* + G */
+        double Gx = 0.0, Gy = 0.0;
+        if (th) {
+          Gx = P->gbeta[0] * (T_s - P->T_ref);
+          Gy = P->gbeta[1] * (T_s - P->T_ref);
+        }
         drho_o[k] = rho_s;
-        ux_o[k] = Ux / (1.0 + alpha[k]);
-        uy_o[k] = Uy / (1.0 + alpha[k]);
+        ux_o[k] = (Ux + Gx) / (1.0 + alpha[k]);
+        uy_o[k] = (Uy + Gy) / (1.0 + alpha[k]);
         if (th) T_o[k] = T_s;
         continue;
       }
@@ -397,6 +407,11 @@ void orc_adjoint_equilibrium(const orc_problem *P, const double *B,
         double dBx = ddx(P, B, i, j, 0), dBy = ddx(P, B, i, j, 1);
         Theta[k] = adj[A_T][k] + 3.0 * (qx * u[0] + qy * u[1]) - B[k] * divq -
                    (dBx * qx + dBy * qy);
+        /* exact mode: the propagated Theta also carries the dependence of
+         * the new velocity on the new temperature through G, whose adjoint
+         * is g beta . V / (1 + alpha) at interior nodes */
+        if (alpha && !on_ring(P, i, j))
+          Theta[k] += (P->gbeta[0] * V[0] + P->gbeta[1] * V[1]) * sc;
       }
     }
   }
@@ -632,6 +647,10 @@ void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
       /* paper: u~ = U~ / (1 + alpha) here; exact: the division is applied to
        * V at this node before the next pull */
       double inv = P->adj_exact ? 1.0 : 1.0 / (1.0 + alpha[k]);
+      /* paper: the Boussinesq coupling 3 dG/dg_i . u~ of eq:albeg_ex adds
+       * 3 g beta . u~ to T~ at interior nodes (sum_i w_i = 1) */
+      if (th && !bnd && !P->adj_exact)
+        Tt += 3.0 * (P->gbeta[0] * Ux + P->gbeta[1] * Uy) * inv;
       adj_out[A_R][k] = r;
       adj_out[A_UX][k] = Ux * inv;
       adj_out[A_UY][k] = Uy * inv;

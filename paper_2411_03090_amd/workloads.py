@@ -71,6 +71,10 @@ class Workload:
     # formed); "exact": the transpose of the discrete Brinkman step (V divided
     # by 1 + alpha at its node, sensitivity alpha' u.V / (1 + alpha))
     adjoint_mode: str = "paper"
+    # Boussinesq force G = g beta (T - T_ref) (eq:boussinesqforce): the vector
+    # g beta and T_ref, lattice units; zero means no force
+    gbeta: tuple = (0.0, 0.0)
+    T_ref: float = 0.0
     mask: np.ndarray = field(default=None, repr=False)      # (ny, nx) uint8
     gamma: np.ndarray = field(default=None, repr=False)     # (ny, nx) f64
     ubar: np.ndarray = field(default=None, repr=False)      # (2, ny, nx) f64
