@@ -123,6 +123,11 @@ typedef struct {
   double Ks_over_Kf;  /* K_s / K_f of eq:conductivity */
   double q_K;         /* q_K of eq:conductivity */
   int thermal;        /* 1: solve the temperature field too */
+  double gbeta[3];    /* g beta of the Boussinesq force G = g beta (T - T_ref)
+                         (eq:boussinesqforce), lattice units; all zero: no
+                         force. Non-zero needs a thermal D2Q9 problem (D3Q19:
+                         LKS_E_UNSUPPORTED); the third component is unused */
+  double T_ref;       /* reference temperature of the Boussinesq force */
 } lks_phys;
 
 typedef struct {

@@ -41,6 +41,8 @@ struct Geo {
   double A;         // eq:A
   double Bf;        // B of the fluid, used on boundary nodes
   double drho_out;  // prescribed outlet density minus 1
+  double gbx, gby;  // g beta of the Boussinesq force (0: none)
+  double Tref;      // its reference temperature
 };
 
 __host__ __device__ inline int tiles_along(int n, int t) {

@@ -350,12 +350,18 @@ __device__ inline void fwd_pull(const Geo& g, const FwdArgs<R>& a, const R* lf, 
   Tn = R(0);
   if (fc == FLOW_INTERIOR) {
     dn = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    const R Ux = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-    const R Uy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+    R Ux = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+    R Uy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+    if constexpr (TH) {
+      Tn = gg[0] + gg[1] + gg[2] + gg[3] + gg[4] + gg[5] + gg[6] + gg[7] + gg[8];
+      // Boussinesq force at the new level, u (1 + alpha) = U* + G
+      // (eq:lbef_ex, eq:boussinesqforce); zero when g beta is zero
+      const R dT = Tn - R(g.Tref);
+      Ux += R(g.gbx) * dT;
+      Uy += R(g.gby) * dT;
+    }
     uxn = Ux * s;
     uyn = Uy * s;
-    if constexpr (TH)
-      Tn = gg[0] + gg[1] + gg[2] + gg[3] + gg[4] + gg[5] + gg[6] + gg[7] + gg[8];
     return;
   }
   const int nx_ = (i == 0) ? -1 : (i == g.nx - 1 ? 1 : 0);
@@ -757,6 +763,10 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
   // instead, after it is formed from the undivided u~
   const R su = a.exact ? R(1) : s;
   const R utx = Ux * su, uty = Uy * su;
+  // paper: the Boussinesq coupling of eq:albeg_ex, 3 g beta . u~ on T~ at
+  // interior nodes (zero when g beta is zero)
+  if constexpr (TH)
+    if (!ring && !a.exact) Tt += R(3) * (R(g.gbx) * utx + R(g.gby) * uty);
   auto ldx = [&](int f) { return lds_dx<INT>(lm + f * SM, pm, 1, i, g.nx, g.periodic); };
   auto ldy = [&](int f) { return lds_dx<INT>(lm + f * SM, pm, PM, j, g.ny, g.periodic); };
   const R dsx = ldx(3) + ldy(4);
@@ -778,6 +788,9 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
     const R dBx = lds_dx<INT>(lB, pr, 1, i, g.nx, g.periodic);
     const R dBy = lds_dx<INT>(lB, pr, PR, j, g.ny, g.periodic);
     Th = Tt + R(3) * (qx * ux + qy * uy) - Bk * divq - (dBx * qx + dBy * qy);
+    // exact: the propagated Theta carries the force's dependence on the new
+    // temperature, g beta . V / (1 + alpha), at interior nodes
+    if (!ring && a.exact) Th += R(g.gbx) * Vx + R(g.gby) * Vy;
   }
   sens = 0.0;
   if (want_sens) {

@@ -225,6 +225,14 @@ lks_status validate_common(const lks_grid* gr, const lks_phys* ph, const lks_bc*
   }
   if (!bc->node_class || !bc->u_bar) return fail(nullptr, LKS_E_INVALID, "null boundary data");
   if (ph->thermal && !bc->T_bar) return fail(nullptr, LKS_E_INVALID, "thermal needs T_bar");
+  const bool force = ph->gbeta[0] != 0.0 || ph->gbeta[1] != 0.0 || ph->gbeta[2] != 0.0;
+  if (!std::isfinite(ph->gbeta[0]) || !std::isfinite(ph->gbeta[1]) ||
+      !std::isfinite(ph->gbeta[2]) || !std::isfinite(ph->T_ref))
+    return fail(nullptr, LKS_E_INVALID, "Boussinesq parameters not finite");
+  if (force && !ph->thermal)
+    return fail(nullptr, LKS_E_INVALID, "the Boussinesq force needs a thermal problem");
+  if (force && gr->lattice == LKS_D3Q19)
+    return fail(nullptr, LKS_E_UNSUPPORTED, "the Boussinesq force is D2Q9 only");
   if (bc->objective != LKS_OBJ_PRESSURE_DROP && bc->objective != LKS_OBJ_HEAT)
     return fail(nullptr, LKS_E_INVALID, "unknown objective");
   if (bc->objective == LKS_OBJ_HEAT && !ph->thermal)
@@ -769,6 +777,9 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
   const double Kf = phys->thermal ? phys->nu / phys->Pr : 0.0;
   g.Bf = 3.0 * (1.0 / 6.0 - Kf);
   g.drho_out = bc->rho_out - 1.0;
+  g.gbx = phys->gbeta[0];
+  g.gby = phys->gbeta[1];
+  g.Tref = phys->T_ref;
   lks::build_ring_ops(g.A, g.Bf, c->ops);
   if (d3) {
     lks::Geo3& g3 = c->geo3;

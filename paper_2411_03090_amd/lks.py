@@ -68,7 +68,8 @@ class Phys(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_double), ("Pr", ctypes.c_double),
                 ("alpha_max", ctypes.c_double), ("q_alpha", ctypes.c_double),
                 ("Ks_over_Kf", ctypes.c_double), ("q_K", ctypes.c_double),
-                ("thermal", ctypes.c_int)]
+                ("thermal", ctypes.c_int), ("gbeta", ctypes.c_double * 3),
+                ("T_ref", ctypes.c_double)]
 
 
 class BC(ctypes.Structure):
@@ -189,8 +190,10 @@ class LKS:
             self.grid = Grid(wl.nx, wl.ny, nz, LKS_D3Q19, prec, int(wl.periodic_axes))
         else:
             self.grid = Grid(wl.nx, wl.ny, 1, LKS_D2Q9, prec, int(wl.periodic))
+        gb = [float(v) for v in getattr(wl, "gbeta", (0.0, 0.0))] + [0.0, 0.0]
         self.phys = Phys(wl.nu, wl.Pr, wl.alpha_max, wl.q_alpha, wl.Ks_over_Kf, wl.q_K,
-                         int(wl.thermal))
+                         int(wl.thermal), (ctypes.c_double * 3)(*gb[:3]),
+                         float(getattr(wl, "T_ref", 0.0)))
         self.bc = BC(self._mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                      _dptr(self._ubar), _dptr(self._Tbar), _dptr(self._ufac),
                      len(self._ufac), wl.rho_out, wl.objective, wl.mode,

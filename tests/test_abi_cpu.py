@@ -86,6 +86,31 @@ def test_heat_objective_needs_thermal():
         _create(wl)
 
 
+def test_boussinesq_force_needs_a_thermal_d2q9_problem():
+    wl = W.steady_channel_uniform(16, 12, Re=10, seed=0)
+    wl.gbeta = (0.0, 0.01)
+    with pytest.raises(lks.LKSError) as e:
+        _create(wl)
+    assert e.value.status == lks.LKS_E_INVALID
+    wl3 = W.heated_block_duct(16, 8, 8, Re=20.0, n_steps=10)
+    wl3.gbeta = (0.0, 0.01, 0.0)
+    with pytest.raises(lks.LKSError) as e:
+        _create(wl3)
+    assert e.value.status == lks.LKS_E_UNSUPPORTED
+    wt = W.unsteady_thermal_channel(16, 12, n_steps=10)
+    wt.gbeta, wt.T_ref = (0.0, 0.01), 0.5
+    _create(wt)
+
+
+def test_adjoint_mode_setter_validates():
+    c = _create(W.steady_channel_uniform(16, 12, Re=10, seed=0))
+    c.set_adjoint_mode("exact")
+    c.set_adjoint_mode("paper")
+    with pytest.raises(lks.LKSError) as e:
+        lks._check(lks._lib.lks_set_adjoint_mode(c.ctx, 7), c.ctx)
+    assert e.value.status == lks.LKS_E_INVALID
+
+
 def test_d3q19_duct_validates_and_plans_without_gpu():
     wl = W.heated_block_duct(32, 16, 12, Re=50.0, n_steps=100)
     c = _create(wl, "fp32")
