@@ -36,6 +36,7 @@ TAG_J_INLET = 16
 TAG_J_OUTLET = 32
 OBJ_PRESSURE_DROP = 0
 OBJ_HEAT = 1
+OBJ_HEAT_EXCHANGE = 2
 MODE_STEADY = 0
 MODE_UNSTEADY = 1
 N_ADJ_FIELDS = 9
@@ -64,7 +65,8 @@ class _Problem(ctypes.Structure):
                 ("ubar", ctypes.POINTER(ctypes.c_double)),
                 ("Tbar", ctypes.POINTER(ctypes.c_double)),
                 ("adj_exact", ctypes.c_int),
-                ("gbeta", ctypes.c_double * 2), ("T_ref", ctypes.c_double)]
+                ("gbeta", ctypes.c_double * 2), ("T_ref", ctypes.c_double),
+                ("beta_max", ctypes.c_double), ("q_beta", ctypes.c_double)]
 
 
 _lib = None
@@ -79,15 +81,19 @@ def lib():
         dd = ctypes.POINTER(d)
         _lib.orc_coefficients.argtypes = [P, d, d, d, d, d]
         _lib.orc_init_state.argtypes = [P, ctypes.c_double, d, d, d, d]
-        _lib.orc_lks_step.argtypes = [P, d, d, ctypes.c_double, d, d, d, d, d, d, d, d]
+        _lib.orc_source_coefficients.argtypes = [P, d, d, d]
+        _lib.orc_lks_step.argtypes = [P, d, d, d, ctypes.c_double, d, d, d, d, d, d, d, d]
+        _lib.orc_source_heat.argtypes = [P, d, d]
+        _lib.orc_source_heat.restype = ctypes.c_double
         _lib.orc_pressure_drop.argtypes = [P, d]
         _lib.orc_pressure_drop.restype = ctypes.c_double
         _lib.orc_probe_heat.argtypes = [P, d, d]
         _lib.orc_probe_heat.restype = ctypes.c_double
-        _lib.orc_adjoint_equilibrium.argtypes = [P, d, d, d, dd, d, d, d, d]
-        _lib.orc_alks_step.argtypes = [P, d, d, d, d, d, d, d, d, dd, dd,
-                                       ctypes.c_double, ctypes.c_double, d]
+        _lib.orc_adjoint_equilibrium.argtypes = [P, d, d, d, dd, d, d, d, d, d]
+        _lib.orc_alks_step.argtypes = [P, d, d, d, d, d, d, d, d, d, dd, dd,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, d]
         _lib.orc_sens_add.argtypes = [P, d, d, d, d, d, d, dd, ctypes.c_double, d]
+        _lib.orc_source_sens_add.argtypes = [P, d, d, d, d, d, d, d, dd, ctypes.c_double, d]
         _lib.orc_boundary_fill.argtypes = [P, ctypes.c_uint8, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double,
@@ -122,7 +128,9 @@ class Problem:
                           _p(self.ubar), _p(self.Tbar),
                           int(getattr(wl, "adjoint_mode", "paper") == "exact"),
                           (ctypes.c_double * 2)(*[float(v) for v in getattr(wl, "gbeta", (0, 0))[:2]]),
-                          float(getattr(wl, "T_ref", 0.0)))
+                          float(getattr(wl, "T_ref", 0.0)),
+                          float(getattr(wl, "beta_max", 0.0)),
+                          float(getattr(wl, "q_beta", 0.1)))
         self.ref = ctypes.byref(self.c)
 
     def zeros(self, k=None):
@@ -147,15 +155,30 @@ def coefficients(pb: Problem, gamma):
     return a, da, B, dB
 
 
+def source_coefficients(pb: Problem, gamma):
+    """(beta, beta') of the heat source eq:heatsource / eq:betagamma, or
+    (None, None) when the problem has no source."""
+    if not getattr(pb.wl, "beta_max", 0.0):
+        return None, None
+    g = np.ascontiguousarray(gamma, dtype=np.float64).reshape(-1)
+    b, db = pb.zeros(2)
+    lib().orc_source_coefficients(pb.ref, _p(g), _p(b), _p(db))
+    return b, db
+
+
+def _opt(a):
+    return None if a is None else _p(a)
+
+
 def init_state(pb: Problem, ufac0=1.0) -> State:
     s = State(*pb.zeros(4))
     lib().orc_init_state(pb.ref, ufac0, _p(s.drho), _p(s.ux), _p(s.uy), _p(s.T))
     return s
 
 
-def lks_step(pb: Problem, alpha, B, ufac, s: State) -> State:
+def lks_step(pb: Problem, alpha, B, ufac, s: State, beta=None) -> State:
     o = State(*pb.zeros(4))
-    lib().orc_lks_step(pb.ref, _p(alpha), _p(B), ufac, _p(s.drho), _p(s.ux), _p(s.uy),
+    lib().orc_lks_step(pb.ref, _p(alpha), _p(B), _opt(beta), ufac, _p(s.drho), _p(s.ux), _p(s.uy),
                        _p(s.T), _p(o.drho), _p(o.ux), _p(o.uy), _p(o.T))
     return o
 
@@ -168,31 +191,39 @@ def probe_heat(pb: Problem, s: State) -> float:
     return lib().orc_probe_heat(pb.ref, _p(s.ux), _p(s.T))
 
 
-def level_objective(pb: Problem, s: State) -> float:
+def source_heat(pb: Problem, beta, s: State) -> float:
+    return lib().orc_source_heat(pb.ref, _p(beta), _p(s.T))
+
+
+def level_objective(pb: Problem, s: State, beta=None) -> float:
     if pb.wl.objective == OBJ_PRESSURE_DROP:
         return pressure_drop(pb, s)
+    if pb.wl.objective == OBJ_HEAT_EXCHANGE:
+        return source_heat(pb, beta if beta is not None else np.zeros(pb.N), s)
     return probe_heat(pb, s)
 
 
-def adjoint_equilibrium(pb: Problem, B, ux, uy, adj, alpha=None):
+def adjoint_equilibrium(pb: Problem, B, ux, uy, adj, alpha=None, beta=None):
     """(V_x, V_y, Theta): the coefficients of eq:afeq / eq:ageq; with alpha,
-    V divided by 1 + alpha (the propagated coefficient of the exact mode)."""
+    V divided by 1 + alpha (the propagated coefficient of the exact mode),
+    and with beta as well, Theta divided by 1 + beta."""
     Vx, Vy, Th = pb.zeros(3)
     pp, keep = _pp(adj)
     a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
     lib().orc_adjoint_equilibrium(pb.ref, _p(B), _p(ux), _p(uy), pp, _p(Vx), _p(Vy),
-                                  _p(Th), None if a is None else _p(a))
+                                  _p(Th), None if a is None else _p(a), _opt(beta))
     return Vx, Vy, Th
 
 
-def alks_step(pb: Problem, alpha, B, src: State, dst: State, adj_in, seed_dp, seed_heat):
+def alks_step(pb: Problem, alpha, B, src: State, dst: State, adj_in, seed_dp, seed_heat,
+              beta=None, seed_src=0.0):
     out = pb.zeros(N_ADJ_FIELDS)
     work = np.zeros(3 * pb.N)
     pin, k1 = _pp(adj_in)
     pout, k2 = _pp(out)
-    lib().orc_alks_step(pb.ref, _p(alpha), _p(B), _p(src.ux), _p(src.uy), _p(src.T),
+    lib().orc_alks_step(pb.ref, _p(alpha), _p(B), _opt(beta), _p(src.ux), _p(src.uy), _p(src.T),
                         _p(dst.ux), _p(dst.uy), _p(dst.T), pin, pout, seed_dp, seed_heat,
-                        _p(work))
+                        seed_src, _p(work))
     return out
 
 
@@ -200,6 +231,14 @@ def sens_add(pb: Problem, alpha, dalpha, dB, s: State, adj, weight, sens):
     pp, keep = _pp(adj)
     lib().orc_sens_add(pb.ref, _p(alpha), _p(dalpha), _p(dB), _p(s.ux), _p(s.uy), _p(s.T),
                        pp, weight, _p(sens))
+
+
+def source_sens_add(pb: Problem, alpha, B, beta, dbeta, s: State, adj, wJ, sens):
+    """Heat-source part of dJ/dgamma at one level (beta'(T - 1)(w_J + T~),
+    or with the propagated Theta in exact mode)."""
+    pp, keep = _pp(adj)
+    lib().orc_source_sens_add(pb.ref, _p(alpha), _p(B), _p(beta), _p(dbeta), _p(s.ux),
+                              _p(s.uy), _p(s.T), pp, wJ, _p(sens))
 
 
 def boundary_fill(pb: Problem, m, normal, Bn, Tn, u, seed_dp, fk, gk):
@@ -222,19 +261,20 @@ def forward(pb: Problem, gamma, n_steps, store=False, state0: State | None = Non
     over levels 1..n_steps."""
     wl = pb.wl
     alpha, _, B, _ = coefficients(pb, gamma)
+    beta, _ = source_coefficients(pb, gamma)
     s = init_state(pb, wl.ufac[0]) if state0 is None else state0.copy()
     traj = [s] if store else None
     acc = 0.0
     for n in range(n_steps):
-        s = lks_step(pb, alpha, B, float(wl.ufac[min(n + 1, len(wl.ufac) - 1)]), s)
+        s = lks_step(pb, alpha, B, float(wl.ufac[min(n + 1, len(wl.ufac) - 1)]), s, beta)
         if wl.mode == MODE_UNSTEADY:
-            acc += level_objective(pb, s)
+            acc += level_objective(pb, s, beta)
         if store:
             traj.append(s)
     if wl.mode == MODE_UNSTEADY:
         J = acc / max(n_steps, 1)
     else:
-        J = level_objective(pb, s)
+        J = level_objective(pb, s, beta)
     return s, J, traj
 
 
@@ -243,13 +283,17 @@ def adjoint_steady(pb: Problem, gamma, state: State, n_adj, seed=1.0):
     every step; returns (adjoint fields, dJ/dgamma)."""
     wl = pb.wl
     alpha, dalpha, B, dB = coefficients(pb, gamma)
+    beta, dbeta = source_coefficients(pb, gamma)
     adj = pb.zeros(N_ADJ_FIELDS)
     sdp = seed if wl.objective == OBJ_PRESSURE_DROP else 0.0
     sh = seed if wl.objective == OBJ_HEAT else 0.0
+    ss = seed if wl.objective == OBJ_HEAT_EXCHANGE else 0.0
     for _ in range(n_adj):
-        adj = alks_step(pb, alpha, B, state, state, adj, sdp, sh)
+        adj = alks_step(pb, alpha, B, state, state, adj, sdp, sh, beta, ss)
     sens = np.zeros(pb.N)
     sens_add(pb, alpha, dalpha, dB, state, adj, 1.0, sens)
+    if beta is not None:
+        source_sens_add(pb, alpha, B, beta, dbeta, state, adj, ss, sens)
     return adj, sens
 
 
@@ -261,16 +305,20 @@ def adjoint_unsteady(pb: Problem, gamma, traj, seed=1.0):
     wl = pb.wl
     N = len(traj) - 1
     alpha, dalpha, B, dB = coefficients(pb, gamma)
+    beta, dbeta = source_coefficients(pb, gamma)
     adj = pb.zeros(N_ADJ_FIELDS)
     sens = np.zeros(pb.N)
     for n in range(N, -1, -1):
         w = seed / N if n >= 1 else 0.0
         sdp = w if wl.objective == OBJ_PRESSURE_DROP else 0.0
         sh = w if wl.objective == OBJ_HEAT else 0.0
+        ss = w if wl.objective == OBJ_HEAT_EXCHANGE else 0.0
         src = traj[min(n + 1, N)]
-        adj = alks_step(pb, alpha, B, src, traj[n], adj, sdp, sh)
+        adj = alks_step(pb, alpha, B, src, traj[n], adj, sdp, sh, beta, ss)
         if n >= 1 or getattr(wl, "adjoint_mode", "paper") != "exact":
             sens_add(pb, alpha, dalpha, dB, traj[n], adj, 1.0, sens)
+            if beta is not None:
+                source_sens_add(pb, alpha, B, beta, dbeta, traj[n], adj, ss, sens)
     return adj, sens
 
 

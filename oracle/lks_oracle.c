@@ -52,6 +52,9 @@ static const double W[Q9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
 #define TAG_J_OUTLET 32
 #define TAG_PROBE 64
 
+/* objectives */
+#define OBJ_HEAT_EXCHANGE 2
+
 typedef struct {
   int nx, ny;
   int periodic;          /* 1: periodic box, every node interior */
@@ -66,6 +69,7 @@ typedef struct {
   int adj_exact;         /* 1: exact discrete adjoint of the Brinkman step */
   double gbeta[2];       /* g beta of the Boussinesq force eq:boussinesqforce */
   double T_ref;          /* its reference temperature */
+  double beta_max, q_beta; /* heat source eq:heatsource with eq:betagamma */
 } orc_problem;
 
 /* ------------------------------------------------------------------ */
@@ -157,6 +161,25 @@ void orc_coefficients(const orc_problem *P, const double *gamma, double *alpha,
   }
 }
 
+/* eq:betagamma  beta = bbar q (1-g)/(q+g), the coefficient of the heat
+ * source Q = beta (1 - T) (eq:heatsource) that acts in the solid only.
+ * Boundary-ring nodes are non-design: beta = 0, beta' = 0. */
+void orc_source_coefficients(const orc_problem *P, const double *gamma,
+                             double *beta, double *dbeta) {
+  int N = P->nx * P->ny;
+  for (int k = 0; k < N; ++k) {
+    int i = k % P->nx, j = k / P->nx;
+    double g = gamma[k], qb = P->q_beta;
+    if (on_ring(P, i, j)) {
+      beta[k] = 0.0;
+      dbeta[k] = 0.0;
+      continue;
+    }
+    beta[k] = P->beta_max * qb * (1.0 - g) / (qb + g);
+    dbeta[k] = -P->beta_max * qb * (1.0 + qb) / ((qb + g) * (qb + g));
+  }
+}
+
 /* ------------------------------------------------------------------ */
 /* forward LKS step                                                    */
 /* ------------------------------------------------------------------ */
@@ -240,9 +263,13 @@ void orc_init_state(const orc_problem *P, double ufac0, double *drho, double *ux
  *   temperature node: T = Tbar
  * where S0, S+ sum the known f_i with c_i.n = 0 and c_i.n > 0.
  * Corners: u = 0; rho and T copied from the neighbour along y at the new
- * level. */
+ * level.
+ *
+ * Heat source (beta non-NULL): eq:lbeg_ex adds dx w_i Q to g_i (the weight
+ * as in the kinetic equation of Appendix A), Q = beta (1 - T) at the new
+ * level, so its zeroth moment gives T (1 + beta) = T* + beta. */
 void orc_lks_step(const orc_problem *P, const double *alpha, const double *B,
-                  double ufac, const double *drho, const double *ux,
+                  const double *beta, double ufac, const double *drho, const double *ux,
                   const double *uy, const double *T, double *drho_o, double *ux_o,
                   double *uy_o, double *T_o) {
   const int nx = P->nx, ny = P->ny, N = nx * ny;
@@ -287,6 +314,7 @@ void orc_lks_step(const orc_problem *P, const double *alpha, const double *B,
          * G = g beta (T - T_ref) (eq:boussinesqforce) at the new level:
          * u (1 + alpha) = U* + G */
         double Gx = 0.0, Gy = 0.0;
+        if (th && beta) T_s = (T_s + beta[k]) / (1.0 + beta[k]);
         if (th) {
           Gx = P->gbeta[0] * (T_s - P->T_ref);
           Gy = P->gbeta[1] * (T_s - P->T_ref);
@@ -354,6 +382,15 @@ double orc_probe_heat(const orc_problem *P, const double *ux, const double *T) {
   return s;
 }
 
+/* Heat-exchange objective eq:objective_heatexchanger at one level:
+ * J = -sum_nodes beta (1 - T) (dOmega = dx^2 = 1). */
+double orc_source_heat(const orc_problem *P, const double *beta, const double *T) {
+  double s = 0.0;
+  int N = P->nx * P->ny;
+  for (int k = 0; k < N; ++k) s -= beta[k] * (1.0 - T[k]);
+  return s;
+}
+
 /* ------------------------------------------------------------------ */
 /* adjoint: equilibrium coefficients                                   */
 /* ------------------------------------------------------------------ */
@@ -385,11 +422,14 @@ static void adj_V(const orc_problem *P, int i, int j, const double *ux,
 }
 
 /* With alpha given (exact mode), V is divided by 1 + alpha at its node: the
- * transpose of u = U* / (1 + alpha) applied where the velocity was formed. */
+ * transpose of u = U* / (1 + alpha) applied where the velocity was formed.
+ * With beta given as well (heat source), Theta is divided by 1 + beta at its
+ * node in the same way, the transpose of T = (T* + beta) / (1 + beta). */
 void orc_adjoint_equilibrium(const orc_problem *P, const double *B,
                              const double *ux, const double *uy,
                              const double *const *adj, double *Vx, double *Vy,
-                             double *Theta, const double *alpha) {
+                             double *Theta, const double *alpha,
+                             const double *beta) {
   const int nx = P->nx, ny = P->ny;
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j) {
@@ -412,6 +452,7 @@ void orc_adjoint_equilibrium(const orc_problem *P, const double *B,
          * is g beta . V / (1 + alpha) at interior nodes */
         if (alpha && !on_ring(P, i, j))
           Theta[k] += (P->gbeta[0] * V[0] + P->gbeta[1] * V[1]) * sc;
+        if (alpha && beta) Theta[k] /= 1.0 + beta[k];
       }
     }
   }
@@ -572,24 +613,32 @@ static void boundary_fill(const orc_problem *P, uint8_t m, const int n[2],
  *
  * Volume seeds (heat objective, J_O = seed_heat * u_x T on probe nodes, with
  * u_x = sum c_ix f_i and T = sum g_i): dJ_O/df_i = seed_heat T c_ix,
- * dJ_O/dg_i = seed_heat u_x, evaluated at level n.
+ * dJ_O/dg_i = seed_heat u_x, evaluated at level n. Heat-exchange objective
+ * J_O = -seed_src sum beta (1 - T): dJ_O/dg_i = seed_src beta.
+ *
+ * Heat source (beta non-NULL): eq:albeg_ex adds dx dQ/dg_i T~ = -beta T~ to
+ * g~_i at the same level, so T~ is implicit like u~:
+ * T~ (1 + beta) = sum_i w_i (g~*_i + 3 dG/dg_i . u~ - dJ_O/dg_i); q~ is
+ * unchanged (sum_i w_i c_i = 0). In exact mode the division moves to Theta
+ * (orc_adjoint_equilibrium).
  *
  * Ring nodes: the pulled values are known for c_i.n <= 0, the rest come
  * from boundary_fill; alpha = 0 there and the coupling and seeds act on the
  * completed set as in the interior (reading). Corners copy the adjoint
  * moments of their neighbour along y (reading). */
 void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
-                   const double *ux_src, const double *uy_src,
+                   const double *beta, const double *ux_src, const double *uy_src,
                    const double *T_src, const double *ux_dst,
                    const double *uy_dst, const double *T_dst,
                    const double *const *adj_in, double *const *adj_out,
-                   double seed_dp, double seed_heat, double *work) {
+                   double seed_dp, double seed_heat, double seed_src,
+                   double *work) {
   const int nx = P->nx, ny = P->ny, N = nx * ny;
   const double A = coef_A(P);
   const int th = P->thermal;
   double *Vx = work, *Vy = work + N, *Th = work + 2 * N;
   orc_adjoint_equilibrium(P, B, ux_src, uy_src, adj_in, Vx, Vy, th ? Th : NULL,
-                          P->adj_exact ? alpha : NULL);
+                          P->adj_exact ? alpha : NULL, beta);
 
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j) {
@@ -623,6 +672,7 @@ void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
         for (int q = 0; q < Q9; ++q) dJdf[q] = seed_heat * Tn * CX[q];
         dJdg = seed_heat * ux_dst[k];
       }
+      if (beta) dJdg += seed_src * beta[k];
       /* g~ and its moments */
       double Tt = 0, qx = 0, qy = 0;
       if (th) {
@@ -651,6 +701,8 @@ void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
        * 3 g beta . u~ to T~ at interior nodes (sum_i w_i = 1) */
       if (th && !bnd && !P->adj_exact)
         Tt += 3.0 * (P->gbeta[0] * Ux + P->gbeta[1] * Uy) * inv;
+      /* paper: the implicit heat source, T~ = (...) / (1 + beta) */
+      if (th && beta && !P->adj_exact) Tt /= 1.0 + beta[k];
       adj_out[A_R][k] = r;
       adj_out[A_UX][k] = Ux * inv;
       adj_out[A_UY][k] = Uy * inv;
@@ -704,6 +756,35 @@ void orc_sens_add(const orc_problem *P, const double *alpha, const double *dalph
       sens[k] += weight * v;
     }
   }
+}
+
+/* Adds the heat-source part of the sensitivity integrand of Sec. 2.5 at
+ * every design node: dJ_O/dgamma - dx dQ/dgamma T~ with Q = beta (1 - T)
+ * and the heat-exchange objective J_O = -w_J sum beta (1 - T), i.e.
+ *   beta'(gamma) (T - 1) (w_J + T~)
+ * (w_J = 0 for other objectives). In exact mode T~ is replaced by the
+ * propagated Theta of the node (divided by 1 + beta), the adjoint of T*
+ * paired with dT/dbeta = (1 - T) / (1 + beta). */
+void orc_source_sens_add(const orc_problem *P, const double *alpha, const double *B,
+                         const double *beta, const double *dbeta, const double *ux,
+                         const double *uy, const double *T, const double *const *adj,
+                         double wJ, double *sens) {
+  const int nx = P->nx, ny = P->ny, N = nx * ny;
+  double *Th = NULL, *Vx = NULL, *Vy = NULL;
+  if (P->adj_exact) {
+    Th = malloc(3 * (size_t)N * sizeof(double));
+    Vx = Th + N;
+    Vy = Th + 2 * N;
+    orc_adjoint_equilibrium(P, B, ux, uy, adj, Vx, Vy, Th, alpha, beta);
+  }
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      int k = idx(P, i, j);
+      if (on_ring(P, i, j)) continue;
+      double a = P->adj_exact ? Th[k] : adj[A_T][k];
+      sens[k] += dbeta[k] * (T[k] - 1.0) * (wJ + a);
+    }
+  free(Th);
 }
 
 /* Exported so that tests can reach the boundary fill directly. mult

@@ -43,6 +43,7 @@ TAG_PROBE = 1 << 6
 
 OBJ_PRESSURE_DROP = 0
 OBJ_HEAT = 1
+OBJ_HEAT_EXCHANGE = 2
 MODE_STEADY = 0
 MODE_UNSTEADY = 1
 
@@ -75,6 +76,11 @@ class Workload:
     # g beta and T_ref, lattice units; zero means no force
     gbeta: tuple = (0.0, 0.0)
     T_ref: float = 0.0
+    # heat source Q = beta_gamma (1 - T) (eq:heatsource) with
+    # beta_gamma = beta_max q_beta (1 - gamma) / (q_beta + gamma)
+    # (eq:betagamma); beta_max = 0 means no source
+    beta_max: float = 0.0
+    q_beta: float = 0.1
     mask: np.ndarray = field(default=None, repr=False)      # (ny, nx) uint8
     gamma: np.ndarray = field(default=None, repr=False)     # (ny, nx) f64
     ubar: np.ndarray = field(default=None, repr=False)      # (2, ny, nx) f64
@@ -236,6 +242,49 @@ def unsteady_thermal_channel(nx=1024, ny=512, Re=200.0, Pr=6.0, sigma=8.0,
                     n_adj=n_steps, mask=mask, gamma=gamma_grf(nx, ny, sigma, seed),
                     ubar=ubar, Tbar=Tbar,
                     ufac=oscillating_factors(n_steps + 1, amp, period))
+
+
+def heat_exchanger(n=201, Re=100.0, Pr=6.0, beta_max=0.1, q_beta=0.1, sigma=8.0,
+                   seed=0, n_fwd=20000, n_adj=20000, nu=0.1):
+    """Steady forced-convection heat exchanger on an n x n grid: coolant
+    enters at T = 0 through the middle third of the left side with a parabolic
+    profile and leaves through the middle third of the right side; every other
+    boundary node is a no-slip adiabatic wall. The solid generates heat
+    Q = beta_gamma (1 - T) and the objective is the heat-exchange amount
+    J = -sum beta_gamma (1 - T) on the final state (Sec. 3.3 at 201 x 201).
+
+    The inlet spans nodes a..b = round(n/3)..n-1-round(n/3) and L = b - a;
+    u_max = Re nu / L is capped at 0.1 with nu lowered to keep Re (the
+    paper's Re = 100, nu = 0.1, L = 200/3 would put u_max at 0.15). The
+    inlet and outlet nodes also carry the pressure-drop tags, for the
+    pressure-drop constraint of the same problem."""
+    a = int(round(n / 3.0))
+    b = n - 1 - a
+    L = b - a
+    u_max = Re * nu / L
+    if u_max > 0.1:
+        u_max = 0.1
+        nu = u_max * L / Re
+    m = np.zeros((n, n), np.uint8)
+    m[1:-1, 0] = FLOW_VELOCITY | THERM_FLUX
+    m[1:-1, -1] = FLOW_VELOCITY | THERM_FLUX
+    m[0, 1:-1] = FLOW_VELOCITY | THERM_FLUX
+    m[-1, 1:-1] = FLOW_VELOCITY | THERM_FLUX
+    m[a:b + 1, 0] = FLOW_VELOCITY | THERM_DIRICHLET | TAG_J_INLET
+    m[a:b + 1, -1] = FLOW_PRESSURE | THERM_FLUX | TAG_J_OUTLET
+    for j, i in ((0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1)):
+        m[j, i] = FLOW_CORNER
+    ubar = np.zeros((2, n, n))
+    jj = np.arange(a, b + 1, dtype=np.float64)
+    ubar[0, a:b + 1, 0] = u_max * 4.0 * (jj - a) * (b - jj) / float(L * L)
+    Tbar = np.zeros((n, n))
+    return Workload(name=f"heat_exchanger_{n}x{n}_Re{Re:g}_b{beta_max:g}", nx=n, ny=n,
+                    nu=nu, u_max=u_max, alpha_max=1e3 / Re, q_alpha=0.1,
+                    thermal=True, Pr=Pr, Ks_over_Kf=1.0, q_K=0.1,
+                    objective=OBJ_HEAT_EXCHANGE, mode=MODE_STEADY, n_fwd=n_fwd,
+                    n_adj=n_adj, beta_max=beta_max, q_beta=q_beta, mask=m,
+                    gamma=gamma_grf(n, n, sigma, seed), ubar=ubar, Tbar=Tbar,
+                    ufac=np.ones(n_fwd + 1))
 
 
 def batch_designs(n_designs=64, sizes=(128, 192, 256, 384, 512),
