@@ -58,7 +58,11 @@ enum { LKS_D2Q9 = 0, LKS_D3Q19 = 1 };
  * FP32DEV: state in float with the density stored as rho - 1; objective and
  * sensitivity accumulated in double. */
 enum { LKS_FP64 = 0, LKS_FP32DEV = 1 };
-enum { LKS_OBJ_PRESSURE_DROP = 0, LKS_OBJ_HEAT = 1 };
+/* objectives: static pressure drop (eq:objective_pipebend); time-averaged
+ * enthalpy flux u_x T through the probe nodes; heat-exchange amount
+ * J = -sum beta_gamma (1 - T) over all nodes (eq:objective_heatexchanger;
+ * needs the heat source, beta_max > 0) */
+enum { LKS_OBJ_PRESSURE_DROP = 0, LKS_OBJ_HEAT = 1, LKS_OBJ_HEAT_EXCHANGE = 2 };
 enum { LKS_STEADY = 0, LKS_UNSTEADY = 1 };
 enum { LKS_ADJ_PAPER = 0, LKS_ADJ_EXACT = 1 };
 
@@ -128,6 +132,11 @@ typedef struct {
                          force. Non-zero needs a thermal D2Q9 problem (D3Q19:
                          LKS_E_UNSUPPORTED); the third component is unused */
   double T_ref;       /* reference temperature of the Boussinesq force */
+  double beta_max;    /* beta-bar of the heat source Q = beta_gamma (1 - T)
+                         (eq:heatsource, eq:betagamma) that heats the solid;
+                         0: no source. Positive needs a thermal D2Q9 problem
+                         (D3Q19: LKS_E_UNSUPPORTED) */
+  double q_beta;      /* q_beta of eq:betagamma (> 0 when beta_max > 0) */
 } lks_phys;
 
 typedef struct {

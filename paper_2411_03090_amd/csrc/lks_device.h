@@ -102,6 +102,7 @@ struct FwdArgs {
   R* T1;
   double* acc;  // per-tile objective accumulator, or nullptr
   int objective;
+  const R* beta = nullptr;  // heat-source coefficient beta_gamma, or nullptr
 };
 
 template <typename R>
@@ -128,6 +129,9 @@ struct AdjArgs {
   int exact;     // 1: exact discrete adjoint of the Brinkman step
   double seed_dp;
   double seed_heat;
+  const R* beta = nullptr;   // heat-source coefficient beta_gamma, or nullptr
+  const R* dbeta = nullptr;  // beta'(gamma)
+  double seed_src = 0.0;     // weight of the heat-exchange objective
 };
 
 // one design of a batch: geometry and the arguments of both ping-pong parities
@@ -249,6 +253,10 @@ template <typename R>
 void launch_coef(const Geo& g, const double* gamma, double alpha_max, double q_alpha,
                  double Kf, double Ks, double q_K, R* inv1pa, R* B, R* dA3, R* dB,
                  hipStream_t s);
+// heat-source coefficients beta_gamma and beta'(gamma) (eq:betagamma)
+template <typename R>
+void launch_source_coef(const Geo& g, const double* gamma, double beta_max, double q_beta,
+                        R* beta, R* dbeta, hipStream_t s);
 template <typename R>
 void launch_init(const Geo& g, const uint8_t* mask, const R* ubx, const R* uby, const R* Tb,
                  double fac0, R* d, R* ux, R* uy, R* T, hipStream_t s);
@@ -266,6 +274,9 @@ void launch_pressure_drop(const Geo& g, const uint8_t* mask, const R* d, double*
 template <typename R>
 void launch_probe_heat(const Geo& g, const uint8_t* mask, const R* ux, const R* T, double* out,
                        hipStream_t s);
+// heat-exchange objective of one level: sum of beta (T - 1) over all nodes
+template <typename R>
+void launch_source_heat(const Geo& g, const R* beta, const R* T, double* out, hipStream_t s);
 template <typename R>
 void launch_lks_step_batch(const BatchFwd<R>* d, const int* tile0, int nd, int total, int ty,
                            bool thermal, int parity, hipStream_t s);

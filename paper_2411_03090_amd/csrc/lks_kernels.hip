@@ -76,6 +76,25 @@ __global__ void coef_kernel(Geo g, const double* __restrict__ gamma, double amax
   dB[k] = R(-3.0 * dK);
 }
 
+// heat source (eq:heatsource, eq:betagamma): beta = bmax q (1 - g) / (q + g)
+// and beta' at design nodes, 0 on the ring
+template <typename R>
+__global__ void source_coef_kernel(Geo g, const double* __restrict__ gamma, double bmax,
+                                   double qb, R* __restrict__ beta, R* __restrict__ dbeta) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.N) return;
+  int i = k % g.nx, j = k / g.nx;
+  bool ring = !g.periodic && (i == 0 || j == 0 || i == g.nx - 1 || j == g.ny - 1);
+  if (ring) {
+    beta[k] = R(0);
+    dbeta[k] = R(0);
+    return;
+  }
+  double ga = gamma[k];
+  beta[k] = R(bmax * qb * (1.0 - ga) / (qb + ga));
+  dbeta[k] = R(-bmax * qb * (1.0 + qb) / ((qb + ga) * (qb + ga)));
+}
+
 // ---------------------------------------------------------------------------
 // level-0 state
 // ---------------------------------------------------------------------------
@@ -354,6 +373,12 @@ __device__ inline void fwd_pull(const Geo& g, const FwdArgs<R>& a, const R* lf, 
     R Uy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
     if constexpr (TH) {
       Tn = gg[0] + gg[1] + gg[2] + gg[3] + gg[4] + gg[5] + gg[6] + gg[7] + gg[8];
+      // heat source Q = beta (1 - T) at the new level (eq:lbeg_ex,
+      // eq:heatsource): T (1 + beta) = T* + beta
+      if (a.beta) {
+        const R b = a.beta[k];
+        Tn = (Tn + b) / (R(1) + b);
+      }
       // Boussinesq force at the new level, u (1 + alpha) = U* + G
       // (eq:lbef_ex, eq:boussinesqforce); zero when g beta is zero
       const R dT = Tn - R(g.Tref);
@@ -492,6 +517,8 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
     if (a.acc) {
       if (a.objective == 1) {
         if (m & TAG_PROBE) part += double(uxn) * double(Tn);
+      } else if (a.objective == 2) {
+        if constexpr (TH) part += double(a.beta[k]) * (double(Tn) - 1.0);
       } else {
         if (m & TAG_J_INLET) part += double(dn);
         if (m & TAG_J_OUTLET) part -= double(dn);
@@ -767,6 +794,17 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
   // interior nodes (zero when g beta is zero)
   if constexpr (TH)
     if (!ring && !a.exact) Tt += R(3) * (R(g.gbx) * utx + R(g.gby) * uty);
+  // heat source (interior nodes; beta = 0 on the ring): the heat-exchange
+  // seed dJ/dg_i = seed_src beta, and in paper mode the implicit
+  // T~ (1 + beta) of eq:albeg_ex
+  R bsrc = R(0);
+  if constexpr (TH) {
+    if (a.beta && !ring) {
+      bsrc = a.beta[k];
+      Tt -= R(a.seed_src) * bsrc;
+      if (!a.exact) Tt /= R(1) + bsrc;
+    }
+  }
   auto ldx = [&](int f) { return lds_dx<INT>(lm + f * SM, pm, 1, i, g.nx, g.periodic); };
   auto ldy = [&](int f) { return lds_dx<INT>(lm + f * SM, pm, PM, j, g.ny, g.periodic); };
   const R dsx = ldx(3) + ldy(4);
@@ -791,6 +829,8 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
     // exact: the propagated Theta carries the force's dependence on the new
     // temperature, g beta . V / (1 + alpha), at interior nodes
     if (!ring && a.exact) Th += R(g.gbx) * Vx + R(g.gby) * Vy;
+    // exact: the division by 1 + beta acts on the propagated Theta
+    if (a.exact && a.beta) Th /= R(1) + bsrc;
   }
   sens = 0.0;
   if (want_sens) {
@@ -801,6 +841,11 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
         const double dTx = double(lds_dx<INT>(lTn, pr, 1, i, g.nx, g.periodic));
         const double dTy = double(lds_dx<INT>(lTn, pr, PR, j, g.ny, g.periodic));
         v -= double(a.dB[k]) * (dTx * double(qx) + dTy * double(qy));
+        // heat source and heat-exchange objective: beta' (T - 1)(w_J + T~),
+        // with the propagated Theta in exact mode
+        if (a.beta)
+          v += double(a.dbeta[k]) * (double(lTn[pr]) - 1.0) *
+               (a.seed_src + double(a.exact ? Th : Tt));
       }
     }
     sens = v;
@@ -1302,6 +1347,19 @@ __global__ __launch_bounds__(NTHREADS) void probe_heat_kernel(Geo g, const uint8
   if (threadIdx.x == 0) *out = s;
 }
 
+// sum of beta (T - 1) over all nodes: the heat-exchange objective
+// -sum beta (1 - T) of one level
+template <typename R>
+__global__ __launch_bounds__(NTHREADS) void source_heat_kernel(Geo g, const R* beta, const R* T,
+                                                              double* out) {
+  __shared__ double red[NTHREADS / 64];
+  double part = 0.0;
+  for (int k = threadIdx.x; k < g.N; k += NTHREADS)
+    part += double(beta[k]) * (double(T[k]) - 1.0);
+  double s = block_sum(part, red);
+  if (threadIdx.x == 0) *out = s;
+}
+
 __global__ __launch_bounds__(NTHREADS) void sum_kernel(const double* v, int n, double* out) {
   __shared__ double red[NTHREADS / 64];
   double part = 0.0;
@@ -1345,6 +1403,11 @@ void launch_coef(const Geo& g, const double* gamma, double amax, double qa, doub
                  double Ks, double qk, R* inv1pa, R* B, R* dA3, R* dB, hipStream_t s) {
   coef_kernel<R><<<blocks_for(g.N), 256, 0, s>>>(g, gamma, amax, qa, Kf, Ks, qk, inv1pa, B, dA3,
                                                  dB);
+}
+template <typename R>
+void launch_source_coef(const Geo& g, const double* gamma, double bmax, double qb, R* beta,
+                        R* dbeta, hipStream_t s) {
+  source_coef_kernel<R><<<blocks_for(g.N), 256, 0, s>>>(g, gamma, bmax, qb, beta, dbeta);
 }
 template <typename R>
 void launch_init(const Geo& g, const uint8_t* mask, const R* ubx, const R* uby, const R* Tb,
@@ -1405,6 +1468,10 @@ template <typename R>
 void launch_probe_heat(const Geo& g, const uint8_t* mask, const R* ux, const R* T, double* out,
                        hipStream_t s) {
   probe_heat_kernel<R><<<1, NTHREADS, 0, s>>>(g, mask, ux, T, out);
+}
+template <typename R>
+void launch_source_heat(const Geo& g, const R* beta, const R* T, double* out, hipStream_t s) {
+  source_heat_kernel<R><<<1, NTHREADS, 0, s>>>(g, beta, T, out);
 }
 template <typename R>
 void launch_lks_step_batch(const BatchFwd<R>* d, const int* tile0, int nd, int total, int ty,
@@ -1482,6 +1549,9 @@ void launch_finite_check(const R* a, size_t n, int* flag, hipStream_t s) {
                                         hipStream_t);                                         \
   template void launch_probe_heat<R>(const Geo&, const uint8_t*, const R*, const R*, double*,  \
                                      hipStream_t);                                            \
+  template void launch_source_coef<R>(const Geo&, const double*, double, double, R*, R*,      \
+                                      hipStream_t);                                           \
+  template void launch_source_heat<R>(const Geo&, const R*, const R*, double*, hipStream_t);  \
   template void launch_fill_r<R>(R*, size_t, hipStream_t);                                    \
   template void launch_lks_step_batch<R>(const BatchFwd<R>*, const int*, int, int, int, bool, int, \
                                          hipStream_t);                                        \

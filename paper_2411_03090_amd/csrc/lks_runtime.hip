@@ -61,6 +61,7 @@ struct lks_ctx {
   void *ubx = nullptr, *uby = nullptr, *ubz = nullptr, *Tb = nullptr;
   double* d_ufac = nullptr;
   void *inv1pa = nullptr, *B = nullptr, *dA3 = nullptr, *dB = nullptr;
+  void *beta = nullptr, *dbeta = nullptr;  // heat source (beta_max > 0)
   // forward ping-pong: drho, ux, uy, T (D2Q9) or drho, ux, uy, uz, T (D3Q19)
   void* S[2][5] = {};
   // adjoint ping-pong: rho~, Vx, Vy, Theta or rho~, Vx, Vy, Vz, Theta
@@ -146,6 +147,8 @@ size_t traj_bytes(const lks_ctx* c, int K) {
   return n_ckpt * ckpt_fields(c) * N * r + size_t(K - 1) * slot_fields(c) * N * r;
 }
 
+bool has_source(const lks_ctx* c) { return c->phys.beta_max > 0.0; }
+
 size_t base_bytes(const lks_ctx* c) {
   const size_t N = size_t(c->N), r = size_t(c->rsz);
   const int nf = nfields(c);
@@ -153,7 +156,7 @@ size_t base_bytes(const lks_ctx* c) {
   b += align256(N);                          // mask
   b += size_t(c->dim + 1) * align256(N * r);  // prescribed velocity, T
   b += align256(sizeof(double) * c->ufac.size());
-  b += 4 * align256(N * r);                  // coefficients
+  b += (has_source(c) ? 6 : 4) * align256(N * r);  // coefficients
   b += 2 * nf * align256(N * r);             // forward ping-pong
   b += 2 * nf * align256(N * r);             // adjoint ping-pong
   b += align256(sizeof(double) * acc_capacity(c));
@@ -233,8 +236,20 @@ lks_status validate_common(const lks_grid* gr, const lks_phys* ph, const lks_bc*
     return fail(nullptr, LKS_E_INVALID, "the Boussinesq force needs a thermal problem");
   if (force && gr->lattice == LKS_D3Q19)
     return fail(nullptr, LKS_E_UNSUPPORTED, "the Boussinesq force is D2Q9 only");
-  if (bc->objective != LKS_OBJ_PRESSURE_DROP && bc->objective != LKS_OBJ_HEAT)
+  if (!std::isfinite(ph->beta_max) || !(ph->beta_max >= 0.0))
+    return fail(nullptr, LKS_E_INVALID, "beta_max must be finite and >= 0");
+  const bool source = ph->beta_max > 0.0;
+  if (source && !(ph->q_beta > 0.0 && std::isfinite(ph->q_beta)))
+    return fail(nullptr, LKS_E_INVALID, "the heat source needs q_beta > 0");
+  if (source && !ph->thermal)
+    return fail(nullptr, LKS_E_INVALID, "the heat source needs a thermal problem");
+  if (source && gr->lattice == LKS_D3Q19)
+    return fail(nullptr, LKS_E_UNSUPPORTED, "the heat source is D2Q9 only");
+  if (bc->objective != LKS_OBJ_PRESSURE_DROP && bc->objective != LKS_OBJ_HEAT &&
+      bc->objective != LKS_OBJ_HEAT_EXCHANGE)
     return fail(nullptr, LKS_E_INVALID, "unknown objective");
+  if (bc->objective == LKS_OBJ_HEAT_EXCHANGE && !source)
+    return fail(nullptr, LKS_E_INVALID, "the heat-exchange objective needs the heat source");
   if (bc->objective == LKS_OBJ_HEAT && !ph->thermal)
     return fail(nullptr, LKS_E_INVALID, "heat objective needs a thermal problem");
   if (bc->mode != LKS_STEADY && bc->mode != LKS_UNSTEADY)
@@ -441,6 +456,7 @@ struct Run {
     a.T1 = out[3];
     a.acc = acc;
     a.objective = c->objective;
+    a.beta = rp<R>(c->beta);
     return a;
   }
 
@@ -462,6 +478,9 @@ struct Run {
     else
       lks::launch_coef<R>(g, gamma, c->phys.alpha_max, c->phys.q_alpha, Kf, Ks, qK,
                           rp<R>(c->inv1pa), rp<R>(c->B), rp<R>(c->dA3), rp<R>(c->dB), c->stream);
+    if (has_source(c))
+      lks::launch_source_coef<R>(g, gamma, c->phys.beta_max, c->phys.q_beta, rp<R>(c->beta),
+                                 rp<R>(c->dbeta), c->stream);
   }
 
   void init(R* const s[5]) {
@@ -535,6 +554,8 @@ struct Run {
                                 LKS_OBJ_PRESSURE_DROP, c->acc, c->scal, c->stream);
       else
         lks::launch_pressure_drop<R>(g, c->d_mask, cur_field(0), c->scal, c->stream);
+    } else if (c->objective == LKS_OBJ_HEAT_EXCHANGE) {
+      lks::launch_source_heat<R>(g, rp<R>(c->beta), cur_field(3), c->scal, c->stream);
     } else {
       probe_heat_steady();
     }
@@ -553,7 +574,7 @@ struct Run {
   }
 
   // one ALKS step with the state st (drho, u..., T) of the destination level
-  void adj_step(R* const st[5], double sdp, double sh, double* sens, int mode) {
+  void adj_step(R* const st[5], double sdp, double sh, double* sens, int mode, double ss = 0.0) {
     const int i0 = c->acur, i1 = c->acur ^ 1;
     if (c->dim == 3) {
       lks::Adj3Args<R> a;
@@ -581,7 +602,9 @@ struct Run {
       c->acur = i1;
       return;
     }
-    lks::launch_alks_step<R>(g, adj_args(st, sdp, sh, sens, mode), c->stream);
+    lks::AdjArgs<R> a = adj_args(st, sdp, sh, sens, mode);
+    a.seed_src = ss;
+    lks::launch_alks_step<R>(g, a, c->stream);
     c->acur = i1;
   }
 
@@ -610,6 +633,8 @@ struct Run {
     a.seed_dp = sdp;
     a.seed_heat = sh;
     a.ops = c->d_ops;
+    a.beta = rp<R>(c->beta);
+    a.dbeta = rp<R>(c->dbeta);
     return a;
   }
 
@@ -620,6 +645,7 @@ struct Run {
     }
     const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? seed : 0.0;
     const double sh = c->objective == LKS_OBJ_HEAT ? seed : 0.0;
+    const double ss = c->objective == LKS_OBJ_HEAT_EXCHANGE ? seed : 0.0;
     R* st[5] = {};
     for (int f = 0; f < nf; ++f) st[f] = cur_field(f);
     if (!c->phys.thermal) st[nf - 1] = nullptr;
@@ -636,7 +662,7 @@ struct Run {
     }
     for (; n < steps; ++n) {
       const bool last = n == steps - 1;
-      adj_step(st, sdp, sh, last ? dJ : nullptr, 2);
+      adj_step(st, sdp, sh, last ? dJ : nullptr, 2, ss);
     }
   }
 
@@ -663,9 +689,10 @@ struct Run {
         const double w = n >= 1 ? seed / Nst : 0.0;
         const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? w : 0.0;
         const double sh = c->objective == LKS_OBJ_HEAT ? w : 0.0;
+        const double ss = c->objective == LKS_OBJ_HEAT_EXCHANGE ? w : 0.0;
         // the exact mode sums the levels the steps produce; level 0 is the
         // initial state, which does not depend on gamma
-        adj_step(lv, sdp, sh, (n == 0 && c->adj_exact) ? nullptr : dJ, 1);
+        adj_step(lv, sdp, sh, (n == 0 && c->adj_exact) ? nullptr : dJ, 1, ss);
       }
     }
   }
@@ -842,6 +869,10 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
   c->B = take(N * r);
   c->dA3 = take(N * r);
   c->dB = take(N * r);
+  if (has_source(c)) {
+    c->beta = take(N * r);
+    c->dbeta = take(N * r);
+  }
   for (int s = 0; s < 2; ++s)
     for (int f = 0; f < 5; ++f) c->S[s][f] = f < nf ? take(N * r) : nullptr;
   for (int s = 0; s < 2; ++s)

@@ -41,7 +41,7 @@ LKS_E_DIVERGED = 5
 LKS_E_UNSUPPORTED = 6
 LKS_D2Q9, LKS_D3Q19 = 0, 1
 LKS_FP64, LKS_FP32DEV = 0, 1
-LKS_OBJ_PRESSURE_DROP, LKS_OBJ_HEAT = 0, 1
+LKS_OBJ_PRESSURE_DROP, LKS_OBJ_HEAT, LKS_OBJ_HEAT_EXCHANGE = 0, 1, 2
 LKS_STEADY, LKS_UNSTEADY = 0, 1
 LKS_ADJ_PAPER, LKS_ADJ_EXACT = 0, 1
 FIELDS = {"drho": 0, "ux": 1, "uy": 2, "T": 3,
@@ -69,7 +69,8 @@ class Phys(ctypes.Structure):
                 ("alpha_max", ctypes.c_double), ("q_alpha", ctypes.c_double),
                 ("Ks_over_Kf", ctypes.c_double), ("q_K", ctypes.c_double),
                 ("thermal", ctypes.c_int), ("gbeta", ctypes.c_double * 3),
-                ("T_ref", ctypes.c_double)]
+                ("T_ref", ctypes.c_double), ("beta_max", ctypes.c_double),
+                ("q_beta", ctypes.c_double)]
 
 
 class BC(ctypes.Structure):
@@ -193,7 +194,9 @@ class LKS:
         gb = [float(v) for v in getattr(wl, "gbeta", (0.0, 0.0))] + [0.0, 0.0]
         self.phys = Phys(wl.nu, wl.Pr, wl.alpha_max, wl.q_alpha, wl.Ks_over_Kf, wl.q_K,
                          int(wl.thermal), (ctypes.c_double * 3)(*gb[:3]),
-                         float(getattr(wl, "T_ref", 0.0)))
+                         float(getattr(wl, "T_ref", 0.0)),
+                         float(getattr(wl, "beta_max", 0.0)),
+                         float(getattr(wl, "q_beta", 0.1)))
         self.bc = BC(self._mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                      _dptr(self._ubar), _dptr(self._Tbar), _dptr(self._ufac),
                      len(self._ufac), wl.rho_out, wl.objective, wl.mode,

@@ -102,6 +102,35 @@ def test_boussinesq_force_needs_a_thermal_d2q9_problem():
     _create(wt)
 
 
+def test_heat_source_validation_and_workspace():
+    wl = W.steady_channel_uniform(16, 12, Re=10, seed=0)
+    wl.beta_max = 0.1
+    with pytest.raises(lks.LKSError) as e:          # needs a thermal problem
+        _create(wl)
+    assert e.value.status == lks.LKS_E_INVALID
+    wx = W.heat_exchanger(n=16, Re=10.0, n_fwd=10, n_adj=10)
+    base = _create(wx).workspace_size()
+    for field, value in (("beta_max", -0.1), ("beta_max", float("nan")), ("q_beta", 0.0)):
+        w = W.heat_exchanger(n=16, Re=10.0, n_fwd=10, n_adj=10)
+        setattr(w, field, value)
+        with pytest.raises(lks.LKSError) as e:
+            _create(w)
+        assert e.value.status == lks.LKS_E_INVALID, field
+    w = W.heat_exchanger(n=16, Re=10.0, n_fwd=10, n_adj=10)
+    w.beta_max = 0.0                                  # objective without a source
+    with pytest.raises(lks.LKSError) as e:
+        _create(w)
+    assert e.value.status == lks.LKS_E_INVALID
+    w.objective = W.OBJ_PRESSURE_DROP
+    # the source adds beta and beta' (two arrays of N doubles)
+    assert base - _create(w).workspace_size() == 2 * 16 * 16 * 8
+    wl3 = W.heated_block_duct(16, 8, 8, Re=20.0, n_steps=10)
+    wl3.beta_max = 0.1
+    with pytest.raises(lks.LKSError) as e:
+        _create(wl3)
+    assert e.value.status == lks.LKS_E_UNSUPPORTED
+
+
 def test_adjoint_mode_setter_validates():
     c = _create(W.steady_channel_uniform(16, 12, Re=10, seed=0))
     c.set_adjoint_mode("exact")
