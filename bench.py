@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--batch-steps", type=int, default=2000)
     p.add_argument("--no-unsteady", action="store_true")
     p.add_argument("--unsteady-steps", type=int, default=20000)
+    p.add_argument("--no-exchanger", action="store_true")
+    p.add_argument("--exchanger-steps", type=int, default=20000)
     p.add_argument("--no-3d", action="store_true")
     p.add_argument("--steps-3d", type=int, default=5000)
     p.add_argument("--copy-calibration", action="store_true",
@@ -125,6 +127,7 @@ def main():
     roofline = alks_roofline(c32, g, wl, nodes, shape32)
     batched = None if args.no_batch else batched_bench(args, dev)
     unsteady = None if args.no_unsteady else unsteady_bench(args, dev)
+    exchanger = None if args.no_exchanger else exchanger_bench(args, dev)
     duct = None if args.no_3d else duct3d_bench(args, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_sample_steps)
 
@@ -157,6 +160,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_64_designs": batched,
         "unsteady_thermal_1024x512": unsteady,
+        "heat_exchanger_201x201": exchanger,
         "duct3d_256x128x128": duct,
     }
     print(json.dumps(line), flush=True)
@@ -295,6 +299,41 @@ def unsteady_bench(args, dev):
     res = _checkpointed(c32, c64, g, wl.nx * wl.ny, n)
     res.update({"nodes": wl.nx * wl.ny, "steps": n, "budget_GiB": {"fp32": 4, "fp64": 8}})
     del c32, c64
+    torch.cuda.empty_cache()
+    return res
+
+
+def exchanger_bench(args, dev):
+    """Steady heat exchanger 201x201 (Re = 100, Pr = 6, heat source with
+    beta_max = 0.1 in the solid, heat-exchange objective), n + n steps, one
+    gradient in FP32 and in FP64."""
+    import torch
+    from paper_2411_03090_amd import lks, workloads as W
+    n = args.exchanger_steps
+    wl = W.heat_exchanger(n=201, n_fwd=n, n_adj=n)
+    g = torch.tensor(wl.gamma.reshape(-1), dtype=torch.float64, device=dev)
+    nodes = wl.nx * wl.ny
+    res, outs = {}, {}
+    for prec in ("fp32", "fp64"):
+        c = lks.LKS(wl, precision=prec, device=dev)
+        out = torch.empty_like(g)
+        c.forward(g, 200)                                   # warm-up
+        torch.cuda.synchronize()
+        e0 = ev()
+        c.forward(g, n)
+        J = c.objective()
+        c.backward(1.0, out, n)
+        e1 = ev()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[prec] = {"ms_per_gradient": ms, "mlups": nodes * 2 * n / (ms * 1e-3) / 1e6,
+                     "gradients_per_s": 1e3 / ms, "J": J}
+        outs[prec] = out.cpu().numpy()
+        del c
+    J64 = res["fp64"]["J"]
+    res["fp32_vs_fp64_rel_error"] = {"J": abs(res["fp32"]["J"] - J64) / abs(J64),
+                                     "dJdgamma_l2": rel(outs["fp32"], outs["fp64"])}
+    res.update({"nodes": nodes, "n_fwd": n, "n_adj": n, "beta_max": wl.beta_max})
     torch.cuda.empty_cache()
     return res
 
