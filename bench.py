@@ -281,7 +281,7 @@ def _checkpointed(ctx_fp32, ctx_fp64, g, nodes, n):
     res["fp32_vs_fp64_rel_error"] = {
         "J": abs(res["fp32"]["J"] - J64) / abs(J64) if J64 else None,
         "dJdgamma_l2": rel(outs["fp32"], outs["fp64"]) if np.any(outs["fp64"]) else None}
-    return res
+    return res, outs["fp32"]
 
 
 def unsteady_bench(args, dev):
@@ -296,7 +296,7 @@ def unsteady_bench(args, dev):
     g = torch.tensor(wl.gamma.reshape(-1), dtype=torch.float64, device=dev)
     c32 = lks.LKS(wl, precision="fp32", mem_budget=4 * 2 ** 30, device=dev)
     c64 = lks.LKS(wl, precision="fp64", mem_budget=8 * 2 ** 30, device=dev)
-    res = _checkpointed(c32, c64, g, wl.nx * wl.ny, n)
+    res, _ = _checkpointed(c32, c64, g, wl.nx * wl.ny, n)
     res.update({"nodes": wl.nx * wl.ny, "steps": n, "budget_GiB": {"fp32": 4, "fp64": 8}})
     del c32, c64
     torch.cuda.empty_cache()
@@ -350,9 +350,32 @@ def duct3d_bench(args, dev):
     c32 = lks.LKS(wl, precision="fp32", mem_budget=16 * 2 ** 30, device=dev)
     c64 = lks.LKS(wl, precision="fp64", mem_budget=32 * 2 ** 30, device=dev)
     nodes = wl.nx * wl.ny * wl.nz
-    res = _checkpointed(c32, c64, g, nodes, n)
+    res, grad16 = _checkpointed(c32, c64, g, nodes, n)
     res.update({"nodes": nodes, "steps": n, "budget_GiB": {"fp32": 16, "fp64": 32}})
     del c32, c64
+    torch.cuda.empty_cache()
+    # the same gradient in 4 GiB: two-level checkpoints do not fit, binomial
+    # snapshots recompute more forward steps
+    cb = lks.LKS(wl, precision="fp32", mem_budget=4 * 2 ** 30, device=dev)
+    out = torch.empty_like(g)
+    torch.cuda.synchronize()
+    e0 = ev()
+    cb.forward(g)
+    cb.objective()
+    e1 = ev()
+    cb.backward(1.0, out)
+    e2 = ev()
+    torch.cuda.synchronize()
+    info = cb.checkpoint_info()
+    ms = e0.elapsed_time(e2)
+    res["fp32_4GiB"] = {"ms_per_gradient": ms, "mlups": nodes * 2 * n / (ms * 1e-3) / 1e6,
+                        "forward_ms": e0.elapsed_time(e1), "backward_ms": e1.elapsed_time(e2),
+                        "scheme": info["scheme"], "snapshots": info["count"],
+                        "replay_steps": info["replay_steps"],
+                        "workspace_GiB": cb.workspace_size() / 2 ** 30,
+                        "dJdgamma_bitwise_equal_to_16GiB_run":
+                            bool((out.cpu().numpy() == grad16).all())}
+    del cb
     torch.cuda.empty_cache()
     return res
 

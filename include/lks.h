@@ -65,6 +65,8 @@ enum { LKS_FP64 = 0, LKS_FP32DEV = 1 };
 enum { LKS_OBJ_PRESSURE_DROP = 0, LKS_OBJ_HEAT = 1, LKS_OBJ_HEAT_EXCHANGE = 2 };
 enum { LKS_STEADY = 0, LKS_UNSTEADY = 1 };
 enum { LKS_ADJ_PAPER = 0, LKS_ADJ_EXACT = 1 };
+/* checkpointing of unsteady sweeps (see lks_set_checkpointing) */
+enum { LKS_CKPT_AUTO = 0, LKS_CKPT_TWO_LEVEL = 1, LKS_CKPT_BINOMIAL = 2 };
 
 /* Node-class byte (one per node):
  *   bits 0-1 flow class: interior (design) node, prescribed velocity
@@ -266,6 +268,33 @@ lks_status lks_launch_shape(const lks_ctx *ctx, int *tile_rows, int *forward_ste
  * is stored; 0 for steady problems). */
 lks_status lks_memory_report(const lks_ctx *ctx, size_t *ckpt_bytes, size_t *state_bytes,
                              int *K);
+
+/* Checkpointing of an unsteady context (the paper keeps every level of the
+ * trajectory, Sec. 3.2 and 3.4; this library trades memory for recomputed
+ * forward steps). Call before lks_bind_workspace; it re-plans the workspace
+ * (query lks_workspace_size again).
+ *   LKS_CKPT_TWO_LEVEL: checkpoints of the whole state every K levels and one
+ *     replay segment of K-1 levels, K the largest that fits the budget; the
+ *     adjoint recomputes at most one forward sweep.
+ *   LKS_CKPT_BINOMIAL: `slots` snapshots of the whole state besides level 0
+ *     (0: as many as the budget holds) placed by Griewank's binomial
+ *     reversal schedule, which recomputes the fewest forward steps possible
+ *     for that many snapshots; for budgets where two-level does not fit.
+ *   LKS_CKPT_AUTO (the default at lks_create): two-level when it fits the
+ *     budget, binomial otherwise.
+ * Results are bitwise the same under every scheme. Errors: LKS_E_STATE after
+ * binding, LKS_E_UNSUPPORTED for steady contexts, LKS_E_INVALID for an
+ * unknown scheme or slots < 0 (slots > 0 needs LKS_CKPT_BINOMIAL),
+ * LKS_E_NOMEM when the plan exceeds the budget of lks_create (the previous
+ * plan is kept). */
+lks_status lks_set_checkpointing(lks_ctx *ctx, int scheme, int slots);
+
+/* The plan of an unsteady context: scheme (LKS_CKPT_TWO_LEVEL or
+ * LKS_CKPT_BINOMIAL), count (the interval K, or the number of snapshots
+ * including level 0) and the LKS steps one adjoint sweep recomputes. Steady
+ * contexts report zeros. */
+lks_status lks_checkpoint_info(const lks_ctx *ctx, int *scheme, int *count,
+                               long long *replay_steps);
 
 /* ---- batches (Sec. 2.7 Steps 2-5 for many independent designs) ----------
  * A batch holds n steady pressure-drop problems of possibly different sizes

@@ -5,6 +5,7 @@
 // problems -- checkpoints every K levels plus one replay segment), and drives
 // the forward sweep, the adjoint sweep and the checkpoint replay on one HIP
 // stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -23,13 +24,27 @@ thread_local std::string g_create_error;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// One action of a binomial reversal schedule: advance `steps` LKS steps from
+// the level `from` held in snapshot `src` (the last step writes snapshot
+// `dst`, or the working buffers when dst < 0), or run the ALKS step of level
+// `from` with its state in snapshot `src` (src < 0: the working buffers).
+struct Act {
+  int adjoint;
+  int from, steps, src, dst;
+};
+
 struct Plan {
-  int K = 0;          // checkpoint interval (N+1: whole trajectory kept)
-  int n_ckpt = 0;     // checkpoints at levels 0, K, 2K, ..., ls
+  int scheme = 0;     // LKS_CKPT_TWO_LEVEL or LKS_CKPT_BINOMIAL (unsteady)
+  int K = 0;          // two-level: checkpoint interval (N+1: whole trajectory kept)
+  int n_ckpt = 0;     // two-level: checkpoints at levels 0, K, 2K, ..., ls;
+                      // binomial: snapshots (level 0 and s free slots)
   int n_slots = 0;    // replay segment slots (K-1)
   int ls = 0;         // level of the last checkpoint
+  long long replay = 0;  // LKS steps the adjoint sweep recomputes
   size_t ckpt_bytes = 0;
   size_t total = 0;
+  std::vector<Act> acts;  // binomial: forward placements, then the reversal
+  int n_pre = 0;          // binomial: leading actions done by the forward pass
 };
 
 }  // namespace
@@ -82,6 +97,9 @@ struct lks_ctx {
   bool have_forward = false;
   bool have_adjoint = false;
   int adj_exact = 0;     // LKS_ADJ_EXACT: transpose of the discrete Brinkman step
+  int ckpt_scheme = 0;   // requested checkpointing (LKS_CKPT_*)
+  int ckpt_slots = 0;    // binomial: requested free snapshot slots (0: budget)
+  void* lastv[5] = {};   // binomial: where the last forward level is held
   int cur = 0;      // steady forward: ping-pong index of the current level
   int acur = 0;     // adjoint: ping-pong index of the current level
   int last_level = 0;
@@ -172,8 +190,119 @@ size_t base_bytes(const lks_ctx* c) {
   return b;
 }
 
-// Largest checkpoint interval whose storage fits the budget: the fewest
-// replayed steps for the memory given. K = N+1 keeps every level.
+// ---- binomial checkpointing (Griewank's reversal schedule) ----------------
+// beta(c, r) = C(c + r, c): the most levels that c snapshots can reverse when
+// no step is evaluated more than r times (saturates at 2^62).
+long long beta_cr(int c, int r) {
+  if (r < 0 || c < 0) return 0;
+  long long b = 1;
+  const int k = std::min(c, r);
+  for (int i = 1; i <= k; ++i) {
+    const long long num = (long long)(c + r - k + i);
+    if (b > (1LL << 62) / num) return 1LL << 62;
+    b = b * num / i;
+  }
+  return b;
+}
+
+// Steps to advance before the next snapshot when levels a..a+t are to be
+// reversed with the level a in a snapshot and s free slots: with l = t + 1
+// levels, c = s + 1 snapshots and r the least repetition count with
+// beta(c, r) >= l, k = min(t - beta(c - 1, r - 1) + 1, beta(c, r - 1)),
+// which attains the least number of recomputed steps.
+int binomial_split(int t, int s) {
+  const long long l = (long long)t + 1;
+  const int c = s + 1;
+  int r = 0;
+  while (beta_cr(c, r) < l) ++r;
+  long long k = std::min((long long)t - beta_cr(c - 1, r - 1) + 1, beta_cr(c, r - 1));
+  return int(std::max(1LL, std::min((long long)t, k)));
+}
+
+// Appends the reversal of levels a..b (level a in snapshot sa; `free_` lists
+// the free snapshots, lowest first) to acts.
+void binomial_reverse(std::vector<Act>& acts, int a, int b, int sa, std::vector<int>& free_) {
+  while (true) {
+    if (a == b) {
+      acts.push_back({1, a, 0, sa, -1});
+      return;
+    }
+    if (free_.empty()) {
+      for (int n = b; n > a; --n) {
+        acts.push_back({0, a, n - a, sa, -1});
+        acts.push_back({1, n, 0, -1, -1});
+      }
+      acts.push_back({1, a, 0, sa, -1});
+      return;
+    }
+    const int m = a + binomial_split(b - a, int(free_.size()));
+    const int j = free_.front();
+    free_.erase(free_.begin());
+    acts.push_back({0, a, m - a, sa, j});
+    binomial_reverse(acts, m, b, j, free_);
+    free_.insert(std::lower_bound(free_.begin(), free_.end(), j), j);
+    b = m - 1;  // then levels a..m-1 with the same snapshots
+  }
+}
+
+// Schedule for n steps with s free snapshots: acts holds the whole reversal;
+// its leading advances into snapshots (the first descent) are the ones the
+// forward sweep performs on its way to level n.
+void binomial_plan(Plan& p, int n, int s) {
+  p.acts.clear();
+  std::vector<int> free_;
+  for (int j = 1; j <= s; ++j) free_.push_back(j);
+  binomial_reverse(p.acts, 0, n, 0, free_);
+  p.n_pre = 0;
+  while (p.n_pre < int(p.acts.size()) && !p.acts[p.n_pre].adjoint && p.acts[p.n_pre].dst >= 0)
+    ++p.n_pre;
+  p.replay = 0;
+  for (size_t i = size_t(p.n_pre); i < p.acts.size(); ++i)
+    if (!p.acts[i].adjoint) p.replay += p.acts[i].steps;
+}
+
+size_t snapshot_bytes(const lks_ctx* c) {
+  return size_t(ckpt_fields(c)) * size_t(c->N) * size_t(c->rsz);
+}
+
+lks_status plan_binomial(lks_ctx* c, Plan& p, size_t base) {
+  const int n = c->n_steps;
+  const size_t one = snapshot_bytes(c);
+  int s = c->ckpt_slots;
+  if (s == 0) {
+    // as many free snapshots as the budget holds, at most one per level
+    if (c->budget == 0) {
+      s = n;
+    } else {
+      if (c->budget < base + one) return fail(nullptr, LKS_E_NOMEM,
+          "memory budget below one snapshot of the state");
+      s = int(std::min<size_t>((c->budget - base) / one - 1, size_t(n)));
+      while (s > 0 && base + align256(size_t(s + 1) * one) > c->budget) --s;
+    }
+  }
+  s = std::min(s, n);
+  const size_t need = base + align256(size_t(s + 1) * one);
+  if (c->budget != 0 && need > c->budget) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "memory budget %zu B below the %d-snapshot plan (%zu B)",
+             c->budget, s, need);
+    return fail(nullptr, LKS_E_NOMEM, buf);
+  }
+  p.scheme = LKS_CKPT_BINOMIAL;
+  p.n_ckpt = s + 1;
+  p.n_slots = 0;
+  p.K = 0;
+  p.ls = 0;
+  p.ckpt_bytes = size_t(s + 1) * one;
+  p.total = need;
+  binomial_plan(p, n, s);
+  return LKS_OK;
+}
+
+// Unsteady problems: two-level checkpointing (the largest interval K whose
+// storage fits the budget, the fewest replayed steps for the memory given;
+// K = N+1 keeps every level) unless binomial checkpointing is requested, or
+// no two-level plan fits the budget and the scheme is automatic.
 lks_status plan_memory(lks_ctx* c) {
   Plan p;
   size_t base = base_bytes(c);
@@ -181,6 +310,11 @@ lks_status plan_memory(lks_ctx* c) {
     p.total = base;
     c->plan = p;
     return LKS_OK;
+  }
+  if (c->ckpt_scheme == LKS_CKPT_BINOMIAL) {
+    lks_status st = plan_binomial(c, p, base);
+    if (st == LKS_OK) c->plan = std::move(p);
+    return st;
   }
   const int n = c->n_steps;
   int best = 0;
@@ -190,6 +324,11 @@ lks_status plan_memory(lks_ctx* c) {
       best = K;
       break;
     }
+  }
+  if (best == 0 && c->ckpt_scheme == LKS_CKPT_AUTO) {
+    lks_status st = plan_binomial(c, p, base);
+    if (st == LKS_OK) c->plan = std::move(p);
+    return st;
   }
   if (best == 0) {
     // report the smallest footprint for the message
@@ -207,7 +346,9 @@ lks_status plan_memory(lks_ctx* c) {
   p.ckpt_bytes = traj_bytes(c, best);
   p.total = base + align256(size_t(p.n_ckpt) * ckpt_fields(c) * c->N * c->rsz) +
             align256(size_t(p.n_slots) * slot_fields(c) * c->N * c->rsz);
-  c->plan = p;
+  p.scheme = LKS_CKPT_TWO_LEVEL;
+  p.replay = best > n ? 0 : (long long)p.ls - (long long)p.ls / best;
+  c->plan = std::move(p);
   return LKS_OK;
 }
 
@@ -493,8 +634,64 @@ struct Run {
                         s[0], s[1], s[2], s[3], c->stream);
   }
 
+  // binomial checkpointing: snapshot j (the layout of a checkpoint) and the
+  // ping-pong working buffers p
+  void snap(int j, R* out[5]) {
+    for (int f = 0; f < 5; ++f) out[f] = f < ckpt_fields(c) ? ckpt(j, f) : nullptr;
+  }
+  void work(int p, R* out[5]) {
+    for (int f = 0; f < 5; ++f) out[f] = f < nf ? rp<R>(c->S[p][f]) : nullptr;
+    if (!c->phys.thermal) out[nf - 1] = nullptr;
+  }
+  // `steps` LKS steps from level `from` held in `in`; the last step writes
+  // `last` when given, the others alternate between the working buffers.
+  // res receives the pointers of the final level.
+  void bin_advance(R* const in[5], int from, int steps, R* const* last, R* res[5], double* acc) {
+    R* cur[5];
+    for (int f = 0; f < 5; ++f) cur[f] = in[f];
+    int p = 0;
+    for (int i = 0; i < steps; ++i) {
+      R* out[5];
+      if (last && i == steps - 1) {
+        for (int f = 0; f < 5; ++f) out[f] = last[f];
+      } else {
+        work(p, out);
+        p ^= 1;
+      }
+      step(cur, out, from + i + 1, acc);
+      for (int f = 0; f < 5; ++f) cur[f] = out[f];
+    }
+    for (int f = 0; f < 5; ++f) res[f] = cur[f];
+  }
+
+  // forward sweep of a binomial plan: level 0 in snapshot 0, the leading
+  // placements of the schedule on the way, the objective over every level
+  void forward_binomial(int steps) {
+    R* cur[5];
+    snap(0, cur);
+    init(cur);
+    int lvl = 0;
+    const Plan& p = c->plan;
+    for (int i = 0; i < p.n_pre; ++i) {
+      const Act& x = p.acts[size_t(i)];
+      R* dst[5];
+      snap(x.dst, dst);
+      bin_advance(cur, lvl, x.steps, dst, cur, c->acc);
+      lvl += x.steps;
+    }
+    bin_advance(cur, lvl, steps - lvl, nullptr, cur, c->acc);
+    for (int f = 0; f < 5; ++f) c->lastv[f] = cur[f];
+    lks::launch_finite_check<R>(cur[1], N, c->flag, c->stream);
+    c->last_level = steps;
+  }
+
   void forward(const double* gamma, int steps) {
     coefficients(gamma);
+    if (c->mode == LKS_UNSTEADY && c->plan.scheme == LKS_CKPT_BINOMIAL) {
+      lks::launch_fill(c->acc, size_t(acc_count(c)), 0.0, c->stream);
+      forward_binomial(steps);
+      return;
+    }
     if (c->mode == LKS_STEADY) {
       R* s0[5] = {};
       for (int f = 0; f < nf; ++f) s0[f] = rp<R>(c->S[0][f]);
@@ -666,7 +863,40 @@ struct Run {
     }
   }
 
+  // reverse sweep of a binomial plan: the schedule's actions after the
+  // placements the forward sweep made
+  void adjoint_binomial(double seed, double* dJ) {
+    const int Nst = c->n_steps;
+    const Plan& p = c->plan;
+    lks::launch_fill(dJ, N, 0.0, c->stream);
+    c->acur = 0;
+    zero_adjoint(0);
+    R* wk[5] = {};
+    for (size_t i = size_t(p.n_pre); i < p.acts.size(); ++i) {
+      const Act& x = p.acts[i];
+      R* src[5];
+      snap(x.src >= 0 ? x.src : 0, src);
+      if (!x.adjoint) {
+        R* dst[5];
+        if (x.dst >= 0) snap(x.dst, dst);
+        bin_advance(src, x.from, x.steps, x.dst >= 0 ? dst : nullptr, wk, nullptr);
+        continue;
+      }
+      R* const* lv = x.src >= 0 ? src : wk;
+      const int n = x.from;
+      const double w = n >= 1 ? seed / Nst : 0.0;
+      const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? w : 0.0;
+      const double sh = c->objective == LKS_OBJ_HEAT ? w : 0.0;
+      const double ss = c->objective == LKS_OBJ_HEAT_EXCHANGE ? w : 0.0;
+      adj_step(lv, sdp, sh, (n == 0 && c->adj_exact) ? nullptr : dJ, 1, ss);
+    }
+  }
+
   void adjoint_unsteady(double seed, double* dJ) {
+    if (c->plan.scheme == LKS_CKPT_BINOMIAL) {
+      adjoint_binomial(seed, dJ);
+      return;
+    }
     const int Nst = c->n_steps, K = c->plan.K;
     lks::launch_fill(dJ, N, 0.0, c->stream);
     c->acur = 0;
@@ -718,6 +948,8 @@ struct Run {
     if ((f = fwd_index(which)) >= 0) {
       if (c->mode == LKS_STEADY) {
         src = c->S[c->cur][f];
+      } else if (c->plan.scheme == LKS_CKPT_BINOMIAL) {
+        src = c->lastv[f];
       } else {
         R* lv[5];
         level(c->last_level, c->plan.ls, lv);
@@ -1090,6 +1322,39 @@ lks_status lks_set_adjoint_mode(lks_ctx* c, int mode) {
     return fail(c, LKS_E_INVALID, "adjoint mode must be LKS_ADJ_PAPER or LKS_ADJ_EXACT");
   if (mode != c->adj_exact) c->have_adjoint = false;
   c->adj_exact = mode;
+  return LKS_OK;
+}
+
+lks_status lks_set_checkpointing(lks_ctx* c, int scheme, int slots) {
+  if (!c) return LKS_E_INVALID;
+  if (c->bound) return fail(c, LKS_E_STATE, "checkpointing is planned before lks_bind_workspace");
+  if (c->mode != LKS_UNSTEADY)
+    return fail(c, LKS_E_UNSUPPORTED, "checkpointing applies to unsteady problems");
+  if (scheme != LKS_CKPT_AUTO && scheme != LKS_CKPT_TWO_LEVEL && scheme != LKS_CKPT_BINOMIAL)
+    return fail(c, LKS_E_INVALID, "unknown checkpointing scheme");
+  if (slots < 0 || (slots > 0 && scheme != LKS_CKPT_BINOMIAL))
+    return fail(c, LKS_E_INVALID, "slots must be >= 0, and 0 unless the scheme is binomial");
+  const int old_scheme = c->ckpt_scheme, old_slots = c->ckpt_slots;
+  c->ckpt_scheme = scheme;
+  c->ckpt_slots = slots;
+  lks_status st = plan_memory(c);
+  if (st != LKS_OK) {
+    c->err = g_create_error;
+    c->ckpt_scheme = old_scheme;
+    c->ckpt_slots = old_slots;
+    plan_memory(c);
+  }
+  return st;
+}
+
+lks_status lks_checkpoint_info(const lks_ctx* c, int* scheme, int* count, long long* replay_steps) {
+  if (!c) return LKS_E_INVALID;
+  const bool uns = c->mode == LKS_UNSTEADY;
+  if (scheme) *scheme = uns ? c->plan.scheme : 0;
+  if (count)
+    *count = !uns ? 0 : (c->plan.scheme == LKS_CKPT_BINOMIAL ? c->plan.n_ckpt
+                                                             : std::min(c->plan.K, c->n_steps));
+  if (replay_steps) *replay_steps = uns ? c->plan.replay : 0;
   return LKS_OK;
 }
 

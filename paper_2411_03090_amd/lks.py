@@ -44,6 +44,8 @@ LKS_FP64, LKS_FP32DEV = 0, 1
 LKS_OBJ_PRESSURE_DROP, LKS_OBJ_HEAT, LKS_OBJ_HEAT_EXCHANGE = 0, 1, 2
 LKS_STEADY, LKS_UNSTEADY = 0, 1
 LKS_ADJ_PAPER, LKS_ADJ_EXACT = 0, 1
+LKS_CKPT_AUTO, LKS_CKPT_TWO_LEVEL, LKS_CKPT_BINOMIAL = 0, 1, 2
+_CKPT = {"auto": LKS_CKPT_AUTO, "two_level": LKS_CKPT_TWO_LEVEL, "binomial": LKS_CKPT_BINOMIAL}
 FIELDS = {"drho": 0, "ux": 1, "uy": 2, "T": 3,
           "adj_rho": 4, "adj_vx": 5, "adj_vy": 6, "adj_theta": 7,
           "uz": 8, "adj_vz": 9}
@@ -55,7 +57,8 @@ EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forwa
             "lks_batch_bind_workspace", "lks_batch_run", "lks_batch_read_field",
             "lks_batch_last_error", "lks_batch_destroy", "lks_autotune",
             "lks_batch_autotune", "lks_set_tile_rows", "lks_set_steps_per_launch",
-            "lks_launch_shape", "lks_batch_set_tile_rows", "lks_set_adjoint_mode")
+            "lks_launch_shape", "lks_batch_set_tile_rows", "lks_set_adjoint_mode",
+            "lks_set_checkpointing", "lks_checkpoint_info")
 
 
 class Grid(ctypes.Structure):
@@ -143,6 +146,11 @@ _lib.lks_launch_shape.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int)] * 3
 _lib.lks_launch_shape.restype = _st
 _lib.lks_set_adjoint_mode.argtypes = [_vp, ctypes.c_int]
 _lib.lks_set_adjoint_mode.restype = _st
+_lib.lks_set_checkpointing.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+_lib.lks_set_checkpointing.restype = _st
+_lib.lks_checkpoint_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_longlong)]
+_lib.lks_checkpoint_info.restype = _st
 _lib.lks_batch_set_tile_rows.argtypes = [_vp, ctypes.c_int]
 _lib.lks_batch_set_tile_rows.restype = _st
 _lib.lks_batch_destroy.argtypes = [_vp]
@@ -173,11 +181,13 @@ class LKS:
 
     ``wl`` is a workloads.Workload (D2Q9) or workloads.Workload3 (D3Q19).
     ``precision`` is "fp64" or "fp32". ``mem_budget`` bounds the unsteady
-    trajectory storage (bytes, 0 = none).
+    trajectory storage (bytes, 0 = none). ``checkpointing`` is None (automatic)
+    or (scheme, slots) with scheme "auto", "two_level" or "binomial"; see
+    lks_set_checkpointing.
     """
 
     def __init__(self, wl, precision="fp64", mem_budget=0, device=None, stream=None,
-                 bind=True):
+                 bind=True, checkpointing=None):
         self.wl = wl
         nz = getattr(wl, "nz", 1)
         self.d3 = nz > 1 or hasattr(wl, "periodic_axes")
@@ -214,6 +224,8 @@ class LKS:
         mode = getattr(wl, "adjoint_mode", "paper")
         if mode != "paper":
             self.set_adjoint_mode(mode)
+        if checkpointing is not None:
+            self.set_checkpointing(*checkpointing)
         if bind:
             self.bind()
 
@@ -283,6 +295,20 @@ class LKS:
         discrete Brinkman step); see lks_set_adjoint_mode."""
         code = {"paper": LKS_ADJ_PAPER, "exact": LKS_ADJ_EXACT}[mode]
         _check(_lib.lks_set_adjoint_mode(self.ctx, code), self.ctx)
+
+    def set_checkpointing(self, scheme, slots=0):
+        """Plan the unsteady checkpoints before binding (see
+        lks_set_checkpointing)."""
+        _check(_lib.lks_set_checkpointing(self.ctx, _CKPT[scheme], int(slots)), self.ctx)
+
+    def checkpoint_info(self):
+        """{"scheme": "two_level" | "binomial" | None, "count": K or snapshots,
+        "replay_steps": forward steps one adjoint sweep recomputes}."""
+        sc, n, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong()
+        _check(_lib.lks_checkpoint_info(self.ctx, ctypes.byref(sc), ctypes.byref(n),
+                                        ctypes.byref(r)), self.ctx)
+        name = {LKS_CKPT_TWO_LEVEL: "two_level", LKS_CKPT_BINOMIAL: "binomial"}.get(sc.value)
+        return {"scheme": name, "count": n.value, "replay_steps": r.value}
 
     def launch_shape(self):
         """(tile rows, forward steps per launch, adjoint steps per launch)."""
