@@ -37,6 +37,8 @@ TAG_J_OUTLET = 32
 OBJ_PRESSURE_DROP = 0
 OBJ_HEAT = 1
 OBJ_HEAT_EXCHANGE = 2
+OBJ_HEAT_SINK = 3
+TAG_PROBE = 64
 MODE_STEADY = 0
 MODE_UNSTEADY = 1
 N_ADJ_FIELDS = 9
@@ -91,13 +93,16 @@ def lib():
         _lib.orc_probe_heat.restype = ctypes.c_double
         _lib.orc_adjoint_equilibrium.argtypes = [P, d, d, d, dd, d, d, d, d, d]
         _lib.orc_alks_step.argtypes = [P, d, d, d, d, d, d, d, d, d, dd, dd,
-                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, d]
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, d]
+        _lib.orc_probe_T.argtypes = [P, d]
+        _lib.orc_probe_T.restype = ctypes.c_double
         _lib.orc_sens_add.argtypes = [P, d, d, d, d, d, d, dd, ctypes.c_double, d]
         _lib.orc_source_sens_add.argtypes = [P, d, d, d, d, d, d, d, dd, ctypes.c_double, d]
         _lib.orc_boundary_fill.argtypes = [P, ctypes.c_uint8, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double,
-                                           ctypes.c_double, d, d, d]
+                                           ctypes.c_double, d, d, d, ctypes.c_double]
     return _lib
 
 
@@ -200,7 +205,21 @@ def level_objective(pb: Problem, s: State, beta=None) -> float:
         return pressure_drop(pb, s)
     if pb.wl.objective == OBJ_HEAT_EXCHANGE:
         return source_heat(pb, beta if beta is not None else np.zeros(pb.N), s)
+    if pb.wl.objective == OBJ_HEAT_SINK:
+        return lib().orc_probe_T(pb.ref, _p(s.T))
     return probe_heat(pb, s)
+
+
+def heated_count(pb: Problem) -> int:
+    return int(np.count_nonzero(pb.mask & TAG_PROBE))
+
+
+def _seeds(pb: Problem, w):
+    """(seed_dp, seed_heat, seed_src, seed_bt) of one level for objective weight w."""
+    o = pb.wl.objective
+    return (w if o == OBJ_PRESSURE_DROP else 0.0, w if o == OBJ_HEAT else 0.0,
+            w if o == OBJ_HEAT_EXCHANGE else 0.0,
+            w / max(heated_count(pb), 1) if o == OBJ_HEAT_SINK else 0.0)
 
 
 def adjoint_equilibrium(pb: Problem, B, ux, uy, adj, alpha=None, beta=None):
@@ -216,14 +235,14 @@ def adjoint_equilibrium(pb: Problem, B, ux, uy, adj, alpha=None, beta=None):
 
 
 def alks_step(pb: Problem, alpha, B, src: State, dst: State, adj_in, seed_dp, seed_heat,
-              beta=None, seed_src=0.0):
+              beta=None, seed_src=0.0, seed_bt=0.0):
     out = pb.zeros(N_ADJ_FIELDS)
     work = np.zeros(3 * pb.N)
     pin, k1 = _pp(adj_in)
     pout, k2 = _pp(out)
     lib().orc_alks_step(pb.ref, _p(alpha), _p(B), _opt(beta), _p(src.ux), _p(src.uy), _p(src.T),
                         _p(dst.ux), _p(dst.uy), _p(dst.T), pin, pout, seed_dp, seed_heat,
-                        seed_src, _p(work))
+                        seed_src, seed_bt, _p(work))
     return out
 
 
@@ -241,14 +260,16 @@ def source_sens_add(pb: Problem, alpha, B, beta, dbeta, s: State, adj, wJ, sens)
                               _p(s.uy), _p(s.T), pp, wJ, _p(sens))
 
 
-def boundary_fill(pb: Problem, m, normal, Bn, Tn, u, seed_dp, fk, gk):
+def boundary_fill(pb: Problem, m, normal, Bn, Tn, u, seed_dp, fk, gk, seed_T=0.0):
     """Completed (f~, g~) at one ring node and the multipliers
-    (flow pair, thermal)."""
+    (flow pair, thermal); seed_T is dJ/dg_i of a boundary temperature
+    objective at the node."""
     fk = np.ascontiguousarray(fk, dtype=np.float64).copy()
     gk = np.ascontiguousarray(gk, dtype=np.float64).copy()
     mult = np.zeros(3)
     lib().orc_boundary_fill(pb.ref, int(m), int(normal[0]), int(normal[1]), Bn, Tn,
-                            float(u[0]), float(u[1]), seed_dp, _p(fk), _p(gk), _p(mult))
+                            float(u[0]), float(u[1]), seed_dp, _p(fk), _p(gk), _p(mult),
+                            float(seed_T))
     return fk, gk, mult
 
 
@@ -285,11 +306,9 @@ def adjoint_steady(pb: Problem, gamma, state: State, n_adj, seed=1.0):
     alpha, dalpha, B, dB = coefficients(pb, gamma)
     beta, dbeta = source_coefficients(pb, gamma)
     adj = pb.zeros(N_ADJ_FIELDS)
-    sdp = seed if wl.objective == OBJ_PRESSURE_DROP else 0.0
-    sh = seed if wl.objective == OBJ_HEAT else 0.0
-    ss = seed if wl.objective == OBJ_HEAT_EXCHANGE else 0.0
+    sdp, sh, ss, sbt = _seeds(pb, seed)
     for _ in range(n_adj):
-        adj = alks_step(pb, alpha, B, state, state, adj, sdp, sh, beta, ss)
+        adj = alks_step(pb, alpha, B, state, state, adj, sdp, sh, beta, ss, sbt)
     sens = np.zeros(pb.N)
     sens_add(pb, alpha, dalpha, dB, state, adj, 1.0, sens)
     if beta is not None:
@@ -310,11 +329,9 @@ def adjoint_unsteady(pb: Problem, gamma, traj, seed=1.0):
     sens = np.zeros(pb.N)
     for n in range(N, -1, -1):
         w = seed / N if n >= 1 else 0.0
-        sdp = w if wl.objective == OBJ_PRESSURE_DROP else 0.0
-        sh = w if wl.objective == OBJ_HEAT else 0.0
-        ss = w if wl.objective == OBJ_HEAT_EXCHANGE else 0.0
+        sdp, sh, ss, sbt = _seeds(pb, w)
         src = traj[min(n + 1, N)]
-        adj = alks_step(pb, alpha, B, src, traj[n], adj, sdp, sh, beta, ss)
+        adj = alks_step(pb, alpha, B, src, traj[n], adj, sdp, sh, beta, ss, sbt)
         if n >= 1 or getattr(wl, "adjoint_mode", "paper") != "exact":
             sens_add(pb, alpha, dalpha, dB, traj[n], adj, 1.0, sens)
             if beta is not None:

@@ -54,6 +54,7 @@ static const double W[Q9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
 
 /* objectives */
 #define OBJ_HEAT_EXCHANGE 2
+#define OBJ_HEAT_SINK 3
 
 typedef struct {
   int nx, ny;
@@ -65,7 +66,8 @@ typedef struct {
   double rho_out;        /* prescribed outlet density (p = rho/3) */
   const uint8_t *mask;   /* nx*ny node classes */
   const double *ubar;    /* 2*nx*ny prescribed velocity (x block, y block) */
-  const double *Tbar;    /* nx*ny prescribed temperature */
+  const double *Tbar;    /* nx*ny prescribed temperature; at heat-flux nodes
+                            the heat flux qbar into the domain */
   int adj_exact;         /* 1: exact discrete adjoint of the Brinkman step */
   double gbeta[2];       /* g beta of the Boussinesq force eq:boussinesqforce */
   double T_ref;          /* its reference temperature */
@@ -259,9 +261,13 @@ void orc_init_state(const orc_problem *P, double ufac0, double *drho, double *ux
  * rho = sum f_i and u.n = sum (c_i.n) f_i:
  *   velocity node: u = ubar, rho = S0 + 2 S+ - u.n
  *   pressure node: rho = rho_out, u_t = 0, u.n = S0 + 2 S+ - rho_out
- *   flux (adiabatic) node: T (1 + u.n) = S0g + 2 S+g
+ *   heat-flux node: T (1 + u.n) = S0g + 2 S+g + qbar
  *   temperature node: T = Tbar
- * where S0, S+ sum the known f_i with c_i.n = 0 and c_i.n > 0.
+ * where S0, S+ sum the known f_i with c_i.n = 0 and c_i.n > 0. The heat-flux
+ * condition of Sec. 2.4, -q.n = qbar with q = sum c_i g_i - u T (the flux
+ * whose variation the kappa~ term of the adjoint boundary conditions
+ * carries), fixes the unknown g_i: with S- their sum, S+ - S- - u.n T = -qbar,
+ * and T = S0 + S+ + S- gives the closure above (qbar = 0: adiabatic).
  * Corners: u = 0; rho and T copied from the neighbour along y at the new
  * level.
  *
@@ -340,7 +346,7 @@ void orc_lks_step(const orc_problem *P, const double *alpha, const double *B,
       }
       if (th) {
         if (THERM(m) == THERM_DIRICHLET) T_o[k] = P->Tbar[k];
-        else T_o[k] = (S0g + 2.0 * Spg) / (1.0 + un);
+        else T_o[k] = (S0g + 2.0 * Spg + P->Tbar[k]) / (1.0 + un);
       }
     }
   }
@@ -380,6 +386,19 @@ double orc_probe_heat(const orc_problem *P, const double *ux, const double *T) {
   for (int k = 0; k < N; ++k)
     if (P->mask[k] & TAG_PROBE) s += ux[k] * T[k];
   return s;
+}
+
+/* Heat-sink objective eq:objective_heatsink at one level: the mean
+ * temperature over the probe-tagged (heated) boundary nodes. */
+double orc_probe_T(const orc_problem *P, const double *T) {
+  double s = 0.0;
+  int n = 0, N = P->nx * P->ny;
+  for (int k = 0; k < N; ++k)
+    if (P->mask[k] & TAG_PROBE) {
+      s += T[k];
+      ++n;
+    }
+  return n ? s / n : 0.0;
 }
 
 /* Heat-exchange objective eq:objective_heatexchanger at one level:
@@ -515,8 +534,10 @@ static void lsq_solve(int rows, int cols, const double *K, const double *b,
  * s_i = +seed/3 on inlet nodes and -seed/3 on outlet nodes.
  *
  * Thermal rows (eq:agboundaryT / eq:agboundaryq), for every i:
- *   r_i = (n.c_i) g~_i - B (n.q~) + [eta~ | kappa~ (c_i - u).n]
- * with q~ expanded through eq:agq. Unknowns: g~_i with c_i.n > 0 and the
+ *   r_i = (n.c_i) g~_i - B (n.q~) + [eta~ | kappa~ (c_i - u).n] + s_T
+ * with q~ expanded through eq:agq and s_T = dJ_dO/dg_i: for the heat-sink
+ * objective (mean T over the heated nodes, T = sum g_i) s_T = seed_T on
+ * heated nodes for every i. Unknowns: g~_i with c_i.n > 0 and the
  * multiplier. The thermal system does not involve f~, so it is solved first
  * and its kappa~ enters the flow rows as a known term.
  *
@@ -524,8 +545,8 @@ static void lsq_solve(int rows, int cols, const double *K, const double *b,
  * Outputs: fk, gk completed in place. */
 static void boundary_fill(const orc_problem *P, uint8_t m, const int n[2],
                           double A, double Bn, double Tn, double unx,
-                          double uny, double seed_dp, double *fk, double *gk,
-                          double *mult) {
+                          double uny, double seed_dp, double seed_T, double *fk,
+                          double *gk, double *mult) {
   double cn[Q9];
   for (int q = 0; q < Q9; ++q) cn[q] = CX[q] * n[0] + CY[q] * n[1];
   int unk[Q9], nu = 0;
@@ -551,7 +572,7 @@ static void boundary_fill(const orc_problem *P, uint8_t m, const int n[2],
         K[r * cols + a] = (q == r ? cn[r] : 0.0) - Bn * W[q] * cn[q];
       }
       K[r * cols + nu] = flux ? (cn[r] - u_n) : 1.0;
-      b[r] = known;
+      b[r] = known + seed_T;
     }
     lsq_solve(Q9, cols, K, b, x);
     for (int a = 0; a < nu; ++a) gk[unk[a]] = x[a];
@@ -614,7 +635,9 @@ static void boundary_fill(const orc_problem *P, uint8_t m, const int n[2],
  * Volume seeds (heat objective, J_O = seed_heat * u_x T on probe nodes, with
  * u_x = sum c_ix f_i and T = sum g_i): dJ_O/df_i = seed_heat T c_ix,
  * dJ_O/dg_i = seed_heat u_x, evaluated at level n. Heat-exchange objective
- * J_O = -seed_src sum beta (1 - T): dJ_O/dg_i = seed_src beta.
+ * J_O = -seed_src sum beta (1 - T): dJ_O/dg_i = seed_src beta. Heat-sink
+ * objective (a boundary objective): seed_bt = dJ/dT at the heated ring nodes
+ * enters their least-squares completion (boundary_fill).
  *
  * Heat source (beta non-NULL): eq:albeg_ex adds dx dQ/dg_i T~ = -beta T~ to
  * g~_i at the same level, so T~ is implicit like u~:
@@ -632,7 +655,7 @@ void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
                    const double *uy_dst, const double *T_dst,
                    const double *const *adj_in, double *const *adj_out,
                    double seed_dp, double seed_heat, double seed_src,
-                   double *work) {
+                   double seed_bt, double *work) {
   const int nx = P->nx, ny = P->ny, N = nx * ny;
   const double A = coef_A(P);
   const int th = P->thermal;
@@ -663,7 +686,8 @@ void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
       }
       double Tn = th ? T_dst[k] : 0.0;
       if (bnd)
-        boundary_fill(P, m, nrm, A, B[k], Tn, ux_dst[k], uy_dst[k], seed_dp, fs,
+        boundary_fill(P, m, nrm, A, B[k], Tn, ux_dst[k], uy_dst[k], seed_dp,
+                      (m & TAG_PROBE) ? seed_bt : 0.0, fs,
                       gs, NULL);
 
       /* volume seeds at level n */
@@ -792,7 +816,8 @@ void orc_source_sens_add(const orc_problem *P, const double *alpha, const double
  * thermal multiplier (eta~ or kappa~). */
 void orc_boundary_fill(const orc_problem *P, uint8_t m, int nx_, int ny_,
                        double Bn, double Tn, double unx, double uny,
-                       double seed_dp, double *fk, double *gk, double *mult) {
+                       double seed_dp, double *fk, double *gk, double *mult,
+                       double seed_T) {
   int n[2] = {nx_, ny_};
-  boundary_fill(P, m, n, coef_A(P), Bn, Tn, unx, uny, seed_dp, fk, gk, mult);
+  boundary_fill(P, m, n, coef_A(P), Bn, Tn, unx, uny, seed_dp, seed_T, fk, gk, mult);
 }

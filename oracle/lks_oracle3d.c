@@ -291,7 +291,8 @@ void orc3_lks_step(const orc3_problem *P, const double *alpha, const double *B,
     }
     if (th) {
       if (THERM(m) == THERM_DIRICHLET) T_o[k] = P->Tbar[k];
-      else T_o[k] = (S0g + 2.0 * Spg) / (1.0 + un);
+      /* heat-flux face: -q.n = qbar (Tbar holds qbar there; 0: adiabatic) */
+      else T_o[k] = (S0g + 2.0 * Spg + P->Tbar[k]) / (1.0 + un);
     }
   }
   for (long k = 0; k < N; ++k) {
