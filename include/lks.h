@@ -61,8 +61,10 @@ enum { LKS_FP64 = 0, LKS_FP32DEV = 1 };
 /* objectives: static pressure drop (eq:objective_pipebend); time-averaged
  * enthalpy flux u_x T through the probe nodes; heat-exchange amount
  * J = -sum beta_gamma (1 - T) over all nodes (eq:objective_heatexchanger;
- * needs the heat source, beta_max > 0) */
-enum { LKS_OBJ_PRESSURE_DROP = 0, LKS_OBJ_HEAT = 1, LKS_OBJ_HEAT_EXCHANGE = 2 };
+ * needs the heat source, beta_max > 0); heat-sink objective: the mean
+ * temperature over the heated boundary (eq:objective_heatsink; D2Q9) */
+enum { LKS_OBJ_PRESSURE_DROP = 0, LKS_OBJ_HEAT = 1, LKS_OBJ_HEAT_EXCHANGE = 2,
+       LKS_OBJ_HEAT_SINK = 3 };
 enum { LKS_STEADY = 0, LKS_UNSTEADY = 1 };
 enum { LKS_ADJ_PAPER = 0, LKS_ADJ_EXACT = 1 };
 /* checkpointing of unsteady sweeps (see lks_set_checkpointing) */
@@ -74,11 +76,14 @@ enum { LKS_CKPT_AUTO = 0, LKS_CKPT_TWO_LEVEL = 1, LKS_CKPT_BINOMIAL = 2 };
  *            edge or corner (D3Q19): u = 0, density, temperature and adjoint
  *            moments copied from the neighbour one step inwards along y
  *            (and z);
- *   bits 2-3 thermal class: none, prescribed temperature, prescribed zero
- *            heat flux (adiabatic);
+ *   bits 2-3 thermal class: none, prescribed temperature, prescribed heat
+ *            flux -q.n = q_bar with q = sum_i c_i g_i - u T (Sec. 2.4), q_bar
+ *            read from T_bar at the node (0: adiabatic);
  *   bit 4/5  member of the inlet/outlet set of the pressure drop
  *            (eq:objective_pipebend);
- *   bit 6    member of the probe set of the heat-transfer objective;
+ *   bit 6    member of the probe set of the heat-transfer objective, or
+ *            of the heated boundary of the heat-sink objective (ring nodes
+ *            of the heat-flux class);
  *   bit 7    D3Q19 only: interior node that is not a design node (its
  *            sensitivity is zero), e.g. a solid held at a prescribed
  *            temperature (interior node with thermal class "prescribed
@@ -147,7 +152,8 @@ typedef struct {
                                 node: x block, y block (, z block); the
                                 velocity prescribed at velocity nodes (copied) */
   const double *T_bar;       /* host, one value per node: temperature at
-                                prescribed-T nodes
+                                prescribed-T nodes, heat flux into the
+                                domain at heat-flux nodes, ignored elsewhere
                                 (copied); may be NULL if not thermal */
   const double *u_factor;    /* host, n_factor: u_bar is scaled by
                                 u_factor[min(n, n_factor-1)] at level n;

@@ -132,6 +132,7 @@ struct AdjArgs {
   const R* beta = nullptr;   // heat-source coefficient beta_gamma, or nullptr
   const R* dbeta = nullptr;  // beta'(gamma)
   double seed_src = 0.0;     // weight of the heat-exchange objective
+  double seed_bt = 0.0;      // dJ/dT at the heated nodes of the heat-sink objective
 };
 
 // one design of a batch: geometry and the arguments of both ping-pong parities
@@ -274,6 +275,9 @@ void launch_pressure_drop(const Geo& g, const uint8_t* mask, const R* d, double*
 template <typename R>
 void launch_probe_heat(const Geo& g, const uint8_t* mask, const R* ux, const R* T, double* out,
                        hipStream_t s);
+// heat-sink objective of one level: sum of T over the probe-tagged nodes
+template <typename R>
+void launch_probe_T(const Geo& g, const uint8_t* mask, const R* T, double* out, hipStream_t s);
 // heat-exchange objective of one level: sum of beta (T - 1) over all nodes
 template <typename R>
 void launch_source_heat(const Geo& g, const R* beta, const R* T, double* out, hipStream_t s);

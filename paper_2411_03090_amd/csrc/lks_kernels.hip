@@ -418,8 +418,10 @@ __device__ inline void fwd_pull(const Geo& g, const FwdArgs<R>& a, const R* lf, 
     uyn = un * R(ny_);
   }
   if constexpr (TH) {
+    // heat-flux node: -q.n = qbar with q = sum c_i g_i - u T (Sec. 2.4); Tb
+    // holds qbar there (0: adiabatic)
     if (((m >> 2) & 3) == THERM_DIRICHLET) Tn = a.Tb[k];
-    else Tn = (S0g + R(2) * Spg) / (R(1) + un);
+    else Tn = (S0g + R(2) * Spg + a.Tb[k]) / (R(1) + un);
   }
 }
 
@@ -519,6 +521,8 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
         if (m & TAG_PROBE) part += double(uxn) * double(Tn);
       } else if (a.objective == 2) {
         if constexpr (TH) part += double(a.beta[k]) * (double(Tn) - 1.0);
+      } else if (a.objective == 3) {
+        if (m & TAG_PROBE) part += double(Tn);
       } else {
         if (m & TAG_J_INLET) part += double(dn);
         if (m & TAG_J_OUTLET) part -= double(dn);
@@ -580,7 +584,11 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
       const int nx_ = o == 0 ? -1 : (o == 1 ? 1 : 0);
       const int ny_ = o == 2 ? -1 : (o == 3 ? 1 : 0);
       const R un = a.ux[k] * R(nx_) + a.uy[k] * R(ny_);
-      R num = R(0);
+      // a boundary-temperature objective adds dJ/dg_i = st to every row; in
+      // the Schur form it enters kappa through sum_r (Q v)_r = A1 - u_n A2
+      // and the unknowns through h1
+      const R st = (m & TAG_PROBE) ? R(a.seed_bt) : R(0);
+      R num = st * (R(op.A1) - un * R(op.A2));
 #pragma unroll
       for (int q = 0; q < 9; ++q) num += (R(op.ga[q]) - un * R(op.ge[q])) * gq[q];
       const R den = R(op.A0) - R(2) * un * R(op.A1) + un * un * R(op.A2);
@@ -590,7 +598,7 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
         R t = R(0);
 #pragma unroll
         for (int q = 0; q < 9; ++q) t += R(op.Lg0[c][q]) * gq[q];
-        gu[c] = t - kappa * (R(op.hc[c]) - un * R(op.h1[c]));
+        gu[c] = t - st * R(op.h1[c]) - kappa * (R(op.hc[c]) - un * R(op.h1[c]));
       }
     }
   }
@@ -1347,6 +1355,18 @@ __global__ __launch_bounds__(NTHREADS) void probe_heat_kernel(Geo g, const uint8
   if (threadIdx.x == 0) *out = s;
 }
 
+// sum of T over the probe-tagged nodes (heat-sink objective, before the mean)
+template <typename R>
+__global__ __launch_bounds__(NTHREADS) void probe_T_kernel(Geo g, const uint8_t* mask, const R* T,
+                                                          double* out) {
+  __shared__ double red[NTHREADS / 64];
+  double part = 0.0;
+  for (int k = threadIdx.x; k < g.N; k += NTHREADS)
+    if (mask[k] & TAG_PROBE) part += double(T[k]);
+  double s = block_sum(part, red);
+  if (threadIdx.x == 0) *out = s;
+}
+
 // sum of beta (T - 1) over all nodes: the heat-exchange objective
 // -sum beta (1 - T) of one level
 template <typename R>
@@ -1470,6 +1490,10 @@ void launch_probe_heat(const Geo& g, const uint8_t* mask, const R* ux, const R* 
   probe_heat_kernel<R><<<1, NTHREADS, 0, s>>>(g, mask, ux, T, out);
 }
 template <typename R>
+void launch_probe_T(const Geo& g, const uint8_t* mask, const R* T, double* out, hipStream_t s) {
+  probe_T_kernel<R><<<1, NTHREADS, 0, s>>>(g, mask, T, out);
+}
+template <typename R>
 void launch_source_heat(const Geo& g, const R* beta, const R* T, double* out, hipStream_t s) {
   source_heat_kernel<R><<<1, NTHREADS, 0, s>>>(g, beta, T, out);
 }
@@ -1552,6 +1576,7 @@ void launch_finite_check(const R* a, size_t n, int* flag, hipStream_t s) {
   template void launch_source_coef<R>(const Geo&, const double*, double, double, R*, R*,      \
                                       hipStream_t);                                           \
   template void launch_source_heat<R>(const Geo&, const R*, const R*, double*, hipStream_t);  \
+  template void launch_probe_T<R>(const Geo&, const uint8_t*, const R*, double*, hipStream_t); \
   template void launch_fill_r<R>(R*, size_t, hipStream_t);                                    \
   template void launch_lks_step_batch<R>(const BatchFwd<R>*, const int*, int, int, int, bool, int, \
                                          hipStream_t);                                        \

@@ -546,7 +546,8 @@ __device__ inline void fwd3_out(const Geo3& g, const Fwd3Args<R>& a, unsigned k,
     if constexpr (TH) {
       const R Qn = pick3(ax, Q[0], Q[1], Q[2]);
       if (((m >> 2) & 3) == THERM_DIRICHLET3) T = Tb;
-      else T = (Ts + R(sg) * Qn) / (R(1) + un);
+      // heat-flux face: Tb holds the flux qbar into the domain (0: adiabatic)
+      else T = (Ts + R(sg) * Qn + Tb) / (R(1) + un);
     }
   }
   a.s1[0][k] = d;

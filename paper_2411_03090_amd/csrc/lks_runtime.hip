@@ -56,7 +56,7 @@ struct lks_ctx {
   double rho_out = 1.0;
   std::vector<uint8_t> mask;
   std::vector<double> ubar, Tbar, ufac;
-  int n_in = 0, n_out = 0;
+  int n_in = 0, n_out = 0, n_probe = 0;
   int dim = 2;         // 2: D2Q9, 3: D3Q19
   int spl_f = 1;       // steady sweeps: time steps per launch (1 or 2),
   int spl_a = 1;       // forward and adjoint
@@ -387,8 +387,15 @@ lks_status validate_common(const lks_grid* gr, const lks_phys* ph, const lks_bc*
   if (source && gr->lattice == LKS_D3Q19)
     return fail(nullptr, LKS_E_UNSUPPORTED, "the heat source is D2Q9 only");
   if (bc->objective != LKS_OBJ_PRESSURE_DROP && bc->objective != LKS_OBJ_HEAT &&
-      bc->objective != LKS_OBJ_HEAT_EXCHANGE)
+      bc->objective != LKS_OBJ_HEAT_EXCHANGE && bc->objective != LKS_OBJ_HEAT_SINK)
     return fail(nullptr, LKS_E_INVALID, "unknown objective");
+  if (bc->objective == LKS_OBJ_HEAT_SINK && !ph->thermal)
+    return fail(nullptr, LKS_E_INVALID, "the heat-sink objective needs a thermal problem");
+  if (bc->objective == LKS_OBJ_HEAT_SINK && gr->lattice == LKS_D3Q19)
+    return fail(nullptr, LKS_E_UNSUPPORTED, "the heat-sink objective is D2Q9 only");
+  if (ph->thermal)
+    for (long long k = 0; k < (long long)gr->nx * gr->ny * std::max(gr->nz, 1); ++k)
+      if (!std::isfinite(bc->T_bar[k])) return fail(nullptr, LKS_E_INVALID, "T_bar not finite");
   if (bc->objective == LKS_OBJ_HEAT_EXCHANGE && !source)
     return fail(nullptr, LKS_E_INVALID, "the heat-exchange objective needs the heat source");
   if (bc->objective == LKS_OBJ_HEAT && !ph->thermal)
@@ -446,6 +453,8 @@ lks_status validate(const lks_grid* gr, const lks_phys* ph, const lks_bc* bc) {
     } else if (ring) {
       if (fc != LKS_FLOW_VELOCITY && fc != LKS_FLOW_PRESSURE)
         return fail(nullptr, LKS_E_INVALID, "ring node needs a velocity or pressure class");
+      if (bc->objective == LKS_OBJ_HEAT_SINK && (m & LKS_TAG_PROBE) && tc != 2)
+        return fail(nullptr, LKS_E_INVALID, "heated boundary nodes need the heat-flux class");
       if (ph->thermal && tc != 1 && tc != 2)
         return fail(nullptr, LKS_E_INVALID, "ring node needs a thermal class");
     } else {
@@ -453,8 +462,16 @@ lks_status validate(const lks_grid* gr, const lks_phys* ph, const lks_bc* bc) {
         return fail(nullptr, LKS_E_INVALID, "interior node with a boundary class");
       if (m & (LKS_TAG_J_INLET | LKS_TAG_J_OUTLET))
         return fail(nullptr, LKS_E_INVALID, "pressure-drop tags belong on ring nodes");
+      if (bc->objective == LKS_OBJ_HEAT_SINK && (m & LKS_TAG_PROBE))
+        return fail(nullptr, LKS_E_INVALID, "the heated boundary lies on ring nodes");
     }
     if (tc == 3) return fail(nullptr, LKS_E_INVALID, "unknown thermal class");
+  }
+  if (bc->objective == LKS_OBJ_HEAT_SINK) {
+    if (gr->periodic) return fail(nullptr, LKS_E_INVALID, "the heat-sink objective needs a boundary");
+    int heated = 0;
+    for (int k = 0; k < N; ++k) heated += (bc->node_class[k] & LKS_TAG_PROBE) ? 1 : 0;
+    if (!heated) return fail(nullptr, LKS_E_INVALID, "the heat-sink objective needs heated nodes");
   }
   return LKS_OK;
 }
@@ -753,6 +770,8 @@ struct Run {
         lks::launch_pressure_drop<R>(g, c->d_mask, cur_field(0), c->scal, c->stream);
     } else if (c->objective == LKS_OBJ_HEAT_EXCHANGE) {
       lks::launch_source_heat<R>(g, rp<R>(c->beta), cur_field(3), c->scal, c->stream);
+    } else if (c->objective == LKS_OBJ_HEAT_SINK) {
+      lks::launch_probe_T<R>(g, c->d_mask, cur_field(3), c->scal, c->stream);
     } else {
       probe_heat_steady();
     }
@@ -771,7 +790,17 @@ struct Run {
   }
 
   // one ALKS step with the state st (drho, u..., T) of the destination level
-  void adj_step(R* const st[5], double sdp, double sh, double* sens, int mode, double ss = 0.0) {
+  // seeds of one level for objective weight w: pressure drop, probe heat,
+  // heat exchange, heated boundary (per node)
+  void seeds(double w, double* sdp, double* sh, double* ss, double* sbt) const {
+    *sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? w : 0.0;
+    *sh = c->objective == LKS_OBJ_HEAT ? w : 0.0;
+    *ss = c->objective == LKS_OBJ_HEAT_EXCHANGE ? w : 0.0;
+    *sbt = c->objective == LKS_OBJ_HEAT_SINK ? w / std::max(c->n_probe, 1) : 0.0;
+  }
+
+  void adj_step(R* const st[5], double sdp, double sh, double* sens, int mode, double ss = 0.0,
+                double sbt = 0.0) {
     const int i0 = c->acur, i1 = c->acur ^ 1;
     if (c->dim == 3) {
       lks::Adj3Args<R> a;
@@ -801,6 +830,7 @@ struct Run {
     }
     lks::AdjArgs<R> a = adj_args(st, sdp, sh, sens, mode);
     a.seed_src = ss;
+    a.seed_bt = sbt;
     lks::launch_alks_step<R>(g, a, c->stream);
     c->acur = i1;
   }
@@ -840,9 +870,8 @@ struct Run {
       c->acur = 0;
       zero_adjoint(0);
     }
-    const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? seed : 0.0;
-    const double sh = c->objective == LKS_OBJ_HEAT ? seed : 0.0;
-    const double ss = c->objective == LKS_OBJ_HEAT_EXCHANGE ? seed : 0.0;
+    double sdp, sh, ss, sbt;
+    seeds(seed, &sdp, &sh, &ss, &sbt);
     R* st[5] = {};
     for (int f = 0; f < nf; ++f) st[f] = cur_field(f);
     if (!c->phys.thermal) st[nf - 1] = nullptr;
@@ -859,7 +888,7 @@ struct Run {
     }
     for (; n < steps; ++n) {
       const bool last = n == steps - 1;
-      adj_step(st, sdp, sh, last ? dJ : nullptr, 2, ss);
+      adj_step(st, sdp, sh, last ? dJ : nullptr, 2, ss, sbt);
     }
   }
 
@@ -884,11 +913,9 @@ struct Run {
       }
       R* const* lv = x.src >= 0 ? src : wk;
       const int n = x.from;
-      const double w = n >= 1 ? seed / Nst : 0.0;
-      const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? w : 0.0;
-      const double sh = c->objective == LKS_OBJ_HEAT ? w : 0.0;
-      const double ss = c->objective == LKS_OBJ_HEAT_EXCHANGE ? w : 0.0;
-      adj_step(lv, sdp, sh, (n == 0 && c->adj_exact) ? nullptr : dJ, 1, ss);
+      double sdp, sh, ss, sbt;
+      seeds(n >= 1 ? seed / Nst : 0.0, &sdp, &sh, &ss, &sbt);
+      adj_step(lv, sdp, sh, (n == 0 && c->adj_exact) ? nullptr : dJ, 1, ss, sbt);
     }
   }
 
@@ -916,13 +943,11 @@ struct Run {
       for (int n = top; n >= b; --n) {
         R* lv[5];
         level(n, b, lv);
-        const double w = n >= 1 ? seed / Nst : 0.0;
-        const double sdp = c->objective == LKS_OBJ_PRESSURE_DROP ? w : 0.0;
-        const double sh = c->objective == LKS_OBJ_HEAT ? w : 0.0;
-        const double ss = c->objective == LKS_OBJ_HEAT_EXCHANGE ? w : 0.0;
+        double sdp, sh, ss, sbt;
+        seeds(n >= 1 ? seed / Nst : 0.0, &sdp, &sh, &ss, &sbt);
         // the exact mode sums the levels the steps produce; level 0 is the
         // initial state, which does not depend on gamma
-        adj_step(lv, sdp, sh, (n == 0 && c->adj_exact) ? nullptr : dJ, 1, ss);
+        adj_step(lv, sdp, sh, (n == 0 && c->adj_exact) ? nullptr : dJ, 1, ss, sbt);
       }
     }
   }
@@ -1022,6 +1047,7 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
   if (bc->u_factor) c->ufac.assign(bc->u_factor, bc->u_factor + bc->n_factor);
   else c->ufac.assign(1, 1.0);
   for (int k = 0; k < N; ++k) {
+    if (c->mask[k] & LKS_TAG_PROBE) ++c->n_probe;
     if (c->mask[k] & LKS_TAG_J_INLET) ++c->n_in;
     if (c->mask[k] & LKS_TAG_J_OUTLET) ++c->n_out;
   }
@@ -1231,7 +1257,8 @@ lks_status lks_objective(lks_ctx* c, double* J) {
     else
       *J = (s + double(c->n_in - c->n_out)) / 3.0;
   } else {
-    *J = c->mode == LKS_UNSTEADY ? s / c->n_steps : s;
+    const double per = c->objective == LKS_OBJ_HEAT_SINK ? double(std::max(c->n_probe, 1)) : 1.0;
+    *J = (c->mode == LKS_UNSTEADY ? s / c->n_steps : s) / per;
   }
   return LKS_OK;
 }

@@ -41,7 +41,7 @@ LKS_E_DIVERGED = 5
 LKS_E_UNSUPPORTED = 6
 LKS_D2Q9, LKS_D3Q19 = 0, 1
 LKS_FP64, LKS_FP32DEV = 0, 1
-LKS_OBJ_PRESSURE_DROP, LKS_OBJ_HEAT, LKS_OBJ_HEAT_EXCHANGE = 0, 1, 2
+LKS_OBJ_PRESSURE_DROP, LKS_OBJ_HEAT, LKS_OBJ_HEAT_EXCHANGE, LKS_OBJ_HEAT_SINK = 0, 1, 2, 3
 LKS_STEADY, LKS_UNSTEADY = 0, 1
 LKS_ADJ_PAPER, LKS_ADJ_EXACT = 0, 1
 LKS_CKPT_AUTO, LKS_CKPT_TWO_LEVEL, LKS_CKPT_BINOMIAL = 0, 1, 2
