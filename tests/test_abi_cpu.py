@@ -131,6 +131,38 @@ def test_heat_source_validation_and_workspace():
     assert e.value.status == lks.LKS_E_UNSUPPORTED
 
 
+def test_heat_sink_objective_validation():
+    _create(W.heat_sink(n=16, n_steps=10))
+    w = W.heat_sink(n=16, n_steps=10)
+    w.mask = w.mask.copy()
+    w.mask[5, 5] |= W.TAG_PROBE                      # interior heated node
+    with pytest.raises(lks.LKSError) as e:
+        _create(w)
+    assert e.value.status == lks.LKS_E_INVALID
+    w = W.heat_sink(n=16, n_steps=10)
+    w.mask = w.mask.copy()
+    w.mask[3, 0] |= W.TAG_PROBE                      # prescribed-temperature wall
+    with pytest.raises(lks.LKSError) as e:
+        _create(w)
+    assert e.value.status == lks.LKS_E_INVALID
+    w = W.heat_sink(n=16, n_steps=10)
+    w.mask = w.mask & ~np.uint8(W.TAG_PROBE)         # no heated node
+    with pytest.raises(lks.LKSError) as e:
+        _create(w)
+    assert e.value.status == lks.LKS_E_INVALID
+    w = W.heat_sink(n=16, n_steps=10)
+    w.Tbar = w.Tbar.copy()
+    w.Tbar[0, 3] = np.inf
+    with pytest.raises(lks.LKSError) as e:
+        _create(w)
+    assert e.value.status == lks.LKS_E_INVALID
+    w3 = W.heated_block_duct(16, 8, 8, Re=20.0, n_steps=10)
+    w3.objective = W.OBJ_HEAT_SINK
+    with pytest.raises(lks.LKSError) as e:
+        _create(w3)
+    assert e.value.status == lks.LKS_E_UNSUPPORTED
+
+
 def test_adjoint_mode_setter_validates():
     c = _create(W.steady_channel_uniform(16, 12, Re=10, seed=0))
     c.set_adjoint_mode("exact")
