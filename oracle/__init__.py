@@ -319,8 +319,11 @@ def adjoint_steady(pb: Problem, gamma, state: State, n_adj, seed=1.0):
 def adjoint_unsteady(pb: Problem, gamma, traj, seed=1.0):
     """Reverse sweep over a stored trajectory of N+1 levels; the objective is
     the average over levels 1..N, so the seed at level n >= 1 is seed/N.
-    The paper's sensitivity sums levels 0..N; the exact mode sums 1..N, the
-    levels the steps produce (the initial state does not depend on gamma)."""
+    The paper's sensitivity sums levels 0..N. The exact mode pairs each term
+    with the step where gamma acts: the Brinkman and source terms with the
+    levels the steps produce (1..N; the initial state does not depend on
+    gamma), the conductivity term B' grad T . q~ with the levels whose
+    equilibria the steps use (0..N-1; at level N q~ = 0)."""
     wl = pb.wl
     N = len(traj) - 1
     alpha, dalpha, B, dB = coefficients(pb, gamma)
@@ -336,6 +339,9 @@ def adjoint_unsteady(pb: Problem, gamma, traj, seed=1.0):
             sens_add(pb, alpha, dalpha, dB, traj[n], adj, 1.0, sens)
             if beta is not None:
                 source_sens_add(pb, alpha, B, beta, dbeta, traj[n], adj, ss, sens)
+        else:
+            # exact mode, level 0: the conductivity term only
+            sens_add(pb, alpha, np.zeros(pb.N), dB, traj[n], adj, 1.0, sens)
     return adj, sens
 
 

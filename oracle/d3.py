@@ -198,7 +198,9 @@ def adjoint_steady(pb: Problem3, gamma, state: State3, n_adj, seed=1.0):
 
 def adjoint_unsteady(pb: Problem3, gamma, traj, seed=1.0):
     """Reverse sweep over a stored trajectory of N+1 levels; the seed at
-    level n >= 1 is seed/N (time average over levels 1..N)."""
+    level n >= 1 is seed/N (time average over levels 1..N). In exact mode the
+    Brinkman term sums levels 1..N and the conductivity term levels 0..N-1
+    (see oracle.adjoint_unsteady)."""
     wl = pb.wl
     N = len(traj) - 1
     alpha, dalpha, B, dB = coefficients(pb, gamma)
@@ -209,9 +211,10 @@ def adjoint_unsteady(pb: Problem3, gamma, traj, seed=1.0):
         sdp = w if wl.objective == OBJ_PRESSURE_DROP else 0.0
         sh = w if wl.objective == OBJ_HEAT else 0.0
         adj = alks_step(pb, alpha, B, traj[min(n + 1, N)], traj[n], adj, sdp, sh)
-        # the exact mode sums the levels the steps produce (1..N)
         if n >= 1 or getattr(wl, "adjoint_mode", "paper") != "exact":
             sens_add(pb, alpha, dalpha, dB, traj[n], adj, 1.0, sens)
+        else:
+            sens_add(pb, alpha, np.zeros(pb.N), dB, traj[n], adj, 1.0, sens)
     return adj, sens
 
 

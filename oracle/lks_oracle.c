@@ -443,13 +443,26 @@ static void adj_V(const orc_problem *P, int i, int j, const double *ux,
 /* With alpha given (exact mode), V is divided by 1 + alpha at its node: the
  * transpose of u = U* / (1 + alpha) applied where the velocity was formed.
  * With beta given as well (heat source), Theta is divided by 1 + beta at its
- * node in the same way, the transpose of T = (T* + beta) / (1 + beta). */
+ * node in the same way, the transpose of T = (T* + beta) / (1 + beta).
+ * The exact mode (the problem's flag, with or without alpha) also takes the
+ * transpose of the forward term B c_i.grad_h T:
+ * -div_h (B q~), the difference stencil applied to the product, in place of
+ * the product rule -B div q~ - grad B . q~ of eq:ageq (the two agree for
+ * uniform B; the transpose is exact on periodic grids). */
 void orc_adjoint_equilibrium(const orc_problem *P, const double *B,
                              const double *ux, const double *uy,
                              const double *const *adj, double *Vx, double *Vy,
                              double *Theta, const double *alpha,
                              const double *beta) {
-  const int nx = P->nx, ny = P->ny;
+  const int nx = P->nx, ny = P->ny, N = nx * ny;
+  double *Bq = NULL;
+  if (Theta && P->adj_exact) {
+    Bq = malloc(2 * (size_t)N * sizeof(double));
+    for (int k = 0; k < N; ++k) {
+      Bq[k] = B[k] * adj[A_QX][k];
+      Bq[N + k] = B[k] * adj[A_QY][k];
+    }
+  }
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j) {
     for (int i = 0; i < nx; ++i) {
@@ -464,8 +477,12 @@ void orc_adjoint_equilibrium(const orc_problem *P, const double *B,
         double qx = adj[A_QX][k], qy = adj[A_QY][k];
         double divq = ddx(P, adj[A_QX], i, j, 0) + ddx(P, adj[A_QY], i, j, 1);
         double dBx = ddx(P, B, i, j, 0), dBy = ddx(P, B, i, j, 1);
-        Theta[k] = adj[A_T][k] + 3.0 * (qx * u[0] + qy * u[1]) - B[k] * divq -
-                   (dBx * qx + dBy * qy);
+        if (Bq)
+          Theta[k] = adj[A_T][k] + 3.0 * (qx * u[0] + qy * u[1]) -
+                     (ddx(P, Bq, i, j, 0) + ddx(P, Bq + N, i, j, 1));
+        else
+          Theta[k] = adj[A_T][k] + 3.0 * (qx * u[0] + qy * u[1]) - B[k] * divq -
+                     (dBx * qx + dBy * qy);
         /* exact mode: the propagated Theta also carries the dependence of
          * the new velocity on the new temperature through G, whose adjoint
          * is g beta . V / (1 + alpha) at interior nodes */
@@ -475,6 +492,7 @@ void orc_adjoint_equilibrium(const orc_problem *P, const double *B,
       }
     }
   }
+  free(Bq);
 }
 
 /* ------------------------------------------------------------------ */

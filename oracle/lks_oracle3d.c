@@ -349,11 +349,19 @@ static void adj_V3(const orc3_problem *P, long k, const int x[3], const double *
   }
 }
 
-/* With alpha given (exact mode), V is divided by 1 + alpha at its node. */
+/* With alpha given (exact mode), V is divided by 1 + alpha at its node. In
+ * exact mode (the problem's flag) the thermal term is the transpose
+ * -div_h (B q~) of the forward B c.grad_h T (see the D2Q9 oracle). */
 void orc3_adjoint_equilibrium(const orc3_problem *P, const double *B, const double *u,
                               const double *const *adj, double *V, double *Theta,
                               const double *alpha) {
   const long N = (long)P->nx * P->ny * P->nz;
+  double *Bq = NULL;
+  if (Theta && P->adj_exact) {
+    Bq = malloc(3 * (size_t)N * sizeof(double));
+    for (int a = 0; a < 3; ++a)
+      for (long k = 0; k < N; ++k) Bq[a * N + k] = B[k] * adj[Q3 + a][k];
+  }
 #pragma omp parallel for schedule(static)
   for (long k = 0; k < N; ++k) {
     int x[3];
@@ -364,15 +372,18 @@ void orc3_adjoint_equilibrium(const orc3_problem *P, const double *B, const doub
     const double sc = alpha ? 1.0 / (1.0 + alpha[k]) : 1.0;
     for (int a = 0; a < 3; ++a) V[a * N + k] = Vk[a] * sc;
     if (Theta) {
-      double qu = 0, divq = 0, gbq = 0;
+      double qu = 0, divq = 0, gbq = 0, dbq = 0;
       for (int a = 0; a < 3; ++a) {
         qu += adj[Q3 + a][k] * uk[a];
         divq += dd3(P, adj[Q3 + a], x, a);
         gbq += dd3(P, B, x, a) * adj[Q3 + a][k];
+        if (Bq) dbq += dd3(P, Bq + a * N, x, a);
       }
-      Theta[k] = adj[T3][k] + 3.0 * qu - B[k] * divq - gbq;
+      Theta[k] = Bq ? adj[T3][k] + 3.0 * qu - dbq
+                    : adj[T3][k] + 3.0 * qu - B[k] * divq - gbq;
     }
   }
+  free(Bq);
 }
 
 /* least squares min ||K x + b|| by the normal equations (Gaussian
