@@ -133,6 +133,7 @@ struct AdjArgs {
   const R* dbeta = nullptr;  // beta'(gamma)
   double seed_src = 0.0;     // weight of the heat-exchange objective
   double seed_bt = 0.0;      // dJ/dT at the heated nodes of the heat-sink objective
+  int sens_b_only = 0;       // exact mode, level 0: the conductivity term only
 };
 
 // one design of a batch: geometry and the arguments of both ping-pong parities
@@ -222,6 +223,7 @@ struct Adj3Args {
   int exact;           // 1: exact discrete adjoint of the Brinkman step
   double seed_dp;
   double seed_heat;
+  int sens_b_only = 0;  // exact mode, level 0: the conductivity term only
 };
 
 int blocks3(int N);  // blocks of a node-parallel 3D launch (multiple of 8)

@@ -278,6 +278,17 @@ __device__ inline R lds_dx(const R* s, int p, int step, int c, int n, int period
   else return lds_d(s, p, step, c, n, periodic);
 }
 
+// the same difference of the product a*b of two LDS fields with their own
+// positions and row steps
+template <bool INT, typename R>
+__device__ inline R lds_dxp(const R* a, int pa, int sa, const R* b, int pb, int sb, int c, int n,
+                            int periodic) {
+  auto at = [&](int o) { return a[pa + o * sa] * b[pb + o * sb]; };
+  if (INT || periodic || (c > 0 && c < n - 1)) return R(0.5) * (at(1) - at(-1));
+  if (c == 0) return R(0.5) * (R(-3) * at(0) + R(4) * at(1) - at(2));
+  return R(0.5) * (R(3) * at(0) - R(4) * at(-1) + at(-2));
+}
+
 // ---------------------------------------------------------------------------
 // LKS step
 // ---------------------------------------------------------------------------
@@ -829,11 +840,18 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
     Vy *= s;
   }
   if constexpr (TH) {
-    const R divq = ldx(7) + ldy(8);
-    const R Bk = lB[pr];
-    const R dBx = lds_dx<INT>(lB, pr, 1, i, g.nx, g.periodic);
-    const R dBy = lds_dx<INT>(lB, pr, PR, j, g.ny, g.periodic);
-    Th = Tt + R(3) * (qx * ux + qy * uy) - Bk * divq - (dBx * qx + dBy * qy);
+    if (a.exact) {
+      // exact: the transpose of the forward B c.grad_h T, -div_h (B q~)
+      const R dbx = lds_dxp<INT>(lB, pr, 1, lm + 7 * SM, pm, 1, i, g.nx, g.periodic);
+      const R dby = lds_dxp<INT>(lB, pr, PR, lm + 8 * SM, pm, PM, j, g.ny, g.periodic);
+      Th = Tt + R(3) * (qx * ux + qy * uy) - (dbx + dby);
+    } else {
+      const R divq = ldx(7) + ldy(8);
+      const R Bk = lB[pr];
+      const R dBx = lds_dx<INT>(lB, pr, 1, i, g.nx, g.periodic);
+      const R dBy = lds_dx<INT>(lB, pr, PR, j, g.ny, g.periodic);
+      Th = Tt + R(3) * (qx * ux + qy * uy) - Bk * divq - (dBx * qx + dBy * qy);
+    }
     // exact: the propagated Theta carries the force's dependence on the new
     // temperature, g beta . V / (1 + alpha), at interior nodes
     if (!ring && a.exact) Th += R(g.gbx) * Vx + R(g.gby) * Vy;
@@ -844,14 +862,16 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
   if (want_sens) {
     double v = 0.0;
     if (!ring) {
-      v = double(a.dA3[k]) * pair;
+      // exact mode at level 0 keeps only the conductivity term: alpha and
+      // beta act on the levels the steps produce, B on the equilibria used
+      v = a.sens_b_only ? 0.0 : double(a.dA3[k]) * pair;
       if constexpr (TH) {
         const double dTx = double(lds_dx<INT>(lTn, pr, 1, i, g.nx, g.periodic));
         const double dTy = double(lds_dx<INT>(lTn, pr, PR, j, g.ny, g.periodic));
         v -= double(a.dB[k]) * (dTx * double(qx) + dTy * double(qy));
         // heat source and heat-exchange objective: beta' (T - 1)(w_J + T~),
         // with the propagated Theta in exact mode
-        if (a.beta)
+        if (a.beta && !a.sens_b_only)
           v += double(a.dbeta[k]) * (double(lTn[pr]) - 1.0) *
                (a.seed_src + double(a.exact ? Th : Tt));
       }

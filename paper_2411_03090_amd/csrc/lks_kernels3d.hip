@@ -339,6 +339,14 @@ __device__ inline R d1(const R* f, int i, int st, int e) {
   if (e < 0) return R(0.5) * (R(-3) * f[i] + R(4) * f[i + st] - f[i + 2 * st]);
   return R(0.5) * (R(3) * f[i] - R(4) * f[i - st] + f[i - 2 * st]);
 }
+// d1 of the product f * h
+template <typename R>
+__device__ inline R d1p(const R* f, const R* h, int i, int st, int e) {
+  auto at = [&](int o) { return f[i + o * st] * h[i + o * st]; };
+  if (e == 0) return R(0.5) * (at(1) - at(-1));
+  if (e < 0) return R(0.5) * (R(-3) * at(0) + R(4) * at(1) - at(2));
+  return R(0.5) * (R(3) * at(0) - R(4) * at(-1) + at(-2));
+}
 
 // ---------------------------------------------------------------------------
 // LKS step
@@ -1044,15 +1052,25 @@ __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
         qv[1] = E[TH ? 6 : 0][ci];
         qv[2] = zc[3];
         const R qu = qv[0] * cu.u[0] + qv[1] * cu.u[1] + qv[2] * cu.u[2];
-        const R divq = d1(E[TH ? 5 : 0], ci, 1, n0.ex) + d1(E[TH ? 6 : 0], ci, CXN, n0.ey) + zd[3];
         const R* Bp = E[TH ? 8 : 0];
-        const R gbq = d1(Bp, ci, 1, n0.ex) * qv[0] + d1(Bp, ci, CXN, n0.ey) * qv[1] + zd[5] * qv[2];
-        a.p1[4][k] = cu.Tt + R(3) * qu - Bp[ci] * divq - gbq;
+        if (a.exact) {
+          // exact: the transpose of the forward B c.grad_h T, -div_h (B q~)
+          const R zbq = dz3(ez, zc[3] * zc[5], zm1[3] * zm1[5], zn[3] * zn[5], z2[3] * z2[5]);
+          const R dbq = d1p(Bp, E[TH ? 5 : 0], ci, 1, n0.ex) +
+                        d1p(Bp, E[TH ? 6 : 0], ci, CXN, n0.ey) + zbq;
+          a.p1[4][k] = cu.Tt + R(3) * qu - dbq;
+        } else {
+          const R divq =
+              d1(E[TH ? 5 : 0], ci, 1, n0.ex) + d1(E[TH ? 6 : 0], ci, CXN, n0.ey) + zd[3];
+          const R gbq =
+              d1(Bp, ci, 1, n0.ex) * qv[0] + d1(Bp, ci, CXN, n0.ey) * qv[1] + zd[5] * qv[2];
+          a.p1[4][k] = cu.Tt + R(3) * qu - Bp[ci] * divq - gbq;
+        }
       }
       if (a.sens_mode) {
         double sv = 0.0;
         if (!n0.ex && !n0.ey && !ez && !(cu.mk & TAG_SOLID3)) {
-          sv = double(cu.dA) * pair;
+          sv = a.sens_b_only ? 0.0 : double(cu.dA) * pair;
           if constexpr (TH) {
             const R* Tp = E[TH ? 7 : 0];
             const R gt[3] = {d1(Tp, ci, 1, n0.ex), d1(Tp, ci, CXN, n0.ey), zd[4]};

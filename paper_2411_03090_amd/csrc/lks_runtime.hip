@@ -799,8 +799,10 @@ struct Run {
     *sbt = c->objective == LKS_OBJ_HEAT_SINK ? w / std::max(c->n_probe, 1) : 0.0;
   }
 
+  // b_only: exact mode at level 0, where the sensitivity keeps the
+  // conductivity term only
   void adj_step(R* const st[5], double sdp, double sh, double* sens, int mode, double ss = 0.0,
-                double sbt = 0.0) {
+                double sbt = 0.0, bool b_only = false) {
     const int i0 = c->acur, i1 = c->acur ^ 1;
     if (c->dim == 3) {
       lks::Adj3Args<R> a;
@@ -824,6 +826,7 @@ struct Run {
       a.exact = c->adj_exact;
       a.seed_dp = sdp;
       a.seed_heat = sh;
+      a.sens_b_only = b_only ? 1 : 0;
       lks::launch_alks3_step<R>(c->geo3, a, c->stream);
       c->acur = i1;
       return;
@@ -831,6 +834,7 @@ struct Run {
     lks::AdjArgs<R> a = adj_args(st, sdp, sh, sens, mode);
     a.seed_src = ss;
     a.seed_bt = sbt;
+    a.sens_b_only = b_only ? 1 : 0;
     lks::launch_alks_step<R>(g, a, c->stream);
     c->acur = i1;
   }
@@ -915,7 +919,7 @@ struct Run {
       const int n = x.from;
       double sdp, sh, ss, sbt;
       seeds(n >= 1 ? seed / Nst : 0.0, &sdp, &sh, &ss, &sbt);
-      adj_step(lv, sdp, sh, (n == 0 && c->adj_exact) ? nullptr : dJ, 1, ss, sbt);
+      adj_step(lv, sdp, sh, dJ, 1, ss, sbt, n == 0 && c->adj_exact);
     }
   }
 
@@ -945,9 +949,10 @@ struct Run {
         level(n, b, lv);
         double sdp, sh, ss, sbt;
         seeds(n >= 1 ? seed / Nst : 0.0, &sdp, &sh, &ss, &sbt);
-        // the exact mode sums the levels the steps produce; level 0 is the
-        // initial state, which does not depend on gamma
-        adj_step(lv, sdp, sh, (n == 0 && c->adj_exact) ? nullptr : dJ, 1, ss, sbt);
+        // the exact mode pairs the Brinkman and source terms with the levels
+        // the steps produce (1..N; the initial state does not depend on
+        // gamma) and the conductivity term with the equilibria the steps use
+        adj_step(lv, sdp, sh, dJ, 1, ss, sbt, n == 0 && c->adj_exact);
       }
     }
   }

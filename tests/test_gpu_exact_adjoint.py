@@ -48,9 +48,9 @@ def _thermal_channel():
     return _exact(wl)
 
 
-def _periodic_thermal():
+def _periodic_thermal(ks=1.0):
     wl = W.periodic_box(40, 21, nu=0.08, thermal=True)
-    wl.alpha_max, wl.Ks_over_Kf, wl.objective = 0.7, 1.0, W.OBJ_HEAT
+    wl.alpha_max, wl.Ks_over_Kf, wl.objective = 0.7, ks, W.OBJ_HEAT
     wl.gamma = np.clip(W.gamma_grf(40, 21, 2.0, 5), 0.05, 1.0)
     wl.mask = wl.mask.copy()
     wl.mask[2:5, 3] |= W.TAG_PROBE
@@ -61,6 +61,8 @@ CASES2 = {
     "channel_70x37": lambda: _exact(W.steady_channel_uniform(70, 37, Re=10.0, seed=1)),
     "thermal_96x21": _thermal_channel,
     "periodic_thermal_40x21": _periodic_thermal,
+    # conductivity contrast: the transposed -div_h (B q~) of the exact mode
+    "periodic_contrast_40x21": lambda: _periodic_thermal(4.0),
 }
 
 
@@ -146,10 +148,12 @@ def test_exact_unsteady_thermal_gradient_checkpointed(prec, tol):
     assert rel(so_paper, so) > 10 * tol
 
 
+@pytest.mark.parametrize("ks", [1.0, 2.0])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_exact_single_adjoint_step_3d(prec):
-    say(f"[gpu] exact-mode 3D adjoint step duct 18x10x12 {prec}")
+def test_exact_single_adjoint_step_3d(prec, ks):
+    say(f"[gpu] exact-mode 3D adjoint step duct 18x10x12 {prec} Ks/Kf={ks}")
     wl = _exact(W.heated_block_duct(18, 10, 12, Re=20.0, Pr=0.71, sigma=2.0, seed=0, n_steps=1))
+    wl.Ks_over_Kf = ks
     wl.mode, wl.ufac = W.MODE_STEADY, np.ones(2)
     rng = np.random.default_rng(12)
     pb = O3.Problem3(wl)
@@ -187,9 +191,11 @@ def test_exact_single_adjoint_step_3d(prec):
     assert rel(dJ.cpu().numpy(), sens) < tol
 
 
-def test_exact_unsteady_duct_gradient_3d():
-    say("[gpu] exact mode 3D duct 18x10x12 60 steps fp64")
+@pytest.mark.parametrize("ks", [1.0, 2.0])
+def test_exact_unsteady_duct_gradient_3d(ks):
+    say(f"[gpu] exact mode 3D duct 18x10x12 60 steps fp64 Ks/Kf={ks}")
     wl = _exact(W.heated_block_duct(18, 10, 12, Re=20.0, Pr=0.71, sigma=2.0, seed=0, n_steps=60))
+    wl.Ks_over_Kf = ks
     pb = O3.Problem3(wl)
     s, Jo, traj = O3.forward(pb, wl.gamma, wl.n_fwd, store=True)
     _, so = O3.adjoint_unsteady(pb, wl.gamma, traj, 1.0)
