@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--no-unsteady", action="store_true")
     p.add_argument("--unsteady-steps", type=int, default=20000)
     p.add_argument("--no-exchanger", action="store_true")
+    p.add_argument("--no-sink", action="store_true")
+    p.add_argument("--sink-steps", type=int, default=20000)
     p.add_argument("--exchanger-steps", type=int, default=20000)
     p.add_argument("--no-3d", action="store_true")
     p.add_argument("--steps-3d", type=int, default=5000)
@@ -128,6 +130,7 @@ def main():
     batched = None if args.no_batch else batched_bench(args, dev)
     unsteady = None if args.no_unsteady else unsteady_bench(args, dev)
     exchanger = None if args.no_exchanger else exchanger_bench(args, dev)
+    sink = None if args.no_sink else sink_bench(args, dev)
     duct = None if args.no_3d else duct3d_bench(args, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_sample_steps)
 
@@ -161,6 +164,7 @@ def main():
         "batched_64_designs": batched,
         "unsteady_thermal_1024x512": unsteady,
         "heat_exchanger_201x201": exchanger,
+        "heat_sink_161x161": sink,
         "duct3d_256x128x128": duct,
     }
     print(json.dumps(line), flush=True)
@@ -334,6 +338,48 @@ def exchanger_bench(args, dev):
     res["fp32_vs_fp64_rel_error"] = {"J": abs(res["fp32"]["J"] - J64) / abs(J64),
                                      "dJdgamma_l2": rel(outs["fp32"], outs["fp64"])}
     res.update({"nodes": nodes, "n_fwd": n, "n_adj": n, "beta_max": wl.beta_max})
+    torch.cuda.empty_cache()
+    return res
+
+
+def sink_bench(args, dev):
+    """Transient natural-convection heat sink 161x161 (Ra = 2e5, Pr = 6,
+    K_s = 10 K_f, heat flux 0.01 on the heated boundary), mean heated
+    temperature averaged over n steps, whole trajectory kept; the adjoint in
+    the exact mode, whose transposed conductivity term stays bounded at this
+    contrast (the paper's form is reported beside it)."""
+    import numpy as np
+    import torch
+    from paper_2411_03090_amd import lks, workloads as W
+    n = args.sink_steps
+    wl = W.heat_sink(n=161, n_steps=n)
+    g = torch.tensor(wl.gamma.reshape(-1), dtype=torch.float64, device=dev)
+    nodes = wl.nx * wl.ny
+    res, outs = {}, {}
+    for prec, mode in (("fp32", "exact"), ("fp64", "exact"), ("fp32", "paper")):
+        wl.adjoint_mode = mode
+        c = lks.LKS(wl, precision=prec, device=dev)
+        out = torch.empty_like(g)
+        torch.cuda.synchronize()
+        e0 = ev()
+        c.forward(g)
+        J = c.objective()
+        c.backward(1.0, out)
+        e1 = ev()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        o = out.cpu().numpy()
+        key = prec if mode == "exact" else "fp32_paper_mode"
+        res[key] = {"ms_per_gradient": ms, "mlups": nodes * 2 * n / (ms * 1e-3) / 1e6,
+                    "gradients_per_s": 1e3 / ms, "J": J,
+                    "dJdgamma_finite": bool(np.isfinite(o).all()),
+                    "dJdgamma_max_abs": float(np.abs(o).max()) if np.isfinite(o).all() else None}
+        outs[key] = o
+        del c
+    J64 = res["fp64"]["J"]
+    res["fp32_vs_fp64_rel_error"] = {"J": abs(res["fp32"]["J"] - J64) / abs(J64),
+                                     "dJdgamma_l2": rel(outs["fp32"], outs["fp64"])}
+    res.update({"nodes": nodes, "steps": n, "adjoint_mode": "exact"})
     torch.cuda.empty_cache()
     return res
 
