@@ -300,7 +300,10 @@ def unsteady_bench(args, dev):
     g = torch.tensor(wl.gamma.reshape(-1), dtype=torch.float64, device=dev)
     c32 = lks.LKS(wl, precision="fp32", mem_budget=4 * 2 ** 30, device=dev)
     c64 = lks.LKS(wl, precision="fp64", mem_budget=8 * 2 ** 30, device=dev)
+    for c in (c32, c64):
+        c.autotune(g, 100)
     res, _ = _checkpointed(c32, c64, g, wl.nx * wl.ny, n)
+    res["tile_rows"] = {"fp32": c32.launch_shape()[0], "fp64": c64.launch_shape()[0]}
     res.update({"nodes": wl.nx * wl.ny, "steps": n, "budget_GiB": {"fp32": 4, "fp64": 8}})
     del c32, c64
     torch.cuda.empty_cache()
@@ -320,6 +323,7 @@ def exchanger_bench(args, dev):
     res, outs = {}, {}
     for prec in ("fp32", "fp64"):
         c = lks.LKS(wl, precision=prec, device=dev)
+        c.autotune(g, 100)
         out = torch.empty_like(g)
         c.forward(g, 200)                                   # warm-up
         torch.cuda.synchronize()
@@ -359,6 +363,7 @@ def sink_bench(args, dev):
     for prec, mode in (("fp32", "exact"), ("fp64", "exact"), ("fp32", "paper")):
         wl.adjoint_mode = mode
         c = lks.LKS(wl, precision=prec, device=dev)
+        c.autotune(g, 100)
         out = torch.empty_like(g)
         torch.cuda.synchronize()
         e0 = ev()

@@ -1062,7 +1062,9 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
   g.N = N;
   g.periodic = grid->periodic ? 1 : 0;
   g.thermal = phys->thermal ? 1 : 0;
-  set_tile_rows(g, 8);
+  // thermal tiles hold twice the LDS arrays; 64 x 4 tiles keep more blocks
+  // resident per CU (the autotuner may still choose another height)
+  set_tile_rows(g, phys->thermal ? 4 : 8);
   g.A = 4.5 * (1.0 / 6.0 - phys->nu);
   const double Kf = phys->thermal ? phys->nu / phys->Pr : 0.0;
   g.Bf = 3.0 * (1.0 / 6.0 - Kf);
