@@ -212,6 +212,13 @@ lks_status lks_objective(lks_ctx *ctx, double *J_host);
  * sensitivity over levels. Returns LKS_E_STATE before a forward run. */
 lks_status alks_backward(lks_ctx *ctx, double J_seed, int adj_steps, double *dJdgamma_dev);
 
+/* Synchronises the stream and reports LKS_E_DIVERGED when the last forward
+ * state or the sensitivity of the last adjoint sweep holds a non-finite value
+ * (the paper's thermal adjoint can grow without bound for a large
+ * conductivity contrast, Sec. 2.5 eq:ageq; the exact adjoint mode does not),
+ * LKS_E_STATE before an adjoint sweep, LKS_OK otherwise. */
+lks_status lks_gradient_status(lks_ctx *ctx);
+
 /* Continue the steady adjoint by `steps` ALKS steps from its current state
  * (no reset), with the state frozen at the current forward level; writes the
  * sensitivity of the final level when dJdgamma_dev is not NULL. */

@@ -293,6 +293,9 @@ template <typename R>
 void launch_pressure_drop_batch(const BatchFwd<R>* d, int nd, int parity, double* out,
                                 hipStream_t s);
 void launch_sum(const double* v, int n, double* out, hipStream_t s);
+// zero one device flag with a kernel (safe inside a captured graph;
+// lks_runtime.hip)
+void launch_clear_flag(int* flag, hipStream_t s);
 void launch_fill(double* p, size_t n, double v, hipStream_t s);
 template <typename R>
 void launch_fill_r(R* p, size_t n, hipStream_t s);

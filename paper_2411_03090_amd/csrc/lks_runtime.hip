@@ -18,6 +18,13 @@
 
 using lks::Geo;
 
+namespace lks {
+__global__ void clear_flag_kernel(int* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+}
+void launch_clear_flag(int* flag, hipStream_t s) { clear_flag_kernel<<<1, 64, 0, s>>>(flag); }
+}  // namespace lks
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -1217,7 +1224,10 @@ static lks_status forward_impl(lks_ctx* c, const double* gamma, int steps, bool 
   } else if (!reset && !c->have_forward) {
     return fail(c, LKS_E_STATE, "advance before forward");
   }
-  if (reset) c->last_level = 0;
+  if (reset) {
+    c->last_level = 0;
+    lks::launch_clear_flag(c->flag, c->stream);  // the divergence flag of this run
+  }
   if (c->rsz == 8) {
     Run<double> r(c);
     if (reset) r.forward(gamma, steps);
@@ -1291,9 +1301,26 @@ static lks_status backward_impl(lks_ctx* c, double seed, int steps, double* dJ, 
     if (c->mode == LKS_UNSTEADY) r.adjoint_unsteady(seed, dJ);
     else r.adjoint_steady(seed, steps, dJ, reset);
   }
+  // flag[1]: a non-finite sensitivity in the last adjoint sweep
+  lks::launch_clear_flag(c->flag + 1, c->stream);
+  if (dJ) lks::launch_finite_check<double>(dJ, size_t(c->N), c->flag + 1, c->stream);
   lks_status st = check_launch(c);
   if (st == LKS_OK) c->have_adjoint = true;
   return st;
+}
+
+lks_status lks_gradient_status(lks_ctx* c) {
+  if (!c) return LKS_E_INVALID;
+  if (!c->have_adjoint) return fail(c, LKS_E_STATE, "gradient status before alks_backward");
+  lks_status st = LKS_OK;
+  int flag[4];
+  if (!hip_ok(c, hipMemcpyAsync(flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream),
+              "read flag", &st) ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "gradient status sync", &st))
+    return st;
+  if (flag[0]) return fail(c, LKS_E_DIVERGED, "non-finite velocity in the forward state");
+  if (flag[1]) return fail(c, LKS_E_DIVERGED, "non-finite sensitivity in the adjoint sweep");
+  return LKS_OK;
 }
 
 lks_status alks_backward(lks_ctx* c, double J_seed, int adj_steps, double* dJdgamma_dev) {

@@ -58,7 +58,7 @@ EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forwa
             "lks_batch_last_error", "lks_batch_destroy", "lks_autotune",
             "lks_batch_autotune", "lks_set_tile_rows", "lks_set_steps_per_launch",
             "lks_launch_shape", "lks_batch_set_tile_rows", "lks_set_adjoint_mode",
-            "lks_set_checkpointing", "lks_checkpoint_info")
+            "lks_set_checkpointing", "lks_checkpoint_info", "lks_gradient_status")
 
 
 class Grid(ctypes.Structure):
@@ -151,6 +151,8 @@ _lib.lks_set_checkpointing.restype = _st
 _lib.lks_checkpoint_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                      ctypes.POINTER(ctypes.c_longlong)]
 _lib.lks_checkpoint_info.restype = _st
+_lib.lks_gradient_status.argtypes = [_vp]
+_lib.lks_gradient_status.restype = _st
 _lib.lks_batch_set_tile_rows.argtypes = [_vp, ctypes.c_int]
 _lib.lks_batch_set_tile_rows.restype = _st
 _lib.lks_batch_destroy.argtypes = [_vp]
@@ -295,6 +297,11 @@ class LKS:
         discrete Brinkman step); see lks_set_adjoint_mode."""
         code = {"paper": LKS_ADJ_PAPER, "exact": LKS_ADJ_EXACT}[mode]
         _check(_lib.lks_set_adjoint_mode(self.ctx, code), self.ctx)
+
+    def gradient_status(self):
+        """Raise LKSError (LKS_E_DIVERGED) if the last forward state or
+        gradient is non-finite (synchronises the stream)."""
+        _check(_lib.lks_gradient_status(self.ctx), self.ctx)
 
     def set_checkpointing(self, scheme, slots=0):
         """Plan the unsteady checkpoints before binding (see
