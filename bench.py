@@ -49,7 +49,7 @@ def parse():
     p.add_argument("--unsteady-steps", type=int, default=20000)
     p.add_argument("--no-exchanger", action="store_true")
     p.add_argument("--no-sink", action="store_true")
-    p.add_argument("--sink-steps", type=int, default=20000)
+    p.add_argument("--sink-steps", type=int, default=50000)
     p.add_argument("--exchanger-steps", type=int, default=20000)
     p.add_argument("--no-3d", action="store_true")
     p.add_argument("--steps-3d", type=int, default=5000)
@@ -164,7 +164,7 @@ def main():
         "batched_64_designs": batched,
         "unsteady_thermal_1024x512": unsteady,
         "heat_exchanger_201x201": exchanger,
-        "heat_sink_161x161": sink,
+        "heat_sink_141x161": sink,
         "duct3d_256x128x128": duct,
     }
     print(json.dumps(line), flush=True)
@@ -347,7 +347,7 @@ def exchanger_bench(args, dev):
 
 
 def sink_bench(args, dev):
-    """Transient natural-convection heat sink 161x161 (Ra = 2e5, Pr = 6,
+    """Transient natural-convection heat sink 141x161 (Ra = 2e5, Pr = 6,
     K_s = 10 K_f, heat flux 0.01 on the heated boundary), mean heated
     temperature averaged over n steps, whole trajectory kept; the adjoint in
     the exact mode, whose transposed conductivity term stays bounded at this
@@ -356,7 +356,7 @@ def sink_bench(args, dev):
     import torch
     from paper_2411_03090_amd import lks, workloads as W
     n = args.sink_steps
-    wl = W.heat_sink(n=161, n_steps=n)
+    wl = W.heat_sink(n_steps=n)
     g = torch.tensor(wl.gamma.reshape(-1), dtype=torch.float64, device=dev)
     nodes = wl.nx * wl.ny
     res, outs = {}, {}

@@ -290,36 +290,40 @@ def heat_exchanger(n=201, Re=100.0, Pr=6.0, beta_max=0.1, q_beta=0.1, sigma=8.0,
                     ufac=np.ones(n_fwd + 1))
 
 
-def heat_sink(n=161, Ra=2e5, Pr=6.0, q0=1e-2, Ks_over_Kf=10.0, heater=0.2, sigma=6.0,
-              seed=0, n_steps=20000, nu=0.1, alpha_max=10.0):
-    """Transient natural-convection heat sink in a closed n x n cavity (Sec.
-    3.4 at n = 161, L = n - 1 = 160): no-slip walls; T = 0 on the left, right
-    and top walls; the bottom wall adiabatic except the heated boundary, the
-    middle `heater` fraction of it, where the heat flux q0 enters; the
-    Boussinesq force G = g beta (T - T_ref) with T_ref = 0 and g beta pointing
-    up, sized by Ra = g beta dT L^3 / (nu K_f) with dT = 1; objective the
-    mean temperature over the heated boundary averaged over levels 1..N."""
-    L = n - 1
+def heat_sink(nx=141, ny=161, Ra=2e5, Pr=6.0, q0=1e-2, Ks_over_Kf=10.0, heater=0.2,
+              sigma=6.0, seed=0, n_steps=50000, nu=0.1, alpha_max=10.0, n=None):
+    """Transient natural-convection heat sink in a closed nx x ny cavity (Sec.
+    3.4: 141 x 161 nodes and 50000 steps, as its memory table lists, with
+    L = ny - 1 = 160; n gives a square n x n cavity instead): no-slip walls;
+    T = 0 on the left, right and top walls; the bottom wall adiabatic except
+    the heated boundary, the middle `heater` fraction of it, where the heat
+    flux q0 enters; the Boussinesq force G = g beta (T - T_ref) with
+    T_ref = 0 and g beta pointing up, sized by Ra = g beta dT L^3 / (nu K_f)
+    with dT = 1; objective the mean temperature over the heated boundary
+    averaged over levels 1..N."""
+    if n is not None:
+        nx = ny = n
+    L = ny - 1
     Kf = nu / Pr
     gb = Ra * nu * Kf / L ** 3
-    m = np.zeros((n, n), np.uint8)
+    m = np.zeros((ny, nx), np.uint8)
     m[1:-1, 0] = FLOW_VELOCITY | THERM_DIRICHLET
     m[1:-1, -1] = FLOW_VELOCITY | THERM_DIRICHLET
     m[-1, 1:-1] = FLOW_VELOCITY | THERM_DIRICHLET
     m[0, 1:-1] = FLOW_VELOCITY | THERM_FLUX
-    h0 = int(round(n * (0.5 - heater / 2)))
-    h1 = n - 1 - h0
+    h0 = int(round(nx * (0.5 - heater / 2)))
+    h1 = nx - 1 - h0
     m[0, h0:h1 + 1] |= TAG_PROBE
-    for j, i in ((0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1)):
+    for j, i in ((0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1)):
         m[j, i] = FLOW_CORNER
-    Tbar = np.zeros((n, n))
+    Tbar = np.zeros((ny, nx))
     Tbar[0, h0:h1 + 1] = q0
-    g = gamma_grf(n, n, sigma, seed)
-    return Workload(name=f"heat_sink_{n}x{n}_Ra{Ra:g}", nx=n, ny=n, nu=nu, u_max=0.0,
+    g = gamma_grf(nx, ny, sigma, seed)
+    return Workload(name=f"heat_sink_{nx}x{ny}_Ra{Ra:g}", nx=nx, ny=ny, nu=nu, u_max=0.0,
                     alpha_max=alpha_max, q_alpha=0.1, thermal=True, Pr=Pr,
                     Ks_over_Kf=Ks_over_Kf, q_K=0.1, objective=OBJ_HEAT_SINK,
                     mode=MODE_UNSTEADY, n_fwd=n_steps, n_adj=n_steps, gbeta=(0.0, gb),
-                    T_ref=0.0, mask=m, gamma=g, ubar=np.zeros((2, n, n)), Tbar=Tbar,
+                    T_ref=0.0, mask=m, gamma=g, ubar=np.zeros((2, ny, nx)), Tbar=Tbar,
                     ufac=np.ones(n_steps + 1))
 
 
