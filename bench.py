@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--batch-steps", type=int, default=2000)
     p.add_argument("--no-unsteady", action="store_true")
     p.add_argument("--unsteady-steps", type=int, default=20000)
+    p.add_argument("--no-large", action="store_true")
+    p.add_argument("--large-steps", type=int, default=2000)
     p.add_argument("--no-exchanger", action="store_true")
     p.add_argument("--no-sink", action="store_true")
     p.add_argument("--sink-steps", type=int, default=50000)
@@ -129,6 +131,7 @@ def main():
     roofline = alks_roofline(c32, g, wl, nodes, shape32)
     batched = None if args.no_batch else batched_bench(args, dev)
     unsteady = None if args.no_unsteady else unsteady_bench(args, dev)
+    large = None if args.no_large else large_bench(args, dev)
     exchanger = None if args.no_exchanger else exchanger_bench(args, dev)
     sink = None if args.no_sink else sink_bench(args, dev)
     duct = None if args.no_3d else duct3d_bench(args, dev)
@@ -163,6 +166,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_64_designs": batched,
         "unsteady_thermal_1024x512": unsteady,
+        "steady_2048x2048": large,
         "heat_exchanger_201x201": exchanger,
         "heat_sink_141x161": sink,
         "duct3d_256x128x128": duct,
@@ -306,6 +310,40 @@ def unsteady_bench(args, dev):
     res["tile_rows"] = {"fp32": c32.launch_shape()[0], "fp64": c64.launch_shape()[0]}
     res.update({"nodes": wl.nx * wl.ny, "steps": n, "budget_GiB": {"fp32": 4, "fp64": 8}})
     del c32, c64
+    torch.cuda.empty_cache()
+    return res
+
+
+def large_bench(args, dev):
+    """The headline's steady channel at 2048x2048 (Re = 100, the same gamma
+    recipe), n + n steps in FP32, autotuned: enough tiles to fill the chip,
+    so the ALKS kernel is measured against HBM bandwidth rather than launch
+    latency."""
+    import torch
+    from paper_2411_03090_amd import lks, workloads as W
+    n = args.large_steps
+    wl = W.steady_channel_grf(2048, 2048, Re=100.0, sigma=8.0, seed=0, n_fwd=n, n_adj=n)
+    g = torch.tensor(wl.gamma.reshape(-1), dtype=torch.float64, device=dev)
+    nodes = wl.nx * wl.ny
+    c = lks.LKS(wl, precision="fp32", device=dev)
+    c.autotune(g, 50)
+    shape = c.launch_shape()
+    out = torch.empty_like(g)
+    torch.cuda.synchronize()
+    e0 = ev()
+    c.forward(g, n)
+    c.objective()
+    c.backward(1.0, out, n)
+    e1 = ev()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    res = {"mlups": nodes * 2 * n / (ms * 1e-3) / 1e6, "ms_per_gradient": ms,
+           "n_fwd": n, "n_adj": n, "nodes": nodes,
+           "launch_shape": {"tile_rows": shape[0], "forward_steps_per_launch": shape[1],
+                            "adjoint_steps_per_launch": shape[2]},
+           "roofline": alks_roofline(c, g, wl, nodes, shape)}
+    res["roofline"]["traffic"] = None   # counters are taken on the 512x512 grid
+    del c
     torch.cuda.empty_cache()
     return res
 
