@@ -578,7 +578,12 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     const int p = p2 + CX[q] + CY[q] * W2;
-    f[q] = sr[p] + R(CX[q]) * svx[p] + R(CY[q]) * svy[p];
+    R e = sr[p];
+    if (CX[q] > 0) e += svx[p];
+    if (CX[q] < 0) e -= svx[p];
+    if (CY[q] > 0) e += svy[p];
+    if (CY[q] < 0) e -= svy[p];
+    f[q] = e;
     if constexpr (TH) gq[q] = sth[p];
   }
   R kappa = R(0), gu[3] = {R(0), R(0), R(0)};
@@ -710,7 +715,13 @@ __device__ inline void adj_pull(const R* lr, const R* lvx, const R* lvy, const R
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     const int p = pr + CX[q] + CY[q] * PR;
-    const R E = lr[p] + R(CX[q]) * lvx[p] + R(CY[q]) * lvy[p];
+    // rho~ + c_i.V with the zero components left out (a product with a
+    // constant 0 is not folded away under IEEE rules)
+    R E = lr[p];
+    if (CX[q] > 0) E += lvx[p];
+    if (CX[q] < 0) E -= lvx[p];
+    if (CY[q] > 0) E += lvy[p];
+    if (CY[q] < 0) E -= lvy[p];
     const R wE = R(WD[q]) * E;
     r += wE;
     if (CX[q]) Ux += R(CX[q]) * wE;
