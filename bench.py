@@ -127,6 +127,9 @@ def main():
     mlups64 = upd / (ms64 * 1e-3) / 1e6
     err_grad = rel(d32.cpu().numpy(), d64.cpu().numpy())
     err_J = abs(J32 - J64) / abs(J64)
+    # final forward fields of the last gradient of each context
+    err_fields = {n: rel(c32.read(n).cpu().numpy(), c64.read(n).cpu().numpy())
+                  for n in ("drho", "ux", "uy")}
 
     roofline = alks_roofline(c32, g, wl, nodes, shape32)
     batched = None if args.no_batch else batched_bench(args, dev)
@@ -161,7 +164,7 @@ def main():
         "fp64_gpu": {"value": mlups64, "unit": "MLUPS", "ms_per_step": ms64,
                      "gradients_per_s": 1e3 / ms64},
         "speedup_vs_fp64_gpu": ms64 / ms32,
-        "fp32_vs_fp64_rel_error": {"J": err_J, "dJdgamma_l2": err_grad},
+        "fp32_vs_fp64_rel_error": {"J": err_J, "dJdgamma_l2": err_grad, "fields_l2": err_fields},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched_64_designs": batched,
