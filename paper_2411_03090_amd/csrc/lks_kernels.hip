@@ -187,6 +187,76 @@ __device__ inline bool interior_tile(const Geo& g, int x0, int x1, int y0, int y
   return x0 >= 2 && y0 >= 2 && x1 <= g.nx - 2 && y1 <= g.ny - 2;
 }
 
+// How a tile treats its nodes:
+//   K_GEN   every node takes the general rule (wrap-around, bounds, ring
+//           rules, one-sided differences): periodic boxes and odd tiles;
+//   K_INT   the tile and its halo lie off the ring: every node is interior;
+//   K_EDGE  a tile of a bounded domain that meets the ring: the nodes off
+//           the ring take the interior rule in the flat walk of the tile,
+//           the few ring nodes are gathered into a second walk of their own,
+//           so a wave does not pay for the ring rules of one of its lanes.
+// The per-node arithmetic is the same function in all three, so the kinds
+// give the same bits.
+constexpr int K_GEN = 0, K_INT = 1, K_EDGE = 2;
+
+template <bool B>
+using BoolC = std::integral_constant<bool, B>;
+
+// true on the boundary ring of a bounded domain, and outside it
+__device__ inline bool on_ring(const Geo& g, int i, int j) {
+  return i <= 0 || j <= 0 || i >= g.nx - 1 || j >= g.ny - 1;
+}
+
+// The ring nodes of the node rectangle [x0, x0 + w) x [y0, y0 + h) clipped
+// to a bounded domain: its parts of the columns i = 0 and i = nx - 1, then
+// of the rows j = 0 and j = ny - 1 without the end nodes of those rows.
+struct RingSet {
+  int ry0, bx0, nl, nr, nb;
+};
+
+__device__ inline int ring_set(const Geo& g, int x0, int y0, int w, int h, RingSet& s) {
+  const int rx0 = max(x0, 0), rx1 = min(x0 + w, g.nx) - 1;
+  const int ry0 = max(y0, 0), ry1 = min(y0 + h, g.ny) - 1;
+  const int hc = ry1 - ry0 + 1;
+  s.ry0 = ry0;
+  s.nl = rx0 == 0 ? hc : 0;
+  s.nr = rx1 == g.nx - 1 ? hc : 0;
+  s.bx0 = max(rx0, 1);
+  const int wr = max(min(rx1, g.nx - 2) - s.bx0 + 1, 0);
+  s.nb = ry0 == 0 ? wr : 0;
+  const int nt = ry1 == g.ny - 1 ? wr : 0;
+  return s.nl + s.nr + s.nb + nt;
+}
+
+__device__ inline void ring_at(const Geo& g, const RingSet& s, int t, int* i, int* j) {
+  if (t < s.nl) {
+    *i = 0;
+    *j = s.ry0 + t;
+  } else if (t < s.nl + s.nr) {
+    *i = g.nx - 1;
+    *j = s.ry0 + t - s.nl;
+  } else if (t < s.nl + s.nr + s.nb) {
+    *i = s.bx0 + t - s.nl - s.nr;
+    *j = 0;
+  } else {
+    *i = s.bx0 + t - s.nl - s.nr - s.nb;
+    *j = g.ny - 1;
+  }
+}
+
+// Visit the ring nodes (i, j) of a rectangle, one per thread from the last
+// thread of the block down (the flat walks leave those idle most often).
+template <typename F>
+__device__ inline void ring_loop(const Geo& g, int x0, int y0, int w, int h, F&& f) {
+  RingSet s;
+  const int n = ring_set(g, x0, y0, w, h, s);
+  for (int t = NTHREADS - 1 - int(threadIdx.x); t < n; t += NTHREADS) {
+    int i, j;
+    ring_at(g, s, t, &i, &j);
+    f(i, j);
+  }
+}
+
 // Visit the positions (lx, ly) of a w x h rectangle, 256 threads, flat order.
 template <bool FULL, int WC, int HC, typename F>
 __device__ inline void rect_loop(int w, int h, F&& f) {
@@ -201,6 +271,38 @@ __device__ inline void rect_loop(int w, int h, F&& f) {
     const int n = w * h;
     for (int p = threadIdx.x; p < n; p += NTHREADS) f(p % w, p / w);
   }
+}
+
+// Walk the region of a tile grown by h nodes on every side (w x hh
+// positions; compile-time extents WC x HC for full tiles): fn(rule, lx, ly,
+// i, j) at each node of the region in the domain, where (lx, ly) is the
+// region position and rule is BoolC<true> for the interior rule. K_GEN
+// wraps a periodic box and skips positions outside a bounded one; K_EDGE
+// walks the nodes off the ring first and its ring nodes after.
+template <int KIND, bool FULL, int WC, int HC, typename F>
+__device__ inline void region_walk(const Geo& g, int x0, int y0, int h, int w, int hh, F&& fn) {
+  rect_loop<FULL, WC, HC>(w, hh, [&](int lx, int ly) {
+    int i = x0 + lx - h, j = y0 + ly - h;
+    if constexpr (KIND == K_EDGE) {
+      if (on_ring(g, i, j)) return;
+    } else if constexpr (KIND == K_GEN) {
+      if (g.periodic) {
+        i = wrapi(i, g.nx);
+        j = wrapi(j, g.ny);
+      } else if (i < 0 || j < 0 || i >= g.nx || j >= g.ny) {
+        return;
+      }
+    }
+    fn(BoolC<KIND != K_GEN>(), lx, ly, i, j);
+  });
+  if constexpr (KIND == K_EDGE)
+    ring_loop(g, x0 - h, y0 - h, w, hh,
+              [&](int i, int j) { fn(BoolC<false>(), i - x0 + h, j - y0 + h, i, j); });
+}
+
+// interior_tile for the two-step kernels, whose tiles carry a 4-node halo
+__device__ inline bool interior_tile2(const Geo& g, int x0, int x1, int y0, int y1) {
+  return x0 >= 4 && y0 >= 4 && x1 <= g.nx - 4 && y1 <= g.ny - 4;
 }
 
 // Load NF fields of the tile plus an H-node halo into LDS arrays of pitch P
@@ -446,11 +548,12 @@ __device__ inline void corner_from(const Geo& g, int i, int j, Put&& put) {
   if (j == g.ny - 2) put(g.ny - 1);
 }
 
-template <typename R, bool TH, int TY, bool FULL, bool INT>
+template <typename R, bool TH, int TY, bool FULL, int KIND>
 __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L, int x0, int y0,
                          int tw, int th, int tile) {
   using TL = Tile<TY>;
   constexpr int W2 = TL::W2, W1 = TL::W1, SF = TL::W1 * TL::H1;
+  constexpr bool INT = KIND == K_INT, EDGE = KIND == K_EDGE;
   const R A = R(g.A);
   if constexpr (FULL) {
     tw = TX;
@@ -481,41 +584,24 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
   }
   __syncthreads();
 
-  rect_loop<FULL, TX + 2, TY + 2>(tw + 2, th + 2, [&](int lx, int ly) {
-    int i = x0 + lx - 1, j = y0 + ly - 1;
-    if constexpr (!INT) {
-      if (g.periodic) {
-        i = wrapi(i, g.nx);
-        j = wrapi(j, g.ny);
-      } else if (i < 0 || j < 0 || i >= g.nx || j >= g.ny) {
-        return;
-      }
-    }
-    fwd_collide<R, TH, W2, SF, INT>(g, A, L.d, L.u, L.v, L.T, L.B, (ly + 1) * W2 + lx + 1, i, j,
-                               &L.f[0][0], &L.gq[0][0], ly * W1 + lx);
+  region_walk<KIND, FULL, TX + 2, TY + 2>(g, x0, y0, 1, tw + 2, th + 2,
+                                          [&](auto in, int lx, int ly, int i, int j) {
+    fwd_collide<R, TH, W2, SF, decltype(in)::value>(g, A, L.d, L.u, L.v, L.T, L.B,
+                                                    (ly + 1) * W2 + lx + 1, i, j, &L.f[0][0],
+                                                    &L.gq[0][0], ly * W1 + lx);
   });
   __syncthreads();
 
   double part = 0.0;
-  int e = 0;
-  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
-    const int i = x0 + lx, j = y0 + ly;
+  // the pull, new state and objective term of node (i, j) with mask m
+  auto pull = [&](auto in, int lx, int ly, int i, int j, int m, R s) {
+    constexpr bool I = decltype(in)::value;
     const int k = j * g.nx + i;
-    int m;
-    R s;
-    if constexpr (FULL) {
-      m = mpre[e];
-      s = spre[e];
-      ++e;
-    } else {
-      m = a.mask[k];
-      s = a.inv1pa[k];
-    }
-    if (!INT && !g.periodic && (m & 3) == FLOW_CORNER) return;
+    if (!I && !g.periodic && (m & 3) == FLOW_CORNER) return;
     R dn, uxn, uyn, Tn;
-    fwd_pull<R, TH, W1, SF, INT>(g, a, &L.f[0][0], &L.gq[0][0], (ly + 1) * W1 + lx + 1, i, j, k,
-                                 m, s, a.level_out, dn, uxn, uyn, Tn);
-    if constexpr (!INT)
+    fwd_pull<R, TH, W1, SF, I>(g, a, &L.f[0][0], &L.gq[0][0], (ly + 1) * W1 + lx + 1, i, j, k, m,
+                               s, a.level_out, dn, uxn, uyn, Tn);
+    if constexpr (!I)
       corner_from(g, i, j, [&](int jc) {
         const int kc = jc * g.nx + i;
         a.d1[kc] = dn;
@@ -539,7 +625,32 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
         if (m & TAG_J_OUTLET) part -= double(dn);
       }
     }
+  };
+  int e = 0;
+  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
+    const int i = x0 + lx, j = y0 + ly;
+    int m;
+    R s;
+    if constexpr (FULL) {
+      m = mpre[e];
+      s = spre[e];
+      ++e;
+      if constexpr (EDGE)
+        if (on_ring(g, i, j)) return;
+    } else {
+      if constexpr (EDGE)
+        if (on_ring(g, i, j)) return;
+      const int k = j * g.nx + i;
+      m = a.mask[k];
+      s = a.inv1pa[k];
+    }
+    pull(BoolC<INT || EDGE>(), lx, ly, i, j, m, s);
   });
+  if constexpr (EDGE)
+    ring_loop(g, x0, y0, tw, th, [&](int i, int j) {
+      const int k = j * g.nx + i;
+      pull(BoolC<false>(), i - x0, j - y0, i, j, int(a.mask[k]), a.inv1pa[k]);
+    });
   if (a.acc) {
     double s = block_sum(part, L.red);
     if (threadIdx.x == 0) a.acc[tile] += s;
@@ -552,12 +663,16 @@ __global__ __launch_bounds__(NTHREADS) void lks_step_kernel(Geo g, FwdArgs<R> a)
   int x0, x1, y0, y1, tile;
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
   const int tw = x1 - x0, th = y1 - y0;
-  if (tw != TX || th != TY)
-    lks_tile<R, TH, TY, false, false>(g, a, L, x0, y0, tw, th, tile);
-  else if (interior_tile(g, x0, x1, y0, y1))
-    lks_tile<R, TH, TY, true, true>(g, a, L, x0, y0, tw, th, tile);
-  else
-    lks_tile<R, TH, TY, true, false>(g, a, L, x0, y0, tw, th, tile);
+  if (tw != TX || th != TY) {
+    if (g.periodic) lks_tile<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th, tile);
+    else lks_tile<R, TH, TY, false, K_EDGE>(g, a, L, x0, y0, tw, th, tile);
+  } else if (interior_tile(g, x0, x1, y0, y1)) {
+    lks_tile<R, TH, TY, true, K_INT>(g, a, L, x0, y0, tw, th, tile);
+  } else if (g.periodic) {
+    lks_tile<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th, tile);
+  } else {
+    lks_tile<R, TH, TY, true, K_EDGE>(g, a, L, x0, y0, tw, th, tile);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -891,11 +1006,12 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
   }
 }
 
-template <typename R, bool TH, int TY, bool FULL, bool INT>
+template <typename R, bool TH, int TY, bool FULL, int KIND>
 __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& L, int x0,
                           int y0, int tw, int th) {
   using TL = Tile<TY>;
   constexpr int W2 = TL::W2, W1 = TL::W1, SM = TL::W1 * TL::H1;
+  constexpr bool INT = KIND == K_INT, EDGE = KIND == K_EDGE;
   if constexpr (FULL) {
     tw = TX;
     th = TY;
@@ -925,18 +1041,11 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
   }
   __syncthreads();
 
-  rect_loop<FULL, TX + 2, TY + 2>(tw + 2, th + 2, [&](int lx, int ly) {
-    int i = x0 + lx - 1, j = y0 + ly - 1;
-    if constexpr (!INT) {
-      if (g.periodic) {
-        i = wrapi(i, g.nx);
-        j = wrapi(j, g.ny);
-      } else if (i < 0 || j < 0 || i >= g.nx || j >= g.ny) {
-        return;
-      }
-    }
-    adj_moments<R, TH, W2, SM, INT>(g, a, L.r, L.vx, L.vy, L.th, L.Tn, (ly + 1) * W2 + lx + 1, i, j,
-                               &L.m[0][0], ly * W1 + lx);
+  region_walk<KIND, FULL, TX + 2, TY + 2>(g, x0, y0, 1, tw + 2, th + 2,
+                                          [&](auto in, int lx, int ly, int i, int j) {
+    adj_moments<R, TH, W2, SM, decltype(in)::value>(g, a, L.r, L.vx, L.vy, L.th, L.Tn,
+                                                    (ly + 1) * W2 + lx + 1, i, j, &L.m[0][0],
+                                                    ly * W1 + lx);
   });
   __syncthreads();
   const bool has_corner =
@@ -946,33 +1055,47 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
     __syncthreads();
   }
 
-  int e = 0;
-  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
-    const int i = x0 + lx, j = y0 + ly;
+  // the local terms, new coefficients and sensitivity of node (i, j)
+  auto local = [&](auto in, int lx, int ly, int i, int j, R s, R ux, R uy) {
     const int k = j * g.nx + i;
-    R s, ux, uy;
-    if constexpr (FULL) {
-      s = spre[e];
-      ux = uxpre[e];
-      uy = uypre[e];
-      ++e;
-    } else {
-      s = a.inv1pa[k];
-      ux = a.ux[k];
-      uy = a.uy[k];
-    }
     R r, Vx, Vy, Th;
     double v;
-    adj_local<R, TH, W2, W1, SM, INT>(g, a, &L.m[0][0], (ly + 1) * W1 + lx + 1, L.Tn, L.B,
-                                 (ly + 2) * W2 + lx + 2, i, j, k, s, ux, uy, r, Vx, Vy, Th,
-                                 a.sens_mode != 0, v);
+    adj_local<R, TH, W2, W1, SM, decltype(in)::value>(
+        g, a, &L.m[0][0], (ly + 1) * W1 + lx + 1, L.Tn, L.B, (ly + 2) * W2 + lx + 2, i, j, k, s,
+        ux, uy, r, Vx, Vy, Th, a.sens_mode != 0, v);
     a.r1[k] = r;
     a.vx1[k] = Vx;
     a.vy1[k] = Vy;
     if constexpr (TH) a.th1[k] = Th;
     if (a.sens_mode == 1) a.sens[k] += v;
     else if (a.sens_mode == 2) a.sens[k] = v;
+  };
+  int e = 0;
+  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
+    const int i = x0 + lx, j = y0 + ly;
+    R s, ux, uy;
+    if constexpr (FULL) {
+      s = spre[e];
+      ux = uxpre[e];
+      uy = uypre[e];
+      ++e;
+      if constexpr (EDGE)
+        if (on_ring(g, i, j)) return;
+    } else {
+      if constexpr (EDGE)
+        if (on_ring(g, i, j)) return;
+      const int k = j * g.nx + i;
+      s = a.inv1pa[k];
+      ux = a.ux[k];
+      uy = a.uy[k];
+    }
+    local(BoolC<INT || EDGE>(), lx, ly, i, j, s, ux, uy);
   });
+  if constexpr (EDGE)
+    ring_loop(g, x0, y0, tw, th, [&](int i, int j) {
+      const int k = j * g.nx + i;
+      local(BoolC<false>(), i - x0, j - y0, i, j, a.inv1pa[k], a.ux[k], a.uy[k]);
+    });
 }
 
 template <typename R, bool TH, int TY>
@@ -981,12 +1104,16 @@ __global__ __launch_bounds__(NTHREADS) void alks_step_kernel(Geo g, AdjArgs<R> a
   int x0, x1, y0, y1, tile;
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
   const int tw = x1 - x0, th = y1 - y0;
-  if (tw != TX || th != TY)
-    alks_tile<R, TH, TY, false, false>(g, a, L, x0, y0, tw, th);
-  else if (interior_tile(g, x0, x1, y0, y1))
-    alks_tile<R, TH, TY, true, true>(g, a, L, x0, y0, tw, th);
-  else
-    alks_tile<R, TH, TY, true, false>(g, a, L, x0, y0, tw, th);
+  if (tw != TX || th != TY) {
+    if (g.periodic) alks_tile<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
+    else alks_tile<R, TH, TY, false, K_EDGE>(g, a, L, x0, y0, tw, th);
+  } else if (interior_tile(g, x0, x1, y0, y1)) {
+    alks_tile<R, TH, TY, true, K_INT>(g, a, L, x0, y0, tw, th);
+  } else if (g.periodic) {
+    alks_tile<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
+  } else {
+    alks_tile<R, TH, TY, true, K_EDGE>(g, a, L, x0, y0, tw, th);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1010,25 +1137,12 @@ struct Fwd2Lds {
   R gq[TH ? 9 * SF : 1];
 };
 
-// node of a region position: the region starts h nodes before the tile;
-// false outside a non-periodic domain
-__device__ inline bool region_node(const Geo& g, int x0, int y0, int h, int lx, int ly, int* i,
-                                   int* j) {
-  *i = x0 + lx - h;
-  *j = y0 + ly - h;
-  if (g.periodic) {
-    *i = wrapi(*i, g.nx);
-    *j = wrapi(*j, g.ny);
-    return true;
-  }
-  return *i >= 0 && *j >= 0 && *i < g.nx && *j < g.ny;
-}
-
-template <typename R, bool TH, int TY, bool FULL>
+template <typename R, bool TH, int TY, bool FULL, int KIND>
 __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>& L, int x0,
                           int y0, int tw, int th) {
   using LD = Fwd2Lds<R, TH, TY>;
   constexpr int WR = LD::WR, WF = LD::WF, SF = LD::SF;
+  constexpr bool INT = KIND == K_INT, EDGE = KIND == K_EDGE;
   const R A = R(g.A);
   if constexpr (FULL) {
     tw = TX;
@@ -1049,38 +1163,39 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
   if constexpr (TH) {
     const R* src[5] = {a.d0, a.ux0, a.uy0, a.T0, a.B};
     R* dst[5] = {L.d, L.u, L.v, L.T, L.B};
-    load_halo<R, FULL, TY, 4, WR, 5>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 4, WR, 5, INT>(g, x0, y0, tw, th, src, dst);
   } else {
     const R* src[3] = {a.d0, a.ux0, a.uy0};
     R* dst[3] = {L.d, L.u, L.v};
-    load_halo<R, FULL, TY, 4, WR, 3>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 4, WR, 3, INT>(g, x0, y0, tw, th, src, dst);
   }
   __syncthreads();
   // first step: collide on the tile + 3, pull on the tile + 2 into LDS
-  rect_loop<FULL, TX + 6, TY + 6>(tw + 6, th + 6, [&](int lx, int ly) {
-    int i, j;
-    if (!region_node(g, x0, y0, 3, lx, ly, &i, &j)) return;
-    fwd_collide<R, TH, WR, SF>(g, A, L.d, L.u, L.v, L.T, L.B, (ly + 1) * WR + lx + 1, i, j, L.f,
-                               L.gq, ly * WF + lx);
+  region_walk<KIND, FULL, TX + 6, TY + 6>(g, x0, y0, 3, tw + 6, th + 6,
+                                          [&](auto in, int lx, int ly, int i, int j) {
+    fwd_collide<R, TH, WR, SF, decltype(in)::value>(g, A, L.d, L.u, L.v, L.T, L.B,
+                                                    (ly + 1) * WR + lx + 1, i, j, L.f, L.gq,
+                                                    ly * WF + lx);
   });
   __syncthreads();
-  rect_loop<FULL, TX + 4, TY + 4>(tw + 4, th + 4, [&](int lx, int ly) {
-    int i, j;
-    if (!region_node(g, x0, y0, 2, lx, ly, &i, &j)) return;
+  region_walk<KIND, FULL, TX + 4, TY + 4>(g, x0, y0, 2, tw + 4, th + 4,
+                                          [&](auto in, int lx, int ly, int i, int j) {
+    constexpr bool I = decltype(in)::value;
     const int k = j * g.nx + i;
-    const int m = a.mask[k];
-    if (!g.periodic && (m & 3) == FLOW_CORNER) return;
+    const int m = I ? 0 : int(a.mask[k]);
+    if (!I && !g.periodic && (m & 3) == FLOW_CORNER) return;
     R dn, uxn, uyn, Tn;
-    fwd_pull<R, TH, WF, SF>(g, a, L.f, L.gq, (ly + 1) * WF + lx + 1, i, j, k, m, a.inv1pa[k],
-                            a.level_mid, dn, uxn, uyn, Tn);
+    fwd_pull<R, TH, WF, SF, I>(g, a, L.f, L.gq, (ly + 1) * WF + lx + 1, i, j, k, m,
+                               a.inv1pa[k], a.level_mid, dn, uxn, uyn, Tn);
     const int pr = (ly + 2) * WR + lx + 2;
-    corner_from(g, i, j, [&](int jc) {
-      const int pc = pr + (jc == 0 ? -WR : WR);
-      L.d[pc] = dn;
-      L.u[pc] = R(0);
-      L.v[pc] = R(0);
-      if constexpr (TH) L.T[pc] = Tn;
-    });
+    if constexpr (!I)
+      corner_from(g, i, j, [&](int jc) {
+        const int pc = pr + (jc == 0 ? -WR : WR);
+        L.d[pc] = dn;
+        L.u[pc] = R(0);
+        L.v[pc] = R(0);
+        if constexpr (TH) L.T[pc] = Tn;
+      });
     L.d[pr] = dn;
     L.u[pr] = uxn;
     L.v[pr] = uyn;
@@ -1088,43 +1203,58 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
   });
   __syncthreads();
   // second step: collide on the tile + 1, pull on the tile into HBM
-  rect_loop<FULL, TX + 2, TY + 2>(tw + 2, th + 2, [&](int lx, int ly) {
-    int i, j;
-    if (!region_node(g, x0, y0, 1, lx, ly, &i, &j)) return;
-    fwd_collide<R, TH, WR, SF>(g, A, L.d, L.u, L.v, L.T, L.B, (ly + 3) * WR + lx + 3, i, j, L.f,
-                               L.gq, (ly + 2) * WF + lx + 2);
+  region_walk<KIND, FULL, TX + 2, TY + 2>(g, x0, y0, 1, tw + 2, th + 2,
+                                          [&](auto in, int lx, int ly, int i, int j) {
+    fwd_collide<R, TH, WR, SF, decltype(in)::value>(g, A, L.d, L.u, L.v, L.T, L.B,
+                                                    (ly + 3) * WR + lx + 3, i, j, L.f, L.gq,
+                                                    (ly + 2) * WF + lx + 2);
   });
   __syncthreads();
+  auto pull = [&](auto in, int lx, int ly, int i, int j, int m, R s) {
+    constexpr bool I = decltype(in)::value;
+    const int k = j * g.nx + i;
+    if (!I && !g.periodic && (m & 3) == FLOW_CORNER) return;
+    R dn, uxn, uyn, Tn;
+    fwd_pull<R, TH, WF, SF, I>(g, a, L.f, L.gq, (ly + 3) * WF + lx + 3, i, j, k, m, s,
+                               a.level_out, dn, uxn, uyn, Tn);
+    if constexpr (!I)
+      corner_from(g, i, j, [&](int jc) {
+        const int kc = jc * g.nx + i;
+        a.d1[kc] = dn;
+        a.ux1[kc] = R(0);
+        a.uy1[kc] = R(0);
+        if constexpr (TH) a.T1[kc] = Tn;
+      });
+    a.d1[k] = dn;
+    a.ux1[k] = uxn;
+    a.uy1[k] = uyn;
+    if constexpr (TH) a.T1[k] = Tn;
+  };
   int e = 0;
   rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
     const int i = x0 + lx, j = y0 + ly;
-    const int k = j * g.nx + i;
     int m;
     R s;
     if constexpr (FULL) {
       m = mpre[e];
       s = spre[e];
       ++e;
+      if constexpr (EDGE)
+        if (on_ring(g, i, j)) return;
     } else {
+      if constexpr (EDGE)
+        if (on_ring(g, i, j)) return;
+      const int k = j * g.nx + i;
       m = a.mask[k];
       s = a.inv1pa[k];
     }
-    if (!g.periodic && (m & 3) == FLOW_CORNER) return;
-    R dn, uxn, uyn, Tn;
-    fwd_pull<R, TH, WF, SF>(g, a, L.f, L.gq, (ly + 3) * WF + lx + 3, i, j, k, m, s, a.level_out,
-                            dn, uxn, uyn, Tn);
-    corner_from(g, i, j, [&](int jc) {
-      const int kc = jc * g.nx + i;
-      a.d1[kc] = dn;
-      a.ux1[kc] = R(0);
-      a.uy1[kc] = R(0);
-      if constexpr (TH) a.T1[kc] = Tn;
-    });
-    a.d1[k] = dn;
-    a.ux1[k] = uxn;
-    a.uy1[k] = uyn;
-    if constexpr (TH) a.T1[k] = Tn;
+    pull(BoolC<INT || EDGE>(), lx, ly, i, j, m, s);
   });
+  if constexpr (EDGE)
+    ring_loop(g, x0, y0, tw, th, [&](int i, int j) {
+      const int k = j * g.nx + i;
+      pull(BoolC<false>(), i - x0, j - y0, i, j, int(a.mask[k]), a.inv1pa[k]);
+    });
 }
 
 template <typename R, bool TH, int TY>
@@ -1133,8 +1263,16 @@ __global__ __launch_bounds__(NTHREADS) void lks_step2_kernel(Geo g, FwdArgs<R> a
   int x0, x1, y0, y1, tile;
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
   const int tw = x1 - x0, th = y1 - y0;
-  if (tw == TX && th == TY) lks_tile2<R, TH, TY, true>(g, a, L, x0, y0, tw, th);
-  else lks_tile2<R, TH, TY, false>(g, a, L, x0, y0, tw, th);
+  if (tw != TX || th != TY) {
+    if (g.periodic) lks_tile2<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
+    else lks_tile2<R, TH, TY, false, K_EDGE>(g, a, L, x0, y0, tw, th);
+  } else if (interior_tile2(g, x0, x1, y0, y1)) {
+    lks_tile2<R, TH, TY, true, K_INT>(g, a, L, x0, y0, tw, th);
+  } else if (g.periodic) {
+    lks_tile2<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
+  } else {
+    lks_tile2<R, TH, TY, true, K_EDGE>(g, a, L, x0, y0, tw, th);
+  }
 }
 
 template <typename R, bool TH, int TY>
@@ -1148,11 +1286,12 @@ struct Adj2Lds {
   R m[NM * SM];
 };
 
-template <typename R, bool TH, int TY, bool FULL>
+template <typename R, bool TH, int TY, bool FULL, int KIND>
 __device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>& L, int x0,
                            int y0, int tw, int th) {
   using LD = Adj2Lds<R, TH, TY>;
   constexpr int WR = LD::WR, WM = LD::WM, SM = LD::SM;
+  constexpr bool INT = KIND == K_INT, EDGE = KIND == K_EDGE;
   if constexpr (FULL) {
     tw = TX;
     th = TY;
@@ -1172,36 +1311,36 @@ __device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>
   if constexpr (TH) {
     const R* src[6] = {a.r0, a.vx0, a.vy0, a.th0, a.T, a.B};
     R* dst[6] = {L.r, L.vx, L.vy, L.th, L.Tn, L.B};
-    load_halo<R, FULL, TY, 4, WR, 6>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 4, WR, 6, INT>(g, x0, y0, tw, th, src, dst);
   } else {
     const R* src[3] = {a.r0, a.vx0, a.vy0};
     R* dst[3] = {L.r, L.vx, L.vy};
-    load_halo<R, FULL, TY, 4, WR, 3>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 4, WR, 3, INT>(g, x0, y0, tw, th, src, dst);
   }
   __syncthreads();
-  const bool near_corner = !g.periodic && (x0 <= 3 || x0 + tw + 3 >= g.nx) &&
+  const bool near_corner = !INT && !g.periodic && (x0 <= 3 || x0 + tw + 3 >= g.nx) &&
                            (y0 <= 3 || y0 + th + 3 >= g.ny);
   // first step: moments on the tile + 3, new coefficients on the tile + 2
-  rect_loop<FULL, TX + 6, TY + 6>(tw + 6, th + 6, [&](int lx, int ly) {
-    int i, j;
-    if (!region_node(g, x0, y0, 3, lx, ly, &i, &j)) return;
-    adj_moments<R, TH, WR, SM>(g, a, L.r, L.vx, L.vy, L.th, L.Tn, (ly + 1) * WR + lx + 1, i, j,
-                               L.m, ly * WM + lx);
+  region_walk<KIND, FULL, TX + 6, TY + 6>(g, x0, y0, 3, tw + 6, th + 6,
+                                          [&](auto in, int lx, int ly, int i, int j) {
+    adj_moments<R, TH, WR, SM, decltype(in)::value>(g, a, L.r, L.vx, L.vy, L.th, L.Tn,
+                                                    (ly + 1) * WR + lx + 1, i, j, L.m,
+                                                    ly * WM + lx);
   });
   __syncthreads();
   if (near_corner) {
     adj_corners<R, TH, WM, SM>(g, L.m, x0 - 3, y0 - 3, tw + 6, th + 6);
     __syncthreads();
   }
-  rect_loop<FULL, TX + 4, TY + 4>(tw + 4, th + 4, [&](int lx, int ly) {
-    int i, j;
-    if (!region_node(g, x0, y0, 2, lx, ly, &i, &j)) return;
+  region_walk<KIND, FULL, TX + 4, TY + 4>(g, x0, y0, 2, tw + 4, th + 4,
+                                          [&](auto in, int lx, int ly, int i, int j) {
     const int k = j * g.nx + i;
     R r, Vx, Vy, Th;
     double v;
     const int pr = (ly + 2) * WR + lx + 2;
-    adj_local<R, TH, WR, WM, SM>(g, a, L.m, (ly + 1) * WM + lx + 1, L.Tn, L.B, pr, i, j, k,
-                                 a.inv1pa[k], a.ux[k], a.uy[k], r, Vx, Vy, Th, false, v);
+    adj_local<R, TH, WR, WM, SM, decltype(in)::value>(g, a, L.m, (ly + 1) * WM + lx + 1, L.Tn,
+                                                      L.B, pr, i, j, k, a.inv1pa[k], a.ux[k],
+                                                      a.uy[k], r, Vx, Vy, Th, false, v);
     L.r[pr] = r;
     L.vx[pr] = Vx;
     L.vy[pr] = Vy;
@@ -1209,44 +1348,57 @@ __device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>
   });
   __syncthreads();
   // second step: moments on the tile + 1, new coefficients on the tile
-  rect_loop<FULL, TX + 2, TY + 2>(tw + 2, th + 2, [&](int lx, int ly) {
-    int i, j;
-    if (!region_node(g, x0, y0, 1, lx, ly, &i, &j)) return;
-    adj_moments<R, TH, WR, SM>(g, a, L.r, L.vx, L.vy, L.th, L.Tn, (ly + 3) * WR + lx + 3, i, j,
-                               L.m, (ly + 2) * WM + lx + 2);
+  region_walk<KIND, FULL, TX + 2, TY + 2>(g, x0, y0, 1, tw + 2, th + 2,
+                                          [&](auto in, int lx, int ly, int i, int j) {
+    adj_moments<R, TH, WR, SM, decltype(in)::value>(g, a, L.r, L.vx, L.vy, L.th, L.Tn,
+                                                    (ly + 3) * WR + lx + 3, i, j, L.m,
+                                                    (ly + 2) * WM + lx + 2);
   });
   __syncthreads();
   if (near_corner) {
     adj_corners<R, TH, WM, SM>(g, L.m + 2 * WM + 2, x0 - 1, y0 - 1, tw + 2, th + 2);
     __syncthreads();
   }
-  int e = 0;
-  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
-    const int i = x0 + lx, j = y0 + ly;
+  auto local = [&](auto in, int lx, int ly, int i, int j, R s, R ux, R uy) {
     const int k = j * g.nx + i;
-    R s, ux, uy;
-    if constexpr (FULL) {
-      s = spre[e];
-      ux = uxpre[e];
-      uy = uypre[e];
-      ++e;
-    } else {
-      s = a.inv1pa[k];
-      ux = a.ux[k];
-      uy = a.uy[k];
-    }
     R r, Vx, Vy, Th;
     double v;
-    adj_local<R, TH, WR, WM, SM>(g, a, L.m, (ly + 3) * WM + lx + 3, L.Tn, L.B,
-                                 (ly + 4) * WR + lx + 4, i, j, k, s, ux, uy, r, Vx, Vy, Th,
-                                 a.sens_mode != 0, v);
+    adj_local<R, TH, WR, WM, SM, decltype(in)::value>(
+        g, a, L.m, (ly + 3) * WM + lx + 3, L.Tn, L.B, (ly + 4) * WR + lx + 4, i, j, k, s, ux, uy,
+        r, Vx, Vy, Th, a.sens_mode != 0, v);
     a.r1[k] = r;
     a.vx1[k] = Vx;
     a.vy1[k] = Vy;
     if constexpr (TH) a.th1[k] = Th;
     if (a.sens_mode == 1) a.sens[k] += v;
     else if (a.sens_mode == 2) a.sens[k] = v;
+  };
+  int e = 0;
+  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
+    const int i = x0 + lx, j = y0 + ly;
+    R s, ux, uy;
+    if constexpr (FULL) {
+      s = spre[e];
+      ux = uxpre[e];
+      uy = uypre[e];
+      ++e;
+      if constexpr (EDGE)
+        if (on_ring(g, i, j)) return;
+    } else {
+      if constexpr (EDGE)
+        if (on_ring(g, i, j)) return;
+      const int k = j * g.nx + i;
+      s = a.inv1pa[k];
+      ux = a.ux[k];
+      uy = a.uy[k];
+    }
+    local(BoolC<INT || EDGE>(), lx, ly, i, j, s, ux, uy);
   });
+  if constexpr (EDGE)
+    ring_loop(g, x0, y0, tw, th, [&](int i, int j) {
+      const int k = j * g.nx + i;
+      local(BoolC<false>(), i - x0, j - y0, i, j, a.inv1pa[k], a.ux[k], a.uy[k]);
+    });
 }
 
 template <typename R, bool TH, int TY>
@@ -1255,8 +1407,16 @@ __global__ __launch_bounds__(NTHREADS) void alks_step2_kernel(Geo g, AdjArgs<R> 
   int x0, x1, y0, y1, tile;
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
   const int tw = x1 - x0, th = y1 - y0;
-  if (tw == TX && th == TY) alks_tile2<R, TH, TY, true>(g, a, L, x0, y0, tw, th);
-  else alks_tile2<R, TH, TY, false>(g, a, L, x0, y0, tw, th);
+  if (tw != TX || th != TY) {
+    if (g.periodic) alks_tile2<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
+    else alks_tile2<R, TH, TY, false, K_EDGE>(g, a, L, x0, y0, tw, th);
+  } else if (interior_tile2(g, x0, x1, y0, y1)) {
+    alks_tile2<R, TH, TY, true, K_INT>(g, a, L, x0, y0, tw, th);
+  } else if (g.periodic) {
+    alks_tile2<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
+  } else {
+    alks_tile2<R, TH, TY, true, K_EDGE>(g, a, L, x0, y0, tw, th);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1289,12 +1449,16 @@ __global__ __launch_bounds__(NTHREADS) void lks_step_batch_kernel(const BatchFwd
   int x0, x1, y0, y1;
   tile_box(g, lt, &x0, &x1, &y0, &y1);
   const int tw = x1 - x0, th = y1 - y0;
-  if (tw != TX || th != TY)
-    lks_tile<R, TH, TY, false, false>(g, a, L, x0, y0, tw, th, lt);
-  else if (interior_tile(g, x0, x1, y0, y1))
-    lks_tile<R, TH, TY, true, true>(g, a, L, x0, y0, tw, th, lt);
-  else
-    lks_tile<R, TH, TY, true, false>(g, a, L, x0, y0, tw, th, lt);
+  if (tw != TX || th != TY) {
+    if (g.periodic) lks_tile<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th, lt);
+    else lks_tile<R, TH, TY, false, K_EDGE>(g, a, L, x0, y0, tw, th, lt);
+  } else if (interior_tile(g, x0, x1, y0, y1)) {
+    lks_tile<R, TH, TY, true, K_INT>(g, a, L, x0, y0, tw, th, lt);
+  } else if (g.periodic) {
+    lks_tile<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th, lt);
+  } else {
+    lks_tile<R, TH, TY, true, K_EDGE>(g, a, L, x0, y0, tw, th, lt);
+  }
 }
 
 template <typename R, bool TH, int TY>
@@ -1313,12 +1477,16 @@ __global__ __launch_bounds__(NTHREADS) void alks_step_batch_kernel(const BatchAd
   int x0, x1, y0, y1;
   tile_box(g, lt, &x0, &x1, &y0, &y1);
   const int tw = x1 - x0, th = y1 - y0;
-  if (tw != TX || th != TY)
-    alks_tile<R, TH, TY, false, false>(g, a, L, x0, y0, tw, th);
-  else if (interior_tile(g, x0, x1, y0, y1))
-    alks_tile<R, TH, TY, true, true>(g, a, L, x0, y0, tw, th);
-  else
-    alks_tile<R, TH, TY, true, false>(g, a, L, x0, y0, tw, th);
+  if (tw != TX || th != TY) {
+    if (g.periodic) alks_tile<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
+    else alks_tile<R, TH, TY, false, K_EDGE>(g, a, L, x0, y0, tw, th);
+  } else if (interior_tile(g, x0, x1, y0, y1)) {
+    alks_tile<R, TH, TY, true, K_INT>(g, a, L, x0, y0, tw, th);
+  } else if (g.periodic) {
+    alks_tile<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
+  } else {
+    alks_tile<R, TH, TY, true, K_EDGE>(g, a, L, x0, y0, tw, th);
+  }
 }
 
 // pressure drop of every design on its current level: one block per design
