@@ -284,10 +284,10 @@ void launch_probe_T(const Geo& g, const uint8_t* mask, const R* T, double* out, 
 template <typename R>
 void launch_source_heat(const Geo& g, const R* beta, const R* T, double* out, hipStream_t s);
 template <typename R>
-void launch_lks_step_batch(const BatchFwd<R>* d, const int* tile0, int nd, int total, int ty,
+void launch_lks_step_batch(const BatchFwd<R>* d, const int* tmap, int total, int ty,
                            bool thermal, int parity, hipStream_t s);
 template <typename R>
-void launch_alks_step_batch(const BatchAdj<R>* d, const int* tile0, int nd, int total, int ty,
+void launch_alks_step_batch(const BatchAdj<R>* d, const int* tmap, int total, int ty,
                             bool thermal, int parity, int last, hipStream_t s);
 template <typename R>
 void launch_pressure_drop_batch(const BatchFwd<R>* d, int nd, int parity, double* out,

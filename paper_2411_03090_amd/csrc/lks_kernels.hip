@@ -1422,30 +1422,21 @@ __global__ __launch_bounds__(NTHREADS) void alks_step2_kernel(Geo g, AdjArgs<R> 
 // ---------------------------------------------------------------------------
 // batched steps: many independent designs in one launch
 // ---------------------------------------------------------------------------
-// Block b runs global tile xcd_tile(total); the design owning it is found by
-// binary search over the designs' first global tiles. All designs advance
-// in lockstep, so one parity selects the ping-pong buffers of every design.
-__device__ inline int design_of(const int* tile0, int nd, int t) {
-  int lo = 0, hi = nd - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tile0[mid] <= t) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
+// Block b runs global tile xcd_tile(total); the host-built table tmap holds,
+// for every global tile, its design and its tile index within the design.
+// All designs advance in lockstep, so one parity selects the ping-pong
+// buffers of every design.
 template <typename R, bool TH, int TY>
 __global__ __launch_bounds__(NTHREADS) void lks_step_batch_kernel(const BatchFwd<R>* __restrict__ d,
-                                                                  const int* __restrict__ tile0,
-                                                                  int nd, int total, int parity) {
+                                                                  const int* __restrict__ tmap,
+                                                                  int total, int parity) {
   __shared__ FwdLds<R, TH, TY> L;
   const int t = xcd_tile(total);
   if (t < 0) return;
-  const int di = design_of(tile0, nd, t);
+  const int di = tmap[2 * t];
   const Geo g = d[di].g;
   const FwdArgs<R> a = d[di].a[parity];
-  const int lt = t - tile0[di];
+  const int lt = tmap[2 * t + 1];
   int x0, x1, y0, y1;
   tile_box(g, lt, &x0, &x1, &y0, &y1);
   const int tw = x1 - x0, th = y1 - y0;
@@ -1463,17 +1454,17 @@ __global__ __launch_bounds__(NTHREADS) void lks_step_batch_kernel(const BatchFwd
 
 template <typename R, bool TH, int TY>
 __global__ __launch_bounds__(NTHREADS) void alks_step_batch_kernel(const BatchAdj<R>* __restrict__ d,
-                                                                   const int* __restrict__ tile0,
-                                                                   int nd, int total, int parity,
+                                                                   const int* __restrict__ tmap,
+                                                                   int total, int parity,
                                                                    int last) {
   __shared__ AdjLds<R, TH, TY> L;
   const int t = xcd_tile(total);
   if (t < 0) return;
-  const int di = design_of(tile0, nd, t);
+  const int di = tmap[2 * t];
   const Geo g = d[di].g;
   AdjArgs<R> a = d[di].a[parity];
   a.sens_mode = last ? 2 : 0;
-  const int lt = t - tile0[di];
+  const int lt = tmap[2 * t + 1];
   int x0, x1, y0, y1;
   tile_box(g, lt, &x0, &x1, &y0, &y1);
   const int tw = x1 - x0, th = y1 - y0;
@@ -1697,40 +1688,40 @@ void launch_source_heat(const Geo& g, const R* beta, const R* T, double* out, hi
   source_heat_kernel<R><<<1, NTHREADS, 0, s>>>(g, beta, T, out);
 }
 template <typename R>
-void launch_lks_step_batch(const BatchFwd<R>* d, const int* tile0, int nd, int total, int ty,
+void launch_lks_step_batch(const BatchFwd<R>* d, const int* tmap, int total, int ty,
                            bool thermal, int parity, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(total));
   if constexpr (std::is_same<R, float>::value) {
     if (ty == 16 && !thermal) {
-      lks_step_batch_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
+      lks_step_batch_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity);
       return;
     }
   }
   if (ty == 8) {
-    if (thermal) lks_step_batch_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
-    else lks_step_batch_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
+    if (thermal) lks_step_batch_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity);
+    else lks_step_batch_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity);
   } else {
-    if (thermal) lks_step_batch_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
-    else lks_step_batch_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity);
+    if (thermal) lks_step_batch_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity);
+    else lks_step_batch_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity);
   }
 }
 template <typename R>
-void launch_alks_step_batch(const BatchAdj<R>* d, const int* tile0, int nd, int total, int ty,
+void launch_alks_step_batch(const BatchAdj<R>* d, const int* tmap, int total, int ty,
                             bool thermal, int parity, int last, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(total));
   if constexpr (std::is_same<R, float>::value) {
     if (ty == 16 && !thermal) {
-      alks_step_batch_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity,
+      alks_step_batch_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity,
                                                                        last);
       return;
     }
   }
   if (ty == 8) {
-    if (thermal) alks_step_batch_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity, last);
-    else alks_step_batch_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity, last);
+    if (thermal) alks_step_batch_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity, last);
+    else alks_step_batch_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity, last);
   } else {
-    if (thermal) alks_step_batch_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity, last);
-    else alks_step_batch_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(d, tile0, nd, total, parity, last);
+    if (thermal) alks_step_batch_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity, last);
+    else alks_step_batch_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity, last);
   }
 }
 template <typename R>
@@ -1777,9 +1768,9 @@ void launch_finite_check(const R* a, size_t n, int* flag, hipStream_t s) {
   template void launch_source_heat<R>(const Geo&, const R*, const R*, double*, hipStream_t);  \
   template void launch_probe_T<R>(const Geo&, const uint8_t*, const R*, double*, hipStream_t); \
   template void launch_fill_r<R>(R*, size_t, hipStream_t);                                    \
-  template void launch_lks_step_batch<R>(const BatchFwd<R>*, const int*, int, int, int, bool, int, \
+  template void launch_lks_step_batch<R>(const BatchFwd<R>*, const int*, int, int, bool, int,      \
                                          hipStream_t);                                        \
-  template void launch_alks_step_batch<R>(const BatchAdj<R>*, const int*, int, int, int, bool, int, \
+  template void launch_alks_step_batch<R>(const BatchAdj<R>*, const int*, int, int, bool, int,     \
                                           int, hipStream_t);                                  \
   template void launch_pressure_drop_batch<R>(const BatchFwd<R>*, int, int, double*, hipStream_t); \
   template void launch_to_double<R>(const R*, double*, size_t, hipStream_t);                  \

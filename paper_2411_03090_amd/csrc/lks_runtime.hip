@@ -1540,8 +1540,10 @@ struct lks_batch {
   char* ws = nullptr;
   std::vector<int> tile0;
   int total_tiles = 0;
+  int max_tiles = 0;        // tiles of all designs at the shortest tile height
+  std::vector<int> tmap;    // (design, tile within the design) of every global tile
   // device
-  int* d_tile0 = nullptr;
+  int* d_tmap = nullptr;
   void* d_fwd = nullptr;     // BatchFwd<R>[n]
   void* d_adj = nullptr;     // BatchAdj<R>[3 n]: parities 0, 1 and the zero-input first step
   double* d_J = nullptr;
@@ -1563,6 +1565,19 @@ lks_status bfail(lks_batch* b, lks_status s, const std::string& msg) {
   if (b) b->err = msg;
   else g_create_error = msg;
   return s;
+}
+
+// (design, tile within the design) of every global tile at the current tile
+// height: the batched kernels look their tile up with one load
+void build_tile_map(lks_batch* b) {
+  b->tmap.assign(2 * size_t(b->total_tiles), 0);
+  for (int d = 0; d < b->n; ++d) {
+    const int nt = n_tiles(b->ctx[d]->geo);
+    for (int t = 0; t < nt; ++t) {
+      b->tmap[2 * size_t(b->tile0[d] + t)] = d;
+      b->tmap[2 * size_t(b->tile0[d] + t) + 1] = t;
+    }
+  }
 }
 
 template <typename R>
@@ -1639,11 +1654,11 @@ void enqueue_batch_steps(lks_batch* b, int nf, int na, hipStream_t s) {
   auto* F = static_cast<const lks::BatchFwd<R>*>(b->d_fwd);
   auto* Aj = static_cast<const lks::BatchAdj<R>*>(b->d_adj);
   for (int k = 0; k < nf; ++k)
-    lks::launch_lks_step_batch<R>(F, b->d_tile0, b->n, b->total_tiles, b->ty, b->thermal, k & 1, s);
+    lks::launch_lks_step_batch<R>(F, b->d_tmap, b->total_tiles, b->ty, b->thermal, k & 1, s);
   lks::launch_pressure_drop_batch<R>(F, b->n, nf & 1, b->d_J, s);
   for (int k = 0; k < na; ++k) {
     const lks::BatchAdj<R>* D = k == 0 ? Aj + 2 * b->n : Aj;
-    lks::launch_alks_step_batch<R>(D, b->d_tile0, b->n, b->total_tiles, b->ty, b->thermal, k & 1,
+    lks::launch_alks_step_batch<R>(D, b->d_tmap, b->total_tiles, b->ty, b->thermal, k & 1,
                                    k == na - 1, s);
   }
 }
@@ -1686,6 +1701,7 @@ lks_status lks_batch_create(int n, const lks_grid* grids, const lks_phys* phys, 
     off += align256(c->plan.total);
     b->tile0.push_back(b->total_tiles);
     b->total_tiles += n_tiles(c->geo);
+    b->max_tiles += max_tiles(c->geo);
     b->maxN = std::max(b->maxN, size_t(c->geo.N));
     b->ty = c->geo.ty;
   }
@@ -1693,7 +1709,8 @@ lks_status lks_batch_create(int n, const lks_grid* grids, const lks_phys* phys, 
   b->thermal = phys[0].thermal ? 1 : 0;
   const size_t fwd = sizeof(lks::BatchFwd<double>) * n;   // the double variant is the larger
   const size_t adj = sizeof(lks::BatchAdj<double>) * 3 * n;
-  off += align256(sizeof(int) * n) + align256(fwd) + align256(adj) + align256(sizeof(double) * n);
+  off += align256(sizeof(int) * 2 * size_t(b->max_tiles)) + align256(fwd) + align256(adj) +
+         align256(sizeof(double) * n);
   off += align256(sizeof(double) * b->maxN * n) + align256(size_t(b->rsz) * b->maxN);
   b->total = off;
   *out = b;
@@ -1722,7 +1739,7 @@ lks_status lks_batch_bind_workspace(lks_batch* b, void* dev_ptr, size_t bytes) {
     p += align256(s);
     return q;
   };
-  b->d_tile0 = reinterpret_cast<int*>(take(sizeof(int) * b->n));
+  b->d_tmap = reinterpret_cast<int*>(take(sizeof(int) * 2 * size_t(b->max_tiles)));
   b->d_fwd = take(sizeof(lks::BatchFwd<double>) * b->n);
   b->d_adj = take(sizeof(lks::BatchAdj<double>) * 3 * b->n);
   b->d_J = reinterpret_cast<double*>(take(sizeof(double) * b->n));
@@ -1732,7 +1749,8 @@ lks_status lks_batch_bind_workspace(lks_batch* b, void* dev_ptr, size_t bytes) {
   hipStream_t s = b->user;
   if (b->rsz == 8) lks::launch_fill_r<double>(static_cast<double*>(b->d_zero), b->maxN, s);
   else lks::launch_fill_r<float>(static_cast<float*>(b->d_zero), b->maxN, s);
-  if (!hip_ok(nullptr, hipMemcpyAsync(b->d_tile0, b->tile0.data(), sizeof(int) * b->n,
+  build_tile_map(b);
+  if (!hip_ok(nullptr, hipMemcpyAsync(b->d_tmap, b->tmap.data(), sizeof(int) * b->tmap.size(),
                                       hipMemcpyHostToDevice, s), "upload tiles", &st) ||
       !hip_ok(nullptr, hipStreamSynchronize(s), "bind sync", &st))
     return bfail(b, st, g_create_error);
@@ -1862,8 +1880,11 @@ static lks_status batch_set_tile_rows(lks_batch* b, int ty) {
     b->graph = nullptr;
   }
   lks_status st = LKS_OK;
+  build_tile_map(b);
+  // the upload is ordered before every later launch on the user stream;
+  // the host table stays alive with the batch
   if (b->bound &&
-      !hip_ok(nullptr, hipMemcpyAsync(b->d_tile0, b->tile0.data(), sizeof(int) * b->n,
+      !hip_ok(nullptr, hipMemcpyAsync(b->d_tmap, b->tmap.data(), sizeof(int) * b->tmap.size(),
                                       hipMemcpyHostToDevice, b->user), "upload tiles", &st))
     return bfail(b, st, g_create_error);
   return LKS_OK;
