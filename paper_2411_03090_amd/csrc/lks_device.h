@@ -218,6 +218,8 @@ struct Adj3Args {
   R* p1[5];            // level n
   R* m;                // moments: rho~, u~ (3), s~ (6), T~, q~ (3); 14 N (10 N without T)
   const FaceOp3* ops;  // -x, +x, -y, +y, -z, +z
+  const int* face;     // boundary nodes: faces by orientation, then edges and corners
+  int nface;
   double* sens;
   int sens_mode;       // 0 none, 1 accumulate, 2 overwrite
   int exact;           // 1: exact discrete adjoint of the Brinkman step
@@ -234,6 +236,10 @@ int zblocks3(const Geo3& g);
 void zplan3(Geo3& g, int rsz);
 // edge and corner nodes in increasing order (out may be null); returns the count
 int copy_nodes3(const Geo3& g, int* out);
+// boundary nodes of the non-periodic axes (out may be null): the face nodes
+// of orientation 0..5 (-x, +x, -y, +y, -z, +z) in increasing order, then the
+// edge and corner nodes; returns the count
+int face_nodes3(const Geo3& g, int* out);
 template <typename R>
 void launch_coef3(const Geo3& g, const uint8_t* mask, const double* gamma, double alpha_max,
                   double q_alpha, double Kf, double Ks, double qK, R* inv1pa, R* B, R* dA3,

@@ -21,6 +21,8 @@
 // keeping the neighbour planes of a block in that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "lks_device.h"
 
 namespace lks {
@@ -825,17 +827,18 @@ __device__ inline void adj_local(const Adj3Args<R>& a, int k, int m, int ne, R T
 }
 
 // moments of the node p (not an edge or corner node) with orientation o if
-// it is a face node
-template <typename R, bool TH>
+// it is a face node; FACE = false compiles the interior rule alone (ne = 0)
+template <typename R, bool TH, bool FACE = true>
 __device__ void alks3_node(const Geo3& g, const Adj3Args<R>& a, P3 p, int k, int ne, int o,
                            R M[14]) {
+  if constexpr (!FACE) ne = 0;
   const int ax = o >> 1, sg = (o & 1) ? 1 : -1;
   R f[19], gq[19];
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
     const int cq[3] = {QX[q], QY[q], QZ[q]};
     int cn = 0;
-    if (ne) cn = sg * (ax == 0 ? cq[0] : (ax == 1 ? cq[1] : cq[2]));
+    if (FACE && ne) cn = sg * (ax == 0 ? cq[0] : (ax == 1 ? cq[1] : cq[2]));
     f[q] = R(0);
     gq[q] = R(0);
     if (cn > 0) continue;
@@ -850,15 +853,38 @@ __device__ void alks3_node(const Geo3& g, const Adj3Args<R>& a, P3 p, int k, int
   mom19<R, TH>(f, gq, M);
   const int m = a.mask[k];
   const R Tn = TH ? a.T[k] : R(0);
-  if (ne) face_fill<R, TH>(a, k, m, o, Tn, f, gq, M);
+  if constexpr (FACE)
+    if (ne) face_fill<R, TH>(a, k, m, o, Tn, f, gq, M);
   // exact mode: u~ stays undivided; the update pass divides V instead
   adj_local<R, TH>(a, k, m, ne, Tn, a.exact ? R(1) : a.inv1pa[k], M);
 }
 
+// ALKS pass 1 at the interior nodes; the boundary nodes are left to
+// alks3_face_kernel, so the face completion does not diverge inside the
+// waves of the rows that end on an x face
 template <typename R, bool TH>
 __global__ __launch_bounds__(NT3) void alks3_pull_kernel(Geo3 g, Adj3Args<R> a) {
   const int k = node3(g.N);
   if (k < 0) return;
+  const P3 p = decode(g, k);
+  int o;
+  if (ends(g, p, &o)) return;
+  R mom[14];
+  alks3_node<R, TH, false>(g, a, p, k, 0, -1, mom);
+  const size_t N = size_t(g.N);
+  constexpr int NM = TH ? 14 : 10;
+#pragma unroll
+  for (int c = 0; c < NM; ++c) a.m[c * N + k] = mom[c];
+}
+
+// ALKS pass 1 at the boundary nodes of the host-built list (faces grouped by
+// orientation, then edges and corners, which take the moments of the node
+// one step inwards along y and z)
+template <typename R, bool TH>
+__global__ __launch_bounds__(NT3) void alks3_face_kernel(Geo3 g, Adj3Args<R> a) {
+  const int t = int(blockIdx.x) * NT3 + int(threadIdx.x);
+  if (t >= a.nface) return;
+  const int k = a.face[t];
   const P3 p = decode(g, k);
   int o;
   const int ne = ends(g, p, &o);
@@ -1174,6 +1200,30 @@ int copy_nodes3(const Geo3& g, int* out) {
   return n;
 }
 
+int face_nodes3(const Geo3& g, int* out) {
+  const int n3[3] = {g.nx, g.ny, g.nz};
+  std::vector<int> bucket[7];  // orientations 0..5, then edges and corners
+  for (int l = 0; l < g.nz; ++l)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        const int c[3] = {i, j, l};
+        int ne = 0, o = -1;
+        for (int ax = 0; ax < 3; ++ax) {
+          if ((g.periodic >> ax) & 1) continue;
+          if (c[ax] == 0) { ++ne; o = 2 * ax; }
+          else if (c[ax] == n3[ax] - 1) { ++ne; o = 2 * ax + 1; }
+        }
+        if (ne) bucket[ne >= 2 ? 6 : o].push_back((l * g.ny + j) * g.nx + i);
+      }
+  int n = 0;
+  for (const auto& v : bucket)
+    for (int k : v) {
+      if (out) out[n] = k;
+      ++n;
+    }
+  return n;
+}
+
 template <typename R>
 void launch_coef3(const Geo3& g, const uint8_t* mask, const double* gamma, double alpha_max,
                   double q_alpha, double Kf, double Ks, double qK, R* inv1pa, R* B, R* dA3,
@@ -1212,11 +1262,14 @@ void launch_alks3_step(const Geo3& g0, const Adj3Args<R>& a, hipStream_t s) {
   g.zc = g0.zca;
   const unsigned nb = unsigned(blocks3(g.N));
   const unsigned nz = unsigned(NXCD * ((zblocks3(g) + NXCD - 1) / NXCD));
+  const unsigned nf = unsigned((a.nface + NT3 - 1) / NT3);
   if (g.thermal) {
     alks3_pull_kernel<R, true><<<nb, NT3, 0, s>>>(g, a);
+    if (a.nface) alks3_face_kernel<R, true><<<nf, NT3, 0, s>>>(g, a);
     alks3e_kernel<R, true><<<nz, ZT, 0, s>>>(g, a);
   } else {
     alks3_pull_kernel<R, false><<<nb, NT3, 0, s>>>(g, a);
+    if (a.nface) alks3_face_kernel<R, false><<<nf, NT3, 0, s>>>(g, a);
     alks3e_kernel<R, false><<<nz, ZT, 0, s>>>(g, a);
   }
 }

@@ -95,8 +95,9 @@ struct lks_ctx {
   lks::FaceOp3* d_ops3 = nullptr;  // D3Q19 face operators (6 orientations)
   lks::FaceOp3 ops3[6];
   int* copy3 = nullptr;  // D3Q19 edge and corner nodes (device)
+  int* face3 = nullptr;  // D3Q19 boundary nodes by orientation (device)
   void* M3 = nullptr;    // D3Q19 adjoint moments of one step
-  std::vector<int> copy3h;
+  std::vector<int> copy3h, face3h;
   double* acc = nullptr; // per-tile objective accumulators
   double* scal = nullptr;
   int* flag = nullptr;
@@ -188,6 +189,7 @@ size_t base_bytes(const lks_ctx* c) {
   if (c->dim == 3) {
     b += align256(6 * sizeof(lks::FaceOp3));  // face operators
     b += align256(sizeof(int) * c->copy3h.size());  // edge and corner nodes
+    b += align256(sizeof(int) * c->face3h.size());  // boundary nodes
     b += align256(size_t(moments3_fields(c)) * N * r);
   } else {
     b += align256(4 * sizeof(lks::RingOp));   // ring operators
@@ -828,6 +830,8 @@ struct Run {
       }
       a.m = rp<R>(c->M3);
       a.ops = c->d_ops3;
+      a.face = c->face3;
+      a.nface = int(c->face3h.size());
       a.sens = sens;
       a.sens_mode = sens ? mode : 0;
       a.exact = c->adj_exact;
@@ -1095,6 +1099,8 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
     lks::build_face_ops3(g3.A, g3.Bf, c->ops3);
     c->copy3h.resize(size_t(lks::copy_nodes3(g3, nullptr)));
     lks::copy_nodes3(g3, c->copy3h.data());
+    c->face3h.resize(size_t(lks::face_nodes3(g3, nullptr)));
+    lks::face_nodes3(g3, c->face3h.data());
   }
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->budget = mem_budget_bytes;
@@ -1153,6 +1159,7 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
   if (nu == 3) {
     c->d_ops3 = reinterpret_cast<lks::FaceOp3*>(take(6 * sizeof(lks::FaceOp3)));
     c->copy3 = reinterpret_cast<int*>(take(sizeof(int) * c->copy3h.size()));
+    c->face3 = reinterpret_cast<int*>(take(sizeof(int) * c->face3h.size()));
     c->M3 = take(size_t(moments3_fields(c)) * N * r);
   } else {
     c->d_ops = reinterpret_cast<lks::RingOp*>(take(4 * sizeof(lks::RingOp)));
@@ -1187,7 +1194,10 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
                                  c->stream), "upload face operators", &st) &&
             hip_ok(c, hipMemcpyAsync(c->copy3, c->copy3h.data(), sizeof(int) * c->copy3h.size(),
                                      hipMemcpyHostToDevice, c->stream),
-                   "upload edge nodes", &st)
+                   "upload edge nodes", &st) &&
+            hip_ok(c, hipMemcpyAsync(c->face3, c->face3h.data(), sizeof(int) * c->face3h.size(),
+                                     hipMemcpyHostToDevice, c->stream),
+                   "upload boundary nodes", &st)
       : hip_ok(c, hipMemcpyAsync(c->d_ops, c->ops, sizeof c->ops, hipMemcpyHostToDevice,
                                  c->stream), "upload ring operators", &st);
   if (!ops_ok ||
