@@ -5,6 +5,7 @@
 // Sec. 2.5.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace lks {
@@ -67,19 +68,47 @@ __host__ __device__ inline int xcd_blocks(int tiles) {
 //   zero-flux node with normal velocity u_n:
 //     kappa = -(sum_q (ga_q - u_n ge_q) g_q) / (A0 - 2 u_n A1 + u_n^2 A2)
 //     g_unk[a] = sum_q Lg0[a][q] g_q - kappa (hc[a] - u_n h1[a])
-struct RingOp {
-  double Lf[2][3][9];
-  double Ls[2][3];
-  double Lk[2][3];
-  double Ld[3][9];
-  double Lg0[3][9];
-  double ga[9], ge[9];
-  double A0, A1, A2;
-  double hc[3], h1[3];
-  double uw[3], ucx[3], ucy[3];  // weight and velocity of the unknown directions
+// The kernels read a copy rounded to their arithmetic type (RingOpT<R>),
+// which is what they used to form from the double entries at every use.
+template <typename T>
+struct RingOpT {
+  T Lf[2][3][9];
+  T Ls[2][3];
+  T Lk[2][3];
+  T Ld[3][9];
+  T Lg0[3][9];
+  T ga[9], ge[9];
+  T A0, A1, A2;
+  T hc[3], h1[3];
+  T uw[3], ucx[3], ucy[3];  // weight and velocity of the unknown directions
   int unk[3];
   int pad;
 };
+using RingOp = RingOpT<double>;
+
+// element-wise conversion of operator tables (host)
+template <typename D, typename S>
+inline void conv_op(D& d, const S& s) { d = D(s); }
+template <typename D, typename S, size_t N>
+inline void conv_op(D (&d)[N], const S (&s)[N]) {
+  for (size_t i = 0; i < N; ++i) conv_op(d[i], s[i]);
+}
+template <typename R>
+inline RingOpT<R> ring_op_as(const RingOp& s) {
+  RingOpT<R> d{};
+  conv_op(d.Lf, s.Lf); conv_op(d.Ls, s.Ls); conv_op(d.Lk, s.Lk); conv_op(d.Ld, s.Ld);
+  conv_op(d.Lg0, s.Lg0); conv_op(d.ga, s.ga); conv_op(d.ge, s.ge); conv_op(d.A0, s.A0);
+  conv_op(d.A1, s.A1); conv_op(d.A2, s.A2); conv_op(d.hc, s.hc); conv_op(d.h1, s.h1);
+  conv_op(d.uw, s.uw); conv_op(d.ucx, s.ucx); conv_op(d.ucy, s.ucy); conv_op(d.unk, s.unk);
+  return d;
+}
+
+// A pointer read through the constant address space: a load whose address
+// is the same in every lane then goes through the scalar unit (read only).
+template <typename T>
+__device__ inline const __attribute__((address_space(4))) T* as_scalar(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
 
 template <typename R>
 struct FwdArgs {
@@ -123,7 +152,7 @@ struct AdjArgs {
   R* vx1;
   R* vy1;
   R* th1;
-  const RingOp* ops;  // 4 ring orientations: -x, +x, -y, +y
+  const RingOpT<R>* ops;  // 4 ring orientations: -x, +x, -y, +y
   double* sens;  // dJ/dgamma (double)
   int sens_mode; // 0 none, 1 accumulate, 2 overwrite
   int exact;     // 1: exact discrete adjoint of the Brinkman step
@@ -171,19 +200,30 @@ struct Geo3 {
 
 // Least-squares completion operators of a face orientation o = 2 axis +
 // (n = +e_axis), the D3Q19 counterpart of RingOp with five unknowns.
-struct FaceOp3 {
-  double Lf[2][5][19];
-  double Ls[2][5];
-  double Lk[2][5];
-  double Ld[5][19];
-  double Lg0[5][19];
-  double ga[19], ge[19];
-  double A0, A1, A2;
-  double hc[5], h1[5];
-  double uw[5], uc[5][3];
+template <typename T>
+struct FaceOpT {
+  T Lf[2][5][19];
+  T Ls[2][5];
+  T Lk[2][5];
+  T Ld[5][19];
+  T Lg0[5][19];
+  T ga[19], ge[19];
+  T A0, A1, A2;
+  T hc[5], h1[5];
+  T uw[5], uc[5][3];
   int unk[5];
   int pad[3];
 };
+using FaceOp3 = FaceOpT<double>;
+template <typename R>
+inline FaceOpT<R> face_op_as(const FaceOp3& s) {
+  FaceOpT<R> d{};
+  conv_op(d.Lf, s.Lf); conv_op(d.Ls, s.Ls); conv_op(d.Lk, s.Lk); conv_op(d.Ld, s.Ld);
+  conv_op(d.Lg0, s.Lg0); conv_op(d.ga, s.ga); conv_op(d.ge, s.ge); conv_op(d.A0, s.A0);
+  conv_op(d.A1, s.A1); conv_op(d.A2, s.A2); conv_op(d.hc, s.hc); conv_op(d.h1, s.h1);
+  conv_op(d.uw, s.uw); conv_op(d.uc, s.uc); conv_op(d.unk, s.unk);
+  return d;
+}
 void build_face_ops3(double A, double Bf, FaceOp3 ops[6]);
 
 // fields of the forward state: drho, ux, uy, uz, T
@@ -217,7 +257,7 @@ struct Adj3Args {
   const R* p0[5];      // level n+1
   R* p1[5];            // level n
   R* m;                // moments: rho~, u~ (3), s~ (6), T~, q~ (3); 14 N (10 N without T)
-  const FaceOp3* ops;  // -x, +x, -y, +y, -z, +z
+  const FaceOpT<R>* ops;  // -x, +x, -y, +y, -z, +z
   const int* face;     // boundary nodes: faces by orientation, then edges and corners
   int nface;
   double* sens;

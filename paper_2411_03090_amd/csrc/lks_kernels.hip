@@ -678,29 +678,11 @@ __global__ __launch_bounds__(NTHREADS) void lks_step_kernel(Geo g, FwdArgs<R> a)
 // ---------------------------------------------------------------------------
 // ALKS step
 // ---------------------------------------------------------------------------
-// Least-squares completion of the adjoint populations at a ring node (see
-// RingOp): the known populations f~_i = rho~ + c_i.V and g~_i = Theta at
-// x + c_i come from LDS (the unknown directions point outside the domain,
-// where LDS holds zeros); returns the raw moments rho~, U~, s~ (xx, xy, yy),
-// T~, q~ of the completed set.
-template <typename R, bool TH, int W2>
-__device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, const R* svx,
-                             const R* svy, const R* sth, const R* sTn, int p2, int i, int j,
-                             int k, int m, R mom[9]) {
-  const int o = (i == 0) ? 0 : (i == g.nx - 1 ? 1 : (j == 0 ? 2 : 3));
-  const RingOp& op = a.ops[o];
-  R f[9], gq[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const int p = p2 + CX[q] + CY[q] * W2;
-    R e = sr[p];
-    if (CX[q] > 0) e += svx[p];
-    if (CX[q] < 0) e -= svx[p];
-    if (CY[q] > 0) e += svy[p];
-    if (CY[q] < 0) e -= svy[p];
-    f[q] = e;
-    if constexpr (TH) gq[q] = sth[p];
-  }
+// the completion of ring_moments with the operator op of orientation o and
+// flow type v (0 velocity, 1 pressure node)
+template <typename R, bool TH, typename OP>
+__device__ inline void ring_apply(OP op, int v, int o, const AdjArgs<R>& a, const R* sTn, int p2,
+                                  int k, int m, const R f[9], const R gq[9], R mom[9]) {
   R kappa = R(0), gu[3] = {R(0), R(0), R(0)};
   if constexpr (TH) {
     if (((m >> 2) & 3) == THERM_DIRICHLET) {
@@ -708,7 +690,7 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
       for (int c = 0; c < 3; ++c) {
         R t = R(0);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) t += R(op.Ld[c][q]) * gq[q];
+        for (int q = 0; q < 9; ++q) t += op->Ld[c][q] * gq[q];
         gu[c] = t;
       }
     } else {
@@ -719,31 +701,30 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
       // the Schur form it enters kappa through sum_r (Q v)_r = A1 - u_n A2
       // and the unknowns through h1
       const R st = (m & TAG_PROBE) ? R(a.seed_bt) : R(0);
-      R num = st * (R(op.A1) - un * R(op.A2));
+      R num = st * (op->A1 - un * op->A2);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) num += (R(op.ga[q]) - un * R(op.ge[q])) * gq[q];
-      const R den = R(op.A0) - R(2) * un * R(op.A1) + un * un * R(op.A2);
+      for (int q = 0; q < 9; ++q) num += (op->ga[q] - un * op->ge[q]) * gq[q];
+      const R den = op->A0 - R(2) * un * op->A1 + un * un * op->A2;
       kappa = -num / den;
 #pragma nounroll
       for (int c = 0; c < 3; ++c) {
         R t = R(0);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) t += R(op.Lg0[c][q]) * gq[q];
-        gu[c] = t - st * R(op.h1[c]) - kappa * (R(op.hc[c]) - un * R(op.h1[c]));
+        for (int q = 0; q < 9; ++q) t += op->Lg0[c][q] * gq[q];
+        gu[c] = t - st * op->h1[c] - kappa * (op->hc[c] - un * op->h1[c]);
       }
     }
   }
   R s = R(0);
   if (m & TAG_J_INLET) s += R(a.seed_dp / 3.0);
   if (m & TAG_J_OUTLET) s -= R(a.seed_dp / 3.0);
-  const int v = (m & 3) == FLOW_VELOCITY ? 0 : 1;
   const R kT = TH ? kappa * sTn[p2] : R(0);
   R fu[3];
 #pragma nounroll
   for (int c = 0; c < 3; ++c) {
-    R t = R(op.Ls[v][c]) * s + R(op.Lk[v][c]) * kT;
+    R t = op->Ls[v][c] * s + op->Lk[v][c] * kT;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) t += R(op.Lf[v][c][q]) * f[q];
+    for (int q = 0; q < 9; ++q) t += op->Lf[v][c][q] * f[q];
     fu[c] = t;
   }
   R r = R(0), Ux = R(0), Uy = R(0), sxx = R(0), sxy = R(0), syy = R(0);
@@ -766,8 +747,8 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const R cx = R(op.ucx[c]), cy = R(op.ucy[c]);
-    const R wf = R(op.uw[c]) * fu[c];
+    const R cx = op->ucx[c], cy = op->ucy[c];
+    const R wf = op->uw[c] * fu[c];
     r += wf;
     Ux += cx * wf;
     Uy += cy * wf;
@@ -775,7 +756,7 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
     sxy += cx * cy * wf;
     syy += cy * cy * wf;
     if constexpr (TH) {
-      const R wg = R(op.uw[c]) * gu[c];
+      const R wg = op->uw[c] * gu[c];
       Tt += wg;
       qx += cx * wg;
       qy += cy * wg;
@@ -790,6 +771,40 @@ __device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, con
   mom[6] = Tt;
   mom[7] = qx;
   mom[8] = qy;
+}
+
+// Least-squares completion of the adjoint populations at a ring node (see
+// RingOp): the known populations f~_i = rho~ + c_i.V and g~_i = Theta at
+// x + c_i come from LDS (the unknown directions point outside the domain,
+// where LDS holds zeros); returns the raw moments rho~, U~, s~ (xx, xy, yy),
+// T~, q~ of the completed set.
+template <typename R, bool TH, int W2>
+__device__ void ring_moments(const Geo& g, const AdjArgs<R>& a, const R* sr, const R* svx,
+                             const R* svy, const R* sth, const R* sTn, int p2, int i, int j,
+                             int k, int m, R mom[9]) {
+  const int o = (i == 0) ? 0 : (i == g.nx - 1 ? 1 : (j == 0 ? 2 : 3));
+  const int v = (m & 3) == FLOW_VELOCITY ? 0 : 1;
+  R f[9], gq[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int p = p2 + CX[q] + CY[q] * W2;
+    R e = sr[p];
+    if (CX[q] > 0) e += svx[p];
+    if (CX[q] < 0) e -= svx[p];
+    if (CY[q] > 0) e += svy[p];
+    if (CY[q] < 0) e -= svy[p];
+    f[q] = e;
+    if constexpr (TH) gq[q] = sth[p];
+  }
+  // a wave whose lanes share orientation and node type reads the operator
+  // through the scalar unit; mixed waves read it per lane
+  const int key = 2 * o + v;
+  const int uk = __builtin_amdgcn_readfirstlane(key);
+  if (__all(key == uk))
+    ring_apply<R, TH>(as_scalar(a.ops) + (uk >> 1), uk & 1, uk >> 1, a, sTn, p2, k, m, f, gq,
+                      mom);
+  else
+    ring_apply<R, TH>(a.ops + o, v, o, a, sTn, p2, k, m, f, gq, mom);
 }
 
 // One ALKS step, adjoint level n+1 -> n. The adjoint state is kept as the

@@ -743,14 +743,12 @@ __device__ inline void mom19(const R f[19], const R g[19], R M[14]) {
   }
 }
 
-// least-squares fill of a face node with orientation o: the moments of its
-// five missing directions from the 14 received ones (zero in f, g at the
-// missing directions), the J seed and the thermal closure
-template <typename R, bool TH>
-__device__ void face_fill(const Adj3Args<R>& a, int k, int m, int o, R Tn, const R f[19],
-                          const R gq[19], R M[14]) {
+// the fill of face_fill with the operator op of orientation o and flow type
+// v (0 velocity, 1 pressure node)
+template <typename R, bool TH, typename OP>
+__device__ inline void face_apply(OP op, int v, int o, const Adj3Args<R>& a, int k, int m, R Tn,
+                                  const R f[19], const R gq[19], R M[14]) {
   const int ax = o >> 1, sg = (o & 1) ? 1 : -1;
-  const FaceOp3& op = a.ops[o];
   R kappa = R(0), gu[5] = {R(0), R(0), R(0), R(0), R(0)};
   if constexpr (TH) {
     if (((m >> 2) & 3) == THERM_DIRICHLET3) {
@@ -758,7 +756,7 @@ __device__ void face_fill(const Adj3Args<R>& a, int k, int m, int o, R Tn, const
       for (int c = 0; c < 5; ++c) {
         R t = R(0);
 #pragma unroll
-        for (int q = 0; q < 19; ++q) t += R(op.Ld[c][q]) * gq[q];
+        for (int q = 0; q < 19; ++q) t += op->Ld[c][q] * gq[q];
         gu[c] = t;
       }
     } else {
@@ -766,30 +764,29 @@ __device__ void face_fill(const Adj3Args<R>& a, int k, int m, int o, R Tn, const
       const R un = R(sg) * un_src[k];
       R num = R(0);
 #pragma unroll
-      for (int q = 0; q < 19; ++q) num += (R(op.ga[q]) - un * R(op.ge[q])) * gq[q];
-      const R den = R(op.A0) - R(2) * un * R(op.A1) + un * un * R(op.A2);
+      for (int q = 0; q < 19; ++q) num += (op->ga[q] - un * op->ge[q]) * gq[q];
+      const R den = op->A0 - R(2) * un * op->A1 + un * un * op->A2;
       kappa = -num / den;
 #pragma nounroll
       for (int c = 0; c < 5; ++c) {
         R t = R(0);
 #pragma unroll
-        for (int q = 0; q < 19; ++q) t += R(op.Lg0[c][q]) * gq[q];
-        gu[c] = t - kappa * (R(op.hc[c]) - un * R(op.h1[c]));
+        for (int q = 0; q < 19; ++q) t += op->Lg0[c][q] * gq[q];
+        gu[c] = t - kappa * (op->hc[c] - un * op->h1[c]);
       }
     }
   }
   R s = R(0);
   if (m & TAG_J_INLET3) s += R(a.seed_dp / 3.0);
   if (m & TAG_J_OUTLET3) s -= R(a.seed_dp / 3.0);
-  const int v = (m & 3) == FLOW_VELOCITY3 ? 0 : 1;
   const R kT = kappa * Tn;
 #pragma nounroll
   for (int c = 0; c < 5; ++c) {
-    R t = R(op.Ls[v][c]) * s + R(op.Lk[v][c]) * kT;
+    R t = op->Ls[v][c] * s + op->Lk[v][c] * kT;
 #pragma unroll
-    for (int q = 0; q < 19; ++q) t += R(op.Lf[v][c][q]) * f[q];
-    const R wf = R(op.uw[c]) * t;
-    const R cx[3] = {R(op.uc[c][0]), R(op.uc[c][1]), R(op.uc[c][2])};
+    for (int q = 0; q < 19; ++q) t += op->Lf[v][c][q] * f[q];
+    const R wf = op->uw[c] * t;
+    const R cx[3] = {op->uc[c][0], op->uc[c][1], op->uc[c][2]};
     M[0] += wf;
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
@@ -798,12 +795,29 @@ __device__ void face_fill(const Adj3Args<R>& a, int k, int m, int o, R Tn, const
       for (int y = x; y < 3; ++y) M[4 + SI[x][y]] += cx[x] * cx[y] * wf;
     }
     if constexpr (TH) {
-      const R wg = R(op.uw[c]) * gu[c];
+      const R wg = op->uw[c] * gu[c];
       M[10] += wg;
 #pragma unroll
       for (int x = 0; x < 3; ++x) M[11 + x] += cx[x] * wg;
     }
   }
+}
+
+// least-squares fill of a face node with orientation o: the moments of its
+// five missing directions from the 14 received ones (zero in f, g at the
+// missing directions), the J seed and the thermal closure. A wave whose
+// lanes share orientation and node type reads the operator through the
+// scalar unit; mixed waves read it per lane.
+template <typename R, bool TH>
+__device__ void face_fill(const Adj3Args<R>& a, int k, int m, int o, R Tn, const R f[19],
+                          const R gq[19], R M[14]) {
+  const int v = (m & 3) == FLOW_VELOCITY3 ? 0 : 1;
+  const int key = 2 * o + v;
+  const int uk = __builtin_amdgcn_readfirstlane(key);
+  if (__all(key == uk))
+    face_apply<R, TH>(as_scalar(a.ops) + (uk >> 1), uk & 1, uk >> 1, a, k, m, Tn, f, gq, M);
+  else
+    face_apply<R, TH>(a.ops + o, v, o, a, k, m, Tn, f, gq, M);
 }
 
 // local terms of the adjoint moments: the probe seed, the prescribed

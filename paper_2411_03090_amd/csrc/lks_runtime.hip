@@ -90,10 +90,12 @@ struct lks_ctx {
   void* P[2][5] = {};
   void* C = nullptr;     // checkpoints
   void* Seg = nullptr;   // replay segment
-  lks::RingOp* d_ops = nullptr;  // adjoint boundary operators (4 orientations)
+  void* d_ops = nullptr;   // adjoint boundary operators (4 orientations), RingOpT<R>
   lks::RingOp ops[4];
-  lks::FaceOp3* d_ops3 = nullptr;  // D3Q19 face operators (6 orientations)
+  lks::RingOpT<float> ops_f[4];
+  void* d_ops3 = nullptr;  // D3Q19 face operators (6 orientations), FaceOpT<R>
   lks::FaceOp3 ops3[6];
+  lks::FaceOpT<float> ops3_f[6];
   int* copy3 = nullptr;  // D3Q19 edge and corner nodes (device)
   int* face3 = nullptr;  // D3Q19 boundary nodes by orientation (device)
   void* M3 = nullptr;    // D3Q19 adjoint moments of one step
@@ -829,7 +831,7 @@ struct Run {
         a.p1[f] = rp<R>(c->P[i1][f]);
       }
       a.m = rp<R>(c->M3);
-      a.ops = c->d_ops3;
+      a.ops = static_cast<const lks::FaceOpT<R>*>(c->d_ops3);
       a.face = c->face3;
       a.nface = int(c->face3h.size());
       a.sens = sens;
@@ -874,7 +876,7 @@ struct Run {
     a.exact = c->adj_exact;
     a.seed_dp = sdp;
     a.seed_heat = sh;
-    a.ops = c->d_ops;
+    a.ops = static_cast<const lks::RingOpT<R>*>(c->d_ops);
     a.beta = rp<R>(c->beta);
     a.dbeta = rp<R>(c->dbeta);
     return a;
@@ -1157,12 +1159,12 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
     for (int f = 0; f < 5; ++f) c->P[s][f] = f < nf ? take(N * r) : nullptr;
   c->acc = reinterpret_cast<double*>(take(sizeof(double) * acc_capacity(c)));
   if (nu == 3) {
-    c->d_ops3 = reinterpret_cast<lks::FaceOp3*>(take(6 * sizeof(lks::FaceOp3)));
+    c->d_ops3 = take(6 * sizeof(lks::FaceOp3));
     c->copy3 = reinterpret_cast<int*>(take(sizeof(int) * c->copy3h.size()));
     c->face3 = reinterpret_cast<int*>(take(sizeof(int) * c->face3h.size()));
     c->M3 = take(size_t(moments3_fields(c)) * N * r);
   } else {
-    c->d_ops = reinterpret_cast<lks::RingOp*>(take(4 * sizeof(lks::RingOp)));
+    c->d_ops = take(4 * sizeof(lks::RingOp));
   }
   c->scal = reinterpret_cast<double*>(take(sizeof(double) * 8));
   c->flag = reinterpret_cast<int*>(take(sizeof(int) * 4));
@@ -1189,8 +1191,19 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
                                   hipMemcpyHostToDevice, c->stream),
                 "upload boundary values", &st))
       return st;
+  // the operators in the arithmetic type of the kernels
+  const bool f32 = c->rsz == 4;
+  if (f32) {
+    for (int o = 0; o < 4; ++o) c->ops_f[o] = lks::ring_op_as<float>(c->ops[o]);
+    for (int o = 0; o < 6; ++o) c->ops3_f[o] = lks::face_op_as<float>(c->ops3[o]);
+  }
+  const void* ops_src = f32 ? static_cast<const void*>(c->ops_f) : static_cast<const void*>(c->ops);
+  const size_t ops_bytes = f32 ? sizeof c->ops_f : sizeof c->ops;
+  const void* ops3_src =
+      f32 ? static_cast<const void*>(c->ops3_f) : static_cast<const void*>(c->ops3);
+  const size_t ops3_bytes = f32 ? sizeof c->ops3_f : sizeof c->ops3;
   const bool ops_ok = nu == 3
-      ? hip_ok(c, hipMemcpyAsync(c->d_ops3, c->ops3, sizeof c->ops3, hipMemcpyHostToDevice,
+      ? hip_ok(c, hipMemcpyAsync(c->d_ops3, ops3_src, ops3_bytes, hipMemcpyHostToDevice,
                                  c->stream), "upload face operators", &st) &&
             hip_ok(c, hipMemcpyAsync(c->copy3, c->copy3h.data(), sizeof(int) * c->copy3h.size(),
                                      hipMemcpyHostToDevice, c->stream),
@@ -1198,8 +1211,8 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
             hip_ok(c, hipMemcpyAsync(c->face3, c->face3h.data(), sizeof(int) * c->face3h.size(),
                                      hipMemcpyHostToDevice, c->stream),
                    "upload boundary nodes", &st)
-      : hip_ok(c, hipMemcpyAsync(c->d_ops, c->ops, sizeof c->ops, hipMemcpyHostToDevice,
-                                 c->stream), "upload ring operators", &st);
+      : hip_ok(c, hipMemcpyAsync(c->d_ops, ops_src, ops_bytes, hipMemcpyHostToDevice, c->stream),
+               "upload ring operators", &st);
   if (!ops_ok ||
       !hip_ok(c, hipMemcpyAsync(c->d_ufac, c->ufac.data(), sizeof(double) * c->ufac.size(),
                                 hipMemcpyHostToDevice, c->stream),
@@ -1645,7 +1658,7 @@ void build_batch_desc(lks_batch* b, double seed, int nf, std::vector<char>& fwd,
         a.vx1 = rp<R>(c->P[p ^ 1][1]);
         a.vy1 = rp<R>(c->P[p ^ 1][2]);
         a.th1 = rp<R>(c->P[p ^ 1][3]);
-        a.ops = c->d_ops;
+        a.ops = static_cast<const lks::RingOpT<R>*>(c->d_ops);
         a.sens = b->d_sens + size_t(d) * b->maxN;
         a.sens_mode = 0;
         a.exact = 0;
