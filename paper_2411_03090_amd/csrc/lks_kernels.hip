@@ -413,7 +413,9 @@ struct FwdLds {
   R d[TL::W2 * TL::H2], u[TL::W2 * TL::H2], v[TL::W2 * TL::H2];
   R T[TH ? TL::W2 * TL::H2 : 1], B[TH ? TL::W2 * TL::H2 : 1];
   R f[9][TL::W1 * TL::H1];
-  R gq[TH ? 9 : 1][TH ? TL::W1 * TL::H1 : 1];
+  // thermal: W = 3 T u + B grad T of each node (x, y); its nine g_i follow
+  // from T and W, so the puller forms them
+  R gq[TH ? 2 : 1][TH ? TL::W1 * TL::H1 : 1];
   double red[NTHREADS / 64];
 };
 
@@ -451,15 +453,26 @@ __device__ inline void fwd_collide(const Geo& g, R A, const R* ld, const R* lu, 
     const R Bk = lB[pr];
     const R Wx = R(3) * T * ux + Bk * lds_dx<INT>(lT, pr, 1, i, g.nx, g.periodic);
     const R Wy = R(3) * T * uy + Bk * lds_dx<INT>(lT, pr, PR, j, g.ny, g.periodic);
-    gq[0 * SF + pf] = w0 * T;
-    gq[1 * SF + pf] = w1 * (T + Wx);
-    gq[2 * SF + pf] = w1 * (T + Wy);
-    gq[3 * SF + pf] = w1 * (T - Wx);
-    gq[4 * SF + pf] = w1 * (T - Wy);
-    gq[5 * SF + pf] = w5 * (T + Wx + Wy);
-    gq[6 * SF + pf] = w5 * (T - Wx + Wy);
-    gq[7 * SF + pf] = w5 * (T - Wx - Wy);
-    gq[8 * SF + pf] = w5 * (T + Wx - Wy);
+    gq[0 * SF + pf] = Wx;
+    gq[1 * SF + pf] = Wy;
+  }
+}
+
+// g_q = w_q [T + c_q.W] (eq:geq2) of the node whose temperature is T and
+// whose W is (Wx, Wy)
+template <typename R>
+__device__ inline R g_eq(int q, R T, R Wx, R Wy) {
+  const R w0 = R(4.0 / 9), w1 = R(1.0 / 9), w5 = R(1.0 / 36);
+  switch (q) {
+    case 0: return w0 * T;
+    case 1: return w1 * (T + Wx);
+    case 2: return w1 * (T + Wy);
+    case 3: return w1 * (T - Wx);
+    case 4: return w1 * (T - Wy);
+    case 5: return w5 * (T + Wx + Wy);
+    case 6: return w5 * (T - Wx + Wy);
+    case 7: return w5 * (T - Wx - Wy);
+    default: return w5 * (T + Wx - Wy);
   }
 }
 
@@ -467,17 +480,22 @@ __device__ inline void fwd_collide(const Geo& g, R A, const R* ld, const R* lu, 
 // post-collision arrays (pitch PF, position pf) and form the new state;
 // ring nodes complete it from the moment balance. `level` is the new level
 // (inflow factor of velocity nodes).
-template <typename R, bool TH, int PF, int SF, bool INT = false>
+template <typename R, bool TH, int PF, int SF, int PR, bool INT = false>
 __device__ inline void fwd_pull(const Geo& g, const FwdArgs<R>& a, const R* lf, const R* lg,
-                                int pf, int i, int j, int k, int m, R s, int level, R& dn,
-                                R& uxn, R& uyn, R& Tn) {
+                                const R* lT, int pf, int pr, int i, int j, int k, int m, R s,
+                                int level, R& dn, R& uxn, R& uyn, R& Tn) {
   const int fc = (INT || g.periodic) ? FLOW_INTERIOR : (m & 3);
   R f[9], gg[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) f[q] = lf[q * SF + pf - CX[q] - CY[q] * PF];
   if constexpr (TH) {
+    // g_q(x - c_q) from the source's T (raw fields, pitch PR, position pr
+    // of this node) and W (pitch PF)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) gg[q] = lg[q * SF + pf - CX[q] - CY[q] * PF];
+    for (int q = 0; q < 9; ++q) {
+      const int pw = pf - CX[q] - CY[q] * PF;
+      gg[q] = g_eq<R>(q, lT[pr - CX[q] - CY[q] * PR], lg[pw], lg[SF + pw]);
+    }
   }
   Tn = R(0);
   if (fc == FLOW_INTERIOR) {
@@ -599,8 +617,9 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
     const int k = j * g.nx + i;
     if (!I && !g.periodic && (m & 3) == FLOW_CORNER) return;
     R dn, uxn, uyn, Tn;
-    fwd_pull<R, TH, W1, SF, I>(g, a, &L.f[0][0], &L.gq[0][0], (ly + 1) * W1 + lx + 1, i, j, k, m,
-                               s, a.level_out, dn, uxn, uyn, Tn);
+    fwd_pull<R, TH, W1, SF, W2, I>(g, a, &L.f[0][0], &L.gq[0][0], L.T, (ly + 1) * W1 + lx + 1,
+                                   (ly + 2) * W2 + lx + 2, i, j, k, m, s, a.level_out, dn, uxn,
+                                   uyn, Tn);
     if constexpr (!I)
       corner_from(g, i, j, [&](int jc) {
         const int kc = jc * g.nx + i;
@@ -1149,7 +1168,10 @@ struct Fwd2Lds {
   R d[WR * HR], u[WR * HR], v[WR * HR];
   R T[TH ? WR * HR : 1], B[TH ? WR * HR : 1];
   R f[9 * SF];
-  R gq[TH ? 9 * SF : 1];
+  R gq[TH ? 2 * SF : 1];
+  // the first pull rewrites the raw fields in place, which a thermal pull
+  // still reads (T of its sources): two steps per launch are non-thermal
+  static_assert(!TH, "two steps per launch are for non-thermal sweeps");
 };
 
 template <typename R, bool TH, int TY, bool FULL, int KIND>
@@ -1200,8 +1222,9 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
     const int m = I ? 0 : int(a.mask[k]);
     if (!I && !g.periodic && (m & 3) == FLOW_CORNER) return;
     R dn, uxn, uyn, Tn;
-    fwd_pull<R, TH, WF, SF, I>(g, a, L.f, L.gq, (ly + 1) * WF + lx + 1, i, j, k, m,
-                               a.inv1pa[k], a.level_mid, dn, uxn, uyn, Tn);
+    fwd_pull<R, TH, WF, SF, WR, I>(g, a, L.f, L.gq, L.T, (ly + 1) * WF + lx + 1,
+                                   (ly + 2) * WR + lx + 2, i, j, k, m, a.inv1pa[k], a.level_mid,
+                                   dn, uxn, uyn, Tn);
     const int pr = (ly + 2) * WR + lx + 2;
     if constexpr (!I)
       corner_from(g, i, j, [&](int jc) {
@@ -1230,8 +1253,9 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
     const int k = j * g.nx + i;
     if (!I && !g.periodic && (m & 3) == FLOW_CORNER) return;
     R dn, uxn, uyn, Tn;
-    fwd_pull<R, TH, WF, SF, I>(g, a, L.f, L.gq, (ly + 3) * WF + lx + 3, i, j, k, m, s,
-                               a.level_out, dn, uxn, uyn, Tn);
+    fwd_pull<R, TH, WF, SF, WR, I>(g, a, L.f, L.gq, L.T, (ly + 3) * WF + lx + 3,
+                                   (ly + 4) * WR + lx + 4, i, j, k, m, s, a.level_out, dn, uxn,
+                                   uyn, Tn);
     if constexpr (!I)
       corner_from(g, i, j, [&](int jc) {
         const int kc = jc * g.nx + i;
