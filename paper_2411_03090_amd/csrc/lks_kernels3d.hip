@@ -366,7 +366,9 @@ template <typename R, bool TH>
 struct FwdZLds {
   R st[2][TH ? 4 : 3][NSR];  // u (3), T of planes s and s + 1
   R fq[16][ZT];              // f'_q arriving at each column
-  R gq[TH ? 16 : 1][ZT];     // g_q arriving at each column
+  // T and G = 3 T u + B grad T of every column of the tile and its ring (1-node
+  // halo region): a column forms the g_q = w_q (T + c_q.G) it receives itself
+  R tg[TH ? 4 : 1][TH ? NCR : 1];
   double red[ZT / 64];
 };
 
@@ -433,6 +435,7 @@ __device__ inline void fwd_src(const Geo3& g, const Fwd3Args<R>& a, FwdZLds<R, T
                                unsigned nxy, R dk, R Bk, R zp[4], FwdAcc<R, TH>& A) {
   if (!n.on) return;
   R fv[19], gv[19];
+  R tgv[4] = {R(0), R(0), R(0), R(0)};
   if (n.off < 0) {
 #pragma unroll
     for (int q = 0; q < 19; ++q) fv[q] = gv[q] = R(0);
@@ -474,6 +477,9 @@ __device__ inline void fwd_src(const Geo3& g, const Fwd3Args<R>& a, FwdZLds<R, T
 #pragma unroll
       for (int c = 0; c < 3; ++c) Gt[c] = R(3) * T * u[c] + Bk * dT[c];
       zp[3] = T;
+      tgv[0] = T;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tgv[1 + c] = Gt[c];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) zp[c] = u[c];
@@ -501,9 +507,11 @@ __device__ inline void fwd_src(const Geo3& g, const Fwd3Args<R>& a, FwdZLds<R, T
     const int px = n.dx + QX[q], py = n.dy + QY[q];
     if (px >= 0 && px < t.w && py >= 0 && py < t.h) {
       L.fq[j][py * ZX + px] = fv[q];
-      if constexpr (TH) L.gq[j][py * ZX + px] = gv[q];
     }
   }
+  if constexpr (TH)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) L.tg[c][n.ci] = tgv[c];
   if constexpr (OWN) {
     facc_add(A, 0, fv[0], gv[0]);
     facc_add(A, 5, fv[5], gv[5]);
@@ -653,7 +661,21 @@ __global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
     if (n0.on) {
       const int me = ly * ZX + lx;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) facc_add(A, LQ[j], L.fq[j][me], TH ? L.gq[j][me] : R(0));
+      for (int j = 0; j < 16; ++j) {
+        const int q = LQ[j];
+        R gv = R(0);
+        if constexpr (TH) {
+          // g_q of the source column x - c_q, summed as at the source
+          const int src = (ly - QY[q] + 1) * CXN + (lx - QX[q] + 1);
+          const int cq[3] = {QX[q], QY[q], QZ[q]};
+          R cg = R(0);
+#pragma unroll
+          for (int x = 0; x < 3; ++x)
+            if (cq[x]) cg += R(cq[x]) * L.tg[1 + x][src];
+          gv = R(QW[q]) * (L.tg[0][src] + cg);
+        }
+        facc_add(A, q, L.fq[j][me], gv);
+      }
     }
     const int p = s - 1;
     if (own && p >= t.z0 && p < t.z1)
