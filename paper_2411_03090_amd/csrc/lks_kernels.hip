@@ -1169,9 +1169,9 @@ struct Fwd2Lds {
   R T[TH ? WR * HR : 1], B[TH ? WR * HR : 1];
   R f[9 * SF];
   R gq[TH ? 2 * SF : 1];
-  // the first pull rewrites the raw fields in place, which a thermal pull
-  // still reads (T of its sources): two steps per launch are non-thermal
-  static_assert(!TH, "two steps per launch are for non-thermal sweeps");
+  // T of the intermediate level: the first pull rewrites drho and u in place
+  // but still reads the sources' T, so the new T goes beside it
+  R T2[TH ? WR * HR : 1];
 };
 
 template <typename R, bool TH, int TY, bool FULL, int KIND>
@@ -1232,18 +1232,18 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
         L.d[pc] = dn;
         L.u[pc] = R(0);
         L.v[pc] = R(0);
-        if constexpr (TH) L.T[pc] = Tn;
+        if constexpr (TH) L.T2[pc] = Tn;
       });
     L.d[pr] = dn;
     L.u[pr] = uxn;
     L.v[pr] = uyn;
-    if constexpr (TH) L.T[pr] = Tn;
+    if constexpr (TH) L.T2[pr] = Tn;
   });
   __syncthreads();
   // second step: collide on the tile + 1, pull on the tile into HBM
   region_walk<KIND, FULL, TX + 2, TY + 2>(g, x0, y0, 1, tw + 2, th + 2,
                                           [&](auto in, int lx, int ly, int i, int j) {
-    fwd_collide<R, TH, WR, SF, decltype(in)::value>(g, A, L.d, L.u, L.v, L.T, L.B,
+    fwd_collide<R, TH, WR, SF, decltype(in)::value>(g, A, L.d, L.u, L.v, L.T2, L.B,
                                                     (ly + 3) * WR + lx + 3, i, j, L.f, L.gq,
                                                     (ly + 2) * WF + lx + 2);
   });
@@ -1253,7 +1253,7 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
     const int k = j * g.nx + i;
     if (!I && !g.periodic && (m & 3) == FLOW_CORNER) return;
     R dn, uxn, uyn, Tn;
-    fwd_pull<R, TH, WF, SF, WR, I>(g, a, L.f, L.gq, L.T, (ly + 3) * WF + lx + 3,
+    fwd_pull<R, TH, WF, SF, WR, I>(g, a, L.f, L.gq, L.T2, (ly + 3) * WF + lx + 3,
                                    (ly + 4) * WR + lx + 4, i, j, k, m, s, a.level_out, dn, uxn,
                                    uyn, Tn);
     if constexpr (!I)
@@ -1700,13 +1700,23 @@ void launch_alks_step(const Geo& g, const AdjArgs<R>& a, hipStream_t s) {
 // two-step kernels exist for tile heights 4 and 8 (the runtime never asks for others)
 void launch_lks_step2(const Geo& g, const FwdArgs<float>& a, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
-  if (g.ty == 8) lks_step2_kernel<float, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
-  else lks_step2_kernel<float, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+  if (g.thermal) {
+    if (g.ty == 8) lks_step2_kernel<float, true, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+    else lks_step2_kernel<float, true, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+  } else {
+    if (g.ty == 8) lks_step2_kernel<float, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+    else lks_step2_kernel<float, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+  }
 }
 void launch_alks_step2(const Geo& g, const AdjArgs<float>& a, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
-  if (g.ty == 8) alks_step2_kernel<float, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
-  else alks_step2_kernel<float, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+  if (g.thermal) {
+    if (g.ty == 8) alks_step2_kernel<float, true, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+    else alks_step2_kernel<float, true, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+  } else {
+    if (g.ty == 8) alks_step2_kernel<float, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+    else alks_step2_kernel<float, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+  }
 }
 template <typename R>
 void launch_pressure_drop(const Geo& g, const uint8_t* mask, const R* d, double* out,

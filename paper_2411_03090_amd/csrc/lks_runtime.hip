@@ -629,10 +629,10 @@ struct Run {
     return a;
   }
 
-  // two time steps per launch: FP32 non-thermal D2Q9 steady sweeps
+  // two time steps per launch: FP32 D2Q9 steady sweeps
   // (two-step kernels exist for 64 x 4 and 64 x 8 tiles)
   bool two_step(int spl) const {
-    return std::is_same<R, float>::value && c->dim == 2 && !c->phys.thermal && spl == 2 &&
+    return std::is_same<R, float>::value && c->dim == 2 && spl == 2 &&
            (c->geo.ty == 4 || c->geo.ty == 8);
   }
 
@@ -895,10 +895,12 @@ struct Run {
     int n = 0;
     if constexpr (std::is_same<R, float>::value) {
       if (two_step(c->spl_a) && steps >= 2) {
-        if (steps % 2) adj_step(st, sdp, sh, nullptr, 2);
+        if (steps % 2) adj_step(st, sdp, sh, nullptr, 2, ss, sbt);
         for (n = steps % 2; n < steps; n += 2) {
-          lks::launch_alks_step2(g, adj_args(st, sdp, sh, n + 2 == steps ? dJ : nullptr, 2),
-                                 c->stream);
+          lks::AdjArgs<R> a = adj_args(st, sdp, sh, n + 2 == steps ? dJ : nullptr, 2);
+          a.seed_src = ss;
+          a.seed_bt = sbt;
+          lks::launch_alks_step2(g, a, c->stream);
           c->acur ^= 1;
         }
       }
@@ -1391,9 +1393,8 @@ lks_status lks_set_steps_per_launch(lks_ctx* c, int forward_steps, int adjoint_s
   if (!c) return LKS_E_INVALID;
   for (int s : {forward_steps, adjoint_steps}) {
     if (s != 1 && s != 2) return fail(c, LKS_E_INVALID, "steps per launch must be 1 or 2");
-    if (s == 2 && (c->dim != 2 || c->rsz != 4 || c->phys.thermal))
-      return fail(c, LKS_E_UNSUPPORTED,
-                  "two steps per launch need an FP32 non-thermal D2Q9 problem");
+    if (s == 2 && (c->dim != 2 || c->rsz != 4))
+      return fail(c, LKS_E_UNSUPPORTED, "two steps per launch need an FP32 D2Q9 problem");
   }
   c->spl_f = forward_steps;
   c->spl_a = adjoint_steps;
@@ -1464,7 +1465,7 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
   float best = 0.0f;
   int best_ty = c->geo.ty, best_f = c->spl_f, best_a = c->spl_a;
   const int mode = c->mode;
-  const int nspl = (c->rsz == 4 && !c->phys.thermal) ? 2 : 1;
+  const int nspl = c->rsz == 4 ? 2 : 1;
   c->mode = LKS_STEADY;  // time plain steps on the ping-pong buffers
   for (int ty : TILE_ROWS) {
     if (!tile_rows_ok(ty, c->rsz, c->phys.thermal)) continue;

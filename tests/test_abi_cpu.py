@@ -233,6 +233,13 @@ def test_launch_shape_controls():
     with pytest.raises(lks.LKSError) as e:
         _create(wl, "fp64").set_steps_per_launch(2)
     assert e.value.status == lks.LKS_E_UNSUPPORTED
+    # thermal FP32 D2Q9 problems take two steps per launch too; D3Q19 does not
+    th = _create(W.heat_exchanger(n=20, n_fwd=5, n_adj=5), "fp32")
+    th.set_steps_per_launch(2)
+    assert th.launch_shape()[1:] == (2, 2)
+    with pytest.raises(lks.LKSError) as e:
+        _create(W.heated_block_duct(20, 10, 8, n_steps=5), "fp32").set_steps_per_launch(2)
+    assert e.value.status == lks.LKS_E_UNSUPPORTED
     with pytest.raises(lks.LKSError) as e:
         _create(W.heated_block_duct(20, 10, 8, n_steps=5), "fp32").set_tile_rows(4)
     assert e.value.status == lks.LKS_E_UNSUPPORTED

@@ -363,6 +363,42 @@ def test_two_steps_per_launch_give_the_same_bits(case, ty):
             assert np.array_equal(a, b)
 
 
+def _steady_exchanger(mode):
+    """Steady heat exchanger (heat source on) on a 70 x 70 grid: ragged
+    tiles, corners, flux and Dirichlet ends; paper or exact adjoint."""
+    wl = W.heat_exchanger(n=70, Re=20.0, sigma=3.0, seed=5, n_fwd=9, n_adj=11)
+    wl.adjoint_mode = mode
+    return wl
+
+
+@pytest.mark.parametrize("ty", [4, 8])
+@pytest.mark.parametrize("mode", ["paper", "exact"])
+def test_two_steps_per_launch_thermal_give_the_same_bits(mode, ty):
+    """The thermal two-step kernels (new temperature of the first step kept
+    beside the old one in LDS) against one step per launch, forward and
+    adjoint, odd and even step counts."""
+    say(f"[gpu] two steps per launch, thermal heat exchanger 70x70 {mode} ty={ty}")
+    wl = _steady_exchanger(mode)
+    out = []
+    for spl in (1, 2):
+        ctx = lks.LKS(wl, precision="fp32", device=DEV)
+        ctx.set_tile_rows(ty)
+        ctx.set_steps_per_launch(spl)
+        assert ctx.launch_shape() == (ty, spl, spl)
+        g = T(wl.gamma)
+        d = torch.empty_like(g)
+        ctx.forward(g, wl.n_fwd)
+        J = ctx.objective()
+        fields = [ctx.read(n).cpu().numpy() for n in ("drho", "ux", "uy", "T")]
+        ctx.backward(0.7, d, wl.n_adj)
+        torch.cuda.synchronize()
+        adj = [ctx.read(n).cpu().numpy() for n in ("adj_rho", "adj_vx", "adj_vy", "adj_theta")]
+        out.append((J, fields + adj + [d.cpu().numpy()]))
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)
+
+
 def test_two_steps_per_launch_full_size_512():
     """At full size the one-step kernel runs interior tiles through its
     branch-free variant, whose floating-point contraction may differ from the
