@@ -246,30 +246,30 @@ __device__ inline void ring_at(const Geo& g, const RingSet& s, int t, int* i, in
 
 // Visit the ring nodes (i, j) of a rectangle, one per thread from the last
 // thread of the block down (the flat walks leave those idle most often).
-template <typename F>
+template <int NT = NTHREADS, typename F>
 __device__ inline void ring_loop(const Geo& g, int x0, int y0, int w, int h, F&& f) {
   RingSet s;
   const int n = ring_set(g, x0, y0, w, h, s);
-  for (int t = NTHREADS - 1 - int(threadIdx.x); t < n; t += NTHREADS) {
+  for (int t = NT - 1 - int(threadIdx.x); t < n; t += NT) {
     int i, j;
     ring_at(g, s, t, &i, &j);
     f(i, j);
   }
 }
 
-// Visit the positions (lx, ly) of a w x h rectangle, 256 threads, flat order.
-template <bool FULL, int WC, int HC, typename F>
+// Visit the positions (lx, ly) of a w x h rectangle, NT threads, flat order.
+template <bool FULL, int WC, int HC, int NT = NTHREADS, typename F>
 __device__ inline void rect_loop(int w, int h, F&& f) {
   if constexpr (FULL) {
     constexpr int n = WC * HC;
 #pragma unroll
-    for (int p0 = 0; p0 < n; p0 += NTHREADS) {
+    for (int p0 = 0; p0 < n; p0 += NT) {
       const int p = p0 + int(threadIdx.x);
       if (p < n) f(p % WC, p / WC);
     }
   } else {
     const int n = w * h;
-    for (int p = threadIdx.x; p < n; p += NTHREADS) f(p % w, p / w);
+    for (int p = threadIdx.x; p < n; p += NT) f(p % w, p / w);
   }
 }
 
@@ -279,9 +279,9 @@ __device__ inline void rect_loop(int w, int h, F&& f) {
 // region position and rule is BoolC<true> for the interior rule. K_GEN
 // wraps a periodic box and skips positions outside a bounded one; K_EDGE
 // walks the nodes off the ring first and its ring nodes after.
-template <int KIND, bool FULL, int WC, int HC, typename F>
+template <int KIND, bool FULL, int WC, int HC, int NT = NTHREADS, typename F>
 __device__ inline void region_walk(const Geo& g, int x0, int y0, int h, int w, int hh, F&& fn) {
-  rect_loop<FULL, WC, HC>(w, hh, [&](int lx, int ly) {
+  rect_loop<FULL, WC, HC, NT>(w, hh, [&](int lx, int ly) {
     int i = x0 + lx - h, j = y0 + ly - h;
     if constexpr (KIND == K_EDGE) {
       if (on_ring(g, i, j)) return;
@@ -296,8 +296,8 @@ __device__ inline void region_walk(const Geo& g, int x0, int y0, int h, int w, i
     fn(BoolC<KIND != K_GEN>(), lx, ly, i, j);
   });
   if constexpr (KIND == K_EDGE)
-    ring_loop(g, x0 - h, y0 - h, w, hh,
-              [&](int i, int j) { fn(BoolC<false>(), i - x0 + h, j - y0 + h, i, j); });
+    ring_loop<NT>(g, x0 - h, y0 - h, w, hh,
+                  [&](int i, int j) { fn(BoolC<false>(), i - x0 + h, j - y0 + h, i, j); });
 }
 
 // interior_tile for the two-step kernels, whose tiles carry a 4-node halo
@@ -308,7 +308,8 @@ __device__ inline bool interior_tile2(const Geo& g, int x0, int x1, int y0, int 
 // Load NF fields of the tile plus an H-node halo into LDS arrays of pitch P
 // (zeros outside a non-periodic domain). For full tiles (TX x TY) every load
 // is issued before any is used so that their latencies overlap.
-template <typename R, bool FULL, int TY, int H, int P, int NF, bool INT = false>
+template <typename R, bool FULL, int TY, int H, int P, int NF, bool INT = false,
+          int NT = NTHREADS>
 __device__ inline void load_halo(const Geo& g, int x0, int y0, int tw, int th,
                                  const R* const (&src)[NF], R* const (&dst)[NF]) {
   auto node = [&](int lx, int ly, int* k) {
@@ -329,12 +330,12 @@ __device__ inline void load_halo(const Geo& g, int x0, int y0, int tw, int th,
   };
   if constexpr (FULL) {
     constexpr int WC = TX + 2 * H, HC = TY + 2 * H, n = WC * HC;
-    constexpr int NP = (n + NTHREADS - 1) / NTHREADS;
+    constexpr int NP = (n + NT - 1) / NT;
     int kk[NP], pp[NP];
     bool ok[NP];
 #pragma unroll
     for (int e = 0; e < NP; ++e) {
-      const int p = e * NTHREADS + int(threadIdx.x);
+      const int p = e * NT + int(threadIdx.x);
       const int lx = p % WC, ly = p / WC;
       ok[e] = node(lx, ly, &kk[e]) && p < n;
       if (p >= n) kk[e] = 0;
@@ -351,7 +352,7 @@ __device__ inline void load_halo(const Geo& g, int x0, int y0, int tw, int th,
 #pragma unroll
         for (int f = 0; f < NF; ++f) dst[f][pp[e]] = ok[e] ? v[f][e] : R(0);
   } else {
-    rect_loop<false, 1, 1>(tw + 2 * H, th + 2 * H, [&](int lx, int ly) {
+    rect_loop<false, 1, 1, NT>(tw + 2 * H, th + 2 * H, [&](int lx, int ly) {
       int k;
       const bool in = node(lx, ly, &k);
       const int p = ly * P + lx;
@@ -1160,6 +1161,13 @@ __global__ __launch_bounds__(NTHREADS) void alks_step_kernel(Geo g, AdjArgs<R> a
 // the same bits as two single steps; the launch count and the global
 // round trips per step halve, the stage work grows by the halo (about 1.3x
 // for 64 x 8 tiles).
+// threads of a two-step block: the stages walk tile + 3, + 2 and + 1 regions of
+// up to 3.4x the tile's nodes, so a non-thermal block of 512 threads (8 waves)
+// keeps each stage to one or two passes; the thermal adjoint would spill
+// registers at 512 and keeps 256
+template <bool TH>
+constexpr int NT2 = TH ? NTHREADS : 512;
+
 template <typename R, bool TH, int TY>
 struct Fwd2Lds {
   static constexpr int WR = TX + 1 + 8, HR = TY + 1 + 8;  // raw state: tile + 4
@@ -1174,7 +1182,7 @@ struct Fwd2Lds {
   R T2[TH ? WR * HR : 1];
 };
 
-template <typename R, bool TH, int TY, bool FULL, int KIND>
+template <typename R, bool TH, int TY, bool FULL, int KIND, int NT>
 __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>& L, int x0,
                           int y0, int tw, int th) {
   using LD = Fwd2Lds<R, TH, TY>;
@@ -1185,13 +1193,14 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
     tw = TX;
     th = TY;
   }
-  constexpr int NB = FULL ? (TX * TY + NTHREADS - 1) / NTHREADS : 1;
+  constexpr int NB = FULL ? (TX * TY + NT - 1) / NT : 1;
   int mpre[NB];
   R spre[NB];
   if constexpr (FULL) {
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-      const int p = e * NTHREADS + int(threadIdx.x);
+      const int p = e * NT + int(threadIdx.x);
+      if (p >= TX * TY) break;  // more threads than tile nodes
       const int k = (y0 + p / TX) * g.nx + x0 + p % TX;
       mpre[e] = a.mask[k];
       spre[e] = a.inv1pa[k];
@@ -1200,22 +1209,22 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
   if constexpr (TH) {
     const R* src[5] = {a.d0, a.ux0, a.uy0, a.T0, a.B};
     R* dst[5] = {L.d, L.u, L.v, L.T, L.B};
-    load_halo<R, FULL, TY, 4, WR, 5, INT>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 4, WR, 5, INT, NT>(g, x0, y0, tw, th, src, dst);
   } else {
     const R* src[3] = {a.d0, a.ux0, a.uy0};
     R* dst[3] = {L.d, L.u, L.v};
-    load_halo<R, FULL, TY, 4, WR, 3, INT>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 4, WR, 3, INT, NT>(g, x0, y0, tw, th, src, dst);
   }
   __syncthreads();
   // first step: collide on the tile + 3, pull on the tile + 2 into LDS
-  region_walk<KIND, FULL, TX + 6, TY + 6>(g, x0, y0, 3, tw + 6, th + 6,
+  region_walk<KIND, FULL, TX + 6, TY + 6, NT>(g, x0, y0, 3, tw + 6, th + 6,
                                           [&](auto in, int lx, int ly, int i, int j) {
     fwd_collide<R, TH, WR, SF, decltype(in)::value>(g, A, L.d, L.u, L.v, L.T, L.B,
                                                     (ly + 1) * WR + lx + 1, i, j, L.f, L.gq,
                                                     ly * WF + lx);
   });
   __syncthreads();
-  region_walk<KIND, FULL, TX + 4, TY + 4>(g, x0, y0, 2, tw + 4, th + 4,
+  region_walk<KIND, FULL, TX + 4, TY + 4, NT>(g, x0, y0, 2, tw + 4, th + 4,
                                           [&](auto in, int lx, int ly, int i, int j) {
     constexpr bool I = decltype(in)::value;
     const int k = j * g.nx + i;
@@ -1241,7 +1250,7 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
   });
   __syncthreads();
   // second step: collide on the tile + 1, pull on the tile into HBM
-  region_walk<KIND, FULL, TX + 2, TY + 2>(g, x0, y0, 1, tw + 2, th + 2,
+  region_walk<KIND, FULL, TX + 2, TY + 2, NT>(g, x0, y0, 1, tw + 2, th + 2,
                                           [&](auto in, int lx, int ly, int i, int j) {
     fwd_collide<R, TH, WR, SF, decltype(in)::value>(g, A, L.d, L.u, L.v, L.T2, L.B,
                                                     (ly + 3) * WR + lx + 3, i, j, L.f, L.gq,
@@ -1270,7 +1279,7 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
     if constexpr (TH) a.T1[k] = Tn;
   };
   int e = 0;
-  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
+  rect_loop<FULL, TX, TY, NT>(tw, th, [&](int lx, int ly) {
     const int i = x0 + lx, j = y0 + ly;
     int m;
     R s;
@@ -1290,27 +1299,27 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
     pull(BoolC<INT || EDGE>(), lx, ly, i, j, m, s);
   });
   if constexpr (EDGE)
-    ring_loop(g, x0, y0, tw, th, [&](int i, int j) {
+    ring_loop<NT>(g, x0, y0, tw, th, [&](int i, int j) {
       const int k = j * g.nx + i;
       pull(BoolC<false>(), i - x0, j - y0, i, j, int(a.mask[k]), a.inv1pa[k]);
     });
 }
 
 template <typename R, bool TH, int TY>
-__global__ __launch_bounds__(NTHREADS) void lks_step2_kernel(Geo g, FwdArgs<R> a) {
+__global__ __launch_bounds__(NT2<TH>) void lks_step2_kernel(Geo g, FwdArgs<R> a) {
   __shared__ Fwd2Lds<R, TH, TY> L;
   int x0, x1, y0, y1, tile;
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
   const int tw = x1 - x0, th = y1 - y0;
   if (tw != TX || th != TY) {
-    if (g.periodic) lks_tile2<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
-    else lks_tile2<R, TH, TY, false, K_EDGE>(g, a, L, x0, y0, tw, th);
+    if (g.periodic) lks_tile2<R, TH, TY, false, K_GEN, NT2<TH>>(g, a, L, x0, y0, tw, th);
+    else lks_tile2<R, TH, TY, false, K_EDGE, NT2<TH>>(g, a, L, x0, y0, tw, th);
   } else if (interior_tile2(g, x0, x1, y0, y1)) {
-    lks_tile2<R, TH, TY, true, K_INT>(g, a, L, x0, y0, tw, th);
+    lks_tile2<R, TH, TY, true, K_INT, NT2<TH>>(g, a, L, x0, y0, tw, th);
   } else if (g.periodic) {
-    lks_tile2<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
+    lks_tile2<R, TH, TY, false, K_GEN, NT2<TH>>(g, a, L, x0, y0, tw, th);
   } else {
-    lks_tile2<R, TH, TY, true, K_EDGE>(g, a, L, x0, y0, tw, th);
+    lks_tile2<R, TH, TY, true, K_EDGE, NT2<TH>>(g, a, L, x0, y0, tw, th);
   }
 }
 
@@ -1325,7 +1334,7 @@ struct Adj2Lds {
   R m[NM * SM];
 };
 
-template <typename R, bool TH, int TY, bool FULL, int KIND>
+template <typename R, bool TH, int TY, bool FULL, int KIND, int NT>
 __device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>& L, int x0,
                            int y0, int tw, int th) {
   using LD = Adj2Lds<R, TH, TY>;
@@ -1335,12 +1344,13 @@ __device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>
     tw = TX;
     th = TY;
   }
-  constexpr int NB = FULL ? (TX * TY + NTHREADS - 1) / NTHREADS : 1;
+  constexpr int NB = FULL ? (TX * TY + NT - 1) / NT : 1;
   R spre[NB], uxpre[NB], uypre[NB];
   if constexpr (FULL) {
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-      const int p = e * NTHREADS + int(threadIdx.x);
+      const int p = e * NT + int(threadIdx.x);
+      if (p >= TX * TY) break;  // more threads than tile nodes
       const int k = (y0 + p / TX) * g.nx + x0 + p % TX;
       spre[e] = a.inv1pa[k];
       uxpre[e] = a.ux[k];
@@ -1350,17 +1360,17 @@ __device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>
   if constexpr (TH) {
     const R* src[6] = {a.r0, a.vx0, a.vy0, a.th0, a.T, a.B};
     R* dst[6] = {L.r, L.vx, L.vy, L.th, L.Tn, L.B};
-    load_halo<R, FULL, TY, 4, WR, 6, INT>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 4, WR, 6, INT, NT>(g, x0, y0, tw, th, src, dst);
   } else {
     const R* src[3] = {a.r0, a.vx0, a.vy0};
     R* dst[3] = {L.r, L.vx, L.vy};
-    load_halo<R, FULL, TY, 4, WR, 3, INT>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 4, WR, 3, INT, NT>(g, x0, y0, tw, th, src, dst);
   }
   __syncthreads();
   const bool near_corner = !INT && !g.periodic && (x0 <= 3 || x0 + tw + 3 >= g.nx) &&
                            (y0 <= 3 || y0 + th + 3 >= g.ny);
   // first step: moments on the tile + 3, new coefficients on the tile + 2
-  region_walk<KIND, FULL, TX + 6, TY + 6>(g, x0, y0, 3, tw + 6, th + 6,
+  region_walk<KIND, FULL, TX + 6, TY + 6, NT>(g, x0, y0, 3, tw + 6, th + 6,
                                           [&](auto in, int lx, int ly, int i, int j) {
     adj_moments<R, TH, WR, SM, decltype(in)::value>(g, a, L.r, L.vx, L.vy, L.th, L.Tn,
                                                     (ly + 1) * WR + lx + 1, i, j, L.m,
@@ -1371,7 +1381,7 @@ __device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>
     adj_corners<R, TH, WM, SM>(g, L.m, x0 - 3, y0 - 3, tw + 6, th + 6);
     __syncthreads();
   }
-  region_walk<KIND, FULL, TX + 4, TY + 4>(g, x0, y0, 2, tw + 4, th + 4,
+  region_walk<KIND, FULL, TX + 4, TY + 4, NT>(g, x0, y0, 2, tw + 4, th + 4,
                                           [&](auto in, int lx, int ly, int i, int j) {
     const int k = j * g.nx + i;
     R r, Vx, Vy, Th;
@@ -1387,7 +1397,7 @@ __device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>
   });
   __syncthreads();
   // second step: moments on the tile + 1, new coefficients on the tile
-  region_walk<KIND, FULL, TX + 2, TY + 2>(g, x0, y0, 1, tw + 2, th + 2,
+  region_walk<KIND, FULL, TX + 2, TY + 2, NT>(g, x0, y0, 1, tw + 2, th + 2,
                                           [&](auto in, int lx, int ly, int i, int j) {
     adj_moments<R, TH, WR, SM, decltype(in)::value>(g, a, L.r, L.vx, L.vy, L.th, L.Tn,
                                                     (ly + 3) * WR + lx + 3, i, j, L.m,
@@ -1413,7 +1423,7 @@ __device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>
     else if (a.sens_mode == 2) a.sens[k] = v;
   };
   int e = 0;
-  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
+  rect_loop<FULL, TX, TY, NT>(tw, th, [&](int lx, int ly) {
     const int i = x0 + lx, j = y0 + ly;
     R s, ux, uy;
     if constexpr (FULL) {
@@ -1434,27 +1444,27 @@ __device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>
     local(BoolC<INT || EDGE>(), lx, ly, i, j, s, ux, uy);
   });
   if constexpr (EDGE)
-    ring_loop(g, x0, y0, tw, th, [&](int i, int j) {
+    ring_loop<NT>(g, x0, y0, tw, th, [&](int i, int j) {
       const int k = j * g.nx + i;
       local(BoolC<false>(), i - x0, j - y0, i, j, a.inv1pa[k], a.ux[k], a.uy[k]);
     });
 }
 
 template <typename R, bool TH, int TY>
-__global__ __launch_bounds__(NTHREADS) void alks_step2_kernel(Geo g, AdjArgs<R> a) {
+__global__ __launch_bounds__(NT2<TH>) void alks_step2_kernel(Geo g, AdjArgs<R> a) {
   __shared__ Adj2Lds<R, TH, TY> L;
   int x0, x1, y0, y1, tile;
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
   const int tw = x1 - x0, th = y1 - y0;
   if (tw != TX || th != TY) {
-    if (g.periodic) alks_tile2<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
-    else alks_tile2<R, TH, TY, false, K_EDGE>(g, a, L, x0, y0, tw, th);
+    if (g.periodic) alks_tile2<R, TH, TY, false, K_GEN, NT2<TH>>(g, a, L, x0, y0, tw, th);
+    else alks_tile2<R, TH, TY, false, K_EDGE, NT2<TH>>(g, a, L, x0, y0, tw, th);
   } else if (interior_tile2(g, x0, x1, y0, y1)) {
-    alks_tile2<R, TH, TY, true, K_INT>(g, a, L, x0, y0, tw, th);
+    alks_tile2<R, TH, TY, true, K_INT, NT2<TH>>(g, a, L, x0, y0, tw, th);
   } else if (g.periodic) {
-    alks_tile2<R, TH, TY, false, K_GEN>(g, a, L, x0, y0, tw, th);
+    alks_tile2<R, TH, TY, false, K_GEN, NT2<TH>>(g, a, L, x0, y0, tw, th);
   } else {
-    alks_tile2<R, TH, TY, true, K_EDGE>(g, a, L, x0, y0, tw, th);
+    alks_tile2<R, TH, TY, true, K_EDGE, NT2<TH>>(g, a, L, x0, y0, tw, th);
   }
 }
 
@@ -1701,21 +1711,21 @@ void launch_alks_step(const Geo& g, const AdjArgs<R>& a, hipStream_t s) {
 void launch_lks_step2(const Geo& g, const FwdArgs<float>& a, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
   if (g.thermal) {
-    if (g.ty == 8) lks_step2_kernel<float, true, 8><<<nb, NTHREADS, 0, s>>>(g, a);
-    else lks_step2_kernel<float, true, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+    if (g.ty == 8) lks_step2_kernel<float, true, 8><<<nb, NT2<true>, 0, s>>>(g, a);
+    else lks_step2_kernel<float, true, 4><<<nb, NT2<true>, 0, s>>>(g, a);
   } else {
-    if (g.ty == 8) lks_step2_kernel<float, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
-    else lks_step2_kernel<float, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+    if (g.ty == 8) lks_step2_kernel<float, false, 8><<<nb, NT2<false>, 0, s>>>(g, a);
+    else lks_step2_kernel<float, false, 4><<<nb, NT2<false>, 0, s>>>(g, a);
   }
 }
 void launch_alks_step2(const Geo& g, const AdjArgs<float>& a, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
   if (g.thermal) {
-    if (g.ty == 8) alks_step2_kernel<float, true, 8><<<nb, NTHREADS, 0, s>>>(g, a);
-    else alks_step2_kernel<float, true, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+    if (g.ty == 8) alks_step2_kernel<float, true, 8><<<nb, NT2<true>, 0, s>>>(g, a);
+    else alks_step2_kernel<float, true, 4><<<nb, NT2<true>, 0, s>>>(g, a);
   } else {
-    if (g.ty == 8) alks_step2_kernel<float, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
-    else alks_step2_kernel<float, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+    if (g.ty == 8) alks_step2_kernel<float, false, 8><<<nb, NT2<false>, 0, s>>>(g, a);
+    else alks_step2_kernel<float, false, 4><<<nb, NT2<false>, 0, s>>>(g, a);
   }
 }
 template <typename R>
