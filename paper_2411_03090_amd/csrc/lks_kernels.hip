@@ -132,6 +132,7 @@ __global__ void init_kernel(Geo g, const uint8_t* __restrict__ mask, const R* __
 // ---------------------------------------------------------------------------
 // block reduction helper (deterministic)
 // ---------------------------------------------------------------------------
+template <int NT = NTHREADS>
 __device__ inline double block_sum(double v, double* red) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -139,9 +140,16 @@ __device__ inline double block_sum(double v, double* red) {
   __syncthreads();
   double s = 0.0;
   if (threadIdx.x == 0)
-    for (int w = 0; w < NTHREADS / 64; ++w) s += red[w];
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
   return s;
 }
+
+// threads of a one-step block: 512 (8 waves, each stage then walks its
+// region in one or two passes) for FP32 tiles of 16 rows and thermal FP32
+// tiles of 8 rows; 256 otherwise (measured: the non-thermal 64 x 8 step on
+// large grids keeps more tiles in flight with 256)
+template <typename R, bool TH, int TY>
+constexpr int NT1 = (sizeof(R) == 4 && (TY == 16 || (TH && TY == 8))) ? 512 : NTHREADS;
 
 // ---------------------------------------------------------------------------
 // tiles
@@ -417,7 +425,7 @@ struct FwdLds {
   // thermal: W = 3 T u + B grad T of each node (x, y); its nine g_i follow
   // from T and W, so the puller forms them
   R gq[TH ? 2 : 1][TH ? TL::W1 * TL::H1 : 1];
-  double red[NTHREADS / 64];
+  double red[8];  // one per wave, up to 512 threads
 };
 
 // Stage A1 at one node (i, j): the post-collision values f'_i (and g_i)
@@ -567,7 +575,7 @@ __device__ inline void corner_from(const Geo& g, int i, int j, Put&& put) {
   if (j == g.ny - 2) put(g.ny - 1);
 }
 
-template <typename R, bool TH, int TY, bool FULL, int KIND>
+template <typename R, bool TH, int TY, bool FULL, int KIND, int NT = NT1<R, TH, TY>>
 __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L, int x0, int y0,
                          int tw, int th, int tile) {
   using TL = Tile<TY>;
@@ -579,13 +587,14 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
     th = TY;
   }
   // node-local inputs of stage B, loaded before the first barrier (full tiles)
-  constexpr int NB = FULL ? (TX * TY + NTHREADS - 1) / NTHREADS : 1;
+  constexpr int NB = FULL ? (TX * TY + NT - 1) / NT : 1;
   int mpre[NB];
   R spre[NB];
   if constexpr (FULL) {
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-      const int p = e * NTHREADS + int(threadIdx.x);
+      const int p = e * NT + int(threadIdx.x);
+      if (p >= TX * TY) break;  // more threads than tile nodes
       const int k = (y0 + p / TX) * g.nx + x0 + p % TX;
       mpre[e] = a.mask[k];
       spre[e] = a.inv1pa[k];
@@ -595,15 +604,15 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
   if constexpr (TH) {
     const R* src[5] = {a.d0, a.ux0, a.uy0, a.T0, a.B};
     R* dst[5] = {L.d, L.u, L.v, L.T, L.B};
-    load_halo<R, FULL, TY, 2, W2, 5, INT>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 2, W2, 5, INT, NT>(g, x0, y0, tw, th, src, dst);
   } else {
     const R* src[3] = {a.d0, a.ux0, a.uy0};
     R* dst[3] = {L.d, L.u, L.v};
-    load_halo<R, FULL, TY, 2, W2, 3, INT>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 2, W2, 3, INT, NT>(g, x0, y0, tw, th, src, dst);
   }
   __syncthreads();
 
-  region_walk<KIND, FULL, TX + 2, TY + 2>(g, x0, y0, 1, tw + 2, th + 2,
+  region_walk<KIND, FULL, TX + 2, TY + 2, NT>(g, x0, y0, 1, tw + 2, th + 2,
                                           [&](auto in, int lx, int ly, int i, int j) {
     fwd_collide<R, TH, W2, SF, decltype(in)::value>(g, A, L.d, L.u, L.v, L.T, L.B,
                                                     (ly + 1) * W2 + lx + 1, i, j, &L.f[0][0],
@@ -647,7 +656,7 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
     }
   };
   int e = 0;
-  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
+  rect_loop<FULL, TX, TY, NT>(tw, th, [&](int lx, int ly) {
     const int i = x0 + lx, j = y0 + ly;
     int m;
     R s;
@@ -667,18 +676,18 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
     pull(BoolC<INT || EDGE>(), lx, ly, i, j, m, s);
   });
   if constexpr (EDGE)
-    ring_loop(g, x0, y0, tw, th, [&](int i, int j) {
+    ring_loop<NT>(g, x0, y0, tw, th, [&](int i, int j) {
       const int k = j * g.nx + i;
       pull(BoolC<false>(), i - x0, j - y0, i, j, int(a.mask[k]), a.inv1pa[k]);
     });
   if (a.acc) {
-    double s = block_sum(part, L.red);
+    double s = block_sum<NT>(part, L.red);
     if (threadIdx.x == 0) a.acc[tile] += s;
   }
 }
 
 template <typename R, bool TH, int TY>
-__global__ __launch_bounds__(NTHREADS) void lks_step_kernel(Geo g, FwdArgs<R> a) {
+__global__ __launch_bounds__((NT1<R, TH, TY>)) void lks_step_kernel(Geo g, FwdArgs<R> a) {
   __shared__ FwdLds<R, TH, TY> L;
   int x0, x1, y0, y1, tile;
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
@@ -1041,7 +1050,7 @@ __device__ inline void adj_local(const Geo& g, const AdjArgs<R>& a, const R* lm,
   }
 }
 
-template <typename R, bool TH, int TY, bool FULL, int KIND>
+template <typename R, bool TH, int TY, bool FULL, int KIND, int NT = NT1<R, TH, TY>>
 __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& L, int x0,
                           int y0, int tw, int th) {
   using TL = Tile<TY>;
@@ -1052,12 +1061,13 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
     th = TY;
   }
   // node-local inputs of stage B, loaded before the first barrier (full tiles)
-  constexpr int NB = FULL ? (TX * TY + NTHREADS - 1) / NTHREADS : 1;
+  constexpr int NB = FULL ? (TX * TY + NT - 1) / NT : 1;
   R spre[NB], uxpre[NB], uypre[NB];
   if constexpr (FULL) {
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-      const int p = e * NTHREADS + int(threadIdx.x);
+      const int p = e * NT + int(threadIdx.x);
+      if (p >= TX * TY) break;  // more threads than tile nodes
       const int k = (y0 + p / TX) * g.nx + x0 + p % TX;
       spre[e] = a.inv1pa[k];
       uxpre[e] = a.ux[k];
@@ -1068,15 +1078,15 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
   if constexpr (TH) {
     const R* src[6] = {a.r0, a.vx0, a.vy0, a.th0, a.T, a.B};
     R* dst[6] = {L.r, L.vx, L.vy, L.th, L.Tn, L.B};
-    load_halo<R, FULL, TY, 2, W2, 6, INT>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 2, W2, 6, INT, NT>(g, x0, y0, tw, th, src, dst);
   } else {
     const R* src[3] = {a.r0, a.vx0, a.vy0};
     R* dst[3] = {L.r, L.vx, L.vy};
-    load_halo<R, FULL, TY, 2, W2, 3, INT>(g, x0, y0, tw, th, src, dst);
+    load_halo<R, FULL, TY, 2, W2, 3, INT, NT>(g, x0, y0, tw, th, src, dst);
   }
   __syncthreads();
 
-  region_walk<KIND, FULL, TX + 2, TY + 2>(g, x0, y0, 1, tw + 2, th + 2,
+  region_walk<KIND, FULL, TX + 2, TY + 2, NT>(g, x0, y0, 1, tw + 2, th + 2,
                                           [&](auto in, int lx, int ly, int i, int j) {
     adj_moments<R, TH, W2, SM, decltype(in)::value>(g, a, L.r, L.vx, L.vy, L.th, L.Tn,
                                                     (ly + 1) * W2 + lx + 1, i, j, &L.m[0][0],
@@ -1106,7 +1116,7 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
     else if (a.sens_mode == 2) a.sens[k] = v;
   };
   int e = 0;
-  rect_loop<FULL, TX, TY>(tw, th, [&](int lx, int ly) {
+  rect_loop<FULL, TX, TY, NT>(tw, th, [&](int lx, int ly) {
     const int i = x0 + lx, j = y0 + ly;
     R s, ux, uy;
     if constexpr (FULL) {
@@ -1127,14 +1137,14 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
     local(BoolC<INT || EDGE>(), lx, ly, i, j, s, ux, uy);
   });
   if constexpr (EDGE)
-    ring_loop(g, x0, y0, tw, th, [&](int i, int j) {
+    ring_loop<NT>(g, x0, y0, tw, th, [&](int i, int j) {
       const int k = j * g.nx + i;
       local(BoolC<false>(), i - x0, j - y0, i, j, a.inv1pa[k], a.ux[k], a.uy[k]);
     });
 }
 
 template <typename R, bool TH, int TY>
-__global__ __launch_bounds__(NTHREADS) void alks_step_kernel(Geo g, AdjArgs<R> a) {
+__global__ __launch_bounds__((NT1<R, TH, TY>)) void alks_step_kernel(Geo g, AdjArgs<R> a) {
   __shared__ AdjLds<R, TH, TY> L;
   int x0, x1, y0, y1, tile;
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
@@ -1476,7 +1486,7 @@ __global__ __launch_bounds__(NT2<TH>) void alks_step2_kernel(Geo g, AdjArgs<R> a
 // All designs advance in lockstep, so one parity selects the ping-pong
 // buffers of every design.
 template <typename R, bool TH, int TY>
-__global__ __launch_bounds__(NTHREADS) void lks_step_batch_kernel(const BatchFwd<R>* __restrict__ d,
+__global__ __launch_bounds__((NT1<R, TH, TY>)) void lks_step_batch_kernel(const BatchFwd<R>* __restrict__ d,
                                                                   const int* __restrict__ tmap,
                                                                   int total, int parity) {
   __shared__ FwdLds<R, TH, TY> L;
@@ -1502,7 +1512,7 @@ __global__ __launch_bounds__(NTHREADS) void lks_step_batch_kernel(const BatchFwd
 }
 
 template <typename R, bool TH, int TY>
-__global__ __launch_bounds__(NTHREADS) void alks_step_batch_kernel(const BatchAdj<R>* __restrict__ d,
+__global__ __launch_bounds__((NT1<R, TH, TY>)) void alks_step_batch_kernel(const BatchAdj<R>* __restrict__ d,
                                                                    const int* __restrict__ tmap,
                                                                    int total, int parity,
                                                                    int last) {
@@ -1678,16 +1688,16 @@ void launch_lks_step(const Geo& g, const FwdArgs<R>& a, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
   if constexpr (std::is_same<R, float>::value) {
     if (g.ty == 16 && !g.thermal) {
-      lks_step_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(g, a);
+      lks_step_kernel<float, false, 16><<<nb, (NT1<float, false, 16>), 0, s>>>(g, a);
       return;
     }
   }
   if (g.ty == 8) {
-    if (g.thermal) lks_step_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(g, a);
-    else lks_step_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+    if (g.thermal) lks_step_kernel<R, true, 8><<<nb, (NT1<R, true, 8>), 0, s>>>(g, a);
+    else lks_step_kernel<R, false, 8><<<nb, (NT1<R, false, 8>), 0, s>>>(g, a);
   } else {
-    if (g.thermal) lks_step_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(g, a);
-    else lks_step_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+    if (g.thermal) lks_step_kernel<R, true, 4><<<nb, (NT1<R, true, 4>), 0, s>>>(g, a);
+    else lks_step_kernel<R, false, 4><<<nb, (NT1<R, false, 4>), 0, s>>>(g, a);
   }
 }
 template <typename R>
@@ -1695,16 +1705,16 @@ void launch_alks_step(const Geo& g, const AdjArgs<R>& a, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
   if constexpr (std::is_same<R, float>::value) {
     if (g.ty == 16 && !g.thermal) {
-      alks_step_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(g, a);
+      alks_step_kernel<float, false, 16><<<nb, (NT1<float, false, 16>), 0, s>>>(g, a);
       return;
     }
   }
   if (g.ty == 8) {
-    if (g.thermal) alks_step_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(g, a);
-    else alks_step_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(g, a);
+    if (g.thermal) alks_step_kernel<R, true, 8><<<nb, (NT1<R, true, 8>), 0, s>>>(g, a);
+    else alks_step_kernel<R, false, 8><<<nb, (NT1<R, false, 8>), 0, s>>>(g, a);
   } else {
-    if (g.thermal) alks_step_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(g, a);
-    else alks_step_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(g, a);
+    if (g.thermal) alks_step_kernel<R, true, 4><<<nb, (NT1<R, true, 4>), 0, s>>>(g, a);
+    else alks_step_kernel<R, false, 4><<<nb, (NT1<R, false, 4>), 0, s>>>(g, a);
   }
 }
 // two-step kernels exist for tile heights 4 and 8 (the runtime never asks for others)
@@ -1752,16 +1762,16 @@ void launch_lks_step_batch(const BatchFwd<R>* d, const int* tmap, int total, int
   const unsigned nb = unsigned(xcd_blocks(total));
   if constexpr (std::is_same<R, float>::value) {
     if (ty == 16 && !thermal) {
-      lks_step_batch_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity);
+      lks_step_batch_kernel<float, false, 16><<<nb, (NT1<float, false, 16>), 0, s>>>(d, tmap, total, parity);
       return;
     }
   }
   if (ty == 8) {
-    if (thermal) lks_step_batch_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity);
-    else lks_step_batch_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity);
+    if (thermal) lks_step_batch_kernel<R, true, 8><<<nb, (NT1<R, true, 8>), 0, s>>>(d, tmap, total, parity);
+    else lks_step_batch_kernel<R, false, 8><<<nb, (NT1<R, false, 8>), 0, s>>>(d, tmap, total, parity);
   } else {
-    if (thermal) lks_step_batch_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity);
-    else lks_step_batch_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity);
+    if (thermal) lks_step_batch_kernel<R, true, 4><<<nb, (NT1<R, true, 4>), 0, s>>>(d, tmap, total, parity);
+    else lks_step_batch_kernel<R, false, 4><<<nb, (NT1<R, false, 4>), 0, s>>>(d, tmap, total, parity);
   }
 }
 template <typename R>
@@ -1770,17 +1780,17 @@ void launch_alks_step_batch(const BatchAdj<R>* d, const int* tmap, int total, in
   const unsigned nb = unsigned(xcd_blocks(total));
   if constexpr (std::is_same<R, float>::value) {
     if (ty == 16 && !thermal) {
-      alks_step_batch_kernel<float, false, 16><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity,
+      alks_step_batch_kernel<float, false, 16><<<nb, (NT1<float, false, 16>), 0, s>>>(d, tmap, total, parity,
                                                                        last);
       return;
     }
   }
   if (ty == 8) {
-    if (thermal) alks_step_batch_kernel<R, true, 8><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity, last);
-    else alks_step_batch_kernel<R, false, 8><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity, last);
+    if (thermal) alks_step_batch_kernel<R, true, 8><<<nb, (NT1<R, true, 8>), 0, s>>>(d, tmap, total, parity, last);
+    else alks_step_batch_kernel<R, false, 8><<<nb, (NT1<R, false, 8>), 0, s>>>(d, tmap, total, parity, last);
   } else {
-    if (thermal) alks_step_batch_kernel<R, true, 4><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity, last);
-    else alks_step_batch_kernel<R, false, 4><<<nb, NTHREADS, 0, s>>>(d, tmap, total, parity, last);
+    if (thermal) alks_step_batch_kernel<R, true, 4><<<nb, (NT1<R, true, 4>), 0, s>>>(d, tmap, total, parity, last);
+    else alks_step_batch_kernel<R, false, 4><<<nb, (NT1<R, false, 4>), 0, s>>>(d, tmap, total, parity, last);
   }
 }
 template <typename R>
