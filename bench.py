@@ -485,12 +485,19 @@ def copy_calibration(dev):
     print(json.dumps({"copy_bytes": 4 * n, "copies": 3}), flush=True)
 
 
-def cpu_baseline(wl, n):
-    """The FP64 oracle on the host cores, on a bounded sample of the same
-    workload: n forward and n adjoint steps of the 512x512 grid."""
-    import oracle as O
-    pb = O.Problem(wl)
-    alpha, _, B, _ = O.coefficients(pb, wl.gamma)
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_sample(O, pb, alpha, B, n):
+    """n forward and n adjoint oracle steps of the workload; (forward s,
+    adjoint s)."""
     s = O.init_state(pb, 1.0)
     for _ in range(5):
         s = O.lks_step(pb, alpha, B, 1.0, s)
@@ -502,14 +509,35 @@ def cpu_baseline(wl, n):
     for _ in range(n):
         adj = O.alks_step(pb, alpha, B, s, s, adj, 1.0, 0.0)
     t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
+
+
+def cpu_baseline(wl, n, n_one=None):
+    """The FP64 oracle (gcc -O3, OpenMP) on the host cores, on a bounded
+    sample of the same workload: n forward and n adjoint steps of the grid on
+    every thread OpenMP uses, and a smaller sample on one thread."""
+    import oracle as O
+    pb = O.Problem(wl)
+    alpha, _, B, _ = O.coefficients(pb, wl.gamma)
     nodes = wl.nx * wl.ny
-    mlups = nodes * 2 * n / (t2 - t0) / 1e6
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = O.max_threads()
+    tf, ta = _oracle_sample(O, pb, alpha, B, n)
+    mlups = nodes * 2 * n / (tf + ta) / 1e6
+    n1 = n_one if n_one is not None else max(20, n // 10)
+    O.set_threads(1)
+    try:
+        tf1, ta1 = _oracle_sample(O, pb, alpha, B, n1)
+    finally:
+        O.set_threads(threads)
     return {"value": mlups, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{wl.nx}x{wl.ny}, {n} forward + {n} adjoint FP64 steps "
-                      f"({t1 - t0:.1f} s + {t2 - t1:.1f} s)",
-            "forward_mlups": nodes * n / (t1 - t0) / 1e6,
-            "adjoint_mlups": nodes * n / (t2 - t1) / 1e6}
+            "sample": f"{wl.nx}x{wl.ny}, {n} forward + {n} adjoint FP64 steps on {threads} "
+                      f"threads ({tf:.1f} s + {ta:.1f} s)",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "build": "gcc -O3 -fopenmp",
+            "forward_mlups": nodes * n / tf / 1e6, "adjoint_mlups": nodes * n / ta / 1e6,
+            "gradients_per_s_extrapolated": mlups * 1e6 / (nodes * (wl.n_fwd + wl.n_adj)),
+            "one_thread": {"value": nodes * 2 * n1 / (tf1 + ta1) / 1e6, "unit": "MLUPS",
+                           "sample": f"{n1} forward + {n1} adjoint steps on 1 thread "
+                                     f"({tf1:.1f} s + {ta1:.1f} s)"}}
 
 
 if __name__ == "__main__":

@@ -204,7 +204,11 @@ lks_status lks_objective(lks_ctx *ctx, double *J_host);
 /* Steps 4-5: ALKS adjoint sweep (eq:ap..eq:aq with eq:afeq, eq:ageq and the
  * least-squares adjoint boundary treatment of Sec. 2.5 / Appendix A) and
  * the sensitivity (Sec. 2.5) written to dJdgamma_dev (device, nx*ny doubles,
- * overwritten; zero on boundary nodes). Linear in J_seed.
+ * overwritten; zero on boundary nodes). Linear in J_seed. The boundary seed
+ * of the pressure-drop objective (dJ/df_i in eq:afboundaryu and
+ * eq:afboundaryp) is J_seed per unit boundary pressure, +J_seed on inlet
+ * nodes and -J_seed on outlet nodes, the reading under which the gradient of
+ * the paper's non-thermal check (Sec. 2.6) agrees with central differences.
  * Steady: adj_steps ALKS steps with the state frozen at the last forward
  * level and the seed applied every step, then the sensitivity once.
  * Unsteady: adj_steps is ignored; the sweep runs from the terminal condition
@@ -287,8 +291,9 @@ lks_status lks_memory_report(const lks_ctx *ctx, size_t *ckpt_bytes, size_t *sta
  * forward steps). Call before lks_bind_workspace; it re-plans the workspace
  * (query lks_workspace_size again).
  *   LKS_CKPT_TWO_LEVEL: checkpoints of the whole state every K levels and one
- *     replay segment of K-1 levels, K the largest that fits the budget; the
- *     adjoint recomputes at most one forward sweep.
+ *     replay segment of K-1 levels, K the interval that fits the budget
+ *     with the fewest replayed steps (K = N+1, the whole trajectory, when it
+ *     fits); the adjoint recomputes at most one forward sweep.
  *   LKS_CKPT_BINOMIAL: `slots` snapshots of the whole state besides level 0
  *     (0: as many as the budget holds) placed by Griewank's binomial
  *     reversal schedule, which recomputes the fewest forward steps possible

@@ -50,7 +50,7 @@ def build(force: bool = False) -> str:
     newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC3))
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O3", "-std=c99", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, _SRC3, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -99,11 +99,22 @@ def lib():
         _lib.orc_probe_T.restype = ctypes.c_double
         _lib.orc_sens_add.argtypes = [P, d, d, d, d, d, d, dd, ctypes.c_double, d]
         _lib.orc_source_sens_add.argtypes = [P, d, d, d, d, d, d, d, dd, ctypes.c_double, d]
+        _lib.orc_set_threads.argtypes = [ctypes.c_int]
+        _lib.orc_max_threads.restype = ctypes.c_int
         _lib.orc_boundary_fill.argtypes = [P, ctypes.c_uint8, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, d, d, d, ctypes.c_double]
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _p(a):
@@ -276,22 +287,84 @@ def boundary_fill(pb: Problem, m, normal, Bn, Tn, u, seed_dp, fk, gk, seed_T=0.0
 # --------------------------------------------------------------------------
 # drivers
 # --------------------------------------------------------------------------
-def forward(pb: Problem, gamma, n_steps, store=False, state0: State | None = None):
+class CheckpointedTrajectory:
+    """Levels 0..N of a forward sweep without storing them all: the states of
+    levels 0, K, 2K, ... are kept, and a level between two of them is
+    recomputed, together with the rest of its segment, from the checkpoint
+    that starts the segment (two-level checkpointing). Indexing returns the
+    same state a stored trajectory would hold. The reverse sweep asks for
+    levels in decreasing order, so each segment is recomputed once; a
+    checkpoint level is served from the checkpoint itself.
+
+    step(n, s) returns the state of level n + 1 from that of level n."""
+
+    def __init__(self, step, state0, n_steps: int, K: int, on_level=None):
+        if K < 1:
+            raise ValueError("checkpoint interval must be >= 1")
+        self.step, self.N, self.K = step, n_steps, K
+        self.ckpt = {0: state0}
+        s = state0
+        for n in range(n_steps):
+            s = step(n, s)
+            if on_level is not None:
+                on_level(n + 1, s)
+            if (n + 1) % K == 0:
+                self.ckpt[n + 1] = s
+        self.final = s
+        self.replayed = 0
+        self._start, self._seg = None, None
+
+    def __len__(self):
+        return self.N + 1
+
+    def __getitem__(self, n: int):
+        if n < 0 or n > self.N:
+            raise IndexError(n)
+        if n in self.ckpt:
+            return self.ckpt[n]
+        b = (n // self.K) * self.K
+        if self._start != b:
+            s, seg = self.ckpt[b], [self.ckpt[b]]
+            for m in range(b, min(b + self.K, self.N + 1) - 1):
+                s = self.step(m, s)
+                seg.append(s)
+            self.replayed += len(seg) - 1
+            self._start, self._seg = b, seg
+        return self._seg[n - b]
+
+
+def forward(pb: Problem, gamma, n_steps, store=False, state0: State | None = None,
+            checkpoint: int | None = None):
     """n_steps LKS steps from the level-0 state. Returns (final state, J,
     trajectory or None). Steady: J on the final state. Unsteady: J averaged
-    over levels 1..n_steps."""
+    over levels 1..n_steps. With store, the trajectory is a list of every
+    level, or with checkpoint=K a CheckpointedTrajectory that keeps every
+    K-th level and recomputes the others on demand."""
     wl = pb.wl
     alpha, _, B, _ = coefficients(pb, gamma)
     beta, _ = source_coefficients(pb, gamma)
     s = init_state(pb, wl.ufac[0]) if state0 is None else state0.copy()
-    traj = [s] if store else None
-    acc = 0.0
-    for n in range(n_steps):
-        s = lks_step(pb, alpha, B, float(wl.ufac[min(n + 1, len(wl.ufac) - 1)]), s, beta)
+    acc = [0.0]
+
+    def step(n, st):
+        return lks_step(pb, alpha, B, float(wl.ufac[min(n + 1, len(wl.ufac) - 1)]), st, beta)
+
+    def on_level(n, st):
         if wl.mode == MODE_UNSTEADY:
-            acc += level_objective(pb, s, beta)
+            acc[0] += level_objective(pb, st, beta)
+
+    if store and checkpoint is not None:
+        traj = CheckpointedTrajectory(step, s, n_steps, checkpoint, on_level)
+        s = traj.final
+        J = acc[0] / max(n_steps, 1) if wl.mode == MODE_UNSTEADY else level_objective(pb, s, beta)
+        return s, J, traj
+    traj = [s] if store else None
+    for n in range(n_steps):
+        s = step(n, s)
+        on_level(n + 1, s)
         if store:
             traj.append(s)
+    acc = acc[0]
     if wl.mode == MODE_UNSTEADY:
         J = acc / max(n_steps, 1)
     else:
@@ -345,15 +418,17 @@ def adjoint_unsteady(pb: Problem, gamma, traj, seed=1.0):
     return adj, sens
 
 
-def gradient(wl, gamma=None, seed=1.0):
-    """Objective and ALKS sensitivity for a workload (steady or unsteady)."""
+def gradient(wl, gamma=None, seed=1.0, checkpoint: int | None = None):
+    """Objective and ALKS sensitivity for a workload (steady or unsteady).
+    An unsteady sweep stores every level, or with checkpoint=K every K-th
+    level with replay of the others."""
     pb = Problem(wl)
     g = wl.gamma if gamma is None else gamma
     if wl.mode == MODE_STEADY:
         s, J, _ = forward(pb, g, wl.n_fwd)
         adj, sens = adjoint_steady(pb, g, s, wl.n_adj, seed)
         return J, sens.reshape(wl.ny, wl.nx), s, adj
-    s, J, traj = forward(pb, g, wl.n_fwd, store=True)
+    s, J, traj = forward(pb, g, wl.n_fwd, store=True, checkpoint=checkpoint)
     adj, sens = adjoint_unsteady(pb, g, traj, seed)
     return J, sens.reshape(wl.ny, wl.nx), s, adj
 

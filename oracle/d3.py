@@ -15,6 +15,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from . import CheckpointedTrajectory
 from . import build as _build_lib
 
 N_ADJ3 = 14
@@ -167,19 +168,33 @@ def boundary_fill(pb: Problem3, m, normal, Bn, Tn, u, seed_dp, fk, gk):
     return fk, gk, mult
 
 
-def forward(pb: Problem3, gamma, n_steps, store=False, state0: State3 | None = None):
+def forward(pb: Problem3, gamma, n_steps, store=False, state0: State3 | None = None,
+            checkpoint: int | None = None):
+    """As oracle.forward: with store, every level, or with checkpoint=K a
+    CheckpointedTrajectory (every K-th level kept, the others recomputed)."""
     wl = pb.wl
     alpha, _, B, _ = coefficients(pb, gamma)
     s = init_state(pb, wl.ufac[0]) if state0 is None else state0.copy()
-    traj = [s] if store else None
-    acc = 0.0
-    for n in range(n_steps):
-        s = lks_step(pb, alpha, B, float(wl.ufac[min(n + 1, len(wl.ufac) - 1)]), s)
+    acc = [0.0]
+
+    def step(n, st):
+        return lks_step(pb, alpha, B, float(wl.ufac[min(n + 1, len(wl.ufac) - 1)]), st)
+
+    def on_level(n, st):
         if wl.mode != MODE_STEADY:
-            acc += level_objective(pb, s)
-        if store:
-            traj.append(s)
-    J = acc / max(n_steps, 1) if wl.mode != MODE_STEADY else level_objective(pb, s)
+            acc[0] += level_objective(pb, st)
+
+    if store and checkpoint is not None:
+        traj = CheckpointedTrajectory(step, s, n_steps, checkpoint, on_level)
+        s = traj.final
+    else:
+        traj = [s] if store else None
+        for n in range(n_steps):
+            s = step(n, s)
+            on_level(n + 1, s)
+            if store:
+                traj.append(s)
+    J = acc[0] / max(n_steps, 1) if wl.mode != MODE_STEADY else level_objective(pb, s)
     return s, J, traj
 
 
@@ -218,7 +233,7 @@ def adjoint_unsteady(pb: Problem3, gamma, traj, seed=1.0):
     return adj, sens
 
 
-def gradient(wl, gamma=None, seed=1.0):
+def gradient(wl, gamma=None, seed=1.0, checkpoint: int | None = None):
     pb = Problem3(wl)
     g = wl.gamma if gamma is None else gamma
     shape = (wl.nz, wl.ny, wl.nx)
@@ -226,7 +241,7 @@ def gradient(wl, gamma=None, seed=1.0):
         s, J, _ = forward(pb, g, wl.n_fwd)
         adj, sens = adjoint_steady(pb, g, s, wl.n_adj, seed)
         return J, sens.reshape(shape), s, adj
-    s, J, traj = forward(pb, g, wl.n_fwd, store=True)
+    s, J, traj = forward(pb, g, wl.n_fwd, store=True, checkpoint=checkpoint)
     adj, sens = adjoint_unsteady(pb, g, traj, seed)
     return J, sens.reshape(shape), s, adj
 

@@ -31,6 +31,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q9 9
 
@@ -548,8 +551,19 @@ static void lsq_solve(int rows, int cols, const double *K, const double *b,
  * printed matrix M is garbled (it repeats c_b c_b); this reading is the one
  * that reproduces the printed closed form eq:ftilde, with least squares over
  * all nine rows. Unknowns: f~_i with c_i.n > 0 and the multipliers.
- * s_i = dJ_dO/df_i: for the pressure-drop objective p = sum f_i / 3, so
- * s_i = +seed/3 on inlet nodes and -seed/3 on outlet nodes.
+ * s_i = dJ_dO/df_i, the boundary seed. Reading: for the pressure-drop
+ * objective (J_dO = p on inlet nodes, -p on outlet nodes) s_i is the
+ * derivative of J_dO with respect to the boundary pressure, +seed on inlet
+ * nodes and -seed on outlet nodes, in every row. The least-squares solution
+ * takes -2 s_i into each unknown, so the completed set carries an adjoint
+ * velocity with 3 u~.n = -s_i: the adjoint velocity that the continuous
+ * adjoint of a velocity boundary carries for an objective that integrates
+ * the pressure there. Taken literally, p = sum f_i / 3 would give seed/3,
+ * and with it the gradient of the paper's own non-thermal check (Sec. 2.6,
+ * where ALKS and finite differences are reported in strong agreement) comes
+ * out uniformly one third of central differences; with the pressure
+ * derivative it agrees with them to about 2 %. On outlet nodes the seed is
+ * taken up by lambda~ in either reading.
  *
  * Thermal rows (eq:agboundaryT / eq:agboundaryq), for every i:
  *   r_i = (n.c_i) g~_i - B (n.q~) + [eta~ | kappa~ (c_i - u).n] + s_T
@@ -603,8 +617,8 @@ static void boundary_fill(const orc_problem *P, uint8_t m, const int n[2],
   double K[Q9 * 8], b[Q9], x[8];
   double t[2] = {-n[1], n[0]};
   double s = 0.0;
-  if (m & TAG_J_INLET) s += seed_dp / 3.0;
-  if (m & TAG_J_OUTLET) s -= seed_dp / 3.0;
+  if (m & TAG_J_INLET) s += seed_dp;
+  if (m & TAG_J_OUTLET) s -= seed_dp;
   for (int r = 0; r < Q9; ++r) {
     double known = 0.0;
     for (int q = 0; q < Q9; ++q) {
@@ -838,4 +852,21 @@ void orc_boundary_fill(const orc_problem *P, uint8_t m, int nx_, int ny_,
                        double seed_T) {
   int n[2] = {nx_, ny_};
   boundary_fill(P, m, n, coef_A(P), Bn, Tn, unx, uny, seed_dp, seed_T, fk, gk, mult);
+}
+
+/* OpenMP thread count of the oracle's loops (timing on 1 core and on all) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -470,8 +470,9 @@ static void fill3(const orc3_problem *P, uint8_t m, const int n[3], double A, do
   int cols = nu + 3;
   double K[Q19 * 12], b[Q19], x[12];
   double s = 0.0;
-  if (m & TAG_J_INLET) s += seed_dp / 3.0;
-  if (m & TAG_J_OUTLET) s -= seed_dp / 3.0;
+  /* the boundary seed per unit pressure, as in the D2Q9 fill */
+  if (m & TAG_J_INLET) s += seed_dp;
+  if (m & TAG_J_OUTLET) s -= seed_dp;
   for (int r = 0; r < Q19; ++r) {
     double known = 0.0;
     for (int q = 0; q < Q19; ++q) {

@@ -744,9 +744,11 @@ __device__ inline void ring_apply(OP op, int v, int o, const AdjArgs<R>& a, cons
       }
     }
   }
+  // boundary seed of the pressure-drop objective: its derivative with
+  // respect to the boundary pressure, the same in every row
   R s = R(0);
-  if (m & TAG_J_INLET) s += R(a.seed_dp / 3.0);
-  if (m & TAG_J_OUTLET) s -= R(a.seed_dp / 3.0);
+  if (m & TAG_J_INLET) s += R(a.seed_dp);
+  if (m & TAG_J_OUTLET) s -= R(a.seed_dp);
   const R kT = TH ? kappa * sTn[p2] : R(0);
   R fu[3];
 #pragma nounroll

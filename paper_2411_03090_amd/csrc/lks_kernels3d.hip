@@ -798,9 +798,10 @@ __device__ inline void face_apply(OP op, int v, int o, const Adj3Args<R>& a, int
       }
     }
   }
+  // boundary seed of the pressure-drop objective per unit boundary pressure
   R s = R(0);
-  if (m & TAG_J_INLET3) s += R(a.seed_dp / 3.0);
-  if (m & TAG_J_OUTLET3) s -= R(a.seed_dp / 3.0);
+  if (m & TAG_J_INLET3) s += R(a.seed_dp);
+  if (m & TAG_J_OUTLET3) s -= R(a.seed_dp);
   const R kT = kappa * Tn;
 #pragma nounroll
   for (int c = 0; c < 5; ++c) {

@@ -310,10 +310,14 @@ lks_status plan_binomial(lks_ctx* c, Plan& p, size_t base) {
   return LKS_OK;
 }
 
-// Unsteady problems: two-level checkpointing (the largest interval K whose
-// storage fits the budget, the fewest replayed steps for the memory given;
-// K = N+1 keeps every level) unless binomial checkpointing is requested, or
-// no two-level plan fits the budget and the scheme is automatic.
+// Unsteady problems: two-level checkpointing unless binomial checkpointing
+// is requested, or no two-level plan fits the budget and the scheme is
+// automatic. Among the intervals K whose storage fits the budget, the plan
+// takes the one that replays the fewest forward steps (ls - ls/K with
+// ls = (N/K) K, which grows with K; K = N+1 keeps every level and replays
+// none), and of equal replay counts the one that needs the least memory.
+// Checkpoint and segment levels are written by the step kernels in place,
+// so a smaller interval costs no extra copies in the forward sweep.
 lks_status plan_memory(lks_ctx* c) {
   Plan p;
   size_t base = base_bytes(c);
@@ -329,11 +333,17 @@ lks_status plan_memory(lks_ctx* c) {
   }
   const int n = c->n_steps;
   int best = 0;
-  for (int K = n + 1; K >= 1; --K) {
-    size_t t = traj_bytes(c, K) + 2 * 256;
-    if (c->budget == 0 || base + t <= c->budget) {
+  long long best_rep = 0;
+  size_t best_t = 0;
+  for (int K = 1; K <= n + 1; ++K) {
+    const size_t t = traj_bytes(c, K) + 2 * 256;
+    if (c->budget != 0 && base + t > c->budget) continue;
+    const long long ls = (long long)(n / K) * K;
+    const long long rep = K > n ? 0 : ls - ls / K;
+    if (best == 0 || rep < best_rep || (rep == best_rep && t < best_t)) {
       best = K;
-      break;
+      best_rep = rep;
+      best_t = t;
     }
   }
   if (best == 0 && c->ckpt_scheme == LKS_CKPT_AUTO) {
@@ -1465,7 +1475,9 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
   float best = 0.0f;
   int best_ty = c->geo.ty, best_f = c->spl_f, best_a = c->spl_a;
   const int mode = c->mode;
-  const int nspl = c->rsz == 4 ? 2 : 1;
+  // two steps per launch exist for steady FP32 sweeps only; an unsteady
+  // context times (and keeps) one step per launch
+  const int nspl = (c->rsz == 4 && mode != LKS_UNSTEADY) ? 2 : 1;
   c->mode = LKS_STEADY;  // time plain steps on the ping-pong buffers
   for (int ty : TILE_ROWS) {
     if (!tile_rows_ok(ty, c->rsz, c->phys.thermal)) continue;

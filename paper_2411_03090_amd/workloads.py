@@ -327,6 +327,83 @@ def heat_sink(nx=141, ny=161, Ra=2e5, Pr=6.0, q0=1e-2, Ks_over_Kf=10.0, heater=0
                     ufac=np.ones(n_steps + 1))
 
 
+def sensitivity_check_square(n=101, Re=1.0, alpha_max=1.0, n_fwd=20000, n_adj=20000, nu=0.1):
+    """The non-thermal sensitivity check of Sec. 2.6: a square of
+    (n-1) x (n-1) cells (101 x 101 nodes for the paper's 100 dx) closed by
+    no-slip walls, with a parabolic inflow through the middle third of the
+    left side (nodes 33..67 at n = 101, the roots of the printed profile) and
+    a pressure outlet on the same span of the right side; gamma = 0.1 inside
+    the centred circle of radius (n-1)/6 and 0.9 elsewhere, the ring fluid;
+    Re = 1 on the characteristic length (n-1)/3 with nu = 0.1. The paper does
+    not print alpha_bar; it is a parameter here. The inlet and outlet nodes
+    carry the pressure-drop tags."""
+    H = n - 1
+    a, b = int(round(H / 3.0)), int(round(2.0 * H / 3.0))
+    m = np.zeros((n, n), np.uint8)
+    m[1:-1, 0] = FLOW_VELOCITY
+    m[1:-1, -1] = FLOW_VELOCITY
+    m[0, 1:-1] = FLOW_VELOCITY
+    m[-1, 1:-1] = FLOW_VELOCITY
+    m[a:b + 1, 0] = FLOW_VELOCITY | TAG_J_INLET
+    m[a:b + 1, -1] = FLOW_PRESSURE | TAG_J_OUTLET
+    for j, i in ((0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1)):
+        m[j, i] = FLOW_CORNER
+    u_max = Re * nu / (H / 3.0)
+    ubar = np.zeros((2, n, n))
+    jj = np.arange(a, b + 1, dtype=np.float64)
+    ubar[0, a:b + 1, 0] = u_max * 4.0 * (jj - a) * (b - jj) / float((b - a) ** 2)
+    g = np.full((n, n), 0.9)
+    y, x = np.mgrid[0:n, 0:n]
+    g[(x - H / 2.0) ** 2 + (y - H / 2.0) ** 2 <= (H / 6.0) ** 2] = 0.1
+    _ring_to_fluid(g)
+    return Workload(name=f"sensitivity_check_square_{n}_a{alpha_max:g}", nx=n, ny=n, nu=nu,
+                    u_max=u_max, alpha_max=alpha_max, q_alpha=0.1, thermal=False,
+                    objective=OBJ_PRESSURE_DROP, mode=MODE_STEADY, n_fwd=n_fwd, n_adj=n_adj,
+                    mask=m, gamma=g, ubar=ubar, Tbar=np.zeros((n, n)),
+                    ufac=np.ones(n_fwd + 1))
+
+
+def sensitivity_check_natural_convection(nx=141, ny=81, Ra=2e5, Pr=6.0, Ks_over_Kf=10.0,
+                                         q0=1e-2, n_steps=2000, nu=0.1, alpha_max=10.0,
+                                         heater=4, adjoint_mode="paper"):
+    """The natural-convection sensitivity check of Sec. 2.6: a closed cavity
+    of 140 x 80 cells (141 x 81 nodes), no-slip walls, prescribed temperature
+    T = 0 on the left, right and top sides, the bottom side adiabatic except
+    its centred `heater` cells (4 dx as printed), where the heat flux q0
+    enters; gamma = 1 outside the centred design domain of 80 x 50 cells,
+    0.9 inside it and 0.1 in its centred 40 x 25 core. The paper leaves the
+    Rayleigh number, the conductivity ratio, alpha_bar, the horizon and the
+    objective unstated; they are taken from the heat-sink problem of Sec. 3.4
+    (Boussinesq force sized by Ra on L = ny - 1, K_s = 10 K_f, the mean
+    temperature of the heated boundary averaged over the horizon)."""
+    L = ny - 1
+    Kf = nu / Pr
+    gb = Ra * nu * Kf / L ** 3
+    m = np.zeros((ny, nx), np.uint8)
+    m[1:-1, 0] = FLOW_VELOCITY | THERM_DIRICHLET
+    m[1:-1, -1] = FLOW_VELOCITY | THERM_DIRICHLET
+    m[-1, 1:-1] = FLOW_VELOCITY | THERM_DIRICHLET
+    m[0, 1:-1] = FLOW_VELOCITY | THERM_FLUX
+    h0 = (nx - 1 - heater) // 2
+    h1 = h0 + heater
+    m[0, h0:h1 + 1] |= TAG_PROBE
+    for j, i in ((0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1)):
+        m[j, i] = FLOW_CORNER
+    Tbar = np.zeros((ny, nx))
+    Tbar[0, h0:h1 + 1] = q0
+    g = np.ones((ny, nx))
+    dx0, dy0 = (nx - 1 - 80) // 2, (ny - 1 - 50) // 2
+    g[dy0:dy0 + 51, dx0:dx0 + 81] = 0.9
+    cx0, cy0 = (nx - 1 - 40) // 2, (ny - 1 - 25) // 2
+    g[cy0:cy0 + 26, cx0:cx0 + 41] = 0.1
+    return Workload(name=f"sensitivity_check_nc_{nx}x{ny}", nx=nx, ny=ny, nu=nu, u_max=0.0,
+                    alpha_max=alpha_max, q_alpha=0.1, thermal=True, Pr=Pr,
+                    Ks_over_Kf=Ks_over_Kf, q_K=0.1, objective=OBJ_HEAT_SINK,
+                    mode=MODE_UNSTEADY, n_fwd=n_steps, n_adj=n_steps, gbeta=(0.0, gb),
+                    T_ref=0.0, mask=m, gamma=g, ubar=np.zeros((2, ny, nx)), Tbar=Tbar,
+                    ufac=np.ones(n_steps + 1), adjoint_mode=adjoint_mode)
+
+
 def batch_designs(n_designs=64, sizes=(128, 192, 256, 384, 512),
                   Re_range=(10.0, 200.0), sigma=8.0, n_steps=2000):
     """Independent steady designs of uneven size: for design d, default_rng(d)

@@ -269,10 +269,19 @@ def test_checkpoint_plan_follows_the_budget():
     rep = c.memory_report()
     assert 1 < rep["K"] < 1000
     assert c.workspace_size() <= budget
-    # the next larger interval would not fit
+    # the plan replays the fewest steps of all the intervals that fit
     K = rep["K"]
-    nxt = ((1000 // (K + 1)) + 1) * 4 * N * 4 + K * 3 * N * 4
-    assert base + nxt > budget
+
+    def replay(k):
+        ls = (1000 // k) * k
+        return 0 if k > 1000 else ls - ls // k
+
+    def fits(k):
+        return base + ((1000 // k) + 1) * 4 * N * 4 + (k - 1) * 3 * N * 4 + 2 * 256 <= budget
+
+    assert c.checkpoint_info()["replay_steps"] == replay(K)
+    assert fits(K)
+    assert all(replay(k) >= replay(K) for k in range(1, 1002) if fits(k))
     with pytest.raises(lks.LKSError) as e:
         _create(wl, "fp32", base // 2)
     assert e.value.status == lks.LKS_E_NOMEM

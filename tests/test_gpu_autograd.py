@@ -56,9 +56,9 @@ def test_backward_recomputes_a_stale_forward():
 
 def test_directional_fd_through_the_function():
     """Central differences of J through LKSFunction.forward along a smooth
-    direction agree with the oracle's; the ALKS directional derivative is
-    highly correlated with them but about a third of their size (the
-    paper's approximate adjoint boundary treatment, as in the oracle pins)."""
+    direction agree with the oracle's; the ALKS directional derivative agrees
+    with them within 10 % (the paper's approximate adjoint boundary treatment;
+    the oracle gives 0.5-4 % on these directions)."""
     print("[gpu] autograd directional FD", flush=True)
     wl = _wl()
     solver = lks.LKS(wl, precision="fp64", device=DEV)
@@ -84,4 +84,4 @@ def test_directional_fd_through_the_function():
         jm = O.objective(w2, (base - eps * d).reshape(wl.ny, wl.nx))
         assert abs((jp - jm) / (2 * eps) - fd[-1]) < 1e-6 * abs(fd[-1]) + 1e-12
     ratio = np.array(adj) / np.array(fd)
-    assert np.all(ratio > 0.15) and np.all(ratio < 0.8), ratio
+    assert np.all(np.abs(ratio - 1.0) < 0.1), ratio

@@ -340,14 +340,66 @@ def test_gradient_matches_fd_periodic_thermal():
     assert np.all(np.abs(adj / fd - 1.0) < 0.15)
 
 
-def test_gradient_vs_fd_channel_steady_is_recorded():
-    """Channel with the paper's least-squares boundary treatment. The
-    gradient is highly correlated with central differences, but its
-    magnitude is about a third of them: under this reading of eq:afboundaryu
-    the least-squares fill passes only part of the inlet seed dJ/df_i into
-    the adjoint (the rest-direction row cannot absorb it). Parity with the
-    exact gradient is unpinned; the figures are recorded here so that a
-    change of reading shows up."""
+def _steady_converged(pb, gamma, s0=None, tol=1e-15, chunk=500, max_steps=200000):
+    """Forward steps until no field changes by more than tol in a step."""
+    alpha, _, B, _ = O.coefficients(pb, gamma)
+    s = O.init_state(pb, 1.0) if s0 is None else s0.copy()
+    n = 0
+    while n < max_steps:
+        for _ in range(chunk):
+            prev, s = s, O.lks_step(pb, alpha, B, 1.0, s)
+        n += chunk
+        if max(np.abs(s.drho - prev.drho).max(), np.abs(s.ux - prev.ux).max(),
+               np.abs(s.uy - prev.uy).max()) < tol:
+            return s, n
+    raise AssertionError("forward did not converge")
+
+
+def test_gradient_matches_fd_on_the_papers_nonthermal_check():
+    """The non-thermal sensitivity check of Sec. 2.6, where the paper reports
+    strong agreement between ALKS and central differences (eq:sensfdm,
+    eps = 1e-3) along a line through the domain: 101 x 101 nodes, inflow
+    through the middle third of the left side, outlet on the same span of the
+    right side, gamma = 0.1 in the centred circle of radius 100/6 and 0.9
+    elsewhere, Re = 1 on L = 100/3, nu = 0.1 (alpha_bar is not printed: 1).
+    The steady state and the steady adjoint are converged; the gradient along
+    the horizontal centre line agrees with central differences within 8 %
+    per node (the largest gap, 6 %, next to the circle's edge, where the paper
+    also notes errors at interfaces) and 3 % in relative L2 (measured on ten
+    nodes: median ratio 0.996, relative L2 1.4 %). This fixes the magnitude of the
+    boundary seed in eq:afboundaryu (the reading of dJ/df_i as the
+    derivative with respect to the boundary pressure: with the literal
+    p = sum f_i / 3 the ratio is one third at every node)."""
+    wl = W.sensitivity_check_square(101, alpha_max=1.0)
+    pb = O.Problem(wl)
+    s, n = _steady_converged(pb, wl.gamma)
+    _, sens = O.adjoint_steady(pb, wl.gamma, s, n + 2000)
+    sens = sens.reshape(wl.ny, wl.nx)
+    jc, eps = 50, 1e-3
+    pts = [12, 32, 52, 72, 92]
+    fd = []
+    for i in pts:
+        v = []
+        for e in (eps, -eps):
+            g = wl.gamma.copy()
+            g[jc, i] += e
+            v.append(O.pressure_drop(pb, _steady_converged(pb, g, s0=s)[0]))
+        fd.append((v[0] - v[1]) / (2 * eps))
+    fd = np.array(fd)
+    adj = sens[jc, pts]
+    assert np.all(np.abs(adj / fd - 1.0) < 0.08)
+    assert np.linalg.norm(adj - fd) / np.linalg.norm(fd) < 0.03
+
+
+def test_gradient_matches_fd_channel_steady():
+    """A small channel (inlet, outlet and walls all within a few nodes of
+    every design node) with the pressure-drop objective: the ALKS gradient
+    agrees with central differences of the converged objective in magnitude
+    (measured: median ratio 1.000, correlation 0.991, relative L2 9.6 %,
+    per-node ratios 0.88-1.26 on nodes at most four cells from a boundary,
+    where the paper notes the errors of its boundary treatment); the
+    least-squares completion with the boundary seed per unit pressure carries
+    the objective into the adjoint at its full magnitude."""
     nx, ny = 14, 10
     wl = W.steady_channel_uniform(nx, ny, Re=10, seed=3, n_fwd=6000, n_adj=6000)
     wl.alpha_max = 0.5
@@ -356,10 +408,9 @@ def test_gradient_vs_fd_channel_steady_is_recorded():
     pts = [(j, i) for j in range(1, ny - 1, 2) for i in range(1, nx - 1, 3)]
     fd = _fd(wl, pts, 1e-4)
     adj = np.array([sens[p] for p in pts])
-    corr = np.corrcoef(adj, fd)[0, 1]
-    ratio = np.median(adj / fd)
-    assert corr > 0.99
-    assert 0.25 < ratio < 0.5
+    assert np.corrcoef(adj, fd)[0, 1] > 0.98
+    assert np.median(adj / fd) == pytest.approx(1.0, abs=0.05)
+    assert np.linalg.norm(adj - fd) / np.linalg.norm(fd) < 0.15
 
 
 @pytest.mark.slow
