@@ -738,6 +738,12 @@ void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
           qx += W[q] * CX[q] * g;
           qy += W[q] * CY[q] * g;
         }
+        /* exact mode: the temperature of a prescribed-temperature node does
+         * not depend on the populations that arrive there, so their adjoint
+         * vanishes (T~ = q~ = 0) in place of the least-squares completion
+         * of eq:agboundaryT; without it a conductivity contrast next to
+         * such a wall makes the adjoint grow without bound */
+        if (bnd && P->adj_exact && THERM(m) == THERM_DIRICHLET) Tt = qx = qy = 0.0;
       }
       /* f~ (without the implicit Brinkman part) and its moments */
       double r = 0, Ux = 0, Uy = 0, sxx = 0, sxy = 0, syy = 0;

@@ -548,7 +548,12 @@ void orc3_alks_step(const orc3_problem *P, const double *alpha, const double *B,
         Tt += w3(q) * g;
         for (int a = 0; a < 3; ++a) qv[a] += w3(q) * C3[q][a] * g;
       }
-      if (!ne && THERM(m) == THERM_DIRICHLET) {
+      /* the temperature of a prescribed-temperature node does not depend
+       * on the populations that arrive there, so their adjoint vanishes:
+       * inside the domain in both modes, and on faces in the exact mode
+       * (the paper's least-squares completion of eq:agboundaryT there
+       * otherwise) */
+      if (THERM(m) == THERM_DIRICHLET && (!ne || P->adj_exact)) {
         Tt = 0.0;
         qv[0] = qv[1] = qv[2] = 0.0;
       }

@@ -793,6 +793,11 @@ __device__ inline void ring_apply(OP op, int v, int o, const AdjArgs<R>& a, cons
       qy += cy * wg;
     }
   }
+  if constexpr (TH) {
+    // exact mode: the temperature of a prescribed-temperature node does not
+    // depend on the populations that arrive there, so their adjoint is zero
+    if (a.exact && ((m >> 2) & 3) == THERM_DIRICHLET) Tt = qx = qy = R(0);
+  }
   mom[0] = r;
   mom[1] = Ux;
   mom[2] = Uy;

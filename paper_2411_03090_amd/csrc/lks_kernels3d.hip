@@ -851,7 +851,9 @@ __device__ inline void adj_local(const Adj3Args<R>& a, int k, int m, int ne, R T
   if constexpr (TH) {
     const bool probe = (m & TAG_PROBE3) && a.seed_heat != 0.0;
     if (probe) M[10] -= R(a.seed_heat) * a.u[0][k];
-    if (!ne && ((m >> 2) & 3) == THERM_DIRICHLET3) {
+    // a prescribed temperature does not depend on the arriving populations:
+    // zero thermal adjoint inside (both modes) and on faces (exact mode)
+    if (((m >> 2) & 3) == THERM_DIRICHLET3 && (!ne || a.exact)) {
       M[10] = R(0);
       M[11] = M[12] = M[13] = R(0);
     }
