@@ -186,6 +186,28 @@ lks_status lks_workspace_size(const lks_ctx *ctx, size_t *bytes);
  * context's use. */
 lks_status lks_bind_workspace(lks_ctx *ctx, void *dev_ptr, size_t bytes);
 
+/* Size of the library's static per-device workspace array (64 MiB). */
+#define LKS_STATIC_WORKSPACE_BYTES (64u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): bind the context
+ * to the library's static workspace array on the current device instead of
+ * caller memory, then use the context as after lks_bind_workspace. The array
+ * (LKS_STATIC_WORKSPACE_BYTES, 256-byte aligned) is part of the library's
+ * code object: each device holds its own copy from the first load of the
+ * library until the process ends; this call allocates no device memory
+ * (no hipMalloc, hipFree or allocating library routine), it uploads the
+ * boundary data and clears the state like lks_bind_workspace.
+ * One array per device is shared by every context: binding a context makes
+ * the context bound to it before on that device unusable (its calls return
+ * LKS_E_STATE until it is bound again), and calls of two contexts that
+ * overlap in time on one device race. The array keeps the last context's
+ * contents; everything a sweep needs cleared is cleared by the sweep.
+ * Errors: LKS_E_NOMEM when lks_workspace_size exceeds
+ * LKS_STATIC_WORKSPACE_BYTES (nothing is bound), LKS_E_HIP when the array's
+ * device address cannot be obtained. */
+lks_status lks_bind_static_workspace(lks_ctx *ctx);
+
 /* Step 2: reset to the level-0 state (rho = 1, u = 0, T = 0 inside, the
  * prescribed values on the boundary) and run `steps` LKS steps
  * (eq:rho, eq:u, eq:T with eq:feq2, eq:geq2 and the implicit Brinkman term

@@ -9,6 +9,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -30,6 +32,14 @@ namespace {
 thread_local std::string g_create_error;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// message of a call on a context without a usable workspace
+template <typename C>
+const char* unbound_reason(const C* c) {
+  return c->static_dev >= 0
+             ? "the static workspace was bound by another context since (bind again)"
+             : "no workspace bound";
+}
 
 // One action of a binomial reversal schedule: advance `steps` LKS steps from
 // the level `from` held in snapshot `src` (the last step writes snapshot
@@ -78,6 +88,7 @@ struct lks_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool bound = false;
+  int static_dev = -1;    // device whose static scratch array is bound, or -1
   // carved device pointers (element type depends on precision)
   uint8_t* d_mask = nullptr;
   void *ubx = nullptr, *uby = nullptr, *ubz = nullptr, *Tb = nullptr;
@@ -1128,6 +1139,25 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
   return LKS_OK;
 }
 
+}  // extern "C"
+
+// The allocation-free workspace: one array per device, loaded with the code
+// object and held until the process ends. Host code never passes the array's
+// name to a kernel (on the host it is a stand-in, not a device address); it
+// asks for the device address once per device and uses that.
+namespace {
+static __device__ __align__(256) unsigned char scratch[LKS_STATIC_WORKSPACE_BYTES];
+
+struct StaticScratch {
+  void* ptr = nullptr;            // device address of `scratch` on the device
+  const lks_ctx* owner = nullptr;  // context bound to it last
+};
+std::mutex g_scratch_mu;
+std::map<int, StaticScratch> g_scratch;  // by device ordinal
+}  // namespace
+
+extern "C" {
+
 lks_status lks_workspace_size(const lks_ctx* c, size_t* bytes) {
   if (!c || !bytes) return LKS_E_INVALID;
   *bytes = c->plan.total;
@@ -1243,14 +1273,52 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
       !hip_ok(c, hipStreamSynchronize(c->stream), "bind sync", &st))
     return st;
   c->bound = true;
+  c->static_dev = -1;
   c->have_forward = false;
   c->have_adjoint = false;
   return check_launch(c);
 }
 
+lks_status lks_bind_static_workspace(lks_ctx* c) {
+  if (!c) return LKS_E_INVALID;
+  if (c->plan.total > size_t(LKS_STATIC_WORKSPACE_BYTES)) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "workspace of %zu B exceeds the static array of %zu B",
+             c->plan.total, size_t(LKS_STATIC_WORKSPACE_BYTES));
+    return fail(c, LKS_E_NOMEM, buf);
+  }
+  lks_status st = LKS_OK;
+  int dev = 0;
+  if (!hip_ok(c, hipGetDevice(&dev), "current device", &st)) return st;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  StaticScratch& sc = g_scratch[dev];
+  if (!sc.ptr) {
+    void* ptr = nullptr;
+    if (!hip_ok(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "static workspace address",
+                &st))
+      return st;
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255))
+      return fail(c, LKS_E_HIP, "static workspace address is null or misaligned");
+    sc.ptr = ptr;
+  }
+  // the previous context of this device loses the array: its state is gone
+  if (sc.owner && sc.owner != c) {
+    lks_ctx* prev = const_cast<lks_ctx*>(sc.owner);
+    prev->bound = false;
+    prev->have_forward = false;
+    prev->have_adjoint = false;
+  }
+  sc.owner = nullptr;
+  st = lks_bind_workspace(c, sc.ptr, size_t(LKS_STATIC_WORKSPACE_BYTES));
+  if (st != LKS_OK) return st;
+  c->static_dev = dev;
+  sc.owner = c;
+  return LKS_OK;
+}
+
 static lks_status forward_impl(lks_ctx* c, const double* gamma, int steps, bool reset) {
   if (!c) return LKS_E_INVALID;
-  if (!c->bound) return fail(c, LKS_E_STATE, "no workspace bound");
+  if (!c->bound) return fail(c, LKS_E_STATE, unbound_reason(c));
   if (!gamma) return fail(c, LKS_E_INVALID, "null gamma");
   if (steps < 0) return fail(c, LKS_E_INVALID, "negative step count");
   if (c->mode == LKS_UNSTEADY) {
@@ -1368,7 +1436,7 @@ lks_status alks_advance(lks_ctx* c, double J_seed, int steps, double* dJdgamma_d
 
 lks_status lks_read_field(lks_ctx* c, int which, double* dev_out) {
   if (!c || !dev_out) return LKS_E_INVALID;
-  if (!c->bound) return fail(c, LKS_E_STATE, "no workspace bound");
+  if (!c->bound) return fail(c, LKS_E_STATE, unbound_reason(c));
   lks_status st = c->rsz == 8 ? Run<double>(c).read(which, dev_out)
                               : Run<float>(c).read(which, dev_out);
   if (st != LKS_OK) return fail(c, st, "field not available");
@@ -1377,7 +1445,7 @@ lks_status lks_read_field(lks_ctx* c, int which, double* dev_out) {
 
 lks_status lks_write_field(lks_ctx* c, int which, const double* dev_in) {
   if (!c || !dev_in) return LKS_E_INVALID;
-  if (!c->bound) return fail(c, LKS_E_STATE, "no workspace bound");
+  if (!c->bound) return fail(c, LKS_E_STATE, unbound_reason(c));
   lks_status st = c->rsz == 8 ? Run<double>(c).write(which, dev_in)
                               : Run<float>(c).write(which, dev_in);
   if (st != LKS_OK) return fail(c, st, "field not writable");
@@ -1465,7 +1533,7 @@ lks_status lks_launch_shape(const lks_ctx* c, int* tile_rows, int* forward_steps
 lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* tile_rows) {
   if (!c || !gamma_dev || steps < 1) return LKS_E_INVALID;
   if (c->dim == 3) return fail(c, LKS_E_UNSUPPORTED, "D3Q19 kernels are not tiled");
-  if (!c->bound) return fail(c, LKS_E_STATE, "no workspace bound");
+  if (!c->bound) return fail(c, LKS_E_STATE, unbound_reason(c));
   lks_status st = LKS_OK;
   hipEvent_t e[3];
   for (auto& ev : e)
@@ -1554,7 +1622,14 @@ const char* lks_last_error(const lks_ctx* c) {
   return c ? c->err.c_str() : g_create_error.c_str();
 }
 
-void lks_destroy(lks_ctx* c) { delete c; }
+void lks_destroy(lks_ctx* c) {
+  if (c && c->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(c->static_dev);
+    if (it != g_scratch.end() && it->second.owner == c) it->second.owner = nullptr;
+  }
+  delete c;
+}
 
 }  // extern "C"
 

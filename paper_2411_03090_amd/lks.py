@@ -58,7 +58,11 @@ EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forwa
             "lks_batch_last_error", "lks_batch_destroy", "lks_autotune",
             "lks_batch_autotune", "lks_set_tile_rows", "lks_set_steps_per_launch",
             "lks_launch_shape", "lks_batch_set_tile_rows", "lks_set_adjoint_mode",
-            "lks_set_checkpointing", "lks_checkpoint_info", "lks_gradient_status")
+            "lks_set_checkpointing", "lks_checkpoint_info", "lks_gradient_status",
+            "lks_bind_static_workspace")
+
+# LKS_STATIC_WORKSPACE_BYTES of lks.h
+STATIC_WORKSPACE_BYTES = 64 * 1024 * 1024
 
 
 class Grid(ctypes.Structure):
@@ -95,6 +99,8 @@ _lib.lks_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
 _lib.lks_workspace_size.restype = _st
 _lib.lks_bind_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
 _lib.lks_bind_workspace.restype = _st
+_lib.lks_bind_static_workspace.argtypes = [_vp]
+_lib.lks_bind_static_workspace.restype = _st
 _lib.lks_forward.argtypes = [_vp, _vp, ctypes.c_int]
 _lib.lks_forward.restype = _st
 _lib.lks_advance.argtypes = [_vp, _vp, ctypes.c_int]
@@ -237,6 +243,12 @@ class LKS:
         _check(_lib.lks_workspace_size(self.ctx, ctypes.byref(n)), self.ctx)
         return n.value
 
+    def bind_static(self):
+        """Bind the library's static per-device workspace array (no device
+        allocation; see lks_bind_static_workspace)."""
+        self.workspace = None
+        _check(_lib.lks_bind_static_workspace(self.ctx), self.ctx)
+
     def bind(self):
         """Allocate the workspace as a torch tensor and hand it to the library."""
         import torch
@@ -271,7 +283,8 @@ class LKS:
     def read(self, name, out=None):
         import torch
         if out is None:
-            out = torch.empty(self.N, dtype=torch.float64, device=self.workspace.device)
+            out = torch.empty(self.N, dtype=torch.float64,
+                              device=torch.device(self.device or "cuda"))
         _check(_lib.lks_read_field(self.ctx, FIELDS[name], _vp(out.data_ptr())), self.ctx)
         return out
 

@@ -285,3 +285,16 @@ def test_checkpoint_plan_follows_the_budget():
     with pytest.raises(lks.LKSError) as e:
         _create(wl, "fp32", base // 2)
     assert e.value.status == lks.LKS_E_NOMEM
+
+
+def test_static_workspace_rejects_a_context_beyond_its_size():
+    """lks_bind_static_workspace refuses, before touching the device, a
+    context whose workspace exceeds the static array."""
+    wl = W.steady_channel_grf(2048, 2048, Re=100.0, sigma=8.0, seed=0, n_fwd=1, n_adj=1)
+    c = _create(wl, "fp32")
+    assert c.workspace_size() > lks.STATIC_WORKSPACE_BYTES
+    with pytest.raises(lks.LKSError) as e:
+        c.bind_static()
+    assert e.value.status == lks.LKS_E_NOMEM
+    assert b"exceeds the static array" in lks.lib().lks_last_error(c.ctx)
+
