@@ -56,8 +56,13 @@ typedef enum {
 enum { LKS_D2Q9 = 0, LKS_D3Q19 = 1 };
 /* FP64: state and arithmetic in double.
  * FP32DEV: state in float with the density stored as rho - 1; objective and
- * sensitivity accumulated in double. */
-enum { LKS_FP64 = 0, LKS_FP32DEV = 1 };
+ * sensitivity accumulated in double.
+ * MIXED (steady D2Q9 problems): the forward sweep and the objective in
+ * double, the adjoint sweep in float (FP32DEV) from the final forward state
+ * rounded to float once; the sensitivity accumulated in double. The forward
+ * fields and J are those of FP64; the gradient carries the FP32 adjoint's
+ * error. */
+enum { LKS_FP64 = 0, LKS_FP32DEV = 1, LKS_MIXED = 2 };
 /* objectives: static pressure drop (eq:objective_pipebend); time-averaged
  * enthalpy flux u_x T through the probe nodes; heat-exchange amount
  * J = -sum beta_gamma (1 - T) over all nodes (eq:objective_heatexchanger;
@@ -121,7 +126,7 @@ enum {
 typedef struct {
   int nx, ny, nz;  /* nodes per axis; nz = 1 for D2Q9 */
   int lattice;     /* LKS_D2Q9 or LKS_D3Q19 */
-  int precision;   /* LKS_FP64 or LKS_FP32DEV */
+  int precision;   /* LKS_FP64, LKS_FP32DEV or LKS_MIXED */
   int periodic;    /* D2Q9: 1 = periodic box, every node interior.
                       D3Q19: mask of periodic axes (bit 0 x, 1 y, 2 z) */
 } lks_grid;

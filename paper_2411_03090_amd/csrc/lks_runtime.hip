@@ -89,6 +89,9 @@ struct lks_ctx {
   size_t ws_bytes = 0;
   bool bound = false;
   int static_dev = -1;    // device whose static scratch array is bound, or -1
+  // mixed precision: the FP32 context that runs the adjoint sweep (this
+  // context runs the forward sweep in FP64)
+  lks_ctx* lo = nullptr;
   // carved device pointers (element type depends on precision)
   uint8_t* d_mask = nullptr;
   void *ubx = nullptr, *uby = nullptr, *ubz = nullptr, *Tb = nullptr;
@@ -1065,6 +1068,27 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
   if (!out) return fail(nullptr, LKS_E_INVALID, "null output pointer");
   *out = nullptr;
   if (!grid || !phys || !bc) return fail(nullptr, LKS_E_INVALID, "null descriptor");
+  if (grid->precision == LKS_MIXED) {
+    // an FP64 context for the forward sweep with an FP32 context for the
+    // adjoint sweep of the same problem
+    if (grid->lattice != LKS_D2Q9 || bc->mode != LKS_STEADY)
+      return fail(nullptr, LKS_E_UNSUPPORTED, "mixed precision applies to steady D2Q9 problems");
+    lks_grid g64 = *grid, g32 = *grid;
+    g64.precision = LKS_FP64;
+    g32.precision = LKS_FP32DEV;
+    lks_ctx* hi = nullptr;
+    lks_ctx* lo = nullptr;
+    lks_status st = lks_create(&g64, phys, bc, mem_budget_bytes, hip_stream, &hi);
+    if (st != LKS_OK) return st;
+    st = lks_create(&g32, phys, bc, mem_budget_bytes, hip_stream, &lo);
+    if (st != LKS_OK) {
+      lks_destroy(hi);
+      return st;
+    }
+    hi->lo = lo;
+    *out = hi;
+    return LKS_OK;
+  }
   const bool d3 = grid->lattice == LKS_D3Q19;
   lks_status st = d3 ? validate3(grid, phys, bc) : validate(grid, phys, bc);
   if (st != LKS_OK) return st;
@@ -1156,11 +1180,16 @@ std::mutex g_scratch_mu;
 std::map<int, StaticScratch> g_scratch;  // by device ordinal
 }  // namespace
 
+// workspace of a context, including the FP32 adjoint context of a mixed one
+static size_t ws_total(const lks_ctx* c) {
+  return c->lo ? align256(c->plan.total) + c->lo->plan.total : c->plan.total;
+}
+
 extern "C" {
 
 lks_status lks_workspace_size(const lks_ctx* c, size_t* bytes) {
   if (!c || !bytes) return LKS_E_INVALID;
-  *bytes = c->plan.total;
+  *bytes = ws_total(c);
   return LKS_OK;
 }
 
@@ -1169,7 +1198,14 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
   if (!dev_ptr) return fail(c, LKS_E_INVALID, "null workspace");
   if (reinterpret_cast<uintptr_t>(dev_ptr) & 255)
     return fail(c, LKS_E_INVALID, "workspace must be 256-byte aligned");
-  if (bytes < c->plan.total) return fail(c, LKS_E_NOMEM, "workspace smaller than lks_workspace_size");
+  if (bytes < ws_total(c)) return fail(c, LKS_E_NOMEM, "workspace smaller than lks_workspace_size");
+  if (c->lo) {
+    // mixed precision: the FP32 adjoint context takes the tail
+    const size_t hi = align256(c->plan.total);
+    lks_status st = lks_bind_workspace(c->lo, static_cast<char*>(dev_ptr) + hi, bytes - hi);
+    if (st != LKS_OK) return fail(c, st, std::string("adjoint part: ") + c->lo->err);
+    bytes = c->plan.total;
+  }
   const size_t N = size_t(c->N), r = size_t(c->rsz);
   const int nf = nfields(c), nu = c->dim;
   char* p = static_cast<char*>(dev_ptr);
@@ -1281,10 +1317,10 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
 
 lks_status lks_bind_static_workspace(lks_ctx* c) {
   if (!c) return LKS_E_INVALID;
-  if (c->plan.total > size_t(LKS_STATIC_WORKSPACE_BYTES)) {
+  if (ws_total(c) > size_t(LKS_STATIC_WORKSPACE_BYTES)) {
     char buf[160];
     snprintf(buf, sizeof buf, "workspace of %zu B exceeds the static array of %zu B",
-             c->plan.total, size_t(LKS_STATIC_WORKSPACE_BYTES));
+             ws_total(c), size_t(LKS_STATIC_WORKSPACE_BYTES));
     return fail(c, LKS_E_NOMEM, buf);
   }
   lks_status st = LKS_OK;
@@ -1344,6 +1380,13 @@ static lks_status forward_impl(lks_ctx* c, const double* gamma, int steps, bool 
   if (st == LKS_OK) {
     c->have_forward = true;
     c->have_adjoint = false;
+    if (c->lo) {
+      // mixed: the FP32 adjoint part takes the design coefficients now
+      if (!c->lo->bound) return fail(c, LKS_E_STATE, "adjoint part not bound");
+      Run<float>(c->lo).coefficients(gamma);
+      c->lo->have_adjoint = false;
+      st = check_launch(c);
+    }
   }
   return st;
 }
@@ -1386,6 +1429,24 @@ lks_status lks_objective(lks_ctx* c, double* J) {
 static lks_status backward_impl(lks_ctx* c, double seed, int steps, double* dJ, bool reset) {
   if (!c) return LKS_E_INVALID;
   if (!c->have_forward) return fail(c, LKS_E_STATE, "alks_backward before lks_forward");
+  if (c->lo) {
+    // mixed precision: the FP32 context takes the design coefficients and the
+    // final FP64 forward state rounded to float, then runs the adjoint
+    lks_ctx* lo = c->lo;
+    if (reset) {
+      if (!lo->bound) return fail(c, LKS_E_STATE, "adjoint part not bound");
+      const int nf = nfields(c);
+      for (int f = 0; f < nf; ++f)
+        lks::launch_from_double<float>(static_cast<const double*>(c->S[c->cur][f]),
+                                       static_cast<float*>(lo->S[lo->cur][f]), c->N, c->stream);
+      lo->have_forward = true;
+      lo->have_adjoint = false;
+    }
+    lks_status st = backward_impl(lo, seed, steps, dJ, reset);
+    if (st != LKS_OK) return fail(c, st, lo->err);
+    c->have_adjoint = true;
+    return LKS_OK;
+  }
   if (!std::isfinite(seed)) return fail(c, LKS_E_INVALID, "seed not finite");
   if (c->mode == LKS_UNSTEADY) {
     if (!reset) return fail(c, LKS_E_UNSUPPORTED, "alks_advance applies to steady problems");
@@ -1422,6 +1483,10 @@ lks_status lks_gradient_status(lks_ctx* c) {
       !hip_ok(c, hipStreamSynchronize(c->stream), "gradient status sync", &st))
     return st;
   if (flag[0]) return fail(c, LKS_E_DIVERGED, "non-finite velocity in the forward state");
+  if (c->lo) {
+    st = lks_gradient_status(c->lo);
+    return st == LKS_OK ? st : fail(c, st, c->lo->err);
+  }
   if (flag[1]) return fail(c, LKS_E_DIVERGED, "non-finite sensitivity in the adjoint sweep");
   return LKS_OK;
 }
@@ -1434,8 +1499,18 @@ lks_status alks_advance(lks_ctx* c, double J_seed, int steps, double* dJdgamma_d
   return backward_impl(c, J_seed, steps, dJdgamma_dev, false);
 }
 
+// fields of the adjoint state (LKS_FIELD_ADJ_*)
+static bool adjoint_field(int which) {
+  return which == LKS_FIELD_ADJ_RHO || which == LKS_FIELD_ADJ_VX || which == LKS_FIELD_ADJ_VY ||
+         which == LKS_FIELD_ADJ_THETA || which == LKS_FIELD_ADJ_VZ;
+}
+
 lks_status lks_read_field(lks_ctx* c, int which, double* dev_out) {
   if (!c || !dev_out) return LKS_E_INVALID;
+  if (c->lo && adjoint_field(which)) {
+    lks_status st = lks_read_field(c->lo, which, dev_out);
+    return st == LKS_OK ? st : fail(c, st, c->lo->err);
+  }
   if (!c->bound) return fail(c, LKS_E_STATE, unbound_reason(c));
   lks_status st = c->rsz == 8 ? Run<double>(c).read(which, dev_out)
                               : Run<float>(c).read(which, dev_out);
@@ -1445,6 +1520,12 @@ lks_status lks_read_field(lks_ctx* c, int which, double* dev_out) {
 
 lks_status lks_write_field(lks_ctx* c, int which, const double* dev_in) {
   if (!c || !dev_in) return LKS_E_INVALID;
+  if (c->lo && adjoint_field(which)) {
+    lks_status st = lks_write_field(c->lo, which, dev_in);
+    if (st != LKS_OK) return fail(c, st, c->lo->err);
+    c->have_adjoint = true;
+    return LKS_OK;
+  }
   if (!c->bound) return fail(c, LKS_E_STATE, unbound_reason(c));
   lks_status st = c->rsz == 8 ? Run<double>(c).write(which, dev_in)
                               : Run<float>(c).write(which, dev_in);
@@ -1456,6 +1537,10 @@ lks_status lks_write_field(lks_ctx* c, int which, const double* dev_in) {
 
 lks_status lks_set_tile_rows(lks_ctx* c, int tile_rows) {
   if (!c) return LKS_E_INVALID;
+  if (c->lo) {
+    lks_status st = lks_set_tile_rows(c->lo, tile_rows);
+    if (st != LKS_OK) return fail(c, st, c->lo->err);
+  }
   if (c->dim == 3) return fail(c, LKS_E_UNSUPPORTED, "D3Q19 kernels are not tiled");
   for (int ty : TILE_ROWS)
     if (ty == tile_rows && tile_rows_ok(ty, c->rsz, c->phys.thermal)) {
@@ -1469,6 +1554,16 @@ lks_status lks_set_tile_rows(lks_ctx* c, int tile_rows) {
 
 lks_status lks_set_steps_per_launch(lks_ctx* c, int forward_steps, int adjoint_steps) {
   if (!c) return LKS_E_INVALID;
+  if (c->lo) {
+    // mixed: the forward runs in FP64 (one step per launch), the adjoint in FP32
+    if (forward_steps != 1)
+      return fail(c, LKS_E_UNSUPPORTED, "the FP64 forward of a mixed context runs one step per launch");
+    lks_status st = lks_set_steps_per_launch(c->lo, 1, adjoint_steps);
+    if (st != LKS_OK) return fail(c, st, c->lo->err);
+    c->spl_f = 1;
+    c->spl_a = 1;
+    return LKS_OK;
+  }
   for (int s : {forward_steps, adjoint_steps}) {
     if (s != 1 && s != 2) return fail(c, LKS_E_INVALID, "steps per launch must be 1 or 2");
     if (s == 2 && (c->dim != 2 || c->rsz != 4))
@@ -1485,6 +1580,7 @@ lks_status lks_set_adjoint_mode(lks_ctx* c, int mode) {
     return fail(c, LKS_E_INVALID, "adjoint mode must be LKS_ADJ_PAPER or LKS_ADJ_EXACT");
   if (mode != c->adj_exact) c->have_adjoint = false;
   c->adj_exact = mode;
+  if (c->lo) return lks_set_adjoint_mode(c->lo, mode);
   return LKS_OK;
 }
 
@@ -1526,12 +1622,23 @@ lks_status lks_launch_shape(const lks_ctx* c, int* tile_rows, int* forward_steps
   if (!c) return LKS_E_INVALID;
   if (tile_rows) *tile_rows = c->dim == 2 ? c->geo.ty : 0;
   if (forward_steps) *forward_steps = c->spl_f;
-  if (adjoint_steps) *adjoint_steps = c->spl_a;
+  if (adjoint_steps) *adjoint_steps = c->lo ? c->lo->spl_a : c->spl_a;
   return LKS_OK;
 }
 
 lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* tile_rows) {
   if (!c || !gamma_dev || steps < 1) return LKS_E_INVALID;
+  if (c->lo) {
+    // mixed: each part keeps the launch shape that is fastest for its own
+    // precision (the FP32 part's forward sweep only serves the timing)
+    lks_status st = lks_autotune(c->lo, gamma_dev, steps, nullptr);
+    if (st != LKS_OK) return fail(c, st, c->lo->err);
+    lks_ctx* lo = c->lo;
+    c->lo = nullptr;
+    st = lks_autotune(c, gamma_dev, steps, tile_rows);
+    c->lo = lo;
+    return st;
+  }
   if (c->dim == 3) return fail(c, LKS_E_UNSUPPORTED, "D3Q19 kernels are not tiled");
   if (!c->bound) return fail(c, LKS_E_STATE, unbound_reason(c));
   lks_status st = LKS_OK;
@@ -1600,7 +1707,7 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
 lks_status lks_memory_report(const lks_ctx* c, size_t* ckpt_bytes, size_t* state_bytes, int* K) {
   if (!c) return LKS_E_INVALID;
   if (ckpt_bytes) *ckpt_bytes = c->plan.ckpt_bytes;
-  if (state_bytes) *state_bytes = c->plan.total - c->plan.ckpt_bytes;
+  if (state_bytes) *state_bytes = ws_total(c) - c->plan.ckpt_bytes;
   if (K) *K = c->mode == LKS_UNSTEADY ? std::min(c->plan.K, c->n_steps) : 0;
   return LKS_OK;
 }
@@ -1623,6 +1730,7 @@ const char* lks_last_error(const lks_ctx* c) {
 }
 
 void lks_destroy(lks_ctx* c) {
+  if (c && c->lo) lks_destroy(c->lo);
   if (c && c->static_dev >= 0) {
     std::lock_guard<std::mutex> lock(g_scratch_mu);
     auto it = g_scratch.find(c->static_dev);
@@ -1789,7 +1897,7 @@ lks_status lks_batch_create(int n, const lks_grid* grids, const lks_phys* phys, 
   size_t off = 0;
   for (int d = 0; d < n; ++d) {
     if (bcs[d].mode != LKS_STEADY || bcs[d].objective != LKS_OBJ_PRESSURE_DROP ||
-        grids[d].lattice != LKS_D2Q9) {
+        grids[d].lattice != LKS_D2Q9 || grids[d].precision == LKS_MIXED) {
       for (auto* p : b->ctx) lks_destroy(p);
       delete b;
       return bfail(nullptr, LKS_E_UNSUPPORTED,

@@ -40,7 +40,8 @@ LKS_E_STATE = 4
 LKS_E_DIVERGED = 5
 LKS_E_UNSUPPORTED = 6
 LKS_D2Q9, LKS_D3Q19 = 0, 1
-LKS_FP64, LKS_FP32DEV = 0, 1
+LKS_FP64, LKS_FP32DEV, LKS_MIXED = 0, 1, 2
+_PRECISION = {"fp64": LKS_FP64, "fp32": LKS_FP32DEV, "mixed": LKS_MIXED}
 LKS_OBJ_PRESSURE_DROP, LKS_OBJ_HEAT, LKS_OBJ_HEAT_EXCHANGE, LKS_OBJ_HEAT_SINK = 0, 1, 2, 3
 LKS_STEADY, LKS_UNSTEADY = 0, 1
 LKS_ADJ_PAPER, LKS_ADJ_EXACT = 0, 1
@@ -188,7 +189,8 @@ class LKS:
     """One forward/adjoint problem bound to a device workspace.
 
     ``wl`` is a workloads.Workload (D2Q9) or workloads.Workload3 (D3Q19).
-    ``precision`` is "fp64" or "fp32". ``mem_budget`` bounds the unsteady
+    ``precision`` is "fp64", "fp32" or "mixed" (steady D2Q9: FP64 forward,
+    FP32 adjoint). ``mem_budget`` bounds the unsteady
     trajectory storage (bytes, 0 = none). ``checkpointing`` is None (automatic)
     or (scheme, slots) with scheme "auto", "two_level" or "binomial"; see
     lks_set_checkpointing.
@@ -204,7 +206,9 @@ class LKS:
         self._ubar = np.ascontiguousarray(wl.ubar, dtype=np.float64).reshape(-1)
         self._Tbar = np.ascontiguousarray(wl.Tbar, dtype=np.float64).reshape(-1)
         self._ufac = np.ascontiguousarray(wl.ufac, dtype=np.float64).reshape(-1)
-        prec = LKS_FP64 if precision == "fp64" else LKS_FP32DEV
+        if precision not in _PRECISION:
+            raise ValueError(f"precision must be one of {sorted(_PRECISION)}")
+        prec = _PRECISION[precision]
         if self.d3:
             self.grid = Grid(wl.nx, wl.ny, nz, LKS_D3Q19, prec, int(wl.periodic_axes))
         else:
