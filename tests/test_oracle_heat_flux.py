@@ -93,11 +93,12 @@ def test_d3q19_flux_face_matches_the_z_invariant_d2q9_step():
 
 
 def test_heat_sink_gradient_vs_fd_is_recorded():
-    """Unsteady heat sink (18 x 18, 150 steps, uniform conductivity, Ra = 2e4):
-    the ALKS gradient of the mean heated temperature correlates with central
-    differences (0.92 measured) but differs in magnitude (relative L2 0.46):
-    the boundary seed enters through the paper's least-squares completion,
-    whose gap to the exact derivative is unpinned."""
+    """Unsteady heat sink (18 x 18, 150 steps, uniform conductivity, Ra = 2e4),
+    every design node within a few cells of the heated boundary: the ALKS
+    gradient of the mean heated temperature correlates with central
+    differences (0.96 measured) but not in magnitude (relative L2 0.9): next
+    to the heated boundary the paper's boundary treatment is approximate
+    (parity unpinned there; the check of Sec. 2.6 below pins the interior)."""
     n = 18
     wl = W.heat_sink(n=n, n_steps=150, Ra=2e4, Ks_over_Kf=1.0, sigma=3.0, seed=1)
     J, sens, _, _ = O.gradient(wl)
@@ -112,4 +113,38 @@ def test_heat_sink_gradient_vs_fd_is_recorded():
         fd.append((v[0] - v[1]) / 2e-4)
     fd = np.array(fd)
     adj = sens.ravel()[ks]
-    assert np.corrcoef(adj, fd)[0, 1] > 0.8
+    assert np.corrcoef(adj, fd)[0, 1] > 0.9
+
+
+@pytest.mark.parametrize("Ks,band", [(1.0, 0.15), (10.0, 0.6)])
+def test_gradient_matches_fd_on_the_papers_natural_convection_check(Ks, band):
+    """The natural-convection check of Sec. 2.6 (140 x 80 cells, walls at
+    T = 0 on three sides, a heated 4-cell patch on the adiabatic bottom, the
+    80 x 50 design domain at gamma = 0.9 with its 40 x 25 core at 0.1), with
+    the heat-sink objective and physics of Sec. 3.4 (Ra = 2e5, Pr = 6) over
+    10000 steps. Along the design domain's centre line the ALKS gradient
+    follows central differences (eq:sensfdm, eps = 1e-3), as the paper
+    reports (fair agreement, errors at the gamma interface). Measured,
+    uniform conductivity: correlation 0.97, median ratio 1.02, relative L2
+    0.10 over 13 nodes; K_s = 10 K_f: correlation 0.97, ratios 0.7-1.1 off the
+    core and 0.2 inside it (the conductivity term in the solid, an error of
+    the continuous adjoint the paper notes at the interface). This fixes the
+    boundary seed of the heat-sink objective (through the heated node's flux
+    closure); the literal uniform row seed gives correlation 0.5 and median
+    ratio 0.05 here."""
+    wl = W.sensitivity_check_natural_convection(Ks_over_Kf=Ks, n_steps=10000)
+    J, sens, _, _ = O.gradient(wl, checkpoint=101)
+    jc, eps = 40, 1e-3
+    pts = [38, 50, 92, 104] if Ks > 1 else [38, 62, 80, 98]
+    fd = []
+    for i in pts:
+        v = []
+        for e in (eps, -eps):
+            g = wl.gamma.copy()
+            g[jc, i] += e
+            v.append(O.objective(wl, g))
+        fd.append((v[0] - v[1]) / (2 * eps))
+    fd = np.array(fd)
+    adj = sens[jc, pts]
+    assert np.all(np.sign(adj) == np.sign(fd))
+    assert np.all(np.abs(adj / fd - 1.0) < band)
