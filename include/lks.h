@@ -67,7 +67,9 @@ enum { LKS_FP64 = 0, LKS_FP32DEV = 1, LKS_MIXED = 2 };
  * enthalpy flux u_x T through the probe nodes; heat-exchange amount
  * J = -sum beta_gamma (1 - T) over all nodes (eq:objective_heatexchanger;
  * needs the heat source, beta_max > 0); heat-sink objective: the mean
- * temperature over the heated boundary (eq:objective_heatsink; D2Q9) */
+ * temperature over the heated boundary (eq:objective_heatsink; D2Q9), whose
+ * adjoint seed follows the heated node's flux closure: seed w / (1 + u.n)
+ * per arriving population, w = 1 along the wall and 2 moving outwards */
 enum { LKS_OBJ_PRESSURE_DROP = 0, LKS_OBJ_HEAT = 1, LKS_OBJ_HEAT_EXCHANGE = 2,
        LKS_OBJ_HEAT_SINK = 3 };
 enum { LKS_STEADY = 0, LKS_UNSTEADY = 1 };
@@ -245,9 +247,11 @@ lks_status alks_backward(lks_ctx *ctx, double J_seed, int adj_steps, double *dJd
 
 /* Synchronises the stream and reports LKS_E_DIVERGED when the last forward
  * state or the sensitivity of the last adjoint sweep holds a non-finite value
- * (the paper's thermal adjoint can grow without bound for a large
- * conductivity contrast, Sec. 2.5 eq:ageq; the exact adjoint mode does not),
- * LKS_E_STATE before an adjoint sweep, LKS_OK otherwise. */
+ * (with a large conductivity contrast next to a prescribed-temperature wall
+ * the paper's least-squares completion of eq:agboundaryT feeds a growing
+ * thermal adjoint mode; the exact adjoint mode, which zeroes the thermal
+ * adjoint there, stays bounded), LKS_E_STATE before an adjoint sweep, LKS_OK
+ * otherwise. */
 lks_status lks_gradient_status(lks_ctx *ctx);
 
 /* Continue the steady adjoint by `steps` ALKS steps from its current state
@@ -297,7 +301,9 @@ lks_status lks_set_steps_per_launch(lks_ctx *ctx, int forward_steps, int adjoint
  * alpha' u.V / (1 + alpha) with the undivided V, and an unsteady sweep sums
  * the sensitivity over levels 1..N only (level 0 is the initial state). On
  * periodic grids with uniform B this gives the exact discrete gradient; ring
- * and face nodes keep the paper's least-squares completion. Changing the
+ * and face nodes keep the paper's least-squares completion, except that the
+ * thermal adjoint of a prescribed-temperature node is zero (its temperature
+ * does not depend on the populations that arrive there). Changing the
  * mode discards the adjoint state. Batches always use LKS_ADJ_PAPER.
  * Errors: LKS_E_INVALID for another value. */
 lks_status lks_set_adjoint_mode(lks_ctx *ctx, int mode);
