@@ -304,7 +304,7 @@ lks_status lks_set_steps_per_launch(lks_ctx *ctx, int forward_steps, int adjoint
  * and face nodes keep the paper's least-squares completion, except that the
  * thermal adjoint of a prescribed-temperature node is zero (its temperature
  * does not depend on the populations that arrive there). Changing the
- * mode discards the adjoint state. Batches always use LKS_ADJ_PAPER.
+ * mode discards the adjoint state. Batches take lks_batch_set_adjoint_mode.
  * Errors: LKS_E_INVALID for another value. */
 lks_status lks_set_adjoint_mode(lks_ctx *ctx, int mode);
 
@@ -348,35 +348,64 @@ lks_status lks_checkpoint_info(const lks_ctx *ctx, int *scheme, int *count,
                                long long *replay_steps);
 
 /* ---- batches (Sec. 2.7 Steps 2-5 for many independent designs) ----------
- * A batch holds n steady pressure-drop problems of possibly different sizes
- * and parameters (same precision, all thermal or all non-thermal). One call runs
- * n_fwd LKS steps, the pressure-drop objective, n_adj ALKS steps and the
- * sensitivity of every design; each step of all designs is one kernel
- * launch, and the whole sequence is captured once as a HIP graph and
- * replayed (use_graph = 1) or launched eagerly (use_graph = 0). */
+ * A batch holds n D2Q9 problems of possibly different sizes and parameters
+ * (same precision and mode, all thermal or all non-thermal, no heat source):
+ *   steady batches: the pressure-drop objective; one call runs n_fwd LKS
+ *     steps, the objective, n_adj ALKS steps and the sensitivity of every
+ *     design;
+ *   unsteady batches: the pressure-drop or enthalpy-flux objective averaged
+ *     over levels 1..N, with one horizon N (lks_bc.n_steps) for all designs;
+ *     one call runs the N LKS steps, the objectives and the whole checkpointed
+ *     adjoint sweep (two-level checkpointing with one interval K for every
+ *     design, chosen by lks_batch_set_memory_budget), the sensitivity summed
+ *     over levels as alks_backward does for one design.
+ * Each step of all designs is one kernel launch, and the whole sequence is
+ * captured once as a HIP graph and replayed (use_graph = 1) or launched
+ * eagerly (use_graph = 0). Each design's results are bitwise those of its own
+ * context at the same tile height. */
 typedef struct lks_batch lks_batch;
 
-/* Validates every design as lks_create does (steady D2Q9 only). Makes no HIP
- * call. grids/phys/bcs are arrays of n descriptors. */
+/* Validates every design as lks_create does. Makes no HIP call. grids/phys/bcs
+ * are arrays of n descriptors. An unsteady batch starts with every level kept
+ * (no budget). Errors: LKS_E_UNSUPPORTED for other lattices, objectives,
+ * MIXED precision or a heat source; LKS_E_INVALID when the designs differ in
+ * precision, physics kind, mode or horizon. */
 lks_status lks_batch_create(int n, const lks_grid *grids, const lks_phys *phys,
                             const lks_bc *bcs, void *hip_stream, lks_batch **out);
+/* Device memory budget of the whole batch (workspace bytes; 0 = no limit),
+ * before binding. Unsteady batches take the checkpoint interval that replays
+ * the fewest forward steps within it (as lks_create plans one design).
+ * Errors: LKS_E_STATE after binding, LKS_E_NOMEM when no plan fits (the
+ * previous plan is kept). Makes no HIP call. */
+lks_status lks_batch_set_memory_budget(lks_batch *b, size_t bytes);
+/* Adjoint mode of every design (as lks_set_adjoint_mode); default paper. */
+lks_status lks_batch_set_adjoint_mode(lks_batch *b, int mode);
+/* The plan: checkpoint interval K and LKS steps one sweep replays (0 and 0
+ * for steady batches), and the workspace bytes. Any pointer may be NULL. */
+lks_status lks_batch_checkpoint_info(const lks_batch *b, int *K, long long *replay_steps,
+                                     size_t *workspace_bytes);
 lks_status lks_batch_workspace_size(const lks_batch *b, size_t *bytes);
 /* Bind caller-owned device memory (256-byte aligned); creates the batch's
  * internal capture stream and events. */
 lks_status lks_batch_bind_workspace(lks_batch *b, void *dev_ptr, size_t bytes);
 /* gamma_dev[d], dJdgamma_dev[d]: device pointers of design d (nx*ny doubles);
- * J_host: n doubles. Synchronises the stream. Linear in J_seed. */
+ * J_host: n doubles. Synchronises the stream. Linear in J_seed. Unsteady
+ * batches need n_fwd == n_steps and ignore n_adj. */
 lks_status lks_batch_run(lks_batch *b, const double *const *gamma_dev, int n_fwd, int n_adj,
                          double J_seed, double *const *dJdgamma_dev, double *J_host,
                          int use_graph);
-/* Tile autotuner of a batch: runs the batch eagerly for `steps` forward and
- * adjoint steps per tile height and keeps the fastest. scratch_dev[d]
- * receives a throw-away sensitivity. Synchronises. */
+/* Tile autotuner of a steady batch: runs the batch eagerly for `steps`
+ * forward and adjoint steps per tile height and keeps the fastest.
+ * scratch_dev[d] receives a throw-away sensitivity. Synchronises. Unsteady
+ * batches: LKS_E_UNSUPPORTED. */
 lks_status lks_batch_autotune(lks_batch *b, const double *const *gamma_dev, int steps,
                               double *const *scratch_dev, int *tile_rows);
-/* Tile height of a batch's step launches (as lks_set_tile_rows). */
+/* Tile height of a batch's step launches (as lks_set_tile_rows; 4 or 8 for
+ * unsteady batches). */
 lks_status lks_batch_set_tile_rows(lks_batch *b, int tile_rows);
-/* Field `which` of design d at its final forward / adjoint level. */
+/* Field `which` of design d at its final forward / adjoint level (unsteady
+ * batches: adjoint fields only, those of level 0; LKS_E_UNSUPPORTED for
+ * forward fields, whose last levels the replays overwrite). */
 lks_status lks_batch_read_field(lks_batch *b, int design, int which, double *dev_out);
 const char *lks_batch_last_error(const lks_batch *b);
 void lks_batch_destroy(lks_batch *b);

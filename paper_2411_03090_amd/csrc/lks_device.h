@@ -177,6 +177,37 @@ struct BatchAdj {
   AdjArgs<R> a[2];
 };
 
+// Unsteady batches (checkpointed sweeps of many designs). The designs share
+// the horizon N and the checkpoint interval K, so the place of a level is
+// the same for all of them: checkpoint n / K when K divides n, else a replay
+// slot (the density in the ping-pong buffer of the level's parity) when the
+// level lies above the base of the segment being replayed, else the
+// ping-pong buffers of its parity.
+enum { LVL_CKPT = 0, LVL_SLOT = 1, LVL_PING = 2 };
+struct LevelRef {
+  int kind, idx, par;
+};
+// where the levels of one design of an unsteady batch are stored
+template <typename R>
+struct BatchStore {
+  R* C;        // checkpoints: ckf fields of N values each
+  R* Seg;      // replay slots: slf fields of N values each (no density)
+  R* S[2][4];  // ping-pong buffers: drho, ux, uy, T
+  int N, ckf, slf;
+  int n_ufac;  // entries of the design's inflow-factor table
+};
+// field f (drho, ux, uy, T) of the level at r; null for T when the fields
+// stored per level stop before it (non-thermal designs)
+template <typename R>
+__host__ __device__ inline R* level_field(const BatchStore<R>& s, LevelRef r, int f) {
+  if (r.kind == LVL_CKPT) return f < s.ckf ? s.C + (size_t(r.idx) * s.ckf + f) * size_t(s.N) : nullptr;
+  if (r.kind == LVL_SLOT) {
+    if (f == 0) return s.S[r.par][0];
+    return f < s.ckf ? s.Seg + (size_t(r.idx) * s.slf + (f - 1)) * size_t(s.N) : nullptr;
+  }
+  return f < s.ckf ? s.S[r.par][f] : nullptr;
+}
+
 // host: the four ring operators for a given A and fluid B
 void build_ring_ops(double A, double Bf, RingOp ops[4]);
 
@@ -338,6 +369,24 @@ void launch_alks_step_batch(const BatchAdj<R>* d, const int* tmap, int total, in
 template <typename R>
 void launch_pressure_drop_batch(const BatchFwd<R>* d, int nd, int parity, double* out,
                                 hipStream_t s);
+// unsteady batches: one LKS step of every design from level `in` to level
+// `out` (= level_out), the objective accumulated per tile when use_acc;
+// one ALKS step of every design at the state of level `lv` with the
+// descriptors' seeds applied when `seeded` (levels 1..N) and the
+// sensitivity accumulated; the per-tile accumulators zeroed and summed per
+// design (out[d], the order of launch_sum)
+template <typename R>
+void launch_lks_step_ubatch(const BatchFwd<R>* d, const BatchStore<R>* st, const int* tmap,
+                            int total, int ty, bool thermal, LevelRef in, LevelRef out,
+                            int level_out, int use_acc, hipStream_t s);
+template <typename R>
+void launch_alks_step_ubatch(const BatchAdj<R>* d, const BatchStore<R>* st, const int* tmap,
+                             int total, int ty, bool thermal, int parity, LevelRef lv,
+                             int seeded, int b_only, hipStream_t s);
+template <typename R>
+void launch_acc_zero_batch(const BatchFwd<R>* d, int nd, hipStream_t s);
+template <typename R>
+void launch_acc_sum_batch(const BatchFwd<R>* d, int nd, double* out, hipStream_t s);
 void launch_sum(const double* v, int n, double* out, hipStream_t s);
 // zero one device flag with a kernel (safe inside a captured graph;
 // lks_runtime.hip)

@@ -1500,17 +1500,11 @@ __global__ __launch_bounds__(NT2<TH>) void alks_step2_kernel(Geo g, AdjArgs<R> a
 // for every global tile, its design and its tile index within the design.
 // All designs advance in lockstep, so one parity selects the ping-pong
 // buffers of every design.
+// the tile lt of design g in the rule its kind takes (as the one-design
+// step launch does, so a design gives the same bits alone and in a batch)
 template <typename R, bool TH, int TY>
-__global__ __launch_bounds__((NT1<R, TH, TY>)) void lks_step_batch_kernel(const BatchFwd<R>* __restrict__ d,
-                                                                  const int* __restrict__ tmap,
-                                                                  int total, int parity) {
-  __shared__ FwdLds<R, TH, TY> L;
-  const int t = xcd_tile(total);
-  if (t < 0) return;
-  const int di = tmap[2 * t];
-  const Geo g = d[di].g;
-  const FwdArgs<R> a = d[di].a[parity];
-  const int lt = tmap[2 * t + 1];
+__device__ inline void batch_fwd_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L,
+                                      int lt) {
   int x0, x1, y0, y1;
   tile_box(g, lt, &x0, &x1, &y0, &y1);
   const int tw = x1 - x0, th = y1 - y0;
@@ -1527,18 +1521,8 @@ __global__ __launch_bounds__((NT1<R, TH, TY>)) void lks_step_batch_kernel(const 
 }
 
 template <typename R, bool TH, int TY>
-__global__ __launch_bounds__((NT1<R, TH, TY>)) void alks_step_batch_kernel(const BatchAdj<R>* __restrict__ d,
-                                                                   const int* __restrict__ tmap,
-                                                                   int total, int parity,
-                                                                   int last) {
-  __shared__ AdjLds<R, TH, TY> L;
-  const int t = xcd_tile(total);
-  if (t < 0) return;
-  const int di = tmap[2 * t];
-  const Geo g = d[di].g;
-  AdjArgs<R> a = d[di].a[parity];
-  a.sens_mode = last ? 2 : 0;
-  const int lt = tmap[2 * t + 1];
+__device__ inline void batch_adj_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& L,
+                                      int lt) {
   int x0, x1, y0, y1;
   tile_box(g, lt, &x0, &x1, &y0, &y1);
   const int tw = x1 - x0, th = y1 - y0;
@@ -1552,6 +1536,106 @@ __global__ __launch_bounds__((NT1<R, TH, TY>)) void alks_step_batch_kernel(const
   } else {
     alks_tile<R, TH, TY, true, K_EDGE>(g, a, L, x0, y0, tw, th);
   }
+}
+
+template <typename R, bool TH, int TY>
+__global__ __launch_bounds__((NT1<R, TH, TY>)) void lks_step_batch_kernel(const BatchFwd<R>* __restrict__ d,
+                                                                  const int* __restrict__ tmap,
+                                                                  int total, int parity) {
+  __shared__ FwdLds<R, TH, TY> L;
+  const int t = xcd_tile(total);
+  if (t < 0) return;
+  const int di = tmap[2 * t];
+  const Geo g = d[di].g;
+  const FwdArgs<R> a = d[di].a[parity];
+  batch_fwd_tile<R, TH, TY>(g, a, L, tmap[2 * t + 1]);
+}
+
+template <typename R, bool TH, int TY>
+__global__ __launch_bounds__((NT1<R, TH, TY>)) void alks_step_batch_kernel(const BatchAdj<R>* __restrict__ d,
+                                                                   const int* __restrict__ tmap,
+                                                                   int total, int parity,
+                                                                   int last) {
+  __shared__ AdjLds<R, TH, TY> L;
+  const int t = xcd_tile(total);
+  if (t < 0) return;
+  const int di = tmap[2 * t];
+  const Geo g = d[di].g;
+  AdjArgs<R> a = d[di].a[parity];
+  a.sens_mode = last ? 2 : 0;
+  batch_adj_tile<R, TH, TY>(g, a, L, tmap[2 * t + 1]);
+}
+
+// unsteady batches: the level pointers of every design resolved from its
+// store (the descriptors' parity-0 arguments give everything else)
+template <typename R, bool TH, int TY>
+__global__ __launch_bounds__((NT1<R, TH, TY>)) void lks_step_ubatch_kernel(
+    const BatchFwd<R>* __restrict__ d, const BatchStore<R>* __restrict__ st,
+    const int* __restrict__ tmap, int total, LevelRef in, LevelRef out, int level_out,
+    int use_acc) {
+  __shared__ FwdLds<R, TH, TY> L;
+  const int t = xcd_tile(total);
+  if (t < 0) return;
+  const int di = tmap[2 * t];
+  const BatchStore<R> s = st[di];
+  const Geo g = d[di].g;
+  FwdArgs<R> a = d[di].a[0];
+  a.d0 = level_field(s, in, 0);
+  a.ux0 = level_field(s, in, 1);
+  a.uy0 = level_field(s, in, 2);
+  a.T0 = level_field(s, in, 3);
+  a.d1 = level_field(s, out, 0);
+  a.ux1 = level_field(s, out, 1);
+  a.uy1 = level_field(s, out, 2);
+  a.T1 = level_field(s, out, 3);
+  a.level_out = level_out < s.n_ufac - 1 ? level_out : s.n_ufac - 1;
+  if (!use_acc) a.acc = nullptr;
+  batch_fwd_tile<R, TH, TY>(g, a, L, tmap[2 * t + 1]);
+}
+
+template <typename R, bool TH, int TY>
+__global__ __launch_bounds__((NT1<R, TH, TY>)) void alks_step_ubatch_kernel(
+    const BatchAdj<R>* __restrict__ d, const BatchStore<R>* __restrict__ st,
+    const int* __restrict__ tmap, int total, int parity, LevelRef lv, int seeded, int b_only) {
+  __shared__ AdjLds<R, TH, TY> L;
+  const int t = xcd_tile(total);
+  if (t < 0) return;
+  const int di = tmap[2 * t];
+  const BatchStore<R> s = st[di];
+  const Geo g = d[di].g;
+  AdjArgs<R> a = d[di].a[parity];
+  a.ux = level_field(s, lv, 1);
+  a.uy = level_field(s, lv, 2);
+  const R* T = level_field(s, lv, 3);
+  a.T = T ? T : a.ux;
+  a.sens_mode = 1;
+  if (!seeded) {
+    a.seed_dp = 0.0;
+    a.seed_heat = 0.0;
+  }
+  a.sens_b_only = b_only;
+  batch_adj_tile<R, TH, TY>(g, a, L, tmap[2 * t + 1]);
+}
+
+// per-tile objective accumulators of every design: zeroed, and summed in the
+// order of sum_kernel (one block per design)
+template <typename R>
+__global__ __launch_bounds__(NTHREADS) void acc_zero_batch_kernel(const BatchFwd<R>* d) {
+  const Geo& g = d[blockIdx.x].g;
+  double* acc = d[blockIdx.x].a[0].acc;
+  for (int t = threadIdx.x; t < g.ntx * g.nty; t += NTHREADS) acc[t] = 0.0;
+}
+template <typename R>
+__global__ __launch_bounds__(NTHREADS) void acc_sum_batch_kernel(const BatchFwd<R>* d,
+                                                                 double* out) {
+  __shared__ double red[NTHREADS / 64];
+  const Geo& g = d[blockIdx.x].g;
+  const double* v = d[blockIdx.x].a[0].acc;
+  const int n = g.ntx * g.nty;
+  double part = 0.0;
+  for (int t = threadIdx.x; t < n; t += NTHREADS) part += v[t];
+  double s = block_sum(part, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 // pressure drop of every design on its current level: one block per design
@@ -1813,6 +1897,48 @@ void launch_pressure_drop_batch(const BatchFwd<R>* d, int nd, int parity, double
                                 hipStream_t s) {
   pressure_drop_batch_kernel<R><<<nd, NTHREADS, 0, s>>>(d, parity, out);
 }
+template <typename R>
+void launch_lks_step_ubatch(const BatchFwd<R>* d, const BatchStore<R>* st, const int* tmap,
+                            int total, int ty, bool thermal, LevelRef in, LevelRef out,
+                            int level_out, int use_acc, hipStream_t s) {
+  const unsigned nb = unsigned(xcd_blocks(total));
+#define UB_FWD(TH, TY)                                                                     \
+  lks_step_ubatch_kernel<R, TH, TY><<<nb, (NT1<R, TH, TY>), 0, s>>>(d, st, tmap, total, in, \
+                                                                    out, level_out, use_acc)
+  if (ty == 8) {
+    if (thermal) UB_FWD(true, 8);
+    else UB_FWD(false, 8);
+  } else {
+    if (thermal) UB_FWD(true, 4);
+    else UB_FWD(false, 4);
+  }
+#undef UB_FWD
+}
+template <typename R>
+void launch_alks_step_ubatch(const BatchAdj<R>* d, const BatchStore<R>* st, const int* tmap,
+                             int total, int ty, bool thermal, int parity, LevelRef lv,
+                             int seeded, int b_only, hipStream_t s) {
+  const unsigned nb = unsigned(xcd_blocks(total));
+#define UB_ADJ(TH, TY)                                                                      \
+  alks_step_ubatch_kernel<R, TH, TY><<<nb, (NT1<R, TH, TY>), 0, s>>>(d, st, tmap, total,     \
+                                                                     parity, lv, seeded, b_only)
+  if (ty == 8) {
+    if (thermal) UB_ADJ(true, 8);
+    else UB_ADJ(false, 8);
+  } else {
+    if (thermal) UB_ADJ(true, 4);
+    else UB_ADJ(false, 4);
+  }
+#undef UB_ADJ
+}
+template <typename R>
+void launch_acc_zero_batch(const BatchFwd<R>* d, int nd, hipStream_t s) {
+  acc_zero_batch_kernel<R><<<nd, NTHREADS, 0, s>>>(d);
+}
+template <typename R>
+void launch_acc_sum_batch(const BatchFwd<R>* d, int nd, double* out, hipStream_t s) {
+  acc_sum_batch_kernel<R><<<nd, NTHREADS, 0, s>>>(d, out);
+}
 void launch_sum(const double* v, int n, double* out, hipStream_t s) {
   sum_kernel<<<1, NTHREADS, 0, s>>>(v, n, out);
 }
@@ -1857,6 +1983,13 @@ void launch_finite_check(const R* a, size_t n, int* flag, hipStream_t s) {
   template void launch_alks_step_batch<R>(const BatchAdj<R>*, const int*, int, int, bool, int,     \
                                           int, hipStream_t);                                  \
   template void launch_pressure_drop_batch<R>(const BatchFwd<R>*, int, int, double*, hipStream_t); \
+  template void launch_lks_step_ubatch<R>(const BatchFwd<R>*, const BatchStore<R>*, const int*,   \
+                                          int, int, bool, LevelRef, LevelRef, int, int,        \
+                                          hipStream_t);                                        \
+  template void launch_alks_step_ubatch<R>(const BatchAdj<R>*, const BatchStore<R>*, const int*,  \
+                                           int, int, bool, int, LevelRef, int, int, hipStream_t); \
+  template void launch_acc_zero_batch<R>(const BatchFwd<R>*, int, hipStream_t);                \
+  template void launch_acc_sum_batch<R>(const BatchFwd<R>*, int, double*, hipStream_t);        \
   template void launch_to_double<R>(const R*, double*, size_t, hipStream_t);                  \
   template void launch_from_double<R>(const double*, R*, size_t, hipStream_t);                \
   template void launch_finite_check<R>(const R*, size_t, int*, hipStream_t);

@@ -332,6 +332,22 @@ lks_status plan_binomial(lks_ctx* c, Plan& p, size_t base) {
 // none), and of equal replay counts the one that needs the least memory.
 // Checkpoint and segment levels are written by the step kernels in place,
 // so a smaller interval costs no extra copies in the forward sweep.
+// the two-level plan with checkpoint interval K
+void set_two_level(lks_ctx* c, int K) {
+  const int n = c->n_steps;
+  Plan p;
+  p.K = K;
+  p.n_ckpt = n / K + 1;
+  p.n_slots = K - 1;
+  p.ls = (n / K) * K;
+  p.ckpt_bytes = traj_bytes(c, K);
+  p.total = base_bytes(c) + align256(size_t(p.n_ckpt) * ckpt_fields(c) * c->N * c->rsz) +
+            align256(size_t(p.n_slots) * slot_fields(c) * c->N * c->rsz);
+  p.scheme = LKS_CKPT_TWO_LEVEL;
+  p.replay = K > n ? 0 : (long long)p.ls - (long long)p.ls / K;
+  c->plan = std::move(p);
+}
+
 lks_status plan_memory(lks_ctx* c) {
   Plan p;
   size_t base = base_bytes(c);
@@ -374,16 +390,7 @@ lks_status plan_memory(lks_ctx* c) {
              c->budget, base + mn);
     return fail(nullptr, LKS_E_NOMEM, buf);
   }
-  p.K = best;
-  p.n_ckpt = n / best + 1;
-  p.n_slots = best - 1;
-  p.ls = (n / best) * best;
-  p.ckpt_bytes = traj_bytes(c, best);
-  p.total = base + align256(size_t(p.n_ckpt) * ckpt_fields(c) * c->N * c->rsz) +
-            align256(size_t(p.n_slots) * slot_fields(c) * c->N * c->rsz);
-  p.scheme = LKS_CKPT_TWO_LEVEL;
-  p.replay = best > n ? 0 : (long long)p.ls - (long long)p.ls / best;
-  c->plan = std::move(p);
+  set_two_level(c, best);
   return LKS_OK;
 }
 
@@ -1775,6 +1782,14 @@ struct lks_batch {
   int g_nf = -1, g_na = -1;
   int last_nf = 0, last_na = 0;
   bool have_run = false;
+  // unsteady batches: checkpointed sweeps over the horizon n_steps shared by
+  // the designs, with one checkpoint interval K for all of them
+  int unsteady = 0;
+  int n_steps = 0;
+  int K = 0;
+  size_t budget = 0;        // device bytes of the whole batch (0: no limit)
+  void* d_store = nullptr;  // BatchStore<R>[n]
+  int exact = 0;            // adjoint mode (LKS_ADJ_*)
   std::string err;
 };
 
@@ -1797,6 +1812,67 @@ void build_tile_map(lks_batch* b) {
       b->tmap[2 * size_t(b->tile0[d] + t) + 1] = t;
     }
   }
+}
+
+// workspace slices of the designs, then the batch's own tables
+void batch_layout(lks_batch* b) {
+  size_t off = 0;
+  b->off.clear();
+  for (auto* c : b->ctx) {
+    b->off.push_back(off);
+    off += align256(c->plan.total);
+  }
+  const size_t fwd = sizeof(lks::BatchFwd<double>) * b->n;  // the double variants are larger
+  const size_t adj = sizeof(lks::BatchAdj<double>) * 3 * b->n;
+  off += align256(sizeof(int) * 2 * size_t(b->max_tiles)) + align256(fwd) + align256(adj) +
+         align256(sizeof(double) * b->n);
+  off += align256(sizeof(double) * b->maxN * b->n) + align256(size_t(b->rsz) * b->maxN);
+  off += align256(sizeof(lks::BatchStore<double>) * b->n);
+  b->total = off;
+}
+
+// unsteady batches: the checkpoint interval shared by the designs, the one
+// that replays the fewest steps with the whole batch within the budget (of
+// equal replay counts the one that needs the least memory), as one design's
+// two-level plan is chosen
+lks_status plan_batch(lks_batch* b) {
+  const int n = b->n_steps;
+  int best = 0;
+  long long best_rep = 0;
+  size_t best_t = 0, smallest = ~size_t(0);
+  for (int K = 1; K <= n + 1; ++K) {
+    for (auto* c : b->ctx) set_two_level(c, K);
+    batch_layout(b);
+    smallest = std::min(smallest, b->total);
+    if (b->budget != 0 && b->total > b->budget) continue;
+    const long long ls = (long long)(n / K) * K;
+    const long long rep = K > n ? 0 : ls - ls / K;
+    if (best == 0 || rep < best_rep || (rep == best_rep && b->total < best_t)) {
+      best = K;
+      best_rep = rep;
+      best_t = b->total;
+    }
+  }
+  const int K = best ? best : (b->K ? b->K : n + 1);
+  for (auto* c : b->ctx) set_two_level(c, K);
+  batch_layout(b);
+  if (!best) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "memory budget %zu B below the smallest checkpoint plan (%zu B)",
+             b->budget, smallest);
+    return bfail(b, LKS_E_NOMEM, buf);
+  }
+  b->K = best;
+  return LKS_OK;
+}
+
+// place of level n when the levels above `base` are held in the replay
+// slots (the forward sweep: base = the last checkpoint level), as
+// Run::level lays them out
+lks::LevelRef level_ref(int n, int base, int K) {
+  if (n % K == 0) return {lks::LVL_CKPT, n / K, n & 1};
+  if (n > base) return {lks::LVL_SLOT, n - base - 1, n & 1};
+  return {lks::LVL_PING, 0, n & 1};
 }
 
 template <typename R>
@@ -1827,7 +1903,7 @@ void build_batch_desc(lks_batch* b, double seed, int nf, std::vector<char>& fwd,
       a.ux1 = rp<R>(c->S[p ^ 1][1]);
       a.uy1 = rp<R>(c->S[p ^ 1][2]);
       a.T1 = rp<R>(c->S[p ^ 1][3]);
-      a.acc = nullptr;
+      a.acc = b->unsteady ? c->acc : nullptr;
       a.objective = c->objective;
     }
     const int fin = nf & 1;  // ping-pong index of the final forward level
@@ -1857,11 +1933,30 @@ void build_batch_desc(lks_batch* b, double seed, int nf, std::vector<char>& fwd,
         a.ops = static_cast<const lks::RingOpT<R>*>(c->d_ops);
         a.sens = b->d_sens + size_t(d) * b->maxN;
         a.sens_mode = 0;
-        a.exact = 0;
-        a.seed_dp = c->objective == LKS_OBJ_PRESSURE_DROP ? seed : 0.0;
-        a.seed_heat = c->objective == LKS_OBJ_HEAT ? seed : 0.0;
+        a.exact = b->exact;
+        // unsteady: the weight of one level of the time average
+        const double w = b->unsteady ? seed / b->n_steps : seed;
+        a.seed_dp = c->objective == LKS_OBJ_PRESSURE_DROP ? w : 0.0;
+        a.seed_heat = c->objective == LKS_OBJ_HEAT ? w : 0.0;
       }
     }
+  }
+}
+
+template <typename R>
+void build_batch_store(lks_batch* b, std::vector<char>& out) {
+  out.assign(sizeof(lks::BatchStore<R>) * b->n, 0);
+  auto* S = reinterpret_cast<lks::BatchStore<R>*>(out.data());
+  for (int d = 0; d < b->n; ++d) {
+    lks_ctx* c = b->ctx[d];
+    S[d].C = rp<R>(c->C);
+    S[d].Seg = rp<R>(c->Seg);
+    for (int p = 0; p < 2; ++p)
+      for (int f = 0; f < 4; ++f) S[d].S[p][f] = rp<R>(c->S[p][f]);
+    S[d].N = c->N;
+    S[d].ckf = ckpt_fields(c);
+    S[d].slf = slot_fields(c);
+    S[d].n_ufac = int(c->ufac.size());
   }
 }
 
@@ -1882,7 +1977,55 @@ void enqueue_batch_steps(lks_batch* b, int nf, int na, hipStream_t s) {
   }
 }
 
+// the checkpointed sweeps of an unsteady batch, Run::forward and
+// Run::adjoint_unsteady for every design at once: N LKS steps with the
+// objective accumulated per tile, the objective sums, then per segment from
+// the last down the replay of its levels and its ALKS steps (the first one
+// from the zero terminal condition), the sensitivity summed over levels
+template <typename R>
+void enqueue_batch_unsteady(lks_batch* b, hipStream_t s) {
+  auto* F = static_cast<const lks::BatchFwd<R>*>(b->d_fwd);
+  auto* Aj = static_cast<const lks::BatchAdj<R>*>(b->d_adj);
+  auto* St = static_cast<const lks::BatchStore<R>*>(b->d_store);
+  const int N = b->n_steps, K = b->K, ls = (N / K) * K;
+  const bool th = b->thermal;
+  lks::launch_acc_zero_batch<R>(F, b->n, s);
+  for (int n = 0; n < N; ++n)
+    lks::launch_lks_step_ubatch<R>(F, St, b->d_tmap, b->total_tiles, b->ty, th,
+                                   level_ref(n, ls, K), level_ref(n + 1, ls, K), n + 1, 1, s);
+  lks::launch_acc_sum_batch<R>(F, b->n, b->d_J, s);
+  lks::launch_fill(b->d_sens, b->maxN * size_t(b->n), 0.0, s);
+  int par = 0;
+  for (int base = ls; base >= 0; base -= K) {
+    const int top = base == ls ? N : base + K - 1;
+    if (base != ls)
+      for (int n = base; n < top; ++n)
+        lks::launch_lks_step_ubatch<R>(F, St, b->d_tmap, b->total_tiles, b->ty, th,
+                                       level_ref(n, base, K), level_ref(n + 1, base, K), n + 1,
+                                       0, s);
+    for (int n = top; n >= base; --n) {
+      const lks::BatchAdj<R>* D = (base == ls && n == top) ? Aj + 2 * b->n : Aj;
+      lks::launch_alks_step_ubatch<R>(D, St, b->d_tmap, b->total_tiles, b->ty, th, par,
+                                      level_ref(n, base, K), n >= 1 ? 1 : 0,
+                                      (n == 0 && b->exact) ? 1 : 0, s);
+      par ^= 1;
+    }
+  }
+}
+
+void enqueue_batch(lks_batch* b, int nf, int na, hipStream_t s) {
+  if (b->unsteady) {
+    if (b->rsz == 8) enqueue_batch_unsteady<double>(b, s);
+    else enqueue_batch_unsteady<float>(b, s);
+  } else {
+    if (b->rsz == 8) enqueue_batch_steps<double>(b, nf, na, s);
+    else enqueue_batch_steps<float>(b, nf, na, s);
+  }
+}
+
 }  // namespace
+
+static lks_status batch_set_tile_rows(lks_batch* b, int ty);
 
 extern "C" {
 
@@ -1894,19 +2037,29 @@ lks_status lks_batch_create(int n, const lks_grid* grids, const lks_phys* phys, 
   lks_batch* b = new lks_batch();
   b->n = n;
   b->user = static_cast<hipStream_t>(hip_stream);
-  size_t off = 0;
+  b->unsteady = bcs[0].mode == LKS_UNSTEADY ? 1 : 0;
+  b->n_steps = b->unsteady ? bcs[0].n_steps : 0;
   for (int d = 0; d < n; ++d) {
-    if (bcs[d].mode != LKS_STEADY || bcs[d].objective != LKS_OBJ_PRESSURE_DROP ||
-        grids[d].lattice != LKS_D2Q9 || grids[d].precision == LKS_MIXED) {
+    const bool steady_ok = bcs[d].mode == LKS_STEADY && bcs[d].objective == LKS_OBJ_PRESSURE_DROP;
+    const bool unsteady_ok =
+        bcs[d].mode == LKS_UNSTEADY &&
+        (bcs[d].objective == LKS_OBJ_PRESSURE_DROP || bcs[d].objective == LKS_OBJ_HEAT);
+    if (!(steady_ok || unsteady_ok) || grids[d].lattice != LKS_D2Q9 ||
+        grids[d].precision == LKS_MIXED || phys[d].beta_max > 0.0) {
       for (auto* p : b->ctx) lks_destroy(p);
       delete b;
       return bfail(nullptr, LKS_E_UNSUPPORTED,
-                   "batches hold steady D2Q9 problems with the pressure-drop objective");
+                   "batches hold D2Q9 problems without a heat source: steady with the "
+                   "pressure-drop objective, or unsteady with the pressure-drop or "
+                   "enthalpy-flux objective");
     }
-    if (grids[d].precision != grids[0].precision || phys[d].thermal != phys[0].thermal) {
+    if (grids[d].precision != grids[0].precision || phys[d].thermal != phys[0].thermal ||
+        bcs[d].mode != bcs[0].mode || (b->unsteady && bcs[d].n_steps != b->n_steps)) {
       for (auto* p : b->ctx) lks_destroy(p);
       delete b;
-      return bfail(nullptr, LKS_E_INVALID, "designs of a batch share precision and physics kind");
+      return bfail(nullptr, LKS_E_INVALID,
+                   "designs of a batch share precision, physics kind, mode and (unsteady) "
+                   "the horizon n_steps");
     }
     lks_ctx* c = nullptr;
     lks_status st = lks_create(&grids[d], &phys[d], &bcs[d], 0, hip_stream, &c);
@@ -1916,8 +2069,6 @@ lks_status lks_batch_create(int n, const lks_grid* grids, const lks_phys* phys, 
       return bfail(nullptr, st, "design " + std::to_string(d) + ": " + g_create_error);
     }
     b->ctx.push_back(c);
-    b->off.push_back(off);
-    off += align256(c->plan.total);
     b->tile0.push_back(b->total_tiles);
     b->total_tiles += n_tiles(c->geo);
     b->max_tiles += max_tiles(c->geo);
@@ -1926,13 +2077,60 @@ lks_status lks_batch_create(int n, const lks_grid* grids, const lks_phys* phys, 
   }
   b->rsz = b->ctx[0]->rsz;
   b->thermal = phys[0].thermal ? 1 : 0;
-  const size_t fwd = sizeof(lks::BatchFwd<double>) * n;   // the double variant is the larger
-  const size_t adj = sizeof(lks::BatchAdj<double>) * 3 * n;
-  off += align256(sizeof(int) * 2 * size_t(b->max_tiles)) + align256(fwd) + align256(adj) +
-         align256(sizeof(double) * n);
-  off += align256(sizeof(double) * b->maxN * n) + align256(size_t(b->rsz) * b->maxN);
-  b->total = off;
+  if (b->unsteady) {
+    // tile heights of the unsteady step launches: 4 and 8
+    if (b->ty == 16) batch_set_tile_rows(b, 8);
+    lks_status st = plan_batch(b);  // no budget yet: every level kept
+    if (st != LKS_OK) {
+      g_create_error = b->err;
+      lks_batch_destroy(b);
+      return st;
+    }
+  } else {
+    batch_layout(b);
+  }
   *out = b;
+  return LKS_OK;
+}
+
+lks_status lks_batch_set_memory_budget(lks_batch* b, size_t bytes) {
+  if (!b) return LKS_E_INVALID;
+  if (b->bound) return bfail(b, LKS_E_STATE, "the budget is planned before lks_batch_bind_workspace");
+  const size_t old = b->budget;
+  b->budget = bytes;
+  if (!b->unsteady) {
+    if (bytes != 0 && b->total > bytes) {
+      b->budget = old;
+      return bfail(b, LKS_E_NOMEM, "the batch's workspace exceeds the budget");
+    }
+    return LKS_OK;
+  }
+  lks_status st = plan_batch(b);
+  if (st != LKS_OK) {
+    const std::string msg = b->err;
+    b->budget = old;
+    plan_batch(b);
+    return bfail(b, st, msg);
+  }
+  return LKS_OK;
+}
+
+lks_status lks_batch_set_adjoint_mode(lks_batch* b, int mode) {
+  if (!b) return LKS_E_INVALID;
+  if (mode != LKS_ADJ_PAPER && mode != LKS_ADJ_EXACT)
+    return bfail(b, LKS_E_INVALID, "adjoint mode must be LKS_ADJ_PAPER or LKS_ADJ_EXACT");
+  if (mode != b->exact) b->have_run = false;
+  b->exact = mode;
+  for (auto* c : b->ctx) c->adj_exact = mode;
+  return LKS_OK;
+}
+
+lks_status lks_batch_checkpoint_info(const lks_batch* b, int* K, long long* replay_steps,
+                                     size_t* workspace_bytes) {
+  if (!b) return LKS_E_INVALID;
+  if (K) *K = b->unsteady ? b->K : 0;
+  if (replay_steps) *replay_steps = b->unsteady ? b->ctx[0]->plan.replay : 0;
+  if (workspace_bytes) *workspace_bytes = b->total;
   return LKS_OK;
 }
 
@@ -1964,6 +2162,7 @@ lks_status lks_batch_bind_workspace(lks_batch* b, void* dev_ptr, size_t bytes) {
   b->d_J = reinterpret_cast<double*>(take(sizeof(double) * b->n));
   b->d_sens = reinterpret_cast<double*>(take(sizeof(double) * b->maxN * b->n));
   b->d_zero = take(size_t(b->rsz) * b->maxN);
+  b->d_store = take(sizeof(lks::BatchStore<double>) * b->n);
   lks_status st = LKS_OK;
   hipStream_t s = b->user;
   if (b->rsz == 8) lks::launch_fill_r<double>(static_cast<double*>(b->d_zero), b->maxN, s);
@@ -1991,37 +2190,52 @@ lks_status lks_batch_run(lks_batch* b, const double* const* gamma_dev, int n_fwd
   if (!b) return LKS_E_INVALID;
   if (!b->bound) return bfail(b, LKS_E_STATE, "no workspace bound");
   if (!gamma_dev || !dJdgamma_dev || !J_host) return bfail(b, LKS_E_INVALID, "null argument");
-  if (n_fwd < 0 || n_adj < 1) return bfail(b, LKS_E_INVALID, "need n_fwd >= 0 and n_adj >= 1");
+  if (b->unsteady) {
+    if (n_fwd != b->n_steps) return bfail(b, LKS_E_INVALID, "unsteady batches need n_fwd == n_steps");
+    n_adj = n_fwd;  // the sweep covers every level
+  } else if (n_fwd < 0 || n_adj < 1) {
+    return bfail(b, LKS_E_INVALID, "need n_fwd >= 0 and n_adj >= 1");
+  }
   if (!std::isfinite(J_seed)) return bfail(b, LKS_E_INVALID, "seed not finite");
   for (int d = 0; d < b->n; ++d)
     if (!gamma_dev[d] || !dJdgamma_dev[d]) return bfail(b, LKS_E_INVALID, "null design pointer");
   lks_status st = LKS_OK;
   // descriptor tables (host -> device, ordered before the steps)
-  std::vector<char> fwd, adj;
-  if (b->rsz == 8) build_batch_desc<double>(b, J_seed, n_fwd, fwd, adj);
-  else build_batch_desc<float>(b, J_seed, n_fwd, fwd, adj);
+  std::vector<char> fwd, adj, store;
+  if (b->rsz == 8) {
+    build_batch_desc<double>(b, J_seed, n_fwd, fwd, adj);
+    build_batch_store<double>(b, store);
+  } else {
+    build_batch_desc<float>(b, J_seed, n_fwd, fwd, adj);
+    build_batch_store<float>(b, store);
+  }
   hipStream_t s = b->user;
   if (!hip_ok(nullptr, hipMemcpyAsync(b->d_fwd, fwd.data(), fwd.size(), hipMemcpyHostToDevice, s),
               "upload descriptors", &st) ||
       !hip_ok(nullptr, hipMemcpyAsync(b->d_adj, adj.data(), adj.size(), hipMemcpyHostToDevice, s),
-              "upload descriptors", &st))
+              "upload descriptors", &st) ||
+      !hip_ok(nullptr, hipMemcpyAsync(b->d_store, store.data(), store.size(),
+                                      hipMemcpyHostToDevice, s), "upload descriptors", &st))
     return bfail(b, st, g_create_error);
   // design coefficients and level-0 states
   for (int d = 0; d < b->n; ++d) {
     lks_ctx* c = b->ctx[d];
     c->last_level = 0;
     c->cur = 0;
+    // level 0: the ping-pong buffer 0 (steady) or checkpoint 0 (unsteady)
     if (b->rsz == 8) {
       Run<double> r(c);
       r.coefficients(gamma_dev[d]);
-      double* s0[4];
-      for (int f = 0; f < 4; ++f) s0[f] = rp<double>(c->S[0][f]);
+      double* s0[5] = {};
+      if (b->unsteady) r.level(0, c->plan.ls, s0);
+      else for (int f = 0; f < 4; ++f) s0[f] = rp<double>(c->S[0][f]);
       r.init(s0);
     } else {
       Run<float> r(c);
       r.coefficients(gamma_dev[d]);
-      float* s0[4];
-      for (int f = 0; f < 4; ++f) s0[f] = rp<float>(c->S[0][f]);
+      float* s0[5] = {};
+      if (b->unsteady) r.level(0, c->plan.ls, s0);
+      else for (int f = 0; f < 4; ++f) s0[f] = rp<float>(c->S[0][f]);
       r.init(s0);
     }
   }
@@ -2036,8 +2250,7 @@ lks_status lks_batch_run(lks_batch* b, const double* const* gamma_dev, int n_fwd
       if (!hip_ok(nullptr, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal),
                   "begin capture", &st))
         return bfail(b, st, g_create_error);
-      if (b->rsz == 8) enqueue_batch_steps<double>(b, n_fwd, n_adj, b->own);
-      else enqueue_batch_steps<float>(b, n_fwd, n_adj, b->own);
+      enqueue_batch(b, n_fwd, n_adj, b->own);
       if (!hip_ok(nullptr, hipStreamEndCapture(b->own, &b->graph), "end capture", &st) ||
           !hip_ok(nullptr, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0),
                   "instantiate graph", &st))
@@ -2052,8 +2265,7 @@ lks_status lks_batch_run(lks_batch* b, const double* const* gamma_dev, int n_fwd
         !hip_ok(nullptr, hipStreamWaitEvent(s, b->ev_out, 0), "wait", &st))
       return bfail(b, st, g_create_error);
   } else {
-    if (b->rsz == 8) enqueue_batch_steps<double>(b, n_fwd, n_adj, s);
-    else enqueue_batch_steps<float>(b, n_fwd, n_adj, s);
+    enqueue_batch(b, n_fwd, n_adj, s);
   }
   // sensitivities to the caller, objectives to the host
   std::vector<double> Js(b->n);
@@ -2071,9 +2283,12 @@ lks_status lks_batch_run(lks_batch* b, const double* const* gamma_dev, int n_fwd
     return bfail(b, st, g_create_error);
   for (int d = 0; d < b->n; ++d) {
     lks_ctx* c = b->ctx[d];
-    J_host[d] = (Js[d] + double(c->n_in - c->n_out)) / 3.0;
+    // the objective as lks_objective forms it from the per-level sums
+    const double sj = b->unsteady ? Js[d] / b->n_steps : Js[d];
+    if (c->objective == LKS_OBJ_PRESSURE_DROP) J_host[d] = (sj + double(c->n_in - c->n_out)) / 3.0;
+    else J_host[d] = sj;
     c->cur = n_fwd & 1;
-    c->acur = n_adj & 1;
+    c->acur = b->unsteady ? (n_fwd + 1) & 1 : n_adj & 1;
     c->last_level = n_fwd;
     c->have_forward = true;
     c->have_adjoint = true;
@@ -2113,6 +2328,8 @@ lks_status lks_batch_autotune(lks_batch* b, const double* const* gamma_dev, int 
                               double* const* scratch_dev, int* tile_rows) {
   if (!b || !gamma_dev || !scratch_dev || steps < 1) return LKS_E_INVALID;
   if (!b->bound) return bfail(b, LKS_E_STATE, "no workspace bound");
+  if (b->unsteady)
+    return bfail(b, LKS_E_UNSUPPORTED, "unsteady batches take their tile height from lks_batch_set_tile_rows");
   std::vector<double> J(b->n);
   float best = 0.0f;
   int best_ty = b->ty;
@@ -2152,8 +2369,9 @@ lks_status lks_batch_set_tile_rows(lks_batch* b, int tile_rows) {
   if (!b) return LKS_E_INVALID;
   bool known = false;
   for (int ty : TILE_ROWS) known = known || ty == tile_rows;
-  if (!known || !tile_rows_ok(tile_rows, b->rsz, b->thermal))
-    return bfail(b, LKS_E_INVALID, "tile height must be 4 or 8 (or 16 for FP32 non-thermal)");
+  if (!known || !tile_rows_ok(tile_rows, b->rsz, b->thermal) || (b->unsteady && tile_rows == 16))
+    return bfail(b, LKS_E_INVALID,
+                 "tile height must be 4 or 8 (or 16 for FP32 non-thermal steady batches)");
   lks_status st = batch_set_tile_rows(b, tile_rows);
   if (st == LKS_OK) b->have_run = false;
   return st;
@@ -2162,6 +2380,10 @@ lks_status lks_batch_set_tile_rows(lks_batch* b, int tile_rows) {
 lks_status lks_batch_read_field(lks_batch* b, int design, int which, double* dev_out) {
   if (!b || design < 0 || design >= b->n) return LKS_E_INVALID;
   if (!b->have_run) return bfail(b, LKS_E_STATE, "read before lks_batch_run");
+  if (b->unsteady && !adjoint_field(which))
+    return bfail(b, LKS_E_UNSUPPORTED,
+                 "unsteady batches keep no forward level after the sweep (the replays reuse "
+                 "its slots); adjoint fields are those of level 0");
   lks_status st = lks_read_field(b->ctx[design], which, dev_out);
   if (st != LKS_OK) return bfail(b, st, b->ctx[design]->err);
   return LKS_OK;

@@ -60,7 +60,8 @@ EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forwa
             "lks_batch_autotune", "lks_set_tile_rows", "lks_set_steps_per_launch",
             "lks_launch_shape", "lks_batch_set_tile_rows", "lks_set_adjoint_mode",
             "lks_set_checkpointing", "lks_checkpoint_info", "lks_gradient_status",
-            "lks_bind_static_workspace")
+            "lks_bind_static_workspace", "lks_batch_set_memory_budget",
+            "lks_batch_set_adjoint_mode", "lks_batch_checkpoint_info")
 
 # LKS_STATIC_WORKSPACE_BYTES of lks.h
 STATIC_WORKSPACE_BYTES = 64 * 1024 * 1024
@@ -164,6 +165,14 @@ _lib.lks_batch_set_tile_rows.argtypes = [_vp, ctypes.c_int]
 _lib.lks_batch_set_tile_rows.restype = _st
 _lib.lks_batch_destroy.argtypes = [_vp]
 _lib.lks_batch_destroy.restype = None
+_lib.lks_batch_set_memory_budget.argtypes = [_vp, ctypes.c_size_t]
+_lib.lks_batch_set_memory_budget.restype = _st
+_lib.lks_batch_set_adjoint_mode.argtypes = [_vp, ctypes.c_int]
+_lib.lks_batch_set_adjoint_mode.restype = _st
+_lib.lks_batch_checkpoint_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_longlong),
+                                           ctypes.POINTER(ctypes.c_size_t)]
+_lib.lks_batch_checkpoint_info.restype = _st
 
 
 class LKSError(RuntimeError):
@@ -325,6 +334,11 @@ class LKS:
         lks_set_checkpointing)."""
         _check(_lib.lks_set_checkpointing(self.ctx, _CKPT[scheme], int(slots)), self.ctx)
 
+    def set_memory_budget(self, nbytes):
+        """Device bytes for the whole batch, before binding (unsteady
+        batches plan their checkpoint interval from it)."""
+        _bcheck(_lib.lks_batch_set_memory_budget(self.b, ctypes.c_size_t(int(nbytes))), self.b)
+
     def checkpoint_info(self):
         """{"scheme": "two_level" | "binomial" | None, "count": K or snapshots,
         "replay_steps": forward steps one adjoint sweep recomputes}."""
@@ -367,11 +381,14 @@ def _bcheck(status, b=None):
 
 
 class Batch:
-    """Many independent steady pressure-drop designs advanced together: one
-    kernel launch per step for all designs, the step sequence replayed as a
-    HIP graph."""
+    """Many independent designs advanced together: one kernel launch per step
+    for all designs, the step sequence replayed as a HIP graph. Steady
+    pressure-drop designs, or unsteady designs sharing one horizon, whose
+    sweeps are checkpointed with one interval chosen for mem_budget bytes
+    (0: every level kept)."""
 
-    def __init__(self, workloads, precision="fp32", device=None, stream=None, bind=True):
+    def __init__(self, workloads, precision="fp32", device=None, stream=None, bind=True,
+                 mem_budget=0, adjoint_mode=None):
         self.wls = list(workloads)
         self.n = len(self.wls)
         self._keep = [LKS(w, precision=precision, bind=False, stream=0) for w in self.wls]
@@ -386,6 +403,13 @@ class Batch:
         self.b = _vp()
         _bcheck(_lib.lks_batch_create(self.n, self.grids, self.phys, self.bcs, _vp(stream or 0),
                                       ctypes.byref(self.b)))
+        if mem_budget:
+            self.set_memory_budget(mem_budget)
+        if adjoint_mode is None:
+            adjoint_mode = getattr(self.wls[0], "adjoint_mode", "paper")
+        if adjoint_mode != "paper":
+            code = {"paper": LKS_ADJ_PAPER, "exact": LKS_ADJ_EXACT}[adjoint_mode]
+            _bcheck(_lib.lks_batch_set_adjoint_mode(self.b, code), self.b)
         self.workspace = None
         if bind:
             self.bind()
@@ -410,6 +434,18 @@ class Batch:
         _bcheck(_lib.lks_batch_run(self.b, g, int(n_fwd), int(n_adj), float(seed), o, J,
                                    int(bool(graph))), self.b)
         return list(J)
+
+    def set_memory_budget(self, nbytes):
+        """Device bytes for the whole batch, before binding (unsteady
+        batches plan their checkpoint interval from it)."""
+        _bcheck(_lib.lks_batch_set_memory_budget(self.b, ctypes.c_size_t(int(nbytes))), self.b)
+
+    def checkpoint_info(self):
+        """(K, replay steps, workspace bytes) of the batch's plan."""
+        K, rep, ws = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_size_t()
+        _bcheck(_lib.lks_batch_checkpoint_info(self.b, ctypes.byref(K), ctypes.byref(rep),
+                                               ctypes.byref(ws)), self.b)
+        return K.value, rep.value, ws.value
 
     def autotune(self, gammas, scratch, steps=100):
         g = (_vp * self.n)(*[t.data_ptr() for t in gammas])

@@ -419,6 +419,27 @@ def batch_designs(n_designs=64, sizes=(128, 192, 256, 384, 512),
     return out
 
 
+def batch_unsteady_designs(n_designs=64, sizes=(128, 192, 256, 384, 512),
+                           Re_range=(10.0, 200.0), sigma=8.0, n_steps=2000,
+                           periods=4.0, aspect=1):
+    """Independent unsteady forced-convection designs of uneven size sharing
+    one horizon (the thermal channel of unsteady_thermal_channel: oscillating
+    inflow at T = 0, heated bottom wall, time-averaged enthalpy flux through
+    the last interior column): for design d, default_rng(d) draws the edge
+    length L (grid aspect*L x L) and Re; the inflow oscillates `periods`
+    times over the horizon."""
+    out = []
+    for d in range(n_designs):
+        rng = np.random.default_rng(d)
+        L = int(rng.choice(sizes))
+        Re = float(rng.uniform(*Re_range))
+        w = unsteady_thermal_channel(aspect * L, L, Re=Re, sigma=sigma, seed=1000 + d,
+                                     n_steps=n_steps, period=n_steps / periods)
+        w.name = f"ubatch{d}_{aspect * L}x{L}_Re{Re:.1f}"
+        out.append(w)
+    return out
+
+
 def periodic_box(nx, ny, nu=0.1, thermal=False, Pr=6.0):
     """Fully periodic box (no boundary nodes): used for the scheme's exact
     discrete invariants."""

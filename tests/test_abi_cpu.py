@@ -298,3 +298,45 @@ def test_static_workspace_rejects_a_context_beyond_its_size():
     assert e.value.status == lks.LKS_E_NOMEM
     assert b"exceeds the static array" in lks.lib().lks_last_error(c.ctx)
 
+
+
+def test_unsteady_batch_plans_one_interval_within_its_budget():
+    """An unsteady batch validates its designs and picks one checkpoint
+    interval for all of them, the one that replays the fewest steps with the
+    whole batch inside the budget, without touching a GPU."""
+    n = 300
+    wls = W.batch_unsteady_designs(5, sizes=(24, 40, 56), n_steps=n, aspect=2)
+    full = lks.Batch(wls, precision="fp32", bind=False)
+    K0, rep0, ws_all = full.checkpoint_info()
+    assert rep0 == 0                                   # every level kept
+    # per design and interval K: 4 stored fields per checkpoint, 3 per slot
+    nodes = sum(w.nx * w.ny for w in wls)
+
+    def traj(k):
+        return ((n // k) + 1) * 4 * nodes * 4 + (k - 1) * 3 * nodes * 4
+
+    def replay(k):
+        ls = (n // k) * k
+        return 0 if k > n else ls - ls // k
+
+    base = ws_all - traj(n + 1)
+    budget = base + traj(n + 1) // 6
+    b = lks.Batch(wls, precision="fp32", bind=False, mem_budget=budget)
+    K, rep, ws = b.checkpoint_info()
+    assert ws <= budget and 1 < K < n and rep == replay(K)
+    slack = 2 * 256 * len(wls) * 2                     # alignment of the two arrays
+    assert all(replay(k) >= rep for k in range(1, n + 2) if base + traj(k) + slack <= budget)
+    # a budget no plan fits keeps the previous plan
+    with pytest.raises(lks.LKSError) as e:
+        b.set_memory_budget(1)
+    assert e.value.status == lks.LKS_E_NOMEM
+    assert b.checkpoint_info() == (K, rep, ws)
+    # designs must share the horizon; batches hold no heat source
+    other = W.batch_unsteady_designs(2, sizes=(24,), n_steps=n + 1)
+    with pytest.raises(lks.LKSError) as e:
+        lks.Batch(wls[:2] + other[:1], precision="fp32", bind=False)
+    assert e.value.status == lks.LKS_E_INVALID
+    hx = W.heat_exchanger(31, n_fwd=10, n_adj=10)
+    with pytest.raises(lks.LKSError) as e:
+        lks.Batch([hx], precision="fp32", bind=False)
+    assert e.value.status == lks.LKS_E_UNSUPPORTED
