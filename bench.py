@@ -51,7 +51,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 CSRC = os.path.join(ROOT, "paper_2411_03090_amd", "csrc")
 KERNEL_SOURCES = ("lks_kernels.hip", "lks_kernels3d.hip", "lks_device.h")
-SECTIONS = ("headline", "batch", "large", "unsteady", "exchanger", "sink", "duct3d")
+SECTIONS = ("headline", "batch", "ubatch", "large", "unsteady", "exchanger", "sink", "duct3d")
 BOUND_FIELDS, BOUND_GRAD = 1e-5, 1e-3
 
 # algorithmic bytes per lattice update, (lattice/physics, sweep) -> (FP32, FP64):
@@ -82,6 +82,8 @@ def parse(argv=None):
     p.add_argument("--cpu-sample-steps", type=int, default=2500)
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--batch-steps", type=int, default=2000)
+    p.add_argument("--no-ubatch", action="store_true")
+    p.add_argument("--ubatch-steps", type=int, default=2000)
     p.add_argument("--no-unsteady", action="store_true")
     p.add_argument("--unsteady-steps", type=int, default=20000)
     p.add_argument("--no-large", action="store_true")
@@ -344,6 +346,83 @@ def batched_bench(args, dev, shapes):
                                  ("2d", "adj_steady"), "float", nodes, adj_us),
             "forward_roofline": roofline("batch", f"lks_step_batch_kernel<float, false, {ty}>",
                                          ("2d", "fwd"), "float", nodes, fwd_us)}
+
+
+def ubatch_bench(args, dev, shapes):
+    """64 independent unsteady forced-convection designs (edge lengths from
+    {128,...,512}, Re in [10, 200], Pr = 6, oscillating inflow, time-averaged
+    enthalpy flux through the last interior column) over one horizon of n
+    steps: the forward sweep and the checkpointed adjoint sweep of all
+    designs, one launch per step for all of them, replayed as a HIP graph;
+    one checkpoint interval for the batch from its memory budget (16 GiB
+    FP32, 32 GiB FP64).
+
+    Step times: a forward-only run (n_adj = 0) gives the LKS step; a full
+    run takes n + R LKS steps (R replayed) and n + 1 ALKS steps."""
+    import numpy as np
+    import torch
+    from paper_2411_03090_amd import lks, workloads as W
+    n = args.ubatch_steps
+    wls = W.batch_unsteady_designs(64, n_steps=n)
+    nodes = sum(w.nx * w.ny for w in wls)
+    gs = [torch.tensor(w.gamma.reshape(-1), dtype=torch.float64, device=dev) for w in wls]
+
+    def timed(prec, budget, ty, reps=2, steps=False):
+        b = lks.Batch(wls, precision=prec, device=dev, mem_budget=budget)
+        b.set_tile_rows(ty)
+        outs = [torch.empty_like(x) for x in gs]
+        Js = b.run(gs, outs, n, n)                      # warm-up, builds the graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.run(gs, outs, n, n)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        K, rep, ws = b.checkpoint_info()
+        out = {"ms_per_batch": ms, "mlups": nodes * 2 * n / (ms * 1e-3) / 1e6,
+               "gradients_per_s": 64 * 1e3 / ms, "K": K, "replay_steps": rep,
+               "workspace_GiB": ws / 2 ** 30, "budget_GiB": budget / 2 ** 30, "tile_rows": ty}
+        sens = np.concatenate([o.cpu().numpy() for o in outs])
+        if steps:
+            b.run(gs, outs, n, 0)                       # forward-only graph
+            torch.cuda.synchronize()
+            e0 = ev()
+            b.run(gs, outs, n, 0)
+            e1 = ev()
+            b.run(gs, outs, n, n)
+            e2 = ev()
+            torch.cuda.synchronize()
+            fwd_us = e0.elapsed_time(e1) * 1e3 / n
+            adj_us = (e1.elapsed_time(e2) * 1e3 - (n + rep) * fwd_us) / (n + 1)
+            out.update({"forward_step_us": fwd_us, "adjoint_step_us": adj_us})
+        b.close()
+        del b, outs
+        torch.cuda.empty_cache()
+        return out, np.array(Js), sens
+
+    res = {"designs": 64, "nodes": nodes, "steps": n}
+    sh = shapes.get("ubatch", {})
+    ty32 = int(sh["fp32"][0]) if "fp32" in sh else None
+    if ty32 is None:                                    # the faster tile height
+        tries = {ty: timed("fp32", 16 * 2 ** 30, ty, reps=1)[0]["ms_per_batch"] for ty in (4, 8)}
+        ty32 = min(tries, key=tries.get)
+    a, J32, s32 = timed("fp32", 16 * 2 ** 30, ty32, steps=True)
+    ty64 = int(sh["fp64"][0]) if "fp64" in sh else 4
+    c, J64, s64 = timed("fp64", 32 * 2 ** 30, ty64)
+    res.update({"fp32": a, "fp64": c,
+                "speedup_fp32_vs_fp64": c["ms_per_batch"] / a["ms_per_batch"],
+                "fp32_vs_fp64_rel_error": {
+                    "J_max": float(np.max(np.abs(J32 - J64) / np.abs(J64))),
+                    "dJdgamma_l2": rel(s32, s64)}})
+    res["roofline"] = roofline("ubatch", f"alks_step_ubatch_kernel<float, true, {ty32}>",
+                               ("2d_thermal", "adj_unsteady"), "float", nodes,
+                               a["adjoint_step_us"])
+    res["roofline"]["note"] = ("step duration: the full run less its forward and replayed "
+                               "steps at the forward-only run's step time")
+    res["forward_roofline"] = roofline("ubatch", f"lks_step_ubatch_kernel<float, true, {ty32}>",
+                                       ("2d_thermal", "fwd"), "float", nodes,
+                                       a["forward_step_us"])
+    return res
 
 
 def large_bench(args, dev, shapes):
@@ -704,7 +783,8 @@ def main():
         print(f"unknown sections {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
     shapes = json.loads(args.shapes) if args.shapes else {}
-    skip = {"batch": args.no_batch, "large": args.no_large, "unsteady": args.no_unsteady,
+    skip = {"batch": args.no_batch, "ubatch": args.no_ubatch, "large": args.no_large,
+            "unsteady": args.no_unsteady,
             "exchanger": args.no_exchanger, "sink": args.no_sink, "duct3d": args.no_3d}
     run = {s: (s in only and not skip.get(s, False)) for s in SECTIONS}
 
@@ -734,6 +814,7 @@ def main():
         if not args.no_cpu_baseline:
             line["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
     for name, key, fn in (("batch", "batched_64_designs", batched_bench),
+                          ("ubatch", "batched_64_unsteady_thermal_designs", ubatch_bench),
                           ("large", "steady_2048x2048", large_bench),
                           ("unsteady", "unsteady_thermal_1024x512", unsteady_bench),
                           ("exchanger", "heat_exchanger_201x201", exchanger_bench),

@@ -390,7 +390,9 @@ lks_status lks_batch_workspace_size(const lks_batch *b, size_t *bytes);
 lks_status lks_batch_bind_workspace(lks_batch *b, void *dev_ptr, size_t bytes);
 /* gamma_dev[d], dJdgamma_dev[d]: device pointers of design d (nx*ny doubles);
  * J_host: n doubles. Synchronises the stream. Linear in J_seed. Unsteady
- * batches need n_fwd == n_steps and ignore n_adj. */
+ * batches need n_fwd == n_steps; n_adj = 0 runs the forward sweep and the
+ * objectives only (dJdgamma_dev untouched), any other n_adj the whole
+ * adjoint sweep. */
 lks_status lks_batch_run(lks_batch *b, const double *const *gamma_dev, int n_fwd, int n_adj,
                          double J_seed, double *const *dJdgamma_dev, double *J_host,
                          int use_graph);

@@ -197,15 +197,17 @@ struct BatchStore {
   int n_ufac;  // entries of the design's inflow-factor table
 };
 // field f (drho, ux, uy, T) of the level at r; null for T when the fields
-// stored per level stop before it (non-thermal designs)
+// stored per level stop before it (non-thermal designs). The ping-pong
+// buffer is picked with a select, not an index: a runtime index into the
+// descriptor would move it to per-lane scratch memory.
 template <typename R>
 __host__ __device__ inline R* level_field(const BatchStore<R>& s, LevelRef r, int f) {
-  if (r.kind == LVL_CKPT) return f < s.ckf ? s.C + (size_t(r.idx) * s.ckf + f) * size_t(s.N) : nullptr;
-  if (r.kind == LVL_SLOT) {
-    if (f == 0) return s.S[r.par][0];
-    return f < s.ckf ? s.Seg + (size_t(r.idx) * s.slf + (f - 1)) * size_t(s.N) : nullptr;
-  }
-  return f < s.ckf ? s.S[r.par][f] : nullptr;
+  if (f >= s.ckf) return nullptr;
+  R* const ping = r.par ? s.S[1][f] : s.S[0][f];
+  if (r.kind == LVL_CKPT) return s.C + (size_t(r.idx) * s.ckf + f) * size_t(s.N);
+  if (r.kind == LVL_SLOT)
+    return f == 0 ? ping : s.Seg + (size_t(r.idx) * s.slf + (f - 1)) * size_t(s.N);
+  return ping;
 }
 
 // host: the four ring operators for a given A and fluid B

@@ -1983,7 +1983,7 @@ void enqueue_batch_steps(lks_batch* b, int nf, int na, hipStream_t s) {
 // the last down the replay of its levels and its ALKS steps (the first one
 // from the zero terminal condition), the sensitivity summed over levels
 template <typename R>
-void enqueue_batch_unsteady(lks_batch* b, hipStream_t s) {
+void enqueue_batch_unsteady(lks_batch* b, bool adjoint, hipStream_t s) {
   auto* F = static_cast<const lks::BatchFwd<R>*>(b->d_fwd);
   auto* Aj = static_cast<const lks::BatchAdj<R>*>(b->d_adj);
   auto* St = static_cast<const lks::BatchStore<R>*>(b->d_store);
@@ -1994,6 +1994,7 @@ void enqueue_batch_unsteady(lks_batch* b, hipStream_t s) {
     lks::launch_lks_step_ubatch<R>(F, St, b->d_tmap, b->total_tiles, b->ty, th,
                                    level_ref(n, ls, K), level_ref(n + 1, ls, K), n + 1, 1, s);
   lks::launch_acc_sum_batch<R>(F, b->n, b->d_J, s);
+  if (!adjoint) return;
   lks::launch_fill(b->d_sens, b->maxN * size_t(b->n), 0.0, s);
   int par = 0;
   for (int base = ls; base >= 0; base -= K) {
@@ -2015,8 +2016,8 @@ void enqueue_batch_unsteady(lks_batch* b, hipStream_t s) {
 
 void enqueue_batch(lks_batch* b, int nf, int na, hipStream_t s) {
   if (b->unsteady) {
-    if (b->rsz == 8) enqueue_batch_unsteady<double>(b, s);
-    else enqueue_batch_unsteady<float>(b, s);
+    if (b->rsz == 8) enqueue_batch_unsteady<double>(b, na > 0, s);
+    else enqueue_batch_unsteady<float>(b, na > 0, s);
   } else {
     if (b->rsz == 8) enqueue_batch_steps<double>(b, nf, na, s);
     else enqueue_batch_steps<float>(b, nf, na, s);
@@ -2192,7 +2193,7 @@ lks_status lks_batch_run(lks_batch* b, const double* const* gamma_dev, int n_fwd
   if (!gamma_dev || !dJdgamma_dev || !J_host) return bfail(b, LKS_E_INVALID, "null argument");
   if (b->unsteady) {
     if (n_fwd != b->n_steps) return bfail(b, LKS_E_INVALID, "unsteady batches need n_fwd == n_steps");
-    n_adj = n_fwd;  // the sweep covers every level
+    if (n_adj != 0) n_adj = n_fwd;  // the sweep covers every level; 0: no sweep
   } else if (n_fwd < 0 || n_adj < 1) {
     return bfail(b, LKS_E_INVALID, "need n_fwd >= 0 and n_adj >= 1");
   }
@@ -2269,7 +2270,7 @@ lks_status lks_batch_run(lks_batch* b, const double* const* gamma_dev, int n_fwd
   }
   // sensitivities to the caller, objectives to the host
   std::vector<double> Js(b->n);
-  for (int d = 0; d < b->n; ++d) {
+  for (int d = 0; d < b->n && n_adj > 0; ++d) {
     const size_t N = size_t(b->ctx[d]->geo.N);
     if (!hip_ok(nullptr, hipMemcpyAsync(dJdgamma_dev[d], b->d_sens + size_t(d) * b->maxN,
                                         N * sizeof(double), hipMemcpyDeviceToDevice, s),
@@ -2291,7 +2292,7 @@ lks_status lks_batch_run(lks_batch* b, const double* const* gamma_dev, int n_fwd
     c->acur = b->unsteady ? (n_fwd + 1) & 1 : n_adj & 1;
     c->last_level = n_fwd;
     c->have_forward = true;
-    c->have_adjoint = true;
+    c->have_adjoint = n_adj > 0;
   }
   b->last_nf = n_fwd;
   b->last_na = n_adj;
@@ -2380,6 +2381,8 @@ lks_status lks_batch_set_tile_rows(lks_batch* b, int tile_rows) {
 lks_status lks_batch_read_field(lks_batch* b, int design, int which, double* dev_out) {
   if (!b || design < 0 || design >= b->n) return LKS_E_INVALID;
   if (!b->have_run) return bfail(b, LKS_E_STATE, "read before lks_batch_run");
+  if (b->unsteady && adjoint_field(which) && b->last_na == 0)
+    return bfail(b, LKS_E_STATE, "the last run had no adjoint sweep");
   if (b->unsteady && !adjoint_field(which))
     return bfail(b, LKS_E_UNSUPPORTED,
                  "unsteady batches keep no forward level after the sweep (the replays reuse "

@@ -138,7 +138,7 @@ def test_unsteady_batch_keeps_every_level_without_a_budget():
     b.set_tile_rows(8)
     gs = [T(w.gamma) for w in wls]
     outs = [torch.full_like(g, float("nan")) for g in gs]
-    Js = b.run(gs, outs, N_STEPS, 0)
+    Js = b.run(gs, outs, N_STEPS, N_STEPS)
     torch.cuda.synchronize()
     for d, w in enumerate(wls):
         Jc, sc = _single(w, "fp32", 8)
@@ -151,3 +151,19 @@ def test_unsteady_batch_keeps_every_level_without_a_budget():
         b.read(0, "ux")
     assert e.value.status == lks.LKS_E_UNSUPPORTED
     assert torch.isfinite(b.read(0, "adj_rho")).all()
+
+
+def test_unsteady_batch_forward_only_run():
+    say(f"[gpu] unsteady batch, forward sweep only (n_adj = 0), fp32, {N_STEPS} steps")
+    wls = _designs()[:2]
+    b = _budget_batch(wls, "fp32")
+    Js, sens = _run(b, wls)
+    gs = [T(w.gamma) for w in wls]
+    outs = [torch.full_like(g, float("nan")) for g in gs]
+    Jf = b.run(gs, outs, N_STEPS, 0)
+    torch.cuda.synchronize()
+    assert Jf == Js                                     # the same objectives, bitwise
+    assert all(torch.isnan(o).all() for o in outs)      # no sensitivity written
+    with pytest.raises(lks.LKSError) as e:
+        b.read(0, "adj_rho")
+    assert e.value.status == lks.LKS_E_STATE
