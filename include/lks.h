@@ -308,6 +308,15 @@ lks_status lks_set_steps_per_launch(lks_ctx *ctx, int forward_steps, int adjoint
  * Errors: LKS_E_INVALID for another value. */
 lks_status lks_set_adjoint_mode(lks_ctx *ctx, int mode);
 
+/* D3Q19 contexts: run each ALKS step (eq:afeq, eq:ageq, eq:afp - eq:agq and
+ * the sensitivity) as one z-marching kernel over the interior planes, which
+ * keeps the adjoint moments of a plane in LDS and registers (fused = 1, the
+ * default), or as a pull pass, a face pass and an update pass that store the
+ * moments of every node between them (fused = 0). Both give the same bits;
+ * boundary nodes take the face pass's moments either way. Errors:
+ * LKS_E_UNSUPPORTED for D2Q9 contexts, LKS_E_INVALID for another value. */
+lks_status lks_set_fused_adjoint(lks_ctx *ctx, int fused);
+
 /* The launch shape in use: tile height (0 for D3Q19) and steps per launch of
  * the forward and adjoint sweeps. */
 lks_status lks_launch_shape(const lks_ctx *ctx, int *tile_rows, int *forward_steps,

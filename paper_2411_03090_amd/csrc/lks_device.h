@@ -226,6 +226,8 @@ struct Geo3 {
   int periodic;     // bit 0: x, bit 1: y, bit 2: z
   int thermal;
   int zc, zca;      // z-planes per block: LKS step, ALKS update pass (>= 2)
+  int zcf;          // z-planes per block of the fused ALKS step (>= 2)
+  int fused;        // ALKS step: 1 fused z-march, 0 pull, face and update passes
   double A;         // eq:A
   double Bf;        // B of the fluid, used on boundary nodes
   double drho_out;  // prescribed outlet density minus 1

@@ -21,6 +21,7 @@
 // keeping the neighbour planes of a block in that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <vector>
 
 #include "lks_device.h"
@@ -218,8 +219,11 @@ struct ZTile {
 
 // tile of this block; logical blocks run x fastest, then y, then z-chunk, and
 // the blocks of XCD x (blockIdx % 8) take the x-th eighth of them
-__device__ inline bool ztile(const Geo3& g, ZTile& t) {
-  const int ntx = ztiles(g.nx, ZX), nty = ztiles(g.ny, ZY), nch = zchunks(g);
+// (output planes: chunks of [zlo, zhi), nch of them when given)
+__device__ inline bool ztile(const Geo3& g, ZTile& t, int zlo = 0, int zhi = -1, int nch = 0) {
+  if (zhi < 0) zhi = g.nz;
+  if (nch <= 0) nch = zchunks(g);
+  const int ntx = ztiles(g.nx, ZX), nty = ztiles(g.ny, ZY);
   const int per = int(gridDim.x) / NXCD;
   t.lb = (int(blockIdx.x) % NXCD) * per + int(blockIdx.x) / NXCD;
   if (t.lb >= ntx * nty * nch) return false;
@@ -230,8 +234,8 @@ __device__ inline bool ztile(const Geo3& g, ZTile& t) {
   t.yo = iy * ZY;
   t.x0 = t.xo < g.nx - t.w ? t.xo : g.nx - t.w;
   t.y0 = t.yo < g.ny - t.h ? t.yo : g.ny - t.h;
-  t.z0 = int((long long)ic * g.nz / nch);
-  t.z1 = int((long long)(ic + 1) * g.nz / nch);
+  t.z0 = zlo + int((long long)ic * (zhi - zlo) / nch);
+  t.z1 = zlo + int((long long)(ic + 1) * (zhi - zlo) / nch);
   return true;
 }
 
@@ -272,11 +276,9 @@ __device__ inline ZNode znode(const Geo3& g, const ZTile& t, int dx, int dy, boo
   return n;
 }
 
-// the thread's column of the ring around the tile; ring positions are dealt
-// round-robin over the four waves
-__device__ inline ZNode zring(const Geo3& g, const ZTile& t) {
-  const int tid = int(threadIdx.x);
-  const int r = (tid % 64) * (ZT / 64) + tid / 64;
+// the ring column at position r of the ring around the tile: the row below
+// the tile, the row above, the column left of it, the column right of it
+__device__ inline ZNode zring_at(const Geo3& g, const ZTile& t, int r) {
   const int a = t.w + 2;
   int dx, dy;
   if (r < a) {
@@ -292,8 +294,16 @@ __device__ inline ZNode zring(const Geo3& g, const ZTile& t) {
     dx = t.w;
     dy = r - 2 * a - t.h;
   }
-  const bool on = r < 2 * a + 2 * t.h;
+  const bool on = r >= 0 && r < 2 * a + 2 * t.h;
   return znode(g, t, on ? dx : 0, on ? dy : 0, on);
+}
+// the thread's ring column: each wave takes a quarter of the ring in
+// consecutive positions, so the ring work is spread evenly over the SIMDs
+// and neighbouring lanes touch neighbouring LDS words
+__device__ inline ZNode zring(const Geo3& g, const ZTile& t) {
+  const int per = (2 * (t.w + 2) + 2 * t.h + 3) / 4;  // at most 35 for 64 x 4 tiles
+  const int lane = int(threadIdx.x) % 64, w = int(threadIdx.x) / 64;
+  return zring_at(g, t, lane < per ? w * per + lane : -1);
 }
 
 // in-plane offsets of the thread's elements of the 2-node halo region; -1
@@ -958,6 +968,94 @@ __device__ inline void zregion1(const Geo3& g, const ZTile& t, int off[2]) {
   }
 }
 
+// per-node inputs of the ALKS update at one node: its moments rho~, u~,
+// T~, its velocity, the coefficients' derivatives, 1/(1 + alpha) and class
+template <typename R>
+struct AdjIn {
+  R r, U[3], Tt, u[3], dA, dB, ip;
+  int mk;
+};
+
+// The ALKS update at node k of a z-march column (eq:afp - eq:agq): V and
+// Theta of the new level from the node's moments (cu), the in-plane moment
+// fields E (s~xx s~xy s~xz s~yy s~yz q~x q~y T B, 1-node halo, index ci,
+// end flags ex, ey) and the z differences zd of s~xz s~yz s~zz q~z T B (z
+// window zc, zm1, zn, z2 for the product difference of the exact mode), and
+// the sensitivity 3 alpha' u.u~ - B' grad T.q~ (paper) or its exact-mode
+// counterpart.
+template <typename R, bool TH>
+__device__ inline void adj3_update(const Adj3Args<R>& a, const Geo3& g, unsigned k,
+                                   const R (*E)[NCR], int ci, int ex, int ey, int ez,
+                                   const AdjIn<R>& cu, const R zd[6], const R zc[6],
+                                   const R zm1[6], const R zn[6], const R z2[6]) {
+  // no fused multiply-adds here: the fused step passes z differences the
+  // compiler could fold into the sums below, the update pass selects them
+  // per plane, and both must round alike
+#pragma clang fp contract(off)
+  const R S[6] = {E[0][ci], E[1][ci], E[2][ci], E[3][ci], E[4][ci], zc[2]};
+  const R A2 = R(2.0 * g.A);
+  const R ds[3] = {d1(E[0], ci, 1, ex) + d1(E[1], ci, CXN, ey) + zd[0],
+                   d1(E[1], ci, 1, ex) + d1(E[3], ci, CXN, ey) + zd[1],
+                   d1(E[2], ci, 1, ex) + d1(E[4], ci, CXN, ey) + zd[2]};
+  R V[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    R su = R(0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) su += S[SI[c][b]] * cu.u[b];
+    V[c] = R(3) * cu.U[c] + R(9) * su - R(3) * cu.r * cu.u[c] - A2 * ds[c];
+  }
+  // the Brinkman pairing of the sensitivity: 3 alpha' u.u~ (paper) or
+  // alpha' u.V / (1 + alpha) with the undivided V, which then propagates
+  // divided by 1 + alpha (exact)
+  double pair = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) pair += double(cu.u[c]) * double(a.exact ? V[c] : cu.U[c]);
+  if (a.exact) {
+    pair *= double(cu.ip) / 3.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) V[c] *= cu.ip;
+  }
+  a.p1[0][k] = cu.r;
+  a.p1[1][k] = V[0];
+  a.p1[2][k] = V[1];
+  a.p1[3][k] = V[2];
+  R qv[3] = {R(0), R(0), R(0)};
+  if constexpr (TH) {
+    qv[0] = E[5][ci];
+    qv[1] = E[6][ci];
+    qv[2] = zc[3];
+    const R qu = qv[0] * cu.u[0] + qv[1] * cu.u[1] + qv[2] * cu.u[2];
+    const R* Bp = E[8];
+    if (a.exact) {
+      // exact: the transpose of the forward B c.grad_h T, -div_h (B q~)
+      const R zbq = dz3(ez, zc[3] * zc[5], zm1[3] * zm1[5], zn[3] * zn[5], z2[3] * z2[5]);
+      const R dbq = d1p(Bp, E[5], ci, 1, ex) + d1p(Bp, E[6], ci, CXN, ey) + zbq;
+      a.p1[4][k] = cu.Tt + R(3) * qu - dbq;
+    } else {
+      const R divq = d1(E[5], ci, 1, ex) + d1(E[6], ci, CXN, ey) + zd[3];
+      const R gbq = d1(Bp, ci, 1, ex) * qv[0] + d1(Bp, ci, CXN, ey) * qv[1] + zd[5] * qv[2];
+      a.p1[4][k] = cu.Tt + R(3) * qu - Bp[ci] * divq - gbq;
+    }
+  }
+  if (a.sens_mode) {
+    double sv = 0.0;
+    if (!ex && !ey && !ez && !(cu.mk & TAG_SOLID3)) {
+      sv = a.sens_b_only ? 0.0 : double(cu.dA) * pair;
+      if constexpr (TH) {
+        const R* Tp = E[7];
+        const R gt[3] = {d1(Tp, ci, 1, ex), d1(Tp, ci, CXN, ey), zd[4]};
+        double gq = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gq += double(gt[c]) * double(qv[c]);
+        sv -= double(cu.dB) * gq;
+      }
+    }
+    if (a.sens_mode == 1) a.sens[k] += sv;
+    else a.sens[k] = sv;
+  }
+}
+
 // ALKS pass 2, z-marching: V, Theta (eq:afp - eq:agq) and the sensitivity
 // from the moments; x and y differences from an LDS plane, z differences
 // from a window of three planes in registers.
@@ -969,13 +1067,23 @@ struct AdjELds {
   R e[2][NE][NCR];
 };
 
-template <typename R, bool TH>
+// ENDS: only the two end planes of a non-periodic z axis (after the fused
+// step, which leaves them): tile chunk 0 takes plane 0, chunk 1 plane nz - 1
+template <typename R, bool TH, bool ENDS = false>
 __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
   constexpr int NE = AdjELds<R, TH>::NE;
   constexpr int NZ = TH ? 6 : 3;  // z window: s~xz s~yz s~zz (q~z T B)
   __shared__ AdjELds<R, TH> L;
   ZTile t;
-  if (!ztile(g, t)) return;
+  if constexpr (ENDS) {
+    if (!ztile(g, t, 0, 2, 2)) return;
+    if (t.z0 == 1) {
+      t.z0 = g.nz - 1;
+      t.z1 = g.nz;
+    }
+  } else {
+    if (!ztile(g, t)) return;
+  }
   const int tid = int(threadIdx.x), lx = tid % ZX, ly = tid / ZX;
   const int pz = g.periodic & 4;
   const unsigned nxy = unsigned(g.nx) * unsigned(g.ny);
@@ -1025,10 +1133,7 @@ __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
     for (int f = 0; f < NZ; ++f) z[f] = FZ[f][k];
   };
   // per-node inputs one plane ahead
-  struct In {
-    R r, U[3], Tt, u[3], dA, dB, ip;
-    int mk;
-  };
+  using In = AdjIn<R>;
   auto node_in = [&](int p, In& q) {
     q.r = q.Tt = q.dA = q.dB = R(0);
     q.ip = R(1);
@@ -1079,82 +1184,229 @@ __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
     R zd[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) zd[f] = dz3(ez, zc[f], zm1[f], zn[f], z2[f]);
-    if (own) {
-      const unsigned k = unsigned(p) * nxy + unsigned(n0.off);
-      const R(*E)[NCR] = L.e[sc];
-      const R S[6] = {E[0][ci], E[1][ci], E[2][ci], E[3][ci], E[4][ci], zc[2]};
-      const R A2 = R(2.0 * g.A);
-      const R ds[3] = {d1(E[0], ci, 1, n0.ex) + d1(E[1], ci, CXN, n0.ey) + zd[0],
-                       d1(E[1], ci, 1, n0.ex) + d1(E[3], ci, CXN, n0.ey) + zd[1],
-                       d1(E[2], ci, 1, n0.ex) + d1(E[4], ci, CXN, n0.ey) + zd[2]};
-      R V[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        R su = R(0);
-#pragma unroll
-        for (int b = 0; b < 3; ++b) su += S[SI[c][b]] * cu.u[b];
-        V[c] = R(3) * cu.U[c] + R(9) * su - R(3) * cu.r * cu.u[c] - A2 * ds[c];
-      }
-      // the Brinkman pairing of the sensitivity: 3 alpha' u.u~ (paper) or
-      // alpha' u.V / (1 + alpha) with the undivided V, which then propagates
-      // divided by 1 + alpha (exact)
-      double pair = 0.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        pair += double(cu.u[c]) * double(a.exact ? V[c] : cu.U[c]);
-      if (a.exact) {
-        pair *= double(cu.ip) / 3.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) V[c] *= cu.ip;
-      }
-      a.p1[0][k] = cu.r;
-      a.p1[1][k] = V[0];
-      a.p1[2][k] = V[1];
-      a.p1[3][k] = V[2];
-      R qv[3] = {R(0), R(0), R(0)};
-      if constexpr (TH) {
-        qv[0] = E[TH ? 5 : 0][ci];
-        qv[1] = E[TH ? 6 : 0][ci];
-        qv[2] = zc[3];
-        const R qu = qv[0] * cu.u[0] + qv[1] * cu.u[1] + qv[2] * cu.u[2];
-        const R* Bp = E[TH ? 8 : 0];
-        if (a.exact) {
-          // exact: the transpose of the forward B c.grad_h T, -div_h (B q~)
-          const R zbq = dz3(ez, zc[3] * zc[5], zm1[3] * zm1[5], zn[3] * zn[5], z2[3] * z2[5]);
-          const R dbq = d1p(Bp, E[TH ? 5 : 0], ci, 1, n0.ex) +
-                        d1p(Bp, E[TH ? 6 : 0], ci, CXN, n0.ey) + zbq;
-          a.p1[4][k] = cu.Tt + R(3) * qu - dbq;
-        } else {
-          const R divq =
-              d1(E[TH ? 5 : 0], ci, 1, n0.ex) + d1(E[TH ? 6 : 0], ci, CXN, n0.ey) + zd[3];
-          const R gbq =
-              d1(Bp, ci, 1, n0.ex) * qv[0] + d1(Bp, ci, CXN, n0.ey) * qv[1] + zd[5] * qv[2];
-          a.p1[4][k] = cu.Tt + R(3) * qu - Bp[ci] * divq - gbq;
-        }
-      }
-      if (a.sens_mode) {
-        double sv = 0.0;
-        if (!n0.ex && !n0.ey && !ez && !(cu.mk & TAG_SOLID3)) {
-          sv = a.sens_b_only ? 0.0 : double(cu.dA) * pair;
-          if constexpr (TH) {
-            const R* Tp = E[TH ? 7 : 0];
-            const R gt[3] = {d1(Tp, ci, 1, n0.ex), d1(Tp, ci, CXN, n0.ey), zd[4]};
-            double gq = 0.0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) gq += double(gt[c]) * double(qv[c]);
-            sv -= double(cu.dB) * gq;
-          }
-        }
-        if (a.sens_mode == 1) a.sens[k] += sv;
-        else a.sens[k] = sv;
-      }
-    }
+    if (own)
+      adj3_update<R, TH>(a, g, unsigned(p) * nxy + unsigned(n0.off), L.e[sc], ci, n0.ex, n0.ey,
+                         ez, cu, zd, zc, zm1, zn, z2);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       zm1[f] = zc[f];
       zc[f] = zn[f];
       zn[f] = znn[f];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// ALKS step, fused
+// ---------------------------------------------------------------------------
+// One z-march per block over the planes 1 .. nz-2 of a non-periodic z axis
+// (every plane of a periodic one). At plane s every column of the tile and of
+// its 1-node ring forms its moments of plane s: an interior node pulls
+// f~_q = rho~ + c_q.V and g~_q = Theta from x + c_q (eq:afeq, eq:ageq) out
+// of four LDS plane slots of the level-(n+1) coefficients (tile plus a
+// 2-node halo) and applies the local terms, as the pull pass does; a
+// boundary node takes the moments the face pass left in the scratch. The
+// plane's in-plane moment fields go to LDS, the column keeps its own in
+// registers, and plane s - 1 is updated (adj3_update) from the moments of
+// planes s - 2, s - 1 and s. The moments that never leave the block are not
+// stored; only the z-window moments of planes 1, 2, nz-3 and nz-2 go to the
+// scratch, for the end planes that alks3e<ENDS> updates afterwards.
+template <typename R, bool TH>
+struct AdjFLds {
+  static constexpr int NP = TH ? 5 : 4;  // rho~, Vx, Vy, Vz (, Theta)
+  static constexpr int NE = TH ? 9 : 5;  // s~xx s~xy s~xz s~yy s~yz (q~x q~y T B)
+  R p[4][NP][NSR];
+  R e[2][NE][NCR];
+};
+
+// node of a column at one plane: index, class, boundary count, T, B and
+// 1/(1 + alpha)
+template <typename R>
+struct ColIn {
+  unsigned k;
+  int m, ne, valid;
+  R T, B, ip;
+};
+
+template <typename R, bool TH>
+__global__ __launch_bounds__(ZT) void alks3f_kernel(Geo3 g, Adj3Args<R> a) {
+  constexpr int NP = AdjFLds<R, TH>::NP;
+  constexpr int NM = TH ? 14 : 10;
+  __shared__ AdjFLds<R, TH> L;
+  const int pz = g.periodic & 4;
+  ZTile t;
+  if (!ztile(g, t, pz ? 0 : 1, pz ? g.nz : g.nz - 1)) return;
+  const int tid = int(threadIdx.x), lx = tid % ZX, ly = tid / ZX;
+  const unsigned nxy = unsigned(g.nx) * unsigned(g.ny);
+  const size_t N = size_t(g.N);
+  int roff[SRL];
+  zregion(g, t, roff);
+  const ZNode n0 = znode(g, t, lx, ly, lx < t.w && ly < t.h);
+  const ZNode n1 = zring(g, t);
+  const bool own = n0.on && t.x0 + lx >= t.xo && t.y0 + ly >= t.yo;
+  const R* F[NP];
+#pragma unroll
+  for (int f = 0; f < NP; ++f) F[f] = a.p0[f];
+  // planes that exist (INT_MIN: none, to skip a column's inputs)
+  auto has = [&](int q) { return q != INT_MIN && (pz || (q >= 0 && q < g.nz)); };
+  const int base = t.z0 - 2;  // first plane held in the LDS slots
+  auto slot = [&](int q) { return (q - base) & 3; };
+  const int last = t.z1 + 1;  // last plane the pulls read
+  R v[SRL][NP];
+  auto load = [&](int q) {
+    zload<R, NP>(F, has(q), unsigned(zwrap(q, g.nz)) * nxy, roff, v);
+  };
+  auto store = [&](int q) { zstore<R, NP>(L.p[slot(q)], v); };
+  auto col_in = [&](const ZNode& n, int q, ColIn<R>& c) {
+    c.k = 0;
+    c.m = c.ne = c.valid = 0;
+    c.T = c.B = c.ip = R(0);
+    if (!n.on || n.off < 0 || !has(q)) return;
+    const int zq = zwrap(q, g.nz);
+    c.k = unsigned(zq) * nxy + unsigned(n.off);
+    c.valid = 1;
+    c.ne = (n.ex != 0) + (n.ey != 0) + (endof(zq, g.nz, pz) != 0);
+    c.m = a.mask[c.k];
+    if constexpr (TH) {
+      c.T = a.T[c.k];
+      c.B = a.B[c.k];
+    }
+    if (!a.exact && !c.ne) c.ip = a.inv1pa[c.k];
+  };
+  // moments of a column's node at plane q (all NM for the own column, the
+  // in-plane fields for a ring column)
+  auto moments = [&](const ZNode& n, const ColIn<R>& c, int q, bool all, R M[14]) {
+#pragma unroll
+    for (int i = 0; i < 14; ++i) M[i] = R(0);
+    if (!c.valid) return;
+    if (c.ne) {
+#pragma unroll
+      for (int i = 0; i < NM; ++i)
+        if (all || i == 4 || i == 5 || i == 6 || i == 7 || i == 8 || i == 11 || i == 12)
+          M[i] = a.m[size_t(i) * N + c.k];
+      return;
+    }
+    const int sl[3] = {slot(q - 1), slot(q), slot(q + 1)};
+    R f[19], gq[19];
+#pragma unroll
+    for (int d = 0; d < 19; ++d) {
+      const int o = n.lds + QX[d] + QY[d] * SX;
+      const int pl = sl[QZ[d] + 1];
+      R x = L.p[pl][0][o];
+      if (QX[d]) x += R(QX[d]) * L.p[pl][1][o];
+      if (QY[d]) x += R(QY[d]) * L.p[pl][2][o];
+      if (QZ[d]) x += R(QZ[d]) * L.p[pl][3][o];
+      f[d] = x;
+      gq[d] = TH ? L.p[pl][TH ? 4 : 0][o] : R(0);
+    }
+    mom19<R, TH>(f, gq, M);
+    adj_local<R, TH>(a, int(c.k), c.m, 0, c.T, a.exact ? R(1) : c.ip, M);
+  };
+  auto store_e = [&](const ZNode& n, const R M[14], const ColIn<R>& c, int sl) {
+    if (!n.on) return;
+    R(*E)[NCR] = L.e[sl];
+    E[0][n.ci] = M[4];
+    E[1][n.ci] = M[5];
+    E[2][n.ci] = M[6];
+    E[3][n.ci] = M[7];
+    E[4][n.ci] = M[8];
+    if constexpr (TH) {
+      E[TH ? 5 : 0][n.ci] = M[11];
+      E[TH ? 6 : 0][n.ci] = M[12];
+      E[TH ? 7 : 0][n.ci] = c.T;
+      E[TH ? 8 : 0][n.ci] = c.B;
+    }
+  };
+  // the own node's inputs of the update at plane q
+  auto upd_in = [&](int q, AdjIn<R>& u) {
+    u.r = u.Tt = u.dA = u.dB = R(0);
+    u.ip = R(1);
+    u.mk = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u.U[c] = u.u[c] = R(0);
+    if (!own || !has(q)) return;
+    const unsigned k = unsigned(zwrap(q, g.nz)) * nxy + unsigned(n0.off);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u.u[c] = a.u[c][k];
+    u.mk = a.mask[k];
+    if (a.exact) u.ip = a.inv1pa[k];
+    if (a.sens_mode) {
+      u.dA = a.dA3[k];
+      if constexpr (TH) u.dB = a.dB[k];
+    }
+  };
+  // the planes z0 - 2 .. z0 in the slots, z0 + 1 in flight
+  load(base);
+  store(base);
+  load(base + 1);
+  store(base + 1);
+  load(base + 2);
+  store(base + 2);
+  load(base + 3);
+  ColIn<R> c0, c1;
+  col_in(n0, t.z0 - 1, c0);
+  col_in(n1, t.z0 - 1, c1);
+  AdjIn<R> ucur, unext;
+  upd_in(INT_MIN, ucur);
+  R Mc[14];
+#pragma unroll
+  for (int i = 0; i < 14; ++i) Mc[i] = R(0);
+  R zm1[6], zc[6], zn[6];
+  const R z0v[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int f = 0; f < 6; ++f) zm1[f] = zc[f] = R(0);
+  for (int s = t.z0 - 1; s <= t.z1; ++s) {
+    lds_barrier();
+    if (s + 2 <= last) store(s + 2);
+    if (s + 3 <= last) load(s + 3);
+    ColIn<R> c0n, c1n;
+    col_in(n0, s + 1 <= t.z1 ? s + 1 : INT_MIN, c0n);
+    col_in(n1, s + 1 <= t.z1 ? s + 1 : INT_MIN, c1n);
+    upd_in(s >= t.z0 && s < t.z1 ? s : INT_MIN, unext);
+    R M[14];
+    {
+      R Mr[14];
+      moments(n1, c1, s, false, Mr);
+      store_e(n1, Mr, c1, s & 1);
+    }
+    moments(n0, c0, s, true, M);
+    store_e(n0, M, c0, s & 1);
+    zn[0] = M[6];
+    zn[1] = M[8];
+    zn[2] = M[9];
+    zn[3] = TH ? M[13] : R(0);
+    zn[4] = c0.T;
+    zn[5] = c0.B;
+    if (own && s - 1 >= t.z0) {
+      AdjIn<R> cu = ucur;
+      cu.r = Mc[0];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) cu.U[c] = Mc[1 + c];
+      cu.Tt = TH ? Mc[10] : R(0);
+      R zd[6];
+#pragma unroll
+      for (int f = 0; f < 6; ++f) zd[f] = dz3(0, zc[f], zm1[f], zn[f], R(0));
+      adj3_update<R, TH>(a, g, unsigned(zwrap(s - 1, g.nz)) * nxy + unsigned(n0.off),
+                         L.e[(s - 1) & 1], n0.ci, n0.ex, n0.ey, 0, cu, zd, zc, zm1, zn, z0v);
+    }
+    // the z-window moments next to the end planes, for alks3e<ENDS>
+    if (!pz && own && c0.valid && !c0.ne && s >= t.z0 && s < t.z1 &&
+        (s <= 2 || s >= g.nz - 3)) {
+      a.m[6 * N + c0.k] = M[6];
+      a.m[8 * N + c0.k] = M[8];
+      a.m[9 * N + c0.k] = M[9];
+      if constexpr (TH) a.m[13 * N + c0.k] = M[13];
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      zm1[f] = zc[f];
+      zc[f] = zn[f];
+    }
+#pragma unroll
+    for (int i = 0; i < 14; ++i) Mc[i] = M[i];
+    ucur = unext;
+    c0 = c0n;
+    c1 = c1n;
   }
 }
 
@@ -1194,11 +1446,11 @@ namespace {
 // planes per chunk so that tiles x chunks fills whole rounds of the kernel's
 // resident blocks (one round when the grid allows)
 template <typename K>
-int zplanes(const Geo3& g, K kernel) {
+int zplanes(const Geo3& g, K kernel, int nt = ZT) {
   int dev = 0, ncu = 0, bpc = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, kernel, ZT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, kernel, nt, 0) != hipSuccess ||
       ncu <= 0 || bpc <= 0)
     return 16;
   const int tiles = ztiles(g.nx, ZX) * ztiles(g.ny, ZY);
@@ -1215,10 +1467,14 @@ void zplan3(Geo3& g, int rsz) {
     g.zc = g.thermal ? zplanes(g, lks3z_kernel<double, true>) : zplanes(g, lks3z_kernel<double, false>);
     g.zca = g.thermal ? zplanes(g, alks3e_kernel<double, true>)
                       : zplanes(g, alks3e_kernel<double, false>);
+    g.zcf = g.thermal ? zplanes(g, alks3f_kernel<double, true>)
+                      : zplanes(g, alks3f_kernel<double, false>);
   } else {
     g.zc = g.thermal ? zplanes(g, lks3z_kernel<float, true>) : zplanes(g, lks3z_kernel<float, false>);
     g.zca = g.thermal ? zplanes(g, alks3e_kernel<float, true>)
                       : zplanes(g, alks3e_kernel<float, false>);
+    g.zcf = g.thermal ? zplanes(g, alks3f_kernel<float, true>)
+                      : zplanes(g, alks3f_kernel<float, false>);
   }
 }
 
@@ -1295,8 +1551,27 @@ void launch_lks3_step(const Geo3& g, const Fwd3Args<R>& a, hipStream_t s) {
   }
 }
 
+template <typename R, bool TH>
+void launch_alks3_fused(const Geo3& g0, const Adj3Args<R>& a, hipStream_t s) {
+  Geo3 g = g0;
+  g.zc = g0.zcf;
+  const unsigned nz = unsigned(NXCD * ((zblocks3(g) + NXCD - 1) / NXCD));
+  const unsigned nf = unsigned((a.nface + NT3 - 1) / NT3);
+  if (a.nface) alks3_face_kernel<R, TH><<<nf, NT3, 0, s>>>(g, a);
+  alks3f_kernel<R, TH><<<nz, ZT, 0, s>>>(g, a);
+  if (!(g.periodic & 4)) {
+    const int ends = 2 * ztiles(g.nx, ZX) * ztiles(g.ny, ZY);
+    alks3e_kernel<R, TH, true><<<unsigned(NXCD * ((ends + NXCD - 1) / NXCD)), ZT, 0, s>>>(g, a);
+  }
+}
+
 template <typename R>
 void launch_alks3_step(const Geo3& g0, const Adj3Args<R>& a, hipStream_t s) {
+  if (g0.fused) {
+    if (g0.thermal) launch_alks3_fused<R, true>(g0, a, s);
+    else launch_alks3_fused<R, false>(g0, a, s);
+    return;
+  }
   Geo3 g = g0;
   g.zc = g0.zca;
   const unsigned nb = unsigned(blocks3(g.N));

@@ -1151,7 +1151,8 @@ lks_status lks_create(const lks_grid* grid, const lks_phys* phys, const lks_bc* 
     g3.A = g.A;
     g3.Bf = g.Bf;
     g3.drho_out = g.drho_out;
-    g3.zc = g3.zca = 16;  // re-planned for the device at bind
+    g3.zc = g3.zca = g3.zcf = 16;  // re-planned for the device at bind
+    g3.fused = 1;
     lks::build_face_ops3(g3.A, g3.Bf, c->ops3);
     c->copy3h.resize(size_t(lks::copy_nodes3(g3, nullptr)));
     lks::copy_nodes3(g3, c->copy3h.data());
@@ -1578,6 +1579,14 @@ lks_status lks_set_steps_per_launch(lks_ctx* c, int forward_steps, int adjoint_s
   }
   c->spl_f = forward_steps;
   c->spl_a = adjoint_steps;
+  return LKS_OK;
+}
+
+lks_status lks_set_fused_adjoint(lks_ctx* c, int fused) {
+  if (!c) return LKS_E_INVALID;
+  if (c->dim != 3) return fail(c, LKS_E_UNSUPPORTED, "the fused ALKS step is a D3Q19 kernel");
+  if (fused != 0 && fused != 1) return fail(c, LKS_E_INVALID, "fused must be 0 or 1");
+  c->geo3.fused = fused;
   return LKS_OK;
 }
 

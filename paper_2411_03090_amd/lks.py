@@ -61,7 +61,8 @@ EXPORTED = ("lks_create", "lks_workspace_size", "lks_bind_workspace", "lks_forwa
             "lks_launch_shape", "lks_batch_set_tile_rows", "lks_set_adjoint_mode",
             "lks_set_checkpointing", "lks_checkpoint_info", "lks_gradient_status",
             "lks_bind_static_workspace", "lks_batch_set_memory_budget",
-            "lks_batch_set_adjoint_mode", "lks_batch_checkpoint_info")
+            "lks_batch_set_adjoint_mode", "lks_batch_checkpoint_info",
+            "lks_set_fused_adjoint")
 
 # LKS_STATIC_WORKSPACE_BYTES of lks.h
 STATIC_WORKSPACE_BYTES = 64 * 1024 * 1024
@@ -154,6 +155,8 @@ _lib.lks_launch_shape.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int)] * 3
 _lib.lks_launch_shape.restype = _st
 _lib.lks_set_adjoint_mode.argtypes = [_vp, ctypes.c_int]
 _lib.lks_set_adjoint_mode.restype = _st
+_lib.lks_set_fused_adjoint.argtypes = [_vp, ctypes.c_int]
+_lib.lks_set_fused_adjoint.restype = _st
 _lib.lks_set_checkpointing.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
 _lib.lks_set_checkpointing.restype = _st
 _lib.lks_checkpoint_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
@@ -323,6 +326,11 @@ class LKS:
         discrete Brinkman step); see lks_set_adjoint_mode."""
         code = {"paper": LKS_ADJ_PAPER, "exact": LKS_ADJ_EXACT}[mode]
         _check(_lib.lks_set_adjoint_mode(self.ctx, code), self.ctx)
+
+    def set_fused_adjoint(self, fused):
+        """D3Q19: the ALKS step as one z-marching kernel (True) or as the
+        pull, face and update passes (False); see lks_set_fused_adjoint."""
+        _check(_lib.lks_set_fused_adjoint(self.ctx, int(bool(fused))), self.ctx)
 
     def gradient_status(self):
         """Raise LKSError (LKS_E_DIVERGED) if the last forward state or
