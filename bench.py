@@ -657,9 +657,10 @@ def duct3d_bench(args, dev, shapes):
     c64 = lks.LKS(wl, precision="fp64", mem_budget=32 * 2 ** 30, device=dev)
     nodes = wl.nx * wl.ny * wl.nz
     res, grad16 = _checkpointed(c32, c64, g, nodes, n)
-    res["roofline"] = roofline("duct3d", "alks3_pull_kernel + alks3_face_kernel + alks3e_kernel"
-                               "<float, true> (one ALKS step)", ("3d_thermal", "adj_unsteady"),
-                               "float", nodes, res["fp32"]["adjoint_step_us"])
+    res["roofline"] = roofline("duct3d", "alks3_face_kernel + alks3f_kernel + alks3e_kernel"
+                               "<float, true> (one fused ALKS step)",
+                               ("3d_thermal", "adj_unsteady"), "float", nodes,
+                               res["fp32"]["adjoint_step_us"])
     res["roofline"]["note"] = "step duration estimated from the backward call less its replay"
     res["forward_roofline"] = roofline("duct3d", "lks3z_kernel + copy3_kernel<float, true> "
                                        "(one LKS step)", ("3d_thermal", "fwd"), "float", nodes,
