@@ -351,6 +351,8 @@ void launch_alks_step(const Geo& g, const AdjArgs<R>& a, hipStream_t s);
 // two steps per launch, FP32 non-thermal steady sweeps: forward n -> n+2
 // (level_mid = n+1, level_out = n+2), adjoint n+2 -> n with the level-n state
 void launch_lks_step2(const Geo& g, const FwdArgs<float>& a, hipStream_t s);
+// FP64 non-thermal forward, two steps per launch
+void launch_lks_step2(const Geo& g, const FwdArgs<double>& a, hipStream_t s);
 void launch_alks_step2(const Geo& g, const AdjArgs<float>& a, hipStream_t s);
 template <typename R>
 void launch_pressure_drop(const Geo& g, const uint8_t* mask, const R* d, double* out,

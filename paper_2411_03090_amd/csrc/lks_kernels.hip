@@ -1827,6 +1827,13 @@ void launch_lks_step2(const Geo& g, const FwdArgs<float>& a, hipStream_t s) {
     else lks_step2_kernel<float, false, 4><<<nb, NT2<false>, 0, s>>>(g, a);
   }
 }
+// FP64: the non-thermal forward step (its LDS, 79 KB at 64 x 4 and 106 KB at
+// 64 x 8, leaves room for one or two blocks per CU)
+void launch_lks_step2(const Geo& g, const FwdArgs<double>& a, hipStream_t s) {
+  const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
+  if (g.ty == 8) lks_step2_kernel<double, false, 8><<<nb, NT2<false>, 0, s>>>(g, a);
+  else lks_step2_kernel<double, false, 4><<<nb, NT2<false>, 0, s>>>(g, a);
+}
 void launch_alks_step2(const Geo& g, const AdjArgs<float>& a, hipStream_t s) {
   const unsigned nb = unsigned(xcd_blocks(g.ntx * g.nty));
   if (g.thermal) {

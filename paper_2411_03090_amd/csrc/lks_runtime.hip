@@ -660,11 +660,16 @@ struct Run {
     return a;
   }
 
-  // two time steps per launch: FP32 D2Q9 steady sweeps
-  // (two-step kernels exist for 64 x 4 and 64 x 8 tiles)
+  // two time steps per launch: FP32 D2Q9 steady sweeps, and the FP64
+  // non-thermal forward sweep (two-step kernels exist for 64 x 4 and 64 x 8
+  // tiles)
   bool two_step(int spl) const {
     return std::is_same<R, float>::value && c->dim == 2 && spl == 2 &&
            (c->geo.ty == 4 || c->geo.ty == 8);
+  }
+  bool two_step_fwd(int spl) const {
+    return two_step(spl) || (c->dim == 2 && spl == 2 && !c->phys.thermal &&
+                             (c->geo.ty == 4 || c->geo.ty == 8));
   }
 
   void coefficients(const double* gamma) {
@@ -778,18 +783,16 @@ struct Run {
 
   void advance(int steps) {
     int n = 0;
-    if constexpr (std::is_same<R, float>::value) {
-      if (two_step(c->spl_f)) {
-        for (; n + 2 <= steps; n += 2) {
-          R* in[5] = {};
-          R* out[5] = {};
-          for (int f = 0; f < nf; ++f) {
-            in[f] = rp<R>(c->S[c->cur][f]);
-            out[f] = rp<R>(c->S[c->cur ^ 1][f]);
-          }
-          lks::launch_lks_step2(g, fwd_args(in, out, c->last_level + n + 2, nullptr), c->stream);
-          c->cur ^= 1;
+    if (two_step_fwd(c->spl_f)) {
+      for (; n + 2 <= steps; n += 2) {
+        R* in[5] = {};
+        R* out[5] = {};
+        for (int f = 0; f < nf; ++f) {
+          in[f] = rp<R>(c->S[c->cur][f]);
+          out[f] = rp<R>(c->S[c->cur ^ 1][f]);
         }
+        lks::launch_lks_step2(g, fwd_args(in, out, c->last_level + n + 2, nullptr), c->stream);
+        c->cur ^= 1;
       }
     }
     for (; n < steps; ++n) {
@@ -1563,20 +1566,23 @@ lks_status lks_set_tile_rows(lks_ctx* c, int tile_rows) {
 lks_status lks_set_steps_per_launch(lks_ctx* c, int forward_steps, int adjoint_steps) {
   if (!c) return LKS_E_INVALID;
   if (c->lo) {
-    // mixed: the forward runs in FP64 (one step per launch), the adjoint in FP32
-    if (forward_steps != 1)
-      return fail(c, LKS_E_UNSUPPORTED, "the FP64 forward of a mixed context runs one step per launch");
+    // mixed: the forward runs in FP64, the adjoint in FP32
     lks_status st = lks_set_steps_per_launch(c->lo, 1, adjoint_steps);
     if (st != LKS_OK) return fail(c, st, c->lo->err);
-    c->spl_f = 1;
-    c->spl_a = 1;
-    return LKS_OK;
+    lks_ctx* lo = c->lo;
+    c->lo = nullptr;
+    st = lks_set_steps_per_launch(c, forward_steps, 1);
+    c->lo = lo;
+    return st;
   }
   for (int s : {forward_steps, adjoint_steps}) {
     if (s != 1 && s != 2) return fail(c, LKS_E_INVALID, "steps per launch must be 1 or 2");
-    if (s == 2 && (c->dim != 2 || c->rsz != 4))
-      return fail(c, LKS_E_UNSUPPORTED, "two steps per launch need an FP32 D2Q9 problem");
+    if (s == 2 && c->dim != 2)
+      return fail(c, LKS_E_UNSUPPORTED, "two steps per launch need a D2Q9 problem");
   }
+  if (c->rsz == 8 && ((forward_steps == 2 && c->phys.thermal) || adjoint_steps == 2))
+    return fail(c, LKS_E_UNSUPPORTED,
+                "FP64 sweeps run two steps per launch for the non-thermal forward only");
   c->spl_f = forward_steps;
   c->spl_a = adjoint_steps;
   return LKS_OK;
@@ -1666,9 +1672,11 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
   float best = 0.0f;
   int best_ty = c->geo.ty, best_f = c->spl_f, best_a = c->spl_a;
   const int mode = c->mode;
-  // two steps per launch exist for steady FP32 sweeps only; an unsteady
-  // context times (and keeps) one step per launch
-  const int nspl = (c->rsz == 4 && mode != LKS_UNSTEADY) ? 2 : 1;
+  // two steps per launch exist for steady FP32 sweeps and the FP64
+  // non-thermal forward; an unsteady context times (and keeps) one step per
+  // launch
+  const bool fwd2 = c->rsz == 4 || !c->phys.thermal;
+  const int nspl = (fwd2 && mode != LKS_UNSTEADY) ? 2 : 1;
   c->mode = LKS_STEADY;  // time plain steps on the ping-pong buffers
   for (int ty : TILE_ROWS) {
     if (!tile_rows_ok(ty, c->rsz, c->phys.thermal)) continue;
@@ -1698,7 +1706,7 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
     }
     if (st != LKS_OK) break;
     const int sf = (nspl_ty == 2 && tf[1] < tf[0]) ? 2 : 1;
-    const int sa = (nspl_ty == 2 && ta[1] < ta[0]) ? 2 : 1;
+    const int sa = (nspl_ty == 2 && c->rsz == 4 && ta[1] < ta[0]) ? 2 : 1;
     const float t = tf[sf - 1] + ta[sa - 1];
     if (best == 0.0f || t < best) {
       best = t;

@@ -230,8 +230,15 @@ def test_launch_shape_controls():
     with pytest.raises(lks.LKSError) as e:
         c.set_steps_per_launch(3)
     assert e.value.status == lks.LKS_E_INVALID
+    # FP64: two steps per launch for the non-thermal forward sweep only
+    c64 = _create(wl, "fp64")
+    c64.set_steps_per_launch(2, 1)
+    assert c64.launch_shape() == (8, 2, 1)
     with pytest.raises(lks.LKSError) as e:
-        _create(wl, "fp64").set_steps_per_launch(2)
+        c64.set_steps_per_launch(1, 2)
+    assert e.value.status == lks.LKS_E_UNSUPPORTED
+    with pytest.raises(lks.LKSError) as e:
+        _create(W.heat_exchanger(n=20, n_fwd=5, n_adj=5), "fp64").set_steps_per_launch(2, 1)
     assert e.value.status == lks.LKS_E_UNSUPPORTED
     # thermal FP32 D2Q9 problems take two steps per launch too; D3Q19 does not
     th = _create(W.heat_exchanger(n=20, n_fwd=5, n_adj=5), "fp32")

@@ -363,6 +363,34 @@ def test_two_steps_per_launch_give_the_same_bits(case, ty):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("ty", [4, 8])
+@pytest.mark.parametrize("case", ["channel_70x37", "periodic_67x13"])
+def test_fp64_two_step_forward_gives_the_same_bits(case, ty):
+    """The FP64 non-thermal forward with two steps per launch against one
+    step per launch, odd and even step counts (the adjoint one step per
+    launch in both)."""
+    say(f"[gpu] FP64 two-step forward {case} ty={ty}")
+    wl = CASES[case]()
+    for nf in (7, 12):
+        out = []
+        for spl in (1, 2):
+            ctx = lks.LKS(wl, precision="fp64", device=DEV)
+            ctx.set_tile_rows(ty)
+            ctx.set_steps_per_launch(spl, 1)
+            assert ctx.launch_shape() == (ty, spl, 1)
+            g = T(wl.gamma)
+            d = torch.empty_like(g)
+            ctx.forward(g, nf)
+            J = ctx.objective()
+            fields = [ctx.read(n).cpu().numpy() for n in ("drho", "ux", "uy")]
+            ctx.backward(0.7, d, 5)
+            torch.cuda.synchronize()
+            out.append((J, fields + [d.cpu().numpy()]))
+        assert out[0][0] == out[1][0]
+        for a, b in zip(out[0][1], out[1][1]):
+            assert np.array_equal(a, b)
+
+
 def _steady_exchanger(mode):
     """Steady heat exchanger (heat source on) on a 70 x 70 grid: ragged
     tiles, corners, flux and Dirichlet ends; paper or exact adjoint."""
