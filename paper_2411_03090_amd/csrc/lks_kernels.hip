@@ -149,7 +149,8 @@ __device__ inline double block_sum(double v, double* red) {
 // tiles of 8 rows; 256 otherwise (measured: the non-thermal 64 x 8 step on
 // large grids keeps more tiles in flight with 256)
 template <typename R, bool TH, int TY>
-constexpr int NT1 = (sizeof(R) == 4 && (TY == 16 || (TH && TY == 8))) ? 512 : NTHREADS;
+constexpr int NT1 =
+    (TY == 16 || (TY == 8 && (TH || sizeof(R) == 8))) ? 512 : NTHREADS;
 
 // ---------------------------------------------------------------------------
 // tiles
