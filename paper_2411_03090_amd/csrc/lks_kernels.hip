@@ -150,7 +150,7 @@ __device__ inline double block_sum(double v, double* red) {
 // large grids keeps more tiles in flight with 256)
 template <typename R, bool TH, int TY>
 constexpr int NT1 =
-    (TY == 16 || (TY == 8 && (TH || sizeof(R) == 8))) ? 512 : NTHREADS;
+    (TY == 16 || TY == 4 || (TY == 8 && (TH || sizeof(R) == 8))) ? 512 : NTHREADS;
 
 // ---------------------------------------------------------------------------
 // tiles
