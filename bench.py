@@ -407,7 +407,7 @@ def ubatch_bench(args, dev, shapes):
         tries = {ty: timed("fp32", 16 * 2 ** 30, ty, reps=1)[0]["ms_per_batch"] for ty in (4, 8)}
         ty32 = min(tries, key=tries.get)
     a, J32, s32 = timed("fp32", 16 * 2 ** 30, ty32, steps=True)
-    ty64 = int(sh["fp64"][0]) if "fp64" in sh else 4
+    ty64 = int(sh["fp64"][0]) if "fp64" in sh else 8
     c, J64, s64 = timed("fp64", 32 * 2 ** 30, ty64)
     res.update({"fp32": a, "fp64": c,
                 "speedup_fp32_vs_fp64": c["ms_per_batch"] / a["ms_per_batch"],

@@ -1076,9 +1076,12 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
     tw = TX;
     th = TY;
   }
-  // node-local inputs of stage B, loaded before the first barrier (full tiles)
+  // node-local inputs of stage B, loaded before the first barrier (full
+  // tiles), the accumulated sensitivity among them: its read-modify-write
+  // would otherwise wait for the load at the end of the tile
   constexpr int NB = FULL ? (TX * TY + NT - 1) / NT : 1;
   R spre[NB], uxpre[NB], uypre[NB];
+  double senspre[NB];
   if constexpr (FULL) {
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
@@ -1088,6 +1091,7 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
       spre[e] = a.inv1pa[k];
       uxpre[e] = a.ux[k];
       uypre[e] = a.uy[k];
+      senspre[e] = a.sens_mode == 1 ? a.sens[k] : 0.0;
     }
   }
 
@@ -1116,8 +1120,10 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
     __syncthreads();
   }
 
-  // the local terms, new coefficients and sensitivity of node (i, j)
-  auto local = [&](auto in, int lx, int ly, int i, int j, R s, R ux, R uy) {
+  // the local terms, new coefficients and sensitivity of node (i, j); sold
+  // is the node's accumulated sensitivity when `pre` (else it is read here)
+  auto local = [&](auto in, int lx, int ly, int i, int j, R s, R ux, R uy, bool pre,
+                   double sold) {
     const int k = j * g.nx + i;
     R r, Vx, Vy, Th;
     double v;
@@ -1128,17 +1134,19 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
     a.vx1[k] = Vx;
     a.vy1[k] = Vy;
     if constexpr (TH) a.th1[k] = Th;
-    if (a.sens_mode == 1) a.sens[k] += v;
+    if (a.sens_mode == 1) a.sens[k] = (pre ? sold : a.sens[k]) + v;
     else if (a.sens_mode == 2) a.sens[k] = v;
   };
   int e = 0;
   rect_loop<FULL, TX, TY, NT>(tw, th, [&](int lx, int ly) {
     const int i = x0 + lx, j = y0 + ly;
     R s, ux, uy;
+    double so = 0.0;
     if constexpr (FULL) {
       s = spre[e];
       ux = uxpre[e];
       uy = uypre[e];
+      so = senspre[e];
       ++e;
       if constexpr (EDGE)
         if (on_ring(g, i, j)) return;
@@ -1150,12 +1158,12 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
       ux = a.ux[k];
       uy = a.uy[k];
     }
-    local(BoolC<INT || EDGE>(), lx, ly, i, j, s, ux, uy);
+    local(BoolC<INT || EDGE>(), lx, ly, i, j, s, ux, uy, FULL, so);
   });
   if constexpr (EDGE)
     ring_loop<NT>(g, x0, y0, tw, th, [&](int i, int j) {
       const int k = j * g.nx + i;
-      local(BoolC<false>(), i - x0, j - y0, i, j, a.inv1pa[k], a.ux[k], a.uy[k]);
+      local(BoolC<false>(), i - x0, j - y0, i, j, a.inv1pa[k], a.ux[k], a.uy[k], false, 0.0);
     });
 }
 

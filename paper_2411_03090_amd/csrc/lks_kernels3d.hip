@@ -540,8 +540,8 @@ __device__ inline R pick3(int ax, R v0, R v1, R v2) {
 // closure on faces; edge and corner nodes are copied afterwards
 template <typename R, bool TH>
 __device__ inline void fwd3_out(const Geo3& g, const Fwd3Args<R>& a, unsigned k, int ex, int ey,
-                                int ez, int m, R s, R Tb, R rho, const R U[3], R Ts,
-                                const R Q[3], double& part) {
+                                int ez, int m, R s, R Tb, const R ubk[3], double fac, R rho,
+                                const R U[3], R Ts, const R Q[3], double& part) {
   const int ne = (ex != 0) + (ey != 0) + (ez != 0);
   if (ne >= 2) return;
   R d, u[3], T = R(0);
@@ -559,9 +559,8 @@ __device__ inline void fwd3_out(const Geo3& g, const Fwd3Args<R>& a, unsigned k,
     const R sn = rho + R(sg) * Un;  // S0 + 2 S+ over the received directions
     R un;
     if ((m & 3) == FLOW_VELOCITY3) {
-      const double fac = a.ufac[a.level_out];
 #pragma unroll
-      for (int x = 0; x < 3; ++x) u[x] = R(double(a.ub[x][k]) * fac);
+      for (int x = 0; x < 3; ++x) u[x] = R(double(ubk[x]) * fac);
       un = R(sg) * pick3(ax, u[0], u[1], u[2]);
       d = sn - un;
     } else {
@@ -629,8 +628,12 @@ __global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
   }
   // per-node inputs one iteration ahead: drho and B of the source nodes,
   // class, Brinkman factor and prescribed temperature of the output node
-  auto node_in = [&](int s, R& d0, R& d1_, R& b0, R& b1, int& mk, R& ip, R& tb) {
+  // the prescribed velocity of a velocity face node is read with the rest,
+  // a plane ahead, and the level's inflow factor once
+  const double fac = a.ufac[a.level_out];
+  auto node_in = [&](int s, R& d0, R& d1_, R& b0, R& b1, int& mk, R& ip, R& tb, R ub[3]) {
     d0 = d1_ = b0 = b1 = ip = tb = R(0);
+    ub[0] = ub[1] = ub[2] = R(0);
     mk = 0;
     if (!has(s)) return;
     const unsigned base = unsigned(zwrap(s, g.nz)) * nxy;
@@ -648,11 +651,14 @@ __global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
       mk = a.mask[k];
       ip = a.inv1pa[k];
       if constexpr (TH) tb = a.Tb[k];
+      if (n0.ex || n0.ey || endof(p, g.nz, pz))  // a face node (not waiting for its class)
+#pragma unroll
+        for (int x = 0; x < 3; ++x) ub[x] = a.ub[x][k];
     }
   };
-  R dd0, dd1, b0, b1, ip, tb;
+  R dd0, dd1, b0, b1, ip, tb, ub[3];
   int mk;
-  node_in(sb, dd0, dd1, b0, b1, mk, ip, tb);
+  node_in(sb, dd0, dd1, b0, b1, mk, ip, tb, ub);
   FwdAcc<R, TH> A = {};
   double part = 0.0;
   for (int s = sb; s <= se; ++s) {
@@ -662,8 +668,9 @@ __global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
     lds_barrier();
     if (has(s + 2)) zload<R, NF>(F, true, unsigned(zwrap(s + 2, g.nz)) * nxy, roff, v);
     const R cd0 = dd0, cd1 = dd1, cb0 = b0, cb1 = b1, cip = ip, ctb = tb;
+    const R cub[3] = {ub[0], ub[1], ub[2]};
     const int cmk = mk;
-    if (s + 1 <= se) node_in(s + 1, dd0, dd1, b0, b1, mk, ip, tb);
+    if (s + 1 <= se) node_in(s + 1, dd0, dd1, b0, b1, mk, ip, tb, ub);
     const int sw = zwrap(s, g.nz);
     fwd_src<R, TH, true>(g, a, L, t, n0, cur, nxt, hn, sw, nxy, cd0, cb0, zp0, A);
     fwd_src<R, TH, false>(g, a, L, t, n1, cur, nxt, hn, sw, nxy, cd1, cb1, zp1, A);
@@ -690,13 +697,15 @@ __global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
     const int p = s - 1;
     if (own && p >= t.z0 && p < t.z1)
       fwd3_out<R, TH>(g, a, unsigned(p) * nxy + unsigned(n0.off), n0.ex, n0.ey,
-                      endof(p, g.nz, pz), cmk, cip, ctb, A.r[0], A.U[0], A.T[0], A.Q[0], part);
+                      endof(p, g.nz, pz), cmk, cip, ctb, cub, fac, A.r[0], A.U[0], A.T[0],
+                      A.Q[0], part);
     facc_shift(A);
   }
   if (!pz && se == g.nz - 1 && own) {
     const unsigned k = unsigned(g.nz - 1) * nxy + unsigned(n0.off);
-    fwd3_out<R, TH>(g, a, k, n0.ex, n0.ey, 1, a.mask[k], a.inv1pa[k], TH ? a.Tb[k] : R(0),
-                    A.r[0], A.U[0], A.T[0], A.Q[0], part);
+    const R ubk[3] = {a.ub[0][k], a.ub[1][k], a.ub[2][k]};
+    fwd3_out<R, TH>(g, a, k, n0.ex, n0.ey, 1, a.mask[k], a.inv1pa[k], TH ? a.Tb[k] : R(0), ubk,
+                    fac, A.r[0], A.U[0], A.T[0], A.Q[0], part);
   }
   if (a.acc) {
     const double s = block_sum3(part, L.red);
@@ -857,10 +866,10 @@ __device__ void face_fill(const Adj3Args<R>& a, int k, int m, int o, R Tn, const
 // temperature inside, the T q~ coupling and the Brinkman factor of u~
 template <typename R, bool TH>
 __device__ inline void adj_local(const Adj3Args<R>& a, int k, int m, int ne, R Tn, R s,
-                                 R M[14]) {
+                                 R M[14], R u0) {
   if constexpr (TH) {
     const bool probe = (m & TAG_PROBE3) && a.seed_heat != 0.0;
-    if (probe) M[10] -= R(a.seed_heat) * a.u[0][k];
+    if (probe) M[10] -= R(a.seed_heat) * u0;
     // a prescribed temperature does not depend on the arriving populations:
     // zero thermal adjoint inside (both modes) and on faces (exact mode)
     if (((m >> 2) & 3) == THERM_DIRICHLET3 && (!ne || a.exact)) {
@@ -905,7 +914,8 @@ __device__ void alks3_node(const Geo3& g, const Adj3Args<R>& a, P3 p, int k, int
   if constexpr (FACE)
     if (ne) face_fill<R, TH>(a, k, m, o, Tn, f, gq, M);
   // exact mode: u~ stays undivided; the update pass divides V instead
-  adj_local<R, TH>(a, k, m, ne, Tn, a.exact ? R(1) : a.inv1pa[k], M);
+  const bool probe = TH && (m & TAG_PROBE3) && a.seed_heat != 0.0;
+  adj_local<R, TH>(a, k, m, ne, Tn, a.exact ? R(1) : a.inv1pa[k], M, probe ? a.u[0][k] : R(0));
 }
 
 // ALKS pass 1 at the interior nodes; the boundary nodes are left to
@@ -974,6 +984,7 @@ template <typename R>
 struct AdjIn {
   R r, U[3], Tt, u[3], dA, dB, ip;
   int mk;
+  double so;  // the node's accumulated sensitivity (sens_mode 1), read ahead
 };
 
 // The ALKS update at node k of a z-march column (eq:afp - eq:agq): V and
@@ -1051,7 +1062,9 @@ __device__ inline void adj3_update(const Adj3Args<R>& a, const Geo3& g, unsigned
         sv -= double(cu.dB) * gq;
       }
     }
-    if (a.sens_mode == 1) a.sens[k] += sv;
+    // the accumulated value was read with the node's other inputs, a plane
+    // ahead, so that the read-modify-write does not wait for it here
+    if (a.sens_mode == 1) a.sens[k] = cu.so + sv;
     else a.sens[k] = sv;
   }
 }
@@ -1138,6 +1151,7 @@ __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
     q.r = q.Tt = q.dA = q.dB = R(0);
     q.ip = R(1);
     q.mk = 0;
+    q.so = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) q.U[c] = q.u[c] = R(0);
     if (!own || p >= t.z1) return;
@@ -1154,6 +1168,7 @@ __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
     if (a.sens_mode) {
       q.dA = a.dA3[k];
       if constexpr (TH) q.dB = a.dB[k];
+      if (a.sens_mode == 1) q.so = a.sens[k];
     }
   };
   load(t.z0);
@@ -1273,17 +1288,31 @@ __global__ __launch_bounds__(ZT) void alks3f_kernel(Geo3 g, Adj3Args<R> a) {
     }
     if (!a.exact && !c.ne) c.ip = a.inv1pa[c.k];
   };
-  // moments of a column's node at plane q (all NM for the own column, the
-  // in-plane fields for a ring column)
-  auto moments = [&](const ZNode& n, const ColIn<R>& c, int q, bool all, R M[14]) {
+  // the face pass's moments of a boundary node (all NM for the own column,
+  // the in-plane fields for a ring column) and the probe's velocity, read at
+  // the top of the plane so that their latency hides behind the pulls
+  auto bnd_in = [&](const ColIn<R>& c, bool all, R Mb[14], R& u0) {
 #pragma unroll
-    for (int i = 0; i < 14; ++i) M[i] = R(0);
+    for (int i = 0; i < 14; ++i) Mb[i] = R(0);
+    u0 = R(0);
     if (!c.valid) return;
     if (c.ne) {
 #pragma unroll
       for (int i = 0; i < NM; ++i)
         if (all || i == 4 || i == 5 || i == 6 || i == 7 || i == 8 || i == 11 || i == 12)
-          M[i] = a.m[size_t(i) * N + c.k];
+          Mb[i] = a.m[size_t(i) * N + c.k];
+    } else if (TH && (c.m & TAG_PROBE3) && a.seed_heat != 0.0) {
+      u0 = a.u[0][c.k];
+    }
+  };
+  // moments of a column's node at plane q
+  auto moments = [&](const ZNode& n, const ColIn<R>& c, int q, const R Mb[14], R u0, R M[14]) {
+#pragma unroll
+    for (int i = 0; i < 14; ++i) M[i] = R(0);
+    if (!c.valid) return;
+    if (c.ne) {
+#pragma unroll
+      for (int i = 0; i < 14; ++i) M[i] = Mb[i];
       return;
     }
     const int sl[3] = {slot(q - 1), slot(q), slot(q + 1)};
@@ -1300,7 +1329,7 @@ __global__ __launch_bounds__(ZT) void alks3f_kernel(Geo3 g, Adj3Args<R> a) {
       gq[d] = TH ? L.p[pl][TH ? 4 : 0][o] : R(0);
     }
     mom19<R, TH>(f, gq, M);
-    adj_local<R, TH>(a, int(c.k), c.m, 0, c.T, a.exact ? R(1) : c.ip, M);
+    adj_local<R, TH>(a, int(c.k), c.m, 0, c.T, a.exact ? R(1) : c.ip, M, u0);
   };
   auto store_e = [&](const ZNode& n, const R M[14], const ColIn<R>& c, int sl) {
     if (!n.on) return;
@@ -1322,6 +1351,7 @@ __global__ __launch_bounds__(ZT) void alks3f_kernel(Geo3 g, Adj3Args<R> a) {
     u.r = u.Tt = u.dA = u.dB = R(0);
     u.ip = R(1);
     u.mk = 0;
+    u.so = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) u.U[c] = u.u[c] = R(0);
     if (!own || !has(q)) return;
@@ -1333,6 +1363,7 @@ __global__ __launch_bounds__(ZT) void alks3f_kernel(Geo3 g, Adj3Args<R> a) {
     if (a.sens_mode) {
       u.dA = a.dA3[k];
       if constexpr (TH) u.dB = a.dB[k];
+      if (a.sens_mode == 1) u.so = a.sens[k];
     }
   };
   // the planes z0 - 2 .. z0 in the slots, z0 + 1 in flight
@@ -1363,13 +1394,18 @@ __global__ __launch_bounds__(ZT) void alks3f_kernel(Geo3 g, Adj3Args<R> a) {
     col_in(n0, s + 1 <= t.z1 ? s + 1 : INT_MIN, c0n);
     col_in(n1, s + 1 <= t.z1 ? s + 1 : INT_MIN, c1n);
     upd_in(s >= t.z0 && s < t.z1 ? s : INT_MIN, unext);
-    R M[14];
+    // (in FP64 the own column's reads wait until the ring column is done:
+    // held across its pulls they cost more registers than they save)
+    R M[14], Mb0[14], u00;
+    if constexpr (sizeof(R) == 4) bnd_in(c0, true, Mb0, u00);
     {
-      R Mr[14];
-      moments(n1, c1, s, false, Mr);
+      R Mr[14], Mb1[14], u01;
+      bnd_in(c1, false, Mb1, u01);
+      moments(n1, c1, s, Mb1, u01, Mr);
       store_e(n1, Mr, c1, s & 1);
     }
-    moments(n0, c0, s, true, M);
+    if constexpr (sizeof(R) != 4) bnd_in(c0, true, Mb0, u00);
+    moments(n0, c0, s, Mb0, u00, M);
     store_e(n0, M, c0, s & 1);
     zn[0] = M[6];
     zn[1] = M[8];
