@@ -324,13 +324,27 @@ __device__ inline void zregion(const Geo3& g, const ZTile& t, int off[SRL]) {
 
 // one plane of NF fields over the thread's region elements (zero where the
 // plane or the node does not exist)
-template <typename R, int NF>
+// (SEL: elements off the domain or of a missing plane load the field's first
+// node and keep zero, with no per-element branches; the LKS step gains by it,
+// the ALKS march, whose loads wait longer, does not)
+template <typename R, int NF, bool SEL = false>
 __device__ inline void zload(const R* const F[NF], bool exists, unsigned base, const int off[SRL],
                              R v[SRL][NF]) {
 #pragma unroll
-  for (int r = 0; r < SRL; ++r)
+  for (int r = 0; r < SRL; ++r) {
+    const bool in = exists && off[r] >= 0;
+    if constexpr (SEL) {
+      const unsigned o = in ? base + unsigned(off[r]) : 0u;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) v[r][f] = (exists && off[r] >= 0) ? F[f][base + unsigned(off[r])] : R(0);
+      for (int f = 0; f < NF; ++f) {
+        const R x = F[f][o];
+        v[r][f] = in ? x : R(0);
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) v[r][f] = in ? F[f][base + unsigned(off[r])] : R(0);
+    }
+  }
 }
 template <typename R, int NF>
 __device__ inline void zstore(R (*dst)[NSR], const R v[SRL][NF]) {
@@ -613,10 +627,10 @@ __global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
 #pragma unroll
   for (int f = 0; f < NF; ++f) F[f] = a.s0[1 + f];
   R v[SRL][NF];
-  zload<R, NF>(F, true, unsigned(zwrap(sb, g.nz)) * nxy, roff, v);
+  zload<R, NF, true>(F, true, unsigned(zwrap(sb, g.nz)) * nxy, roff, v);
   zstore<R, NF>(L.st[0], v);
   auto has = [&](int s) { return pz || (s >= 0 && s < g.nz); };
-  if (has(sb + 1)) zload<R, NF>(F, true, unsigned(zwrap(sb + 1, g.nz)) * nxy, roff, v);
+  if (has(sb + 1)) zload<R, NF, true>(F, true, unsigned(zwrap(sb + 1, g.nz)) * nxy, roff, v);
   R zp0[4] = {R(0), R(0), R(0), R(0)}, zp1[4] = {R(0), R(0), R(0), R(0)};
   if (has(sb - 1)) {
     const unsigned b = unsigned(zwrap(sb - 1, g.nz)) * nxy;
@@ -666,7 +680,7 @@ __global__ __launch_bounds__(ZT) void lks3z_kernel(Geo3 g, Fwd3Args<R> a) {
     const bool hn = has(s + 1);
     if (hn) zstore<R, NF>(L.st[nxt], v);
     lds_barrier();
-    if (has(s + 2)) zload<R, NF>(F, true, unsigned(zwrap(s + 2, g.nz)) * nxy, roff, v);
+    if (has(s + 2)) zload<R, NF, true>(F, true, unsigned(zwrap(s + 2, g.nz)) * nxy, roff, v);
     const R cd0 = dd0, cd1 = dd1, cb0 = b0, cb1 = b1, cip = ip, ctb = tb;
     const R cub[3] = {ub[0], ub[1], ub[2]};
     const int cmk = mk;
