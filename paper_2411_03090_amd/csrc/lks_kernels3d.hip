@@ -297,13 +297,16 @@ __device__ inline ZNode zring_at(const Geo3& g, const ZTile& t, int r) {
   const bool on = r >= 0 && r < 2 * a + 2 * t.h;
   return znode(g, t, on ? dx : 0, on ? dy : 0, on);
 }
-// the thread's ring column: each wave takes a quarter of the ring in
-// consecutive positions, so the ring work is spread evenly over the SIMDs
-// and neighbouring lanes touch neighbouring LDS words
+// the thread's ring column: three of the four waves take a third of the ring
+// each, in consecutive positions (neighbouring lanes touch neighbouring LDS
+// words); the wave left out rotates with the block, so that over the blocks
+// resident on a CU the ring work is spread evenly over the SIMDs, and a wave
+// runs the ring code only where it holds ring columns
 __device__ inline ZNode zring(const Geo3& g, const ZTile& t) {
-  const int per = (2 * (t.w + 2) + 2 * t.h + 3) / 4;  // at most 35 for 64 x 4 tiles
+  const int per = (2 * (t.w + 2) + 2 * t.h + 2) / 3;  // at most 47 for 64 x 4 tiles
   const int lane = int(threadIdx.x) % 64, w = int(threadIdx.x) / 64;
-  return zring_at(g, t, lane < per ? w * per + lane : -1);
+  const int k = (w - (t.lb & 3) + 4) & 3;  // 0: the wave without ring columns
+  return zring_at(g, t, (k > 0 && lane < per) ? (k - 1) * per + lane : -1);
 }
 
 // in-plane offsets of the thread's elements of the 2-node halo region; -1
