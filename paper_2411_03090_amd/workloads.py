@@ -524,20 +524,20 @@ def gamma_grf3(nx, ny, nz, sigma, seed):
 
 def heated_block_duct(nx=256, ny=128, nz=128, Re=100.0, Pr=0.71, sigma=6.0, seed=0,
                       n_steps=5000, nu=0.1, block=((0.25, 0.375), (0.0, 0.25),
-                                                    (0.375, 0.625))):
+                                                    (0.375, 0.625)), probe_col=None):
     """Unsteady forced convection in a duct past a heated solid block (the
     256x128x128, Re=100, Pr=0.71, 5000-step case at its defaults): inflow at
     T=0 with the duct profile, started from rest; the block, given as
     fractions of the domain along x, y, z (x in [64,96), y in [0,32),
     z in [48,80) at full size, resting on the y=0 wall), is a non-design solid
     (gamma = 0) held at T = 1; objective is the time-averaged enthalpy flux
-    through the plane x = nx-2."""
+    through the plane x = nx-2 (x = probe_col when given)."""
     H = ny - 1
     u_max = Re * nu / H
     if u_max > 0.1:
         u_max = 0.1
         nu = u_max * H / Re
-    m = duct_mask3(nx, ny, nz, probe_col=nx - 2)
+    m = duct_mask3(nx, ny, nz, probe_col=nx - 2 if probe_col is None else probe_col)
     ubar = np.zeros((3, nz, ny, nx))
     ubar[0, 1:-1, 1:-1, 0] = duct_inflow3(ny, nz, u_max)[1:-1, 1:-1]
     Tbar = np.zeros((nz, ny, nx))

@@ -144,6 +144,21 @@ def test_batch_64_full_horizon(precision, tol):
         _close(outs[d].cpu().numpy()[rec["sens_nodes"]], rec["sens"], tol)
 
 
+@pytest.mark.parametrize("precision,budget", [("fp64", 8 * 2 ** 30), ("fp32", 4 * 2 ** 30)])
+def test_duct3d_full_size_200_steps(precision, budget):
+    """The full-size duct over 200 steps, checkpointed, with the enthalpy-flux
+    plane at x = 60, which the inflow and the block's heat reach in that time."""
+    say(f"[gpu] D3Q19 duct 256x128x128, 200 steps, probe plane x = 60, {precision}, checkpointed")
+    gold = _golden("duct3d_200")
+    wl = W.heated_block_duct(n_steps=200, probe_col=60)
+    J, sens, fields = _gradient(wl, precision, None, budget)
+    assert gold["J"] > 0
+    if precision == "fp64":
+        _check(gold, J, sens, fields, 1e-12, 1e-12, 1e-12)
+    else:
+        _check(gold, J, sens, fields, 1e-3, 1e-3, 2e-5)
+
+
 @pytest.mark.parametrize("precision,budget", [("fp64", 32 * 2 ** 30), ("fp32", 16 * 2 ** 30)])
 def test_duct3d_full_horizon(precision, budget):
     say(f"[gpu] full horizon D3Q19 duct 256x128x128 5000 steps {precision}, checkpointed")
