@@ -283,14 +283,18 @@ lks_status lks_autotune(lks_ctx *ctx, const double *gamma_dev, int steps, int *t
  * with 16 every launch runs one step. */
 lks_status lks_set_tile_rows(lks_ctx *ctx, int tile_rows);
 
-/* Time steps per kernel launch of the steady sweeps, forward (lks_advance
- * and the steady lks_forward) and adjoint (steady alks_backward,
- * alks_advance): 1, or 2 for FP32 D2Q9 problems and for the forward sweep of
- * FP64 non-thermal D2Q9 problems (LKS_E_UNSUPPORTED otherwise; a MIXED
- * context applies forward_steps to its FP64 forward and adjoint_steps to its
- * FP32 adjoint). With 2, each launch loads its tile with a 4-node halo and
- * runs two steps, the first on the tile and a 2-node halo kept in LDS; the
- * results are bitwise those of one step per launch. */
+/* Time steps per kernel launch, forward (lks_advance, lks_forward, and the
+ * checkpoint replays of an unsteady alks_backward) and adjoint (steady
+ * alks_backward, alks_advance; an unsteady adjoint sweep runs one step per
+ * launch): 1, or 2 for FP32 D2Q9 problems and for the forward sweep of FP64
+ * non-thermal D2Q9 problems (LKS_E_UNSUPPORTED otherwise; a MIXED context
+ * applies forward_steps to its FP64 forward and adjoint_steps to its FP32
+ * adjoint). With 2, each launch loads its tile with a 4-node halo and runs
+ * two steps, the first on the tile and a 2-node halo kept in LDS; an unsteady
+ * sweep stores from there what a checkpoint or replay slot keeps of the level
+ * between. The states are bitwise those of one step per launch; an unsteady
+ * objective sums the same terms per tile and level, in another order within
+ * a tile. */
 lks_status lks_set_steps_per_launch(lks_ctx *ctx, int forward_steps, int adjoint_steps);
 
 /* Adjoint formulation used by alks_backward and alks_advance.

@@ -132,6 +132,12 @@ struct FwdArgs {
   double* acc;  // per-tile objective accumulator, or nullptr
   int objective;
   const R* beta = nullptr;  // heat-source coefficient beta_gamma, or nullptr
+  // two-step launches: where the first step's level is kept (fields left
+  // null are not written; all null when the level is not kept)
+  R* dm = nullptr;
+  R* uxm = nullptr;
+  R* uym = nullptr;
+  R* Tm = nullptr;
 };
 
 template <typename R>

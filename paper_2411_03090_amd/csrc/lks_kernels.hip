@@ -576,6 +576,23 @@ __device__ inline void corner_from(const Geo& g, int i, int j, Put&& put) {
   if (j == g.ny - 2) put(g.ny - 1);
 }
 
+// the objective's term of node k with class m at a new level (pressure drop,
+// probe enthalpy flux, heat exchange or heated-node temperature)
+template <typename R, bool TH>
+__device__ inline void obj_add(const FwdArgs<R>& a, int m, int k, R dn, R uxn, R Tn,
+                               double& part) {
+  if (a.objective == 1) {
+    if (m & TAG_PROBE) part += double(uxn) * double(Tn);
+  } else if (a.objective == 2) {
+    if constexpr (TH) part += double(a.beta[k]) * (double(Tn) - 1.0);
+  } else if (a.objective == 3) {
+    if (m & TAG_PROBE) part += double(Tn);
+  } else {
+    if (m & TAG_J_INLET) part += double(dn);
+    if (m & TAG_J_OUTLET) part -= double(dn);
+  }
+}
+
 template <typename R, bool TH, int TY, bool FULL, int KIND, int NT = NT1<R, TH, TY>>
 __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L, int x0, int y0,
                          int tw, int th, int tile) {
@@ -643,18 +660,7 @@ __device__ void lks_tile(const Geo& g, const FwdArgs<R>& a, FwdLds<R, TH, TY>& L
     a.ux1[k] = uxn;
     a.uy1[k] = uyn;
     if constexpr (TH) a.T1[k] = Tn;
-    if (a.acc) {
-      if (a.objective == 1) {
-        if (m & TAG_PROBE) part += double(uxn) * double(Tn);
-      } else if (a.objective == 2) {
-        if constexpr (TH) part += double(a.beta[k]) * (double(Tn) - 1.0);
-      } else if (a.objective == 3) {
-        if (m & TAG_PROBE) part += double(Tn);
-      } else {
-        if (m & TAG_J_INLET) part += double(dn);
-        if (m & TAG_J_OUTLET) part -= double(dn);
-      }
-    }
+    if (a.acc) obj_add<R, TH>(a, m, k, dn, uxn, Tn, part);
   };
   int e = 0;
   rect_loop<FULL, TX, TY, NT>(tw, th, [&](int lx, int ly) {
@@ -1196,11 +1202,10 @@ __global__ __launch_bounds__((NT1<R, TH, TY>)) void alks_step_kernel(Geo g, AdjA
 // round trips per step halve, the stage work grows by the halo (about 1.3x
 // for 64 x 8 tiles).
 // threads of a two-step block: the stages walk tile + 3, + 2 and + 1 regions of
-// up to 3.4x the tile's nodes, so a non-thermal block of 512 threads (8 waves)
-// keeps each stage to one or two passes; the thermal adjoint would spill
-// registers at 512 and keeps 256
+// up to 3.4x the tile's nodes, so a block of 512 threads (8 waves) keeps each
+// stage to one or two passes
 template <bool TH>
-constexpr int NT2 = TH ? NTHREADS : 512;
+constexpr int NT2 = 512;
 
 template <typename R, bool TH, int TY>
 struct Fwd2Lds {
@@ -1214,11 +1219,12 @@ struct Fwd2Lds {
   // T of the intermediate level: the first pull rewrites drho and u in place
   // but still reads the sources' T, so the new T goes beside it
   R T2[TH ? WR * HR : 1];
+  double red[8];
 };
 
 template <typename R, bool TH, int TY, bool FULL, int KIND, int NT>
-__device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>& L, int x0,
-                          int y0, int tw, int th) {
+__device__ __forceinline__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>& L, int x0,
+                          int y0, int tw, int th, int tile) {
   using LD = Fwd2Lds<R, TH, TY>;
   constexpr int WR = LD::WR, WF = LD::WF, SF = LD::SF;
   constexpr bool INT = KIND == K_INT, EDGE = KIND == K_EDGE;
@@ -1283,6 +1289,39 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
     if constexpr (TH) L.T2[pr] = Tn;
   });
   __syncthreads();
+  // the first step's level on the tile: kept where wanted (corner nodes
+  // included), and its objective term (corner nodes excluded, as in the pull)
+  if (a.uxm || a.acc) {
+    double pm = 0.0;
+    auto mid = [&](int lx, int ly, int i, int j) {
+      const int k = j * g.nx + i;
+      const int pr = (ly + 4) * WR + lx + 4;  // tile position in the tile + 4 region
+      const R dn = L.d[pr], uxn = L.u[pr], uyn = L.v[pr];
+      const R Tn = TH ? L.T2[pr] : R(0);
+      if (a.uxm) {
+        if (a.dm) a.dm[k] = dn;
+        a.uxm[k] = uxn;
+        a.uym[k] = uyn;
+        if constexpr (TH) a.Tm[k] = Tn;
+      }
+      if (a.acc) {
+        const int m = a.mask[k];
+        if (g.periodic || (m & 3) != FLOW_CORNER) obj_add<R, TH>(a, m, k, dn, uxn, Tn, pm);
+      }
+    };
+    rect_loop<FULL, TX, TY, NT>(tw, th, [&](int lx, int ly) {
+      const int i = x0 + lx, j = y0 + ly;
+      if constexpr (EDGE)
+        if (on_ring(g, i, j)) return;
+      mid(lx, ly, i, j);
+    });
+    if constexpr (EDGE)
+      ring_loop<NT>(g, x0, y0, tw, th, [&](int i, int j) { mid(i - x0, j - y0, i, j); });
+    if (a.acc) {
+      const double sm = block_sum<NT>(pm, L.red);
+      if (threadIdx.x == 0) a.acc[tile] += sm;
+    }
+  }
   // second step: collide on the tile + 1, pull on the tile into HBM
   region_walk<KIND, FULL, TX + 2, TY + 2, NT>(g, x0, y0, 1, tw + 2, th + 2,
                                           [&](auto in, int lx, int ly, int i, int j) {
@@ -1291,6 +1330,7 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
                                                     (ly + 2) * WF + lx + 2);
   });
   __syncthreads();
+  double part = 0.0;
   auto pull = [&](auto in, int lx, int ly, int i, int j, int m, R s) {
     constexpr bool I = decltype(in)::value;
     const int k = j * g.nx + i;
@@ -1311,6 +1351,7 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
     a.ux1[k] = uxn;
     a.uy1[k] = uyn;
     if constexpr (TH) a.T1[k] = Tn;
+    if (a.acc) obj_add<R, TH>(a, m, k, dn, uxn, Tn, part);
   };
   int e = 0;
   rect_loop<FULL, TX, TY, NT>(tw, th, [&](int lx, int ly) {
@@ -1337,6 +1378,10 @@ __device__ void lks_tile2(const Geo& g, const FwdArgs<R>& a, Fwd2Lds<R, TH, TY>&
       const int k = j * g.nx + i;
       pull(BoolC<false>(), i - x0, j - y0, i, j, int(a.mask[k]), a.inv1pa[k]);
     });
+  if (a.acc) {
+    const double s = block_sum<NT>(part, L.red);
+    if (threadIdx.x == 0) a.acc[tile] += s;
+  }
 }
 
 template <typename R, bool TH, int TY>
@@ -1346,14 +1391,14 @@ __global__ __launch_bounds__(NT2<TH>) void lks_step2_kernel(Geo g, FwdArgs<R> a)
   if (!block_tile(g, &x0, &x1, &y0, &y1, &tile)) return;
   const int tw = x1 - x0, th = y1 - y0;
   if (tw != TX || th != TY) {
-    if (g.periodic) lks_tile2<R, TH, TY, false, K_GEN, NT2<TH>>(g, a, L, x0, y0, tw, th);
-    else lks_tile2<R, TH, TY, false, K_EDGE, NT2<TH>>(g, a, L, x0, y0, tw, th);
+    if (g.periodic) lks_tile2<R, TH, TY, false, K_GEN, NT2<TH>>(g, a, L, x0, y0, tw, th, tile);
+    else lks_tile2<R, TH, TY, false, K_EDGE, NT2<TH>>(g, a, L, x0, y0, tw, th, tile);
   } else if (interior_tile2(g, x0, x1, y0, y1)) {
-    lks_tile2<R, TH, TY, true, K_INT, NT2<TH>>(g, a, L, x0, y0, tw, th);
+    lks_tile2<R, TH, TY, true, K_INT, NT2<TH>>(g, a, L, x0, y0, tw, th, tile);
   } else if (g.periodic) {
-    lks_tile2<R, TH, TY, false, K_GEN, NT2<TH>>(g, a, L, x0, y0, tw, th);
+    lks_tile2<R, TH, TY, false, K_GEN, NT2<TH>>(g, a, L, x0, y0, tw, th, tile);
   } else {
-    lks_tile2<R, TH, TY, true, K_EDGE, NT2<TH>>(g, a, L, x0, y0, tw, th);
+    lks_tile2<R, TH, TY, true, K_EDGE, NT2<TH>>(g, a, L, x0, y0, tw, th, tile);
   }
 }
 
@@ -1369,7 +1414,7 @@ struct Adj2Lds {
 };
 
 template <typename R, bool TH, int TY, bool FULL, int KIND, int NT>
-__device__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>& L, int x0,
+__device__ __forceinline__ void alks_tile2(const Geo& g, const AdjArgs<R>& a, Adj2Lds<R, TH, TY>& L, int x0,
                            int y0, int tw, int th) {
   using LD = Adj2Lds<R, TH, TY>;
   constexpr int WR = LD::WR, WM = LD::WM, SM = LD::SM;

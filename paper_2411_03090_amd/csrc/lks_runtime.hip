@@ -123,7 +123,7 @@ struct lks_ctx {
   int adj_exact = 0;     // LKS_ADJ_EXACT: transpose of the discrete Brinkman step
   int ckpt_scheme = 0;   // requested checkpointing (LKS_CKPT_*)
   int ckpt_slots = 0;    // binomial: requested free snapshot slots (0: budget)
-  void* lastv[5] = {};   // binomial: where the last forward level is held
+  void* lastv[5] = {};   // unsteady: where the last forward level is held
   int cur = 0;      // steady forward: ping-pong index of the current level
   int acur = 0;     // adjoint: ping-pong index of the current level
   int last_level = 0;
@@ -590,9 +590,13 @@ struct Run {
 
   // pointers (drho, u..., T) of level n of an unsteady run; seg_base is the
   // first level of the segment held in the replay slots; T is null when the
-  // problem is not thermal
-  void level(int n, int seg_base, R* out[5]) {
+  // problem is not thermal. What a checkpoint or slot does not hold (drho of
+  // a slot level, every field of a level between checkpoints) lives in the
+  // ping-pong buffers pp (n & 1 unless the sweep tracks it: the adjoint reads
+  // only u and T, which never live there).
+  void level(int n, int seg_base, R* out[5], int pp = -1) {
     const int K = c->plan.K, nst = ckpt_fields(c);
+    if (pp < 0) pp = n & 1;
     for (int f = 0; f < 5; ++f) out[f] = nullptr;
     if (n % K == 0) {
       const int m = n / K;
@@ -601,12 +605,51 @@ struct Run {
     }
     if (n > seg_base) {
       const int s = n - seg_base - 1;
-      out[0] = rp<R>(c->S[n & 1][0]);
+      out[0] = rp<R>(c->S[pp][0]);
       for (int f = 1; f < nst; ++f) out[f] = slot(s, f - 1);
       return;
     }
-    for (int f = 0; f < nf; ++f) out[f] = rp<R>(c->S[n & 1][f]);
+    for (int f = 0; f < nf; ++f) out[f] = rp<R>(c->S[pp][f]);
     if (!c->phys.thermal) out[nf - 1] = nullptr;
+  }
+
+  // LKS steps from level `from` to level `to` of an unsteady two-level plan,
+  // each level where level() puts it for seg_base, the objective into acc
+  // when given. With two steps per launch a launch skips the level between
+  // (or writes what a checkpoint or slot keeps of it), so the ping-pong
+  // buffer is tracked here rather than taken from the level's parity; the
+  // pointers of level `to` are returned in last.
+  void sweep(int from, int to, int seg_base, double* acc, R* last[5]) {
+    const bool two = c->dim == 2 && two_step_fwd(c->spl_f);
+    int pp = 0;  // the ping-pong buffers of the current level
+    R* in[5];
+    level(from, seg_base, in, pp);
+    for (int n = from; n < to;) {
+      R* out[5];
+      if (two && n + 2 <= to) {
+        R* mid[5];
+        level(n + 1, seg_base, mid, pp ^ 1);
+        level(n + 2, seg_base, out, pp ^ 1);
+        // what of the middle level is kept: the checkpoint or slot fields
+        for (int f = 0; f < 5; ++f)
+          if (mid[f] && (mid[f] == rp<R>(c->S[0][f]) || mid[f] == rp<R>(c->S[1][f])))
+            mid[f] = nullptr;
+        lks::FwdArgs<R> a = fwd_args(in, out, n + 2, acc);
+        a.dm = mid[0];
+        a.uxm = mid[1];
+        a.uym = mid[2];
+        a.Tm = mid[3];
+        lks::launch_lks_step2(g, a, c->stream);
+        n += 2;
+      } else {
+        level(n + 1, seg_base, out, pp ^ 1);
+        step(in, out, n + 1, acc);
+        n += 1;
+      }
+      pp ^= 1;
+      for (int f = 0; f < 5; ++f) in[f] = out[f];
+    }
+    for (int f = 0; f < 5; ++f) last[f] = in[f];
   }
 
   void step(R* const in[5], R* const out[5], int level_out, double* acc) {
@@ -660,9 +703,9 @@ struct Run {
     return a;
   }
 
-  // two time steps per launch: FP32 D2Q9 steady sweeps, and the FP64
-  // non-thermal forward sweep (two-step kernels exist for 64 x 4 and 64 x 8
-  // tiles)
+  // two time steps per launch: FP32 D2Q9 sweeps (the adjoint ones steady),
+  // and the FP64 non-thermal forward sweep (two-step kernels exist for 64 x 4
+  // and 64 x 8 tiles)
   bool two_step(int spl) const {
     return std::is_same<R, float>::value && c->dim == 2 && spl == 2 &&
            (c->geo.ty == 4 || c->geo.ty == 8);
@@ -768,15 +811,9 @@ struct Run {
     R* lv[5];
     level(0, c->plan.ls, lv);
     init(lv);
-    for (int n = 0; n < steps; ++n) {
-      R* in[5];
-      R* out[5];
-      level(n, c->plan.ls, in);
-      level(n + 1, c->plan.ls, out);
-      step(in, out, n + 1, c->acc);
-    }
     R* last[5];
-    level(steps, c->plan.ls, last);
+    sweep(0, steps, c->plan.ls, c->acc, last);
+    for (int f = 0; f < 5; ++f) c->lastv[f] = last[f];
     lks::launch_finite_check<R>(last[1], N, c->flag, c->stream);
     c->last_level = steps;
   }
@@ -985,13 +1022,8 @@ struct Run {
       const int top = (b == c->plan.ls) ? Nst : b + K - 1;
       if (b != c->plan.ls) {
         // replay levels b+1 .. top into the segment slots
-        for (int n = b; n < top; ++n) {
-          R* in[5];
-          R* out[5];
-          level(n, b, in);
-          level(n + 1, b, out);
-          step(in, out, n + 1, nullptr);
-        }
+        R* last[5];
+        sweep(b, top, b, nullptr, last);
       }
       for (int n = top; n >= b; --n) {
         R* lv[5];
@@ -1027,18 +1059,17 @@ struct Run {
     if ((f = fwd_index(which)) >= 0) {
       if (c->mode == LKS_STEADY) {
         src = c->S[c->cur][f];
-      } else if (c->plan.scheme == LKS_CKPT_BINOMIAL) {
-        src = c->lastv[f];
       } else {
-        R* lv[5];
-        level(c->last_level, c->plan.ls, lv);
-        src = lv[f];
+        // the final level of the forward sweep (the sweeps track where its
+        // ping-pong fields are)
+        src = c->lastv[f];
       }
     } else if ((f = adj_index(which)) >= 0) {
       src = c->P[c->acur][f];
     } else {
       return LKS_E_INVALID;
     }
+    if (!src) return LKS_E_STATE;  // no unsteady forward sweep on this workspace yet
     lks::launch_to_double<R>(static_cast<const R*>(src), out, N, c->stream);
     return LKS_OK;
   }
@@ -1246,6 +1277,7 @@ lks_status lks_bind_workspace(lks_ctx* c, void* dev_ptr, size_t bytes) {
     for (int f = 0; f < 5; ++f) c->S[s][f] = f < nf ? take(N * r) : nullptr;
   for (int s = 0; s < 2; ++s)
     for (int f = 0; f < 5; ++f) c->P[s][f] = f < nf ? take(N * r) : nullptr;
+  for (auto& p : c->lastv) p = nullptr;
   c->acc = reinterpret_cast<double*>(take(sizeof(double) * acc_capacity(c)));
   if (nu == 3) {
     c->d_ops3 = take(6 * sizeof(lks::FaceOp3));
@@ -1672,11 +1704,10 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
   float best = 0.0f;
   int best_ty = c->geo.ty, best_f = c->spl_f, best_a = c->spl_a;
   const int mode = c->mode;
-  // two steps per launch exist for steady FP32 sweeps and the FP64
-  // non-thermal forward; an unsteady context times (and keeps) one step per
-  // launch
+  // two steps per launch exist for FP32 sweeps and the FP64 non-thermal
+  // forward; an unsteady adjoint sweep runs one step per launch
   const bool fwd2 = c->rsz == 4 || !c->phys.thermal;
-  const int nspl = (fwd2 && mode != LKS_UNSTEADY) ? 2 : 1;
+  const int nspl = fwd2 ? 2 : 1;
   c->mode = LKS_STEADY;  // time plain steps on the ping-pong buffers
   for (int ty : TILE_ROWS) {
     if (!tile_rows_ok(ty, c->rsz, c->phys.thermal)) continue;
@@ -1706,7 +1737,7 @@ lks_status lks_autotune(lks_ctx* c, const double* gamma_dev, int steps, int* til
     }
     if (st != LKS_OK) break;
     const int sf = (nspl_ty == 2 && tf[1] < tf[0]) ? 2 : 1;
-    const int sa = (nspl_ty == 2 && c->rsz == 4 && ta[1] < ta[0]) ? 2 : 1;
+    const int sa = (nspl_ty == 2 && c->rsz == 4 && mode != LKS_UNSTEADY && ta[1] < ta[0]) ? 2 : 1;
     const float t = tf[sf - 1] + ta[sa - 1];
     if (best == 0.0f || t < best) {
       best = t;

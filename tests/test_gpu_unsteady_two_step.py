@@ -1,0 +1,143 @@
+"""GPU: two LKS steps per launch in the unsteady sweeps. The first sweep and
+the checkpoint replays fuse pairs of steps, storing from LDS what a
+checkpoint or replay slot keeps of the level between, with the objective
+summed at both levels. Every level must hold the bits of one step per launch,
+so the adjoint sweep and dJ/dgamma are bitwise the same; J sums the same
+terms per tile and level in another order within a tile."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+from paper_2411_03090_amd import lks, workloads as W  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1), device=DEV)
+
+
+def _run(wl, prec, ty, spl, budget=0):
+    ctx = lks.LKS(wl, precision=prec, mem_budget=budget, device=DEV,
+                  checkpointing=("two_level", 0))
+    ctx.set_tile_rows(ty)
+    ctx.set_steps_per_launch(spl, 1)
+    assert ctx.launch_shape() == (ty, spl, 1)
+    g = T(wl.gamma)
+    dJ = torch.full_like(g, float("nan"))
+    ctx.forward(g, wl.n_fwd)
+    J = ctx.objective()
+    fields = {n: ctx.read(n).cpu().numpy() for n in ("drho", "ux", "uy")}
+    if wl.thermal:
+        fields["T"] = ctx.read("T").cpu().numpy()
+    ctx.backward(1.0, dJ, wl.n_fwd)
+    torch.cuda.synchronize()
+    info = ctx.checkpoint_info()
+    del ctx
+    return J, dJ.cpu().numpy(), fields, info
+
+
+def _budget(wl, prec, levels):
+    """A budget that holds the non-trajectory memory and about `levels`
+    stored levels (without a budget every level after the first is kept in
+    a slot of u (and T))."""
+    full = lks.LKS(wl, precision=prec, mem_budget=0, bind=False)
+    ws = full.workspace_size()
+    del full
+    r = 8 if prec == "fp64" else 4
+    slot = (3 if wl.thermal else 2) * wl.nx * wl.ny * r
+    return int(ws - wl.n_fwd * slot + levels * (slot + wl.nx * wl.ny * r))
+
+
+def _compare(ref, got, tag):
+    J0, d0, f0, _ = ref
+    J1, d1, f1, _ = got
+    assert abs(J0) > 1e-8, (tag, J0)
+    assert abs(J1 - J0) <= 1e-13 * abs(J0), (tag, J0, J1)
+    for n in f0:
+        assert np.array_equal(f0[n], f1[n]), (tag, n)
+    assert np.array_equal(d0, d1), tag
+
+
+def _thermal(n_steps=97, mode="paper"):
+    wl = W.unsteady_thermal_channel(70, 26, Re=60.0, sigma=3.0, seed=4, n_steps=n_steps,
+                                    period=40.0)
+    # the enthalpy flux through column 20, which the inflow reaches within
+    # the horizon (at the outlet column J is zero up to rounding)
+    wl.mask = W.channel_mask(70, 26, thermal=True, probe_col=20)
+    wl.adjoint_mode = mode
+    return wl
+
+
+@pytest.mark.parametrize("ty", [4, 8])
+@pytest.mark.parametrize("levels", [None, 20])
+def test_thermal_two_step_forward_gives_the_same_levels(ty, levels):
+    """70 x 26 thermal channel, 97 steps (an odd horizon: the sweep ends on
+    one step), with every level kept and with a budget of about 20 levels
+    (checkpointed, replayed segments of both parities)."""
+    wl = _thermal()
+    budget = 0 if levels is None else _budget(wl, "fp32", levels)
+    say(f"[gpu] unsteady 70x26 97 steps fp32, tile rows {ty}, budget {budget}")
+    ref = _run(wl, "fp32", ty, 1, budget)
+    got = _run(wl, "fp32", ty, 2, budget)
+    if levels is not None:
+        assert 2 < got[3]["count"] < 97 and got[3]["replay_steps"] > 0
+    _compare(ref, got, (ty, levels))
+
+
+@pytest.mark.parametrize("K_levels", [16, 24])
+def test_heat_sink_exact_mode_two_step(K_levels):
+    """The heat-sink objective (heated-node temperature, prescribed heat
+    flux, Boussinesq force) in the exact adjoint mode, checkpointed."""
+    wl = W.heat_sink(n=40, n_steps=60)
+    wl.adjoint_mode = "exact"
+    budget = _budget(wl, "fp32", K_levels)
+    say(f"[gpu] heat sink 40x40 60 steps exact mode fp32, budget of {K_levels} levels")
+    ref = _run(wl, "fp32", 4, 1, budget)
+    got = _run(wl, "fp32", 4, 2, budget)
+    assert got[3]["replay_steps"] > 0
+    _compare(ref, got, K_levels)
+
+
+def test_heat_exchange_objective_two_step():
+    """The heat source and the heat-exchange objective over an unsteady
+    sweep, both modes of the adjoint on the same forward."""
+    wl = _thermal(n_steps=40)
+    wl.beta_max, wl.objective = 0.1, W.OBJ_HEAT_EXCHANGE
+    for mode in ("paper", "exact"):
+        wl.adjoint_mode = mode
+        say(f"[gpu] unsteady heat exchange 70x26 40 steps fp32, {mode} mode")
+        budget = _budget(wl, "fp32", 14)
+        _compare(_run(wl, "fp32", 8, 1, budget), _run(wl, "fp32", 8, 2, budget), mode)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pressure_drop_unsteady_two_step_matches_oracle(prec):
+    """A non-thermal channel with an oscillating inflow, the pressure drop
+    summed over the levels: FP64 runs two forward steps per launch too; the
+    FP64 result also matches the oracle."""
+    wl = W.steady_channel_uniform(70, 26, Re=10.0, seed=2, n_fwd=61, n_adj=61)
+    wl.mode = W.MODE_UNSTEADY
+    wl.ufac = W.oscillating_factors(62, 0.3, 20.0)
+    budget = _budget(wl, prec, 16)
+    say(f"[gpu] unsteady pressure drop 70x26 61 steps {prec}")
+    ref = _run(wl, prec, 8, 1, budget)
+    got = _run(wl, prec, 8, 2, budget)
+    _compare(ref, got, prec)
+    if prec == "fp64":
+        Jo, so, _, _ = O.gradient(wl)
+        assert abs(got[0] - Jo) <= 1e-12 * abs(Jo)
+        assert np.linalg.norm(got[1] - so.ravel()) <= 1e-12 * np.linalg.norm(so)
