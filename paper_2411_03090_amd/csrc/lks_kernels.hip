@@ -129,6 +129,17 @@ __global__ void init_kernel(Geo g, const uint8_t* __restrict__ mask, const R* __
   if (g.thermal) T[k] = t;
 }
 
+// element e of a small per-thread array by selects, so the array stays in
+// registers where the compiler cannot resolve e (a runtime index moves it to
+// per-lane scratch memory)
+template <typename T, int N>
+__device__ inline T pick(const T (&a)[N], int e) {
+  T v = a[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) v = e == i ? a[i] : v;
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // block reduction helper (deterministic)
 // ---------------------------------------------------------------------------
@@ -1149,10 +1160,10 @@ __device__ void alks_tile(const Geo& g, const AdjArgs<R>& a, AdjLds<R, TH, TY>& 
     R s, ux, uy;
     double so = 0.0;
     if constexpr (FULL) {
-      s = spre[e];
-      ux = uxpre[e];
-      uy = uypre[e];
-      so = senspre[e];
+      s = pick(spre, e);
+      ux = pick(uxpre, e);
+      uy = pick(uypre, e);
+      so = pick(senspre, e);
       ++e;
       if constexpr (EDGE)
         if (on_ring(g, i, j)) return;
