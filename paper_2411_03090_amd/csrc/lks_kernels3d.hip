@@ -1235,20 +1235,27 @@ __global__ __launch_bounds__(ZT) void alks3e_kernel(Geo3 g, Adj3Args<R> a) {
 // (every plane of a periodic one). At plane s every column of the tile and of
 // its 1-node ring forms its moments of plane s: an interior node pulls
 // f~_q = rho~ + c_q.V and g~_q = Theta from x + c_q (eq:afeq, eq:ageq) out
-// of four LDS plane slots of the level-(n+1) coefficients (tile plus a
-// 2-node halo) and applies the local terms, as the pull pass does; a
+// of three LDS plane slots of the level-(n+1) coefficients (tile plus a
+// 2-node halo; the next plane waits in registers) and applies the local
+// terms, as the pull pass does; a
 // boundary node takes the moments the face pass left in the scratch. The
 // plane's in-plane moment fields go to LDS, the column keeps its own in
 // registers, and plane s - 1 is updated (adj3_update) from the moments of
 // planes s - 2, s - 1 and s. The moments that never leave the block are not
 // stored; only the z-window moments of planes 1, 2, nz-3 and nz-2 go to the
 // scratch, for the end planes that alks3e<ENDS> updates afterwards.
+// FP32 keeps three coefficient slots and one plane of moment fields, with
+// three barriers per plane (their LDS allows three blocks per CU); FP64, held
+// to one block per CU by its registers either way, keeps four slots and two
+// moment planes with one barrier per plane
 template <typename R, bool TH>
 struct AdjFLds {
   static constexpr int NP = TH ? 5 : 4;  // rho~, Vx, Vy, Vz (, Theta)
   static constexpr int NE = TH ? 9 : 5;  // s~xx s~xy s~xz s~yy s~yz (q~x q~y T B)
-  R p[4][NP][NSR];
-  R e[2][NE][NCR];
+  static constexpr bool LEAN = sizeof(R) == 4;
+  static constexpr int NS = LEAN ? 3 : 4;
+  R p[NS][NP][NSR];
+  R e[LEAN ? 1 : 2][NE][NCR];
 };
 
 // node of a column at one plane: index, class, boundary count, T, B and
@@ -1262,7 +1269,8 @@ struct ColIn {
 
 template <typename R, bool TH>
 __global__ __launch_bounds__(ZT) void alks3f_kernel(Geo3 g, Adj3Args<R> a) {
-  constexpr int NP = AdjFLds<R, TH>::NP;
+  constexpr int NP = AdjFLds<R, TH>::NP, NS = AdjFLds<R, TH>::NS;
+  constexpr bool LEAN = AdjFLds<R, TH>::LEAN;
   constexpr int NM = TH ? 14 : 10;
   __shared__ AdjFLds<R, TH> L;
   const int pz = g.periodic & 4;
@@ -1282,7 +1290,7 @@ __global__ __launch_bounds__(ZT) void alks3f_kernel(Geo3 g, Adj3Args<R> a) {
   // planes that exist (INT_MIN: none, to skip a column's inputs)
   auto has = [&](int q) { return q != INT_MIN && (pz || (q >= 0 && q < g.nz)); };
   const int base = t.z0 - 2;  // first plane held in the LDS slots
-  auto slot = [&](int q) { return (q - base) & 3; };
+  auto slot = [&](int q) { return (q - base) % NS; };
   const int last = t.z1 + 1;  // last plane the pulls read
   R v[SRL][NP];
   auto load = [&](int q) {
@@ -1403,6 +1411,74 @@ __global__ __launch_bounds__(ZT) void alks3f_kernel(Geo3 g, Adj3Args<R> a) {
   const R z0v[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
   for (int f = 0; f < 6; ++f) zm1[f] = zc[f] = R(0);
+  // FP32, three barriers per plane: the pulls of plane s read three
+  // coefficient slots; after them plane s + 2 takes the slot of plane s - 1
+  // and the update of plane s - 1 reads the in-plane moment fields; after
+  // that plane s replaces them
+  if constexpr (LEAN)
+  for (int s = t.z0 - 1; s <= t.z1; ++s) {
+    lds_barrier();
+    ColIn<R> c0n, c1n;
+    col_in(n0, s + 1 <= t.z1 ? s + 1 : INT_MIN, c0n);
+    col_in(n1, s + 1 <= t.z1 ? s + 1 : INT_MIN, c1n);
+    upd_in(s >= t.z0 && s < t.z1 ? s : INT_MIN, unext);
+    // (in FP64 the own column's reads wait until the ring column is done:
+    // held across its pulls they cost more registers than they save)
+    R M[14], Mr[14], Mb0[14], u00;
+    if constexpr (sizeof(R) == 4) bnd_in(c0, true, Mb0, u00);
+    {
+      R Mb1[14], u01;
+      bnd_in(c1, false, Mb1, u01);
+      moments(n1, c1, s, Mb1, u01, Mr);
+    }
+    if constexpr (sizeof(R) != 4) bnd_in(c0, true, Mb0, u00);
+    moments(n0, c0, s, Mb0, u00, M);
+    lds_barrier();
+    if (s + 2 <= last) store(s + 2);
+    if (s + 3 <= last) load(s + 3);
+    zn[0] = M[6];
+    zn[1] = M[8];
+    zn[2] = M[9];
+    zn[3] = TH ? M[13] : R(0);
+    zn[4] = c0.T;
+    zn[5] = c0.B;
+    if (own && s - 1 >= t.z0) {
+      AdjIn<R> cu = ucur;
+      cu.r = Mc[0];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) cu.U[c] = Mc[1 + c];
+      cu.Tt = TH ? Mc[10] : R(0);
+      R zd[6];
+#pragma unroll
+      for (int f = 0; f < 6; ++f) zd[f] = dz3(0, zc[f], zm1[f], zn[f], R(0));
+      adj3_update<R, TH>(a, g, unsigned(zwrap(s - 1, g.nz)) * nxy + unsigned(n0.off), L.e[0],
+                         n0.ci, n0.ex, n0.ey, 0, cu, zd, zc, zm1, zn, z0v);
+    }
+    // the z-window moments next to the end planes, for alks3e<ENDS>
+    if (!pz && own && c0.valid && !c0.ne && s >= t.z0 && s < t.z1 &&
+        (s <= 2 || s >= g.nz - 3)) {
+      a.m[6 * N + c0.k] = M[6];
+      a.m[8 * N + c0.k] = M[8];
+      a.m[9 * N + c0.k] = M[9];
+      if constexpr (TH) a.m[13 * N + c0.k] = M[13];
+    }
+    lds_barrier();
+    store_e(n1, Mr, c1, 0);
+    store_e(n0, M, c0, 0);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      zm1[f] = zc[f];
+      zc[f] = zn[f];
+    }
+#pragma unroll
+    for (int i = 0; i < 14; ++i) Mc[i] = M[i];
+    ucur = unext;
+    c0 = c0n;
+    c1 = c1n;
+  }
+  // FP64, one barrier per plane: plane s + 2 goes to the fourth slot and the
+  // moment fields alternate between two planes
+  else
   for (int s = t.z0 - 1; s <= t.z1; ++s) {
     lds_barrier();
     if (s + 2 <= last) store(s + 2);
