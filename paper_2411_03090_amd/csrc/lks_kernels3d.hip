@@ -1415,127 +1415,128 @@ __global__ __launch_bounds__(ZT) void alks3f_kernel(Geo3 g, Adj3Args<R> a) {
   // coefficient slots; after them plane s + 2 takes the slot of plane s - 1
   // and the update of plane s - 1 reads the in-plane moment fields; after
   // that plane s replaces them
-  if constexpr (LEAN)
-  for (int s = t.z0 - 1; s <= t.z1; ++s) {
-    lds_barrier();
-    ColIn<R> c0n, c1n;
-    col_in(n0, s + 1 <= t.z1 ? s + 1 : INT_MIN, c0n);
-    col_in(n1, s + 1 <= t.z1 ? s + 1 : INT_MIN, c1n);
-    upd_in(s >= t.z0 && s < t.z1 ? s : INT_MIN, unext);
-    // (in FP64 the own column's reads wait until the ring column is done:
-    // held across its pulls they cost more registers than they save)
-    R M[14], Mr[14], Mb0[14], u00;
-    if constexpr (sizeof(R) == 4) bnd_in(c0, true, Mb0, u00);
-    {
-      R Mb1[14], u01;
-      bnd_in(c1, false, Mb1, u01);
-      moments(n1, c1, s, Mb1, u01, Mr);
-    }
-    if constexpr (sizeof(R) != 4) bnd_in(c0, true, Mb0, u00);
-    moments(n0, c0, s, Mb0, u00, M);
-    lds_barrier();
-    if (s + 2 <= last) store(s + 2);
-    if (s + 3 <= last) load(s + 3);
-    zn[0] = M[6];
-    zn[1] = M[8];
-    zn[2] = M[9];
-    zn[3] = TH ? M[13] : R(0);
-    zn[4] = c0.T;
-    zn[5] = c0.B;
-    if (own && s - 1 >= t.z0) {
-      AdjIn<R> cu = ucur;
-      cu.r = Mc[0];
+  if constexpr (LEAN) {
+    for (int s = t.z0 - 1; s <= t.z1; ++s) {
+      lds_barrier();
+      ColIn<R> c0n, c1n;
+      col_in(n0, s + 1 <= t.z1 ? s + 1 : INT_MIN, c0n);
+      col_in(n1, s + 1 <= t.z1 ? s + 1 : INT_MIN, c1n);
+      upd_in(s >= t.z0 && s < t.z1 ? s : INT_MIN, unext);
+      // (in FP64 the own column's reads wait until the ring column is done:
+      // held across its pulls they cost more registers than they save)
+      R M[14], Mr[14], Mb0[14], u00;
+      if constexpr (sizeof(R) == 4) bnd_in(c0, true, Mb0, u00);
+      {
+        R Mb1[14], u01;
+        bnd_in(c1, false, Mb1, u01);
+        moments(n1, c1, s, Mb1, u01, Mr);
+      }
+      if constexpr (sizeof(R) != 4) bnd_in(c0, true, Mb0, u00);
+      moments(n0, c0, s, Mb0, u00, M);
+      lds_barrier();
+      if (s + 2 <= last) store(s + 2);
+      if (s + 3 <= last) load(s + 3);
+      zn[0] = M[6];
+      zn[1] = M[8];
+      zn[2] = M[9];
+      zn[3] = TH ? M[13] : R(0);
+      zn[4] = c0.T;
+      zn[5] = c0.B;
+      if (own && s - 1 >= t.z0) {
+        AdjIn<R> cu = ucur;
+        cu.r = Mc[0];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) cu.U[c] = Mc[1 + c];
-      cu.Tt = TH ? Mc[10] : R(0);
-      R zd[6];
+        for (int c = 0; c < 3; ++c) cu.U[c] = Mc[1 + c];
+        cu.Tt = TH ? Mc[10] : R(0);
+        R zd[6];
 #pragma unroll
-      for (int f = 0; f < 6; ++f) zd[f] = dz3(0, zc[f], zm1[f], zn[f], R(0));
-      adj3_update<R, TH>(a, g, unsigned(zwrap(s - 1, g.nz)) * nxy + unsigned(n0.off), L.e[0],
-                         n0.ci, n0.ex, n0.ey, 0, cu, zd, zc, zm1, zn, z0v);
-    }
-    // the z-window moments next to the end planes, for alks3e<ENDS>
-    if (!pz && own && c0.valid && !c0.ne && s >= t.z0 && s < t.z1 &&
-        (s <= 2 || s >= g.nz - 3)) {
-      a.m[6 * N + c0.k] = M[6];
-      a.m[8 * N + c0.k] = M[8];
-      a.m[9 * N + c0.k] = M[9];
-      if constexpr (TH) a.m[13 * N + c0.k] = M[13];
-    }
-    lds_barrier();
-    store_e(n1, Mr, c1, 0);
-    store_e(n0, M, c0, 0);
+        for (int f = 0; f < 6; ++f) zd[f] = dz3(0, zc[f], zm1[f], zn[f], R(0));
+        adj3_update<R, TH>(a, g, unsigned(zwrap(s - 1, g.nz)) * nxy + unsigned(n0.off), L.e[0],
+                           n0.ci, n0.ex, n0.ey, 0, cu, zd, zc, zm1, zn, z0v);
+      }
+      // the z-window moments next to the end planes, for alks3e<ENDS>
+      if (!pz && own && c0.valid && !c0.ne && s >= t.z0 && s < t.z1 &&
+          (s <= 2 || s >= g.nz - 3)) {
+        a.m[6 * N + c0.k] = M[6];
+        a.m[8 * N + c0.k] = M[8];
+        a.m[9 * N + c0.k] = M[9];
+        if constexpr (TH) a.m[13 * N + c0.k] = M[13];
+      }
+      lds_barrier();
+      store_e(n1, Mr, c1, 0);
+      store_e(n0, M, c0, 0);
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      zm1[f] = zc[f];
-      zc[f] = zn[f];
-    }
+      for (int f = 0; f < 6; ++f) {
+        zm1[f] = zc[f];
+        zc[f] = zn[f];
+      }
 #pragma unroll
-    for (int i = 0; i < 14; ++i) Mc[i] = M[i];
-    ucur = unext;
-    c0 = c0n;
-    c1 = c1n;
-  }
-  // FP64, one barrier per plane: plane s + 2 goes to the fourth slot and the
-  // moment fields alternate between two planes
-  else
-  for (int s = t.z0 - 1; s <= t.z1; ++s) {
-    lds_barrier();
-    if (s + 2 <= last) store(s + 2);
-    if (s + 3 <= last) load(s + 3);
-    ColIn<R> c0n, c1n;
-    col_in(n0, s + 1 <= t.z1 ? s + 1 : INT_MIN, c0n);
-    col_in(n1, s + 1 <= t.z1 ? s + 1 : INT_MIN, c1n);
-    upd_in(s >= t.z0 && s < t.z1 ? s : INT_MIN, unext);
-    // (in FP64 the own column's reads wait until the ring column is done:
-    // held across its pulls they cost more registers than they save)
-    R M[14], Mb0[14], u00;
-    if constexpr (sizeof(R) == 4) bnd_in(c0, true, Mb0, u00);
-    {
-      R Mr[14], Mb1[14], u01;
-      bnd_in(c1, false, Mb1, u01);
-      moments(n1, c1, s, Mb1, u01, Mr);
-      store_e(n1, Mr, c1, s & 1);
+      for (int i = 0; i < 14; ++i) Mc[i] = M[i];
+      ucur = unext;
+      c0 = c0n;
+      c1 = c1n;
     }
-    if constexpr (sizeof(R) != 4) bnd_in(c0, true, Mb0, u00);
-    moments(n0, c0, s, Mb0, u00, M);
-    store_e(n0, M, c0, s & 1);
-    zn[0] = M[6];
-    zn[1] = M[8];
-    zn[2] = M[9];
-    zn[3] = TH ? M[13] : R(0);
-    zn[4] = c0.T;
-    zn[5] = c0.B;
-    if (own && s - 1 >= t.z0) {
-      AdjIn<R> cu = ucur;
-      cu.r = Mc[0];
+  } else {
+    // FP64, one barrier per plane: plane s + 2 goes to the fourth slot and
+    // the moment fields alternate between two planes
+    for (int s = t.z0 - 1; s <= t.z1; ++s) {
+      lds_barrier();
+      if (s + 2 <= last) store(s + 2);
+      if (s + 3 <= last) load(s + 3);
+      ColIn<R> c0n, c1n;
+      col_in(n0, s + 1 <= t.z1 ? s + 1 : INT_MIN, c0n);
+      col_in(n1, s + 1 <= t.z1 ? s + 1 : INT_MIN, c1n);
+      upd_in(s >= t.z0 && s < t.z1 ? s : INT_MIN, unext);
+      // (in FP64 the own column's reads wait until the ring column is done:
+      // held across its pulls they cost more registers than they save)
+      R M[14], Mb0[14], u00;
+      if constexpr (sizeof(R) == 4) bnd_in(c0, true, Mb0, u00);
+      {
+        R Mr[14], Mb1[14], u01;
+        bnd_in(c1, false, Mb1, u01);
+        moments(n1, c1, s, Mb1, u01, Mr);
+        store_e(n1, Mr, c1, s & 1);
+      }
+      if constexpr (sizeof(R) != 4) bnd_in(c0, true, Mb0, u00);
+      moments(n0, c0, s, Mb0, u00, M);
+      store_e(n0, M, c0, s & 1);
+      zn[0] = M[6];
+      zn[1] = M[8];
+      zn[2] = M[9];
+      zn[3] = TH ? M[13] : R(0);
+      zn[4] = c0.T;
+      zn[5] = c0.B;
+      if (own && s - 1 >= t.z0) {
+        AdjIn<R> cu = ucur;
+        cu.r = Mc[0];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) cu.U[c] = Mc[1 + c];
-      cu.Tt = TH ? Mc[10] : R(0);
-      R zd[6];
+        for (int c = 0; c < 3; ++c) cu.U[c] = Mc[1 + c];
+        cu.Tt = TH ? Mc[10] : R(0);
+        R zd[6];
 #pragma unroll
-      for (int f = 0; f < 6; ++f) zd[f] = dz3(0, zc[f], zm1[f], zn[f], R(0));
-      adj3_update<R, TH>(a, g, unsigned(zwrap(s - 1, g.nz)) * nxy + unsigned(n0.off),
-                         L.e[(s - 1) & 1], n0.ci, n0.ex, n0.ey, 0, cu, zd, zc, zm1, zn, z0v);
+        for (int f = 0; f < 6; ++f) zd[f] = dz3(0, zc[f], zm1[f], zn[f], R(0));
+        adj3_update<R, TH>(a, g, unsigned(zwrap(s - 1, g.nz)) * nxy + unsigned(n0.off),
+                           L.e[(s - 1) & 1], n0.ci, n0.ex, n0.ey, 0, cu, zd, zc, zm1, zn, z0v);
+      }
+      // the z-window moments next to the end planes, for alks3e<ENDS>
+      if (!pz && own && c0.valid && !c0.ne && s >= t.z0 && s < t.z1 &&
+          (s <= 2 || s >= g.nz - 3)) {
+        a.m[6 * N + c0.k] = M[6];
+        a.m[8 * N + c0.k] = M[8];
+        a.m[9 * N + c0.k] = M[9];
+        if constexpr (TH) a.m[13 * N + c0.k] = M[13];
+      }
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        zm1[f] = zc[f];
+        zc[f] = zn[f];
+      }
+#pragma unroll
+      for (int i = 0; i < 14; ++i) Mc[i] = M[i];
+      ucur = unext;
+      c0 = c0n;
+      c1 = c1n;
     }
-    // the z-window moments next to the end planes, for alks3e<ENDS>
-    if (!pz && own && c0.valid && !c0.ne && s >= t.z0 && s < t.z1 &&
-        (s <= 2 || s >= g.nz - 3)) {
-      a.m[6 * N + c0.k] = M[6];
-      a.m[8 * N + c0.k] = M[8];
-      a.m[9 * N + c0.k] = M[9];
-      if constexpr (TH) a.m[13 * N + c0.k] = M[13];
-    }
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      zm1[f] = zc[f];
-      zc[f] = zn[f];
-    }
-#pragma unroll
-    for (int i = 0; i < 14; ++i) Mc[i] = M[i];
-    ucur = unext;
-    c0 = c0n;
-    c1 = c1n;
   }
 }
 
