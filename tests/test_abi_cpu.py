@@ -250,6 +250,12 @@ def test_launch_shape_controls():
     with pytest.raises(lks.LKSError) as e:
         _create(W.heated_block_duct(20, 10, 8, n_steps=5), "fp32").set_tile_rows(4)
     assert e.value.status == lks.LKS_E_UNSUPPORTED
+    # unsteady sweeps: the forward (first sweep and replays) takes two steps
+    # per launch; 64 x 16 tiles run one
+    un = _create(W.unsteady_thermal_channel(70, 26, n_steps=9), "fp32")
+    un.set_tile_rows(8)
+    un.set_steps_per_launch(2, 1)
+    assert un.launch_shape() == (8, 2, 1)
 
 
 def test_calls_out_of_order_report_state_errors():
