@@ -447,6 +447,7 @@ template <typename R, bool TH, int PR, int SF, bool INT = false>
 __device__ inline void fwd_collide(const Geo& g, R A, const R* ld, const R* lu, const R* lv,
                                    const R* lT, const R* lB, int pr, int i, int j, R* f, R* gq,
                                    int pf) {
+#pragma clang fp contract(on)
   const R d = ld[pr], ux = lu[pr], uy = lv[pr];
   const R uxx = lds_dx<INT>(lu, pr, 1, i, g.nx, g.periodic);
   const R uxy = lds_dx<INT>(lu, pr, PR, j, g.ny, g.periodic);
@@ -483,6 +484,7 @@ __device__ inline void fwd_collide(const Geo& g, R A, const R* ld, const R* lu, 
 // whose W is (Wx, Wy)
 template <typename R>
 __device__ inline R g_eq(int q, R T, R Wx, R Wy) {
+#pragma clang fp contract(on)
   const R w0 = R(4.0 / 9), w1 = R(1.0 / 9), w5 = R(1.0 / 36);
   switch (q) {
     case 0: return w0 * T;
@@ -505,6 +507,7 @@ template <typename R, bool TH, int PF, int SF, int PR, bool INT = false>
 __device__ inline void fwd_pull(const Geo& g, const FwdArgs<R>& a, const R* lf, const R* lg,
                                 const R* lT, int pf, int pr, int i, int j, int k, int m, R s,
                                 int level, R& dn, R& uxn, R& uyn, R& Tn) {
+#pragma clang fp contract(on)
   const int fc = (INT || g.periodic) ? FLOW_INTERIOR : (m & 3);
   R f[9], gg[9];
 #pragma unroll

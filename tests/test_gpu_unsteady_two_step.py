@@ -141,3 +141,18 @@ def test_pressure_drop_unsteady_two_step_matches_oracle(prec):
         Jo, so, _, _ = O.gradient(wl)
         assert abs(got[0] - Jo) <= 1e-12 * abs(Jo)
         assert np.linalg.norm(got[1] - so.ravel()) <= 1e-12 * np.linalg.norm(so)
+
+
+def test_periodic_box_two_step():
+    """A periodic box (every tile wraps; 70 x 26 leaves odd tiles) heated by
+    the source and stirred by the Boussinesq force, the heat-exchange
+    objective, checkpointed."""
+    wl = W.periodic_box(70, 26, nu=0.08, thermal=True)
+    wl.gamma = W.gamma_grf(70, 26, 3.0, 5)
+    wl.alpha_max, wl.beta_max, wl.objective = 1.0, 0.1, W.OBJ_HEAT_EXCHANGE
+    wl.gbeta, wl.T_ref = (0.0, 1e-4), 0.5
+    wl.mode, wl.n_fwd, wl.n_adj, wl.ufac = W.MODE_UNSTEADY, 41, 41, np.ones(42)
+    budget = _budget(wl, "fp32", 14)
+    say("[gpu] periodic box 70x26 41 steps fp32, heat source and force")
+    for ty in (4, 8):
+        _compare(_run(wl, "fp32", ty, 1, budget), _run(wl, "fp32", ty, 2, budget), ty)
