@@ -399,14 +399,27 @@ def _steady_exchanger(mode):
     return wl
 
 
+def _heated_periodic_box(mode):
+    """Periodic thermal box 70 x 26 (tiles that are not full in x and y,
+    wrapped halos), heated by the source and stirred by the Boussinesq
+    force; paper or exact adjoint."""
+    wl = W.periodic_box(70, 26, nu=0.08, thermal=True)
+    wl.gamma = W.gamma_grf(70, 26, 3.0, 5)
+    wl.alpha_max, wl.beta_max, wl.objective = 1.0, 0.1, W.OBJ_HEAT_EXCHANGE
+    wl.gbeta, wl.T_ref = (0.0, 1e-4), 0.5
+    wl.n_fwd, wl.n_adj, wl.adjoint_mode = 9, 11, mode
+    return wl
+
+
 @pytest.mark.parametrize("ty", [4, 8])
 @pytest.mark.parametrize("mode", ["paper", "exact"])
-def test_two_steps_per_launch_thermal_give_the_same_bits(mode, ty):
+@pytest.mark.parametrize("make", [_steady_exchanger, _heated_periodic_box])
+def test_two_steps_per_launch_thermal_give_the_same_bits(make, mode, ty):
     """The thermal two-step kernels (new temperature of the first step kept
     beside the old one in LDS) against one step per launch, forward and
     adjoint, odd and even step counts."""
-    say(f"[gpu] two steps per launch, thermal heat exchanger 70x70 {mode} ty={ty}")
-    wl = _steady_exchanger(mode)
+    wl = make(mode)
+    say(f"[gpu] two steps per launch, thermal {wl.name} {mode} ty={ty}")
     out = []
     for spl in (1, 2):
         ctx = lks.LKS(wl, precision="fp32", device=DEV)
